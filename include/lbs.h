@@ -1,0 +1,190 @@
+/*
+ * lbs.h -- C-ABI of liblbs, a gfx950 (MI355X) solver for the Dirichlet
+ * problem of the Laplace-Beltrami operator on the unit sphere with islands.
+ *
+ * Method (Kropinski & Nigam, "Fast integral equation methods for the
+ * Laplace-Beltrami equation on the sphere"): the sphere minus M islands is
+ * mapped to the plane by stereographic projection (Section 3); the solution
+ * is a double-layer potential plus one log source per island
+ * (Section 4.1, eq. eqn:u_multi), whose density and strengths solve the
+ * Nystrom system of eq. matrix_eqns (Section 5):
+ *
+ *     [ I + K   E ] [ sigma ]   [ 2 g ]
+ *     [   F     D ] [   A   ] = [  0  ]
+ *
+ * The system is solved by GMRES on the left-preconditioned form of
+ * eq. matrix_eqns_c, and every product with I + K is evaluated by a 2D
+ * Coulomb fast multipole method in the stereographic plane (Section 5).
+ *
+ * Conventions shared by every call:
+ *  - Array arguments are DEVICE pointers unless the name ends in _host.
+ *    Doubles are IEEE binary64.  Work is enqueued on `stream` (a
+ *    hipStream_t passed as void*, NULL = the default stream) and the call
+ *    returns without synchronizing unless stated otherwise.
+ *  - Node order ("API order") is curve-major: island 0's nodes in
+ *    parameter order t_j = 2 pi j / N_0, j = 0..N_0-1, then island 1, ...
+ *    (Section 5, the vector sigma after eq. matrix_eqns).
+ *  - Multi-right-hand-side arrays are column-major: column r of an
+ *    (n x nrhs) array starts at offset r * n.
+ *  - Ownership: inputs are borrowed for the duration of the call; outputs
+ *    are caller-allocated.  A handle owns its device memory and must be
+ *    used from one host thread at a time, with one stream at a time.
+ *  - Errors: every call returns an lbs_status; nothing throws across the
+ *    ABI.  On error, outputs are undefined (except where stated) and
+ *    lbs_last_error() describes the failure.
+ */
+#ifndef LBS_H
+#define LBS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbs_ctx *lbs_handle;
+
+typedef enum {
+  LBS_OK = 0,
+  LBS_ERR_INVALID_ARG = 1,    /* bad pointer, size or option             */
+  LBS_ERR_GEOMETRY = 2,       /* overlapping caps, pole inside or too    */
+                              /* close to an island, non-finite input,   */
+                              /* radius out of (0, pi/2)                 */
+  LBS_ERR_NO_CONVERGENCE = 3, /* iteration limit reached; last iterate   */
+                              /* and info are still written              */
+  LBS_ERR_NOT_FINITE = 4,     /* NaN or Inf in the data                  */
+  LBS_ERR_OUT_OF_MEMORY = 5,
+  LBS_ERR_HIP = 6,            /* a HIP runtime call failed               */
+  LBS_ERR_UNSUPPORTED = 7     /* valid request this build does not serve */
+} lbs_status;
+
+/* One island (Section 1.3): a simply connected cap-like region bounded by a
+ * smooth curve.  Its boundary is the set of points at geodesic distance
+ * r(t) from `center` in direction cos t e1 + sin t e2, e2 = e1 x center,
+ * with r(t) = r0 (1 + sum_{n=1..8} coef[n-1] cos nt + coef[7+n] sin nt).
+ * `center` is also the island's log-source point c_k (eq. eqn:u_multi).
+ * center and e1 must be unit vectors with e1 . center = 0 (to 1e-10). */
+typedef struct {
+  double center[3];
+  double e1[3];
+  double r0;
+  double coef[16];
+} lbs_island;
+
+enum { LBS_FP64 = 0, LBS_MIXED = 1 };            /* precision            */
+enum { LBS_OP_IPLUSK = 0,  /* y = (I + K) sigma            (x, y: N)      */
+       LBS_OP_K = 1,       /* y = K sigma                  (x, y: N)      */
+       LBS_OP_SYSTEM = 2,  /* [y_s; y_a] = A [sigma; A]    (x, y: N + M)  */
+       LBS_OP_PRECOND = 3  /* [y_s; y_a] = P^-1 A [sigma; A] (N + M)      */
+};
+enum { LBS_MATVEC_FMM = 0, LBS_MATVEC_DIRECT = 1 }; /* far-field method   */
+
+typedef struct {
+  int32_t p64;       /* FP64 expansion terms (default 30)                  */
+  int32_t p32;       /* FP32 expansion terms (default 16)                  */
+  int32_t leaf_max;  /* max nodes per quadtree leaf (default 48)           */
+  int32_t restart;   /* GMRES restart length (default 50, Section 6)       */
+  int32_t max_iter;  /* GMRES iteration cap per solve (default 400)        */
+  int32_t max_outer; /* mixed precision: refinement steps cap (default 8)  */
+  double inner_tol;  /* mixed precision: inner GMRES tolerance (1e-5)      */
+  int32_t matvec;    /* LBS_MATVEC_FMM (default) or LBS_MATVEC_DIRECT      */
+  int32_t reserved;
+} lbs_options;
+
+typedef struct {
+  int32_t iters;          /* total GMRES iterations (all restarts, inner)  */
+  int32_t outer_steps;    /* refinement steps (mixed precision), else 0    */
+  double rel_resid;       /* final |P^-1 (b - A x)| / |P^-1 b|, FP64       */
+  double ms_solve;        /* wall time of the call                         */
+  int32_t fp64_matvecs;   /* FMM applications in FP64                      */
+  int32_t fp32_matvecs;   /* FMM applications with the FP32 far field      */
+} lbs_solve_info;
+
+/* Fill *opt with the defaults listed above. */
+void lbs_default_options(lbs_options *opt_host);
+
+/* Build a solver for the boundary curves of `n_islands` islands
+ * (Section 1.3) discretized with nodes_per_curve_host[k] >= 8 equispaced
+ * nodes each (Section 5).  Computes the nodes and their stereographic
+ * images (Section 3), the quadtree and interaction lists of the FMM, the
+ * Schur complement S = D - F E of the block preconditioner and its inverse
+ * (eq. matrix_eqns_c).  Synchronous.  opt_host may be NULL (defaults).
+ * The north pole must lie outside every island's bounding cap (the cap of
+ * radius max r(t) about the centre) and bounding caps must be disjoint;
+ * both problems are rotation invariant, so callers rotate the sphere to
+ * meet this.  Returns LBS_ERR_GEOMETRY otherwise. */
+lbs_status lbs_setup(const lbs_island *islands_host, int32_t n_islands,
+                     const int32_t *nodes_per_curve_host,
+                     const lbs_options *opt_host, void *stream,
+                     lbs_handle *out_host);
+
+/* Total node count N and island count M of a handle. */
+lbs_status lbs_sizes(lbs_handle h, int64_t *n_nodes_host,
+                     int32_t *n_islands_host);
+
+/* Node positions on the sphere, API order, xyz: device (N x 3) row-major.
+ * Use them to build Dirichlet data g. */
+lbs_status lbs_nodes(lbs_handle h, double *xyz, void *stream);
+
+/* Apply an operator of the discrete system (eq. matrix_eqns) to nrhs
+ * vectors.  op is one of LBS_OP_*; precision LBS_FP64 evaluates the far
+ * field with p64 terms in FP64, LBS_MIXED with p32 terms in FP32 (FP32
+ * near field on hi/lo coordinates); the log-source and constraint rows are
+ * always FP64.  x and y are device (n x nrhs), n = N or N + M by op. */
+lbs_status lbs_matvec(lbs_handle h, int32_t op, int32_t precision,
+                      int32_t nrhs, const double *x, double *y,
+                      void *stream);
+
+/* Solve the system for Dirichlet data g (device, N x nrhs, API order):
+ * GMRES(restart) on P^-1 A [sigma; A] = P^-1 [2g; 0] from x0 = 0 until the
+ * preconditioned relative residual is <= tol (Section 5, Section 6).
+ * precision LBS_FP64: every matvec in FP64.  LBS_MIXED: iterative
+ * refinement, outer residual with the FP64 operator, inner GMRES with the
+ * FP32 far field to opt.inner_tol.  Writes sigma (N x nrhs) and the
+ * log-source strengths A (M x nrhs); info_host may be NULL.  Synchronizes
+ * `stream` once per GMRES iteration (an 8-byte residual read). */
+lbs_status lbs_solve(lbs_handle h, int32_t precision, int32_t nrhs,
+                     const double *g, double tol, double *sigma, double *A,
+                     lbs_solve_info *info_host, void *stream);
+
+/* Evaluate psi = W sigma + sum_m A_m G(x, c_m) (eq. eqn:u_multi) at
+ * n_targets sphere points xyz_targets (device, T x 3 row-major) for nrhs
+ * density/strength columns; u is device (T x nrhs).  Targets must lie in
+ * the domain, a few node spacings away from every curve (the trapezoidal
+ * rule is used as is); the north pole is allowed.  Synchronous (builds a
+ * target tree on the host). */
+lbs_status lbs_eval(lbs_handle h, int32_t nrhs, const double *sigma,
+                    const double *A, int64_t n_targets,
+                    const double *xyz_targets, double *u, void *stream);
+
+/* Release a handle and its device memory.  NULL is accepted. */
+lbs_status lbs_destroy(lbs_handle h);
+
+/* Message for the last non-OK status returned on this host thread. */
+const char *lbs_last_error(void);
+
+/* Quadtree statistics of a handle: depth, boxes, leaves and the pair counts
+ * of the four interaction lists (U: near-field leaf pairs, V: same-level
+ * M2L pairs, W: multipole-to-target, X: source-to-local). */
+typedef struct {
+  int32_t levels, boxes, leaves, reserved;
+  int64_t u_pairs, v_pairs, w_pairs, x_pairs;
+  int64_t p2p_interactions; /* source-target point pairs of the U lists   */
+} lbs_tree_stats;
+lbs_status lbs_tree_info(lbs_handle h, lbs_tree_stats *stats_host);
+
+/* Host-only check of the quadtree builder (no GPU needed): builds the tree
+ * for n planar points (x_host, y_host) with leaves of at most leaf_max
+ * points and verifies that every ordered point pair (i, j), i != j, is
+ * covered exactly once by the U, V, W and X lists.  *bad_pairs_host gets
+ * the number of pairs covered zero or several times; stats_host may be
+ * NULL.  O(n^2): for small n. */
+lbs_status lbs_check_tree_host(const double *x_host, const double *y_host,
+                               int64_t n, int32_t leaf_max,
+                               int64_t *bad_pairs_host,
+                               lbs_tree_stats *stats_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBS_H */

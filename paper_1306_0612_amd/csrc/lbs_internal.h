@@ -1,0 +1,222 @@
+// Internal declarations shared by the host driver (api.cpp) and the HIP
+// kernel files.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lbs.h"
+#include "tree.h"
+
+namespace lbs {
+
+struct HipError {
+  hipError_t code;
+  std::string where;
+};
+struct ApiError {
+  lbs_status code;
+  std::string msg;
+};
+
+#define LBS_HIP(call)                                                     \
+  do {                                                                    \
+    hipError_t e_ = (call);                                               \
+    if (e_ != hipSuccess)                                                 \
+      throw ::lbs::HipError{e_, std::string(#call) + " @" __FILE__ ":" +   \
+                                    std::to_string(__LINE__)};            \
+  } while (0)
+
+// Device buffer with RAII release.
+template <typename T>
+struct DBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count == 0) return;
+    hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      n = 0;
+      if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        throw ApiError{LBS_ERR_OUT_OF_MEMORY,
+                       "device allocation of " +
+                           std::to_string(count * sizeof(T)) + " bytes"};
+      throw HipError{e, "hipMalloc"};
+    }
+  }
+  void upload(const std::vector<T> &v, hipStream_t s) {
+    alloc(v.size());
+    if (!v.empty())
+      LBS_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T),
+                             hipMemcpyHostToDevice, s));
+  }
+  std::vector<T> download(hipStream_t s) const {
+    std::vector<T> v(n);
+    if (n) {
+      LBS_HIP(hipMemcpyAsync(v.data(), p, n * sizeof(T),
+                             hipMemcpyDeviceToHost, s));
+      LBS_HIP(hipStreamSynchronize(s));
+    }
+    return v;
+  }
+};
+
+// Quadtree and lists on the device (one FMM plan).
+struct DevPlan {
+  int nbox = 0, nlevels = 0;
+  int64_t ns = 0, nt = 0;
+  bool self = true;
+  std::vector<int32_t> level_ptr;            // host copy
+  std::vector<int32_t> leaf_t_host;          // leaves with targets
+  int n_leaf_t = 0, n_leaf_s = 0, n_m2l = 0;
+  DBuf<double> cx, cy, rad;
+  DBuf<int32_t> parent, child0, nchild, quad, lev;
+  DBuf<int64_t> s0, s1, t0, t1;
+  DBuf<uint8_t> leaf, has_tgt;
+  DBuf<int32_t> v_ptr, v_src, x_ptr, x_src, u_ptr, u_src, w_ptr, w_src;
+  DBuf<uint8_t> v_code;
+  DBuf<int32_t> leaf_t, leaf_s, m2l_box;     // work lists
+  // points in tree order
+  DBuf<double> sx, sy, tx, ty;
+  DBuf<float> sxh, sxl, syh, syl, txh, txl, tyh, tyl;  // FP32 hi/lo
+  DBuf<int64_t> src_perm, tgt_perm;
+  Tree host;                                  // host tree (statistics)
+};
+
+// Translation tables for expansions of P terms (see fmm.hip).
+struct Tables {
+  int P = 0;
+  DBuf<double> m2m64, l2l64, h64, itp64;  // complex pairs interleaved
+  DBuf<float> m2m32, l2l32, h32, itp32;
+};
+
+// One geometry handle.
+struct Geometry {
+  int64_t N = 0;
+  int M = 0;
+  std::vector<int32_t> nodes;        // per island
+  std::vector<int64_t> offs;         // node offset per island (M+1)
+  std::vector<double> sign;          // orientation sign per island
+  std::vector<double> cxyz;          // centres (M x 3)
+  std::vector<double> eta_x, eta_y;  // projected centres
+  std::vector<double> rho;           // planar island radius about eta
+  // device, API order
+  DBuf<double> xyz;                  // N x 3
+  DBuf<double> xi, dxi, ddxi;        // complex interleaved (N x 2)
+  DBuf<double> qfac;                 // (s h / pi) xi'   complex (N x 2)
+  DBuf<double> tau;                  // -(s h / 2 pi) Im(xi''/xi')
+  DBuf<double> gw;                   // (s h / pi) Im(conj(xi) xi' / (1+|xi|^2))
+  DBuf<double> ell;                  // log(1 + |xi|^2)
+  DBuf<int32_t> island;              // island of each node
+  DBuf<double> qfac_t;               // qfac in tree order
+  DBuf<double> dcenter, deta, drho, dellc;  // centres, eta, rho, log(1+|eta|^2)
+  DBuf<int64_t> doffs;
+  DBuf<int32_t> near_ptr, near_idx;  // near centres per island (log sources)
+  DBuf<double> Sinv;                 // M x M inverse Schur complement
+};
+
+struct Workspace {
+  int nrhs_cap = 0;
+  DBuf<double> pstr64, mult64, loc64;
+  DBuf<float> pstr32, mult32, loc32;
+  DBuf<double> gam;       // per rhs
+  DBuf<double> red;       // reduction scratch
+  DBuf<double> tmpN, tmpM, tmpM2, logL;
+  void ensure(const DevPlan &pl, int P64, int P32, int nrhs, int64_t N,
+              int M, int Plog);
+};
+
+constexpr int kPlog = 30;  // terms of the per-island log-source expansions
+
+// ----- launchers (HIP files) ------------------------------------------
+void build_tables(Tables &t, int P, hipStream_t s);
+void launch_geometry(const lbs_island *isl_dev, int M, const int64_t *offs_dev,
+                     const int32_t *island_dev, int64_t N, double *xyz,
+                     double *xi, double *dxi, double *ddxi, hipStream_t s);
+void launch_node_coeffs(int64_t N, const int32_t *island, const double *sign,
+                        const int64_t *offs, const double *xi,
+                        const double *dxi, const double *ddxi, double *qfac,
+                        double *tau, double *gw, double *ell, hipStream_t s);
+void launch_permute_complex(int64_t n, const int64_t *perm, const double *in,
+                            double *out, hipStream_t s);
+
+// far field: y_field[perm] = scale * Re sum_j p_j / (z_i - z_j) (+ assembly)
+struct Assembly {
+  const double *sigma = nullptr;  // API order, stride ldx (null: no terms)
+  const double *tau = nullptr;    // diagonal coefficient per node
+  const double *gamma = nullptr;  // per rhs constant added to every row
+  double ident = 0.0;             // coefficient of sigma (1 for I + K)
+  int64_t ldx = 0;
+};
+void fmm_apply64(const DevPlan &pl, const Tables &tb, Workspace &ws,
+                 const double *qfac_t, const double *sigma, int64_t ldx,
+                 int nrhs, double *out, int64_t ldy, double scale,
+                 const Assembly &as, hipStream_t s);
+void fmm_apply32(const DevPlan &pl, const Tables &tb, Workspace &ws,
+                 const double *qfac_t, const double *sigma, int64_t ldx,
+                 int nrhs, double *out, int64_t ldy, double scale,
+                 const Assembly &as, hipStream_t s);
+void direct_apply64(int64_t N, const double *xi, const double *qfac,
+                    const double *sigma, int64_t ldx, int nrhs, double *out,
+                    int64_t ldy, const Assembly &as, hipStream_t s);
+void direct_eval64(int64_t N, const double *xi, const double *qfac,
+                   const double *sigma, int64_t ldx, int64_t T,
+                   const double *txi, const uint8_t *pole, int nrhs,
+                   double *out, int64_t ldy, double scale, hipStream_t s);
+
+// dot products: out[r] = sum_i a[r*lda + i] * b[r*ldb + i], i < n
+void launch_dots(int64_t n, int nrhs, const double *a, int64_t lda,
+                 const double *b, int64_t ldb, double *out, double *scratch,
+                 hipStream_t s);
+
+// log sources and constraint rows (solver.hip)
+void launch_logsrc_apply(const Geometry &g, Workspace &ws, const double *z,
+                         int64_t ldz, int nrhs, double *out, int64_t ldo,
+                         double alpha, hipStream_t s);
+void launch_island_sums(const Geometry &g, const double *y, int64_t ldy,
+                        int nrhs, double *out, int64_t ldo, hipStream_t s);
+void launch_constraint_rows(const Geometry &g, const double *sigma,
+                            int64_t ldx, const double *A, int64_t lda,
+                            int nrhs, double *out, int64_t ldo,
+                            hipStream_t s);
+void launch_build_schur(const Geometry &g, double *S, hipStream_t s);
+void invert_dense(int M, double *S, double *Sinv, hipStream_t s);
+void launch_gemv(int M, const double *A, const double *x, int64_t ldx,
+                 int nrhs, double *y, int64_t ldy, double alpha,
+                 hipStream_t s);
+void launch_eval_logsrc(int64_t T, const double *txyz, int M,
+                        const double *cxyz, const double *A, int64_t lda,
+                        int nrhs, const double *add, double *u, int64_t ldu,
+                        hipStream_t s);
+
+// GMRES building blocks (solver.hip)
+void launch_maxpy(int64_t n, int k1, const double *V, int64_t ldv,
+                  const double *h, double *w, double *hacc, hipStream_t s);
+void launch_update(int64_t n, int k, const double *V, int64_t ldv,
+                   const double *y, double *x, hipStream_t s);
+void launch_normalize(int64_t n, const double *nrm2, const double *w,
+                      double *v, double *hout, hipStream_t s);
+void launch_axpby(int64_t n, double a, const double *x, double b, double *y,
+                  hipStream_t s);
+void launch_fill(int64_t n, double v, double *x, hipStream_t s);
+void launch_givens(int k, int m, double *H, double *cs, double *sn,
+                   double *gvec, double *resid, hipStream_t s);
+void launch_backsolve(int k, int m, const double *H, const double *gvec,
+                      double *y, hipStream_t s);
+void launch_init_g(int m, const double *nrm2, double *g, hipStream_t s);
+
+}  // namespace lbs

@@ -1,0 +1,56 @@
+// Adaptive quadtree and the four interaction lists of the adaptive 2D FMM
+// (host side, plain C++; no GPU needed).
+//
+// The paper evaluates every product with I + K by the 2D Coulomb FMM on an
+// adaptive quadtree that is refined until no leaf holds more than a preset
+// number of points (Section 5; Section 6, Example 3).  Lists (for a box b):
+//   U(b)  leaf b: leaves adjacent to b, b included          -> direct sum
+//   V(b)  children of the parent's colleagues not adjacent to b -> M2L
+//   W(b)  leaf b: descendants of b's colleagues that are not adjacent to b
+//         while their parent is                               -> M2P
+//   X(b)  leaves c with b in W(c)                              -> P2L
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace lbs {
+
+constexpr int kMaxLevel = 29;   // Morton keys of 29 bits per axis
+
+struct Tree {
+  double x0 = 0, y0 = 0, R0 = 1;  // root centre and half-width
+  int nlevels = 0;                // number of levels present (root = 0)
+  bool self = true;               // targets are the sources
+  // boxes in level-major order; children of a box are contiguous
+  std::vector<double> cx, cy, rad;
+  std::vector<int32_t> level, parent, child0, nchild, ix, iy;
+  std::vector<int64_t> s0, s1, t0, t1;  // source / target ranges (sorted)
+  std::vector<uint8_t> leaf;
+  std::vector<int32_t> level_ptr;       // boxes of level l: [lp[l], lp[l+1])
+  // CSR lists over boxes
+  std::vector<int32_t> v_ptr, v_src;
+  std::vector<uint8_t> v_code;          // (dx + 3) * 7 + (dy + 3)
+  std::vector<int32_t> x_ptr, x_src;
+  std::vector<int32_t> u_ptr, u_src;
+  std::vector<int32_t> w_ptr, w_src;
+  std::vector<int64_t> src_perm, tgt_perm;  // sorted position -> input index
+  int64_t p2p_pairs = 0;
+
+  int nbox() const { return (int)cx.size(); }
+};
+
+// Build the tree over ns source points and nt target points.  With
+// self == true the targets are the sources (tx, ty, nt ignored).  A box is
+// split while it holds more than leaf_max points (sources + targets, or
+// sources when self) and its level is below kMaxLevel.  Lists keep only
+// pairs that move information from a box holding sources to one holding
+// targets.
+void build_tree(const double *sx, const double *sy, int64_t ns,
+                const double *tx, const double *ty, int64_t nt, bool self,
+                int leaf_max, Tree &T);
+
+// Count ordered point pairs (i in targets, j in sources, i != j when self)
+// covered zero or several times by U, V, W and X.  O(leaves^2 depth).
+int64_t check_coverage(const Tree &T);
+
+}  // namespace lbs

@@ -1,0 +1,268 @@
+"""Python binding of liblbs (include/lbs.h): argument marshalling only.
+
+Device arrays are torch tensors on the GPU (float64, contiguous); streams are
+torch's current stream.  Every computation runs in the HIP library; there is
+no fallback: if liblbs.so is missing or the GPU is absent, calls raise.
+Multi-right-hand-side arrays are tensors of shape (nrhs, n), i.e. the
+column-major (n x nrhs) layout of the C-ABI.
+"""
+import ctypes
+import os
+
+import torch  # loads the HIP runtime that liblbs shares
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbs.so")
+
+LBS_FP64, LBS_MIXED = 0, 1
+OPS = {"iplusk": 0, "k": 1, "system": 2, "precond": 3}
+PRECISIONS = {"fp64": LBS_FP64, "mixed": LBS_MIXED, "fp32": LBS_MIXED}
+STATUS = {0: "LBS_OK", 1: "LBS_ERR_INVALID_ARG", 2: "LBS_ERR_GEOMETRY",
+          3: "LBS_ERR_NO_CONVERGENCE", 4: "LBS_ERR_NOT_FINITE",
+          5: "LBS_ERR_OUT_OF_MEMORY", 6: "LBS_ERR_HIP",
+          7: "LBS_ERR_UNSUPPORTED"}
+
+c_double_p = ctypes.POINTER(ctypes.c_double)
+
+
+class Island(ctypes.Structure):
+    _fields_ = [("center", ctypes.c_double * 3), ("e1", ctypes.c_double * 3),
+                ("r0", ctypes.c_double), ("coef", ctypes.c_double * 16)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("p64", ctypes.c_int32), ("p32", ctypes.c_int32),
+                ("leaf_max", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("matvec", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer_steps", ctypes.c_int32),
+                ("rel_resid", ctypes.c_double), ("ms_solve", ctypes.c_double),
+                ("fp64_matvecs", ctypes.c_int32),
+                ("fp32_matvecs", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TreeStats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("boxes", ctypes.c_int32),
+                ("leaves", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("u_pairs", ctypes.c_int64), ("v_pairs", ctypes.c_int64),
+                ("w_pairs", ctypes.c_int64), ("x_pairs", ctypes.c_int64),
+                ("p2p_interactions", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_
+                if f != "reserved"}
+
+
+class LBSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+_lib = None
+
+
+def load():
+    """Load liblbs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblbs.so is not built; run "
+                           "`python -m paper_1306_0612_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    H = ctypes.c_void_p
+    vp = ctypes.c_void_p
+    lib.lbs_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.lbs_default_options.restype = None
+    lib.lbs_last_error.argtypes = []
+    lib.lbs_last_error.restype = ctypes.c_char_p
+    lib.lbs_setup.argtypes = [ctypes.POINTER(Island), ctypes.c_int32,
+                              ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(Options), vp,
+                              ctypes.POINTER(H)]
+    lib.lbs_sizes.argtypes = [H, ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int32)]
+    lib.lbs_nodes.argtypes = [H, vp, vp]
+    lib.lbs_matvec.argtypes = [H, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.c_int32, vp, vp, vp]
+    lib.lbs_solve.argtypes = [H, ctypes.c_int32, ctypes.c_int32, vp,
+                              ctypes.c_double, vp, vp,
+                              ctypes.POINTER(SolveInfo), vp]
+    lib.lbs_eval.argtypes = [H, ctypes.c_int32, vp, vp, ctypes.c_int64, vp,
+                             vp, vp]
+    lib.lbs_destroy.argtypes = [H]
+    lib.lbs_tree_info.argtypes = [H, ctypes.POINTER(TreeStats)]
+    lib.lbs_check_tree_host.argtypes = [c_double_p, c_double_p,
+                                        ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(TreeStats)]
+    for name in ("lbs_setup", "lbs_sizes", "lbs_nodes", "lbs_matvec",
+                 "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
+                 "lbs_check_tree_host"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != 0:
+        msg = load().lbs_last_error()
+        raise LBSError(code, msg.decode() if msg else "")
+
+
+def default_options(**kw):
+    o = Options()
+    load().lbs_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "matvec":
+            v = {"fmm": 0, "direct": 1}.get(v, v)
+        setattr(o, k, v)
+    return o
+
+
+def islands_array(isl):
+    """ctypes array of Island from an object with center, e1, r0, coef."""
+    m = len(isl.r0)
+    arr = (Island * m)()
+    for k in range(m):
+        arr[k].center[:] = [float(v) for v in isl.center[k]]
+        arr[k].e1[:] = [float(v) for v in isl.e1[k]]
+        arr[k].r0 = float(isl.r0[k])
+        arr[k].coef[:] = [float(v) for v in isl.coef[k]]
+    return arr
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, n=None):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and
+            t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _rhs(t, n):
+    if t.dim() == 1:
+        if t.shape[0] != n:
+            raise ValueError("length %d, expected %d" % (t.shape[0], n))
+        return 1
+    if t.dim() != 2 or t.shape[1] != n:
+        raise ValueError("shape %s, expected (nrhs, %d)" % (tuple(t.shape), n))
+    return t.shape[0]
+
+
+class Solver:
+    """One island geometry on the GPU (lbs_setup ... lbs_destroy)."""
+
+    def __init__(self, islands, nodes=None, options=None, **kw):
+        lib = load()
+        arr = islands_array(islands)
+        n = islands.n if nodes is None else nodes
+        m = len(islands.r0)
+        nn = (ctypes.c_int32 * m)(*[int(v) for v in
+                                    (n if hasattr(n, "__len__") else [n] * m)])
+        self.options = options if options is not None else default_options(**kw)
+        h = ctypes.c_void_p()
+        _check(lib.lbs_setup(arr, m, nn, ctypes.byref(self.options), _stream(),
+                             ctypes.byref(h)))
+        self._h = h
+        nt = ctypes.c_int64()
+        mt = ctypes.c_int32()
+        _check(lib.lbs_sizes(h, ctypes.byref(nt), ctypes.byref(mt)))
+        self.n_nodes, self.n_islands = nt.value, mt.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lbs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def nodes(self):
+        out = torch.empty((self.n_nodes, 3), dtype=torch.float64, device="cuda")
+        _check(load().lbs_nodes(self._h, _dev(out), _stream()))
+        return out
+
+    def matvec(self, x, op="iplusk", precision="fp64", out=None):
+        n = self.n_nodes + (self.n_islands if op in ("system", "precond")
+                            else 0)
+        nrhs = _rhs(x, n)
+        y = torch.empty_like(x) if out is None else out
+        _check(load().lbs_matvec(self._h, OPS[op], PRECISIONS[precision], nrhs,
+                                 _dev(x), _dev(y), _stream()))
+        return y
+
+    def solve(self, g, tol=1e-12, precision="fp64", check=True):
+        nrhs = _rhs(g, self.n_nodes)
+        shape = (self.n_nodes,) if g.dim() == 1 else (nrhs, self.n_nodes)
+        sig = torch.empty(shape, dtype=torch.float64, device="cuda")
+        a = torch.empty(shape[:-1] + (self.n_islands,), dtype=torch.float64,
+                        device="cuda")
+        info = SolveInfo()
+        code = load().lbs_solve(self._h, PRECISIONS[precision], nrhs, _dev(g),
+                                float(tol), _dev(sig), _dev(a),
+                                ctypes.byref(info), _stream())
+        if check:
+            _check(code)
+        d = info.as_dict()
+        d["status"] = STATUS.get(code, code)
+        return sig, a, d
+
+    def eval(self, sigma, A, targets):
+        nrhs = _rhs(sigma, self.n_nodes)
+        t = targets.shape[0]
+        shape = (t,) if sigma.dim() == 1 else (nrhs, t)
+        u = torch.empty(shape, dtype=torch.float64, device="cuda")
+        _check(load().lbs_eval(self._h, nrhs, _dev(sigma), _dev(A), t,
+                               _dev(targets), _dev(u), _stream()))
+        return u
+
+    def tree_info(self):
+        st = TreeStats()
+        _check(load().lbs_tree_info(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+
+def check_tree_host(x, y, leaf_max):
+    """Host-only quadtree coverage check (see lbs_check_tree_host)."""
+    import numpy as np
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    bad = ctypes.c_int64()
+    st = TreeStats()
+    _check(load().lbs_check_tree_host(
+        x.ctypes.data_as(c_double_p), y.ctypes.data_as(c_double_p),
+        x.shape[0], int(leaf_max), ctypes.byref(bad), ctypes.byref(st)))
+    return bad.value, st.as_dict()
+
+
+def setup_status(islands, nodes=None, **kw):
+    """Status name returned by lbs_setup for this input, without keeping the
+    handle (for validation tests)."""
+    lib = load()
+    arr = islands_array(islands)
+    m = len(islands.r0)
+    n = islands.n if nodes is None else nodes
+    nn = (ctypes.c_int32 * m)(*[int(v) for v in
+                                (n if hasattr(n, "__len__") else [n] * m)])
+    opts = default_options(**kw)
+    h = ctypes.c_void_p()
+    code = lib.lbs_setup(arr, m, nn, ctypes.byref(opts), None, ctypes.byref(h))
+    if code == 0:
+        lib.lbs_destroy(h)
+    return STATUS.get(code, code)

@@ -1,0 +1,103 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every declared symbol, validates its input before touching the GPU, and its
+quadtree builder covers every point pair exactly once."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.geometry import Curves
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lbs():
+    from paper_1306_0612_amd import lbs as mod
+    if not os.path.exists(mod.LIB_PATH):
+        from paper_1306_0612_amd import build
+        build.build()
+    mod.load()
+    return mod
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lbs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbs_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(lbs):
+    names = _declared()
+    assert "lbs_setup" in names and "lbs_solve" in names
+    lib = lbs.load()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_default_options(lbs):
+    o = lbs.default_options()
+    assert (o.p64, o.p32, o.restart) == (30, 16, 50)
+    assert o.inner_tol == 1e-5
+
+
+@pytest.mark.parametrize("case", ["uniform", "curves", "clustered", "tiny"])
+def test_quadtree_covers_each_pair_once(lbs, case):
+    rng = np.random.default_rng(1)
+    if case == "uniform":
+        x, y, lm = rng.random(1500), rng.random(1500), 12
+    elif case == "curves":
+        cv = Curves(synth.star_islands(11, 6, (0.1, 0.3), nodes=150))
+        x, y, lm = cv.xi.real, cv.xi.imag, 16
+    elif case == "clustered":
+        x = np.concatenate([rng.random(300) * 1e-7, 1 + rng.random(300)])
+        y = np.concatenate([rng.random(300) * 1e-7, rng.random(300)])
+        lm = 5
+    else:
+        x, y, lm = np.array([0.0, 1.0, 0.5]), np.array([0.0, 1.0, 0.25]), 1
+    bad, st = lbs.check_tree_host(x, y, lm)
+    assert bad == 0, st
+    assert st["leaves"] >= 1
+
+
+def test_quadtree_depth_grows_with_clustering(lbs):
+    """Points crowded near one spot force a deep adaptive tree, as under the
+    stereographic distortion of Section 6, Example 3."""
+    rng = np.random.default_rng(2)
+    _, shallow = lbs.check_tree_host(rng.random(400), rng.random(400), 8)
+    x = np.concatenate([rng.random(200), 0.5 + 1e-6 * rng.random(200)])
+    y = np.concatenate([rng.random(200), 0.5 + 1e-6 * rng.random(200)])
+    _, deep = lbs.check_tree_host(x, y, 8)
+    assert deep["levels"] > shallow["levels"] + 10
+
+
+def _bad_islands(kind):
+    isl = synth.star_islands(3, 4, (0.1, 0.2), nodes=32)
+    if kind == "overlap":
+        isl.center[1] = isl.center[0]
+        isl.e1[1] = isl.e1[0]
+    elif kind == "pole":
+        isl.center[2] = np.array([0.0, 0.0, 1.0])
+        isl.e1[2] = np.array([1.0, 0.0, 0.0])
+    elif kind == "nan":
+        isl.r0[0] = np.nan
+    elif kind == "frame":
+        isl.e1[0] = isl.center[0]
+    elif kind == "radius":
+        isl.coef[0, :] = 0.2
+    return isl
+
+
+@pytest.mark.parametrize("kind", ["overlap", "pole", "nan", "frame",
+                                  "radius"])
+def test_setup_rejects_bad_geometry(lbs, kind):
+    assert lbs.setup_status(_bad_islands(kind)) == "LBS_ERR_GEOMETRY"
+
+
+def test_setup_rejects_bad_options(lbs):
+    isl = synth.star_islands(3, 2, (0.1, 0.2), nodes=32)
+    assert lbs.setup_status(isl, p64=31) == "LBS_ERR_UNSUPPORTED"
+    assert lbs.setup_status(isl, restart=0) == "LBS_ERR_INVALID_ARG"
+    assert lbs.setup_status(isl, nodes=4) == "LBS_ERR_INVALID_ARG"
