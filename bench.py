@@ -1,0 +1,220 @@
+#!/usr/bin/env python
+"""Benchmark: FMM matvecs/s and GMRES solve seconds at 1,024,000 nodes.
+
+Workload: 2000 star islands r0 (1 + 0.3 cos k t), r0 ~ U[0.01, 0.03] rad,
+k ~ U{3..7}, 512 nodes each (seed 5), density sigma ~ N(0, 1) (seed 51).
+A step is one application of (I + K) sigma with the FP32 far field and FP32
+near field (p = 16), FP64 assembly.  Also reported: the FP64 FMM (p = 30)
+matvec rate, GMRES solve seconds to a preconditioned relative residual of
+1e-10 with mixed-precision refinement and with FP64 only (data of the
+paper's examples), the error of the solved u at 1e5 sphere targets against
+the exact solution, per-stage GPU times, the roofline position of the
+dominant kernel and the CPU oracle timed on sampled rows.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("FMM matvecs/s & GMRES solve s at 1M nodes, FP32-mixed vs FP64, "
+          "1e-10 err")
+WORKLOAD = "stars2000x512"
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+# algorithmic FLOP counts (see the roofline section of the design notes)
+FLOP_P2P_PAIR = 11        # Re(p/(z - w)): 2 sub, |d|^2 (3), p.d (3), div, acc
+FLOP_CMAC = 8             # one complex multiply-add
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_matvecs(torch, sol, x, prec, steps, warmup):
+    y = torch.empty_like(x)
+    for _ in range(warmup):
+        sol.matvec(x, "iplusk", prec, out=y)
+    torch.cuda.synchronize()
+    sol.stage_times()
+    sol.stage_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sol.matvec(x, "iplusk", prec, out=y)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sol.stage_timing(False)
+    st = sol.stage_times()
+    return dt, y, {k: v[0] / steps for k, v in st.items() if v[1]}
+
+
+def stage_flops(tree, n_nodes, P):
+    return {
+        "leaf": FLOP_P2P_PAIR * tree["p2p_interactions"]
+        + FLOP_CMAC * P * (n_nodes + tree["m2p_evals"]),
+        "m2l": (4 * P * P + 14 * P) * tree["v_pairs"]
+        + FLOP_CMAC * P * tree["p2l_evals"],
+        "p2m": FLOP_CMAC * P * n_nodes,
+    }
+
+
+def cpu_baseline(islands, sigma, rows_n, y64, y32):
+    from threadpoolctl import threadpool_limits
+    from oracle import nystrom
+    from oracle.geometry import Curves
+    cv = Curves(islands)
+    rows = np.sort(np.random.default_rng(52).choice(cv.n, rows_n,
+                                                    replace=False))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        ref = nystrom.apply_iplusk(cv, sigma, rows)
+        dt = time.perf_counter() - t0
+    scale = np.abs(ref).max()
+    return {
+        "value": rows_n / cv.n / dt, "unit": "matvecs/s", "cores": 1,
+        "kind": "oracle",
+        "sample": "%d sampled rows of the direct O(N^2) sum of (I+K) sigma "
+                  "at %d nodes (%.1f s, one thread), scaled to full "
+                  "matvecs" % (rows_n, cv.n, dt),
+    }, {
+        "fmm64_rows_rel_err": float(np.abs(y64[rows] - ref).max() / scale),
+        "fmm32_rows_rel_err": float(np.abs(y32[rows] - ref).max() / scale),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=512)
+    ap.add_argument("--targets", type=int, default=100000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs the solver on one GPU; --gpus %d is not "
+              "supported (the multi-GPU design is documented, not built)"
+              % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+    import synth
+    from paper_1306_0612_amd import lbs
+    lbs.load()
+    dev = torch.device("cuda:0")
+
+    log("generating islands", args.workload)
+    islands = synth.config_islands(args.workload)
+    t0 = time.perf_counter()
+    sol = lbs.Solver(islands)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    N, M = sol.n_nodes, sol.n_islands
+    tree = sol.tree_info()
+    log("setup %.2f s, N=%d M=%d tree=%s" % (setup_s, N, M, tree))
+    sigma = synth.random_vector(51, N)
+    x = torch.tensor(sigma, dtype=torch.float64, device=dev)
+
+    dt32, y32, st32 = timed_matvecs(torch, sol, x, "mixed", args.steps,
+                                    args.warmup)
+    log("mixed matvec %.3f ms" % (1e3 * dt32 / args.steps), st32)
+    k64 = max(1, args.steps // 2)
+    dt64, y64, st64 = timed_matvecs(torch, sol, x, "fp64", k64,
+                                    max(1, args.warmup // 2))
+    log("fp64 matvec %.3f ms" % (1e3 * dt64 / k64), st64)
+    y32n, y64n = y32.cpu().numpy(), y64.cpu().numpy()
+    mixed_vs_fp64 = float(np.abs(y32n - y64n).max() / np.abs(y64n).max())
+
+    P32, P64 = sol.options.p32, sol.options.p64
+    fl32 = stage_flops(tree, N, P32)
+    dom = max(st32, key=st32.get)
+    dom_ms = st32[dom]
+    if dom in fl32:
+        achieved = fl32[dom] / (dom_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": "k_%s32 (%s stage)" % (dom, dom),
+                    "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                    "traffic": None, "avg_ms": dom_ms,
+                    "flop_per_launch": fl32[dom]}
+    else:
+        roofline = {"bound": "alu", "kernel": dom, "achieved": None,
+                    "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "frac": None, "traffic": None, "avg_ms": dom_ms}
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / dt32,
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2000 star islands x 512 nodes (1,024,000 "
+                               "nodes), (I+K) sigma by FMM, FP32 far and "
+                               "near field p=16, FP64 assembly",
+                   "islands": M, "nodes": N, "p32": P32, "p64": P64,
+                   "leaf_max": sol.options.leaf_max},
+        "fp64_matvecs_per_s": k64 / dt64,
+        "fp64_ms_per_matvec": 1e3 * dt64 / k64,
+        "mixed_vs_fp64_matvec_rel": mixed_vs_fp64,
+        "setup_s": setup_s,
+        "stages_ms_mixed": st32,
+        "stages_ms_fp64": st64,
+        "tree": tree,
+        "roofline": roofline,
+    }
+
+    if not args.no_solve:
+        xyz = sol.nodes().cpu().numpy()
+        coeffs = synth.paper_data_coeffs(M)
+        g = torch.tensor(synth.exact_harmonic(xyz, islands.center, coeffs),
+                         dtype=torch.float64, device=dev)
+        tg = synth.sphere_targets(55, args.targets, islands)
+        exact = synth.exact_harmonic(tg, islands.center, coeffs)
+        tgd = torch.tensor(tg, dtype=torch.float64, device=dev)
+        for prec in ("mixed", "fp64"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s, a, info = sol.solve(g, tol=1e-10, precision=prec, check=False)
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            u = sol.eval(s, a, tgd)
+            torch.cuda.synchronize()
+            te = time.perf_counter() - t0
+            err = np.abs(u.cpu().numpy() - exact).max() / np.abs(exact).max()
+            out["solve_s_" + prec] = ts
+            out["solve_" + prec] = {k: info[k] for k in (
+                "status", "iters", "outer_steps", "rel_resid",
+                "fp64_matvecs", "fp32_matvecs")}
+            out["u_rel_err_" + prec] = float(err)
+            out["eval_s_" + prec] = te
+            log(prec, "solve %.3f s" % ts, info, "u err %.2e" % err)
+
+    if not args.no_cpu_baseline:
+        cb, acc = cpu_baseline(islands, sigma, args.cpu_rows, y64n, y32n)
+        out["cpu_baseline"] = cb
+        out.update(acc)
+        log("cpu baseline", cb, acc)
+    sol.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -157,6 +157,26 @@ lbs_status lbs_eval(lbs_handle h, int32_t nrhs, const double *sigma,
                     const double *A, int64_t n_targets,
                     const double *xyz_targets, double *u, void *stream);
 
+/* Per-stage GPU timing of operator applications.  With enable != 0 every
+ * stage of every later lbs_matvec / lbs_solve call is bracketed by a pair
+ * of HIP events recorded on the call's stream; lbs_stage_times waits for
+ * them, returns the accumulated milliseconds and interval counts per stage
+ * (n >= LBS_NSTAGES entries, indexed by LBS_STAGE_*) and resets them.  The
+ * M2M and L2L stages cover all tree levels of one application. */
+enum { LBS_STAGE_STRENGTHS = 0, /* p_j = -i q_j sigma_j, tree order       */
+       LBS_STAGE_P2M = 1,       /* leaf multipoles                         */
+       LBS_STAGE_M2M = 2,       /* upward pass, all levels                 */
+       LBS_STAGE_M2L = 3,       /* V-list M2L and X-list P2L, all boxes    */
+       LBS_STAGE_L2L = 4,       /* downward pass, all levels               */
+       LBS_STAGE_LEAF = 5,      /* L2P + W-list M2P + U-list P2P + assembly*/
+       LBS_STAGE_GAMMA = 6,     /* correction-term reduction               */
+       LBS_STAGE_LOGSRC = 7,    /* log-source product E z                  */
+       LBS_STAGE_CONSTRAINT = 8,/* F y and the Schur-complement solve      */
+       LBS_NSTAGES = 9 };
+lbs_status lbs_stage_timing(lbs_handle h, int32_t enable);
+lbs_status lbs_stage_times(lbs_handle h, double *ms_host,
+                           int64_t *launches_host, int32_t n);
+
 /* Release a handle and its device memory.  NULL is accepted. */
 lbs_status lbs_destroy(lbs_handle h);
 
@@ -170,6 +190,8 @@ typedef struct {
   int32_t levels, boxes, leaves, reserved;
   int64_t u_pairs, v_pairs, w_pairs, x_pairs;
   int64_t p2p_interactions; /* source-target point pairs of the U lists   */
+  int64_t m2p_evals;        /* (W box, target point) multipole evaluations*/
+  int64_t p2l_evals;        /* (X source point, box) local contributions  */
 } lbs_tree_stats;
 lbs_status lbs_tree_info(lbs_handle h, lbs_tree_stats *stats_host);
 

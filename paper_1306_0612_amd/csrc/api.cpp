@@ -174,6 +174,7 @@ struct lbs_ctx {
   Tables tab64, tab32;
   Workspace ws;
   std::vector<double> xi_x, xi_y;  // node images, API order (eval trees)
+  StageTimer timer;
   // GMRES state (vector length n = N + M)
   int64_t n = 0;
   DBuf<double> V, H, cs, sn, gv, yv, h2, nrm2, resid, bvec, rvec, xvec, dvec;
@@ -189,7 +190,10 @@ void apply_K(lbs_ctx &c, int prec, int nrhs, const double *x, int64_t ldx,
              double *y, int64_t ldy, double ident, hipStream_t s) {
   Geometry &g = c.geo;
   c.ws.ensure(c.plan, c.opt.p64, c.opt.p32, nrhs, g.N, g.M, kPlog);
-  launch_dots(g.N, nrhs, g.gw.p, 0, x, ldx, c.ws.gam.p, c.ws.red.p, s);
+  {
+    TimerScope ts(c.ws.timer, ST_GAMMA, s);
+    launch_dots(g.N, nrhs, g.gw.p, 0, x, ldx, c.ws.gam.p, c.ws.red.p, s);
+  }
   Assembly as;
   as.sigma = x;
   as.tau = g.tau.p;
@@ -197,6 +201,7 @@ void apply_K(lbs_ctx &c, int prec, int nrhs, const double *x, int64_t ldx,
   as.ident = ident;
   as.ldx = ldx;
   if (c.opt.matvec == LBS_MATVEC_DIRECT) {
+    TimerScope ts(c.ws.timer, ST_LEAF, s);
     direct_apply64(g.N, g.xi.p, g.qfac.p, x, ldx, nrhs, y, ldy, as, s);
   } else if (prec == LBS_FP64) {
     fmm_apply64(c.plan, c.tab64, c.ws, g.qfac_t.p, x, ldx, nrhs, y, ldy, 1.0,
@@ -213,9 +218,15 @@ void apply_precond_op(lbs_ctx &c, int prec, int nrhs, const double *x,
   Geometry &g = c.geo;
   const int64_t n = g.N + g.M;
   apply_K(c, prec, nrhs, x, n, y, n, 0.0, s);
-  launch_island_sums(g, y, n, nrhs, c.ws.tmpM.p, g.M, s);
-  launch_gemv(g.M, g.Sinv.p, c.ws.tmpM.p, g.M, nrhs, y + g.N, n, -1.0, s);
-  launch_logsrc_apply(g, c.ws, y + g.N, n, nrhs, y, n, -1.0, s);
+  {
+    TimerScope ts(c.ws.timer, ST_CONSTRAINT, s);
+    launch_island_sums(g, y, n, nrhs, c.ws.tmpM.p, g.M, s);
+    launch_gemv(g.M, g.Sinv.p, c.ws.tmpM.p, g.M, nrhs, y + g.N, n, -1.0, s);
+  }
+  {
+    TimerScope ts(c.ws.timer, ST_LOGSRC, s);
+    launch_logsrc_apply(g, c.ws, y + g.N, n, nrhs, y, n, -1.0, s);
+  }
   launch_axpby(n * nrhs, 1.0, x, 1.0, y, s);
 }
 
@@ -225,7 +236,11 @@ void apply_system(lbs_ctx &c, int prec, int nrhs, const double *x, double *y,
   Geometry &g = c.geo;
   const int64_t n = g.N + g.M;
   apply_K(c, prec, nrhs, x, n, y, n, 1.0, s);
-  launch_logsrc_apply(g, c.ws, x + g.N, n, nrhs, y, n, 1.0, s);
+  {
+    TimerScope ts(c.ws.timer, ST_LOGSRC, s);
+    launch_logsrc_apply(g, c.ws, x + g.N, n, nrhs, y, n, 1.0, s);
+  }
+  TimerScope ts(c.ws.timer, ST_CONSTRAINT, s);
   launch_constraint_rows(g, x, n, x + g.N, n, nrhs, y + g.N, n, s);
 }
 
@@ -712,6 +727,32 @@ lbs_status lbs_eval(lbs_handle h, int32_t nrhs, const double *sigma, const doubl
   });
 }
 
+lbs_status lbs_stage_timing(lbs_handle h, int32_t enable) {
+  return guard([&] {
+    check_handle(h);
+    if (enable) {
+      h->ws.timer = &h->timer;
+    } else {
+      h->timer.collect();
+      h->ws.timer = nullptr;
+    }
+  });
+}
+
+lbs_status lbs_stage_times(lbs_handle h, double *ms, int64_t *launches, int32_t n) {
+  return guard([&] {
+    check_handle(h);
+    if (!ms || n < ST_NSTAGES) fail(LBS_ERR_INVALID_ARG, "need LBS_NSTAGES entries");
+    h->timer.collect();
+    for (int i = 0; i < ST_NSTAGES; ++i) {
+      ms[i] = h->timer.ms[i];
+      if (launches) launches[i] = h->timer.cnt[i];
+      h->timer.ms[i] = 0;
+      h->timer.cnt[i] = 0;
+    }
+  });
+}
+
 lbs_status lbs_destroy(lbs_handle h) {
   return guard([&] { delete h; });
 }
@@ -730,6 +771,8 @@ lbs_status lbs_tree_info(lbs_handle h, lbs_tree_stats *st) {
     st->w_pairs = (int64_t)T.w_src.size();
     st->x_pairs = (int64_t)T.x_src.size();
     st->p2p_interactions = T.p2p_pairs;
+    st->m2p_evals = T.m2p_evals;
+    st->p2l_evals = T.p2l_evals;
   });
 }
 
@@ -751,6 +794,8 @@ lbs_status lbs_check_tree_host(const double *x, const double *y, int64_t n, int3
       st->w_pairs = (int64_t)T.w_src.size();
       st->x_pairs = (int64_t)T.x_src.size();
       st->p2p_interactions = T.p2p_pairs;
+      st->m2p_evals = T.m2p_evals;
+      st->p2l_evals = T.p2l_evals;
     }
   });
 }

@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(64)
 template <typename T, int P>
 static void upward_downward(const DevPlan &pl, const Tables &tb,
                             const cx<T> *p, cx<T> *M, cx<T> *L, int nrhs,
-                            hipStream_t s) {
+                            StageTimer *tm, hipStream_t s) {
   const cx<T> *m2m, *l2l, *itp;
   const T *H;
   if constexpr (sizeof(T) == 8) {
@@ -485,11 +485,14 @@ static void upward_downward(const DevPlan &pl, const Tables &tb,
     H = (const T *)tb.h32.p;
   }
   if (pl.n_leaf_s > 0) {
+    TimerScope ts(tm, ST_P2M, s);
     dim3 grid((pl.n_leaf_s + 63) / 64, nrhs);
     hipLaunchKernelGGL((k_p2m<T, P>), grid, dim3(64), 0, s, pl.n_leaf_s,
                        pl.leaf_s.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p,
                        pl.rad.p, pl.sx.p, pl.sy.p, p, pl.ns, M, pl.nbox);
   }
+  {
+  TimerScope ts(tm, ST_M2M, s);
   for (int l = pl.nlevels - 2; l >= 2; --l) {
     int b0 = pl.level_ptr[l], b1 = pl.level_ptr[l + 1];
     int threads = (b1 - b0) * P;
@@ -499,7 +502,9 @@ static void upward_downward(const DevPlan &pl, const Tables &tb,
                        pl.leaf.p, pl.child0.p, pl.nchild.p, pl.quad.p,
                        pl.s0.p, pl.s1.p, m2m, M, pl.nbox);
   }
+  }
   if (pl.n_m2l > 0) {
+    TimerScope ts(tm, ST_M2L, s);
     dim3 grid(pl.n_m2l, nrhs);
     hipLaunchKernelGGL((k_m2l<T, P>), grid, dim3(64), 0, s, pl.n_m2l,
                        pl.m2l_box.p, pl.v_ptr.p, pl.v_src.p, pl.v_code.p,
@@ -507,6 +512,7 @@ static void upward_downward(const DevPlan &pl, const Tables &tb,
                        pl.s0.p, pl.s1.p, pl.sx.p, pl.sy.p, p, pl.ns, H, itp,
                        (const cx<T> *)M, L, pl.nbox);
   }
+  TimerScope ts(tm, ST_L2L, s);
   for (int l = 3; l < pl.nlevels; ++l) {
     int b0 = pl.level_ptr[l], b1 = pl.level_ptr[l + 1];
     int threads = (b1 - b0) * P;
@@ -525,8 +531,9 @@ static void run64(const DevPlan &pl, const Tables &tb, Workspace &ws,
   auto *p = (cx<double> *)ws.pstr64.p;
   auto *M = (cx<double> *)ws.mult64.p;
   auto *L = (cx<double> *)ws.loc64.p;
-  upward_downward<double, P>(pl, tb, p, M, L, nrhs, s);
+  upward_downward<double, P>(pl, tb, p, M, L, nrhs, ws.timer, s);
   if (pl.n_leaf_t > 0) {
+    TimerScope ts(ws.timer, ST_LEAF, s);
     dim3 grid(pl.n_leaf_t, nrhs);
     hipLaunchKernelGGL((k_leaf64<P>), grid, dim3(64), 0, s, pl.leaf_t.p,
                        pl.t0.p, pl.t1.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p,
@@ -545,8 +552,9 @@ static void run32(const DevPlan &pl, const Tables &tb, Workspace &ws,
   auto *p = (cx<float> *)ws.pstr32.p;
   auto *M = (cx<float> *)ws.mult32.p;
   auto *L = (cx<float> *)ws.loc32.p;
-  upward_downward<float, P>(pl, tb, p, M, L, nrhs, s);
+  upward_downward<float, P>(pl, tb, p, M, L, nrhs, ws.timer, s);
   if (pl.n_leaf_t > 0) {
+    TimerScope ts(ws.timer, ST_LEAF, s);
     dim3 grid(pl.n_leaf_t, nrhs);
     hipLaunchKernelGGL((k_leaf32<P>), grid, dim3(64), 0, s, pl.leaf_t.p,
                        pl.t0.p, pl.t1.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p,
@@ -564,6 +572,7 @@ void fmm_apply64(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  int nrhs, double *out, int64_t ldy, double scale,
                  const Assembly &as, hipStream_t s) {
   if (pl.ns > 0) {
+    TimerScope ts(ws.timer, ST_STRENGTHS, s);
     dim3 grid((unsigned)((pl.ns + 255) / 256), nrhs);
     hipLaunchKernelGGL((k_strengths<double>), grid, dim3(256), 0, s, pl.ns,
                        pl.src_perm.p, qfac_t, sigma, ldx,
@@ -588,6 +597,7 @@ void fmm_apply32(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  int nrhs, double *out, int64_t ldy, double scale,
                  const Assembly &as, hipStream_t s) {
   if (pl.ns > 0) {
+    TimerScope ts(ws.timer, ST_STRENGTHS, s);
     dim3 grid((unsigned)((pl.ns + 255) / 256), nrhs);
     hipLaunchKernelGGL((k_strengths<float>), grid, dim3(256), 0, s, pl.ns,
                        pl.src_perm.p, qfac_t, sigma, ldx,

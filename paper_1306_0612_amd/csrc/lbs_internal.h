@@ -129,7 +129,67 @@ struct Geometry {
   DBuf<double> Sinv;                 // M x M inverse Schur complement
 };
 
+// Per-stage GPU timing with HIP events recorded on the launch stream.
+enum Stage {
+  ST_STRENGTHS = 0, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_LEAF, ST_GAMMA,
+  ST_LOGSRC, ST_CONSTRAINT, ST_NSTAGES
+};
+struct StageTimer {
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Pending {
+    int st;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  double ms[ST_NSTAGES] = {};
+  int64_t cnt[ST_NSTAGES] = {};
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      LBS_HIP(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(int st, hipStream_t s) {
+    hipEvent_t a = get();
+    LBS_HIP(hipEventRecord(a, s));
+    pending.push_back({st, a, nullptr});
+  }
+  void end(hipStream_t s) {
+    hipEvent_t b = get();
+    LBS_HIP(hipEventRecord(b, s));
+    pending.back().b = b;
+  }
+  void collect() {
+    for (auto &p : pending) {
+      float f = 0;
+      LBS_HIP(hipEventSynchronize(p.b));
+      LBS_HIP(hipEventElapsedTime(&f, p.a, p.b));
+      ms[p.st] += f;
+      cnt[p.st] += 1;
+    }
+    pending.clear();
+    used = 0;
+  }
+  ~StageTimer() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+struct TimerScope {
+  StageTimer *t;
+  hipStream_t s;
+  TimerScope(StageTimer *t_, int st, hipStream_t s_) : t(t_), s(s_) {
+    if (t) t->begin(st, s);
+  }
+  ~TimerScope() {
+    if (t) t->end(s);
+  }
+};
+
 struct Workspace {
+  StageTimer *timer = nullptr;
   int nrhs_cap = 0;
   DBuf<double> pstr64, mult64, loc64;
   DBuf<float> pstr32, mult32, loc32;

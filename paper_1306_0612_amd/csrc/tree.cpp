@@ -250,12 +250,19 @@ void build_tree(const double *sx, const double *sy, int64_t ns,
     for (auto &e : vl[b]) { T.v_src.push_back(e.first); T.v_code.push_back(e.second); }
     T.v_ptr[b + 1] = (int32_t)T.v_src.size();
   }
-  T.p2p_pairs = 0;
-  for (int b = 0; b < nb; ++b)
+  T.p2p_pairs = T.m2p_evals = T.p2l_evals = 0;
+  for (int b = 0; b < nb; ++b) {
+    const int64_t ntb = T.t1[b] - T.t0[b];
     for (int k = T.u_ptr[b]; k < T.u_ptr[b + 1]; ++k) {
       int s = T.u_src[k];
-      T.p2p_pairs += (T.t1[b] - T.t0[b]) * (T.s1[s] - T.s0[s]);
+      T.p2p_pairs += ntb * (T.s1[s] - T.s0[s]);
     }
+    T.m2p_evals += ntb * (T.w_ptr[b + 1] - T.w_ptr[b]);
+    for (int k = T.x_ptr[b]; k < T.x_ptr[b + 1]; ++k) {
+      int s = T.x_src[k];
+      T.p2l_evals += T.s1[s] - T.s0[s];
+    }
+  }
 }
 
 int64_t check_coverage(const Tree &T) {

@@ -34,7 +34,7 @@ struct Tree {
   std::vector<int32_t> u_ptr, u_src;
   std::vector<int32_t> w_ptr, w_src;
   std::vector<int64_t> src_perm, tgt_perm;  // sorted position -> input index
-  int64_t p2p_pairs = 0;
+  int64_t p2p_pairs = 0, m2p_evals = 0, p2l_evals = 0;
 
   int nbox() const { return (int)cx.size(); }
 };

@@ -23,6 +23,8 @@ STATUS = {0: "LBS_OK", 1: "LBS_ERR_INVALID_ARG", 2: "LBS_ERR_GEOMETRY",
           7: "LBS_ERR_UNSUPPORTED"}
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
+STAGES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "gamma",
+          "logsrc", "constraint")
 
 
 class Island(ctypes.Structure):
@@ -53,7 +55,8 @@ class TreeStats(ctypes.Structure):
                 ("leaves", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("u_pairs", ctypes.c_int64), ("v_pairs", ctypes.c_int64),
                 ("w_pairs", ctypes.c_int64), ("x_pairs", ctypes.c_int64),
-                ("p2p_interactions", ctypes.c_int64)]
+                ("p2p_interactions", ctypes.c_int64),
+                ("m2p_evals", ctypes.c_int64), ("p2l_evals", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_
@@ -100,6 +103,10 @@ def load():
     lib.lbs_eval.argtypes = [H, ctypes.c_int32, vp, vp, ctypes.c_int64, vp,
                              vp, vp]
     lib.lbs_destroy.argtypes = [H]
+    lib.lbs_stage_timing.argtypes = [H, ctypes.c_int32]
+    lib.lbs_stage_times.argtypes = [H, c_double_p,
+                                    ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.c_int32]
     lib.lbs_tree_info.argtypes = [H, ctypes.POINTER(TreeStats)]
     lib.lbs_check_tree_host.argtypes = [c_double_p, c_double_p,
                                         ctypes.c_int64, ctypes.c_int32,
@@ -107,6 +114,7 @@ def load():
                                         ctypes.POINTER(TreeStats)]
     for name in ("lbs_setup", "lbs_sizes", "lbs_nodes", "lbs_matvec",
                  "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
+                 "lbs_stage_timing", "lbs_stage_times",
                  "lbs_check_tree_host"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -231,6 +239,16 @@ class Solver:
         _check(load().lbs_eval(self._h, nrhs, _dev(sigma), _dev(A), t,
                                _dev(targets), _dev(u), _stream()))
         return u
+
+    def stage_timing(self, enable=True):
+        _check(load().lbs_stage_timing(self._h, 1 if enable else 0))
+
+    def stage_times(self):
+        """{stage: (total ms, intervals)} accumulated since the last call."""
+        ms = (ctypes.c_double * len(STAGES))()
+        cnt = (ctypes.c_int64 * len(STAGES))()
+        _check(load().lbs_stage_times(self._h, ms, cnt, len(STAGES)))
+        return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
 
     def tree_info(self):
         st = TreeStats()
