@@ -39,18 +39,24 @@ def log(*a):
 
 
 def timed_matvecs(torch, sol, x, prec, steps, warmup):
+    """Two timed regions of `steps` matvecs each: the first without any
+    event (the rate), the second with HIP events around every stage on the
+    library's stream (per-stage averages)."""
     y = torch.empty_like(x)
     for _ in range(warmup):
         sol.matvec(x, "iplusk", prec, out=y)
-    torch.cuda.synchronize()
-    sol.stage_times()
-    sol.stage_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         sol.matvec(x, "iplusk", prec, out=y)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    sol.stage_times()
+    sol.stage_timing(True)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        sol.matvec(x, "iplusk", prec, out=y)
+    torch.cuda.synchronize()
     sol.stage_timing(False)
     st = sol.stage_times()
     return dt, y, {k: v[0] / steps for k, v in st.items() if v[1]}
@@ -60,9 +66,8 @@ def stage_flops(tree, n_nodes, P):
     return {
         "leaf": FLOP_P2P_PAIR * tree["p2p_interactions"]
         + FLOP_CMAC * P * (n_nodes + tree["m2p_evals"]),
-        "m2l": (4 * P * P + 14 * P) * tree["v_pairs"]
-        + FLOP_CMAC * P * tree["p2l_evals"],
-        "p2m": FLOP_CMAC * P * n_nodes,
+        "m2l": (4 * P * P + 14 * P) * tree["v_pairs"],
+        "p2l": FLOP_CMAC * P * tree["p2l_evals"],
     }
 
 
@@ -100,6 +105,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=512)
     ap.add_argument("--targets", type=int, default=100000)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain elementwise copy kernel that "
+                    "reads and writes BYTES each (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs the solver on one GPU; --gpus %d is not "
@@ -108,6 +116,17 @@ def main():
         return 2
 
     import torch
+    if args.copy_probe:
+        n = args.copy_probe // 8
+        a = torch.rand(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 8 * n,
+                          "copy_probe_bytes_written": 8 * n,
+                          "dispatches": 3}))
+        return 0
     import synth
     from paper_1306_0612_amd import lbs
     lbs.load()
@@ -141,7 +160,10 @@ def main():
     dom_ms = st32[dom]
     if dom in fl32:
         achieved = fl32[dom] / (dom_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "kernel": "k_%s32 (%s stage)" % (dom, dom),
+        kname = {"leaf": "k_leaf32<16>", "m2l": "k_m2l_mfma16",
+                 "p2l": "k_p2l<float,16>"}[dom]
+        roofline = {"bound": "mfma" if dom == "m2l" else "alu",
+                    "kernel": kname,
                     "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                     "traffic": None, "avg_ms": dom_ms,

@@ -118,6 +118,29 @@ lbs_status lbs_setup(const lbs_island *islands_host, int32_t n_islands,
                      const lbs_options *opt_host, void *stream,
                      lbs_handle *out_host);
 
+/* Batch of n_geoms independent geometries in one handle (one FMM forest;
+ * every FMM stage is launched once for all geometries and right-hand
+ * sides).  islands_host and nodes_per_curve_host are concatenated
+ * geometry-major; geometry g owns islands_per_geom_host[g] islands.  Node,
+ * island and data arrays of every later call are geometry-major as well
+ * (API order inside a geometry); each (geometry, right-hand side) pair is
+ * its own system, solved by GMRES in lockstep with its own Hessenberg
+ * matrix and tolerance.  Validation as lbs_setup, per geometry.  The
+ * direct matvec mode is not available for batches.  Synchronous. */
+lbs_status lbs_setup_batch(int32_t n_geoms,
+                           const int32_t *islands_per_geom_host,
+                           const lbs_island *islands_host,
+                           const int32_t *nodes_per_curve_host,
+                           const lbs_options *opt_host, void *stream,
+                           lbs_handle *out_host);
+
+/* Geometry count and the node and island offsets of each geometry
+ * (node_offsets_host: n_geoms + 1 entries, island_offsets_host: same);
+ * either array may be NULL. */
+lbs_status lbs_batch_info(lbs_handle h, int32_t *n_geoms_host,
+                          int64_t *node_offsets_host,
+                          int32_t *island_offsets_host);
+
 /* Total node count N and island count M of a handle. */
 lbs_status lbs_sizes(lbs_handle h, int64_t *n_nodes_host,
                      int32_t *n_islands_host);
@@ -157,18 +180,26 @@ lbs_status lbs_eval(lbs_handle h, int32_t nrhs, const double *sigma,
                     const double *A, int64_t n_targets,
                     const double *xyz_targets, double *u, void *stream);
 
+/* lbs_eval for a batch handle: targets [offsets[g], offsets[g+1]) belong to
+ * geometry g (target_offsets_host: n_geoms + 1 host entries, offsets[0] = 0);
+ * u is (offsets[n_geoms] x nrhs). */
+lbs_status lbs_eval_batch(lbs_handle h, int32_t nrhs, const double *sigma,
+                          const double *A,
+                          const int64_t *target_offsets_host,
+                          const double *xyz_targets, double *u, void *stream);
+
 /* Per-stage GPU timing of operator applications.  With enable != 0 every
  * stage of every later lbs_matvec / lbs_solve call is bracketed by a pair
  * of HIP events recorded on the call's stream; lbs_stage_times waits for
  * them, returns the accumulated milliseconds and interval counts per stage
- * (n >= LBS_NSTAGES entries, indexed by LBS_STAGE_*) and resets them.  The
- * M2M and L2L stages cover all tree levels of one application. */
+ * (n >= LBS_NSTAGES entries, indexed by LBS_STAGE_*) and resets them. */
 enum { LBS_STAGE_STRENGTHS = 0, /* p_j = -i q_j sigma_j, tree order       */
-       LBS_STAGE_P2M = 1,       /* leaf multipoles                         */
-       LBS_STAGE_M2M = 2,       /* upward pass, all levels                 */
-       LBS_STAGE_M2L = 3,       /* V-list M2L and X-list P2L, all boxes    */
-       LBS_STAGE_L2L = 4,       /* downward pass, all levels               */
-       LBS_STAGE_LEAF = 5,      /* L2P + W-list M2P + U-list P2P + assembly*/
+       LBS_STAGE_UPWARD = 1,    /* leaf multipoles + M2M, all levels       */
+       LBS_STAGE_L2L = 2,       /* L2L, all levels                         */
+       LBS_STAGE_M2L = 3,       /* V-list M2L, all boxes                   */
+       LBS_STAGE_P2L = 4,       /* X-list P2L, all boxes                   */
+       LBS_STAGE_LEAF = 5,      /* L2P + W-list M2P + U-list P2P + row     */
+                                /* assembly                                */
        LBS_STAGE_GAMMA = 6,     /* correction-term reduction               */
        LBS_STAGE_LOGSRC = 7,    /* log-source product E z                  */
        LBS_STAGE_CONSTRAINT = 8,/* F y and the Schur-complement solve      */

@@ -1,5 +1,7 @@
 // C-ABI of liblbs (include/lbs.h): set-up, operator application, GMRES
 // solve with the block preconditioner, and evaluation at sphere targets.
+// A handle holds G >= 1 independent island geometries; every right-hand
+// side of every geometry is its own linear system.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -14,8 +16,6 @@ using namespace lbs;
 
 namespace {
 thread_local std::string g_err;
-
-struct ErrNoConv {};
 
 template <class F>
 lbs_status guard(F &&f) {
@@ -46,9 +46,9 @@ bool p64_ok(int p) {
 }
 bool p32_ok(int p) { return p == 12 || p == 16 || p == 20 || p == 24; }
 
-// Upload a host tree as a device plan.  sx/sy (tx/ty) are the source
-// (target) coordinates in input order; tgt_index maps a target's input
-// position to the index written by the leaf kernel.
+// Upload a host tree (or forest) as a device plan.  sx/sy (tx/ty) are the
+// source (target) coordinates in input order; tgt_index maps a target's
+// input position to the index written by the leaf kernel.
 void upload_plan(Tree &T, const double *sx, const double *sy,
                  const double *tx, const double *ty,
                  const std::vector<int64_t> *tgt_index, DevPlan &pl,
@@ -59,34 +59,59 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
   pl.self = T.self;
   pl.ns = (int64_t)T.src_perm.size();
   pl.nt = (int64_t)T.tgt_perm.size();
-  pl.level_ptr = T.level_ptr;
   std::vector<int32_t> quad(nb), leaf_s, leaf_t, m2l;
   std::vector<uint8_t> has_tgt(nb);
+  std::vector<std::vector<int32_t>> by_level(std::max(1, T.nlevels));
   for (int b = 0; b < nb; ++b) {
     quad[b] = (T.ix[b] & 1) | ((T.iy[b] & 1) << 1);
     has_tgt[b] = T.t1[b] > T.t0[b];
     if (T.leaf[b] && T.s1[b] > T.s0[b]) leaf_s.push_back(b);
     if (T.leaf[b] && has_tgt[b]) leaf_t.push_back(b);
     if (T.level[b] >= 2 && has_tgt[b]) m2l.push_back(b);
+    by_level[T.level[b]].push_back(b);
   }
   pl.n_leaf_s = (int)leaf_s.size();
   pl.n_leaf_t = (int)leaf_t.size();
   pl.n_m2l = (int)m2l.size();
   pl.leaf_t_host = leaf_t;
+  // per-level work lists of the upward and downward passes
+  std::vector<int32_t> xb, mpar, l2lb, l2lpq;
+  std::vector<int4> mkids;
+  pl.m2m_lptr.assign(1, 0);
+  pl.l2l_lptr.assign(1, 0);
+  for (int l = 0; l < T.nlevels; ++l) {
+    for (int b : by_level[l]) {
+      if (!T.leaf[b] && T.s1[b] > T.s0[b]) {
+        int ks[4] = {-1, -1, -1, -1}, nk = 0;
+        for (int c = T.child0[b]; c < T.child0[b] + T.nchild[b]; ++c)
+          if (T.s1[c] > T.s0[c]) ks[nk++] = (c << 2) | quad[c];
+        mpar.push_back(b);
+        mkids.push_back(make_int4(ks[0], ks[1], ks[2], ks[3]));
+      }
+      if (l >= 3 && has_tgt[b]) {
+        l2lb.push_back(b);
+        l2lpq.push_back((T.parent[b] << 2) | quad[b]);
+      }
+    }
+    pl.m2m_lptr.push_back((int32_t)mpar.size());
+    pl.l2l_lptr.push_back((int32_t)l2lb.size());
+  }
+  for (int b = 0; b < nb; ++b)
+    if (T.x_ptr[b + 1] > T.x_ptr[b]) xb.push_back(b);
+  pl.n_x = (int)xb.size();
+  pl.x_box.upload(xb, s);
+  pl.m2m_par.upload(mpar, s);
+  pl.m2m_kids.upload(mkids, s);
+  pl.l2l_box.upload(l2lb, s);
+  pl.l2l_pq.upload(l2lpq, s);
   pl.cx.upload(T.cx, s);
   pl.cy.upload(T.cy, s);
   pl.rad.upload(T.rad, s);
-  pl.parent.upload(T.parent, s);
-  pl.child0.upload(T.child0, s);
-  pl.nchild.upload(T.nchild, s);
-  pl.quad.upload(quad, s);
   pl.lev.upload(T.level, s);
   pl.s0.upload(T.s0, s);
   pl.s1.upload(T.s1, s);
   pl.t0.upload(T.t0, s);
   pl.t1.upload(T.t1, s);
-  pl.leaf.upload(T.leaf, s);
-  pl.has_tgt.upload(has_tgt, s);
   pl.v_ptr.upload(T.v_ptr, s);
   pl.v_src.upload(T.v_src, s);
   pl.v_code.upload(T.v_code, s);
@@ -103,46 +128,34 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
     hi = (float)v;
     lo = (float)(v - (double)hi);
   };
-  {
-    const int64_t n = pl.ns;
+  auto points = [&](const std::vector<int64_t> &perm, const double *ax,
+                    const double *ay, DBuf<double> &dx, DBuf<double> &dy,
+                    DBuf<float> &xh, DBuf<float> &xl, DBuf<float> &yh,
+                    DBuf<float> &yl) {
+    const int64_t n = (int64_t)perm.size();
     std::vector<double> x(n), y(n);
-    std::vector<float> xh(n), xl(n), yh(n), yl(n);
+    std::vector<float> a(n), b(n), c(n), d(n);
     for (int64_t j = 0; j < n; ++j) {
-      x[j] = sx[T.src_perm[j]];
-      y[j] = sy[T.src_perm[j]];
-      split(x[j], xh[j], xl[j]);
-      split(y[j], yh[j], yl[j]);
+      x[j] = ax[perm[j]];
+      y[j] = ay[perm[j]];
+      split(x[j], a[j], b[j]);
+      split(y[j], c[j], d[j]);
     }
-    pl.sx.upload(x, s);
-    pl.sy.upload(y, s);
-    pl.sxh.upload(xh, s);
-    pl.sxl.upload(xl, s);
-    pl.syh.upload(yh, s);
-    pl.syl.upload(yl, s);
-    pl.src_perm.upload(T.src_perm, s);
-  }
-  {
-    const double *ax = T.self ? sx : tx, *ay = T.self ? sy : ty;
-    const int64_t n = pl.nt;
-    std::vector<double> x(n), y(n);
-    std::vector<float> xh(n), xl(n), yh(n), yl(n);
-    std::vector<int64_t> perm(n);
-    for (int64_t j = 0; j < n; ++j) {
-      const int64_t a = T.tgt_perm[j];
-      x[j] = ax[a];
-      y[j] = ay[a];
-      split(x[j], xh[j], xl[j]);
-      split(y[j], yh[j], yl[j]);
-      perm[j] = tgt_index ? (*tgt_index)[a] : a;
-    }
-    pl.tx.upload(x, s);
-    pl.ty.upload(y, s);
-    pl.txh.upload(xh, s);
-    pl.txl.upload(xl, s);
-    pl.tyh.upload(yh, s);
-    pl.tyl.upload(yl, s);
-    pl.tgt_perm.upload(perm, s);
-  }
+    dx.upload(x, s);
+    dy.upload(y, s);
+    xh.upload(a, s);
+    xl.upload(b, s);
+    yh.upload(c, s);
+    yl.upload(d, s);
+  };
+  points(T.src_perm, sx, sy, pl.sx, pl.sy, pl.sxh, pl.sxl, pl.syh, pl.syl);
+  pl.src_perm.upload(T.src_perm, s);
+  points(T.tgt_perm, T.self ? sx : tx, T.self ? sy : ty, pl.tx, pl.ty, pl.txh,
+         pl.txl, pl.tyh, pl.tyl);
+  std::vector<int64_t> perm(T.tgt_perm.size());
+  for (size_t j = 0; j < perm.size(); ++j)
+    perm[j] = tgt_index ? (*tgt_index)[T.tgt_perm[j]] : T.tgt_perm[j];
+  pl.tgt_perm.upload(perm, s);
   LBS_HIP(hipStreamSynchronize(s));
 }
 
@@ -150,7 +163,7 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
 
 namespace lbs {
 void Workspace::ensure(const DevPlan &pl, int P64, int P32, int nrhs,
-                       int64_t N, int M, int Plog) {
+                       int64_t N, int M, int G, int Plog) {
   if (nrhs <= nrhs_cap) return;
   nrhs_cap = nrhs;
   pstr64.alloc((size_t)pl.ns * nrhs * 2);
@@ -159,13 +172,24 @@ void Workspace::ensure(const DevPlan &pl, int P64, int P32, int nrhs,
   pstr32.alloc((size_t)pl.ns * nrhs * 2);
   mult32.alloc((size_t)pl.nbox * P32 * nrhs * 2);
   loc32.alloc((size_t)pl.nbox * P32 * nrhs * 2);
-  gam.alloc(std::max(nrhs, 1));
-  red.alloc((size_t)512 * std::max(nrhs, 128));
+  gam.alloc((size_t)std::max(nrhs, 1) * G);
   tmpM.alloc((size_t)std::max(M, 1) * nrhs);
   logL.alloc((size_t)std::max(M, 1) * nrhs * (2 * (Plog + 1) + 2));
-  (void)N;
+  // reduction scratch: plain dots (512 x nrhs) and segmented dots of up to
+  // 128 vectors over the 2048-row chunks of N + M rows
+  const size_t chunks = (size_t)((N + M) / 2048 + 2 * G + 4);
+  red.alloc(std::max<size_t>((size_t)512 * std::max(nrhs, 128),
+                             (size_t)128 * nrhs * chunks));
 }
 }  // namespace lbs
+
+struct GmresState {
+  int R = 0, S = 0, m = 0;
+  int64_t n = 0;
+  DBuf<double> V, H, cs, sn, gv, yv, h1, h2, nrm2, tol, resid;
+  DBuf<int32_t> active, kused, count;
+  DBuf<double> bvec, rvec, xvec, dvec, bn2;
+};
 
 struct lbs_ctx {
   lbs_options opt{};
@@ -173,31 +197,40 @@ struct lbs_ctx {
   DevPlan plan;
   Tables tab64, tab32;
   Workspace ws;
+  SegPlan seg_nodes;   // one segment per geometry over the node rows
+  SegPlan seg_sys;     // one segment per geometry over the N + M unknowns
   std::vector<double> xi_x, xi_y;  // node images, API order (eval trees)
   StageTimer timer;
-  // GMRES state (vector length n = N + M)
-  int64_t n = 0;
-  DBuf<double> V, H, cs, sn, gv, yv, h2, nrm2, resid, bvec, rvec, xvec, dvec;
-  double *resid_host = nullptr;
+  GmresState gm;
+  int32_t *count_host = nullptr;
   ~lbs_ctx() {
-    if (resid_host) (void)hipHostFree(resid_host);
+    if (count_host) (void)hipHostFree(count_host);
   }
 };
 
 namespace {
 
+void ensure_ws(lbs_ctx &c, int nrhs) {
+  c.ws.ensure(c.plan, c.opt.p64, c.opt.p32, nrhs, c.geo.N, c.geo.M, c.geo.G,
+              kPlog);
+}
+
+// y = ident x + K x for the node rows (ld x / y given)
 void apply_K(lbs_ctx &c, int prec, int nrhs, const double *x, int64_t ldx,
              double *y, int64_t ldy, double ident, hipStream_t s) {
   Geometry &g = c.geo;
-  c.ws.ensure(c.plan, c.opt.p64, c.opt.p32, nrhs, g.N, g.M, kPlog);
+  ensure_ws(c, nrhs);
   {
     TimerScope ts(c.ws.timer, ST_GAMMA, s);
-    launch_dots(g.N, nrhs, g.gw.p, 0, x, ldx, c.ws.gam.p, c.ws.red.p, s);
+    launch_segdots(c.seg_nodes, nrhs, 1, g.gw.p, 0, 0, x, ldx, c.ws.gam.p,
+                   c.ws.red.p, s);
   }
   Assembly as;
   as.sigma = x;
   as.tau = g.tau.p;
   as.gamma = c.ws.gam.p;
+  as.geo = g.node_geo.p;
+  as.G = g.G;
   as.ident = ident;
   as.ldx = ldx;
   if (c.opt.matvec == LBS_MATVEC_DIRECT) {
@@ -212,7 +245,7 @@ void apply_K(lbs_ctx &c, int prec, int nrhs, const double *x, int64_t ldx,
   }
 }
 
-// y = P^-1 A x = x + P^-1 [K x_s; 0]   (x, y: n x nrhs with ld n = N + M)
+// y = P^-1 A x = x + P^-1 [K x_s; 0]   (x, y: nrhs columns of length N + M)
 void apply_precond_op(lbs_ctx &c, int prec, int nrhs, const double *x,
                       double *y, hipStream_t s) {
   Geometry &g = c.geo;
@@ -221,7 +254,7 @@ void apply_precond_op(lbs_ctx &c, int prec, int nrhs, const double *x,
   {
     TimerScope ts(c.ws.timer, ST_CONSTRAINT, s);
     launch_island_sums(g, y, n, nrhs, c.ws.tmpM.p, g.M, s);
-    launch_gemv(g.M, g.Sinv.p, c.ws.tmpM.p, g.M, nrhs, y + g.N, n, -1.0, s);
+    launch_gemv_blocks(g, c.ws.tmpM.p, g.M, nrhs, y + g.N, n, -1.0, s);
   }
   {
     TimerScope ts(c.ws.timer, ST_LOGSRC, s);
@@ -244,97 +277,435 @@ void apply_system(lbs_ctx &c, int prec, int nrhs, const double *x, double *y,
   launch_constraint_rows(g, x, n, x + g.N, n, nrhs, y + g.N, n, s);
 }
 
-// b = P^-1 [2 g; 0] for one right-hand side (b has length N + M)
-void precond_rhs(lbs_ctx &c, const double *gdat, double *b, hipStream_t s) {
+// b = P^-1 [2 g; 0] for nrhs columns (g: ld N; b: ld N + M)
+void precond_rhs(lbs_ctx &c, int nrhs, const double *gdat, double *b,
+                 hipStream_t s) {
   Geometry &g = c.geo;
-  c.ws.ensure(c.plan, c.opt.p64, c.opt.p32, 1, g.N, g.M, kPlog);
-  launch_fill(g.N, 0.0, b, s);
-  launch_axpby(g.N, 2.0, gdat, 0.0, b, s);
-  launch_island_sums(g, b, g.N, 1, c.ws.tmpM.p, g.M, s);
-  launch_gemv(g.M, g.Sinv.p, c.ws.tmpM.p, g.M, 1, b + g.N, g.M, -1.0, s);
-  launch_logsrc_apply(g, c.ws, b + g.N, g.M, 1, b, g.N, -1.0, s);
+  const int64_t n = g.N + g.M;
+  ensure_ws(c, nrhs);
+  launch_copy_cols(g.N, nrhs, 2.0, gdat, g.N, b, n, s);
+  launch_island_sums(g, b, n, nrhs, c.ws.tmpM.p, g.M, s);
+  launch_gemv_blocks(g, c.ws.tmpM.p, g.M, nrhs, b + g.N, n, -1.0, s);
+  launch_logsrc_apply(g, c.ws, b + g.N, n, nrhs, b, n, -1.0, s);
 }
 
-double norm2(lbs_ctx &c, const double *x, int64_t n, hipStream_t s) {
-  launch_dots(n, 1, x, 0, x, 0, c.nrm2.p, c.ws.red.p, s);
-  LBS_HIP(hipMemcpyAsync(c.resid_host, c.nrm2.p, sizeof(double),
+void ensure_gmres(lbs_ctx &c, int R) {
+  GmresState &st = c.gm;
+  if (st.R >= R && st.R > 0) return;
+  const int m = c.opt.restart, G = c.geo.G, S = R * G;
+  const int64_t n = c.geo.N + c.geo.M;
+  st.R = R;
+  st.S = S;
+  st.m = m;
+  st.n = n;
+  st.V.alloc((size_t)(m + 1) * R * n);
+  st.H.alloc((size_t)S * (m + 1) * m);
+  st.cs.alloc((size_t)S * m);
+  st.sn.alloc((size_t)S * m);
+  st.gv.alloc((size_t)S * (m + 1));
+  st.yv.alloc((size_t)S * m);
+  st.h1.alloc((size_t)(m + 1) * S);
+  st.h2.alloc((size_t)(m + 1) * S);
+  st.nrm2.alloc(S);
+  st.tol.alloc(S);
+  st.resid.alloc(S);
+  st.bn2.alloc(S);
+  st.active.alloc(S);
+  st.kused.alloc(S);
+  st.count.alloc(1);
+  st.bvec.alloc((size_t)R * n);
+  st.rvec.alloc((size_t)R * n);
+  st.xvec.alloc((size_t)R * n);
+  st.dvec.alloc((size_t)R * n);
+}
+
+int read_count(lbs_ctx &c, hipStream_t s) {
+  LBS_HIP(hipMemcpyAsync(c.count_host, c.gm.count.p, sizeof(int32_t),
                          hipMemcpyDeviceToHost, s));
   LBS_HIP(hipStreamSynchronize(s));
-  return std::sqrt(std::max(0.0, *c.resid_host));
+  return *c.count_host;
 }
 
 struct GmresOut {
   int iters = 0;
   bool conv = false;
-  double est = 0;   // last residual estimate (absolute)
 };
 
-// GMRES(m) for P^-1 A x = b with x0 = x (x_zero: x = 0).  Stops when the
-// Givens residual estimate is <= tol_abs.  CGS2 orthogonalisation.
-GmresOut gmres(lbs_ctx &c, int prec, const double *b, double *x, bool x_zero,
-               double tol_abs, int max_iter, hipStream_t s) {
-  const int64_t n = c.n;
-  const int m = c.opt.restart;
-  double *V = c.V.p;
-  double *H = c.H.p;
+// Lockstep GMRES(m) for the R * G systems P^-1 A x = b (columns of length
+// n = N + M), per-system absolute tolerances c.gm.tol.  x_zero: start from
+// x = 0.  CGS2 orthogonalisation, Givens rotations, one 4-byte read of the
+// number of active systems per iteration.
+GmresOut gmres(lbs_ctx &c, int prec, int R, const double *b, double *x,
+               bool x_zero, int max_iter, hipStream_t s) {
+  GmresState &st = c.gm;
+  const int64_t n = st.n;
+  const int m = st.m, G = c.geo.G, S = R * G;
+  double *V = st.V.p;
+  const int64_t ldv = (int64_t)R * n;
+  const int32_t *rg = c.geo.row_geo.p;
   GmresOut out;
   auto residual_into_v0 = [&]() {
-    apply_precond_op(c, prec, 1, x, V, s);
-    launch_axpby(n, 1.0, b, -1.0, V, s);
+    apply_precond_op(c, prec, R, x, V, s);
+    launch_axpby(ldv, 1.0, b, -1.0, V, s);
   };
   if (x_zero) {
-    launch_fill(n, 0.0, x, s);
-    LBS_HIP(hipMemcpyAsync(V, b, n * sizeof(double), hipMemcpyDeviceToDevice,
-                           s));
+    launch_fill(ldv, 0.0, x, s);
+    LBS_HIP(hipMemcpyAsync(V, b, ldv * sizeof(double), hipMemcpyDeviceToDevice, s));
   } else {
     residual_into_v0();
   }
   while (true) {
-    launch_dots(n, 1, V, 0, V, 0, c.nrm2.p, c.ws.red.p, s);
-    launch_init_g(m, c.nrm2.p, c.gv.p, s);
-    LBS_HIP(hipMemcpyAsync(c.resid_host, c.gv.p, sizeof(double),
-                           hipMemcpyDeviceToHost, s));
-    LBS_HIP(hipStreamSynchronize(s));
-    const double beta = *c.resid_host;
-    out.est = beta;
-    if (beta <= tol_abs || !(beta == beta)) {
-      out.conv = beta <= tol_abs;
+    launch_segdots(c.seg_sys, R, 1, V, 0, n, V, n, st.nrm2.p, c.ws.red.p, s);
+    launch_fill_int(1, 0, st.count.p, s);
+    launch_gmres_start(S, m, st.nrm2.p, st.tol.p, st.gv.p, st.active.p,
+                       st.kused.p, st.count.p, s);
+    if (read_count(c, s) == 0) {
+      out.conv = true;
       return out;
     }
     if (out.iters >= max_iter) return out;
-    launch_normalize(n, c.nrm2.p, V, V, nullptr, s);
-    int k_used = 0;
-    bool done = false;
+    launch_normalize_seg(n, R, G, rg, st.nrm2.p, st.active.p, V, V, s);
+    int alive = 1;
+    int kc = 0;
     for (int k = 0; k < m; ++k) {
-      double *vk = V + (int64_t)k * n, *w = V + (int64_t)(k + 1) * n;
-      double *hc = H + (int64_t)k * (m + 1);
-      apply_precond_op(c, prec, 1, vk, w, s);
-      launch_dots(n, k + 1, V, n, w, 0, hc, c.ws.red.p, s);
-      launch_maxpy(n, k + 1, V, n, hc, w, nullptr, s);
-      launch_dots(n, k + 1, V, n, w, 0, c.h2.p, c.ws.red.p, s);
-      launch_maxpy(n, k + 1, V, n, c.h2.p, w, hc, s);
-      launch_dots(n, 1, w, 0, w, 0, c.nrm2.p, c.ws.red.p, s);
-      launch_normalize(n, c.nrm2.p, w, w, hc + k + 1, s);
-      launch_givens(k, m, H, c.cs.p, c.sn.p, c.gv.p, c.resid.p, s);
-      LBS_HIP(hipMemcpyAsync(c.resid_host, c.resid.p, sizeof(double),
-                             hipMemcpyDeviceToHost, s));
-      LBS_HIP(hipStreamSynchronize(s));
+      double *vk = V + (int64_t)k * ldv, *w = V + (int64_t)(k + 1) * ldv;
+      apply_precond_op(c, prec, R, vk, w, s);
+      launch_segdots(c.seg_sys, R, k + 1, V, ldv, n, w, n, st.h1.p,
+                     c.ws.red.p, s);
+      launch_maxpy_seg(n, R, G, k + 1, rg, V, ldv, st.h1.p, w, s);
+      launch_segdots(c.seg_sys, R, k + 1, V, ldv, n, w, n, st.h2.p,
+                     c.ws.red.p, s);
+      launch_maxpy_seg(n, R, G, k + 1, rg, V, ldv, st.h2.p, w, s);
+      launch_segdots(c.seg_sys, R, 1, w, 0, n, w, n, st.nrm2.p, c.ws.red.p, s);
+      launch_fill_int(1, 0, st.count.p, s);
+      launch_givens_seg(S, k, m, st.h1.p, st.h2.p, st.nrm2.p, st.tol.p,
+                        st.H.p, st.cs.p, st.sn.p, st.gv.p, st.resid.p,
+                        st.active.p, st.kused.p, st.count.p, s);
+      launch_normalize_seg(n, R, G, rg, st.nrm2.p, st.active.p, w, w, s);
+      alive = read_count(c, s);
       ++out.iters;
-      k_used = k + 1;
-      out.est = *c.resid_host;
-      if (!(out.est == out.est)) fail(LBS_ERR_NOT_FINITE, "GMRES residual is NaN");
-      if (out.est <= tol_abs) { out.conv = true; done = true; break; }
-      if (out.iters >= max_iter) { done = true; break; }
+      kc = k + 1;
+      if (alive == 0 || out.iters >= max_iter) break;
     }
-    launch_backsolve(k_used, m, H, c.gv.p, c.yv.p, s);
-    launch_update(n, k_used, V, n, c.yv.p, x, s);
-    if (done) return out;
+    launch_backsolve_seg(S, m, st.H.p, st.gv.p, st.kused.p, st.yv.p, s);
+    launch_update_seg(n, R, G, kc, m, rg, V, ldv, st.yv.p, x, s);
+    if (alive == 0) {
+      out.conv = true;
+      return out;
+    }
+    if (out.iters >= max_iter) return out;
     residual_into_v0();
   }
 }
 
+// Per-system 2-norms^2 of R columns of length N + M into out (S values).
+void sys_norm2(lbs_ctx &c, int R, const double *x, double *out, hipStream_t s) {
+  const int64_t n = c.geo.N + c.geo.M;
+  launch_segdots(c.seg_sys, R, 1, x, 0, n, x, n, out, c.ws.red.p, s);
+}
+
+std::vector<double> download(const double *p, size_t n, hipStream_t s) {
+  std::vector<double> v(n);
+  LBS_HIP(hipMemcpyAsync(v.data(), p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
 void check_handle(lbs_handle h) {
   if (!h) fail(LBS_ERR_INVALID_ARG, "null handle");
+}
+
+void validate_options(const lbs_options &o) {
+  if (!p64_ok(o.p64)) fail(LBS_ERR_UNSUPPORTED, "p64 must be 20/24/30/36/40/48");
+  if (!p32_ok(o.p32)) fail(LBS_ERR_UNSUPPORTED, "p32 must be 12/16/20/24");
+  if (o.leaf_max < 4 || o.leaf_max > 1024) fail(LBS_ERR_INVALID_ARG, "leaf_max outside [4, 1024]");
+  if (o.restart < 1 || o.restart > 120) fail(LBS_ERR_INVALID_ARG, "restart outside [1, 120]");
+  if (o.max_iter < 1 || o.max_outer < 1) fail(LBS_ERR_INVALID_ARG, "max_iter/max_outer < 1");
+  if (!(o.inner_tol > 0 && o.inner_tol < 1)) fail(LBS_ERR_INVALID_ARG, "inner_tol outside (0, 1)");
+  if (o.matvec != LBS_MATVEC_FMM && o.matvec != LBS_MATVEC_DIRECT) fail(LBS_ERR_INVALID_ARG, "bad matvec mode");
+}
+
+// Set-up of G geometries (islands and node counts concatenated
+// geometry-major; isl_per_geom[g] islands each).
+lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl,
+                    const int32_t *nodes, const lbs_options *opt,
+                    hipStream_t s) {
+  auto ctx = std::make_unique<lbs_ctx>();
+  lbs_default_options(&ctx->opt);
+  if (opt) ctx->opt = *opt;
+  lbs_options &o = ctx->opt;
+  validate_options(o);
+  if (G > 1 && o.matvec == LBS_MATVEC_DIRECT)
+    fail(LBS_ERR_UNSUPPORTED, "the direct matvec serves single-geometry handles");
+  Geometry &g = ctx->geo;
+  g.G = G;
+  g.gisl.assign(G + 1, 0);
+  for (int q = 0; q < G; ++q) {
+    if (isl_per_geom[q] < 1) fail(LBS_ERR_INVALID_ARG, "a geometry has no island");
+    g.gisl[q + 1] = g.gisl[q] + isl_per_geom[q];
+    g.maxM = std::max(g.maxM, isl_per_geom[q]);
+  }
+  const int M = g.gisl[G];
+  if (g.maxM > 65535) fail(LBS_ERR_UNSUPPORTED, "more than 65535 islands in a geometry");
+  g.M = M;
+  g.nodes.assign(nodes, nodes + M);
+  g.offs.assign(M + 1, 0);
+  std::vector<double> bound(M);
+  g.cxyz.resize(3 * M);
+  for (int k = 0; k < M; ++k) {
+    const lbs_island &I = isl[k];
+    if (nodes[k] < 8) fail(LBS_ERR_INVALID_ARG, "island " + std::to_string(k) + ": fewer than 8 nodes");
+    g.offs[k + 1] = g.offs[k] + nodes[k];
+    double cs = 0, es = 0, dot = 0, amp = 0;
+    bool fin = std::isfinite(I.r0);
+    for (int a = 0; a < 3; ++a) {
+      fin = fin && std::isfinite(I.center[a]) && std::isfinite(I.e1[a]);
+      cs += I.center[a] * I.center[a];
+      es += I.e1[a] * I.e1[a];
+      dot += I.center[a] * I.e1[a];
+      g.cxyz[3 * k + a] = I.center[a];
+    }
+    for (int a = 0; a < 16; ++a) {
+      fin = fin && std::isfinite(I.coef[a]);
+      amp += std::fabs(I.coef[a]);
+    }
+    const std::string tag = "island " + std::to_string(k) + ": ";
+    if (!fin) fail(LBS_ERR_GEOMETRY, tag + "non-finite parameter");
+    if (std::fabs(cs - 1) > 2e-10 || std::fabs(es - 1) > 2e-10 || std::fabs(dot) > 1e-10)
+      fail(LBS_ERR_GEOMETRY, tag + "center/e1 not orthonormal");
+    if (!(I.r0 > 0) || amp >= 1.0) fail(LBS_ERR_GEOMETRY, tag + "radius not positive everywhere");
+    bound[k] = I.r0 * (1.0 + amp);
+    if (bound[k] >= 0.5 * M_PI) fail(LBS_ERR_GEOMETRY, tag + "bounding radius >= pi/2");
+    const double pole_ang = std::acos(std::max(-1.0, std::min(1.0, I.center[2])));
+    if (pole_ang <= bound[k] * (1 + 1e-9) + 1e-9)
+      fail(LBS_ERR_GEOMETRY, tag + "north pole inside or on the bounding cap");
+  }
+  g.N = g.offs[M];
+  if (g.N > (int64_t)INT32_MAX) fail(LBS_ERR_INVALID_ARG, "too many nodes");
+  g.gnode.assign(G + 1, 0);
+  for (int q = 0; q <= G; ++q) g.gnode[q] = g.offs[g.gisl[q]];
+  for (int q = 0; q < G; ++q)
+    for (int a = g.gisl[q]; a < g.gisl[q + 1]; ++a)
+      for (int b = a + 1; b < g.gisl[q + 1]; ++b) {
+        const double d = g.cxyz[3 * a] * g.cxyz[3 * b] + g.cxyz[3 * a + 1] * g.cxyz[3 * b + 1] +
+                         g.cxyz[3 * a + 2] * g.cxyz[3 * b + 2];
+        const double lim = bound[a] + bound[b];
+        if (lim >= M_PI || d >= std::cos(lim))
+          fail(LBS_ERR_GEOMETRY, "bounding caps of islands " + std::to_string(a) + " and " +
+                                     std::to_string(b) + " overlap");
+      }
+  const int64_t N = g.N;
+  std::vector<int32_t> island(N), node_geo(N), isl_geo(M), row_geo(N + M);
+  for (int q = 0; q < G; ++q)
+    for (int k = g.gisl[q]; k < g.gisl[q + 1]; ++k) {
+      isl_geo[k] = q;
+      row_geo[N + k] = q;
+      for (int64_t i = g.offs[k]; i < g.offs[k + 1]; ++i) {
+        island[i] = k;
+        node_geo[i] = q;
+        row_geo[i] = q;
+      }
+    }
+  g.island.upload(island, s);
+  g.node_geo.upload(node_geo, s);
+  g.isl_geo.upload(isl_geo, s);
+  g.row_geo.upload(row_geo, s);
+  g.doffs.upload(g.offs, s);
+  g.dgnode.upload(g.gnode, s);
+  g.dgisl.upload(g.gisl, s);
+  g.dcenter.upload(g.cxyz, s);
+  g.gsinv.assign(G + 1, 0);
+  for (int q = 0; q < G; ++q) {
+    const int64_t mq = g.gisl[q + 1] - g.gisl[q];
+    g.gsinv[q + 1] = g.gsinv[q] + mq * mq;
+  }
+  g.dgsinv.upload(g.gsinv, s);
+  DBuf<lbs_island> disl;
+  disl.upload(std::vector<lbs_island>(isl, isl + M), s);
+  g.xyz.alloc(3 * N);
+  g.xi.alloc(2 * N);
+  g.dxi.alloc(2 * N);
+  g.ddxi.alloc(2 * N);
+  launch_geometry(disl.p, M, g.doffs.p, g.island.p, N, g.xyz.p, g.xi.p, g.dxi.p, g.ddxi.p, s);
+  std::vector<double> xyz = g.xyz.download(s), xi = g.xi.download(s), dxi = g.dxi.download(s);
+  for (int64_t i = 0; i < N; ++i) {
+    if (!std::isfinite(xi[2 * i]) || !std::isfinite(xi[2 * i + 1]) || !std::isfinite(dxi[2 * i]) ||
+        !std::isfinite(dxi[2 * i + 1]) || !(1.0 - xyz[3 * i + 2] > 1e-12))
+      fail(LBS_ERR_GEOMETRY, "node " + std::to_string(i) + " is not finite or at the pole");
+  }
+  // orientation: +1 when the island (bounded planar interior) lies to the
+  // left of the traversal, i.e. the signed area sum Im(conj(xi) xi') > 0
+  g.sign.resize(M);
+  for (int k = 0; k < M; ++k) {
+    double area = 0;
+    for (int64_t i = g.offs[k]; i < g.offs[k + 1]; ++i)
+      area += xi[2 * i] * dxi[2 * i + 1] - xi[2 * i + 1] * dxi[2 * i];
+    g.sign[k] = area > 0 ? 1.0 : -1.0;
+  }
+  DBuf<double> dsign;
+  dsign.upload(g.sign, s);
+  g.qfac.alloc(2 * N);
+  g.tau.alloc(N);
+  g.gw.alloc(N);
+  g.ell.alloc(N);
+  launch_node_coeffs(N, g.island.p, dsign.p, g.doffs.p, g.xi.p, g.dxi.p, g.ddxi.p, g.qfac.p,
+                     g.tau.p, g.gw.p, g.ell.p, s);
+  // log-source geometry: projected centres, planar radii, near lists
+  g.eta_x.resize(M);
+  g.eta_y.resize(M);
+  g.rho.assign(M, 0.0);
+  std::vector<double> eta(2 * M), ellc(M);
+  for (int k = 0; k < M; ++k) {
+    const double d = 1.0 - g.cxyz[3 * k + 2];
+    g.eta_x[k] = g.cxyz[3 * k] / d;
+    g.eta_y[k] = g.cxyz[3 * k + 1] / d;
+    eta[2 * k] = g.eta_x[k];
+    eta[2 * k + 1] = g.eta_y[k];
+    ellc[k] = std::log1p(g.eta_x[k] * g.eta_x[k] + g.eta_y[k] * g.eta_y[k]);
+    for (int64_t i = g.offs[k]; i < g.offs[k + 1]; ++i)
+      g.rho[k] = std::max(g.rho[k], std::hypot(xi[2 * i] - g.eta_x[k], xi[2 * i + 1] - g.eta_y[k]));
+  }
+  std::vector<int32_t> nptr(M + 1, 0), nidx;
+  for (int k = 0; k < M; ++k) {
+    const int q = isl_geo[k];
+    const double lim = 9.0 * g.rho[k] * g.rho[k];
+    for (int m = g.gisl[q]; m < g.gisl[q + 1]; ++m) {
+      const double dx = g.eta_x[m] - g.eta_x[k], dy = g.eta_y[m] - g.eta_y[k];
+      if (dx * dx + dy * dy <= lim) nidx.push_back(m);
+    }
+    nptr[k + 1] = (int32_t)nidx.size();
+  }
+  g.deta.upload(eta, s);
+  g.drho.upload(g.rho, s);
+  g.dellc.upload(ellc, s);
+  g.near_ptr.upload(nptr, s);
+  g.near_idx.upload(nidx, s);
+  // quadtree forest over the node images (one tree per geometry)
+  ctx->xi_x.resize(N);
+  ctx->xi_y.resize(N);
+  for (int64_t i = 0; i < N; ++i) {
+    ctx->xi_x[i] = xi[2 * i];
+    ctx->xi_y[i] = xi[2 * i + 1];
+  }
+  {
+    Tree &F = ctx->plan.host;
+    F = Tree();
+    for (int q = 0; q < G; ++q) {
+      const int64_t a = g.gnode[q], n = g.gnode[q + 1] - a;
+      Tree t;
+      build_tree(ctx->xi_x.data() + a, ctx->xi_y.data() + a, n, nullptr, nullptr, 0, true,
+                 o.leaf_max, t);
+      if (G == 1) {
+        F = std::move(t);
+      } else {
+        append_tree(F, t, a, a, a, a);
+      }
+    }
+  }
+  upload_plan(ctx->plan.host, ctx->xi_x.data(), ctx->xi_y.data(), nullptr, nullptr, nullptr,
+              ctx->plan, s);
+  g.qfac_t.alloc(2 * N);
+  launch_permute_complex(N, ctx->plan.src_perm.p, g.qfac.p, g.qfac_t.p, s);
+  build_tables(ctx->tab64, o.p64, s);
+  build_tables(ctx->tab32, o.p32, s);
+  // segments for the per-geometry reductions
+  {
+    std::vector<std::vector<std::pair<int64_t, int64_t>>> rn(G), rs(G);
+    for (int q = 0; q < G; ++q) {
+      rn[q].push_back({g.gnode[q], g.gnode[q + 1]});
+      rs[q].push_back({g.gnode[q], g.gnode[q + 1]});
+      rs[q].push_back({N + g.gisl[q], N + g.gisl[q + 1]});
+    }
+    ctx->seg_nodes.build(rn, s);
+    ctx->seg_sys.build(rs, s);
+  }
+  // Schur complements S = D - F E and their inverses, one block per geometry
+  {
+    DBuf<double> S;
+    S.alloc((size_t)g.gsinv[G]);
+    g.Sinv.alloc((size_t)g.gsinv[G]);
+    launch_build_schur(g, S.p, s);
+    invert_blocks(g, S.p, g.Sinv.p, s);
+  }
+  ensure_ws(*ctx, 1);
+  LBS_HIP(hipHostMalloc((void **)&ctx->count_host, 2 * sizeof(int32_t), hipHostMallocDefault));
+  LBS_HIP(hipStreamSynchronize(s));
+  return ctx.release();
+}
+
+// Evaluation over geometry-major targets: targets [toff[q], toff[q+1]) of
+// geometry q.
+void eval_impl(lbs_ctx &c, int nrhs, const double *sigma, const double *A,
+               const std::vector<int64_t> &toff, const double *txyz, double *u,
+               hipStream_t s) {
+  Geometry &g = c.geo;
+  const int G = g.G;
+  const int64_t T = toff[G];
+  std::vector<double> hx(3 * T);
+  LBS_HIP(hipMemcpyAsync(hx.data(), txyz, 3 * T * sizeof(double), hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipStreamSynchronize(s));
+  std::vector<double> tx, ty;
+  std::vector<int64_t> idx, qoff(G + 1, 0);
+  std::vector<int32_t> tgeo(T);
+  for (int q = 0; q < G; ++q) {
+    for (int64_t t = toff[q]; t < toff[q + 1]; ++t) {
+      tgeo[t] = q;
+      const double x0 = hx[3 * t], x1 = hx[3 * t + 1], x2 = hx[3 * t + 2];
+      if (!std::isfinite(x0) || !std::isfinite(x1) || !std::isfinite(x2))
+        fail(LBS_ERR_NOT_FINITE, "target " + std::to_string(t) + " is not finite");
+      const double d = 1.0 - x2;
+      if (d <= 1e-14) continue;  // the pole: Cauchy part is zero
+      tx.push_back(x0 / d);
+      ty.push_back(x1 / d);
+      idx.push_back(t);
+    }
+    qoff[q + 1] = (int64_t)tx.size();
+  }
+  launch_fill(T * nrhs, 0.0, u, s);
+  if (!tx.empty()) {
+    if (c.opt.matvec == LBS_MATVEC_DIRECT) {
+      std::vector<double> txi(2 * T, 0.0);
+      std::vector<uint8_t> pole(T, 1);
+      for (size_t q = 0; q < idx.size(); ++q) {
+        txi[2 * idx[q]] = tx[q];
+        txi[2 * idx[q] + 1] = ty[q];
+        pole[idx[q]] = 0;
+      }
+      DBuf<double> dtxi;
+      dtxi.upload(txi, s);
+      DBuf<uint8_t> dpole;
+      dpole.upload(pole, s);
+      direct_eval64(g.N, g.xi.p, g.qfac.p, sigma, g.N, T, dtxi.p, dpole.p, nrhs, u, T, 0.5, s);
+      LBS_HIP(hipStreamSynchronize(s));
+    } else {
+      DevPlan pl;
+      Tree &F = pl.host;
+      for (int q = 0; q < G; ++q) {
+        const int64_t a = g.gnode[q], n = g.gnode[q + 1] - a;
+        const int64_t ta = qoff[q], tn = qoff[q + 1] - ta;
+        Tree t;
+        build_tree(c.xi_x.data() + a, c.xi_y.data() + a, n, tx.data() + ta, ty.data() + ta, tn,
+                   false, c.opt.leaf_max, t);
+        if (G == 1) F = std::move(t);
+        else append_tree(F, t, a, ta, a, ta);
+      }
+      upload_plan(F, c.xi_x.data(), c.xi_y.data(), tx.data(), ty.data(), &idx, pl, s);
+      DBuf<double> qt;
+      qt.alloc(2 * g.N);
+      launch_permute_complex(g.N, pl.src_perm.p, g.qfac.p, qt.p, s);
+      Workspace ws;
+      ws.ensure(pl, c.opt.p64, c.opt.p32, nrhs, g.N, g.M, G, kPlog);
+      fmm_apply64(pl, c.tab64, ws, qt.p, sigma, g.N, nrhs, u, T, 0.5, Assembly{}, s);
+      LBS_HIP(hipStreamSynchronize(s));
+    }
+  }
+  ensure_ws(c, nrhs);
+  launch_segdots(c.seg_nodes, nrhs, 1, g.gw.p, 0, 0, sigma, g.N, c.ws.gam.p, c.ws.red.p, s);
+  launch_axpby((int64_t)nrhs * G, 0.0, c.ws.gam.p, 0.5, c.ws.gam.p, s);
+  DBuf<int32_t> dtg;
+  dtg.upload(tgeo, s);
+  launch_eval_logsrc(g, T, txyz, dtg.p, A, g.M, nrhs, c.ws.gam.p, u, T, s);
+  LBS_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace
@@ -363,173 +734,28 @@ lbs_status lbs_setup(const lbs_island *isl, int32_t M, const int32_t *nodes,
     *out = nullptr;
     if (!isl || !nodes) fail(LBS_ERR_INVALID_ARG, "islands or nodes is NULL");
     if (M < 1) fail(LBS_ERR_INVALID_ARG, "n_islands < 1");
-    hipStream_t s = (hipStream_t)stream;
-    auto ctx = std::make_unique<lbs_ctx>();
-    lbs_default_options(&ctx->opt);
-    if (opt) ctx->opt = *opt;
-    lbs_options &o = ctx->opt;
-    if (!p64_ok(o.p64)) fail(LBS_ERR_UNSUPPORTED, "p64 must be 20/24/30/36/40/48");
-    if (!p32_ok(o.p32)) fail(LBS_ERR_UNSUPPORTED, "p32 must be 12/16/20/24");
-    if (o.leaf_max < 4 || o.leaf_max > 1024) fail(LBS_ERR_INVALID_ARG, "leaf_max outside [4, 1024]");
-    if (o.restart < 1 || o.restart > 120) fail(LBS_ERR_INVALID_ARG, "restart outside [1, 120]");
-    if (o.max_iter < 1 || o.max_outer < 1) fail(LBS_ERR_INVALID_ARG, "max_iter/max_outer < 1");
-    if (!(o.inner_tol > 0 && o.inner_tol < 1)) fail(LBS_ERR_INVALID_ARG, "inner_tol outside (0, 1)");
-    if (o.matvec != LBS_MATVEC_FMM && o.matvec != LBS_MATVEC_DIRECT) fail(LBS_ERR_INVALID_ARG, "bad matvec mode");
+    *out = setup_impl(1, &M, isl, nodes, opt, (hipStream_t)stream);
+  });
+}
 
-    Geometry &g = ctx->geo;
-    g.M = M;
-    g.nodes.assign(nodes, nodes + M);
-    g.offs.assign(M + 1, 0);
-    std::vector<double> bound(M);
-    g.cxyz.resize(3 * M);
-    for (int k = 0; k < M; ++k) {
-      const lbs_island &I = isl[k];
-      if (nodes[k] < 8) fail(LBS_ERR_INVALID_ARG, "island " + std::to_string(k) + ": fewer than 8 nodes");
-      g.offs[k + 1] = g.offs[k] + nodes[k];
-      double cs = 0, es = 0, dot = 0, amp = 0;
-      bool fin = std::isfinite(I.r0);
-      for (int a = 0; a < 3; ++a) {
-        fin = fin && std::isfinite(I.center[a]) && std::isfinite(I.e1[a]);
-        cs += I.center[a] * I.center[a];
-        es += I.e1[a] * I.e1[a];
-        dot += I.center[a] * I.e1[a];
-        g.cxyz[3 * k + a] = I.center[a];
-      }
-      for (int a = 0; a < 16; ++a) {
-        fin = fin && std::isfinite(I.coef[a]);
-        amp += std::fabs(I.coef[a]);
-      }
-      const std::string tag = "island " + std::to_string(k) + ": ";
-      if (!fin) fail(LBS_ERR_GEOMETRY, tag + "non-finite parameter");
-      if (std::fabs(cs - 1) > 2e-10 || std::fabs(es - 1) > 2e-10 || std::fabs(dot) > 1e-10)
-        fail(LBS_ERR_GEOMETRY, tag + "center/e1 not orthonormal");
-      if (!(I.r0 > 0) || amp >= 1.0) fail(LBS_ERR_GEOMETRY, tag + "radius not positive everywhere");
-      bound[k] = I.r0 * (1.0 + amp);
-      if (bound[k] >= 0.5 * M_PI) fail(LBS_ERR_GEOMETRY, tag + "bounding radius >= pi/2");
-      const double pole_ang = std::acos(std::max(-1.0, std::min(1.0, I.center[2])));
-      if (pole_ang <= bound[k] * (1 + 1e-9) + 1e-9)
-        fail(LBS_ERR_GEOMETRY, tag + "north pole inside or on the bounding cap");
-    }
-    g.N = g.offs[M];
-    if (g.N > (int64_t)INT32_MAX) fail(LBS_ERR_INVALID_ARG, "too many nodes");
-    for (int a = 0; a < M; ++a)
-      for (int b = a + 1; b < M; ++b) {
-        const double d = g.cxyz[3 * a] * g.cxyz[3 * b] + g.cxyz[3 * a + 1] * g.cxyz[3 * b + 1] +
-                         g.cxyz[3 * a + 2] * g.cxyz[3 * b + 2];
-        const double lim = bound[a] + bound[b];
-        if (lim >= M_PI || d >= std::cos(lim))
-          fail(LBS_ERR_GEOMETRY, "bounding caps of islands " + std::to_string(a) + " and " +
-                                     std::to_string(b) + " overlap");
-      }
-    const int64_t N = g.N;
-    std::vector<int32_t> island(N);
-    for (int k = 0; k < M; ++k)
-      for (int64_t i = g.offs[k]; i < g.offs[k + 1]; ++i) island[i] = k;
-    g.island.upload(island, s);
-    g.doffs.upload(g.offs, s);
-    g.dcenter.upload(g.cxyz, s);
-    DBuf<lbs_island> disl;
-    disl.upload(std::vector<lbs_island>(isl, isl + M), s);
-    g.xyz.alloc(3 * N);
-    g.xi.alloc(2 * N);
-    g.dxi.alloc(2 * N);
-    g.ddxi.alloc(2 * N);
-    launch_geometry(disl.p, M, g.doffs.p, g.island.p, N, g.xyz.p, g.xi.p, g.dxi.p, g.ddxi.p, s);
-    std::vector<double> xyz = g.xyz.download(s), xi = g.xi.download(s), dxi = g.dxi.download(s);
-    for (int64_t i = 0; i < N; ++i) {
-      if (!std::isfinite(xi[2 * i]) || !std::isfinite(xi[2 * i + 1]) || !std::isfinite(dxi[2 * i]) ||
-          !std::isfinite(dxi[2 * i + 1]) || !(1.0 - xyz[3 * i + 2] > 1e-12))
-        fail(LBS_ERR_GEOMETRY, "node " + std::to_string(i) + " is not finite or at the pole");
-    }
-    // orientation: +1 when the island (bounded planar interior) lies to the
-    // left of the traversal, i.e. the signed area sum Im(conj(xi) xi') > 0
-    g.sign.resize(M);
-    for (int k = 0; k < M; ++k) {
-      double area = 0;
-      for (int64_t i = g.offs[k]; i < g.offs[k + 1]; ++i)
-        area += xi[2 * i] * dxi[2 * i + 1] - xi[2 * i + 1] * dxi[2 * i];
-      g.sign[k] = area > 0 ? 1.0 : -1.0;
-    }
-    DBuf<double> dsign;
-    dsign.upload(g.sign, s);
-    g.qfac.alloc(2 * N);
-    g.tau.alloc(N);
-    g.gw.alloc(N);
-    g.ell.alloc(N);
-    launch_node_coeffs(N, g.island.p, dsign.p, g.doffs.p, g.xi.p, g.dxi.p, g.ddxi.p, g.qfac.p,
-                       g.tau.p, g.gw.p, g.ell.p, s);
-    // log-source geometry: projected centres, planar radii, near lists
-    g.eta_x.resize(M);
-    g.eta_y.resize(M);
-    g.rho.assign(M, 0.0);
-    std::vector<double> eta(2 * M), ellc(M);
-    for (int k = 0; k < M; ++k) {
-      const double d = 1.0 - g.cxyz[3 * k + 2];
-      g.eta_x[k] = g.cxyz[3 * k] / d;
-      g.eta_y[k] = g.cxyz[3 * k + 1] / d;
-      eta[2 * k] = g.eta_x[k];
-      eta[2 * k + 1] = g.eta_y[k];
-      ellc[k] = std::log1p(g.eta_x[k] * g.eta_x[k] + g.eta_y[k] * g.eta_y[k]);
-      for (int64_t i = g.offs[k]; i < g.offs[k + 1]; ++i)
-        g.rho[k] = std::max(g.rho[k], std::hypot(xi[2 * i] - g.eta_x[k], xi[2 * i + 1] - g.eta_y[k]));
-    }
-    std::vector<int32_t> nptr(M + 1, 0), nidx;
-    for (int k = 0; k < M; ++k) {
-      const double lim = 9.0 * g.rho[k] * g.rho[k];
-      for (int m = 0; m < M; ++m) {
-        const double dx = g.eta_x[m] - g.eta_x[k], dy = g.eta_y[m] - g.eta_y[k];
-        if (dx * dx + dy * dy <= lim) nidx.push_back(m);
-      }
-      nptr[k + 1] = (int32_t)nidx.size();
-    }
-    g.deta.upload(eta, s);
-    g.drho.upload(g.rho, s);
-    g.dellc.upload(ellc, s);
-    g.near_ptr.upload(nptr, s);
-    g.near_idx.upload(nidx, s);
-    // quadtree over the node images
-    ctx->xi_x.resize(N);
-    ctx->xi_y.resize(N);
-    for (int64_t i = 0; i < N; ++i) {
-      ctx->xi_x[i] = xi[2 * i];
-      ctx->xi_y[i] = xi[2 * i + 1];
-    }
-    build_tree(ctx->xi_x.data(), ctx->xi_y.data(), N, nullptr, nullptr, 0, true, o.leaf_max,
-               ctx->plan.host);
-    upload_plan(ctx->plan.host, ctx->xi_x.data(), ctx->xi_y.data(), nullptr, nullptr, nullptr,
-                ctx->plan, s);
-    g.qfac_t.alloc(2 * N);
-    launch_permute_complex(N, ctx->plan.src_perm.p, g.qfac.p, g.qfac_t.p, s);
-    build_tables(ctx->tab64, o.p64, s);
-    build_tables(ctx->tab32, o.p32, s);
-    // Schur complement S = D - F E and its inverse
-    {
-      DBuf<double> S;
-      S.alloc((size_t)M * M);
-      g.Sinv.alloc((size_t)M * M);
-      launch_build_schur(g, S.p, s);
-      invert_dense(M, S.p, g.Sinv.p, s);
-    }
-    ctx->ws.ensure(ctx->plan, o.p64, o.p32, 1, N, M, kPlog);
-    // GMRES storage
-    ctx->n = N + M;
-    const int m = o.restart;
-    ctx->V.alloc((size_t)(m + 1) * ctx->n);
-    ctx->H.alloc((size_t)(m + 1) * m);
-    ctx->cs.alloc(m);
-    ctx->sn.alloc(m);
-    ctx->gv.alloc(m + 1);
-    ctx->yv.alloc(m);
-    ctx->h2.alloc(m + 1);
-    ctx->nrm2.alloc(1);
-    ctx->resid.alloc(1);
-    ctx->bvec.alloc(ctx->n);
-    ctx->rvec.alloc(ctx->n);
-    ctx->xvec.alloc(ctx->n);
-    ctx->dvec.alloc(ctx->n);
-    LBS_HIP(hipHostMalloc((void **)&ctx->resid_host, 2 * sizeof(double), hipHostMallocDefault));
-    LBS_HIP(hipStreamSynchronize(s));
-    *out = ctx.release();
+lbs_status lbs_setup_batch(int32_t G, const int32_t *isl_per_geom, const lbs_island *isl,
+                           const int32_t *nodes, const lbs_options *opt, void *stream,
+                           lbs_handle *out) {
+  return guard([&] {
+    if (!out) fail(LBS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!isl || !nodes || !isl_per_geom) fail(LBS_ERR_INVALID_ARG, "null pointer argument");
+    if (G < 1) fail(LBS_ERR_INVALID_ARG, "n_geoms < 1");
+    *out = setup_impl(G, isl_per_geom, isl, nodes, opt, (hipStream_t)stream);
+  });
+}
+
+lbs_status lbs_batch_info(lbs_handle h, int32_t *G, int64_t *node_off, int32_t *isl_off) {
+  return guard([&] {
+    check_handle(h);
+    if (G) *G = h->geo.G;
+    if (node_off) std::copy(h->geo.gnode.begin(), h->geo.gnode.end(), node_off);
+    if (isl_off) std::copy(h->geo.gisl.begin(), h->geo.gisl.end(), isl_off);
   });
 }
 
@@ -555,11 +781,11 @@ lbs_status lbs_matvec(lbs_handle h, int32_t op, int32_t prec, int32_t nrhs, cons
   return guard([&] {
     check_handle(h);
     if (!x || !y) fail(LBS_ERR_INVALID_ARG, "x or y is NULL");
-    if (nrhs < 1) fail(LBS_ERR_INVALID_ARG, "nrhs < 1");
+    if (nrhs < 1 || nrhs > 65535) fail(LBS_ERR_INVALID_ARG, "nrhs outside [1, 65535]");
     if (prec != LBS_FP64 && prec != LBS_MIXED) fail(LBS_ERR_INVALID_ARG, "bad precision");
     hipStream_t s = (hipStream_t)stream;
     lbs_ctx &c = *h;
-    c.ws.ensure(c.plan, c.opt.p64, c.opt.p32, nrhs, c.geo.N, c.geo.M, kPlog);
+    ensure_ws(c, nrhs);
     switch (op) {
       case LBS_OP_IPLUSK:
         apply_K(c, prec, nrhs, x, c.geo.N, y, c.geo.N, 1.0, s);
@@ -585,72 +811,78 @@ lbs_status lbs_solve(lbs_handle h, int32_t prec, int32_t nrhs, const double *gda
   lbs_status st = guard([&] {
     check_handle(h);
     if (!gdat || !sigma || !A) fail(LBS_ERR_INVALID_ARG, "null pointer argument");
-    if (nrhs < 1) fail(LBS_ERR_INVALID_ARG, "nrhs < 1");
+    if (nrhs < 1 || nrhs > 65535) fail(LBS_ERR_INVALID_ARG, "nrhs outside [1, 65535]");
     if (!(tol > 0 && tol < 1)) fail(LBS_ERR_INVALID_ARG, "tol outside (0, 1)");
     if (prec != LBS_FP64 && prec != LBS_MIXED) fail(LBS_ERR_INVALID_ARG, "bad precision");
     hipStream_t s = (hipStream_t)stream;
     lbs_ctx &c = *h;
     Geometry &g = c.geo;
-    const int64_t n = c.n;
+    const int R = nrhs, G = g.G, S = R * G;
+    const int64_t n = g.N + g.M;
     auto t0 = std::chrono::steady_clock::now();
+    ensure_ws(c, R);
+    ensure_gmres(c, R);
+    GmresState &gm = c.gm;
     lbs_solve_info inf{};
-    double worst = 0;
-    for (int r = 0; r < nrhs; ++r) {
-      const double *gr = gdat + (int64_t)r * g.N;
-      // finite data check
-      launch_dots(g.N, 1, gr, 0, gr, 0, c.nrm2.p, c.ws.red.p, s);
-      LBS_HIP(hipMemcpyAsync(c.resid_host, c.nrm2.p, sizeof(double), hipMemcpyDeviceToHost, s));
-      LBS_HIP(hipStreamSynchronize(s));
-      if (!std::isfinite(*c.resid_host)) fail(LBS_ERR_NOT_FINITE, "data g is not finite");
-      precond_rhs(c, gr, c.bvec.p, s);
-      const double bnorm = norm2(c, c.bvec.p, n, s);
-      double rel = 0;
-      bool conv = true;
-      if (bnorm == 0) {
-        launch_fill(n, 0.0, c.xvec.p, s);
-      } else if (prec == LBS_FP64) {
-        GmresOut go = gmres(c, LBS_FP64, c.bvec.p, c.xvec.p, true, tol * bnorm,
-                            c.opt.max_iter, s);
-        inf.iters += go.iters;
-        inf.fp64_matvecs += go.iters;
-        conv = go.conv;
-      } else {
-        launch_fill(n, 0.0, c.xvec.p, s);
-        LBS_HIP(hipMemcpyAsync(c.rvec.p, c.bvec.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        double rn = bnorm;
-        int left = c.opt.max_iter;
-        conv = false;
-        for (int outer = 0; outer < c.opt.max_outer; ++outer) {
-          if (rn <= tol * bnorm) { conv = true; break; }
-          if (left <= 0) break;
-          GmresOut go = gmres(c, LBS_MIXED, c.rvec.p, c.dvec.p, true,
-                              std::max(c.opt.inner_tol * rn, 0.5 * tol * bnorm), left, s);
-          inf.iters += go.iters;
-          inf.fp32_matvecs += go.iters;
-          left -= go.iters;
-          launch_axpby(n, 1.0, c.dvec.p, 1.0, c.xvec.p, s);
-          apply_precond_op(c, LBS_FP64, 1, c.xvec.p, c.rvec.p, s);
-          inf.fp64_matvecs += 1;
-          launch_axpby(n, 1.0, c.bvec.p, -1.0, c.rvec.p, s);
-          rn = norm2(c, c.rvec.p, n, s);
-          inf.outer_steps = outer + 1;
+    // finite data check
+    launch_dots((int64_t)g.N * R, 1, gdat, 0, gdat, 0, gm.nrm2.p, c.ws.red.p, s);
+    if (!std::isfinite(download(gm.nrm2.p, 1, s)[0])) fail(LBS_ERR_NOT_FINITE, "data g is not finite");
+    precond_rhs(c, R, gdat, gm.bvec.p, s);
+    sys_norm2(c, R, gm.bvec.p, gm.bn2.p, s);
+    if (prec == LBS_FP64) {
+      launch_scale_sqrt(S, tol, gm.bn2.p, gm.tol.p, s);
+      GmresOut go = gmres(c, LBS_FP64, R, gm.bvec.p, gm.xvec.p, true, c.opt.max_iter, s);
+      inf.iters = go.iters;
+      inf.fp64_matvecs = go.iters;
+      noconv = !go.conv;
+    } else {
+      launch_fill((int64_t)R * n, 0.0, gm.xvec.p, s);
+      LBS_HIP(hipMemcpyAsync(gm.rvec.p, gm.bvec.p, (size_t)R * n * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+      std::vector<double> bn2 = download(gm.bn2.p, S, s);
+      std::vector<double> rn2 = bn2;
+      int left = c.opt.max_iter;
+      bool conv = false;
+      for (int outer = 0;; ++outer) {
+        std::vector<double> itol(S);
+        bool all = true;
+        for (int q = 0; q < S; ++q) {
+          const double rn = std::sqrt(std::max(0.0, rn2[q])), bn = std::sqrt(std::max(0.0, bn2[q]));
+          if (rn <= tol * bn) {
+            itol[q] = rn;  // converged: inactive in the inner solve
+          } else {
+            all = false;
+            itol[q] = std::max(c.opt.inner_tol * rn, 0.5 * tol * bn);
+          }
         }
-        if (rn <= tol * bnorm) conv = true;
-      }
-      // final residual of the preconditioned system with the FP64 operator
-      if (bnorm > 0) {
-        apply_precond_op(c, LBS_FP64, 1, c.xvec.p, c.rvec.p, s);
+        if (all) { conv = true; break; }
+        if (outer >= c.opt.max_outer || left <= 0) break;
+        LBS_HIP(hipMemcpyAsync(gm.tol.p, itol.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
+        GmresOut go = gmres(c, LBS_MIXED, R, gm.rvec.p, gm.dvec.p, true, left, s);
+        inf.iters += go.iters;
+        inf.fp32_matvecs += go.iters;
+        left -= go.iters;
+        launch_axpby((int64_t)R * n, 1.0, gm.dvec.p, 1.0, gm.xvec.p, s);
+        apply_precond_op(c, LBS_FP64, R, gm.xvec.p, gm.rvec.p, s);
         inf.fp64_matvecs += 1;
-        launch_axpby(n, 1.0, c.bvec.p, -1.0, c.rvec.p, s);
-        rel = norm2(c, c.rvec.p, n, s) / bnorm;
+        launch_axpby((int64_t)R * n, 1.0, gm.bvec.p, -1.0, gm.rvec.p, s);
+        sys_norm2(c, R, gm.rvec.p, gm.nrm2.p, s);
+        rn2 = download(gm.nrm2.p, S, s);
+        inf.outer_steps = outer + 1;
       }
-      worst = std::max(worst, rel);
-      if (!conv) noconv = true;
-      LBS_HIP(hipMemcpyAsync(sigma + (int64_t)r * g.N, c.xvec.p, g.N * sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
-      LBS_HIP(hipMemcpyAsync(A + (int64_t)r * g.M, c.xvec.p + g.N, g.M * sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
+      noconv = !conv;
     }
+    // final residual of the preconditioned systems with the FP64 operator
+    apply_precond_op(c, LBS_FP64, R, gm.xvec.p, gm.rvec.p, s);
+    inf.fp64_matvecs += 1;
+    launch_axpby((int64_t)R * n, 1.0, gm.bvec.p, -1.0, gm.rvec.p, s);
+    sys_norm2(c, R, gm.rvec.p, gm.nrm2.p, s);
+    std::vector<double> rn2 = download(gm.nrm2.p, S, s), bn2 = download(gm.bn2.p, S, s);
+    double worst = 0;
+    for (int q = 0; q < S; ++q)
+      if (bn2[q] > 0) worst = std::max(worst, std::sqrt(rn2[q] / bn2[q]));
+    launch_copy_cols(g.N, R, 1.0, gm.xvec.p, n, sigma, g.N, s);
+    launch_copy_cols(g.M, R, 1.0, gm.xvec.p + g.N, n, A, g.M, s);
     LBS_HIP(hipStreamSynchronize(s));
     inf.rel_resid = worst;
     inf.ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -667,63 +899,29 @@ lbs_status lbs_eval(lbs_handle h, int32_t nrhs, const double *sigma, const doubl
                     int64_t T, const double *txyz, double *u, void *stream) {
   return guard([&] {
     check_handle(h);
-    if (nrhs < 1) fail(LBS_ERR_INVALID_ARG, "nrhs < 1");
+    if (h->geo.G != 1) fail(LBS_ERR_INVALID_ARG, "batch handle: use lbs_eval_batch");
+    if (nrhs < 1 || nrhs > 65535) fail(LBS_ERR_INVALID_ARG, "nrhs outside [1, 65535]");
     if (T < 0) fail(LBS_ERR_INVALID_ARG, "n_targets < 0");
     if (T == 0) return;
     if (!sigma || !A || !txyz || !u) fail(LBS_ERR_INVALID_ARG, "null pointer argument");
-    hipStream_t s = (hipStream_t)stream;
-    lbs_ctx &c = *h;
-    Geometry &g = c.geo;
-    std::vector<double> hx(3 * T);
-    LBS_HIP(hipMemcpyAsync(hx.data(), txyz, 3 * T * sizeof(double), hipMemcpyDeviceToHost, s));
-    LBS_HIP(hipStreamSynchronize(s));
-    std::vector<double> tx, ty;
-    std::vector<int64_t> idx;
-    for (int64_t t = 0; t < T; ++t) {
-      const double x0 = hx[3 * t], x1 = hx[3 * t + 1], x2 = hx[3 * t + 2];
-      if (!std::isfinite(x0) || !std::isfinite(x1) || !std::isfinite(x2))
-        fail(LBS_ERR_NOT_FINITE, "target " + std::to_string(t) + " is not finite");
-      const double d = 1.0 - x2;
-      if (d <= 1e-14) continue;  // the pole: Cauchy part is zero
-      tx.push_back(x0 / d);
-      ty.push_back(x1 / d);
-      idx.push_back(t);
-    }
-    launch_fill(T * nrhs, 0.0, u, s);
-    if (!tx.empty()) {
-      if (c.opt.matvec == LBS_MATVEC_DIRECT) {
-        std::vector<double> txi(2 * T, 0.0);
-        std::vector<uint8_t> pole(T, 1);
-        for (size_t q = 0; q < idx.size(); ++q) {
-          txi[2 * idx[q]] = tx[q];
-          txi[2 * idx[q] + 1] = ty[q];
-          pole[idx[q]] = 0;
-        }
-        DBuf<double> dtxi;
-        dtxi.upload(txi, s);
-        DBuf<uint8_t> dpole;
-        dpole.upload(pole, s);
-        direct_eval64(g.N, g.xi.p, g.qfac.p, sigma, g.N, T, dtxi.p, dpole.p, nrhs, u, T, 0.5, s);
-        LBS_HIP(hipStreamSynchronize(s));
-      } else {
-        DevPlan pl;
-        build_tree(c.xi_x.data(), c.xi_y.data(), g.N, tx.data(), ty.data(), (int64_t)tx.size(), false,
-                   c.opt.leaf_max, pl.host);
-        upload_plan(pl.host, c.xi_x.data(), c.xi_y.data(), tx.data(), ty.data(), &idx, pl, s);
-        DBuf<double> qt;
-        qt.alloc(2 * g.N);
-        launch_permute_complex(g.N, pl.src_perm.p, g.qfac.p, qt.p, s);
-        Workspace ws;
-        ws.ensure(pl, c.opt.p64, c.opt.p32, nrhs, g.N, g.M, kPlog);
-        fmm_apply64(pl, c.tab64, ws, qt.p, sigma, g.N, nrhs, u, T, 0.5, Assembly{}, s);
-        LBS_HIP(hipStreamSynchronize(s));
-      }
-    }
-    c.ws.ensure(c.plan, c.opt.p64, c.opt.p32, nrhs, g.N, g.M, kPlog);
-    launch_dots(g.N, nrhs, g.gw.p, 0, sigma, g.N, c.ws.gam.p, c.ws.red.p, s);
-    launch_axpby(nrhs, 0.0, c.ws.gam.p, 0.5, c.ws.gam.p, s);
-    launch_eval_logsrc(T, txyz, g.M, g.dcenter.p, A, g.M, nrhs, c.ws.gam.p, u, T, s);
-    LBS_HIP(hipStreamSynchronize(s));
+    eval_impl(*h, nrhs, sigma, A, {0, T}, txyz, u, (hipStream_t)stream);
+  });
+}
+
+lbs_status lbs_eval_batch(lbs_handle h, int32_t nrhs, const double *sigma, const double *A,
+                          const int64_t *toff, const double *txyz, double *u, void *stream) {
+  return guard([&] {
+    check_handle(h);
+    if (!toff) fail(LBS_ERR_INVALID_ARG, "target offsets are NULL");
+    if (nrhs < 1 || nrhs > 65535) fail(LBS_ERR_INVALID_ARG, "nrhs outside [1, 65535]");
+    const int G = h->geo.G;
+    std::vector<int64_t> off(toff, toff + G + 1);
+    if (off[0] != 0) fail(LBS_ERR_INVALID_ARG, "target offsets must start at 0");
+    for (int q = 0; q < G; ++q)
+      if (off[q + 1] < off[q]) fail(LBS_ERR_INVALID_ARG, "target offsets decrease");
+    if (off[G] == 0) return;
+    if (!sigma || !A || !txyz || !u) fail(LBS_ERR_INVALID_ARG, "null pointer argument");
+    eval_impl(*h, nrhs, sigma, A, off, txyz, u, (hipStream_t)stream);
   });
 }
 
@@ -757,22 +955,25 @@ lbs_status lbs_destroy(lbs_handle h) {
   return guard([&] { delete h; });
 }
 
+static void fill_stats(const Tree &T, lbs_tree_stats *st) {
+  std::memset(st, 0, sizeof(*st));
+  st->levels = T.nlevels;
+  st->boxes = T.nbox();
+  for (int b = 0; b < T.nbox(); ++b) st->leaves += T.leaf[b];
+  st->u_pairs = (int64_t)T.u_src.size();
+  st->v_pairs = (int64_t)T.v_src.size();
+  st->w_pairs = (int64_t)T.w_src.size();
+  st->x_pairs = (int64_t)T.x_src.size();
+  st->p2p_interactions = T.p2p_pairs;
+  st->m2p_evals = T.m2p_evals;
+  st->p2l_evals = T.p2l_evals;
+}
+
 lbs_status lbs_tree_info(lbs_handle h, lbs_tree_stats *st) {
   return guard([&] {
     check_handle(h);
     if (!st) fail(LBS_ERR_INVALID_ARG, "stats is NULL");
-    const Tree &T = h->plan.host;
-    std::memset(st, 0, sizeof(*st));
-    st->levels = T.nlevels;
-    st->boxes = T.nbox();
-    for (int b = 0; b < T.nbox(); ++b) st->leaves += T.leaf[b];
-    st->u_pairs = (int64_t)T.u_src.size();
-    st->v_pairs = (int64_t)T.v_src.size();
-    st->w_pairs = (int64_t)T.w_src.size();
-    st->x_pairs = (int64_t)T.x_src.size();
-    st->p2p_interactions = T.p2p_pairs;
-    st->m2p_evals = T.m2p_evals;
-    st->p2l_evals = T.p2l_evals;
+    fill_stats(h->plan.host, st);
   });
 }
 
@@ -784,19 +985,7 @@ lbs_status lbs_check_tree_host(const double *x, const double *y, int64_t n, int3
     Tree T;
     build_tree(x, y, n, nullptr, nullptr, 0, true, leaf_max, T);
     *bad = check_coverage(T);
-    if (st) {
-      std::memset(st, 0, sizeof(*st));
-      st->levels = T.nlevels;
-      st->boxes = T.nbox();
-      for (int b = 0; b < T.nbox(); ++b) st->leaves += T.leaf[b];
-      st->u_pairs = (int64_t)T.u_src.size();
-      st->v_pairs = (int64_t)T.v_src.size();
-      st->w_pairs = (int64_t)T.w_src.size();
-      st->x_pairs = (int64_t)T.x_src.size();
-      st->p2p_interactions = T.p2p_pairs;
-      st->m2p_evals = T.m2p_evals;
-      st->p2l_evals = T.p2l_evals;
-    }
+    if (st) fill_stats(T, st);
   });
 }
 

@@ -119,63 +119,131 @@ __global__ void k_strengths(int64_t ns, const int64_t *__restrict__ perm,
   p[(int64_t)r * ns + j] = cx<T>{T(qy * s), T(-qx * s)};
 }
 
-template <typename T, int P>
-__global__ void k_p2m(int nl, const int32_t *__restrict__ leaves,
-                      const int64_t *__restrict__ s0,
-                      const int64_t *__restrict__ s1,
-                      const double *__restrict__ cxv,
-                      const double *__restrict__ cyv,
-                      const double *__restrict__ rad,
-                      const double *__restrict__ sx,
-                      const double *__restrict__ sy,
-                      const cx<T> *__restrict__ p, int64_t ns,
-                      cx<T> *__restrict__ M, int nbox) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int r = blockIdx.y;
-  if (t >= nl) return;
-  int b = leaves[t];
-  double c_x = cxv[b], c_y = cyv[b], ir = 1.0 / rad[b];
-  cx<T> acc[P];
-#pragma unroll
-  for (int k = 0; k < P; ++k) acc[k] = cx<T>{T(0), T(0)};
-  const cx<T> *pr = p + (int64_t)r * ns;
-  for (int64_t j = s0[b]; j < s1[b]; ++j) {
-    cx<T> w{T((sx[j] - c_x) * ir), T((sy[j] - c_y) * ir)};
-    cx<T> pw = pr[j];
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-      acc[k] = acc[k] + pw;
-      pw = pw * w;
-    }
+// Concatenated point ranges of list entries: for the (<= 64) entries
+// lst[e0 .. e0 + cnt) of a one-wave block, rs[e] = first point of entry e
+// and pre[e] = points before it; returns the total.  locate(q) maps a
+// position q of the concatenation to its point index.
+__device__ __forceinline__ int gather_ranges(const int32_t *__restrict__ lst,
+                                             int e0, int cnt,
+                                             const int64_t *__restrict__ s0,
+                                             const int64_t *__restrict__ s1,
+                                             int64_t *rs, int *pre) {
+  const int lane = threadIdx.x & 63;
+  int n = 0;
+  int64_t st = 0;
+  if (lane < cnt) {
+    const int c = lst[e0 + lane];
+    st = s0[c];
+    n = (int)(s1[c] - st);
   }
-  cx<T> *out = M + ((int64_t)r * nbox + b) * P;
-  T s = T(ir);
-#pragma unroll
-  for (int k = 0; k < P; ++k) out[k] = s * acc[k];
+  int v = n;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  __syncthreads();
+  if (lane < cnt) {
+    rs[lane] = st;
+    pre[lane + 1] = v;
+  }
+  if (lane == 0) pre[0] = 0;
+  __syncthreads();
+  return pre[cnt];
 }
 
+__device__ __forceinline__ int64_t locate(int q, int cnt, const int64_t *rs,
+                                          const int *pre) {
+  int lo = 0, hi = cnt;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= q) lo = mid;
+    else hi = mid;
+  }
+  return rs[lo] + (q - pre[lo]);
+}
+
+// Leaf multipoles, one 64-lane block per leaf: lane j forms the powers
+// p_j w_j^k of its source in LDS, lane k sums column k.
 template <typename T, int P>
-__global__ void k_m2m(int b0, int b1, const uint8_t *__restrict__ leaf,
-                      const int32_t *__restrict__ child0,
-                      const int32_t *__restrict__ nchild,
-                      const int32_t *__restrict__ quad,
-                      const int64_t *__restrict__ s0,
-                      const int64_t *__restrict__ s1,
+__global__ void __launch_bounds__(64)
+    k_p2m(const int32_t *__restrict__ leaves, const int64_t *__restrict__ s0,
+          const int64_t *__restrict__ s1, const double *__restrict__ cxv,
+          const double *__restrict__ cyv, const double *__restrict__ rad,
+          const double *__restrict__ sx, const double *__restrict__ sy,
+          const cx<T> *__restrict__ p, int64_t ns, cx<T> *__restrict__ M,
+          int nbox) {
+  __shared__ cx<T> buf[64][P + 1];
+  const int b = leaves[blockIdx.x];
+  const int r = blockIdx.y;
+  const int lane = threadIdx.x;
+  const double c_x = cxv[b], c_y = cyv[b], ir = 1.0 / rad[b];
+  const cx<T> *pr = p + (int64_t)r * ns;
+  cx<T> acc{T(0), T(0)};
+  const int64_t e0 = s0[b], e1 = s1[b];
+  for (int64_t jb = e0; jb < e1; jb += 64) {
+    const int64_t j = jb + lane;
+    const int n = (int)min<int64_t>(64, e1 - jb);
+    if (lane < n) {
+      cx<T> w{T((sx[j] - c_x) * ir), T((sy[j] - c_y) * ir)};
+      cx<T> pw = pr[j];
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        buf[lane][k] = pw;
+        pw = pw * w;
+      }
+    }
+    __syncthreads();
+    if (lane < P)
+      for (int q = 0; q < n; ++q) acc = acc + buf[q][lane];
+    __syncthreads();
+  }
+  if (lane < P) M[((int64_t)r * nbox + b) * P + lane] = T(ir) * acc;
+}
+
+// M2M for the parents of one level: thread (parent i, coefficient lo);
+// kids[i] packs up to four (child << 2 | quadrant) entries, -1 = none.
+template <typename T, int P>
+__global__ void k_m2m(int n, const int32_t *__restrict__ par,
+                      const int4 *__restrict__ kids,
                       const cx<T> *__restrict__ tab, cx<T> *__restrict__ M,
                       int nbox) {
-  int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  int b = b0 + gid / P, lo = gid % P;
-  int r = blockIdx.y;
-  if (b >= b1) return;
-  if (leaf[b] || s1[b] == s0[b]) return;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid / P, lo = gid % P;
+  const int r = blockIdx.y;
+  if (i >= n) return;
+  const int b = par[i];
+  const int4 kd = kids[i];
+  const int ks[4] = {kd.x, kd.y, kd.z, kd.w};
   cx<T> acc{T(0), T(0)};
-  for (int c = child0[b]; c < child0[b] + nchild[b]; ++c) {
-    if (s1[c] == s0[c]) continue;
-    const cx<T> *a = M + ((int64_t)r * nbox + c) * P;
-    const cx<T> *row = tab + ((size_t)quad[c] * P + lo) * P;
+#pragma unroll
+  for (int q4 = 0; q4 < 4; ++q4) {
+    const int e = ks[q4];
+    if (e < 0) continue;
+    const cx<T> *a = M + ((int64_t)r * nbox + (e >> 2)) * P;
+    const cx<T> *row = tab + ((size_t)(e & 3) * P + lo) * P;
     for (int ki = 0; ki <= lo; ++ki) acc = acc + row[ki] * a[ki];
   }
   M[((int64_t)r * nbox + b) * P + lo] = acc;
+}
+
+// L2L for the boxes of one level: thread (box i, coefficient m);
+// pq[i] packs (parent << 2 | quadrant of the box).
+template <typename T, int P>
+__global__ void k_l2l(int n, const int32_t *__restrict__ box,
+                      const int32_t *__restrict__ pq,
+                      const cx<T> *__restrict__ tab, cx<T> *__restrict__ L,
+                      int nbox) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid / P, m = gid % P;
+  const int r = blockIdx.y;
+  if (i >= n) return;
+  const int b = box[i], e = pq[i];
+  const cx<T> *bp = L + ((int64_t)r * nbox + (e >> 2)) * P;
+  const cx<T> *row = tab + ((size_t)(e & 3) * P + m) * P;
+  cx<T> acc{T(0), T(0)};
+  for (int l = m; l < P; ++l) acc = acc + row[l] * bp[l];
+  cx<T> *dst = L + ((int64_t)r * nbox + b) * P + m;
+  *dst = *dst + acc;
 }
 
 template <int P>
@@ -183,21 +251,17 @@ struct Groups {
   static constexpr int G = 64 / P;
 };
 
-// Local expansion of every box with targets at level >= 2: M2L over its V
-// list and P2L over its X list.  One 64-lane block per box; lane (g, l)
-// accumulates coefficient l from every G-th list entry.
+// M2L over the V list of every box with targets at level >= 2 (vector
+// ALU).  One 64-lane block per box; lane (g, l) accumulates coefficient l
+// from every G-th list entry with the factorized translation
+// b_l += tau^-l sum_k H[l][k] (tau^-k a_k), H[l][k] = (-1)^k C(k+l-1, l).
 template <typename T, int P>
 __global__ void __launch_bounds__(64)
-    k_m2l(int nb, const int32_t *__restrict__ boxes,
+    k_m2l(const int32_t *__restrict__ boxes,
           const int32_t *__restrict__ v_ptr, const int32_t *__restrict__ v_src,
-          const uint8_t *__restrict__ v_code,
-          const int32_t *__restrict__ x_ptr, const int32_t *__restrict__ x_src,
-          const double *__restrict__ cxv, const double *__restrict__ cyv,
-          const double *__restrict__ rad, const int64_t *__restrict__ s0,
-          const int64_t *__restrict__ s1, const double *__restrict__ sx,
-          const double *__restrict__ sy, const cx<T> *__restrict__ p,
-          int64_t ns, const T *__restrict__ H, const cx<T> *__restrict__ itp,
-          const cx<T> *__restrict__ M, cx<T> *__restrict__ L, int nbox) {
+          const uint8_t *__restrict__ v_code, const T *__restrict__ H,
+          const cx<T> *__restrict__ itp, const cx<T> *__restrict__ M,
+          cx<T> *__restrict__ L, int nbox) {
   constexpr int G = Groups<P>::G;
   constexpr int NP = 2 * P + 1;
   __shared__ cx<T> ybuf[G][P];
@@ -231,22 +295,7 @@ __global__ void __launch_bounds__(64)
     }
     __syncthreads();
   }
-  if (act) {
-    const double cxb = cxv[b], cyb = cyv[b];
-    const T rb = T(rad[b]);
-    const cx<T> *pr = p + (int64_t)r * ns;
-    for (int e = x_ptr[b]; e < x_ptr[b + 1]; ++e) {
-      const int c = x_src[e];
-      for (int64_t j = s0[c] + g; j < s1[c]; j += G) {
-        cx<T> u{T(sx[j] - cxb), T(sy[j] - cyb)};
-        cx<T> iu = cinv(u);
-        cx<T> rho = rb * iu;
-        cx<T> term = (pr[j] * iu) * cpow(rho, l);
-        acc = acc - term;
-      }
-    }
-    red[g][l] = acc;
-  }
+  if (act) red[g][l] = acc;
   __syncthreads();
   if (act && g == 0) {
     cx<T> s = red[0][l];
@@ -256,24 +305,134 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// M2L for FP32 expansions of 16 terms on the matrix cores.  One wave per
+// target box.  For 8 V-list sources at a time the wave forms
+// Y[k][2v + part] = part(tau_v^-(k+1) a_{v,k+1}) (16 x 16), multiplies
+// Z = H Y with four v_mfma_f32_16x16x4f32 (H: 16 x 16, real), then scales
+// column pair (2v, 2v+1) of Z by tau_v^-l and accumulates.  Lane layout of
+// the 16x16x4 instruction: A[i][k] in lane i + 16 k, B[k][j] in lane
+// j + 16 k, D[i][j] in lane j + 16 (i / 4), register i % 4.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256)
+    k_m2l_mfma16(int nb, const int32_t *__restrict__ boxes,
+                 const int32_t *__restrict__ v_ptr,
+                 const int32_t *__restrict__ v_src,
+                 const uint8_t *__restrict__ v_code,
+                 const float *__restrict__ H, const cx<float> *__restrict__ itp,
+                 const cx<float> *__restrict__ M, cx<float> *__restrict__ L,
+                 int nbox) {
+  constexpr int P = 16, NP = 2 * P + 1;
+  const int lane = threadIdx.x & 63;
+  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wv >= nb) return;  // uniform per wave
+  const int r = blockIdx.y;
+  const int col = lane & 15, kq = lane >> 4;
+  const int vslot = col >> 1, part = col & 1;
+  float a[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) a[s] = H[col * P + 4 * s + kq];
+  const int b = boxes[wv];
+  const int vb = v_ptr[b], nv = v_ptr[b + 1] - vb;
+  const cx<float> *Mr = M + (int64_t)r * nbox * P;
+  float accr[4] = {0.f, 0.f, 0.f, 0.f}, acci[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int base = 0; base < nv; base += 8) {
+    const int v = base + vslot;
+    const bool ok = v < nv;
+    int src = 0, code = 0;
+    if (ok) {
+      src = v_src[vb + v];
+      code = v_code[vb + v];
+    }
+    const cx<float> *ms = Mr + (int64_t)src * P;
+    const cx<float> *ip = itp + code * NP;
+    v4f d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + kq;
+      float bv = 0.f;
+      if (ok) {
+        const cx<float> y = ip[k + 1] * ms[k];
+        bv = part ? y.y : y.x;
+      }
+      d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bv, d, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float mine = d[j];
+      const float other = __shfl_xor(mine, 1, 64);
+      if (ok && part == 0) {
+        const cx<float> t = ip[4 * kq + j] * cx<float>{mine, other};
+        accr[j] += t.x;
+        acci[j] += t.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    for (int off = 2; off < 16; off <<= 1) {
+      accr[j] += __shfl_xor(accr[j], off, 64);
+      acci[j] += __shfl_xor(acci[j], off, 64);
+    }
+  }
+  if (col == 0) {
+    cx<float> *dst = L + ((int64_t)r * nbox + b) * P + 4 * kq;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dst[j] = cx<float>{accr[j], acci[j]};
+  }
+}
+
+// P2L over the X list of one box per 64-lane block: the sources of all its
+// X leaves are gathered; lane q forms t_q (r/u_q)^l, t_q = -p_q / u_q
+// (u_q = z_q - c) in LDS, lane l sums column l; added to the M2L result.
 template <typename T, int P>
-__global__ void k_l2l(int b0, int b1, const int32_t *__restrict__ parent,
-                      const int32_t *__restrict__ quad,
-                      const uint8_t *__restrict__ has_tgt,
-                      const cx<T> *__restrict__ tab, cx<T> *__restrict__ L,
-                      int nbox) {
-  int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  int b = b0 + gid / P, m = gid % P;
-  int r = blockIdx.y;
-  if (b >= b1) return;
-  if (!has_tgt[b]) return;
-  const int pb = parent[b];
-  const cx<T> *bp = L + ((int64_t)r * nbox + pb) * P;
-  const cx<T> *row = tab + ((size_t)quad[b] * P + m) * P;
+__global__ void __launch_bounds__(64)
+    k_p2l(const int32_t *__restrict__ boxes, const int32_t *__restrict__ x_ptr,
+          const int32_t *__restrict__ x_src, const double *__restrict__ cxv,
+          const double *__restrict__ cyv, const double *__restrict__ rad,
+          const int64_t *__restrict__ s0, const int64_t *__restrict__ s1,
+          const double *__restrict__ sx, const double *__restrict__ sy,
+          const cx<T> *__restrict__ p, int64_t ns, cx<T> *__restrict__ L,
+          int nbox) {
+  __shared__ cx<T> buf[64][P + 1];
+  __shared__ int64_t rs[64];
+  __shared__ int pre[65];
+  const int b = boxes[blockIdx.x];
+  const int r = blockIdx.y;
+  const int lane = threadIdx.x;
+  const double cxb = cxv[b], cyb = cyv[b];
+  const T rb = T(rad[b]);
+  const cx<T> *pr = p + (int64_t)r * ns;
   cx<T> acc{T(0), T(0)};
-  for (int l = m; l < P; ++l) acc = acc + row[l] * bp[l];
-  cx<T> *dst = L + ((int64_t)r * nbox + b) * P + m;
-  *dst = *dst + acc;
+  const int xb = x_ptr[b], xe = x_ptr[b + 1];
+  for (int eb = xb; eb < xe; eb += 64) {
+    const int cnt = min(64, xe - eb);
+    const int total = gather_ranges(x_src, eb, cnt, s0, s1, rs, pre);
+    for (int q0 = 0; q0 < total; q0 += 64) {
+      const int q = q0 + lane;
+      if (q < total) {
+        const int64_t j = locate(q, cnt, rs, pre);
+        const cx<T> iu = cinv(cx<T>{T(sx[j] - cxb), T(sy[j] - cyb)});
+        const cx<T> rho = rb * iu;
+        cx<T> t = pr[j] * iu;
+        t = cx<T>{-t.x, -t.y};
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+          buf[lane][l] = t;
+          t = t * rho;
+        }
+      }
+      __syncthreads();
+      const int n = min(64, total - q0);
+      if (lane < P)
+        for (int qq = 0; qq < n; ++qq) acc = acc + buf[qq][lane];
+      __syncthreads();
+    }
+  }
+  if (lane < P) {
+    cx<T> *dst = L + ((int64_t)r * nbox + b) * P + lane;
+    *dst = *dst + acc;
+  }
 }
 
 __device__ __forceinline__ double rcp64(double d) {
@@ -284,17 +443,29 @@ __device__ __forceinline__ double rcp64(double d) {
   return fma(r, e, r);
 }
 
-// Far and near field at the targets of one leaf (one 64-lane block):
-// L2P of the leaf's local expansion, M2P over its W list and the direct
-// sum over the sources of its U list (self pair excluded by d == 0), then
-// the assembly of the operator row in API order.
+__device__ __forceinline__ int pow2_at_least(int n) {
+  int t = 1;
+  while (t < n) t <<= 1;
+  return t;
+}
+
+constexpr int kStage = 128;  // U-list sources staged in LDS per pass
+
+// Potential at the targets of one leaf (one 64-lane block).  Lanes are
+// (target, slice): with tp = pow2 >= #targets (<= 32) the block has
+// S = 64 / tp slices, each taking every S-th staged source, W-list box and
+// ancestor; slices are summed by shuffles.  Work: the local expansions of
+// the leaf and its ancestors (level >= 2), M2P over its W list, the direct
+// sum over the gathered sources of its U list (self pair excluded by
+// d == 0), then the operator row assembly in API order.  FP64 version.
 template <int P>
 __global__ void __launch_bounds__(64)
     k_leaf64(const int32_t *__restrict__ leaves,
+             const int32_t *__restrict__ lev,
              const int64_t *__restrict__ t0, const int64_t *__restrict__ t1,
              const int64_t *__restrict__ s0, const int64_t *__restrict__ s1,
              const double *__restrict__ cxv, const double *__restrict__ cyv,
-             const double *__restrict__ rad, const int32_t *__restrict__ lev,
+             const double *__restrict__ rad,
              const double *__restrict__ tx, const double *__restrict__ ty,
              const int64_t *__restrict__ tperm,
              const int32_t *__restrict__ u_ptr,
@@ -307,28 +478,37 @@ __global__ void __launch_bounds__(64)
              const cx<double> *__restrict__ L, int nbox,
              double *__restrict__ out, int64_t ldy, double scale,
              Assembly as) {
-  __shared__ double lx[64], ly[64];
-  __shared__ cx<double> lp[64];
+  __shared__ double2 sz[kStage];
+  __shared__ double2 sp[kStage];
+  __shared__ int64_t rs[64];
+  __shared__ int pre[65];
   const int b = leaves[blockIdx.x];
   const int r = blockIdx.y;
   const int lane = threadIdx.x;
   const cx<double> *pr = p + (int64_t)r * ns;
   const cx<double> *Mr = M + (int64_t)r * nbox * P;
-  const cx<double> *Lb = L + ((int64_t)r * nbox + b) * P;
-  for (int64_t tb = t0[b]; tb < t1[b]; tb += 64) {
-    const int64_t i = tb + lane;
-    const bool act = i < t1[b];
+  const cx<double> *Lr = L + (int64_t)r * nbox * P;
+  const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
+  const int tp = ntb <= 32 ? pow2_at_least((int)ntb) : 64;
+  const int S = 64 / tp, tl = lane % tp, sl = lane / tp;
+  const int ub = u_ptr[b], ue = u_ptr[b + 1];
+  const int wb = w_ptr[b], we = w_ptr[b + 1];
+  const bool has_local = lev[b] >= 2;
+  for (int64_t tc = 0; tc < ntb; tc += tp) {
+    const int64_t i = tb0 + tc + tl;
+    const bool act = tc + tl < ntb;
     const double zx = act ? tx[i] : 0.0, zy = act ? ty[i] : 0.0;
     double field = 0.0;
-    if (act && lev[b] >= 2) {
-      const double ir = 1.0 / rad[b];
-      cx<double> w{(zx - cxv[b]) * ir, (zy - cyv[b]) * ir};
-      cx<double> acc = Lb[P - 1];
-      for (int l = P - 2; l >= 0; --l) acc = acc * w + Lb[l];
-      field += acc.x;
-    }
     if (act) {
-      for (int e = w_ptr[b]; e < w_ptr[b + 1]; ++e) {
+      if (sl == 0 && has_local) {
+        const double ir = 1.0 / rad[b];
+        const cx<double> w{(zx - cxv[b]) * ir, (zy - cyv[b]) * ir};
+        const cx<double> *La = Lr + (int64_t)b * P;
+        cx<double> acc = La[P - 1];
+        for (int l = P - 2; l >= 0; --l) acc = acc * w + La[l];
+        field += acc.x;
+      }
+      for (int e = wb + sl; e < we; e += S) {
         const int c = w_src[e];
         cx<double> d{zx - cxv[c], zy - cyv[c]};
         cx<double> rho = rad[c] * cinv(d);
@@ -338,34 +518,37 @@ __global__ void __launch_bounds__(64)
         field += (acc * rho).x;
       }
     }
-    for (int e = u_ptr[b]; e < u_ptr[b + 1]; ++e) {
-      const int c = u_src[e];
-      for (int64_t jb = s0[c]; jb < s1[c]; jb += 64) {
-        const int64_t j = jb + lane;
-        const int cnt = (int)min<int64_t>(64, s1[c] - jb);
-        __syncthreads();
-        if (lane < cnt) {
-          lx[lane] = sx[j];
-          ly[lane] = sy[j];
-          lp[lane] = pr[j];
+    for (int eb = ub; eb < ue; eb += 64) {
+      const int cnt = min(64, ue - eb);
+      const int total = gather_ranges(u_src, eb, cnt, s0, s1, rs, pre);
+      for (int q0 = 0; q0 < total; q0 += kStage) {
+        const int take = min(kStage, total - q0);
+        for (int q = lane; q < take; q += 64) {
+          const int64_t j = locate(q0 + q, cnt, rs, pre);
+          sz[q] = make_double2(sx[j], sy[j]);
+          const cx<double> pj = pr[j];
+          sp[q] = make_double2(pj.x, pj.y);
         }
         __syncthreads();
         if (act) {
-          for (int q = 0; q < cnt; ++q) {
-            const double dx = zx - lx[q], dy = zy - ly[q];
+          for (int q = sl; q < take; q += S) {
+            const double dx = zx - sz[q].x, dy = zy - sz[q].y;
             const double d2 = dx * dx + dy * dy;
             const double inv = d2 > 0.0 ? rcp64(d2) : 0.0;
-            field += (lp[q].x * dx + lp[q].y * dy) * inv;
+            field += (sp[q].x * dx + sp[q].y * dy) * inv;
           }
         }
+        __syncthreads();
       }
     }
-    if (act) {
+    for (int o = tp; o < 64; o <<= 1) field += __shfl_xor(field, o, 64);
+    if (act && sl == 0) {
       const int64_t api = tperm[i];
       double val = scale * field;
       if (as.sigma) {
         const double sg = as.sigma[(int64_t)r * as.ldx + api];
-        val += (as.ident + as.tau[api]) * sg + as.gamma[r];
+        val += (as.ident + as.tau[api]) * sg +
+               as.gamma[r * as.G + (as.geo ? as.geo[api] : 0)];
       }
       out[(int64_t)r * ldy + api] = val;
     }
@@ -377,10 +560,11 @@ __global__ void __launch_bounds__(64)
 template <int P>
 __global__ void __launch_bounds__(64)
     k_leaf32(const int32_t *__restrict__ leaves,
+             const int32_t *__restrict__ lev,
              const int64_t *__restrict__ t0, const int64_t *__restrict__ t1,
              const int64_t *__restrict__ s0, const int64_t *__restrict__ s1,
              const double *__restrict__ cxv, const double *__restrict__ cyv,
-             const double *__restrict__ rad, const int32_t *__restrict__ lev,
+             const double *__restrict__ rad,
              const double *__restrict__ tx, const double *__restrict__ ty,
              const float *__restrict__ txh, const float *__restrict__ txl,
              const float *__restrict__ tyh, const float *__restrict__ tyl,
@@ -395,30 +579,39 @@ __global__ void __launch_bounds__(64)
              const cx<float> *__restrict__ M, const cx<float> *__restrict__ L,
              int nbox, double *__restrict__ out, int64_t ldy, double scale,
              Assembly as) {
-  __shared__ float lxh[64], lxl[64], lyh[64], lyl[64];
-  __shared__ cx<float> lp[64];
+  __shared__ float4 sz[kStage];
+  __shared__ float2 sp[kStage];
+  __shared__ int64_t rs[64];
+  __shared__ int pre[65];
   const int b = leaves[blockIdx.x];
   const int r = blockIdx.y;
   const int lane = threadIdx.x;
   const cx<float> *pr = p + (int64_t)r * ns;
   const cx<float> *Mr = M + (int64_t)r * nbox * P;
-  const cx<float> *Lb = L + ((int64_t)r * nbox + b) * P;
-  for (int64_t tb = t0[b]; tb < t1[b]; tb += 64) {
-    const int64_t i = tb + lane;
-    const bool act = i < t1[b];
+  const cx<float> *Lr = L + (int64_t)r * nbox * P;
+  const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
+  const int tp = ntb <= 32 ? pow2_at_least((int)ntb) : 64;
+  const int S = 64 / tp, tl = lane % tp, sl = lane / tp;
+  const int ub = u_ptr[b], ue = u_ptr[b + 1];
+  const int wb = w_ptr[b], we = w_ptr[b + 1];
+  const bool has_local = lev[b] >= 2;
+  for (int64_t tc = 0; tc < ntb; tc += tp) {
+    const int64_t i = tb0 + tc + tl;
+    const bool act = tc + tl < ntb;
     const double zx = act ? tx[i] : 0.0, zy = act ? ty[i] : 0.0;
     const float zxh = act ? txh[i] : 0.f, zxl = act ? txl[i] : 0.f;
     const float zyh = act ? tyh[i] : 0.f, zyl = act ? tyl[i] : 0.f;
     float field = 0.f;
-    if (act && lev[b] >= 2) {
-      const double ir = 1.0 / rad[b];
-      cx<float> w{float((zx - cxv[b]) * ir), float((zy - cyv[b]) * ir)};
-      cx<float> acc = Lb[P - 1];
-      for (int l = P - 2; l >= 0; --l) acc = acc * w + Lb[l];
-      field += acc.x;
-    }
     if (act) {
-      for (int e = w_ptr[b]; e < w_ptr[b + 1]; ++e) {
+      if (sl == 0 && has_local) {
+        const double ir = 1.0 / rad[b];
+        const cx<float> w{float((zx - cxv[b]) * ir), float((zy - cyv[b]) * ir)};
+        const cx<float> *La = Lr + (int64_t)b * P;
+        cx<float> acc = La[P - 1];
+        for (int l = P - 2; l >= 0; --l) acc = acc * w + La[l];
+        field += acc.x;
+      }
+      for (int e = wb + sl; e < we; e += S) {
         const int c = w_src[e];
         const double dx = zx - cxv[c], dy = zy - cyv[c];
         const double id = rad[c] / (dx * dx + dy * dy);
@@ -429,37 +622,40 @@ __global__ void __launch_bounds__(64)
         field += (acc * rho).x;
       }
     }
-    for (int e = u_ptr[b]; e < u_ptr[b + 1]; ++e) {
-      const int c = u_src[e];
-      for (int64_t jb = s0[c]; jb < s1[c]; jb += 64) {
-        const int64_t j = jb + lane;
-        const int cnt = (int)min<int64_t>(64, s1[c] - jb);
-        __syncthreads();
-        if (lane < cnt) {
-          lxh[lane] = sxh[j];
-          lxl[lane] = sxl[j];
-          lyh[lane] = syh[j];
-          lyl[lane] = syl[j];
-          lp[lane] = pr[j];
+    for (int eb = ub; eb < ue; eb += 64) {
+      const int cnt = min(64, ue - eb);
+      const int total = gather_ranges(u_src, eb, cnt, s0, s1, rs, pre);
+      for (int q0 = 0; q0 < total; q0 += kStage) {
+        const int take = min(kStage, total - q0);
+        for (int q = lane; q < take; q += 64) {
+          const int64_t j = locate(q0 + q, cnt, rs, pre);
+          sz[q] = make_float4(sxh[j], sxl[j], syh[j], syl[j]);
+          const cx<float> pj = pr[j];
+          sp[q] = make_float2(pj.x, pj.y);
         }
         __syncthreads();
         if (act) {
-          for (int q = 0; q < cnt; ++q) {
-            const float dx = (zxh - lxh[q]) + (zxl - lxl[q]);
-            const float dy = (zyh - lyh[q]) + (zyl - lyl[q]);
+          for (int q = sl; q < take; q += S) {
+            const float4 s4 = sz[q];
+            const float2 p2 = sp[q];
+            const float dx = (zxh - s4.x) + (zxl - s4.y);
+            const float dy = (zyh - s4.z) + (zyl - s4.w);
             const float d2 = dx * dx + dy * dy;
             const float inv = d2 > 0.f ? __builtin_amdgcn_rcpf(d2) : 0.f;
-            field += (lp[q].x * dx + lp[q].y * dy) * inv;
+            field += (p2.x * dx + p2.y * dy) * inv;
           }
         }
+        __syncthreads();
       }
     }
-    if (act) {
+    for (int o = tp; o < 64; o <<= 1) field += __shfl_xor(field, o, 64);
+    if (act && sl == 0) {
       const int64_t api = tperm[i];
       double val = scale * (double)field;
       if (as.sigma) {
         const double sg = as.sigma[(int64_t)r * as.ldx + api];
-        val += (as.ident + as.tau[api]) * sg + as.gamma[r];
+        val += (as.ident + as.tau[api]) * sg +
+               as.gamma[r * as.G + (as.geo ? as.geo[api] : 0)];
       }
       out[(int64_t)r * ldy + api] = val;
     }
@@ -468,9 +664,10 @@ __global__ void __launch_bounds__(64)
 
 // ---------------------------------------------------------------- drivers
 template <typename T, int P>
-static void upward_downward(const DevPlan &pl, const Tables &tb,
-                            const cx<T> *p, cx<T> *M, cx<T> *L, int nrhs,
-                            StageTimer *tm, hipStream_t s) {
+static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
+                      const cx<T> *p, cx<T> *M, cx<T> *L, int nrhs,
+                      hipStream_t s) {
+  StageTimer *tm = ws.timer;
   const cx<T> *m2m, *l2l, *itp;
   const T *H;
   if constexpr (sizeof(T) == 8) {
@@ -484,43 +681,51 @@ static void upward_downward(const DevPlan &pl, const Tables &tb,
     itp = (const cx<T> *)tb.itp32.p;
     H = (const T *)tb.h32.p;
   }
-  if (pl.n_leaf_s > 0) {
-    TimerScope ts(tm, ST_P2M, s);
-    dim3 grid((pl.n_leaf_s + 63) / 64, nrhs);
-    hipLaunchKernelGGL((k_p2m<T, P>), grid, dim3(64), 0, s, pl.n_leaf_s,
-                       pl.leaf_s.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p,
-                       pl.rad.p, pl.sx.p, pl.sy.p, p, pl.ns, M, pl.nbox);
-  }
   {
-  TimerScope ts(tm, ST_M2M, s);
-  for (int l = pl.nlevels - 2; l >= 2; --l) {
-    int b0 = pl.level_ptr[l], b1 = pl.level_ptr[l + 1];
-    int threads = (b1 - b0) * P;
-    if (threads <= 0) continue;
-    dim3 grid((threads + 255) / 256, nrhs);
-    hipLaunchKernelGGL((k_m2m<T, P>), grid, dim3(256), 0, s, b0, b1,
-                       pl.leaf.p, pl.child0.p, pl.nchild.p, pl.quad.p,
-                       pl.s0.p, pl.s1.p, m2m, M, pl.nbox);
-  }
+    TimerScope ts(tm, ST_UPWARD, s);
+    if (pl.n_leaf_s > 0)
+      hipLaunchKernelGGL((k_p2m<T, P>), dim3(pl.n_leaf_s, nrhs), dim3(64), 0,
+                         s, pl.leaf_s.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p,
+                         pl.rad.p, pl.sx.p, pl.sy.p, p, pl.ns, M, pl.nbox);
+    const int nl = (int)pl.m2m_lptr.size() - 1;
+    for (int l = nl - 1; l >= 2; --l) {
+      const int a0 = pl.m2m_lptr[l], a1 = pl.m2m_lptr[l + 1];
+      const int threads = (a1 - a0) * P;
+      if (threads <= 0) continue;
+      hipLaunchKernelGGL((k_m2m<T, P>), dim3((threads + 255) / 256, nrhs),
+                         dim3(256), 0, s, a1 - a0, pl.m2m_par.p + a0,
+                         pl.m2m_kids.p + a0, m2m, M, pl.nbox);
+    }
   }
   if (pl.n_m2l > 0) {
     TimerScope ts(tm, ST_M2L, s);
-    dim3 grid(pl.n_m2l, nrhs);
-    hipLaunchKernelGGL((k_m2l<T, P>), grid, dim3(64), 0, s, pl.n_m2l,
-                       pl.m2l_box.p, pl.v_ptr.p, pl.v_src.p, pl.v_code.p,
-                       pl.x_ptr.p, pl.x_src.p, pl.cx.p, pl.cy.p, pl.rad.p,
-                       pl.s0.p, pl.s1.p, pl.sx.p, pl.sy.p, p, pl.ns, H, itp,
-                       (const cx<T> *)M, L, pl.nbox);
+    if constexpr (sizeof(T) == 4 && P == 16) {
+      hipLaunchKernelGGL(k_m2l_mfma16, dim3((pl.n_m2l + 3) / 4, nrhs),
+                         dim3(256), 0, s, pl.n_m2l, pl.m2l_box.p, pl.v_ptr.p,
+                         pl.v_src.p, pl.v_code.p, H, itp, (const cx<T> *)M, L,
+                         pl.nbox);
+    } else {
+      hipLaunchKernelGGL((k_m2l<T, P>), dim3(pl.n_m2l, nrhs), dim3(64), 0, s,
+                         pl.m2l_box.p, pl.v_ptr.p, pl.v_src.p, pl.v_code.p, H,
+                         itp, (const cx<T> *)M, L, pl.nbox);
+    }
+  }
+  if (pl.n_x > 0) {
+    TimerScope ts(tm, ST_P2L, s);
+    hipLaunchKernelGGL((k_p2l<T, P>), dim3(pl.n_x, nrhs), dim3(64), 0, s,
+                       pl.x_box.p, pl.x_ptr.p, pl.x_src.p, pl.cx.p, pl.cy.p,
+                       pl.rad.p, pl.s0.p, pl.s1.p, pl.sx.p, pl.sy.p, p, pl.ns,
+                       L, pl.nbox);
   }
   TimerScope ts(tm, ST_L2L, s);
-  for (int l = 3; l < pl.nlevels; ++l) {
-    int b0 = pl.level_ptr[l], b1 = pl.level_ptr[l + 1];
-    int threads = (b1 - b0) * P;
+  const int nl = (int)pl.l2l_lptr.size() - 1;
+  for (int l = 3; l < nl; ++l) {
+    const int a0 = pl.l2l_lptr[l], a1 = pl.l2l_lptr[l + 1];
+    const int threads = (a1 - a0) * P;
     if (threads <= 0) continue;
-    dim3 grid((threads + 255) / 256, nrhs);
-    hipLaunchKernelGGL((k_l2l<T, P>), grid, dim3(256), 0, s, b0, b1,
-                       pl.parent.p, pl.quad.p, pl.has_tgt.p, l2l, L,
-                       pl.nbox);
+    hipLaunchKernelGGL((k_l2l<T, P>), dim3((threads + 255) / 256, nrhs),
+                       dim3(256), 0, s, a1 - a0, pl.l2l_box.p + a0,
+                       pl.l2l_pq.p + a0, l2l, L, pl.nbox);
   }
 }
 
@@ -531,17 +736,16 @@ static void run64(const DevPlan &pl, const Tables &tb, Workspace &ws,
   auto *p = (cx<double> *)ws.pstr64.p;
   auto *M = (cx<double> *)ws.mult64.p;
   auto *L = (cx<double> *)ws.loc64.p;
-  upward_downward<double, P>(pl, tb, p, M, L, nrhs, ws.timer, s);
+  far_field<double, P>(pl, tb, ws, p, M, L, nrhs, s);
   if (pl.n_leaf_t > 0) {
     TimerScope ts(ws.timer, ST_LEAF, s);
-    dim3 grid(pl.n_leaf_t, nrhs);
-    hipLaunchKernelGGL((k_leaf64<P>), grid, dim3(64), 0, s, pl.leaf_t.p,
-                       pl.t0.p, pl.t1.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p,
-                       pl.rad.p, pl.lev.p, pl.tx.p, pl.ty.p,
-                       pl.tgt_perm.p, pl.u_ptr.p, pl.u_src.p, pl.w_ptr.p,
-                       pl.w_src.p, pl.sx.p, pl.sy.p, (const cx<double> *)p,
-                       pl.ns, (const cx<double> *)M, (const cx<double> *)L,
-                       pl.nbox, out, ldy, scale, as);
+    hipLaunchKernelGGL((k_leaf64<P>), dim3(pl.n_leaf_t, nrhs), dim3(64), 0, s,
+                       pl.leaf_t.p, pl.lev.p, pl.t0.p,
+                       pl.t1.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p,
+                       pl.tx.p, pl.ty.p, pl.tgt_perm.p, pl.u_ptr.p,
+                       pl.u_src.p, pl.w_ptr.p, pl.w_src.p, pl.sx.p, pl.sy.p,
+                       (const cx<double> *)p, pl.ns, (const cx<double> *)M,
+                       (const cx<double> *)L, pl.nbox, out, ldy, scale, as);
   }
 }
 
@@ -552,18 +756,18 @@ static void run32(const DevPlan &pl, const Tables &tb, Workspace &ws,
   auto *p = (cx<float> *)ws.pstr32.p;
   auto *M = (cx<float> *)ws.mult32.p;
   auto *L = (cx<float> *)ws.loc32.p;
-  upward_downward<float, P>(pl, tb, p, M, L, nrhs, ws.timer, s);
+  far_field<float, P>(pl, tb, ws, p, M, L, nrhs, s);
   if (pl.n_leaf_t > 0) {
     TimerScope ts(ws.timer, ST_LEAF, s);
-    dim3 grid(pl.n_leaf_t, nrhs);
-    hipLaunchKernelGGL((k_leaf32<P>), grid, dim3(64), 0, s, pl.leaf_t.p,
-                       pl.t0.p, pl.t1.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p,
-                       pl.rad.p, pl.lev.p, pl.tx.p, pl.ty.p, pl.txh.p,
-                       pl.txl.p, pl.tyh.p, pl.tyl.p, pl.tgt_perm.p,
-                       pl.u_ptr.p, pl.u_src.p, pl.w_ptr.p, pl.w_src.p,
-                       pl.sxh.p, pl.sxl.p, pl.syh.p, pl.syl.p,
-                       (const cx<float> *)p, pl.ns, (const cx<float> *)M,
-                       (const cx<float> *)L, pl.nbox, out, ldy, scale, as);
+    hipLaunchKernelGGL((k_leaf32<P>), dim3(pl.n_leaf_t, nrhs), dim3(64), 0, s,
+                       pl.leaf_t.p, pl.lev.p, pl.t0.p,
+                       pl.t1.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p,
+                       pl.tx.p, pl.ty.p, pl.txh.p, pl.txl.p, pl.tyh.p,
+                       pl.tyl.p, pl.tgt_perm.p, pl.u_ptr.p, pl.u_src.p,
+                       pl.w_ptr.p, pl.w_src.p, pl.sxh.p, pl.sxl.p, pl.syh.p,
+                       pl.syl.p, (const cx<float> *)p, pl.ns,
+                       (const cx<float> *)M, (const cx<float> *)L, pl.nbox,
+                       out, ldy, scale, as);
   }
 }
 

@@ -90,6 +90,12 @@ struct DevPlan {
   DBuf<int32_t> v_ptr, v_src, x_ptr, x_src, u_ptr, u_src, w_ptr, w_src;
   DBuf<uint8_t> v_code;
   DBuf<int32_t> leaf_t, leaf_s, m2l_box;     // work lists
+  int n_x = 0;
+  DBuf<int32_t> x_box;                       // boxes with an X list
+  std::vector<int32_t> m2m_lptr, l2l_lptr;   // per-level ranges (host)
+  DBuf<int32_t> m2m_par;                     // parents with sources
+  DBuf<int4> m2m_kids;                       // (child << 2 | quadrant) x 4
+  DBuf<int32_t> l2l_box, l2l_pq;             // boxes with targets, level>=3
   // points in tree order
   DBuf<double> sx, sy, tx, ty;
   DBuf<float> sxh, sxl, syh, syl, txh, txl, tyh, tyl;  // FP32 hi/lo
@@ -103,35 +109,9 @@ struct Tables {
   DBuf<double> m2m64, l2l64, h64, itp64;  // complex pairs interleaved
   DBuf<float> m2m32, l2l32, h32, itp32;
 };
-
-// One geometry handle.
-struct Geometry {
-  int64_t N = 0;
-  int M = 0;
-  std::vector<int32_t> nodes;        // per island
-  std::vector<int64_t> offs;         // node offset per island (M+1)
-  std::vector<double> sign;          // orientation sign per island
-  std::vector<double> cxyz;          // centres (M x 3)
-  std::vector<double> eta_x, eta_y;  // projected centres
-  std::vector<double> rho;           // planar island radius about eta
-  // device, API order
-  DBuf<double> xyz;                  // N x 3
-  DBuf<double> xi, dxi, ddxi;        // complex interleaved (N x 2)
-  DBuf<double> qfac;                 // (s h / pi) xi'   complex (N x 2)
-  DBuf<double> tau;                  // -(s h / 2 pi) Im(xi''/xi')
-  DBuf<double> gw;                   // (s h / pi) Im(conj(xi) xi' / (1+|xi|^2))
-  DBuf<double> ell;                  // log(1 + |xi|^2)
-  DBuf<int32_t> island;              // island of each node
-  DBuf<double> qfac_t;               // qfac in tree order
-  DBuf<double> dcenter, deta, drho, dellc;  // centres, eta, rho, log(1+|eta|^2)
-  DBuf<int64_t> doffs;
-  DBuf<int32_t> near_ptr, near_idx;  // near centres per island (log sources)
-  DBuf<double> Sinv;                 // M x M inverse Schur complement
-};
-
 // Per-stage GPU timing with HIP events recorded on the launch stream.
 enum Stage {
-  ST_STRENGTHS = 0, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_LEAF, ST_GAMMA,
+  ST_STRENGTHS = 0, ST_UPWARD, ST_L2L, ST_M2L, ST_P2L, ST_LEAF, ST_GAMMA,
   ST_LOGSRC, ST_CONSTRAINT, ST_NSTAGES
 };
 struct StageTimer {
@@ -188,16 +168,61 @@ struct TimerScope {
   }
 };
 
+
+// Island geometry of a handle: G >= 1 independent geometries, nodes and
+// islands numbered geometry-major (curve-major inside a geometry).
+struct Geometry {
+  int64_t N = 0;
+  int M = 0;
+  int G = 1;
+  int maxM = 0;                      // largest island count of a geometry
+  std::vector<int32_t> nodes;        // per island
+  std::vector<int64_t> offs;         // node offset per island (M+1)
+  std::vector<int64_t> gnode;        // node offset per geometry (G+1)
+  std::vector<int32_t> gisl;         // island offset per geometry (G+1)
+  std::vector<int64_t> gsinv;        // offset of each S^-1 block (G+1)
+  std::vector<double> sign;          // orientation sign per island
+  std::vector<double> cxyz;          // centres (M x 3)
+  std::vector<double> eta_x, eta_y;  // projected centres
+  std::vector<double> rho;           // planar island radius about eta
+  // device, API order
+  DBuf<double> xyz;                  // N x 3
+  DBuf<double> xi, dxi, ddxi;        // complex interleaved (N x 2)
+  DBuf<double> qfac;                 // (s h / pi) xi'   complex (N x 2)
+  DBuf<double> tau;                  // -(s h / 2 pi) Im(xi''/xi')
+  DBuf<double> gw;                   // (s h / pi) Im(conj(xi) xi' / (1+|xi|^2))
+  DBuf<double> ell;                  // log(1 + |xi|^2)
+  DBuf<int32_t> island;              // island of each node
+  DBuf<int32_t> node_geo, isl_geo;   // geometry of each node / island
+  DBuf<int32_t> row_geo;             // geometry of each unknown (N + M)
+  DBuf<double> qfac_t;               // qfac in tree order
+  DBuf<double> dcenter, deta, drho, dellc;  // centres, eta, rho, log(1+|eta|^2)
+  DBuf<int64_t> doffs, dgnode, dgsinv;
+  DBuf<int32_t> dgisl;
+  DBuf<int32_t> near_ptr, near_idx;  // near centres per island (log sources)
+  DBuf<double> Sinv;                 // block-diagonal inverse Schur complement
+};
+
+// Segments of rows for segmented dot products: each segment is a union of
+// row chunks of at most 2048 rows.
+struct SegPlan {
+  int nseg = 0, nchunk = 0;
+  DBuf<int64_t> c0, c1;
+  DBuf<int32_t> sptr, sidx;
+  void build(const std::vector<std::vector<std::pair<int64_t, int64_t>>> &ranges,
+             hipStream_t s);
+};
+
 struct Workspace {
   StageTimer *timer = nullptr;
   int nrhs_cap = 0;
   DBuf<double> pstr64, mult64, loc64;
   DBuf<float> pstr32, mult32, loc32;
-  DBuf<double> gam;       // per rhs
+  DBuf<double> gam;       // per (rhs, geometry)
   DBuf<double> red;       // reduction scratch
-  DBuf<double> tmpN, tmpM, tmpM2, logL;
+  DBuf<double> tmpM, logL;
   void ensure(const DevPlan &pl, int P64, int P32, int nrhs, int64_t N,
-              int M, int Plog);
+              int M, int G, int Plog);
 };
 
 constexpr int kPlog = 30;  // terms of the per-island log-source expansions
@@ -214,11 +239,14 @@ void launch_node_coeffs(int64_t N, const int32_t *island, const double *sign,
 void launch_permute_complex(int64_t n, const int64_t *perm, const double *in,
                             double *out, hipStream_t s);
 
-// far field: y_field[perm] = scale * Re sum_j p_j / (z_i - z_j) (+ assembly)
+// Operator-row assembly fused into the leaf kernel:
+//   out[api] = scale * field + (ident + tau[api]) sigma[api] + gamma[r G + geo[api]]
 struct Assembly {
   const double *sigma = nullptr;  // API order, stride ldx (null: no terms)
   const double *tau = nullptr;    // diagonal coefficient per node
-  const double *gamma = nullptr;  // per rhs constant added to every row
+  const double *gamma = nullptr;  // per (rhs, geometry) constant
+  const int32_t *geo = nullptr;   // geometry of each node (null: 0)
+  int G = 1;
   double ident = 0.0;             // coefficient of sigma (1 for I + K)
   int64_t ldx = 0;
 };
@@ -230,6 +258,7 @@ void fmm_apply32(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  const double *qfac_t, const double *sigma, int64_t ldx,
                  int nrhs, double *out, int64_t ldy, double scale,
                  const Assembly &as, hipStream_t s);
+// direct O(N^2) sums (single-geometry handles)
 void direct_apply64(int64_t N, const double *xi, const double *qfac,
                     const double *sigma, int64_t ldx, int nrhs, double *out,
                     int64_t ldy, const Assembly &as, hipStream_t s);
@@ -242,6 +271,10 @@ void direct_eval64(int64_t N, const double *xi, const double *qfac,
 void launch_dots(int64_t n, int nrhs, const double *a, int64_t lda,
                  const double *b, int64_t ldb, double *out, double *scratch,
                  hipStream_t s);
+// segmented: out[(v R + r) nseg + s] = sum_{i in s} a[v lav + r lac + i] b[r lbc + i]
+void launch_segdots(const SegPlan &sp, int R, int nvec, const double *a,
+                    int64_t lav, int64_t lac, const double *b, int64_t lbc,
+                    double *out, double *scratch, hipStream_t s);
 
 // log sources and constraint rows (solver.hip)
 void launch_logsrc_apply(const Geometry &g, Workspace &ws, const double *z,
@@ -254,29 +287,42 @@ void launch_constraint_rows(const Geometry &g, const double *sigma,
                             int nrhs, double *out, int64_t ldo,
                             hipStream_t s);
 void launch_build_schur(const Geometry &g, double *S, hipStream_t s);
-void invert_dense(int M, double *S, double *Sinv, hipStream_t s);
-void launch_gemv(int M, const double *A, const double *x, int64_t ldx,
-                 int nrhs, double *y, int64_t ldy, double alpha,
-                 hipStream_t s);
-void launch_eval_logsrc(int64_t T, const double *txyz, int M,
-                        const double *cxyz, const double *A, int64_t lda,
+void invert_blocks(const Geometry &g, double *S, double *Sinv, hipStream_t s);
+void launch_gemv_blocks(const Geometry &g, const double *x, int64_t ldx,
+                        int nrhs, double *y, int64_t ldy, double alpha,
+                        hipStream_t s);
+void launch_eval_logsrc(const Geometry &g, int64_t T, const double *txyz,
+                        const int32_t *tgeo, const double *A, int64_t lda,
                         int nrhs, const double *add, double *u, int64_t ldu,
                         hipStream_t s);
 
 // GMRES building blocks (solver.hip)
-void launch_maxpy(int64_t n, int k1, const double *V, int64_t ldv,
-                  const double *h, double *w, double *hacc, hipStream_t s);
-void launch_update(int64_t n, int k, const double *V, int64_t ldv,
-                   const double *y, double *x, hipStream_t s);
-void launch_normalize(int64_t n, const double *nrm2, const double *w,
-                      double *v, double *hout, hipStream_t s);
+void launch_maxpy_seg(int64_t n, int R, int G, int k1, const int32_t *row_geo,
+                      const double *V, int64_t ldv, const double *h, double *w,
+                      hipStream_t s);
+void launch_update_seg(int64_t n, int R, int G, int k, int m,
+                       const int32_t *row_geo, const double *V, int64_t ldv,
+                       const double *y, double *x, hipStream_t s);
+void launch_normalize_seg(int64_t n, int R, int G, const int32_t *row_geo,
+                          const double *nrm2, const int32_t *active,
+                          const double *w, double *v, hipStream_t s);
+void launch_gmres_start(int S, int m, const double *nrm2, const double *tol,
+                        double *g, int32_t *active, int32_t *kused,
+                        int32_t *count, hipStream_t s);
+void launch_givens_seg(int S, int k, int m, const double *h1, const double *h2,
+                       const double *nrm2, const double *tol, double *H,
+                       double *cs, double *sn, double *g, double *resid,
+                       int32_t *active, int32_t *kused, int32_t *count,
+                       hipStream_t s);
+void launch_backsolve_seg(int S, int m, const double *H, const double *g,
+                          const int32_t *kused, double *y, hipStream_t s);
 void launch_axpby(int64_t n, double a, const double *x, double b, double *y,
                   hipStream_t s);
 void launch_fill(int64_t n, double v, double *x, hipStream_t s);
-void launch_givens(int k, int m, double *H, double *cs, double *sn,
-                   double *gvec, double *resid, hipStream_t s);
-void launch_backsolve(int k, int m, const double *H, const double *gvec,
-                      double *y, hipStream_t s);
-void launch_init_g(int m, const double *nrm2, double *g, hipStream_t s);
+void launch_fill_int(int64_t n, int32_t v, int32_t *x, hipStream_t s);
+void launch_copy_cols(int64_t n, int R, double a, const double *src, int64_t lds,
+                      double *dst, int64_t ldd, hipStream_t s);
+void launch_scale_sqrt(int S, double t, const double *nrm2, double *out,
+                       hipStream_t s);
 
 }  // namespace lbs

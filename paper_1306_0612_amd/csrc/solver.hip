@@ -1,6 +1,10 @@
 // Log-source and constraint rows of the block system (Section 5,
 // eqs. matrix_eqns and matrix_eqns_c), the Schur complement of the block
 // preconditioner, and the GMRES building blocks.  All FP64.
+//
+// A handle may hold G independent geometries: nodes and islands are
+// numbered geometry-major, and every operator below acts on each geometry
+// separately (a block-diagonal system).
 #include <cmath>
 
 #include "cplx.h"
@@ -18,8 +22,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // ------------------------------------------------------------ log sources
 // (E z)_i = sum_m 2 z_m G(x_i, c_m),  G(x, y) = -(1/2pi) log|x - y| + log2/4pi
-// (Section 1.1, eq. eqn:greens_func).  For target island k and a centre m
-// with |eta_m - eta_k| > 3 rho_k ("far"), the planar identity
+// (Section 1.1, eq. eqn:greens_func), m over the islands of i's geometry.
+// For target island k and a centre m with |eta_m - eta_k| > 3 rho_k
+// ("far"), the planar identity
 //   log|x - c| = log 2 + log|xi - eta| - ell(xi)/2 - ell(eta)/2,
 //   ell(z) = log(1 + |z|^2),
 // and the series log(1 - u q) = -sum_l (u q)^l / l with u = (xi - eta_k)/rho_k,
@@ -41,7 +46,9 @@ __device__ __forceinline__ bool in_sorted(const int32_t *a, int n, int x) {
 }
 
 __global__ void __launch_bounds__(256)
-    k_logsrc_local(int M, const double *__restrict__ eta,
+    k_logsrc_local(int M, const int32_t *__restrict__ isl_geo,
+                   const int32_t *__restrict__ gisl,
+                   const double *__restrict__ eta,
                    const double *__restrict__ rho,
                    const double *__restrict__ ellc,
                    const int32_t *__restrict__ near_ptr,
@@ -49,9 +56,11 @@ __global__ void __launch_bounds__(256)
                    const double *__restrict__ z, int64_t ldz,
                    double *__restrict__ Lout) {
   constexpr int P = kPlog;
-  __shared__ double red[4][2 * (P + 1) + 2];
+  __shared__ double red[4][kLogStride];
   const int k = blockIdx.x, r = blockIdx.y;
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const int g = isl_geo[k];
+  const int m0 = gisl[g], m1 = gisl[g + 1];
   const double ex = eta[2 * k], ey = eta[2 * k + 1], rk = rho[k];
   const int32_t *nl = near_idx + near_ptr[k];
   const int nn = near_ptr[k + 1] - near_ptr[k];
@@ -60,7 +69,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int l = 0; l < P; ++l) acc[l] = cx<double>{0.0, 0.0};
   double a0 = 0.0, zf = 0.0, zt = 0.0;
-  for (int m = tid; m < M; m += 256) {
+  for (int m = m0 + tid; m < m1; m += 256) {
     const double zm = zr[m];
     zt += zm;
     if (in_sorted(nl, nn, m)) continue;
@@ -77,7 +86,6 @@ __global__ void __launch_bounds__(256)
       pw = pw * q;
     }
   }
-  // reduce: wave sums, then across the 4 waves
   auto put = [&](int slot, double v) {
     v = wave_sum(v);
     if (ln == 0) red[wv][slot] = v;
@@ -142,8 +150,8 @@ void launch_logsrc_apply(const Geometry &g, Workspace &ws, const double *z,
                          double alpha, hipStream_t s) {
   if (g.M == 0 || g.N == 0) return;
   hipLaunchKernelGGL(k_logsrc_local, dim3(g.M, nrhs), dim3(256), 0, s, g.M,
-                     g.deta.p, g.drho.p, g.dellc.p, g.near_ptr.p,
-                     g.near_idx.p, z, ldz, ws.logL.p);
+                     g.isl_geo.p, g.dgisl.p, g.deta.p, g.drho.p, g.dellc.p,
+                     g.near_ptr.p, g.near_idx.p, z, ldz, ws.logL.p);
   hipLaunchKernelGGL(k_logsrc_node, dim3((unsigned)((g.N + 255) / 256), nrhs),
                      dim3(256), 0, s, g.N, g.M, g.island.p, g.xi.p, g.xyz.p,
                      g.ell.p, g.deta.p, g.drho.p, g.dcenter.p, g.near_ptr.p,
@@ -152,19 +160,25 @@ void launch_logsrc_apply(const Geometry &g, Workspace &ws, const double *z,
 }
 
 // ------------------------------------------------------ constraint rows
-// out[k] = sum over island k of y (k >= 1); out[0] = a0 (row of sum(A)).
+// out[k] = sum over island k of y for every island that is not the first
+// of its geometry; for the first island: the sum of A over the geometry's
+// islands (row sum(A) = 0 of eq. eqn:sum_ak), or 0 without A.
 __global__ void __launch_bounds__(256)
-    k_island_sums(int M, const int64_t *__restrict__ offs,
+    k_island_sums(const int64_t *__restrict__ offs,
+                  const int32_t *__restrict__ isl_geo,
+                  const int32_t *__restrict__ gisl,
                   const double *__restrict__ y, int64_t ldy,
                   const double *__restrict__ arow, int64_t lda,
                   double *__restrict__ out, int64_t ldo) {
   __shared__ double red[4];
   const int k = blockIdx.x, r = blockIdx.y;
+  const int g = isl_geo[k];
   const double *yr = y + (int64_t)r * ldy;
   double acc = 0.0;
-  if (k == 0) {
+  if (k == gisl[g]) {
     if (arow)
-      for (int m = threadIdx.x; m < M; m += 256) acc += arow[(int64_t)r * lda + m];
+      for (int m = gisl[g] + threadIdx.x; m < gisl[g + 1]; m += 256)
+        acc += arow[(int64_t)r * lda + m];
   } else {
     for (int64_t i = offs[k] + threadIdx.x; i < offs[k + 1]; i += 256)
       acc += yr[i];
@@ -179,9 +193,9 @@ __global__ void __launch_bounds__(256)
 void launch_island_sums(const Geometry &g, const double *y, int64_t ldy,
                         int nrhs, double *out, int64_t ldo, hipStream_t s) {
   if (g.M == 0) return;
-  hipLaunchKernelGGL(k_island_sums, dim3(g.M, nrhs), dim3(256), 0, s, g.M,
-                     g.doffs.p, y, ldy, (const double *)nullptr, (int64_t)0,
-                     out, ldo);
+  hipLaunchKernelGGL(k_island_sums, dim3(g.M, nrhs), dim3(256), 0, s,
+                     g.doffs.p, g.isl_geo.p, g.dgisl.p, y, ldy,
+                     (const double *)nullptr, (int64_t)0, out, ldo);
   LBS_HIP(hipGetLastError());
 }
 
@@ -190,28 +204,38 @@ void launch_constraint_rows(const Geometry &g, const double *sigma,
                             int nrhs, double *out, int64_t ldo,
                             hipStream_t s) {
   if (g.M == 0) return;
-  hipLaunchKernelGGL(k_island_sums, dim3(g.M, nrhs), dim3(256), 0, s, g.M,
-                     g.doffs.p, sigma, ldx, A, lda, out, ldo);
+  hipLaunchKernelGGL(k_island_sums, dim3(g.M, nrhs), dim3(256), 0, s,
+                     g.doffs.p, g.isl_geo.p, g.dgisl.p, sigma, ldx, A, lda,
+                     out, ldo);
   LBS_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------ Schur complement
-// S = D - F E: row 0 is (1, ..., 1) (sum(A) = 0 has no sigma part); row
-// k >= 1 is -sum_{i in island k} 2 G(x_i, c_m).
-__global__ void k_build_schur(int M, const int64_t *__restrict__ offs,
+// Per geometry (M_g islands, block at gsinv[g], row-major M_g x M_g):
+// S = D - F E; local row 0 is (1, ..., 1); local row kl >= 1 is
+// -sum_{i in island} 2 G(x_i, c_m).
+__global__ void k_build_schur(const int32_t *__restrict__ isl_geo,
+                              const int32_t *__restrict__ gisl,
+                              const int64_t *__restrict__ gsinv,
+                              const int64_t *__restrict__ offs,
                               const double *__restrict__ xyz,
                               const double *__restrict__ cxyz,
                               double *__restrict__ S) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
-  if (m >= M) return;
-  if (k == 0) {
-    S[m] = 1.0;
+  const int g = isl_geo[k];
+  const int Mg = gisl[g + 1] - gisl[g];
+  const int ml = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ml >= Mg) return;
+  const int kl = k - gisl[g];
+  double *Sg = S + gsinv[g];
+  if (kl == 0) {
+    Sg[ml] = 1.0;
     return;
   }
+  const int m = gisl[g] + ml;
   const double c0 = cxyz[3 * m], c1 = cxyz[3 * m + 1], c2 = cxyz[3 * m + 2];
   double acc = 0.0;
-  int64_t n = offs[k + 1] - offs[k];
+  const int64_t n = offs[k + 1] - offs[k];
   for (int64_t i = offs[k]; i < offs[k + 1]; ++i) {
     const double d0 = xyz[3 * i] - c0, d1 = xyz[3 * i + 1] - c1,
                  d2 = xyz[3 * i + 2] - c2;
@@ -219,25 +243,40 @@ __global__ void k_build_schur(int M, const int64_t *__restrict__ offs,
   }
   // 2 G = -(1/2pi) log|d|^2 + log2 / 2pi
   const double sum2g = -0.5 * kInvPi * acc + 0.5 * kInvPi * kLog2 * (double)n;
-  S[(int64_t)k * M + m] = -sum2g;
+  Sg[(int64_t)kl * Mg + ml] = -sum2g;
 }
 
 void launch_build_schur(const Geometry &g, double *S, hipStream_t s) {
   if (g.M == 0) return;
-  hipLaunchKernelGGL(k_build_schur, dim3((g.M + 255) / 256, g.M), dim3(256),
-                     0, s, g.M, g.doffs.p, g.xyz.p, g.dcenter.p, S);
+  hipLaunchKernelGGL(k_build_schur, dim3((g.maxM + 255) / 256, g.M),
+                     dim3(256), 0, s, g.isl_geo.p, g.dgisl.p, g.dgsinv.p,
+                     g.doffs.p, g.xyz.p, g.dcenter.p, S);
   LBS_HIP(hipGetLastError());
 }
 
-// Gauss-Jordan elimination with partial pivoting on [S | I].
+// Gauss-Jordan elimination with partial pivoting on [S_g | I] for every
+// geometry's block at once; step c touches the blocks with M_g > c.
+// Grid: blockIdx.z = geometry.
+__device__ __forceinline__ bool gj_block(const int32_t *gisl, int g, int c,
+                                         int &Mg) {
+  Mg = gisl[g + 1] - gisl[g];
+  return c < Mg;
+}
+
 __global__ void __launch_bounds__(256)
-    k_gj_pivot(int M, int c, const double *__restrict__ A, int *__restrict__ piv) {
+    k_gj_pivot(int c, const int32_t *__restrict__ gisl,
+               const int64_t *__restrict__ gsinv,
+               const double *__restrict__ A, int *__restrict__ piv) {
   __shared__ double bv[256];
   __shared__ int bi[256];
+  const int g = blockIdx.z;
+  int Mg;
+  if (!gj_block(gisl, g, c, Mg)) return;
+  const double *Ag = A + gsinv[g];
   double best = -1.0;
   int at = c;
-  for (int r = c + threadIdx.x; r < M; r += 256) {
-    double v = fabs(A[(int64_t)r * M + c]);
+  for (int r = c + threadIdx.x; r < Mg; r += 256) {
+    double v = fabs(Ag[(int64_t)r * Mg + c]);
     if (v > best) { best = v; at = r; }
   }
   bv[threadIdx.x] = best;
@@ -254,230 +293,448 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) piv[0] = bi[0];
+  if (threadIdx.x == 0) piv[g] = bi[0];
 }
 
-__global__ void k_gj_swap_scale(int M, int c, double *__restrict__ A,
-                                double *__restrict__ B,
-                                const int *__restrict__ piv,
-                                double *__restrict__ f) {
+__global__ void k_gj_swap(int c, const int32_t *__restrict__ gisl,
+                          const int64_t *__restrict__ gsinv,
+                          double *__restrict__ A, double *__restrict__ B,
+                          const int *__restrict__ piv) {
+  const int g = blockIdx.z;
+  int Mg;
+  if (!gj_block(gisl, g, c, Mg)) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = piv[0];
-  if (j < M) {
-    if (p != c) {
-      double t = A[(int64_t)c * M + j];
-      A[(int64_t)c * M + j] = A[(int64_t)p * M + j];
-      A[(int64_t)p * M + j] = t;
-      t = B[(int64_t)c * M + j];
-      B[(int64_t)c * M + j] = B[(int64_t)p * M + j];
-      B[(int64_t)p * M + j] = t;
-    }
-  }
+  const int p = piv[g];
+  if (j >= Mg || p == c) return;
+  double *Ag = A + gsinv[g], *Bg = B + gsinv[g];
+  double t = Ag[(int64_t)c * Mg + j];
+  Ag[(int64_t)c * Mg + j] = Ag[(int64_t)p * Mg + j];
+  Ag[(int64_t)p * Mg + j] = t;
+  t = Bg[(int64_t)c * Mg + j];
+  Bg[(int64_t)c * Mg + j] = Bg[(int64_t)p * Mg + j];
+  Bg[(int64_t)p * Mg + j] = t;
 }
 
-__global__ void k_gj_norm(int M, int c, double *__restrict__ A,
-                          double *__restrict__ B, double *__restrict__ f) {
+// Column-c factors of the other rows, then the pivot row scaled by the
+// inverse pivot (its diagonal entry is set to 1 by k_gj_fix).
+__global__ void k_gj_norm(int c, const int32_t *__restrict__ gisl,
+                          const int64_t *__restrict__ gsinv,
+                          double *__restrict__ A, double *__restrict__ B,
+                          double *__restrict__ f, int fstride) {
+  const int g = blockIdx.z;
+  int Mg;
+  if (!gj_block(gisl, g, c, Mg)) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const double inv = 1.0 / A[(int64_t)c * M + c];
-  __syncthreads();
-  if (j < M) {
-    // factors of the other rows (column c before elimination)
-    f[j] = (j == c) ? 0.0 : A[(int64_t)j * M + c];
-  }
-  if (j < M && j != c) {
-    A[(int64_t)c * M + j] *= inv;
-  }
-  if (j < M) B[(int64_t)c * M + j] *= inv;
+  if (j >= Mg) return;
+  double *Ag = A + gsinv[g], *Bg = B + gsinv[g];
+  const double inv = 1.0 / Ag[(int64_t)c * Mg + c];
+  f[(int64_t)g * fstride + j] = (j == c) ? 0.0 : Ag[(int64_t)j * Mg + c];
+  if (j != c) Ag[(int64_t)c * Mg + j] *= inv;
+  Bg[(int64_t)c * Mg + j] *= inv;
 }
 
-__global__ void k_gj_fix_pivot(int M, int c, double *__restrict__ A) {
-  A[(int64_t)c * M + c] = 1.0;
+__global__ void k_gj_fix(int c, const int32_t *__restrict__ gisl,
+                         const int64_t *__restrict__ gsinv,
+                         double *__restrict__ A) {
+  const int g = blockIdx.z;
+  int Mg;
+  if (!gj_block(gisl, g, c, Mg)) return;
+  if (threadIdx.x == 0) A[gsinv[g] + (int64_t)c * Mg + c] = 1.0;
 }
 
-__global__ void k_gj_eliminate(int M, int c, double *__restrict__ A,
-                               double *__restrict__ B,
-                               const double *__restrict__ f) {
+__global__ void k_gj_eliminate(int c, const int32_t *__restrict__ gisl,
+                               const int64_t *__restrict__ gsinv,
+                               double *__restrict__ A, double *__restrict__ B,
+                               const double *__restrict__ f, int fstride) {
+  const int g = blockIdx.z;
+  int Mg;
+  if (!gj_block(gisl, g, c, Mg)) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (j >= M || r == c) return;
-  const double fr = f[r];
+  if (j >= Mg || r >= Mg || r == c) return;
+  const double fr = f[(int64_t)g * fstride + r];
   if (fr == 0.0) return;
-  if (j > c) A[(int64_t)r * M + j] -= fr * A[(int64_t)c * M + j];
-  B[(int64_t)r * M + j] -= fr * B[(int64_t)c * M + j];
+  double *Ag = A + gsinv[g], *Bg = B + gsinv[g];
+  if (j > c) Ag[(int64_t)r * Mg + j] -= fr * Ag[(int64_t)c * Mg + j];
+  Bg[(int64_t)r * Mg + j] -= fr * Bg[(int64_t)c * Mg + j];
 }
 
-__global__ void k_gj_zero_col(int M, int c, double *__restrict__ A) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < M && r != c) A[(int64_t)r * M + c] = 0.0;
-}
-
-__global__ void k_identity(int M, double *__restrict__ B) {
+__global__ void k_gj_identity(const int32_t *__restrict__ gisl,
+                              const int64_t *__restrict__ gsinv,
+                              double *__restrict__ B) {
+  const int g = blockIdx.z;
+  const int Mg = gisl[g + 1] - gisl[g];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (j < M) B[(int64_t)r * M + j] = (r == j) ? 1.0 : 0.0;
+  if (j < Mg && r < Mg) B[gsinv[g] + (int64_t)r * Mg + j] = (r == j) ? 1.0 : 0.0;
 }
 
-void invert_dense(int M, double *S, double *Sinv, hipStream_t s) {
-  if (M == 0) return;
+void invert_blocks(const Geometry &g, double *S, double *Sinv, hipStream_t s) {
+  if (g.M == 0) return;
+  const int G = g.G, maxM = g.maxM;
   DBuf<int> piv;
-  piv.alloc(1);
+  piv.alloc(G);
   DBuf<double> f;
-  f.alloc(M);
-  const unsigned nb = (M + 255) / 256;
-  hipLaunchKernelGGL(k_identity, dim3(nb, M), dim3(256), 0, s, M, Sinv);
-  for (int c = 0; c < M; ++c) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, M, c, S, piv.p);
-    hipLaunchKernelGGL(k_gj_swap_scale, dim3(nb), dim3(256), 0, s, M, c, S,
-                       Sinv, piv.p, f.p);
-    // f must be read from the swapped matrix before the pivot row is scaled:
-    // k_gj_norm reads column c of every row (pivot row excluded) and scales
-    // the pivot row except its diagonal entry, which k_gj_fix_pivot sets.
-    hipLaunchKernelGGL(k_gj_norm, dim3(nb), dim3(256), 0, s, M, c, S, Sinv,
-                       f.p);
-    hipLaunchKernelGGL(k_gj_fix_pivot, dim3(1), dim3(1), 0, s, M, c, S);
-    hipLaunchKernelGGL(k_gj_eliminate, dim3(nb, M), dim3(256), 0, s, M, c, S,
-                       Sinv, f.p);
-    hipLaunchKernelGGL(k_gj_zero_col, dim3(nb), dim3(256), 0, s, M, c, S);
+  f.alloc((size_t)G * maxM);
+  const unsigned nb = (maxM + 255) / 256;
+  hipLaunchKernelGGL(k_gj_identity, dim3(nb, maxM, G), dim3(256), 0, s,
+                     g.dgisl.p, g.dgsinv.p, Sinv);
+  for (int c = 0; c < maxM; ++c) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1, 1, G), dim3(256), 0, s, c, g.dgisl.p,
+                       g.dgsinv.p, S, piv.p);
+    hipLaunchKernelGGL(k_gj_swap, dim3(nb, 1, G), dim3(256), 0, s, c, g.dgisl.p,
+                       g.dgsinv.p, S, Sinv, piv.p);
+    hipLaunchKernelGGL(k_gj_norm, dim3(nb, 1, G), dim3(256), 0, s, c, g.dgisl.p,
+                       g.dgsinv.p, S, Sinv, f.p, maxM);
+    hipLaunchKernelGGL(k_gj_fix, dim3(1, 1, G), dim3(64), 0, s, c, g.dgisl.p,
+                       g.dgsinv.p, S);
+    hipLaunchKernelGGL(k_gj_eliminate, dim3(nb, maxM, G), dim3(256), 0, s, c,
+                       g.dgisl.p, g.dgsinv.p, S, Sinv, f.p, maxM);
   }
   LBS_HIP(hipGetLastError());
   LBS_HIP(hipStreamSynchronize(s));
 }
 
-// y = alpha A x (A: M x M row-major), one wave per row.
+// y[k] = alpha sum_m Sinv_g[kl][ml] x[gisl[g] + ml] (block diagonal),
+// one wave per island row.
 __global__ void __launch_bounds__(256)
-    k_gemv(int M, const double *__restrict__ A, const double *__restrict__ x,
-           int64_t ldx, double *__restrict__ y, int64_t ldy, double alpha) {
+    k_gemv_blocks(int M, const int32_t *__restrict__ isl_geo,
+                  const int32_t *__restrict__ gisl,
+                  const int64_t *__restrict__ gsinv,
+                  const double *__restrict__ A, const double *__restrict__ x,
+                  int64_t ldx, double *__restrict__ y, int64_t ldy,
+                  double alpha) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int ln = threadIdx.x & 63;
   const int r = blockIdx.y;
   if (row >= M) return;
-  const double *xr = x + (int64_t)r * ldx;
-  const double *a = A + (int64_t)row * M;
+  const int g = isl_geo[row];
+  const int m0 = gisl[g], Mg = gisl[g + 1] - m0;
+  const double *xr = x + (int64_t)r * ldx + m0;
+  const double *a = A + gsinv[g] + (int64_t)(row - m0) * Mg;
   double acc = 0.0;
-  for (int j = ln; j < M; j += 64) acc += a[j] * xr[j];
+  for (int j = ln; j < Mg; j += 64) acc += a[j] * xr[j];
   acc = wave_sum(acc);
   if (ln == 0) y[(int64_t)r * ldy + row] = alpha * acc;
 }
 
-void launch_gemv(int M, const double *A, const double *x, int64_t ldx,
-                 int nrhs, double *y, int64_t ldy, double alpha,
-                 hipStream_t s) {
-  if (M == 0) return;
-  hipLaunchKernelGGL(k_gemv, dim3((M + 3) / 4, nrhs), dim3(256), 0, s, M, A,
-                     x, ldx, y, ldy, alpha);
+void launch_gemv_blocks(const Geometry &g, const double *x, int64_t ldx,
+                        int nrhs, double *y, int64_t ldy, double alpha,
+                        hipStream_t s) {
+  if (g.M == 0) return;
+  hipLaunchKernelGGL(k_gemv_blocks, dim3((g.M + 3) / 4, nrhs), dim3(256), 0,
+                     s, g.M, g.isl_geo.p, g.dgisl.p, g.dgsinv.p, g.Sinv.p, x,
+                     ldx, y, ldy, alpha);
   LBS_HIP(hipGetLastError());
 }
 
-// u_t += sum_m A_m G(x_t, c_m) + add[r]  (direct, one thread per target)
+// u_t += sum_m A_m G(x_t, c_m) + add[r G + geometry] over the islands of
+// target t's geometry (direct, one thread per target).
 __global__ void __launch_bounds__(256)
-    k_eval_logsrc(int64_t T, const double *__restrict__ txyz, int M,
+    k_eval_logsrc(int64_t T, const double *__restrict__ txyz,
+                  const int32_t *__restrict__ tgeo, int G,
+                  const int32_t *__restrict__ gisl,
                   const double *__restrict__ cxyz,
                   const double *__restrict__ A, int64_t lda,
                   const double *__restrict__ add, double *__restrict__ u,
                   int64_t ldu) {
-  __shared__ double c[256][3];
-  __shared__ double a[256];
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int r = blockIdx.y;
-  const bool act = t < T;
-  const double x0 = act ? txyz[3 * t] : 0.0, x1 = act ? txyz[3 * t + 1] : 0.0,
-               x2 = act ? txyz[3 * t + 2] : 0.0;
+  if (t >= T) return;
+  const int g = tgeo ? tgeo[t] : 0;
+  const double x0 = txyz[3 * t], x1 = txyz[3 * t + 1], x2 = txyz[3 * t + 2];
   double acc = 0.0, asum = 0.0;
-  for (int mb = 0; mb < M; mb += 256) {
-    __syncthreads();
-    const int m = mb + threadIdx.x;
-    if (m < M) {
-      c[threadIdx.x][0] = cxyz[3 * m];
-      c[threadIdx.x][1] = cxyz[3 * m + 1];
-      c[threadIdx.x][2] = cxyz[3 * m + 2];
-      a[threadIdx.x] = A[(int64_t)r * lda + m];
-    }
-    __syncthreads();
-    const int cnt = min(256, M - mb);
-    for (int q = 0; q < cnt; ++q) {
-      const double d0 = x0 - c[q][0], d1 = x1 - c[q][1], d2 = x2 - c[q][2];
-      acc += a[q] * log(d0 * d0 + d1 * d1 + d2 * d2);
-      asum += a[q];
-    }
+  const double *Ar = A + (int64_t)r * lda;
+  for (int m = gisl[g]; m < gisl[g + 1]; ++m) {
+    const double d0 = x0 - cxyz[3 * m], d1 = x1 - cxyz[3 * m + 1],
+                 d2 = x2 - cxyz[3 * m + 2];
+    acc += Ar[m] * log(d0 * d0 + d1 * d1 + d2 * d2);
+    asum += Ar[m];
   }
-  if (!act) return;
   // G = -(1/4pi) log|d|^2 + log2/4pi
-  u[(int64_t)r * ldu + t] += -0.25 * kInvPi * acc + 0.25 * kInvPi * kLog2 * asum +
-                             add[r];
+  u[(int64_t)r * ldu + t] += -0.25 * kInvPi * acc +
+                             0.25 * kInvPi * kLog2 * asum + add[r * G + g];
 }
 
-void launch_eval_logsrc(int64_t T, const double *txyz, int M,
-                        const double *cxyz, const double *A, int64_t lda,
+void launch_eval_logsrc(const Geometry &g, int64_t T, const double *txyz,
+                        const int32_t *tgeo, const double *A, int64_t lda,
                         int nrhs, const double *add, double *u, int64_t ldu,
                         hipStream_t s) {
   if (T == 0) return;
   hipLaunchKernelGGL(k_eval_logsrc, dim3((unsigned)((T + 255) / 256), nrhs),
-                     dim3(256), 0, s, T, txyz, M, cxyz, A, lda, add, u, ldu);
+                     dim3(256), 0, s, T, txyz, tgeo, g.G, g.dgisl.p,
+                     g.dcenter.p, A, lda, add, u, ldu);
+  LBS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------ segmented dots
+// out[(v * R + r) * nseg + s] = sum_{i in segment s} a_v[r][i] b[r][i],
+// a_v[r][i] = a[v * lav + r * lac + i], b[r][i] = b[r * lbc + i].
+// Segments are unions of row chunks (seg of each chunk).
+constexpr int kChunkRows = 2048;
+
+__global__ void __launch_bounds__(256)
+    k_seg_partial(const int64_t *__restrict__ c0, const int64_t *__restrict__ c1,
+                  int nchunk, const double *__restrict__ a, int64_t lav,
+                  int64_t lac, const double *__restrict__ b, int64_t lbc,
+                  double *__restrict__ part) {
+  __shared__ double red[4];
+  const int c = blockIdx.x, r = blockIdx.y, v = blockIdx.z;
+  const int R = gridDim.y;
+  const double *ar = a + (int64_t)v * lav + (int64_t)r * lac;
+  const double *br = b + (int64_t)r * lbc;
+  double acc = 0.0;
+  for (int64_t i = c0[c] + threadIdx.x; i < c1[c]; i += 256) acc += ar[i] * br[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part[((int64_t)v * R + r) * nchunk + c] = red[0] + red[1] + red[2] + red[3];
+}
+
+// One wave per output value: lanes stride over the segment's chunks.
+__global__ void __launch_bounds__(256)
+    k_seg_reduce(int nseg, int nchunk, int64_t nout,
+                 const int32_t *__restrict__ sptr,
+                 const int32_t *__restrict__ sidx,
+                 const double *__restrict__ part, double *__restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int ln = threadIdx.x & 63;
+  if (t >= nout) return;
+  const int s = (int)(t % nseg);
+  const int64_t vr = t / nseg;
+  double acc = 0.0;
+  for (int e = sptr[s] + ln; e < sptr[s + 1]; e += 64)
+    acc += part[vr * nchunk + sidx[e]];
+  acc = wave_sum(acc);
+  if (ln == 0) out[t] = acc;
+}
+
+void SegPlan::build(const std::vector<std::vector<std::pair<int64_t, int64_t>>> &ranges,
+                    hipStream_t s) {
+  std::vector<int64_t> a0, a1;
+  std::vector<int32_t> ptr(1, 0), idx;
+  nseg = (int)ranges.size();
+  for (int g = 0; g < nseg; ++g) {
+    for (auto &rg : ranges[g])
+      for (int64_t x = rg.first; x < rg.second; x += kChunkRows) {
+        idx.push_back((int32_t)a0.size());
+        a0.push_back(x);
+        a1.push_back(std::min<int64_t>(rg.second, x + kChunkRows));
+      }
+    ptr.push_back((int32_t)idx.size());
+  }
+  nchunk = (int)a0.size();
+  c0.upload(a0, s);
+  c1.upload(a1, s);
+  sptr.upload(ptr, s);
+  sidx.upload(idx, s);
+}
+
+void launch_segdots(const SegPlan &sp, int R, int nvec, const double *a,
+                    int64_t lav, int64_t lac, const double *b, int64_t lbc,
+                    double *out, double *scratch, hipStream_t s) {
+  if (sp.nchunk > 0)
+    hipLaunchKernelGGL(k_seg_partial, dim3(sp.nchunk, R, nvec), dim3(256), 0,
+                       s, sp.c0.p, sp.c1.p, sp.nchunk, a, lav, lac, b, lbc,
+                       scratch);
+  const int64_t n = (int64_t)nvec * R * sp.nseg;
+  hipLaunchKernelGGL(k_seg_reduce, dim3((unsigned)((n + 3) / 4)), dim3(256),
+                     0, s, sp.nseg, sp.nchunk, n, sp.sptr.p, sp.sidx.p,
+                     scratch, out);
   LBS_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------------ GMRES parts
-// w -= sum_{j < k1} h[j] V_j ; optionally hacc[j] += h[j]
-__global__ void k_maxpy(int64_t n, int k1, const double *__restrict__ V,
-                        int64_t ldv, const double *__restrict__ h,
-                        double *__restrict__ w, double *__restrict__ hacc) {
-  __shared__ double hs[128];
-  for (int j = threadIdx.x; j < k1; j += blockDim.x) hs[j] = h[j];
-  __syncthreads();
-  if (hacc && blockIdx.x == 0)
-    for (int j = threadIdx.x; j < k1; j += blockDim.x) hacc[j] += hs[j];
+// Systems s = r * G + g (right-hand side r, geometry g) run GMRES(m) in
+// lockstep on one Krylov array V[j][r][row], row over the N + M unknowns of
+// all geometries; row_geo gives each row's geometry.  Per-system state:
+// H[s][(m+1) m] (column-major per system), cs, sn, g (m+1), y, residual,
+// tolerance, active flag and the number of Arnoldi columns in use.
+
+// w[r][i] -= sum_{j < k1} h[j S + s] V_j[r][i]
+__global__ void k_maxpy_seg(int64_t n, int R, int G, int k1,
+                            const int32_t *__restrict__ row_geo,
+                            const double *__restrict__ V, int64_t ldv,
+                            const double *__restrict__ h,
+                            double *__restrict__ w) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
   if (i >= n) return;
+  const int S = R * G;
+  const int s = r * G + row_geo[i];
+  const int64_t off = (int64_t)r * n + i;
   double acc = 0.0;
-  for (int j = 0; j < k1; ++j) acc += hs[j] * V[(int64_t)j * ldv + i];
-  w[i] -= acc;
+  for (int j = 0; j < k1; ++j) acc += h[j * S + s] * V[(int64_t)j * ldv + off];
+  w[off] -= acc;
 }
 
-void launch_maxpy(int64_t n, int k1, const double *V, int64_t ldv,
-                  const double *h, double *w, double *hacc, hipStream_t s) {
-  hipLaunchKernelGGL(k_maxpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     s, n, k1, V, ldv, h, w, hacc);
+void launch_maxpy_seg(int64_t n, int R, int G, int k1, const int32_t *row_geo,
+                      const double *V, int64_t ldv, const double *h, double *w,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_maxpy_seg, dim3((unsigned)((n + 255) / 256), R),
+                     dim3(256), 0, s, n, R, G, k1, row_geo, V, ldv, h, w);
   LBS_HIP(hipGetLastError());
 }
 
-// x += sum_{j < k} y[j] V_j
-__global__ void k_update(int64_t n, int k, const double *__restrict__ V,
-                         int64_t ldv, const double *__restrict__ y,
-                         double *__restrict__ x) {
-  __shared__ double ys[128];
-  for (int j = threadIdx.x; j < k; j += blockDim.x) ys[j] = y[j];
-  __syncthreads();
+// x[r][i] += sum_{j < k} y[s][j] V_j[r][i]   (y zero beyond each system's k)
+__global__ void k_update_seg(int64_t n, int R, int G, int k, int m,
+                             const int32_t *__restrict__ row_geo,
+                             const double *__restrict__ V, int64_t ldv,
+                             const double *__restrict__ y,
+                             double *__restrict__ x) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
   if (i >= n) return;
+  const int s = r * G + row_geo[i];
+  const int64_t off = (int64_t)r * n + i;
   double acc = 0.0;
-  for (int j = 0; j < k; ++j) acc += ys[j] * V[(int64_t)j * ldv + i];
-  x[i] += acc;
+  for (int j = 0; j < k; ++j) acc += y[(int64_t)s * m + j] * V[(int64_t)j * ldv + off];
+  x[off] += acc;
 }
 
-void launch_update(int64_t n, int k, const double *V, int64_t ldv,
-                   const double *y, double *x, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     s, n, k, V, ldv, y, x);
+void launch_update_seg(int64_t n, int R, int G, int k, int m,
+                       const int32_t *row_geo, const double *V, int64_t ldv,
+                       const double *y, double *x, hipStream_t s) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_update_seg, dim3((unsigned)((n + 255) / 256), R),
+                     dim3(256), 0, s, n, R, G, k, m, row_geo, V, ldv, y, x);
   LBS_HIP(hipGetLastError());
 }
 
-// v = w / sqrt(nrm2) and hout = sqrt(nrm2) (v = 0 on breakdown)
-__global__ void k_normalize(int64_t n, const double *__restrict__ nrm2,
-                            const double *__restrict__ w,
-                            double *__restrict__ v, double *__restrict__ hout) {
-  const double s = sqrt(fmax(nrm2[0], 0.0));
+// v[r][i] = active[s] ? w[r][i] / sqrt(nrm2[s]) : 0
+__global__ void k_normalize_seg(int64_t n, int R, int G,
+                                const int32_t *__restrict__ row_geo,
+                                const double *__restrict__ nrm2,
+                                const int32_t *__restrict__ active,
+                                const double *__restrict__ w,
+                                double *__restrict__ v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0 && hout) hout[0] = s;
-  if (i < n) v[i] = s > 0.0 ? w[i] / s : 0.0;
+  const int r = blockIdx.y;
+  if (i >= n) return;
+  const int s = r * G + row_geo[i];
+  const double q = sqrt(fmax(nrm2[s], 0.0));
+  const int64_t off = (int64_t)r * n + i;
+  v[off] = (active[s] && q > 0.0) ? w[off] / q : 0.0;
 }
 
-void launch_normalize(int64_t n, const double *nrm2, const double *w,
-                      double *v, double *hout, hipStream_t s) {
-  hipLaunchKernelGGL(k_normalize, dim3((unsigned)((n + 255) / 256)), dim3(256),
-                     0, s, n, nrm2, w, v, hout);
+void launch_normalize_seg(int64_t n, int R, int G, const int32_t *row_geo,
+                          const double *nrm2, const int32_t *active,
+                          const double *w, double *v, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalize_seg, dim3((unsigned)((n + 255) / 256), R),
+                     dim3(256), 0, s, n, R, G, row_geo, nrm2, active, w, v);
   LBS_HIP(hipGetLastError());
 }
 
+// Cycle start: g = (beta, 0, ...), active = beta > tol, kused = 0; counts
+// active systems into *count (reset by the caller's fill).
+__global__ void k_gmres_start(int S, int m, const double *__restrict__ nrm2,
+                              const double *__restrict__ tol,
+                              double *__restrict__ g, int32_t *__restrict__ active,
+                              int32_t *__restrict__ kused,
+                              int32_t *__restrict__ count) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const double beta = sqrt(fmax(nrm2[s], 0.0));
+  for (int j = 0; j <= m; ++j) g[(int64_t)s * (m + 1) + j] = (j == 0) ? beta : 0.0;
+  const int a = beta > tol[s];
+  active[s] = a;
+  kused[s] = 0;
+  if (a) atomicAdd(count, 1);
+}
+
+void launch_gmres_start(int S, int m, const double *nrm2, const double *tol,
+                        double *g, int32_t *active, int32_t *kused,
+                        int32_t *count, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_start, dim3((S + 255) / 256), dim3(256), 0, s, S,
+                     m, nrm2, tol, g, active, kused, count);
+  LBS_HIP(hipGetLastError());
+}
+
+// Arnoldi step k for every active system: column k of H from the two CGS
+// passes (h1 + h2) and the norm, previous rotations, new rotation, g
+// update, residual, convergence flag; counts systems still active.
+__global__ void k_givens_seg(int S, int k, int m, const double *__restrict__ h1,
+                             const double *__restrict__ h2,
+                             const double *__restrict__ nrm2,
+                             const double *__restrict__ tol,
+                             double *__restrict__ H, double *__restrict__ cs,
+                             double *__restrict__ sn, double *__restrict__ g,
+                             double *__restrict__ resid,
+                             int32_t *__restrict__ active,
+                             int32_t *__restrict__ kused,
+                             int32_t *__restrict__ count) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S || !active[s]) return;
+  double *h = H + (int64_t)s * (m + 1) * m + (int64_t)k * (m + 1);
+  double *c = cs + (int64_t)s * m, *sg = sn + (int64_t)s * m;
+  double *gg = g + (int64_t)s * (m + 1);
+  for (int j = 0; j <= k; ++j) h[j] = h1[j * S + s] + h2[j * S + s];
+  h[k + 1] = sqrt(fmax(nrm2[s], 0.0));
+  for (int j = 0; j < k; ++j) {
+    const double t = c[j] * h[j] + sg[j] * h[j + 1];
+    h[j + 1] = -sg[j] * h[j] + c[j] * h[j + 1];
+    h[j] = t;
+  }
+  const double a = h[k], b = h[k + 1];
+  const double den = hypot(a, b);
+  double cc = 1.0, ss = 0.0;
+  if (den > 0.0) {
+    cc = a / den;
+    ss = b / den;
+  }
+  c[k] = cc;
+  sg[k] = ss;
+  h[k] = den;
+  h[k + 1] = 0.0;
+  gg[k + 1] = -ss * gg[k];
+  gg[k] = cc * gg[k];
+  const double res = fabs(gg[k + 1]);
+  resid[s] = res;
+  kused[s] = k + 1;
+  if (res <= tol[s] || !(res == res)) active[s] = 0;
+  else atomicAdd(count, 1);
+}
+
+void launch_givens_seg(int S, int k, int m, const double *h1, const double *h2,
+                       const double *nrm2, const double *tol, double *H,
+                       double *cs, double *sn, double *g, double *resid,
+                       int32_t *active, int32_t *kused, int32_t *count,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_givens_seg, dim3((S + 63) / 64), dim3(64), 0, s, S, k,
+                     m, h1, h2, nrm2, tol, H, cs, sn, g, resid, active, kused,
+                     count);
+  LBS_HIP(hipGetLastError());
+}
+
+// y[s] = R_s^{-1} g_s over the first kused[s] columns (zeros beyond).
+__global__ void k_backsolve_seg(int S, int m, const double *__restrict__ H,
+                                const double *__restrict__ g,
+                                const int32_t *__restrict__ kused,
+                                double *__restrict__ y) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const double *Hs = H + (int64_t)s * (m + 1) * m;
+  const double *gs = g + (int64_t)s * (m + 1);
+  double *ys = y + (int64_t)s * m;
+  const int k = kused[s];
+  for (int i = m - 1; i >= k; --i) ys[i] = 0.0;
+  for (int i = k - 1; i >= 0; --i) {
+    double acc = gs[i];
+    for (int j = i + 1; j < k; ++j) acc -= Hs[(int64_t)j * (m + 1) + i] * ys[j];
+    const double d = Hs[(int64_t)i * (m + 1) + i];
+    ys[i] = d != 0.0 ? acc / d : 0.0;
+  }
+}
+
+void launch_backsolve_seg(int S, int m, const double *H, const double *g,
+                          const int32_t *kused, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_backsolve_seg, dim3((S + 63) / 64), dim3(64), 0, s, S,
+                     m, H, g, kused, y);
+  LBS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ vectors
 // y = a x + b y
 __global__ void k_axpby(int64_t n, double a, const double *__restrict__ x,
                         double b, double *__restrict__ y) {
@@ -505,70 +762,45 @@ void launch_fill(int64_t n, double v, double *x, hipStream_t s) {
   LBS_HIP(hipGetLastError());
 }
 
-// Givens step k of GMRES(m): H is column-major with leading dimension
-// m + 1; column k holds h_{0..k+1, k}.  Applies the previous rotations,
-// forms rotation k, updates g and writes |g_{k+1}| to resid.
-__global__ void k_givens(int k, int m, double *__restrict__ H,
-                         double *__restrict__ cs, double *__restrict__ sn,
-                         double *__restrict__ g, double *__restrict__ resid) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double *h = H + (int64_t)k * (m + 1);
-  for (int j = 0; j < k; ++j) {
-    const double t = cs[j] * h[j] + sn[j] * h[j + 1];
-    h[j + 1] = -sn[j] * h[j] + cs[j] * h[j + 1];
-    h[j] = t;
-  }
-  const double a = h[k], b = h[k + 1];
-  const double den = hypot(a, b);
-  double c = 1.0, s = 0.0;
-  if (den > 0.0) {
-    c = a / den;
-    s = b / den;
-  }
-  cs[k] = c;
-  sn[k] = s;
-  h[k] = den;
-  h[k + 1] = 0.0;
-  g[k + 1] = -s * g[k];
-  g[k] = c * g[k];
-  resid[0] = fabs(g[k + 1]);
+__global__ void k_fill_int(int64_t n, int32_t v, int32_t *__restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
 }
 
-void launch_givens(int k, int m, double *H, double *cs, double *sn,
-                   double *gvec, double *resid, hipStream_t s) {
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, k, m, H, cs, sn, gvec,
-                     resid);
+void launch_fill_int(int64_t n, int32_t v, int32_t *x, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((n + 255) / 256)), dim3(256),
+                     0, s, n, v, x);
   LBS_HIP(hipGetLastError());
 }
 
-// Solve the k x k upper triangle of H for y (H y = g).
-__global__ void k_backsolve(int k, int m, const double *__restrict__ H,
-                            const double *__restrict__ g,
-                            double *__restrict__ y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int i = k - 1; i >= 0; --i) {
-    double acc = g[i];
-    for (int j = i + 1; j < k; ++j) acc -= H[(int64_t)j * (m + 1) + i] * y[j];
-    const double d = H[(int64_t)i * (m + 1) + i];
-    y[i] = d != 0.0 ? acc / d : 0.0;
-  }
+// Strided copy of R columns: dst[r * ldd + i] = a * src[r * lds + i]
+__global__ void k_copy_cols(int64_t n, double a, const double *__restrict__ src,
+                            int64_t lds, double *__restrict__ dst, int64_t ldd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i < n) dst[(int64_t)r * ldd + i] = a * src[(int64_t)r * lds + i];
 }
 
-void launch_backsolve(int k, int m, const double *H, const double *gvec,
-                      double *y, hipStream_t s) {
-  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, k, m, H, gvec, y);
+void launch_copy_cols(int64_t n, int R, double a, const double *src, int64_t lds,
+                      double *dst, int64_t ldd, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)((n + 255) / 256), R),
+                     dim3(256), 0, s, n, a, src, lds, dst, ldd);
   LBS_HIP(hipGetLastError());
 }
 
-// g = (beta, 0, ..., 0) with beta = sqrt(nrm2)
-__global__ void k_init_g(int m, const double *__restrict__ nrm2,
-                         double *__restrict__ g) {
-  const int j = threadIdx.x;
-  if (j <= m) g[j] = (j == 0) ? sqrt(fmax(nrm2[0], 0.0)) : 0.0;
+// tol[s] = t * sqrt(nrm2[s])
+__global__ void k_scale_sqrt(int S, double t, const double *__restrict__ nrm2,
+                             double *__restrict__ out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S) out[s] = t * sqrt(fmax(nrm2[s], 0.0));
 }
 
-void launch_init_g(int m, const double *nrm2, double *g, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_g, dim3(1), dim3(128), 0, s, m, nrm2, g);
+void launch_scale_sqrt(int S, double t, const double *nrm2, double *out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_sqrt, dim3((S + 255) / 256), dim3(256), 0, s, S,
+                     t, nrm2, out);
   LBS_HIP(hipGetLastError());
 }
 

@@ -305,3 +305,51 @@ int64_t check_coverage(const Tree &T) {
 }
 
 }  // namespace lbs
+
+namespace lbs {
+
+void append_tree(Tree &F, const Tree &t, int64_t src_base, int64_t tgt_base,
+                 int64_t src_index_base, int64_t tgt_index_base) {
+  const int off = F.nbox();
+  auto cat = [](auto &dst, const auto &src) {
+    dst.insert(dst.end(), src.begin(), src.end());
+  };
+  cat(F.cx, t.cx);
+  cat(F.cy, t.cy);
+  cat(F.rad, t.rad);
+  cat(F.level, t.level);
+  cat(F.ix, t.ix);
+  cat(F.iy, t.iy);
+  cat(F.leaf, t.leaf);
+  cat(F.nchild, t.nchild);
+  for (int b = 0; b < t.nbox(); ++b) {
+    F.parent.push_back(t.parent[b] < 0 ? -1 : t.parent[b] + off);
+    F.child0.push_back(t.child0[b] < 0 ? -1 : t.child0[b] + off);
+    F.s0.push_back(t.s0[b] + src_base);
+    F.s1.push_back(t.s1[b] + src_base);
+    F.t0.push_back(t.t0[b] + tgt_base);
+    F.t1.push_back(t.t1[b] + tgt_base);
+  }
+  auto cat_csr = [&](std::vector<int32_t> &fp, std::vector<int32_t> &fi,
+                     const std::vector<int32_t> &tp,
+                     const std::vector<int32_t> &ti) {
+    if (fp.empty()) fp.push_back(0);
+    const int32_t base = fp.back();
+    for (int b = 0; b < t.nbox(); ++b) fp.push_back(base + tp[b + 1]);
+    for (int32_t v : ti) fi.push_back(v + off);
+  };
+  cat_csr(F.v_ptr, F.v_src, t.v_ptr, t.v_src);
+  cat(F.v_code, t.v_code);
+  cat_csr(F.x_ptr, F.x_src, t.x_ptr, t.x_src);
+  cat_csr(F.u_ptr, F.u_src, t.u_ptr, t.u_src);
+  cat_csr(F.w_ptr, F.w_src, t.w_ptr, t.w_src);
+  for (int64_t v : t.src_perm) F.src_perm.push_back(v + src_index_base);
+  for (int64_t v : t.tgt_perm) F.tgt_perm.push_back(v + tgt_index_base);
+  F.nlevels = std::max(F.nlevels, t.nlevels);
+  F.self = t.self;
+  F.p2p_pairs += t.p2p_pairs;
+  F.m2p_evals += t.m2p_evals;
+  F.p2l_evals += t.p2l_evals;
+}
+
+}  // namespace lbs

@@ -49,6 +49,11 @@ void build_tree(const double *sx, const double *sy, int64_t ns,
                 const double *tx, const double *ty, int64_t nt, bool self,
                 int leaf_max, Tree &T);
 
+// Append tree t to the forest F: box indices shift by F's box count, point
+// ranges by src_base / tgt_base, permutation entries by the index bases.
+void append_tree(Tree &F, const Tree &t, int64_t src_base, int64_t tgt_base,
+                 int64_t src_index_base, int64_t tgt_index_base);
+
 // Count ordered point pairs (i in targets, j in sources, i != j when self)
 // covered zero or several times by U, V, W and X.  O(leaves^2 depth).
 int64_t check_coverage(const Tree &T);

@@ -23,8 +23,8 @@ STATUS = {0: "LBS_OK", 1: "LBS_ERR_INVALID_ARG", 2: "LBS_ERR_GEOMETRY",
           7: "LBS_ERR_UNSUPPORTED"}
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
-STAGES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "gamma",
-          "logsrc", "constraint")
+STAGES = ("strengths", "upward", "l2l", "m2l", "p2l", "leaf",
+          "gamma", "logsrc", "constraint")
 
 
 class Island(ctypes.Structure):
@@ -103,6 +103,17 @@ def load():
     lib.lbs_eval.argtypes = [H, ctypes.c_int32, vp, vp, ctypes.c_int64, vp,
                              vp, vp]
     lib.lbs_destroy.argtypes = [H]
+    lib.lbs_setup_batch.argtypes = [ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(Island),
+                                    ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(Options), vp,
+                                    ctypes.POINTER(H)]
+    lib.lbs_batch_info.argtypes = [H, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_int32)]
+    lib.lbs_eval_batch.argtypes = [H, ctypes.c_int32, vp, vp,
+                                   ctypes.POINTER(ctypes.c_int64), vp, vp, vp]
     lib.lbs_stage_timing.argtypes = [H, ctypes.c_int32]
     lib.lbs_stage_times.argtypes = [H, c_double_p,
                                     ctypes.POINTER(ctypes.c_int64),
@@ -114,7 +125,8 @@ def load():
                                         ctypes.POINTER(TreeStats)]
     for name in ("lbs_setup", "lbs_sizes", "lbs_nodes", "lbs_matvec",
                  "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
-                 "lbs_stage_timing", "lbs_stage_times",
+                 "lbs_stage_timing", "lbs_stage_times", "lbs_setup_batch",
+                 "lbs_batch_info", "lbs_eval_batch",
                  "lbs_check_tree_host"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -171,24 +183,53 @@ def _rhs(t, n):
 
 
 class Solver:
-    """One island geometry on the GPU (lbs_setup ... lbs_destroy)."""
+    """Island geometries on the GPU (lbs_setup / lbs_setup_batch ...
+    lbs_destroy).  `islands` is one island set, or a list of them for a
+    batch handle (geometry-major node and island numbering)."""
 
     def __init__(self, islands, nodes=None, options=None, **kw):
         lib = load()
-        arr = islands_array(islands)
-        n = islands.n if nodes is None else nodes
-        m = len(islands.r0)
-        nn = (ctypes.c_int32 * m)(*[int(v) for v in
-                                    (n if hasattr(n, "__len__") else [n] * m)])
         self.options = options if options is not None else default_options(**kw)
         h = ctypes.c_void_p()
-        _check(lib.lbs_setup(arr, m, nn, ctypes.byref(self.options), _stream(),
-                             ctypes.byref(h)))
+        if isinstance(islands, (list, tuple)):
+            sets = list(islands)
+            g = len(sets)
+            per = (ctypes.c_int32 * g)(*[len(s.r0) for s in sets])
+            m = sum(per)
+            arr = (Island * m)()
+            nn = (ctypes.c_int32 * m)()
+            k = 0
+            for s in sets:
+                a = islands_array(s)
+                for q in range(len(s.r0)):
+                    arr[k] = a[q]
+                    nn[k] = int(s.n[q])
+                    k += 1
+            _check(lib.lbs_setup_batch(g, per, arr, nn,
+                                       ctypes.byref(self.options), _stream(),
+                                       ctypes.byref(h)))
+        else:
+            arr = islands_array(islands)
+            n = islands.n if nodes is None else nodes
+            m = len(islands.r0)
+            nn = (ctypes.c_int32 * m)(*[int(v) for v in
+                                        (n if hasattr(n, "__len__")
+                                         else [n] * m)])
+            _check(lib.lbs_setup(arr, m, nn, ctypes.byref(self.options),
+                                 _stream(), ctypes.byref(h)))
         self._h = h
         nt = ctypes.c_int64()
         mt = ctypes.c_int32()
         _check(lib.lbs_sizes(h, ctypes.byref(nt), ctypes.byref(mt)))
         self.n_nodes, self.n_islands = nt.value, mt.value
+        gq = ctypes.c_int32()
+        _check(lib.lbs_batch_info(h, ctypes.byref(gq), None, None))
+        self.n_geoms = gq.value
+        noff = (ctypes.c_int64 * (gq.value + 1))()
+        ioff = (ctypes.c_int32 * (gq.value + 1))()
+        _check(lib.lbs_batch_info(h, None, noff, ioff))
+        self.node_offsets = list(noff)
+        self.island_offsets = list(ioff)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -231,13 +272,22 @@ class Solver:
         d["status"] = STATUS.get(code, code)
         return sig, a, d
 
-    def eval(self, sigma, A, targets):
+    def eval(self, sigma, A, targets, target_offsets=None):
+        """u at sphere targets (T x 3).  For a batch handle pass the
+        geometry-major target_offsets (n_geoms + 1 entries)."""
         nrhs = _rhs(sigma, self.n_nodes)
         t = targets.shape[0]
         shape = (t,) if sigma.dim() == 1 else (nrhs, t)
         u = torch.empty(shape, dtype=torch.float64, device="cuda")
-        _check(load().lbs_eval(self._h, nrhs, _dev(sigma), _dev(A), t,
-                               _dev(targets), _dev(u), _stream()))
+        if target_offsets is None:
+            _check(load().lbs_eval(self._h, nrhs, _dev(sigma), _dev(A), t,
+                                   _dev(targets), _dev(u), _stream()))
+        else:
+            off = (ctypes.c_int64 * len(target_offsets))(
+                *[int(v) for v in target_offsets])
+            _check(load().lbs_eval_batch(self._h, nrhs, _dev(sigma), _dev(A),
+                                         off, _dev(targets), _dev(u),
+                                         _stream()))
         return u
 
     def stage_timing(self, enable=True):
