@@ -188,6 +188,52 @@ lbs_status lbs_eval_batch(lbs_handle h, int32_t nrhs, const double *sigma,
                           const int64_t *target_offsets_host,
                           const double *xyz_targets, double *u, void *stream);
 
+/* ---------------------------------------------------------------- adjoint
+ * Derivatives of a scalar L(u) of the solution u = T x at targets, where
+ * x = [sigma; A] solves the system of eqs. matrix_eqns with right-hand side
+ * [2 g; 0] and T is the evaluation of eq. eqn:u_multi (Sections 4.1, 5):
+ *   lambda = A^-T T^T w,  w = dL/du,
+ *   dL/dg = 2 lambda_sigma,
+ *   dL/dbeta = w^T (dT/dbeta) x - lambda^T (dA/dbeta) x,
+ * beta = the 16 radius coefficients (a_1..a_8, b_1..b_8) of every island,
+ * which move the nodes and with them xi, xi', xi'' (Section 3) in the
+ * kernel, the log-source rows and the evaluation.  The node data g is a
+ * vector held fixed when beta moves.  All in FP64 with the FMM of p64
+ * terms.  Single-geometry handles (LBS_ERR_UNSUPPORTED otherwise, except
+ * lbs_solve_T, which takes batch handles).  Device pointers, column-major
+ * as in lbs_solve; calls are stream-ordered on `stream` and return after it
+ * has drained. */
+
+/* T^T w: gs (N x nrhs) = the double-layer part of the transposed
+ * evaluation, ga (M x nrhs) = its log-source part, for target weights w
+ * (n_targets x nrhs) at xyz_targets (n_targets x 3, as in lbs_eval; targets
+ * at the north pole carry no Cauchy part).  n_targets = 0 gives zeros. */
+lbs_status lbs_eval_T(lbs_handle h, int32_t nrhs, const double *w,
+                      int64_t n_targets, const double *xyz_targets,
+                      double *gs, double *ga, void *stream);
+
+/* Solve A^T [lam_s; lam_a] = [rhs_s; rhs_a] (rhs_s, lam_s: N x nrhs;
+ * rhs_a, lam_a: M x nrhs; rhs_a may be NULL for zeros) by GMRES with the
+ * transposed block preconditioner on the right, to the relative residual
+ * tol of the unpreconditioned transposed system, per system.  info as in
+ * lbs_solve (iters, rel_resid; fp64_matvecs counts transposed operator
+ * applications).  LBS_ERR_NO_CONVERGENCE when max_iter is reached; the
+ * iterate is still written. */
+lbs_status lbs_solve_T(lbs_handle h, int32_t nrhs, const double *rhs_s,
+                       const double *rhs_a, double tol, double *lam_s,
+                       double *lam_a, lbs_solve_info *info_host,
+                       void *stream);
+
+/* dcoef (M x 16, island-major, coefficient order of lbs_island.coef) =
+ * w^T (dT/dbeta) x - lambda^T (dA/dbeta) x for one solution (sigma: N,
+ * A: M), the adjoint density lam_s (N; lambda's island part does not enter
+ * because the constraint rows do not depend on the shape) and target
+ * weights w (n_targets) at xyz_targets. */
+lbs_status lbs_shape_vjp(lbs_handle h, const double *sigma, const double *A,
+                         const double *lam_s, int64_t n_targets,
+                         const double *xyz_targets, const double *w,
+                         double *dcoef, void *stream);
+
 /* Per-stage GPU timing of operator applications.  With enable != 0 every
  * stage of every later lbs_matvec / lbs_solve call is bracketed by a pair
  * of HIP events recorded on the call's stream; lbs_stage_times waits for

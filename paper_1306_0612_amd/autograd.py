@@ -1,0 +1,63 @@
+"""Differentiable solve-and-evaluate: u(g, beta) at sphere targets.
+
+Forward: set up the islands with radius coefficients beta, solve the system
+of eqs. matrix_eqns with data g (FP64 FMM, GMRES with the block
+preconditioner) and evaluate eq. eqn:u_multi at the targets.  Backward, for
+the incoming w = dL/du: the transposed evaluation T^T w, the transposed solve
+A^T lambda = T^T w, then dL/dg = 2 lambda_sigma and dL/dbeta from the shape
+derivatives of the operator and the evaluation.  Every step runs in liblbs
+(lbs_setup, lbs_solve, lbs_eval, lbs_eval_T, lbs_solve_T, lbs_shape_vjp);
+this module only moves tensors.
+"""
+import types
+
+import torch
+
+from . import lbs
+
+
+def _islands_with(islands, coef):
+    c = coef.detach().to("cpu", torch.float64).numpy()
+    if c.shape != (len(islands.r0), 16):
+        raise ValueError("coef must have shape (M, 16)")
+    return types.SimpleNamespace(center=islands.center, e1=islands.e1,
+                                 r0=islands.r0, coef=c, n=islands.n)
+
+
+class SolveEval(torch.autograd.Function):
+    """u = SolveEval.apply(g, coef, islands, targets, tol, options)."""
+
+    @staticmethod
+    def forward(ctx, g, coef, islands, targets, tol, options):
+        sol = lbs.Solver(_islands_with(islands, coef), **options)
+        sig, A, info = sol.solve(g.detach().contiguous(), tol=tol,
+                                 precision="fp64")
+        u = sol.eval(sig, A, targets)
+        ctx.sol = sol
+        ctx.targets = targets
+        ctx.tol = tol
+        ctx.coef_device = coef.device
+        ctx.forward_info = info
+        ctx.save_for_backward(sig, A)
+        return u
+
+    @staticmethod
+    def backward(ctx, w):
+        sol, targets = ctx.sol, ctx.targets
+        sig, A = ctx.saved_tensors
+        w = w.detach().to(torch.float64).contiguous()
+        gs, ga = sol.eval_T(w, targets)
+        lam_s, _, info = sol.solve_T(gs, ga, tol=ctx.tol)
+        ctx.adjoint_info = info
+        dg = 2.0 * lam_s if ctx.needs_input_grad[0] else None
+        dc = None
+        if ctx.needs_input_grad[1]:
+            dc = sol.shape_vjp(sig, A, lam_s, w, targets).to(ctx.coef_device)
+        return dg, dc, None, None, None, None
+
+
+def solve_eval(g, coef, islands, targets, tol=1e-12, **options):
+    """u at `targets` (T x 3, float64 CUDA) for node data g (N, float64
+    CUDA) on islands whose radius coefficients are `coef` (M x 16);
+    `islands` supplies center, e1, r0 and n.  Differentiable in g and coef."""
+    return SolveEval.apply(g, coef, islands, targets, tol, options)

@@ -1,0 +1,614 @@
+// Transposed operators and the shape derivative of a target misfit
+// (adjoint of the method of Section 5).  All FP64.
+//
+// With the system A(beta) x = [2g; 0] (eq. matrix_eqns) and the evaluation
+// u = T(beta) x (eq. eqn:u_multi), the misfit L = 1/2 |u - u*|^2 has
+//   dL/dg = 2 lambda_sigma,     A^T lambda = T^T w,  w = u - u*,
+//   dL/dbeta = w^T (dT/dbeta) x - lambda^T (dA/dbeta) x.
+// beta are the Fourier coefficients of the island radii; they move the
+// nodes, hence xi, xi', xi'' (Section 3) of the kernel and the node
+// positions of the log-source rows.  Complex cotangents g of a complex
+// quantity z are defined by d(Phi) = Re(g dz).
+#include <cmath>
+
+#include "cplx.h"
+#include "lbs_internal.h"
+
+namespace lbs {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kInvPi_ = 0.31830988618379067154;
+constexpr double kLog2_ = 0.69314718055994530942;
+
+__device__ __forceinline__ double wsum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ bool in_sorted(const int32_t *a, int n, int x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < n && a[lo] == x;
+}
+
+// out_j = ident y_j + Re(i q_j F_j) + tau_j y_j + gw_j Y_geo(j), the rows of
+// (I + K)^T y: q_j = (s h / pi) xi'_j, F_j = sum_{i != j} y_i / (xi_j - xi_i),
+// Y = sum of y over the geometry.
+__global__ void k_kT_assemble(int64_t N, const double *__restrict__ y,
+                              const double *__restrict__ F,
+                              const double *__restrict__ qfac,
+                              const double *__restrict__ tau,
+                              const double *__restrict__ gw,
+                              const int32_t *__restrict__ geo,
+                              const double *__restrict__ ysum, double ident,
+                              double *__restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const double qx = qfac[2 * j], qy = qfac[2 * j + 1];
+  const double fx = F[2 * j], fy = F[2 * j + 1];
+  // Re(i (q F)) = -Im(q F)
+  const double t = -(qx * fy + qy * fx);
+  out[j] = ident * y[j] + t + tau[j] * y[j] + gw[j] * ysum[geo[j]];
+}
+
+void launch_kT_assemble(const Geometry &g, const double *y, const double *F,
+                        const double *ysum, double ident, double *out,
+                        hipStream_t s) {
+  if (g.N == 0) return;
+  hipLaunchKernelGGL(k_kT_assemble, dim3((unsigned)((g.N + 255) / 256)),
+                     dim3(256), 0, s, g.N, y, F, g.qfac.p, g.tau.p, g.gw.p,
+                     g.node_geo.p, ysum, ident, out);
+  LBS_HIP(hipGetLastError());
+}
+
+// complex strengths from a real vector: out = (y, 0)
+__global__ void k_real_to_complex(int64_t n, const double *__restrict__ y,
+                                  double *__restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) {
+    out[2 * j] = y[j];
+    out[2 * j + 1] = 0.0;
+  }
+}
+
+void launch_real_to_complex(int64_t n, const double *y, double *out,
+                            hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_real_to_complex, dim3((unsigned)((n + 255) / 256)),
+                     dim3(256), 0, s, n, y, out);
+  LBS_HIP(hipGetLastError());
+}
+
+// out = (y[idx[q]], 0) for q < n
+__global__ void k_gather_complex(int64_t n, const int64_t *__restrict__ idx,
+                                 const double *__restrict__ y,
+                                 double *__restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) {
+    out[2 * q] = y[idx[q]];
+    out[2 * q + 1] = 0.0;
+  }
+}
+
+void launch_gather_complex(int64_t n, const int64_t *idx, const double *y,
+                           double *out, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_gather_complex, dim3((unsigned)((n + 255) / 256)),
+                     dim3(256), 0, s, n, idx, y, out);
+  LBS_HIP(hipGetLastError());
+}
+
+// out[0] = sum of x (one block)
+__global__ void __launch_bounds__(1024)
+    k_sum(int64_t n, const double *__restrict__ x, double *__restrict__ out) {
+  __shared__ double red[16];
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) a += x[i];
+  a = wsum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t += red[q];
+    out[0] = t;
+  }
+}
+
+void launch_sum(int64_t n, const double *x, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, s, n, x, out);
+  LBS_HIP(hipGetLastError());
+}
+
+// the double-layer strengths p_j = -i qfac_j sigma_j (API order)
+__global__ void k_dl_strengths(int64_t n, const double *__restrict__ qfac,
+                               const double *__restrict__ sigma,
+                               double *__restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) {
+    out[2 * j] = qfac[2 * j + 1] * sigma[j];
+    out[2 * j + 1] = -qfac[2 * j] * sigma[j];
+  }
+}
+
+void launch_dl_strengths(const Geometry &g, const double *sigma, double *out,
+                         hipStream_t s) {
+  if (g.N == 0) return;
+  hipLaunchKernelGGL(k_dl_strengths, dim3((unsigned)((g.N + 255) / 256)),
+                     dim3(256), 0, s, g.N, g.qfac.p, sigma, out);
+  LBS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ E^T
+// (E^T y)_m = sum_i 2 G(x_i, c_m) y_i over the nodes of m's geometry.  For
+// an island k with m not among k's near centres, the far form
+//   sum_{i in k} y_i log|x_i - c_m| = Y_k (log 2 + log|eta_m - eta_k|
+//       - ell(eta_m)/2) - Re sum_l q^l Q_k[l] / l - ELL_k / 2,
+// q = rho_k / (eta_m - eta_k), Q_k[l] = sum_i y_i ((xi_i - eta_k)/rho_k)^l,
+// Y_k = sum_i y_i, ELL_k = sum_i y_i ell(xi_i); near islands directly in 3D.
+
+__global__ void __launch_bounds__(256)
+    k_island_moments(const int64_t *__restrict__ offs,
+                     const double *__restrict__ xi,
+                     const double *__restrict__ ell,
+                     const double *__restrict__ eta,
+                     const double *__restrict__ rho,
+                     const double *__restrict__ y, double *__restrict__ mom) {
+  constexpr int P = kPlog;
+  __shared__ double red[4][kMomStride];
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const double ex = eta[2 * k], ey = eta[2 * k + 1], ir = 1.0 / rho[k];
+  cx<double> acc[P];
+#pragma unroll
+  for (int l = 0; l < P; ++l) acc[l] = cx<double>{0.0, 0.0};
+  double ys = 0.0, ys_ell = 0.0;
+  for (int64_t i = offs[k] + tid; i < offs[k + 1]; i += 256) {
+    const double yi = y[i];
+    ys += yi;
+    ys_ell += yi * ell[i];
+    const cx<double> u{(xi[2 * i] - ex) * ir, (xi[2 * i + 1] - ey) * ir};
+    cx<double> pw = yi * u;
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+      acc[l] = acc[l] + pw;
+      pw = pw * u;
+    }
+  }
+  auto put = [&](int slot, double v) {
+    v = wsum(v);
+    if (ln == 0) red[wv][slot] = v;
+  };
+#pragma unroll
+  for (int l = 0; l < P; ++l) {
+    put(2 * l, acc[l].x);
+    put(2 * l + 1, acc[l].y);
+  }
+  put(2 * P, ys);
+  put(2 * P + 1, ys_ell);
+  __syncthreads();
+  for (int s = tid; s < kMomStride; s += 256)
+    mom[(int64_t)k * kMomStride + s] = red[0][s] + red[1][s] + red[2][s] + red[3][s];
+}
+
+__global__ void __launch_bounds__(256)
+    k_logsrc_T(const int32_t *__restrict__ isl_geo,
+               const int32_t *__restrict__ gisl,
+               const int64_t *__restrict__ offs,
+               const double *__restrict__ eta, const double *__restrict__ rho,
+               const double *__restrict__ ellc,
+               const double *__restrict__ cxyz,
+               const double *__restrict__ xyz,
+               const int32_t *__restrict__ nearT_ptr,
+               const int32_t *__restrict__ nearT_idx,
+               const double *__restrict__ mom, const double *__restrict__ y,
+               double alpha, double *__restrict__ out) {
+  constexpr int P = kPlog;
+  __shared__ double red[4];
+  const int m = blockIdx.x;
+  const int tid = threadIdx.x, ln = tid & 63;
+  const int g = isl_geo[m];
+  const double emx = eta[2 * m], emy = eta[2 * m + 1];
+  const int32_t *nl = nearT_idx + nearT_ptr[m];
+  const int nn = nearT_ptr[m + 1] - nearT_ptr[m];
+  double tot = 0.0, ysum = 0.0;
+  for (int k = gisl[g] + tid; k < gisl[g + 1]; k += 256) {
+    const double *mk = mom + (int64_t)k * kMomStride;
+    ysum += mk[2 * P];
+    if (in_sorted(nl, nn, k)) continue;
+    const double dx = emx - eta[2 * k], dy = emy - eta[2 * k + 1];
+    const double d2 = dx * dx + dy * dy;
+    const double f = rho[k] / d2;
+    const cx<double> q{dx * f, -dy * f};  // rho_k / (eta_m - eta_k)
+    cx<double> pw = q, ser{0.0, 0.0};
+    for (int l = 1; l <= P; ++l) {
+      const cx<double> Ql{mk[2 * (l - 1)], mk[2 * (l - 1) + 1]};
+      ser = ser + (1.0 / (double)l) * (pw * Ql);
+      pw = pw * q;
+    }
+    tot += mk[2 * P] * (kLog2_ + 0.5 * log(d2) - 0.5 * ellc[m]) - ser.x -
+           0.5 * mk[2 * P + 1];
+  }
+  const double c0 = cxyz[3 * m], c1 = cxyz[3 * m + 1], c2 = cxyz[3 * m + 2];
+  for (int e = 0; e < nn; ++e) {
+    const int k = nl[e];
+    for (int64_t i = offs[k] + tid; i < offs[k + 1]; i += 256) {
+      const double d0 = xyz[3 * i] - c0, d1 = xyz[3 * i + 1] - c1,
+                   d2 = xyz[3 * i + 2] - c2;
+      tot += y[i] * 0.5 * log(d0 * d0 + d1 * d1 + d2 * d2);
+    }
+  }
+  tot = wsum(tot);
+  ysum = wsum(ysum);
+  if (ln == 0) red[tid >> 6] = tot;
+  __syncthreads();
+  double t4 = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  if (ln == 0) red[tid >> 6] = ysum;
+  __syncthreads();
+  const double ys4 = red[0] + red[1] + red[2] + red[3];
+  if (tid == 0) out[m] = alpha * (-kInvPi_ * t4 + 0.5 * kInvPi_ * kLog2_ * ys4);
+}
+
+void launch_logsrc_T(const Geometry &g, const double *y, double *mom,
+                     double alpha, double *out, hipStream_t s) {
+  if (g.M == 0) return;
+  hipLaunchKernelGGL(k_island_moments, dim3(g.M), dim3(256), 0, s, g.doffs.p,
+                     g.xi.p, g.ell.p, g.deta.p, g.drho.p, y, mom);
+  hipLaunchKernelGGL(k_logsrc_T, dim3(g.M), dim3(256), 0, s, g.isl_geo.p,
+                     g.dgisl.p, g.doffs.p, g.deta.p, g.drho.p, g.dellc.p,
+                     g.dcenter.p, g.xyz.p, g.nearT_ptr.p, g.nearT_idx.p, mom,
+                     y, alpha, out);
+  LBS_HIP(hipGetLastError());
+}
+
+// F^T z: node i gets z of its island unless the island is its geometry's
+// first (which carries the row sum(A) = 0 instead of a constraint).
+// out_i = a * x_i + b * (F^T z)_i
+__global__ void k_FT(int64_t N, const int32_t *__restrict__ island,
+                     const int32_t *__restrict__ isl_geo,
+                     const int32_t *__restrict__ gisl,
+                     const double *__restrict__ z, double a,
+                     const double *__restrict__ x, double b,
+                     double *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int k = island[i];
+  const double f = (k == gisl[isl_geo[k]]) ? 0.0 : z[k];
+  out[i] = a * x[i] + b * f;
+}
+
+void launch_FT(const Geometry &g, const double *z, double a, const double *x,
+               double b, double *out, hipStream_t s) {
+  if (g.N == 0) return;
+  hipLaunchKernelGGL(k_FT, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0,
+                     s, g.N, g.island.p, g.isl_geo.p, g.dgisl.p, z, a, x, b,
+                     out);
+  LBS_HIP(hipGetLastError());
+}
+
+// y[k] = alpha sum_m Sinv_g[m][kl] x[m] (transpose of the block inverse)
+__global__ void k_gemvT_blocks(int M, const int32_t *__restrict__ isl_geo,
+                               const int32_t *__restrict__ gisl,
+                               const int64_t *__restrict__ gsinv,
+                               const double *__restrict__ A,
+                               const double *__restrict__ x,
+                               double *__restrict__ y, double alpha) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const int g = isl_geo[k];
+  const int m0 = gisl[g], Mg = gisl[g + 1] - m0, kl = k - m0;
+  const double *Ag = A + gsinv[g];
+  double acc = 0.0;
+  for (int ml = 0; ml < Mg; ++ml) acc += Ag[(int64_t)ml * Mg + kl] * x[m0 + ml];
+  y[k] = alpha * acc;
+}
+
+void launch_gemvT_blocks(const Geometry &g, const double *x, double *y,
+                         double alpha, hipStream_t s) {
+  if (g.M == 0) return;
+  hipLaunchKernelGGL(k_gemvT_blocks, dim3((g.M + 255) / 256), dim3(256), 0, s,
+                     g.M, g.isl_geo.p, g.dgisl.p, g.dgsinv.p, g.Sinv.p, x, y,
+                     alpha);
+  LBS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ T^T
+// (T^T w)_a[m] = sum_t w_t G(x_t, c_m) (direct).
+__global__ void __launch_bounds__(256)
+    k_evalT_logsrc(int64_t T, const double *__restrict__ txyz,
+                   const double *__restrict__ w, int M,
+                   const double *__restrict__ cxyz, double *__restrict__ out) {
+  __shared__ double red[4];
+  const int m = blockIdx.x;
+  const int tid = threadIdx.x, ln = tid & 63;
+  const double c0 = cxyz[3 * m], c1 = cxyz[3 * m + 1], c2 = cxyz[3 * m + 2];
+  double acc = 0.0, ws = 0.0;
+  for (int64_t t = tid; t < T; t += 256) {
+    const double d0 = txyz[3 * t] - c0, d1 = txyz[3 * t + 1] - c1,
+                 d2 = txyz[3 * t + 2] - c2;
+    acc += w[t] * log(d0 * d0 + d1 * d1 + d2 * d2);
+    ws += w[t];
+  }
+  acc = wsum(acc);
+  ws = wsum(ws);
+  if (ln == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  const double a4 = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  if (ln == 0) red[tid >> 6] = ws;
+  __syncthreads();
+  const double w4 = red[0] + red[1] + red[2] + red[3];
+  // G = -(1/4pi) log|d|^2 + log2/4pi
+  if (tid == 0) out[m] = -0.25 * kInvPi_ * a4 + 0.25 * kInvPi_ * kLog2_ * w4;
+}
+
+void launch_evalT_logsrc(const Geometry &g, int64_t T, const double *txyz,
+                         const double *w, double *out, hipStream_t s) {
+  if (g.M == 0) return;
+  hipLaunchKernelGGL(k_evalT_logsrc, dim3(g.M), dim3(256), 0, s, T, txyz, w,
+                     g.M, g.dcenter.p, out);
+  LBS_HIP(hipGetLastError());
+}
+
+// (T^T w)_sigma[j] = 1/2 Re(i q_j F^T_j) + 1/2 gw_j W
+__global__ void k_evalT_sigma(int64_t N, const double *__restrict__ FT,
+                              const double *__restrict__ qfac,
+                              const double *__restrict__ gw,
+                              const double *__restrict__ wsum_dev,
+                              double *__restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const double qx = qfac[2 * j], qy = qfac[2 * j + 1];
+  const double fx = FT[2 * j], fy = FT[2 * j + 1];
+  out[j] = 0.5 * (-(qx * fy + qy * fx)) + 0.5 * gw[j] * wsum_dev[0];
+}
+
+void launch_evalT_sigma(const Geometry &g, const double *FT,
+                        const double *wsum_dev, double *out, hipStream_t s) {
+  if (g.N == 0) return;
+  hipLaunchKernelGGL(k_evalT_sigma, dim3((unsigned)((g.N + 255) / 256)),
+                     dim3(256), 0, s, g.N, FT, g.qfac.p, g.gw.p, wsum_dev,
+                     out);
+  LBS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ shape VJP
+// Dual numbers with three tangent directions (r, r', r'').
+struct D3 {
+  double v, d0, d1, d2;
+};
+__device__ __forceinline__ D3 dc(double v) { return D3{v, 0, 0, 0}; }
+__device__ __forceinline__ D3 operator+(D3 a, D3 b) {
+  return D3{a.v + b.v, a.d0 + b.d0, a.d1 + b.d1, a.d2 + b.d2};
+}
+__device__ __forceinline__ D3 operator-(D3 a, D3 b) {
+  return D3{a.v - b.v, a.d0 - b.d0, a.d1 - b.d1, a.d2 - b.d2};
+}
+__device__ __forceinline__ D3 operator*(D3 a, D3 b) {
+  return D3{a.v * b.v, a.d0 * b.v + a.v * b.d0, a.d1 * b.v + a.v * b.d1,
+            a.d2 * b.v + a.v * b.d2};
+}
+__device__ __forceinline__ D3 operator*(double s, D3 a) {
+  return D3{s * a.v, s * a.d0, s * a.d1, s * a.d2};
+}
+__device__ __forceinline__ D3 inv(D3 a) {
+  const double i = 1.0 / a.v, i2 = -i * i;
+  return D3{i, a.d0 * i2, a.d1 * i2, a.d2 * i2};
+}
+__device__ __forceinline__ D3 dsin(D3 a) {
+  const double s = sin(a.v), c = cos(a.v);
+  return D3{s, c * a.d0, c * a.d1, c * a.d2};
+}
+__device__ __forceinline__ D3 dcos(D3 a) {
+  const double s = sin(a.v), c = cos(a.v);
+  return D3{c, -s * a.d0, -s * a.d1, -s * a.d2};
+}
+
+// Per node: cotangents of (xi, xi', xi'') of
+//   Phi = w^T T x - lambda^T A x   (x = [sigma; A])
+// pulled back through the curve and projection formulas to r, r', r'' and
+// then to the 16 radius coefficients; summed per island (one block each).
+__global__ void __launch_bounds__(256)
+    k_shape_vjp(const lbs_island *__restrict__ isl,
+                const int64_t *__restrict__ offs,
+                const int32_t *__restrict__ isl_geo,
+                const double *__restrict__ sign,
+                const double *__restrict__ xi, const double *__restrict__ dxi,
+                const double *__restrict__ ddxi,
+                const double *__restrict__ sigma,
+                const double *__restrict__ lam,
+                const double *__restrict__ Fl, const double *__restrict__ dFl,
+                const double *__restrict__ dFp, const double *__restrict__ Fw,
+                const double *__restrict__ dFw, const double *__restrict__ LSd,
+                const double *__restrict__ lam_sum,
+                const double *__restrict__ a_sum,
+                const double *__restrict__ w_sum,
+                double *__restrict__ dcoef) {
+  __shared__ double red[4][16];
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x, ln = tid & 63, wv = tid >> 6;
+  const int g = isl_geo[k];
+  const lbs_island I = isl[k];
+  const int64_t n = offs[k + 1] - offs[k];
+  const double h = 2.0 * kPi / (double)n;
+  const double c = sign[k] * h / kPi;
+  const double Lam = lam_sum[g], As = a_sum[g], W = w_sum[0];
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int64_t i = offs[k] + tid; i < offs[k + 1]; i += 256) {
+    const int64_t j = i - offs[k];
+    const double t = (2.0 * kPi * (double)j) / (double)n;
+    const cx<double> z{xi[2 * i], xi[2 * i + 1]};
+    const cx<double> zd{dxi[2 * i], dxi[2 * i + 1]};
+    const cx<double> zdd{ddxi[2 * i], ddxi[2 * i + 1]};
+    const double sg = sigma[i], lm = lam[i];
+    const cx<double> I1{0.0, 1.0};
+    const double a2 = z.x * z.x + z.y * z.y, den = 1.0 / (1.0 + a2);
+    const cx<double> zbar{z.x, -z.y};
+    const cx<double> p = cx<double>{0.0, -c * sg} * zd;   // -i c sigma xi'
+    const cx<double> izd = cinv(zd);
+    // d(xi'): Kernel (A), diagonal (B), correction (C), eval (T)
+    const cx<double> F{Fl[2 * i], Fl[2 * i + 1]};
+    const cx<double> Fw_{Fw[2 * i], Fw[2 * i + 1]};
+    cx<double> g_d = (c * sg) * (I1 * F);
+    g_d = g_d + (-0.5 * c * lm * sg) * (I1 * zdd * izd * izd);
+    const cx<double> corr_d = (c * sg * den) * (cx<double>{0.0, -1.0} * zbar);
+    g_d = g_d + Lam * corr_d;
+    const cx<double> gT_d = (0.5 * c * sg) * (I1 * Fw_) + (0.5 * W) * corr_d;
+    // d(xi'')
+    const cx<double> g_dd = (0.5 * c * lm * sg) * (I1 * izd);
+    // d(xi)
+    const cx<double> H{-dFl[2 * i], -dFl[2 * i + 1]};   // sum lam/(z-z_i)^2
+    const cx<double> D{-dFp[2 * i], -dFp[2 * i + 1]};   // sum p/(z-z_j)^2
+    const cx<double> HT{-dFw[2 * i], -dFw[2 * i + 1]};
+    cx<double> g_z = (-lm) * D + p * H;
+    const cx<double> alpha = (den * den) * zd;
+    const cx<double> beta = (-den * den) * (zbar * zbar * zd);
+    const cx<double> corr_z =
+        (c * sg) * (cx<double>{0.0, -1.0} * (beta - cx<double>{alpha.x, -alpha.y}));
+    g_z = g_z + Lam * corr_z;
+    const cx<double> LS{LSd[2 * i], LSd[2 * i + 1]};
+    g_z = g_z + (-kInvPi_ * lm) * (LS - (As * den) * zbar);
+    const cx<double> gT_z = (0.5) * (p * HT) + (0.5 * W) * corr_z;
+    // total cotangents of Phi = Phi_T - Phi_A
+    const cx<double> Gz = gT_z - g_z, Gd = gT_d - g_d;
+    const cx<double> Gdd = cx<double>{-g_dd.x, -g_dd.y};
+    // xi, xi', xi'' as functions of (r, r', r'') at this t
+    double rr = 1.0, rt = 0.0, rtt = 0.0;
+    double cs[8], sn[8];
+    for (int m = 1; m <= 8; ++m) {
+      sincos((double)m * t, &sn[m - 1], &cs[m - 1]);
+      const double am = I.coef[m - 1], bm = I.coef[7 + m];
+      rr += am * cs[m - 1] + bm * sn[m - 1];
+      rt += (double)m * (-am * sn[m - 1] + bm * cs[m - 1]);
+      rtt += (double)(m * m) * (-am * cs[m - 1] - bm * sn[m - 1]);
+    }
+    const D3 R{I.r0 * rr, 1, 0, 0}, Rt{I.r0 * rt, 0, 1, 0},
+        Rtt{I.r0 * rtt, 0, 0, 1};
+    double st, ct;
+    sincos(t, &st, &ct);
+    const double *cc = I.center, *e1 = I.e1;
+    const double e2[3] = {e1[1] * cc[2] - e1[2] * cc[1],
+                          e1[2] * cc[0] - e1[0] * cc[2],
+                          e1[0] * cc[1] - e1[1] * cc[0]};
+    double u[3], v[3];
+    for (int a = 0; a < 3; ++a) {
+      u[a] = ct * e1[a] + st * e2[a];
+      v[a] = -st * e1[a] + ct * e2[a];
+    }
+    const D3 sr = dsin(R), cr = dcos(R);
+    D3 X[3], Xt[3], Xtt[3];
+    const D3 pc = dc(-1.0) * Rt * sr, pu = Rt * cr;
+    const D3 qc = dc(-1.0) * (Rtt * sr + Rt * Rt * cr);
+    const D3 qu = Rtt * cr - Rt * Rt * sr - sr, qv = 2.0 * (Rt * cr);
+    for (int a = 0; a < 3; ++a) {
+      X[a] = cc[a] * cr + u[a] * sr;
+      Xt[a] = cc[a] * pc + u[a] * pu + v[a] * sr;
+      Xtt[a] = cc[a] * qc + u[a] * qu + v[a] * qv;
+    }
+    const D3 id = inv(dc(1.0) - X[2]);
+    const D3 id2 = id * id, id3 = id2 * id;
+    // xi = w id, xi' = w' id + w x3' id^2,
+    // xi'' = w'' id + 2 w' x3' id^2 + w x3'' id^2 + 2 w x3'^2 id^3
+    D3 zr[3][2];  // [quantity][re, im]
+    for (int part = 0; part < 2; ++part) {
+      const D3 w = X[part], wt = Xt[part], wtt = Xtt[part];
+      zr[0][part] = w * id;
+      zr[1][part] = wt * id + w * Xt[2] * id2;
+      zr[2][part] = wtt * id + 2.0 * (wt * Xt[2] * id2) + w * Xtt[2] * id2 +
+                    2.0 * (w * Xt[2] * Xt[2] * id3);
+    }
+    // dPhi/d(r, r', r'') = Re(G_z dxi + G_d dxi' + G_dd dxi'')
+    auto contract = [&](int dir) {
+      auto dv = [&](const D3 &x) {
+        return dir == 0 ? x.d0 : (dir == 1 ? x.d1 : x.d2);
+      };
+      const cx<double> Gs[3] = {Gz, Gd, Gdd};
+      double s = 0.0;
+      for (int q = 0; q < 3; ++q) s += Gs[q].x * dv(zr[q][0]) - Gs[q].y * dv(zr[q][1]);
+      return s;
+    };
+    const double dr = contract(0), drt = contract(1), drtt = contract(2);
+    for (int m = 1; m <= 8; ++m) {
+      const double fm = (double)m;
+      acc[m - 1] += I.r0 * (dr * cs[m - 1] - drt * fm * sn[m - 1] -
+                            drtt * fm * fm * cs[m - 1]);
+      acc[7 + m] += I.r0 * (dr * sn[m - 1] + drt * fm * cs[m - 1] -
+                            drtt * fm * fm * sn[m - 1]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const double v = wsum(acc[q]);
+    if (ln == 0) red[wv][q] = v;
+  }
+  __syncthreads();
+  if (tid < 16)
+    dcoef[(int64_t)k * 16 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+}
+
+void launch_shape_vjp(const Geometry &g, const double *sigma,
+                      const double *lam, const double *Fl, const double *dFl,
+                      const double *dFp, const double *Fw, const double *dFw,
+                      const double *LSd, const double *lam_sum,
+                      const double *a_sum, const double *w_sum, double *dcoef,
+                      hipStream_t s) {
+  if (g.M == 0) return;
+  hipLaunchKernelGGL(k_shape_vjp, dim3(g.M), dim3(256), 0, s, g.disl.p,
+                     g.doffs.p, g.isl_geo.p, g.dsign.p, g.xi.p, g.dxi.p,
+                     g.ddxi.p, sigma, lam, Fl, dFl, dFp, Fw, dFw, LSd,
+                     lam_sum, a_sum, w_sum, dcoef);
+  LBS_HIP(hipGetLastError());
+}
+
+// Sum_m A_m / (xi_n - eta_m) over m's geometry: derivative of the
+// per-island log-source expansion (far centres, coefficients of
+// k_logsrc_local for z = A) plus the near centres directly.
+__global__ void k_logsrc_deriv(int64_t N, int M, const int32_t *__restrict__ island,
+                               const double *__restrict__ xi,
+                               const double *__restrict__ eta,
+                               const double *__restrict__ rho,
+                               const int32_t *__restrict__ near_ptr,
+                               const int32_t *__restrict__ near_idx,
+                               const double *__restrict__ A,
+                               const double *__restrict__ Lc,
+                               double *__restrict__ out) {
+  constexpr int P = kPlog;
+  constexpr int stride = 2 * (kPlog + 1) + 2;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int k = island[i];
+  const double *L = Lc + (int64_t)k * stride;
+  const double ir = 1.0 / rho[k];
+  const cx<double> z{xi[2 * i], xi[2 * i + 1]};
+  const cx<double> u{(z.x - eta[2 * k]) * ir, (z.y - eta[2 * k + 1]) * ir};
+  cx<double> d = (double)P * cx<double>{L[2 * P], L[2 * P + 1]};
+  for (int l = P - 1; l >= 1; --l)
+    d = d * u + (double)l * cx<double>{L[2 * l], L[2 * l + 1]};
+  d = ir * d;
+  for (int e = near_ptr[k]; e < near_ptr[k + 1]; ++e) {
+    const int m = near_idx[e];
+    d = d + A[m] * cinv(cx<double>{z.x - eta[2 * m], z.y - eta[2 * m + 1]});
+  }
+  out[2 * i] = d.x;
+  out[2 * i + 1] = d.y;
+  (void)M;
+}
+
+void launch_logsrc_deriv(const Geometry &g, Workspace &ws, const double *A,
+                         double *out, hipStream_t s) {
+  if (g.N == 0) return;
+  // expansion coefficients of the far centres for z = A
+  launch_logsrc_local(g, ws, A, s);
+  hipLaunchKernelGGL(k_logsrc_deriv, dim3((unsigned)((g.N + 255) / 256)),
+                     dim3(256), 0, s, g.N, g.M, g.island.p, g.xi.p, g.deta.p,
+                     g.drho.p, g.near_ptr.p, g.near_idx.p, A, ws.logL.p, out);
+  LBS_HIP(hipGetLastError());
+}
+
+}  // namespace lbs

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -191,6 +192,17 @@ struct GmresState {
   DBuf<double> bvec, rvec, xvec, dvec, bn2;
 };
 
+// Buffers of the transposed operators (one column).
+struct AdjState {
+  bool ready = false;
+  DBuf<double> ones;   // max(N, M) ones (segment sums)
+  DBuf<double> mom;    // island moments, M x kMomStride
+  DBuf<double> tA;     // M
+  DBuf<double> lam;    // N + M
+  DBuf<double> pc, Fc; // complex, N x 2
+  DBuf<double> ysum;   // per geometry
+};
+
 struct lbs_ctx {
   lbs_options opt{};
   Geometry geo;
@@ -202,6 +214,7 @@ struct lbs_ctx {
   std::vector<double> xi_x, xi_y;  // node images, API order (eval trees)
   StageTimer timer;
   GmresState gm;
+  AdjState adj;
   int32_t *count_host = nullptr;
   ~lbs_ctx() {
     if (count_host) (void)hipHostFree(count_host);
@@ -335,7 +348,9 @@ struct GmresOut {
 // n = N + M), per-system absolute tolerances c.gm.tol.  x_zero: start from
 // x = 0.  CGS2 orthogonalisation, Givens rotations, one 4-byte read of the
 // number of active systems per iteration.
-GmresOut gmres(lbs_ctx &c, int prec, int R, const double *b, double *x,
+using OpFn = std::function<void(const double *, double *)>;
+
+GmresOut gmres(lbs_ctx &c, const OpFn &op, int R, const double *b, double *x,
                bool x_zero, int max_iter, hipStream_t s) {
   GmresState &st = c.gm;
   const int64_t n = st.n;
@@ -345,7 +360,7 @@ GmresOut gmres(lbs_ctx &c, int prec, int R, const double *b, double *x,
   const int32_t *rg = c.geo.row_geo.p;
   GmresOut out;
   auto residual_into_v0 = [&]() {
-    apply_precond_op(c, prec, R, x, V, s);
+    op(x, V);
     launch_axpby(ldv, 1.0, b, -1.0, V, s);
   };
   if (x_zero) {
@@ -369,7 +384,7 @@ GmresOut gmres(lbs_ctx &c, int prec, int R, const double *b, double *x,
     int kc = 0;
     for (int k = 0; k < m; ++k) {
       double *vk = V + (int64_t)k * ldv, *w = V + (int64_t)(k + 1) * ldv;
-      apply_precond_op(c, prec, R, vk, w, s);
+      op(vk, w);
       launch_segdots(c.seg_sys, R, k + 1, V, ldv, n, w, n, st.h1.p,
                      c.ws.red.p, s);
       launch_maxpy_seg(n, R, G, k + 1, rg, V, ldv, st.h1.p, w, s);
@@ -396,6 +411,14 @@ GmresOut gmres(lbs_ctx &c, int prec, int R, const double *b, double *x,
     if (out.iters >= max_iter) return out;
     residual_into_v0();
   }
+}
+
+// GMRES on P^-1 A with the FMM of the given precision.
+GmresOut gmres(lbs_ctx &c, int prec, int R, const double *b, double *x,
+               bool x_zero, int max_iter, hipStream_t s) {
+  return gmres(
+      c, [&](const double *in, double *out) { apply_precond_op(c, prec, R, in, out, s); }, R,
+      b, x, x_zero, max_iter, s);
 }
 
 // Per-system 2-norms^2 of R columns of length N + M into out (S values).
@@ -520,13 +543,12 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl,
     g.gsinv[q + 1] = g.gsinv[q] + mq * mq;
   }
   g.dgsinv.upload(g.gsinv, s);
-  DBuf<lbs_island> disl;
-  disl.upload(std::vector<lbs_island>(isl, isl + M), s);
+  g.disl.upload(std::vector<lbs_island>(isl, isl + M), s);
   g.xyz.alloc(3 * N);
   g.xi.alloc(2 * N);
   g.dxi.alloc(2 * N);
   g.ddxi.alloc(2 * N);
-  launch_geometry(disl.p, M, g.doffs.p, g.island.p, N, g.xyz.p, g.xi.p, g.dxi.p, g.ddxi.p, s);
+  launch_geometry(g.disl.p, M, g.doffs.p, g.island.p, N, g.xyz.p, g.xi.p, g.dxi.p, g.ddxi.p, s);
   std::vector<double> xyz = g.xyz.download(s), xi = g.xi.download(s), dxi = g.dxi.download(s);
   for (int64_t i = 0; i < N; ++i) {
     if (!std::isfinite(xi[2 * i]) || !std::isfinite(xi[2 * i + 1]) || !std::isfinite(dxi[2 * i]) ||
@@ -542,13 +564,12 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl,
       area += xi[2 * i] * dxi[2 * i + 1] - xi[2 * i + 1] * dxi[2 * i];
     g.sign[k] = area > 0 ? 1.0 : -1.0;
   }
-  DBuf<double> dsign;
-  dsign.upload(g.sign, s);
+  g.dsign.upload(g.sign, s);
   g.qfac.alloc(2 * N);
   g.tau.alloc(N);
   g.gw.alloc(N);
   g.ell.alloc(N);
-  launch_node_coeffs(N, g.island.p, dsign.p, g.doffs.p, g.xi.p, g.dxi.p, g.ddxi.p, g.qfac.p,
+  launch_node_coeffs(N, g.island.p, g.dsign.p, g.doffs.p, g.xi.p, g.dxi.p, g.ddxi.p, g.qfac.p,
                      g.tau.p, g.gw.p, g.ell.p, s);
   // log-source geometry: projected centres, planar radii, near lists
   g.eta_x.resize(M);
@@ -580,6 +601,17 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl,
   g.dellc.upload(ellc, s);
   g.near_ptr.upload(nptr, s);
   g.near_idx.upload(nidx, s);
+  {
+    // transpose: for centre m, the islands k with m among k's near centres
+    std::vector<int32_t> tptr(M + 1, 0), tidx(nidx.size());
+    for (int32_t m : nidx) ++tptr[m + 1];
+    for (int m = 0; m < M; ++m) tptr[m + 1] += tptr[m];
+    std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1);
+    for (int k = 0; k < M; ++k)
+      for (int e = nptr[k]; e < nptr[k + 1]; ++e) tidx[fill[nidx[e]]++] = k;
+    g.nearT_ptr.upload(tptr, s);
+    g.nearT_idx.upload(tidx, s);
+  }
   // quadtree forest over the node images (one tree per geometry)
   ctx->xi_x.resize(N);
   ctx->xi_y.resize(N);
@@ -706,6 +738,110 @@ void eval_impl(lbs_ctx &c, int nrhs, const double *sigma, const double *A,
   dtg.upload(tgeo, s);
   launch_eval_logsrc(g, T, txyz, dtg.p, A, g.M, nrhs, c.ws.gam.p, u, T, s);
   LBS_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------- adjoint
+// Transposed system A^T lambda = r (eq. matrix_eqns transposed) by GMRES on
+// A^T P^-T (right preconditioning with the transposed block preconditioner),
+// whose residual is the unpreconditioned one:
+//   A^T P^-T mu = mu + [K^T (P^-T mu)_s; 0],   lambda = P^-T mu,
+//   P^-T [r_s; r_a] = [r_s - F^T z; z],  z = S^-T (r_a - E^T r_s).
+void ensure_adj(lbs_ctx &c) {
+  AdjState &a = c.adj;
+  if (a.ready) return;
+  const Geometry &g = c.geo;
+  const int64_t n = g.N + g.M;
+  a.ones.upload(std::vector<double>((size_t)std::max<int64_t>(g.N, g.M), 1.0), (hipStream_t)0);
+  a.mom.alloc((size_t)g.M * kMomStride);
+  a.tA.alloc((size_t)g.M);
+  a.lam.alloc((size_t)n);
+  a.pc.alloc((size_t)2 * g.N);
+  a.Fc.alloc((size_t)2 * g.N);
+  a.ysum.alloc((size_t)g.G);
+  LBS_HIP(hipStreamSynchronize((hipStream_t)0));
+  a.ready = true;
+}
+
+// lam = P^-T mu, one column of length N + M (lam and mu distinct)
+void precond_T(lbs_ctx &c, const double *mu, double *lam, hipStream_t s) {
+  Geometry &g = c.geo;
+  AdjState &a = c.adj;
+  launch_logsrc_T(g, mu, a.mom.p, -1.0, a.tA.p, s);
+  launch_axpby(g.M, 1.0, mu + g.N, 1.0, a.tA.p, s);
+  launch_gemvT_blocks(g, a.tA.p, lam + g.N, 1.0, s);
+  launch_FT(g, lam + g.N, 1.0, mu, -1.0, lam, s);
+}
+
+// y = ident x + K^T x over the node rows (one column), FP64 FMM
+void apply_KT(lbs_ctx &c, const double *x, double *y, double ident, hipStream_t s) {
+  Geometry &g = c.geo;
+  AdjState &a = c.adj;
+  launch_real_to_complex(g.N, x, a.pc.p, s);
+  fmm_apply64_full(c.plan, c.tab64, c.ws, a.pc.p, a.Fc.p, nullptr, s);
+  launch_segdots(c.seg_nodes, 1, 1, a.ones.p, 0, 0, x, g.N, a.ysum.p, c.ws.red.p, s);
+  launch_kT_assemble(g, x, a.Fc.p, a.ysum.p, ident, y, s);
+}
+
+// y = A^T P^-T x for R columns of length N + M
+void apply_op_T(lbs_ctx &c, int R, const double *x, double *y, hipStream_t s) {
+  Geometry &g = c.geo;
+  const int64_t n = g.N + g.M;
+  for (int r = 0; r < R; ++r) {
+    precond_T(c, x + r * n, c.adj.lam.p, s);
+    apply_KT(c, c.adj.lam.p, y + r * n, 0.0, s);
+    launch_fill(g.M, 0.0, y + r * n + g.N, s);
+  }
+  launch_axpby((int64_t)R * n, 1.0, x, 1.0, y, s);
+}
+
+// FMM plan with the (non-pole) targets as sources and the nodes as targets,
+// for the transposed evaluation.  idx: compacted position -> target index.
+struct EvalTPlan {
+  DevPlan pl;
+  Workspace ws;
+  DBuf<int64_t> idx;
+  int64_t n = 0;
+};
+
+void build_eval_T_plan(lbs_ctx &c, int64_t T, const double *txyz, EvalTPlan &ep,
+                       hipStream_t s) {
+  std::vector<double> hx(3 * T);
+  LBS_HIP(hipMemcpyAsync(hx.data(), txyz, 3 * T * sizeof(double), hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipStreamSynchronize(s));
+  std::vector<double> tx, ty;
+  std::vector<int64_t> idx;
+  for (int64_t t = 0; t < T; ++t) {
+    const double x0 = hx[3 * t], x1 = hx[3 * t + 1], x2 = hx[3 * t + 2];
+    if (!std::isfinite(x0) || !std::isfinite(x1) || !std::isfinite(x2))
+      fail(LBS_ERR_NOT_FINITE, "target " + std::to_string(t) + " is not finite");
+    const double d = 1.0 - x2;
+    if (d <= 1e-14) continue;  // the pole: no Cauchy part
+    tx.push_back(x0 / d);
+    ty.push_back(x1 / d);
+    idx.push_back(t);
+  }
+  ep.n = (int64_t)idx.size();
+  if (ep.n == 0) return;
+  const Geometry &g = c.geo;
+  Tree &t = ep.pl.host;
+  build_tree(tx.data(), ty.data(), ep.n, c.xi_x.data(), c.xi_y.data(), g.N, false,
+             c.opt.leaf_max, t);
+  upload_plan(t, tx.data(), ty.data(), c.xi_x.data(), c.xi_y.data(), nullptr, ep.pl, s);
+  ep.ws.ensure(ep.pl, c.opt.p64, c.opt.p32, 1, g.N, g.M, g.G, kPlog);
+  ep.idx.upload(idx, s);
+}
+
+// psi (and dpsi) at the nodes of sum_t w_t / (xi - zeta_t), one column
+void eval_T_field(lbs_ctx &c, EvalTPlan &ep, const double *w, double *pcw, double *psi,
+                  double *dpsi, hipStream_t s) {
+  const int64_t N = c.geo.N;
+  if (ep.n == 0) {
+    launch_fill(2 * N, 0.0, psi, s);
+    if (dpsi) launch_fill(2 * N, 0.0, dpsi, s);
+    return;
+  }
+  launch_gather_complex(ep.n, ep.idx.p, w, pcw, s);
+  fmm_apply64_full(ep.pl, c.tab64, ep.ws, pcw, psi, dpsi, s);
 }
 
 }  // namespace
@@ -922,6 +1058,142 @@ lbs_status lbs_eval_batch(lbs_handle h, int32_t nrhs, const double *sigma, const
     if (off[G] == 0) return;
     if (!sigma || !A || !txyz || !u) fail(LBS_ERR_INVALID_ARG, "null pointer argument");
     eval_impl(*h, nrhs, sigma, A, off, txyz, u, (hipStream_t)stream);
+  });
+}
+
+lbs_status lbs_eval_T(lbs_handle h, int32_t nrhs, const double *w, int64_t T, const double *txyz,
+                      double *gs, double *ga, void *stream) {
+  return guard([&] {
+    check_handle(h);
+    lbs_ctx &c = *h;
+    Geometry &g = c.geo;
+    if (g.G != 1) fail(LBS_ERR_UNSUPPORTED, "adjoint entry points serve single-geometry handles");
+    if (nrhs < 1 || nrhs > 65535) fail(LBS_ERR_INVALID_ARG, "nrhs outside [1, 65535]");
+    if (T < 0) fail(LBS_ERR_INVALID_ARG, "n_targets < 0");
+    if (!gs || !ga || (T > 0 && (!w || !txyz))) fail(LBS_ERR_INVALID_ARG, "null pointer argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (T == 0) {
+      launch_fill((int64_t)g.N * nrhs, 0.0, gs, s);
+      launch_fill((int64_t)g.M * nrhs, 0.0, ga, s);
+      return;
+    }
+    ensure_ws(c, 1);
+    ensure_adj(c);
+    EvalTPlan ep;
+    build_eval_T_plan(c, T, txyz, ep, s);
+    DBuf<double> pcw, wsum;
+    pcw.alloc((size_t)2 * std::max<int64_t>(ep.n, 1));
+    wsum.alloc(1);
+    for (int r = 0; r < nrhs; ++r) {
+      const double *wr = w + (int64_t)r * T;
+      eval_T_field(c, ep, wr, pcw.p, c.adj.Fc.p, nullptr, s);
+      launch_sum(T, wr, wsum.p, s);
+      launch_evalT_sigma(g, c.adj.Fc.p, wsum.p, gs + (int64_t)r * g.N, s);
+      launch_evalT_logsrc(g, T, txyz, wr, ga + (int64_t)r * g.M, s);
+    }
+    LBS_HIP(hipStreamSynchronize(s));
+  });
+}
+
+lbs_status lbs_solve_T(lbs_handle h, int32_t nrhs, const double *rs, const double *ra, double tol,
+                       double *lam_s, double *lam_a, lbs_solve_info *info, void *stream) {
+  bool noconv = false;
+  lbs_status st = guard([&] {
+    check_handle(h);
+    if (!rs || !lam_s || !lam_a) fail(LBS_ERR_INVALID_ARG, "null pointer argument");
+    if (nrhs < 1 || nrhs > 65535) fail(LBS_ERR_INVALID_ARG, "nrhs outside [1, 65535]");
+    if (!(tol > 0 && tol < 1)) fail(LBS_ERR_INVALID_ARG, "tol outside (0, 1)");
+    hipStream_t s = (hipStream_t)stream;
+    lbs_ctx &c = *h;
+    Geometry &g = c.geo;
+    const int R = nrhs, S = R * g.G;
+    const int64_t n = g.N + g.M;
+    auto t0 = std::chrono::steady_clock::now();
+    ensure_ws(c, R);
+    ensure_gmres(c, R);
+    ensure_adj(c);
+    GmresState &gm = c.gm;
+    lbs_solve_info inf{};
+    launch_copy_cols(g.N, R, 1.0, rs, g.N, gm.bvec.p, n, s);
+    if (ra) launch_copy_cols(g.M, R, 1.0, ra, g.M, gm.bvec.p + g.N, n, s);
+    else
+      for (int r = 0; r < R; ++r) launch_fill(g.M, 0.0, gm.bvec.p + r * n + g.N, s);
+    launch_dots((int64_t)R * n, 1, gm.bvec.p, 0, gm.bvec.p, 0, gm.nrm2.p, c.ws.red.p, s);
+    if (!std::isfinite(download(gm.nrm2.p, 1, s)[0]))
+      fail(LBS_ERR_NOT_FINITE, "right-hand side is not finite");
+    sys_norm2(c, R, gm.bvec.p, gm.bn2.p, s);
+    launch_scale_sqrt(S, tol, gm.bn2.p, gm.tol.p, s);
+    OpFn op = [&](const double *in, double *out) { apply_op_T(c, R, in, out, s); };
+    GmresOut go = gmres(c, op, R, gm.bvec.p, gm.xvec.p, true, c.opt.max_iter, s);
+    inf.iters = go.iters;
+    inf.fp64_matvecs = go.iters + 1;
+    noconv = !go.conv;
+    // residual of A^T lambda = b (equal to that of the right-preconditioned system)
+    op(gm.xvec.p, gm.rvec.p);
+    launch_axpby((int64_t)R * n, 1.0, gm.bvec.p, -1.0, gm.rvec.p, s);
+    sys_norm2(c, R, gm.rvec.p, gm.nrm2.p, s);
+    std::vector<double> rn2 = download(gm.nrm2.p, S, s), bn2 = download(gm.bn2.p, S, s);
+    double worst = 0;
+    for (int q = 0; q < S; ++q)
+      if (bn2[q] > 0) worst = std::max(worst, std::sqrt(rn2[q] / bn2[q]));
+    for (int r = 0; r < R; ++r) precond_T(c, gm.xvec.p + r * n, gm.dvec.p + r * n, s);
+    launch_copy_cols(g.N, R, 1.0, gm.dvec.p, n, lam_s, g.N, s);
+    launch_copy_cols(g.M, R, 1.0, gm.dvec.p + g.N, n, lam_a, g.M, s);
+    LBS_HIP(hipStreamSynchronize(s));
+    inf.rel_resid = worst;
+    inf.ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+  });
+  if (st == LBS_OK && noconv) {
+    g_err = "GMRES reached the iteration limit before the tolerance";
+    return LBS_ERR_NO_CONVERGENCE;
+  }
+  return st;
+}
+
+lbs_status lbs_shape_vjp(lbs_handle h, const double *sigma, const double *A, const double *lam_s,
+                         int64_t T, const double *txyz, const double *w, double *dcoef,
+                         void *stream) {
+  return guard([&] {
+    check_handle(h);
+    lbs_ctx &c = *h;
+    Geometry &g = c.geo;
+    if (g.G != 1) fail(LBS_ERR_UNSUPPORTED, "adjoint entry points serve single-geometry handles");
+    if (T < 0) fail(LBS_ERR_INVALID_ARG, "n_targets < 0");
+    if (!sigma || !A || !lam_s || !dcoef || (T > 0 && (!w || !txyz)))
+      fail(LBS_ERR_INVALID_ARG, "null pointer argument");
+    hipStream_t s = (hipStream_t)stream;
+    ensure_ws(c, 1);
+    ensure_adj(c);
+    const int64_t N = g.N;
+    DBuf<double> buf;
+    buf.alloc((size_t)12 * N + 8);
+    double *Fl = buf.p, *dFl = Fl + 2 * N, *dFp = dFl + 2 * N, *Fw = dFp + 2 * N,
+           *dFw = Fw + 2 * N, *LSd = dFw + 2 * N, *sums = LSd + 2 * N;
+    AdjState &a = c.adj;
+    // fields of the adjoint density and of the double-layer strengths
+    launch_real_to_complex(N, lam_s, a.pc.p, s);
+    fmm_apply64_full(c.plan, c.tab64, c.ws, a.pc.p, Fl, dFl, s);
+    launch_dl_strengths(g, sigma, a.pc.p, s);
+    fmm_apply64_full(c.plan, c.tab64, c.ws, a.pc.p, a.Fc.p, dFp, s);
+    // field of the target weights at the nodes
+    EvalTPlan ep;
+    DBuf<double> pcw;
+    if (T > 0) {
+      build_eval_T_plan(c, T, txyz, ep, s);
+      pcw.alloc((size_t)2 * std::max<int64_t>(ep.n, 1));
+      eval_T_field(c, ep, w, pcw.p, Fw, dFw, s);
+      launch_sum(T, w, sums + 2, s);
+    } else {
+      launch_fill(4 * N, 0.0, Fw, s);
+      launch_fill(1, 0.0, sums + 2, s);
+    }
+    launch_logsrc_deriv(g, c.ws, A, LSd, s);
+    launch_sum(N, lam_s, sums, s);
+    launch_sum(g.M, A, sums + 1, s);
+    launch_shape_vjp(g, sigma, lam_s, Fl, dFl, dFp, Fw, dFw, LSd, sums, sums + 1, sums + 2,
+                     dcoef, s);
+    LBS_HIP(hipStreamSynchronize(s));
   });
 }
 

@@ -818,4 +818,154 @@ void fmm_apply32(const DevPlan &pl, const Tables &tb, Workspace &ws,
   LBS_HIP(hipGetLastError());
 }
 
+
+// ------------------------------------------------- full complex output
+// Psi(z) = sum_j p_j / (z - z_j) and Psi'(z) at the targets, complex, FP64,
+// for given complex strengths (API order of the plan's sources).  Used by
+// the transposed operator and the shape derivatives.
+__global__ void k_strengths_given(int64_t ns, const int64_t *__restrict__ perm,
+                                  const double *__restrict__ pin,
+                                  cx<double> *__restrict__ p) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ns) return;
+  const int64_t a = perm[j];
+  p[j] = cx<double>{pin[2 * a], pin[2 * a + 1]};
+}
+
+template <int P>
+__global__ void __launch_bounds__(64)
+    k_leaf64_full(const int32_t *__restrict__ leaves,
+                  const int32_t *__restrict__ lev,
+                  const int64_t *__restrict__ t0, const int64_t *__restrict__ t1,
+                  const int64_t *__restrict__ s0, const int64_t *__restrict__ s1,
+                  const double *__restrict__ cxv, const double *__restrict__ cyv,
+                  const double *__restrict__ rad,
+                  const double *__restrict__ tx, const double *__restrict__ ty,
+                  const int64_t *__restrict__ tperm,
+                  const int32_t *__restrict__ u_ptr,
+                  const int32_t *__restrict__ u_src,
+                  const int32_t *__restrict__ w_ptr,
+                  const int32_t *__restrict__ w_src,
+                  const double *__restrict__ sx, const double *__restrict__ sy,
+                  const cx<double> *__restrict__ p,
+                  const cx<double> *__restrict__ M,
+                  const cx<double> *__restrict__ L,
+                  double *__restrict__ psi, double *__restrict__ dpsi) {
+  __shared__ double2 sz[kStage];
+  __shared__ double2 sp[kStage];
+  __shared__ int64_t rs[64];
+  __shared__ int pre[65];
+  const int b = leaves[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
+  const int ub = u_ptr[b], ue = u_ptr[b + 1];
+  const int wb = w_ptr[b], we = w_ptr[b + 1];
+  for (int64_t tc = 0; tc < ntb; tc += 64) {
+    const int64_t i = tb0 + tc + lane;
+    const bool act = tc + lane < ntb;
+    const double zx = act ? tx[i] : 0.0, zy = act ? ty[i] : 0.0;
+    cx<double> f{0.0, 0.0}, df{0.0, 0.0};
+    if (act && lev[b] >= 2) {
+      const double ir = 1.0 / rad[b];
+      const cx<double> w{(zx - cxv[b]) * ir, (zy - cyv[b]) * ir};
+      const cx<double> *Lb = L + (int64_t)b * P;
+      cx<double> acc = Lb[P - 1], dacc = (double)(P - 1) * Lb[P - 1];
+      for (int l = P - 2; l >= 1; --l) {
+        acc = acc * w + Lb[l];
+        dacc = dacc * w + (double)l * Lb[l];
+      }
+      acc = acc * w + Lb[0];
+      f = f + acc;
+      df = df + ir * dacc;
+    }
+    if (act) {
+      for (int e = wb; e < we; ++e) {
+        const int c = w_src[e];
+        const cx<double> iz = cinv(cx<double>{zx - cxv[c], zy - cyv[c]});
+        const cx<double> rho = rad[c] * iz;
+        const cx<double> *a = M + (int64_t)c * P;
+        cx<double> acc = a[P - 1], dacc = (double)P * a[P - 1];
+        for (int k = P - 2; k >= 0; --k) {
+          acc = acc * rho + a[k];
+          dacc = dacc * rho + (double)(k + 1) * a[k];
+        }
+        f = f + acc * rho;
+        const cx<double> d = (dacc * rho) * iz;
+        df = df - d;
+      }
+    }
+    for (int eb = ub; eb < ue; eb += 64) {
+      const int cnt = min(64, ue - eb);
+      const int total = gather_ranges(u_src, eb, cnt, s0, s1, rs, pre);
+      for (int q0 = 0; q0 < total; q0 += kStage) {
+        const int take = min(kStage, total - q0);
+        for (int q = lane; q < take; q += 64) {
+          const int64_t j = locate(q0 + q, cnt, rs, pre);
+          sz[q] = make_double2(sx[j], sy[j]);
+          sp[q] = make_double2(p[j].x, p[j].y);
+        }
+        __syncthreads();
+        if (act) {
+          for (int q = 0; q < take; ++q) {
+            const cx<double> d{zx - sz[q].x, zy - sz[q].y};
+            if (d.x == 0.0 && d.y == 0.0) continue;
+            const cx<double> iv = cinv(d);
+            const cx<double> t = cx<double>{sp[q].x, sp[q].y} * iv;
+            f = f + t;
+            df = df - t * iv;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (act) {
+      const int64_t api = tperm[i];
+      psi[2 * api] = f.x;
+      psi[2 * api + 1] = f.y;
+      if (dpsi) {
+        dpsi[2 * api] = df.x;
+        dpsi[2 * api + 1] = df.y;
+      }
+    }
+  }
+}
+
+template <int P>
+static void run64_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
+                       double *psi, double *dpsi, hipStream_t s) {
+  auto *p = (cx<double> *)ws.pstr64.p;
+  auto *M = (cx<double> *)ws.mult64.p;
+  auto *L = (cx<double> *)ws.loc64.p;
+  far_field<double, P>(pl, tb, ws, p, M, L, 1, s);
+  if (pl.n_leaf_t > 0)
+    hipLaunchKernelGGL((k_leaf64_full<P>), dim3(pl.n_leaf_t), dim3(64), 0, s,
+                       pl.leaf_t.p, pl.lev.p, pl.t0.p, pl.t1.p, pl.s0.p,
+                       pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p, pl.tx.p, pl.ty.p,
+                       pl.tgt_perm.p, pl.u_ptr.p, pl.u_src.p, pl.w_ptr.p,
+                       pl.w_src.p, pl.sx.p, pl.sy.p, (const cx<double> *)p,
+                       (const cx<double> *)M, (const cx<double> *)L, psi,
+                       dpsi);
+}
+
+void fmm_apply64_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
+                      const double *pin, double *psi, double *dpsi,
+                      hipStream_t s) {
+  if (pl.ns > 0)
+    hipLaunchKernelGGL(k_strengths_given, dim3((unsigned)((pl.ns + 255) / 256)),
+                       dim3(256), 0, s, pl.ns, pl.src_perm.p, pin,
+                       (cx<double> *)ws.pstr64.p);
+  switch (tb.P) {
+    case 20: run64_full<20>(pl, tb, ws, psi, dpsi, s); break;
+    case 24: run64_full<24>(pl, tb, ws, psi, dpsi, s); break;
+    case 30: run64_full<30>(pl, tb, ws, psi, dpsi, s); break;
+    case 36: run64_full<36>(pl, tb, ws, psi, dpsi, s); break;
+    case 40: run64_full<40>(pl, tb, ws, psi, dpsi, s); break;
+    case 48: run64_full<48>(pl, tb, ws, psi, dpsi, s); break;
+    default:
+      throw ApiError{LBS_ERR_UNSUPPORTED,
+                     "p64 must be one of 20, 24, 30, 36, 40, 48"};
+  }
+  LBS_HIP(hipGetLastError());
+}
+
 }  // namespace lbs

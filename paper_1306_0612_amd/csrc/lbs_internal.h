@@ -200,6 +200,9 @@ struct Geometry {
   DBuf<int64_t> doffs, dgnode, dgsinv;
   DBuf<int32_t> dgisl;
   DBuf<int32_t> near_ptr, near_idx;  // near centres per island (log sources)
+  DBuf<int32_t> nearT_ptr, nearT_idx;  // islands having a centre as near (sorted)
+  DBuf<lbs_island> disl;             // island parameters
+  DBuf<double> dsign;                // orientation sign per island
   DBuf<double> Sinv;                 // block-diagonal inverse Schur complement
 };
 
@@ -254,6 +257,12 @@ void fmm_apply64(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  const double *qfac_t, const double *sigma, int64_t ldx,
                  int nrhs, double *out, int64_t ldy, double scale,
                  const Assembly &as, hipStream_t s);
+// Psi(z) = sum_j p_j / (z - z_j) and Psi'(z) (complex, FP64) at the plan's
+// targets for complex strengths pin (API order of the plan's sources);
+// outputs in the targets' API order, dpsi may be null.  One column.
+void fmm_apply64_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
+                      const double *pin, double *psi, double *dpsi,
+                      hipStream_t s);
 void fmm_apply32(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  const double *qfac_t, const double *sigma, int64_t ldx,
                  int nrhs, double *out, int64_t ldy, double scale,
@@ -280,6 +289,8 @@ void launch_segdots(const SegPlan &sp, int R, int nvec, const double *a,
 void launch_logsrc_apply(const Geometry &g, Workspace &ws, const double *z,
                          int64_t ldz, int nrhs, double *out, int64_t ldo,
                          double alpha, hipStream_t s);
+void launch_logsrc_local(const Geometry &g, Workspace &ws, const double *z,
+                         hipStream_t s);
 void launch_island_sums(const Geometry &g, const double *y, int64_t ldy,
                         int nrhs, double *out, int64_t ldo, hipStream_t s);
 void launch_constraint_rows(const Geometry &g, const double *sigma,
@@ -324,5 +335,36 @@ void launch_copy_cols(int64_t n, int R, double a, const double *src, int64_t lds
                       double *dst, int64_t ldd, hipStream_t s);
 void launch_scale_sqrt(int S, double t, const double *nrm2, double *out,
                        hipStream_t s);
+
+// transposed operators and shape derivatives (adjoint.hip)
+constexpr int kMomStride = 2 * kPlog + 2;  // island moments per island
+void launch_kT_assemble(const Geometry &g, const double *y, const double *F,
+                        const double *ysum, double ident, double *out,
+                        hipStream_t s);
+void launch_real_to_complex(int64_t n, const double *y, double *out,
+                            hipStream_t s);
+void launch_gather_complex(int64_t n, const int64_t *idx, const double *y,
+                           double *out, hipStream_t s);
+void launch_dl_strengths(const Geometry &g, const double *sigma, double *out,
+                         hipStream_t s);
+void launch_logsrc_T(const Geometry &g, const double *y, double *mom,
+                     double alpha, double *out, hipStream_t s);
+void launch_FT(const Geometry &g, const double *z, double a, const double *x,
+               double b, double *out, hipStream_t s);
+void launch_gemvT_blocks(const Geometry &g, const double *x, double *y,
+                         double alpha, hipStream_t s);
+void launch_evalT_logsrc(const Geometry &g, int64_t T, const double *txyz,
+                         const double *w, double *out, hipStream_t s);
+void launch_evalT_sigma(const Geometry &g, const double *FT,
+                        const double *wsum_dev, double *out, hipStream_t s);
+void launch_sum(int64_t n, const double *x, double *out, hipStream_t s);
+void launch_logsrc_deriv(const Geometry &g, Workspace &ws, const double *A,
+                         double *out, hipStream_t s);
+void launch_shape_vjp(const Geometry &g, const double *sigma,
+                      const double *lam, const double *Fl, const double *dFl,
+                      const double *dFp, const double *Fw, const double *dFw,
+                      const double *LSd, const double *lam_sum,
+                      const double *a_sum, const double *w_sum, double *dcoef,
+                      hipStream_t s);
 
 }  // namespace lbs

@@ -145,6 +145,16 @@ __global__ void k_logsrc_node(int64_t N, int M, const int32_t *__restrict__ isla
   out[(int64_t)r * ldo + i] += alpha * ez;
 }
 
+// Expansion coefficients L_k of the far centres for one column z (ws.logL).
+void launch_logsrc_local(const Geometry &g, Workspace &ws, const double *z,
+                         hipStream_t s) {
+  if (g.M == 0) return;
+  hipLaunchKernelGGL(k_logsrc_local, dim3(g.M, 1), dim3(256), 0, s, g.M,
+                     g.isl_geo.p, g.dgisl.p, g.deta.p, g.drho.p, g.dellc.p,
+                     g.near_ptr.p, g.near_idx.p, z, (int64_t)g.M, ws.logL.p);
+  LBS_HIP(hipGetLastError());
+}
+
 void launch_logsrc_apply(const Geometry &g, Workspace &ws, const double *z,
                          int64_t ldz, int nrhs, double *out, int64_t ldo,
                          double alpha, hipStream_t s) {

@@ -123,11 +123,18 @@ def load():
                                         ctypes.c_int64, ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(TreeStats)]
+    lib.lbs_eval_T.argtypes = [H, ctypes.c_int32, vp, ctypes.c_int64, vp,
+                               vp, vp, vp]
+    lib.lbs_solve_T.argtypes = [H, ctypes.c_int32, vp, vp, ctypes.c_double,
+                                vp, vp, ctypes.POINTER(SolveInfo), vp]
+    lib.lbs_shape_vjp.argtypes = [H, vp, vp, vp, ctypes.c_int64, vp, vp, vp,
+                                  vp]
     for name in ("lbs_setup", "lbs_sizes", "lbs_nodes", "lbs_matvec",
                  "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
                  "lbs_stage_timing", "lbs_stage_times", "lbs_setup_batch",
                  "lbs_batch_info", "lbs_eval_batch",
-                 "lbs_check_tree_host"):
+                 "lbs_check_tree_host", "lbs_eval_T", "lbs_solve_T",
+                 "lbs_shape_vjp"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -289,6 +296,56 @@ class Solver:
                                          off, _dev(targets), _dev(u),
                                          _stream()))
         return u
+
+    # ------------------------------------------------------------ adjoint
+    def eval_T(self, w, targets):
+        """Transposed evaluation T^T w -> (gs (N), ga (M)); w: (T,) or
+        (nrhs, T)."""
+        t = targets.shape[0]
+        nrhs = _rhs(w, t)
+        lead = () if w.dim() == 1 else (nrhs,)
+        gs = torch.empty(lead + (self.n_nodes,), dtype=torch.float64,
+                         device="cuda")
+        ga = torch.empty(lead + (self.n_islands,), dtype=torch.float64,
+                         device="cuda")
+        _check(load().lbs_eval_T(self._h, nrhs, _dev(w), t, _dev(targets),
+                                 _dev(gs), _dev(ga), _stream()))
+        return gs, ga
+
+    def solve_T(self, rhs_s, rhs_a=None, tol=1e-12, check=True):
+        """Solve A^T [lam_s; lam_a] = [rhs_s; rhs_a] -> (lam_s, lam_a, info)."""
+        nrhs = _rhs(rhs_s, self.n_nodes)
+        lead = () if rhs_s.dim() == 1 else (nrhs,)
+        if rhs_a is not None:
+            _rhs(rhs_a, self.n_islands)
+        ls = torch.empty(lead + (self.n_nodes,), dtype=torch.float64,
+                         device="cuda")
+        la = torch.empty(lead + (self.n_islands,), dtype=torch.float64,
+                         device="cuda")
+        info = SolveInfo()
+        code = load().lbs_solve_T(self._h, nrhs, _dev(rhs_s),
+                                  None if rhs_a is None else _dev(rhs_a),
+                                  float(tol), _dev(ls), _dev(la),
+                                  ctypes.byref(info), _stream())
+        if check:
+            _check(code)
+        d = info.as_dict()
+        d["status"] = STATUS.get(code, code)
+        return ls, la, d
+
+    def shape_vjp(self, sigma, A, lam_s, w, targets):
+        """w^T (dT/dbeta) x - lam^T (dA/dbeta) x as an (M, 16) tensor."""
+        _rhs(sigma, self.n_nodes)
+        _rhs(lam_s, self.n_nodes)
+        _rhs(A, self.n_islands)
+        t = targets.shape[0]
+        _rhs(w, t)
+        out = torch.empty((self.n_islands, 16), dtype=torch.float64,
+                          device="cuda")
+        _check(load().lbs_shape_vjp(self._h, _dev(sigma), _dev(A),
+                                    _dev(lam_s), t, _dev(targets), _dev(w),
+                                    _dev(out), _stream()))
+        return out
 
     def stage_timing(self, enable=True):
         _check(load().lbs_stage_timing(self._h, 1 if enable else 0))
