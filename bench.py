@@ -14,6 +14,7 @@ dominant kernel and the CPU oracle timed on sampled rows.
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +30,7 @@ METRIC = ("FMM matvecs/s & GMRES solve s at 1M nodes, FP32-mixed vs FP64, "
 WORKLOAD = "stars2000x512"
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
 # algorithmic FLOP counts (see the roofline section of the design notes)
 FLOP_P2P_PAIR = 11        # Re(p/(z - w)): 2 sub, |d|^2 (3), p.d (3), div, acc
 FLOP_CMAC = 8             # one complex multiply-add
@@ -62,13 +64,165 @@ def timed_matvecs(torch, sol, x, prec, steps, warmup):
     return dt, y, {k: v[0] / steps for k, v in st.items() if v[1]}
 
 
-def stage_flops(tree, n_nodes, P):
+def stage_work(tree, n_nodes, P, fp64):
+    """Algorithmic work of one operator application per stage: FLOPs for
+    the arithmetic-bound stages, HBM bytes for the streaming ones."""
+    boxes = tree["boxes"]
+    sb = 16 if fp64 else 8                 # bytes of one complex strength
     return {
-        "leaf": FLOP_P2P_PAIR * tree["p2p_interactions"]
-        + FLOP_CMAC * P * (n_nodes + tree["m2p_evals"]),
-        "m2l": (4 * P * P + 14 * P) * tree["v_pairs"],
-        "p2l": FLOP_CMAC * P * tree["p2l_evals"],
+        "strengths": ("hbm", (8 + 16 + 8) * n_nodes + sb * n_nodes),
+        "upward": ("alu", FLOP_CMAC * P * n_nodes
+                   + FLOP_CMAC * P * (P + 1) // 2 * (boxes - 1)),
+        "l2l": ("alu", FLOP_CMAC * P * (P + 1) // 2 * (boxes - 1)),
+        "m2l": ("mfma" if not fp64 else "alu",
+                (4 * P * P + 14 * P) * tree["v_pairs"]),
+        "p2l": ("alu", FLOP_CMAC * P * tree["p2l_evals"]),
+        "leaf": ("alu", FLOP_P2P_PAIR * tree["p2p_interactions"]
+                 + FLOP_CMAC * P * (n_nodes + tree["m2p_evals"])),
+        "gamma": ("hbm", 16 * n_nodes),
     }
+
+
+def stage_roofline(tree, n_nodes, P, stages_ms, fp64):
+    peak_flops = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
+    out = {}
+    for name, (bound, work) in stage_work(tree, n_nodes, P, fp64).items():
+        ms = stages_ms.get(name)
+        if not ms:
+            continue
+        if bound == "hbm":
+            ach = work / (ms * 1e-3) / 1e9
+            out[name] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                         "avg_ms": ms, "bytes_per_launch": work}
+        else:
+            ach = work / (ms * 1e-3) / 1e12
+            out[name] = {"bound": bound, "achieved": ach, "peak": peak_flops,
+                         "unit": "TFLOP/s", "frac": ach / peak_flops,
+                         "avg_ms": ms, "flop_per_launch": work}
+    return out
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the summary is missing or was taken on other kernel
+    sources than the ones built now."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_stars2000x512.txt")
+    src = os.path.join(ROOT, "paper_1306_0612_amd", "csrc", "fmm.hip")
+    if not os.path.exists(path):
+        return None
+    rec, sha = {}, None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("source_sha256 "):
+                sha = line.split()[1]
+            if line.startswith("kernel "):
+                kv = dict(t.split("=", 1) for t in line.split()[1:])
+                rec[kv["name"]] = float(kv["bytes_per_launch"])
+    with open(src, "rb") as f:
+        now = hashlib.sha256(f.read()).hexdigest()
+    if sha != now:
+        return None
+    return rec.get(kernel)
+
+
+def adjoint_leg(torch, sol, islands, dev, n_targets):
+    """Gradient of L = 1/2 |u - u*|^2 at 1e5 sphere targets with respect to
+    the node data and the 16 shape coefficients of every island: forward
+    solve (mixed, 1e-10) and evaluation, then the transposed evaluation,
+    the transposed solve (FP64, 1e-10) and the shape VJP."""
+    M = sol.n_islands
+    xyz = sol.nodes().cpu().numpy()
+    import synth
+    g = torch.tensor(synth.exact_harmonic(xyz, islands.center,
+                                          synth.paper_data_coeffs(M)),
+                     dtype=torch.float64, device=dev)
+    tg = synth.sphere_targets(56, n_targets, islands)
+    ustar = synth.exact_harmonic(tg, islands.center,
+                                 synth.random_data_coeffs(57, islands))
+    tgd = torch.tensor(tg, dtype=torch.float64, device=dev)
+    usd = torch.tensor(ustar, dtype=torch.float64, device=dev)
+    res = {}
+
+    def timed(name, f):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        res[name + "_s"] = time.perf_counter() - t0
+        return r
+
+    sig, A, info = timed("forward_solve", lambda: sol.solve(
+        g, tol=1e-10, precision="mixed", check=False))
+    u = timed("forward_eval", lambda: sol.eval(sig, A, tgd))
+    w = (u - usd).contiguous()
+    gs, ga = timed("eval_T", lambda: sol.eval_T(w, tgd))
+    ls, la, infoT = timed("solve_T", lambda: sol.solve_T(gs, ga, tol=1e-10,
+                                                         check=False))
+    dc = timed("shape_vjp", lambda: sol.shape_vjp(sig, A, ls, w, tgd))
+    res["backward_s"] = res["eval_T_s"] + res["solve_T_s"] + res["shape_vjp_s"]
+    res["solve_T"] = {k: infoT[k] for k in ("status", "iters", "rel_resid")}
+    # u is linear in g: w . u = (2 lambda_sigma) . g up to the tolerances
+    J = float(w @ u)
+    res["duality_rel"] = abs(J - float(2.0 * ls @ g)) / float(
+        (w.abs() * u.abs()).sum())
+    res["grad_g_norm"] = float((2.0 * ls).norm())
+    res["grad_coef_norm"] = float(dc.norm())
+    res["n_targets"] = n_targets
+    return res
+
+
+def batch_leg(torch, lbs, dev, n_geoms, n_rhs, steps):
+    """64 geometries of 10-400 islands (4k-100k nodes each) with 16
+    right-hand sides each in one handle: mixed-precision operator
+    applications per second over all systems, and one mixed solve of all
+    systems to 1e-10."""
+    import synth
+    geoms = synth.batch_geometries(n_geoms)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol = lbs.Solver(geoms)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    N, no = sol.n_nodes, sol.node_offsets
+    xyz = sol.nodes().cpu().numpy()
+    xi = (xyz[:, 0] + 1j * xyz[:, 1]) / (1.0 - xyz[:, 2])
+    rng = np.random.default_rng(58)
+    G = np.empty((n_rhs, N))
+    for q, gm in enumerate(geoms):
+        sl = slice(no[q], no[q + 1])
+        for r in range(n_rhs):
+            k = rng.integers(gm.m)
+            c = gm.center[k]
+            eta = (c[0] + 1j * c[1]) / (1.0 - c[2])
+            a = rng.standard_normal() + 1j * rng.standard_normal()
+            G[r, sl] = np.real(a / (xi[sl] - eta))
+    Gd = torch.tensor(G, dtype=torch.float64, device=dev)
+    X = torch.tensor(rng.standard_normal((n_rhs, N)), dtype=torch.float64,
+                     device=dev)
+    Y = torch.empty_like(X)
+    sol.matvec(X, "iplusk", "mixed", out=Y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sol.matvec(X, "iplusk", "mixed", out=Y)
+    torch.cuda.synchronize()
+    mv = (time.perf_counter() - t0) / steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, info = sol.solve(Gd, tol=1e-10, precision="mixed", check=False)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    out = {"geometries": n_geoms, "rhs": n_rhs, "nodes": N,
+           "islands": sol.n_islands, "setup_s": setup,
+           "matvec_ms_all_systems": 1e3 * mv,
+           "system_matvecs_per_s": n_geoms * n_rhs / mv,
+           "node_rhs_per_s": N * n_rhs / mv,
+           "solve_s_mixed": ts,
+           "solve": {k: info[k] for k in ("status", "iters", "outer_steps",
+                                          "rel_resid")}}
+    sol.close()
+    return out
 
 
 def cpu_baseline(islands, sigma, rows_n, y64, y32):
@@ -103,6 +257,10 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-geoms", type=int, default=64)
+    ap.add_argument("--batch-rhs", type=int, default=16)
     ap.add_argument("--cpu-rows", type=int, default=512)
     ap.add_argument("--targets", type=int, default=100000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -155,23 +313,18 @@ def main():
     mixed_vs_fp64 = float(np.abs(y32n - y64n).max() / np.abs(y64n).max())
 
     P32, P64 = sol.options.p32, sol.options.p64
-    fl32 = stage_flops(tree, N, P32)
+    rl32 = stage_roofline(tree, N, P32, st32, False)
+    rl64 = stage_roofline(tree, N, P64, st64, True)
     dom = max(st32, key=st32.get)
-    dom_ms = st32[dom]
-    if dom in fl32:
-        achieved = fl32[dom] / (dom_ms * 1e-3) / 1e12
-        kname = {"leaf": "k_leaf32<16>", "m2l": "k_m2l_mfma16",
-                 "p2l": "k_p2l<float,16>"}[dom]
-        roofline = {"bound": "mfma" if dom == "m2l" else "alu",
-                    "kernel": kname,
-                    "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                    "traffic": None, "avg_ms": dom_ms,
-                    "flop_per_launch": fl32[dom]}
-    else:
-        roofline = {"bound": "alu", "kernel": dom, "achieved": None,
-                    "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                    "frac": None, "traffic": None, "avg_ms": dom_ms}
+    kname = {"leaf": "k_leaf32<16>", "m2l": "k_m2l_mfma16",
+             "p2l": "k_p2l<float,16>", "upward": "k_p2m/k_m2m<float,16>",
+             "l2l": "k_l2l<float,16>"}.get(dom, dom)
+    r = rl32.get(dom, {})
+    roofline = {"bound": r.get("bound", "alu"), "kernel": kname,
+                "achieved": r.get("achieved"),
+                "peak": r.get("peak", PEAK_FP32_TFLOPS),
+                "unit": r.get("unit", "TFLOP/s"), "frac": r.get("frac"),
+                "traffic": measured_traffic(kname), "avg_ms": st32[dom]}
 
     out = {
         "metric": METRIC,
@@ -199,6 +352,8 @@ def main():
         "stages_ms_fp64": st64,
         "tree": tree,
         "roofline": roofline,
+        "roofline_stages_mixed": rl32,
+        "roofline_stages_fp64": rl64,
     }
 
     if not args.no_solve:
@@ -228,12 +383,20 @@ def main():
             out["eval_s_" + prec] = te
             log(prec, "solve %.3f s" % ts, info, "u err %.2e" % err)
 
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(torch, sol, islands, dev, args.targets)
+        log("adjoint", out["adjoint"])
+    sol.close()
+    if not args.no_batch:
+        out["batch"] = batch_leg(torch, lbs, dev, args.batch_geoms,
+                                 args.batch_rhs, max(3, args.steps // 5))
+        log("batch", out["batch"])
+
     if not args.no_cpu_baseline:
         cb, acc = cpu_baseline(islands, sigma, args.cpu_rows, y64n, y32n)
         out["cpu_baseline"] = cb
         out.update(acc)
         log("cpu baseline", cb, acc)
-    sol.close()
     print(json.dumps(out), flush=True)
     return 0
 

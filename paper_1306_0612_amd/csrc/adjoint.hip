@@ -143,25 +143,25 @@ void launch_dl_strengths(const Geometry &g, const double *sigma, double *out,
 }
 
 // ------------------------------------------------------------ E^T
-// (E^T y)_m = sum_i 2 G(x_i, c_m) y_i over the nodes of m's geometry.  For
-// an island k with m not among k's near centres, the far form
-//   sum_{i in k} y_i log|x_i - c_m| = Y_k (log 2 + log|eta_m - eta_k|
-//       - ell(eta_m)/2) - Re sum_l q^l Q_k[l] / l - ELL_k / 2,
-// q = rho_k / (eta_m - eta_k), Q_k[l] = sum_i y_i ((xi_i - eta_k)/rho_k)^l,
-// Y_k = sum_i y_i, ELL_k = sum_i y_i ell(xi_i); near islands directly in 3D.
-
+// (E^T y)_m = sum_i 2 G(x_i, c_m) y_i over the nodes of m's geometry.  In
+// island k's own frame (xi' = projection from the antipode of c_k, the frame
+// of the forward log-source product), for m not among k's near centres,
+//   sum_{i in k} y_i log|x_i - c_m| = Y_k log|c_k - c_m|
+//       - Re sum_l q^l Q_k[l] / l - ELL_k / 2,
+// q = 2 rho'_k (a - i b) / |c_k - c_m|^2 (a, b: c_m on k's frame vectors),
+// Q_k[l] = sum_i y_i (xi'_i / rho'_k)^l, Y_k = sum_i y_i,
+// ELL_k = sum_i y_i log(1 + |xi'_i|^2); near islands directly in 3D.
 __global__ void __launch_bounds__(256)
     k_island_moments(const int64_t *__restrict__ offs,
-                     const double *__restrict__ xi,
-                     const double *__restrict__ ell,
-                     const double *__restrict__ eta,
-                     const double *__restrict__ rho,
+                     const double *__restrict__ xil,
+                     const double *__restrict__ elll,
+                     const double *__restrict__ rhol,
                      const double *__restrict__ y, double *__restrict__ mom) {
   constexpr int P = kPlog;
   __shared__ double red[4][kMomStride];
   const int k = blockIdx.x;
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
-  const double ex = eta[2 * k], ey = eta[2 * k + 1], ir = 1.0 / rho[k];
+  const double ir = 1.0 / rhol[k];
   cx<double> acc[P];
 #pragma unroll
   for (int l = 0; l < P; ++l) acc[l] = cx<double>{0.0, 0.0};
@@ -169,8 +169,8 @@ __global__ void __launch_bounds__(256)
   for (int64_t i = offs[k] + tid; i < offs[k + 1]; i += 256) {
     const double yi = y[i];
     ys += yi;
-    ys_ell += yi * ell[i];
-    const cx<double> u{(xi[2 * i] - ex) * ir, (xi[2 * i + 1] - ey) * ir};
+    ys_ell += yi * elll[i];
+    const cx<double> u{xil[2 * i] * ir, xil[2 * i + 1] * ir};
     cx<double> pw = yi * u;
 #pragma unroll
     for (int l = 0; l < P; ++l) {
@@ -198,9 +198,9 @@ __global__ void __launch_bounds__(256)
     k_logsrc_T(const int32_t *__restrict__ isl_geo,
                const int32_t *__restrict__ gisl,
                const int64_t *__restrict__ offs,
-               const double *__restrict__ eta, const double *__restrict__ rho,
-               const double *__restrict__ ellc,
                const double *__restrict__ cxyz,
+               const double *__restrict__ frame,
+               const double *__restrict__ rhol,
                const double *__restrict__ xyz,
                const int32_t *__restrict__ nearT_ptr,
                const int32_t *__restrict__ nearT_idx,
@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(256)
   const int m = blockIdx.x;
   const int tid = threadIdx.x, ln = tid & 63;
   const int g = isl_geo[m];
-  const double emx = eta[2 * m], emy = eta[2 * m + 1];
+  const double x0 = cxyz[3 * m], x1 = cxyz[3 * m + 1], x2 = cxyz[3 * m + 2];
   const int32_t *nl = nearT_idx + nearT_ptr[m];
   const int nn = nearT_ptr[m + 1] - nearT_ptr[m];
   double tot = 0.0, ysum = 0.0;
@@ -219,25 +219,27 @@ __global__ void __launch_bounds__(256)
     const double *mk = mom + (int64_t)k * kMomStride;
     ysum += mk[2 * P];
     if (in_sorted(nl, nn, k)) continue;
-    const double dx = emx - eta[2 * k], dy = emy - eta[2 * k + 1];
-    const double d2 = dx * dx + dy * dy;
-    const double f = rho[k] / d2;
-    const cx<double> q{dx * f, -dy * f};  // rho_k / (eta_m - eta_k)
+    const double *fr = frame + 6 * k;
+    const double d0 = x0 - cxyz[3 * k], d1 = x1 - cxyz[3 * k + 1],
+                 d2 = x2 - cxyz[3 * k + 2];
+    const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+    const double a = x0 * fr[0] + x1 * fr[1] + x2 * fr[2];
+    const double b = x0 * fr[3] + x1 * fr[4] + x2 * fr[5];
+    const double f = 2.0 * rhol[k] / dd;
+    const cx<double> q{a * f, -b * f};
     cx<double> pw = q, ser{0.0, 0.0};
     for (int l = 1; l <= P; ++l) {
       const cx<double> Ql{mk[2 * (l - 1)], mk[2 * (l - 1) + 1]};
       ser = ser + (1.0 / (double)l) * (pw * Ql);
       pw = pw * q;
     }
-    tot += mk[2 * P] * (kLog2_ + 0.5 * log(d2) - 0.5 * ellc[m]) - ser.x -
-           0.5 * mk[2 * P + 1];
+    tot += mk[2 * P] * 0.5 * log(dd) - ser.x - 0.5 * mk[2 * P + 1];
   }
-  const double c0 = cxyz[3 * m], c1 = cxyz[3 * m + 1], c2 = cxyz[3 * m + 2];
   for (int e = 0; e < nn; ++e) {
     const int k = nl[e];
     for (int64_t i = offs[k] + tid; i < offs[k + 1]; i += 256) {
-      const double d0 = xyz[3 * i] - c0, d1 = xyz[3 * i + 1] - c1,
-                   d2 = xyz[3 * i + 2] - c2;
+      const double d0 = xyz[3 * i] - x0, d1 = xyz[3 * i + 1] - x1,
+                   d2 = xyz[3 * i + 2] - x2;
       tot += y[i] * 0.5 * log(d0 * d0 + d1 * d1 + d2 * d2);
     }
   }
@@ -257,11 +259,11 @@ void launch_logsrc_T(const Geometry &g, const double *y, double *mom,
                      double alpha, double *out, hipStream_t s) {
   if (g.M == 0) return;
   hipLaunchKernelGGL(k_island_moments, dim3(g.M), dim3(256), 0, s, g.doffs.p,
-                     g.xi.p, g.ell.p, g.deta.p, g.drho.p, y, mom);
+                     g.xil.p, g.elll.p, g.rhol.p, y, mom);
   hipLaunchKernelGGL(k_logsrc_T, dim3(g.M), dim3(256), 0, s, g.isl_geo.p,
-                     g.dgisl.p, g.doffs.p, g.deta.p, g.drho.p, g.dellc.p,
-                     g.dcenter.p, g.xyz.p, g.nearT_ptr.p, g.nearT_idx.p, mom,
-                     y, alpha, out);
+                     g.dgisl.p, g.doffs.p, g.dcenter.p, g.frame.p, g.rhol.p,
+                     g.xyz.p, g.nearRT_ptr.p, g.nearRT_idx.p, mom, y, alpha,
+                     out);
   LBS_HIP(hipGetLastError());
 }
 
@@ -287,32 +289,6 @@ void launch_FT(const Geometry &g, const double *z, double a, const double *x,
   hipLaunchKernelGGL(k_FT, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0,
                      s, g.N, g.island.p, g.isl_geo.p, g.dgisl.p, z, a, x, b,
                      out);
-  LBS_HIP(hipGetLastError());
-}
-
-// y[k] = alpha sum_m Sinv_g[m][kl] x[m] (transpose of the block inverse)
-__global__ void k_gemvT_blocks(int M, const int32_t *__restrict__ isl_geo,
-                               const int32_t *__restrict__ gisl,
-                               const int64_t *__restrict__ gsinv,
-                               const double *__restrict__ A,
-                               const double *__restrict__ x,
-                               double *__restrict__ y, double alpha) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= M) return;
-  const int g = isl_geo[k];
-  const int m0 = gisl[g], Mg = gisl[g + 1] - m0, kl = k - m0;
-  const double *Ag = A + gsinv[g];
-  double acc = 0.0;
-  for (int ml = 0; ml < Mg; ++ml) acc += Ag[(int64_t)ml * Mg + kl] * x[m0 + ml];
-  y[k] = alpha * acc;
-}
-
-void launch_gemvT_blocks(const Geometry &g, const double *x, double *y,
-                         double alpha, hipStream_t s) {
-  if (g.M == 0) return;
-  hipLaunchKernelGGL(k_gemvT_blocks, dim3((g.M + 255) / 256), dim3(256), 0, s,
-                     g.M, g.isl_geo.p, g.dgisl.p, g.dgsinv.p, g.Sinv.p, x, y,
-                     alpha);
   LBS_HIP(hipGetLastError());
 }
 

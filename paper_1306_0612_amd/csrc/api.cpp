@@ -601,16 +601,50 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl,
   g.dellc.upload(ellc, s);
   g.near_ptr.upload(nptr, s);
   g.near_idx.upload(nidx, s);
+  // log sources in each island's own frame (projection from the antipode of
+  // its centre): node images, radii, frames, near lists and their transpose
   {
-    // transpose: for centre m, the islands k with m among k's near centres
-    std::vector<int32_t> tptr(M + 1, 0), tidx(nidx.size());
-    for (int32_t m : nidx) ++tptr[m + 1];
-    for (int m = 0; m < M; ++m) tptr[m + 1] += tptr[m];
-    std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1);
+    g.xil.alloc(2 * N);
+    g.elll.alloc(N);
+    launch_local_frame(N, g.island.p, g.disl.p, g.xyz.p, g.xil.p, g.elll.p, s);
+    std::vector<double> xl = g.xil.download(s);
+    std::vector<double> rl(M, 0.0), fr(6 * M);
+    for (int k = 0; k < M; ++k) {
+      for (int64_t i = g.offs[k]; i < g.offs[k + 1]; ++i)
+        rl[k] = std::max(rl[k], std::hypot(xl[2 * i], xl[2 * i + 1]));
+      const double *c = isl[k].center, *e1 = isl[k].e1;
+      fr[6 * k] = e1[0];
+      fr[6 * k + 1] = e1[1];
+      fr[6 * k + 2] = e1[2];
+      fr[6 * k + 3] = e1[1] * c[2] - e1[2] * c[1];
+      fr[6 * k + 4] = e1[2] * c[0] - e1[0] * c[2];
+      fr[6 * k + 5] = e1[0] * c[1] - e1[1] * c[0];
+    }
+    // centre m is near island k when |eta'| <= 3 rho'_k, i.e. with
+    // h = c_m . c_k:  (1 - h) <= 9 rho'^2 (1 + h)
+    std::vector<int32_t> rp(M + 1, 0), ri;
+    for (int k = 0; k < M; ++k) {
+      const int q = isl_geo[k];
+      const double lim = 9.0 * rl[k] * rl[k];
+      for (int m = g.gisl[q]; m < g.gisl[q + 1]; ++m) {
+        const double h = g.cxyz[3 * m] * g.cxyz[3 * k] + g.cxyz[3 * m + 1] * g.cxyz[3 * k + 1] +
+                         g.cxyz[3 * m + 2] * g.cxyz[3 * k + 2];
+        if (m == k || 1.0 - h <= lim * (1.0 + h)) ri.push_back(m);
+      }
+      rp[k + 1] = (int32_t)ri.size();
+    }
+    std::vector<int32_t> tp(M + 1, 0), ti(ri.size());
+    for (int32_t m : ri) ++tp[m + 1];
+    for (int m = 0; m < M; ++m) tp[m + 1] += tp[m];
+    std::vector<int32_t> fill(tp.begin(), tp.end() - 1);
     for (int k = 0; k < M; ++k)
-      for (int e = nptr[k]; e < nptr[k + 1]; ++e) tidx[fill[nidx[e]]++] = k;
-    g.nearT_ptr.upload(tptr, s);
-    g.nearT_idx.upload(tidx, s);
+      for (int e = rp[k]; e < rp[k + 1]; ++e) ti[fill[ri[e]]++] = k;
+    g.rhol.upload(rl, s);
+    g.frame.upload(fr, s);
+    g.nearR_ptr.upload(rp, s);
+    g.nearR_idx.upload(ri, s);
+    g.nearRT_ptr.upload(tp, s);
+    g.nearRT_idx.upload(ti, s);
   }
   // quadtree forest over the node images (one tree per geometry)
   ctx->xi_x.resize(N);
@@ -758,6 +792,8 @@ void ensure_adj(lbs_ctx &c) {
   a.pc.alloc((size_t)2 * g.N);
   a.Fc.alloc((size_t)2 * g.N);
   a.ysum.alloc((size_t)g.G);
+  c.geo.SinvT.alloc(c.geo.Sinv.n);
+  launch_transpose_blocks(g, g.Sinv.p, c.geo.SinvT.p, (hipStream_t)0);
   LBS_HIP(hipStreamSynchronize((hipStream_t)0));
   a.ready = true;
 }
@@ -768,7 +804,7 @@ void precond_T(lbs_ctx &c, const double *mu, double *lam, hipStream_t s) {
   AdjState &a = c.adj;
   launch_logsrc_T(g, mu, a.mom.p, -1.0, a.tA.p, s);
   launch_axpby(g.M, 1.0, mu + g.N, 1.0, a.tA.p, s);
-  launch_gemvT_blocks(g, a.tA.p, lam + g.N, 1.0, s);
+  launch_gemv_blocks_with(g, g.SinvT.p, a.tA.p, g.M, 1, lam + g.N, g.M, 1.0, s);
   launch_FT(g, lam + g.N, 1.0, mu, -1.0, lam, s);
 }
 

@@ -137,6 +137,42 @@ void launch_node_coeffs(int64_t N, const int32_t *island, const double *sign,
   LBS_HIP(hipGetLastError());
 }
 
+// Node images in their own island's frame (log-source expansions): with
+// a = x.e1, b = x.e2, h = x.c of island k, the stereographic projection from
+// the antipode -c maps x to xi' = (a + i b)/(1 + h), the island centre to 0
+// and keeps the chord identity
+//   |x - y|^2 = 4 |xi'_x - xi'_y|^2 / ((1 + |xi'_x|^2)(1 + |xi'_y|^2)).
+// Outputs xi' (complex) and ell' = log(1 + |xi'|^2).
+__global__ void k_local_frame(int64_t N, const int32_t *__restrict__ island,
+                              const lbs_island *__restrict__ isl,
+                              const double *__restrict__ xyz,
+                              double *__restrict__ xil,
+                              double *__restrict__ elll) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const lbs_island &I = isl[island[i]];
+  const double *c = I.center, *e1 = I.e1;
+  const double e2[3] = {e1[1] * c[2] - e1[2] * c[1], e1[2] * c[0] - e1[0] * c[2],
+                        e1[0] * c[1] - e1[1] * c[0]};
+  const double x0 = xyz[3 * i], x1 = xyz[3 * i + 1], x2 = xyz[3 * i + 2];
+  const double a = x0 * e1[0] + x1 * e1[1] + x2 * e1[2];
+  const double b = x0 * e2[0] + x1 * e2[1] + x2 * e2[2];
+  const double h = x0 * c[0] + x1 * c[1] + x2 * c[2];
+  const double inv = 1.0 / (1.0 + h);
+  xil[2 * i] = a * inv;
+  xil[2 * i + 1] = b * inv;
+  elll[i] = log1p((a * a + b * b) * inv * inv);
+}
+
+void launch_local_frame(int64_t N, const int32_t *island,
+                        const lbs_island *isl, const double *xyz, double *xil,
+                        double *elll, hipStream_t s) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_local_frame, dim3((unsigned)((N + 255) / 256)),
+                     dim3(256), 0, s, N, island, isl, xyz, xil, elll);
+  LBS_HIP(hipGetLastError());
+}
+
 __global__ void k_permute_complex(int64_t n, const int64_t *__restrict__ perm,
                                   const double *__restrict__ in,
                                   double *__restrict__ out) {

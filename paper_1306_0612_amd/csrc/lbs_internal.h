@@ -200,10 +200,16 @@ struct Geometry {
   DBuf<int64_t> doffs, dgnode, dgsinv;
   DBuf<int32_t> dgisl;
   DBuf<int32_t> near_ptr, near_idx;  // near centres per island (log sources)
-  DBuf<int32_t> nearT_ptr, nearT_idx;  // islands having a centre as near (sorted)
+  // log sources in each island's own frame (projection from the antipode of
+  // its centre): node images xi', log(1 + |xi'|^2), radius max|xi'|, frame
+  // vectors (e1, e2 per island), near centres (|eta'| <= 3 rho') and the
+  // transposed lists (islands having a centre as near), sorted
+  DBuf<double> xil, elll, rhol, frame;
+  DBuf<int32_t> nearR_ptr, nearR_idx, nearRT_ptr, nearRT_idx;
   DBuf<lbs_island> disl;             // island parameters
   DBuf<double> dsign;                // orientation sign per island
   DBuf<double> Sinv;                 // block-diagonal inverse Schur complement
+  DBuf<double> SinvT;                // its transpose (adjoint; made on first use)
 };
 
 // Segments of rows for segmented dot products: each segment is a union of
@@ -239,6 +245,9 @@ void launch_node_coeffs(int64_t N, const int32_t *island, const double *sign,
                         const int64_t *offs, const double *xi,
                         const double *dxi, const double *ddxi, double *qfac,
                         double *tau, double *gw, double *ell, hipStream_t s);
+void launch_local_frame(int64_t N, const int32_t *island,
+                        const lbs_island *isl, const double *xyz, double *xil,
+                        double *elll, hipStream_t s);
 void launch_permute_complex(int64_t n, const int64_t *perm, const double *in,
                             double *out, hipStream_t s);
 
@@ -302,6 +311,9 @@ void invert_blocks(const Geometry &g, double *S, double *Sinv, hipStream_t s);
 void launch_gemv_blocks(const Geometry &g, const double *x, int64_t ldx,
                         int nrhs, double *y, int64_t ldy, double alpha,
                         hipStream_t s);
+void launch_gemv_blocks_with(const Geometry &g, const double *A,
+                             const double *x, int64_t ldx, int nrhs, double *y,
+                             int64_t ldy, double alpha, hipStream_t s);
 void launch_eval_logsrc(const Geometry &g, int64_t T, const double *txyz,
                         const int32_t *tgeo, const double *A, int64_t lda,
                         int nrhs, const double *add, double *u, int64_t ldu,
@@ -351,8 +363,8 @@ void launch_logsrc_T(const Geometry &g, const double *y, double *mom,
                      double alpha, double *out, hipStream_t s);
 void launch_FT(const Geometry &g, const double *z, double a, const double *x,
                double b, double *out, hipStream_t s);
-void launch_gemvT_blocks(const Geometry &g, const double *x, double *y,
-                         double alpha, hipStream_t s);
+void launch_transpose_blocks(const Geometry &g, const double *A, double *AT,
+                             hipStream_t s);
 void launch_evalT_logsrc(const Geometry &g, int64_t T, const double *txyz,
                          const double *w, double *out, hipStream_t s);
 void launch_evalT_sigma(const Geometry &g, const double *FT,

@@ -23,16 +23,24 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ------------------------------------------------------------ log sources
 // (E z)_i = sum_m 2 z_m G(x_i, c_m),  G(x, y) = -(1/2pi) log|x - y| + log2/4pi
 // (Section 1.1, eq. eqn:greens_func), m over the islands of i's geometry.
-// For target island k and a centre m with |eta_m - eta_k| > 3 rho_k
-// ("far"), the planar identity
-//   log|x - c| = log 2 + log|xi - eta| - ell(xi)/2 - ell(eta)/2,
-//   ell(z) = log(1 + |z|^2),
-// and the series log(1 - u q) = -sum_l (u q)^l / l with u = (xi - eta_k)/rho_k,
-// q = rho_k / (eta_m - eta_k), |u| <= 1, |q| < 1/3 give
-//   sum_far z_m log|x_i - c_m| = Re sum_l L_k[l] u^l - Z_k ell_i / 2,
-//   L_k[0] = sum_far z_m (log 2 + log|eta_k - eta_m| - ell(eta_m)/2),
-//   L_k[l] = -sum_far z_m q^l / l,   Z_k = sum_far z_m.
-// Near centres (own centre included) are summed directly in 3D.
+//
+// Expansions in each island's own frame.  For target island k with centre c,
+// frame (e1, e2 = e1 x c) and node images xi' = (x.e1 + i x.e2)/(1 + x.c)
+// (the stereographic projection from -c, which sends c to 0), a centre m has
+// eta' = (a + i b)/(1 + h), a = c_m.e1, b = c_m.e2, h = c_m.c, and the chord
+// identity gives
+//   log|x_i - c_m| = log|c - c_m| + Re log(1 - u q) - ell'_i / 2,
+//   u = xi'_i / rho'_k,  q = rho'_k / eta' = 2 rho'_k (a - i b) / |c - c_m|^2,
+// ell'_i = log(1 + |xi'_i|^2), rho'_k = max |xi'| over the island.  For
+// |eta'| > 3 rho'_k ("far") the series log(1 - u q) = -sum_l (u q)^l / l
+// converges with |u q| < 1/3, so
+//   sum_far z_m log|x_i - c_m| = Re sum_l L_k[l] u^l - Z_k ell'_i / 2,
+//   L_k[0] = sum_far z_m log|c - c_m|,  L_k[l] = -sum_far z_m q^l / l,
+//   Z_k = sum_far z_m.
+// Near centres (own centre included) are summed directly in 3D.  In this
+// frame an island is a disk of radius about tan(r/2) at the origin, so the
+// near lists hold only the neighbouring islands wherever the island lies
+// on the sphere.
 constexpr int kLogStride = 2 * (kPlog + 1) + 2;
 
 __device__ __forceinline__ bool in_sorted(const int32_t *a, int n, int x) {
@@ -45,23 +53,26 @@ __device__ __forceinline__ bool in_sorted(const int32_t *a, int n, int x) {
   return lo < n && a[lo] == x;
 }
 
-__global__ void __launch_bounds__(256)
+// L_k for every island k (block per island, threads over the centres)
+__global__ void __launch_bounds__(128)
     k_logsrc_local(int M, const int32_t *__restrict__ isl_geo,
                    const int32_t *__restrict__ gisl,
-                   const double *__restrict__ eta,
-                   const double *__restrict__ rho,
-                   const double *__restrict__ ellc,
+                   const double *__restrict__ cxyz,
+                   const double *__restrict__ frame,
+                   const double *__restrict__ rhol,
                    const int32_t *__restrict__ near_ptr,
                    const int32_t *__restrict__ near_idx,
                    const double *__restrict__ z, int64_t ldz,
                    double *__restrict__ Lout) {
   constexpr int P = kPlog;
-  __shared__ double red[4][kLogStride];
+  __shared__ double red[2][kLogStride];
   const int k = blockIdx.x, r = blockIdx.y;
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
   const int g = isl_geo[k];
   const int m0 = gisl[g], m1 = gisl[g + 1];
-  const double ex = eta[2 * k], ey = eta[2 * k + 1], rk = rho[k];
+  const double c0 = cxyz[3 * k], c1 = cxyz[3 * k + 1], c2 = cxyz[3 * k + 2];
+  const double *fr = frame + 6 * k;
+  const double rk2 = 2.0 * rhol[k];
   const int32_t *nl = near_idx + near_ptr[k];
   const int nn = near_ptr[k + 1] - near_ptr[k];
   const double *zr = z + (int64_t)r * ldz;
@@ -69,8 +80,115 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int l = 0; l < P; ++l) acc[l] = cx<double>{0.0, 0.0};
   double a0 = 0.0, zf = 0.0, zt = 0.0;
-  for (int m = m0 + tid; m < m1; m += 256) {
+  for (int m = m0 + tid; m < m1; m += 128) {
     const double zm = zr[m];
+    zt += zm;
+    if (in_sorted(nl, nn, m)) continue;
+    const double x0 = cxyz[3 * m], x1 = cxyz[3 * m + 1], x2 = cxyz[3 * m + 2];
+    const double d0 = x0 - c0, d1 = x1 - c1, d2 = x2 - c2;
+    const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+    const double a = x0 * fr[0] + x1 * fr[1] + x2 * fr[2];
+    const double b = x0 * fr[3] + x1 * fr[4] + x2 * fr[5];
+    zf += zm;
+    a0 += zm * 0.5 * log(dd);
+    const double f = rk2 / dd;
+    const cx<double> q{a * f, -b * f};
+    cx<double> pw = zm * q;
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+      acc[l] = acc[l] + pw;
+      pw = pw * q;
+    }
+  }
+  auto put = [&](int slot, double v) {
+    v = wave_sum(v);
+    if (ln == 0) red[wv][slot] = v;
+  };
+  put(0, a0);
+  put(1, 0.0);
+#pragma unroll
+  for (int l = 0; l < P; ++l) {
+    put(2 * (l + 1), acc[l].x);
+    put(2 * (l + 1) + 1, acc[l].y);
+  }
+  put(2 * (P + 1), zf);
+  put(2 * (P + 1) + 1, zt);
+  __syncthreads();
+  double *out = Lout + ((int64_t)r * M + k) * kLogStride;
+  for (int s = tid; s < kLogStride; s += 128) {
+    double v = red[0][s] + red[1][s];
+    if (s >= 2 && s < 2 * (P + 1)) v *= -1.0 / (double)(s / 2);  // -q^l / l
+    out[s] = v;
+  }
+}
+
+__global__ void k_logsrc_node(int64_t N, int M, const int32_t *__restrict__ island,
+                              const double *__restrict__ xil,
+                              const double *__restrict__ xyz,
+                              const double *__restrict__ elll,
+                              const double *__restrict__ rhol,
+                              const double *__restrict__ cxyz,
+                              const int32_t *__restrict__ near_ptr,
+                              const int32_t *__restrict__ near_idx,
+                              const double *__restrict__ z, int64_t ldz,
+                              const double *__restrict__ Lc,
+                              double *__restrict__ out, int64_t ldo,
+                              double alpha) {
+  constexpr int P = kPlog;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= N) return;
+  const int k = island[i];
+  const double *L = Lc + ((int64_t)r * M + k) * kLogStride;
+  const double ir = 1.0 / rhol[k];
+  const cx<double> u{xil[2 * i] * ir, xil[2 * i + 1] * ir};
+  cx<double> s{L[2 * P], L[2 * P + 1]};
+  for (int l = P - 1; l >= 0; --l) s = s * u + cx<double>{L[2 * l], L[2 * l + 1]};
+  double tot = s.x - 0.5 * L[2 * (P + 1)] * elll[i];
+  const double x0 = xyz[3 * i], x1 = xyz[3 * i + 1], x2 = xyz[3 * i + 2];
+  const double *zr = z + (int64_t)r * ldz;
+  for (int e = near_ptr[k]; e < near_ptr[k + 1]; ++e) {
+    const int m = near_idx[e];
+    const double d0 = x0 - cxyz[3 * m], d1 = x1 - cxyz[3 * m + 1],
+                 d2 = x2 - cxyz[3 * m + 2];
+    tot += zr[m] * 0.5 * log(d0 * d0 + d1 * d1 + d2 * d2);
+  }
+  const double ez = -kInvPi * tot + kLog2 * 0.5 * kInvPi * L[2 * (P + 1) + 1];
+  out[(int64_t)r * ldo + i] += alpha * ez;
+}
+
+// The same expansion about the planar centre eta_k of the common projection
+// (for the shape derivative, which needs sum_m z_m / (xi - eta_m) in that
+// plane):
+//   log|x - c| = log 2 + log|xi - eta| - ell(xi)/2 - ell(eta)/2,
+//   ell(z) = log(1 + |z|^2),  u = (xi - eta_k)/rho_k,  q = rho_k/(eta_m - eta_k),
+//   L_k[0] = sum_far z_m (log 2 + log|eta_k - eta_m| - ell(eta_m)/2),
+//   L_k[l] = -sum_far z_m q^l / l,   far: |eta_m - eta_k| > 3 rho_k.
+__global__ void __launch_bounds__(256)
+    k_logsrc_local_plane(int M, const int32_t *__restrict__ isl_geo,
+                         const int32_t *__restrict__ gisl,
+                         const double *__restrict__ eta,
+                         const double *__restrict__ rho,
+                         const double *__restrict__ ellc,
+                         const int32_t *__restrict__ near_ptr,
+                         const int32_t *__restrict__ near_idx,
+                         const double *__restrict__ z,
+                         double *__restrict__ Lout) {
+  constexpr int P = kPlog;
+  __shared__ double red[4][kLogStride];
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const int g = isl_geo[k];
+  const int m0 = gisl[g], m1 = gisl[g + 1];
+  const double ex = eta[2 * k], ey = eta[2 * k + 1], rk = rho[k];
+  const int32_t *nl = near_idx + near_ptr[k];
+  const int nn = near_ptr[k + 1] - near_ptr[k];
+  cx<double> acc[P];
+#pragma unroll
+  for (int l = 0; l < P; ++l) acc[l] = cx<double>{0.0, 0.0};
+  double a0 = 0.0, zf = 0.0, zt = 0.0;
+  for (int m = m0 + tid; m < m1; m += 256) {
+    const double zm = z[m];
     zt += zm;
     if (in_sorted(nl, nn, m)) continue;
     const double dx = eta[2 * m] - ex, dy = eta[2 * m + 1] - ey;
@@ -100,58 +218,21 @@ __global__ void __launch_bounds__(256)
   put(2 * (P + 1), zf);
   put(2 * (P + 1) + 1, zt);
   __syncthreads();
-  double *out = Lout + ((int64_t)r * M + k) * kLogStride;
+  double *out = Lout + (int64_t)k * kLogStride;
   for (int s = tid; s < kLogStride; s += 256) {
     double v = red[0][s] + red[1][s] + red[2][s] + red[3][s];
-    if (s >= 2 && s < 2 * (P + 1)) v *= -1.0 / (double)(s / 2);  // -q^l / l
+    if (s >= 2 && s < 2 * (P + 1)) v *= -1.0 / (double)(s / 2);
     out[s] = v;
   }
 }
 
-__global__ void k_logsrc_node(int64_t N, int M, const int32_t *__restrict__ island,
-                              const double *__restrict__ xi,
-                              const double *__restrict__ xyz,
-                              const double *__restrict__ ell,
-                              const double *__restrict__ eta,
-                              const double *__restrict__ rho,
-                              const double *__restrict__ cxyz,
-                              const int32_t *__restrict__ near_ptr,
-                              const int32_t *__restrict__ near_idx,
-                              const double *__restrict__ z, int64_t ldz,
-                              const double *__restrict__ Lc,
-                              double *__restrict__ out, int64_t ldo,
-                              double alpha) {
-  constexpr int P = kPlog;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (i >= N) return;
-  const int k = island[i];
-  const double *L = Lc + ((int64_t)r * M + k) * kLogStride;
-  const double ir = 1.0 / rho[k];
-  const cx<double> u{(xi[2 * i] - eta[2 * k]) * ir,
-                     (xi[2 * i + 1] - eta[2 * k + 1]) * ir};
-  cx<double> s{L[2 * P], L[2 * P + 1]};
-  for (int l = P - 1; l >= 0; --l) s = s * u + cx<double>{L[2 * l], L[2 * l + 1]};
-  double tot = s.x - 0.5 * L[2 * (P + 1)] * ell[i];
-  const double x0 = xyz[3 * i], x1 = xyz[3 * i + 1], x2 = xyz[3 * i + 2];
-  const double *zr = z + (int64_t)r * ldz;
-  for (int e = near_ptr[k]; e < near_ptr[k + 1]; ++e) {
-    const int m = near_idx[e];
-    const double d0 = x0 - cxyz[3 * m], d1 = x1 - cxyz[3 * m + 1],
-                 d2 = x2 - cxyz[3 * m + 2];
-    tot += zr[m] * 0.5 * log(d0 * d0 + d1 * d1 + d2 * d2);
-  }
-  const double ez = -kInvPi * tot + kLog2 * 0.5 * kInvPi * L[2 * (P + 1) + 1];
-  out[(int64_t)r * ldo + i] += alpha * ez;
-}
-
-// Expansion coefficients L_k of the far centres for one column z (ws.logL).
+// Planar-centre expansion coefficients L_k for one column z (ws.logL).
 void launch_logsrc_local(const Geometry &g, Workspace &ws, const double *z,
                          hipStream_t s) {
   if (g.M == 0) return;
-  hipLaunchKernelGGL(k_logsrc_local, dim3(g.M, 1), dim3(256), 0, s, g.M,
+  hipLaunchKernelGGL(k_logsrc_local_plane, dim3(g.M), dim3(256), 0, s, g.M,
                      g.isl_geo.p, g.dgisl.p, g.deta.p, g.drho.p, g.dellc.p,
-                     g.near_ptr.p, g.near_idx.p, z, (int64_t)g.M, ws.logL.p);
+                     g.near_ptr.p, g.near_idx.p, z, ws.logL.p);
   LBS_HIP(hipGetLastError());
 }
 
@@ -159,13 +240,13 @@ void launch_logsrc_apply(const Geometry &g, Workspace &ws, const double *z,
                          int64_t ldz, int nrhs, double *out, int64_t ldo,
                          double alpha, hipStream_t s) {
   if (g.M == 0 || g.N == 0) return;
-  hipLaunchKernelGGL(k_logsrc_local, dim3(g.M, nrhs), dim3(256), 0, s, g.M,
-                     g.isl_geo.p, g.dgisl.p, g.deta.p, g.drho.p, g.dellc.p,
-                     g.near_ptr.p, g.near_idx.p, z, ldz, ws.logL.p);
+  hipLaunchKernelGGL(k_logsrc_local, dim3(g.M, nrhs), dim3(128), 0, s, g.M,
+                     g.isl_geo.p, g.dgisl.p, g.dcenter.p, g.frame.p, g.rhol.p,
+                     g.nearR_ptr.p, g.nearR_idx.p, z, ldz, ws.logL.p);
   hipLaunchKernelGGL(k_logsrc_node, dim3((unsigned)((g.N + 255) / 256), nrhs),
-                     dim3(256), 0, s, g.N, g.M, g.island.p, g.xi.p, g.xyz.p,
-                     g.ell.p, g.deta.p, g.drho.p, g.dcenter.p, g.near_ptr.p,
-                     g.near_idx.p, z, ldz, ws.logL.p, out, ldo, alpha);
+                     dim3(256), 0, s, g.N, g.M, g.island.p, g.xil.p, g.xyz.p,
+                     g.elll.p, g.rhol.p, g.dcenter.p, g.nearR_ptr.p,
+                     g.nearR_idx.p, z, ldz, ws.logL.p, out, ldo, alpha);
   LBS_HIP(hipGetLastError());
 }
 
@@ -428,13 +509,41 @@ __global__ void __launch_bounds__(256)
   if (ln == 0) y[(int64_t)r * ldy + row] = alpha * acc;
 }
 
+void launch_gemv_blocks_with(const Geometry &g, const double *A,
+                             const double *x, int64_t ldx, int nrhs, double *y,
+                             int64_t ldy, double alpha, hipStream_t s) {
+  if (g.M == 0) return;
+  hipLaunchKernelGGL(k_gemv_blocks, dim3((g.M + 3) / 4, nrhs), dim3(256), 0,
+                     s, g.M, g.isl_geo.p, g.dgisl.p, g.dgsinv.p, A, x, ldx, y,
+                     ldy, alpha);
+  LBS_HIP(hipGetLastError());
+}
+
 void launch_gemv_blocks(const Geometry &g, const double *x, int64_t ldx,
                         int nrhs, double *y, int64_t ldy, double alpha,
                         hipStream_t s) {
+  launch_gemv_blocks_with(g, g.Sinv.p, x, ldx, nrhs, y, ldy, alpha, s);
+}
+
+// AT = transpose of every diagonal block of A (block per row)
+__global__ void k_transpose_blocks(const int32_t *__restrict__ isl_geo,
+                                   const int32_t *__restrict__ gisl,
+                                   const int64_t *__restrict__ gsinv,
+                                   const double *__restrict__ A,
+                                   double *__restrict__ AT) {
+  const int row = blockIdx.x;
+  const int g = isl_geo[row];
+  const int m0 = gisl[g], Mg = gisl[g + 1] - m0, rl = row - m0;
+  const int64_t base = gsinv[g];
+  for (int j = threadIdx.x; j < Mg; j += blockDim.x)
+    AT[base + (int64_t)j * Mg + rl] = A[base + (int64_t)rl * Mg + j];
+}
+
+void launch_transpose_blocks(const Geometry &g, const double *A, double *AT,
+                             hipStream_t s) {
   if (g.M == 0) return;
-  hipLaunchKernelGGL(k_gemv_blocks, dim3((g.M + 3) / 4, nrhs), dim3(256), 0,
-                     s, g.M, g.isl_geo.p, g.dgisl.p, g.dgsinv.p, g.Sinv.p, x,
-                     ldx, y, ldy, alpha);
+  hipLaunchKernelGGL(k_transpose_blocks, dim3(g.M), dim3(256), 0, s,
+                     g.isl_geo.p, g.dgisl.p, g.dgsinv.p, A, AT);
   LBS_HIP(hipGetLastError());
 }
 
