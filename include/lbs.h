@@ -88,7 +88,12 @@ typedef struct {
   int32_t max_outer; /* mixed precision: refinement steps cap (default 8)  */
   double inner_tol;  /* mixed precision: inner GMRES tolerance (1e-5)      */
   int32_t matvec;    /* LBS_MATVEC_FMM (default) or LBS_MATVEC_DIRECT      */
-  int32_t reserved;
+  int32_t graphs;    /* 1 (default): every GMRES iteration (operator,      */
+                     /* orthogonalisation, Givens update) is captured once */
+                     /* per iteration index as a HIP graph on an internal  */
+                     /* stream and replayed on the caller's stream; 0:     */
+                     /* launched kernel by kernel.  Ignored while stage    */
+                     /* timing is enabled.                                 */
 } lbs_options;
 
 typedef struct {

@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <memory>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -192,6 +194,25 @@ struct GmresState {
   DBuf<double> bvec, rvec, xvec, dvec, bn2;
 };
 
+// FMM plan of an evaluation at sphere targets, kept for the next call with
+// the same targets.  Forward: sources = nodes, targets = the targets (one
+// tree per geometry); transposed: the (non-pole) targets are the sources and
+// the nodes the targets.  Targets at the north pole carry no Cauchy part and
+// are left out of the trees.
+struct EvalPlan {
+  std::vector<double> key;      // host copy of the targets (T x 3)
+  std::vector<int64_t> toff;    // geometry-major target offsets
+  std::vector<int32_t> tgeo;    // geometry of each target
+  std::vector<double> tx, ty;   // projected non-pole targets (compact)
+  std::vector<int64_t> idx;     // compact position -> target index
+  bool tree = false;
+  DevPlan pl;
+  Workspace ws;
+  DBuf<double> qt;              // forward: qfac in the plan's source order
+  DBuf<int64_t> didx;           // transposed: idx on the device
+  DBuf<int32_t> dtgeo;
+};
+
 // Buffers of the transposed operators (one column).
 struct AdjState {
   bool ready = false;
@@ -201,6 +222,22 @@ struct AdjState {
   DBuf<double> lam;    // N + M
   DBuf<double> pc, Fc; // complex, N x 2
   DBuf<double> ysum;   // per geometry
+};
+
+// HIP graphs of GMRES iterations, keyed by (operator, systems per column
+// count, iteration index), and the device buffers they were captured with.
+struct GraphCache {
+  hipStream_t cap = nullptr;  // capture stream (non-blocking, default priority)
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> exec;
+  std::vector<const void *> sig;
+  void clear() {
+    for (auto &e : exec) (void)hipGraphExecDestroy(e.second);
+    exec.clear();
+  }
+  ~GraphCache() {
+    clear();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
 };
 
 struct lbs_ctx {
@@ -215,6 +252,8 @@ struct lbs_ctx {
   StageTimer timer;
   GmresState gm;
   AdjState adj;
+  std::unique_ptr<EvalPlan> evf, evt;  // cached forward / transposed plans
+  GraphCache graphs;
   int32_t *count_host = nullptr;
   ~lbs_ctx() {
     if (count_host) (void)hipHostFree(count_host);
@@ -344,14 +383,29 @@ struct GmresOut {
   bool conv = false;
 };
 
-// Lockstep GMRES(m) for the R * G systems P^-1 A x = b (columns of length
+using OpFn = std::function<void(const double *, double *, hipStream_t)>;
+
+// Buffers every captured iteration reads or writes; a change of any of them
+// (reallocation) invalidates the cached graphs.
+std::vector<const void *> graph_signature(lbs_ctx &c) {
+  const GmresState &st = c.gm;
+  const Workspace &w = c.ws;
+  const AdjState &a = c.adj;
+  return {st.V.p, st.H.p, st.cs.p, st.sn.p, st.gv.p, st.h1.p, st.h2.p, st.nrm2.p,
+          st.tol.p, st.resid.p, st.active.p, st.kused.p, st.count.p, w.pstr64.p,
+          w.mult64.p, w.loc64.p, w.pstr32.p, w.mult32.p, w.loc32.p, w.gam.p,
+          w.red.p, w.tmpM.p, w.logL.p, a.mom.p, a.tA.p, a.lam.p, a.pc.p, a.Fc.p,
+          a.ysum.p, c.geo.SinvT.p};
+}
+
+// Lockstep GMRES(m) for the R * G systems op(x) = b (columns of length
 // n = N + M), per-system absolute tolerances c.gm.tol.  x_zero: start from
 // x = 0.  CGS2 orthogonalisation, Givens rotations, one 4-byte read of the
-// number of active systems per iteration.
-using OpFn = std::function<void(const double *, double *)>;
-
-GmresOut gmres(lbs_ctx &c, const OpFn &op, int R, const double *b, double *x,
-               bool x_zero, int max_iter, hipStream_t s) {
+// number of active systems per iteration.  With graph_id >= 0 (and graphs
+// enabled, stage timing off) the body of iteration k is captured once as a
+// HIP graph under the key (graph_id, R, k) and replayed afterwards.
+GmresOut gmres(lbs_ctx &c, const OpFn &op, int graph_id, int R, const double *b,
+               double *x, bool x_zero, int max_iter, hipStream_t s) {
   GmresState &st = c.gm;
   const int64_t n = st.n;
   const int m = st.m, G = c.geo.G, S = R * G;
@@ -359,8 +413,17 @@ GmresOut gmres(lbs_ctx &c, const OpFn &op, int R, const double *b, double *x,
   const int64_t ldv = (int64_t)R * n;
   const int32_t *rg = c.geo.row_geo.p;
   GmresOut out;
+  const bool use_graphs = graph_id >= 0 && c.opt.graphs && c.ws.timer == nullptr;
+  if (use_graphs) {
+    std::vector<const void *> sig = graph_signature(c);
+    if (sig != c.graphs.sig) {
+      c.graphs.clear();
+      c.graphs.sig = sig;
+    }
+    if (!c.graphs.cap) LBS_HIP(hipStreamCreateWithFlags(&c.graphs.cap, hipStreamNonBlocking));
+  }
   auto residual_into_v0 = [&]() {
-    op(x, V);
+    op(x, V, s);
     launch_axpby(ldv, 1.0, b, -1.0, V, s);
   };
   if (x_zero) {
@@ -384,19 +447,43 @@ GmresOut gmres(lbs_ctx &c, const OpFn &op, int R, const double *b, double *x,
     int kc = 0;
     for (int k = 0; k < m; ++k) {
       double *vk = V + (int64_t)k * ldv, *w = V + (int64_t)(k + 1) * ldv;
-      op(vk, w);
-      launch_segdots(c.seg_sys, R, k + 1, V, ldv, n, w, n, st.h1.p,
-                     c.ws.red.p, s);
-      launch_maxpy_seg(n, R, G, k + 1, rg, V, ldv, st.h1.p, w, s);
-      launch_segdots(c.seg_sys, R, k + 1, V, ldv, n, w, n, st.h2.p,
-                     c.ws.red.p, s);
-      launch_maxpy_seg(n, R, G, k + 1, rg, V, ldv, st.h2.p, w, s);
-      launch_segdots(c.seg_sys, R, 1, w, 0, n, w, n, st.nrm2.p, c.ws.red.p, s);
-      launch_fill_int(1, 0, st.count.p, s);
-      launch_givens_seg(S, k, m, st.h1.p, st.h2.p, st.nrm2.p, st.tol.p,
-                        st.H.p, st.cs.p, st.sn.p, st.gv.p, st.resid.p,
-                        st.active.p, st.kused.p, st.count.p, s);
-      launch_normalize_seg(n, R, G, rg, st.nrm2.p, st.active.p, w, w, s);
+      auto body = [&](hipStream_t q) {
+        op(vk, w, q);
+        launch_segdots(c.seg_sys, R, k + 1, V, ldv, n, w, n, st.h1.p, c.ws.red.p, q);
+        launch_maxpy_seg(n, R, G, k + 1, rg, V, ldv, st.h1.p, w, q);
+        launch_segdots(c.seg_sys, R, k + 1, V, ldv, n, w, n, st.h2.p, c.ws.red.p, q);
+        launch_maxpy_seg(n, R, G, k + 1, rg, V, ldv, st.h2.p, w, q);
+        launch_segdots(c.seg_sys, R, 1, w, 0, n, w, n, st.nrm2.p, c.ws.red.p, q);
+        launch_fill_int(1, 0, st.count.p, q);
+        launch_givens_seg(S, k, m, st.h1.p, st.h2.p, st.nrm2.p, st.tol.p, st.H.p,
+                          st.cs.p, st.sn.p, st.gv.p, st.resid.p, st.active.p,
+                          st.kused.p, st.count.p, q);
+        launch_normalize_seg(n, R, G, rg, st.nrm2.p, st.active.p, w, w, q);
+      };
+      if (use_graphs) {
+        const auto key = std::make_tuple(graph_id, R, k);
+        auto it = c.graphs.exec.find(key);
+        if (it == c.graphs.exec.end()) {
+          hipGraph_t gr = nullptr;
+          LBS_HIP(hipStreamBeginCapture(c.graphs.cap, hipStreamCaptureModeThreadLocal));
+          try {
+            body(c.graphs.cap);
+          } catch (...) {
+            (void)hipStreamEndCapture(c.graphs.cap, &gr);
+            if (gr) (void)hipGraphDestroy(gr);
+            throw;
+          }
+          LBS_HIP(hipStreamEndCapture(c.graphs.cap, &gr));
+          hipGraphExec_t ex = nullptr;
+          hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(gr);
+          LBS_HIP(e);
+          it = c.graphs.exec.emplace(key, ex).first;
+        }
+        LBS_HIP(hipGraphLaunch(it->second, s));
+      } else {
+        body(s);
+      }
       alive = read_count(c, s);
       ++out.iters;
       kc = k + 1;
@@ -417,8 +504,11 @@ GmresOut gmres(lbs_ctx &c, const OpFn &op, int R, const double *b, double *x,
 GmresOut gmres(lbs_ctx &c, int prec, int R, const double *b, double *x,
                bool x_zero, int max_iter, hipStream_t s) {
   return gmres(
-      c, [&](const double *in, double *out) { apply_precond_op(c, prec, R, in, out, s); }, R,
-      b, x, x_zero, max_iter, s);
+      c,
+      [&](const double *in, double *out, hipStream_t q) {
+        apply_precond_op(c, prec, R, in, out, q);
+      },
+      prec, R, b, x, x_zero, max_iter, s);
 }
 
 // Per-system 2-norms^2 of R columns of length N + M into out (S values).
@@ -446,6 +536,7 @@ void validate_options(const lbs_options &o) {
   if (o.max_iter < 1 || o.max_outer < 1) fail(LBS_ERR_INVALID_ARG, "max_iter/max_outer < 1");
   if (!(o.inner_tol > 0 && o.inner_tol < 1)) fail(LBS_ERR_INVALID_ARG, "inner_tol outside (0, 1)");
   if (o.matvec != LBS_MATVEC_FMM && o.matvec != LBS_MATVEC_DIRECT) fail(LBS_ERR_INVALID_ARG, "bad matvec mode");
+  if (o.graphs != 0 && o.graphs != 1) fail(LBS_ERR_INVALID_ARG, "graphs must be 0 or 1");
 }
 
 // Set-up of G geometries (islands and node counts concatenated
@@ -699,6 +790,73 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl,
   return ctx.release();
 }
 
+// The evaluation plan for these targets (cached on the handle).
+EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &toff,
+                    const double *txyz, hipStream_t s) {
+  Geometry &g = c.geo;
+  const int G = g.G;
+  const int64_t T = toff[G];
+  std::vector<double> hx(3 * T);
+  LBS_HIP(hipMemcpyAsync(hx.data(), txyz, 3 * T * sizeof(double), hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipStreamSynchronize(s));
+  std::unique_ptr<EvalPlan> &slot = transposed ? c.evt : c.evf;
+  if (slot && slot->toff == toff && slot->key == hx) return *slot;
+  slot.reset();
+  auto ep = std::make_unique<EvalPlan>();
+  ep->toff = toff;
+  ep->tgeo.resize(T);
+  std::vector<int64_t> qoff(G + 1, 0);
+  for (int q = 0; q < G; ++q) {
+    for (int64_t t = toff[q]; t < toff[q + 1]; ++t) {
+      ep->tgeo[t] = q;
+      const double x0 = hx[3 * t], x1 = hx[3 * t + 1], x2 = hx[3 * t + 2];
+      if (!std::isfinite(x0) || !std::isfinite(x1) || !std::isfinite(x2))
+        fail(LBS_ERR_NOT_FINITE, "target " + std::to_string(t) + " is not finite");
+      const double d = 1.0 - x2;
+      if (d <= 1e-14) continue;  // the pole: Cauchy part is zero
+      ep->tx.push_back(x0 / d);
+      ep->ty.push_back(x1 / d);
+      ep->idx.push_back(t);
+    }
+    qoff[q + 1] = (int64_t)ep->tx.size();
+  }
+  ep->dtgeo.upload(ep->tgeo, s);
+  const int64_t n = (int64_t)ep->idx.size();
+  if (n > 0 && (transposed || c.opt.matvec != LBS_MATVEC_DIRECT)) {
+    Tree &F = ep->pl.host;
+    for (int q = 0; q < G; ++q) {
+      const int64_t a = g.gnode[q], nn = g.gnode[q + 1] - a;
+      const int64_t ta = qoff[q], tn = qoff[q + 1] - ta;
+      Tree t;
+      if (transposed)
+        build_tree(ep->tx.data() + ta, ep->ty.data() + ta, tn, c.xi_x.data() + a,
+                   c.xi_y.data() + a, nn, false, c.opt.leaf_max, t);
+      else
+        build_tree(c.xi_x.data() + a, c.xi_y.data() + a, nn, ep->tx.data() + ta,
+                   ep->ty.data() + ta, tn, false, c.opt.leaf_max, t);
+      if (G == 1) F = std::move(t);
+      else if (transposed) append_tree(F, t, ta, a, ta, a);
+      else append_tree(F, t, a, ta, a, ta);
+    }
+    if (transposed) {
+      upload_plan(F, ep->tx.data(), ep->ty.data(), c.xi_x.data(), c.xi_y.data(), nullptr,
+                  ep->pl, s);
+      ep->didx.upload(ep->idx, s);
+    } else {
+      upload_plan(F, c.xi_x.data(), c.xi_y.data(), ep->tx.data(), ep->ty.data(), &ep->idx,
+                  ep->pl, s);
+      ep->qt.alloc(2 * g.N);
+      launch_permute_complex(g.N, ep->pl.src_perm.p, g.qfac.p, ep->qt.p, s);
+    }
+    ep->ws.ensure(ep->pl, c.opt.p64, c.opt.p32, 1, g.N, g.M, G, kPlog);
+    ep->tree = true;
+  }
+  LBS_HIP(hipStreamSynchronize(s));
+  ep->key = std::move(hx);
+  slot = std::move(ep);
+  return *slot;
+}
+
 // Evaluation over geometry-major targets: targets [toff[q], toff[q+1]) of
 // geometry q.
 void eval_impl(lbs_ctx &c, int nrhs, const double *sigma, const double *A,
@@ -707,35 +865,16 @@ void eval_impl(lbs_ctx &c, int nrhs, const double *sigma, const double *A,
   Geometry &g = c.geo;
   const int G = g.G;
   const int64_t T = toff[G];
-  std::vector<double> hx(3 * T);
-  LBS_HIP(hipMemcpyAsync(hx.data(), txyz, 3 * T * sizeof(double), hipMemcpyDeviceToHost, s));
-  LBS_HIP(hipStreamSynchronize(s));
-  std::vector<double> tx, ty;
-  std::vector<int64_t> idx, qoff(G + 1, 0);
-  std::vector<int32_t> tgeo(T);
-  for (int q = 0; q < G; ++q) {
-    for (int64_t t = toff[q]; t < toff[q + 1]; ++t) {
-      tgeo[t] = q;
-      const double x0 = hx[3 * t], x1 = hx[3 * t + 1], x2 = hx[3 * t + 2];
-      if (!std::isfinite(x0) || !std::isfinite(x1) || !std::isfinite(x2))
-        fail(LBS_ERR_NOT_FINITE, "target " + std::to_string(t) + " is not finite");
-      const double d = 1.0 - x2;
-      if (d <= 1e-14) continue;  // the pole: Cauchy part is zero
-      tx.push_back(x0 / d);
-      ty.push_back(x1 / d);
-      idx.push_back(t);
-    }
-    qoff[q + 1] = (int64_t)tx.size();
-  }
+  EvalPlan &ep = eval_plan(c, false, toff, txyz, s);
   launch_fill(T * nrhs, 0.0, u, s);
-  if (!tx.empty()) {
+  if (!ep.idx.empty()) {
     if (c.opt.matvec == LBS_MATVEC_DIRECT) {
       std::vector<double> txi(2 * T, 0.0);
       std::vector<uint8_t> pole(T, 1);
-      for (size_t q = 0; q < idx.size(); ++q) {
-        txi[2 * idx[q]] = tx[q];
-        txi[2 * idx[q] + 1] = ty[q];
-        pole[idx[q]] = 0;
+      for (size_t q = 0; q < ep.idx.size(); ++q) {
+        txi[2 * ep.idx[q]] = ep.tx[q];
+        txi[2 * ep.idx[q] + 1] = ep.ty[q];
+        pole[ep.idx[q]] = 0;
       }
       DBuf<double> dtxi;
       dtxi.upload(txi, s);
@@ -744,33 +883,14 @@ void eval_impl(lbs_ctx &c, int nrhs, const double *sigma, const double *A,
       direct_eval64(g.N, g.xi.p, g.qfac.p, sigma, g.N, T, dtxi.p, dpole.p, nrhs, u, T, 0.5, s);
       LBS_HIP(hipStreamSynchronize(s));
     } else {
-      DevPlan pl;
-      Tree &F = pl.host;
-      for (int q = 0; q < G; ++q) {
-        const int64_t a = g.gnode[q], n = g.gnode[q + 1] - a;
-        const int64_t ta = qoff[q], tn = qoff[q + 1] - ta;
-        Tree t;
-        build_tree(c.xi_x.data() + a, c.xi_y.data() + a, n, tx.data() + ta, ty.data() + ta, tn,
-                   false, c.opt.leaf_max, t);
-        if (G == 1) F = std::move(t);
-        else append_tree(F, t, a, ta, a, ta);
-      }
-      upload_plan(F, c.xi_x.data(), c.xi_y.data(), tx.data(), ty.data(), &idx, pl, s);
-      DBuf<double> qt;
-      qt.alloc(2 * g.N);
-      launch_permute_complex(g.N, pl.src_perm.p, g.qfac.p, qt.p, s);
-      Workspace ws;
-      ws.ensure(pl, c.opt.p64, c.opt.p32, nrhs, g.N, g.M, G, kPlog);
-      fmm_apply64(pl, c.tab64, ws, qt.p, sigma, g.N, nrhs, u, T, 0.5, Assembly{}, s);
-      LBS_HIP(hipStreamSynchronize(s));
+      ep.ws.ensure(ep.pl, c.opt.p64, c.opt.p32, nrhs, g.N, g.M, G, kPlog);
+      fmm_apply64(ep.pl, c.tab64, ep.ws, ep.qt.p, sigma, g.N, nrhs, u, T, 0.5, Assembly{}, s);
     }
   }
   ensure_ws(c, nrhs);
   launch_segdots(c.seg_nodes, nrhs, 1, g.gw.p, 0, 0, sigma, g.N, c.ws.gam.p, c.ws.red.p, s);
   launch_axpby((int64_t)nrhs * G, 0.0, c.ws.gam.p, 0.5, c.ws.gam.p, s);
-  DBuf<int32_t> dtg;
-  dtg.upload(tgeo, s);
-  launch_eval_logsrc(g, T, txyz, dtg.p, A, g.M, nrhs, c.ws.gam.p, u, T, s);
+  launch_eval_logsrc(g, T, txyz, ep.dtgeo.p, A, g.M, nrhs, c.ws.gam.p, u, T, s);
   LBS_HIP(hipStreamSynchronize(s));
 }
 
@@ -830,53 +950,16 @@ void apply_op_T(lbs_ctx &c, int R, const double *x, double *y, hipStream_t s) {
   launch_axpby((int64_t)R * n, 1.0, x, 1.0, y, s);
 }
 
-// FMM plan with the (non-pole) targets as sources and the nodes as targets,
-// for the transposed evaluation.  idx: compacted position -> target index.
-struct EvalTPlan {
-  DevPlan pl;
-  Workspace ws;
-  DBuf<int64_t> idx;
-  int64_t n = 0;
-};
-
-void build_eval_T_plan(lbs_ctx &c, int64_t T, const double *txyz, EvalTPlan &ep,
-                       hipStream_t s) {
-  std::vector<double> hx(3 * T);
-  LBS_HIP(hipMemcpyAsync(hx.data(), txyz, 3 * T * sizeof(double), hipMemcpyDeviceToHost, s));
-  LBS_HIP(hipStreamSynchronize(s));
-  std::vector<double> tx, ty;
-  std::vector<int64_t> idx;
-  for (int64_t t = 0; t < T; ++t) {
-    const double x0 = hx[3 * t], x1 = hx[3 * t + 1], x2 = hx[3 * t + 2];
-    if (!std::isfinite(x0) || !std::isfinite(x1) || !std::isfinite(x2))
-      fail(LBS_ERR_NOT_FINITE, "target " + std::to_string(t) + " is not finite");
-    const double d = 1.0 - x2;
-    if (d <= 1e-14) continue;  // the pole: no Cauchy part
-    tx.push_back(x0 / d);
-    ty.push_back(x1 / d);
-    idx.push_back(t);
-  }
-  ep.n = (int64_t)idx.size();
-  if (ep.n == 0) return;
-  const Geometry &g = c.geo;
-  Tree &t = ep.pl.host;
-  build_tree(tx.data(), ty.data(), ep.n, c.xi_x.data(), c.xi_y.data(), g.N, false,
-             c.opt.leaf_max, t);
-  upload_plan(t, tx.data(), ty.data(), c.xi_x.data(), c.xi_y.data(), nullptr, ep.pl, s);
-  ep.ws.ensure(ep.pl, c.opt.p64, c.opt.p32, 1, g.N, g.M, g.G, kPlog);
-  ep.idx.upload(idx, s);
-}
-
 // psi (and dpsi) at the nodes of sum_t w_t / (xi - zeta_t), one column
-void eval_T_field(lbs_ctx &c, EvalTPlan &ep, const double *w, double *pcw, double *psi,
+void eval_T_field(lbs_ctx &c, EvalPlan &ep, const double *w, double *pcw, double *psi,
                   double *dpsi, hipStream_t s) {
   const int64_t N = c.geo.N;
-  if (ep.n == 0) {
+  if (!ep.tree) {
     launch_fill(2 * N, 0.0, psi, s);
     if (dpsi) launch_fill(2 * N, 0.0, dpsi, s);
     return;
   }
-  launch_gather_complex(ep.n, ep.idx.p, w, pcw, s);
+  launch_gather_complex((int64_t)ep.idx.size(), ep.didx.p, w, pcw, s);
   fmm_apply64_full(ep.pl, c.tab64, ep.ws, pcw, psi, dpsi, s);
 }
 
@@ -895,6 +978,7 @@ void lbs_default_options(lbs_options *o) {
   o->max_outer = 8;
   o->inner_tol = 1e-5;
   o->matvec = LBS_MATVEC_FMM;
+  o->graphs = 1;
 }
 
 const char *lbs_last_error(void) { return g_err.c_str(); }
@@ -1115,10 +1199,9 @@ lbs_status lbs_eval_T(lbs_handle h, int32_t nrhs, const double *w, int64_t T, co
     }
     ensure_ws(c, 1);
     ensure_adj(c);
-    EvalTPlan ep;
-    build_eval_T_plan(c, T, txyz, ep, s);
+    EvalPlan &ep = eval_plan(c, true, {0, T}, txyz, s);
     DBuf<double> pcw, wsum;
-    pcw.alloc((size_t)2 * std::max<int64_t>(ep.n, 1));
+    pcw.alloc((size_t)2 * std::max<size_t>(ep.idx.size(), 1));
     wsum.alloc(1);
     for (int r = 0; r < nrhs; ++r) {
       const double *wr = w + (int64_t)r * T;
@@ -1159,13 +1242,13 @@ lbs_status lbs_solve_T(lbs_handle h, int32_t nrhs, const double *rs, const doubl
       fail(LBS_ERR_NOT_FINITE, "right-hand side is not finite");
     sys_norm2(c, R, gm.bvec.p, gm.bn2.p, s);
     launch_scale_sqrt(S, tol, gm.bn2.p, gm.tol.p, s);
-    OpFn op = [&](const double *in, double *out) { apply_op_T(c, R, in, out, s); };
-    GmresOut go = gmres(c, op, R, gm.bvec.p, gm.xvec.p, true, c.opt.max_iter, s);
+    OpFn op = [&](const double *in, double *out, hipStream_t q) { apply_op_T(c, R, in, out, q); };
+    GmresOut go = gmres(c, op, 2, R, gm.bvec.p, gm.xvec.p, true, c.opt.max_iter, s);
     inf.iters = go.iters;
     inf.fp64_matvecs = go.iters + 1;
     noconv = !go.conv;
     // residual of A^T lambda = b (equal to that of the right-preconditioned system)
-    op(gm.xvec.p, gm.rvec.p);
+    op(gm.xvec.p, gm.rvec.p, s);
     launch_axpby((int64_t)R * n, 1.0, gm.bvec.p, -1.0, gm.rvec.p, s);
     sys_norm2(c, R, gm.rvec.p, gm.nrm2.p, s);
     std::vector<double> rn2 = download(gm.nrm2.p, S, s), bn2 = download(gm.bn2.p, S, s);
@@ -1213,11 +1296,10 @@ lbs_status lbs_shape_vjp(lbs_handle h, const double *sigma, const double *A, con
     launch_dl_strengths(g, sigma, a.pc.p, s);
     fmm_apply64_full(c.plan, c.tab64, c.ws, a.pc.p, a.Fc.p, dFp, s);
     // field of the target weights at the nodes
-    EvalTPlan ep;
     DBuf<double> pcw;
     if (T > 0) {
-      build_eval_T_plan(c, T, txyz, ep, s);
-      pcw.alloc((size_t)2 * std::max<int64_t>(ep.n, 1));
+      EvalPlan &ep = eval_plan(c, true, {0, T}, txyz, s);
+      pcw.alloc((size_t)2 * std::max<size_t>(ep.idx.size(), 1));
       eval_T_field(c, ep, w, pcw.p, Fw, dFw, s);
       launch_sum(T, w, sums + 2, s);
     } else {

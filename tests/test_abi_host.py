@@ -41,6 +41,7 @@ def test_default_options(lbs):
     o = lbs.default_options()
     assert (o.p64, o.p32, o.restart) == (30, 16, 50)
     assert o.inner_tol == 1e-5
+    assert (o.matvec, o.graphs) == (0, 1)
 
 
 @pytest.mark.parametrize("case", ["uniform", "curves", "clustered", "tiny"])
@@ -101,3 +102,4 @@ def test_setup_rejects_bad_options(lbs):
     assert lbs.setup_status(isl, p64=31) == "LBS_ERR_UNSUPPORTED"
     assert lbs.setup_status(isl, restart=0) == "LBS_ERR_INVALID_ARG"
     assert lbs.setup_status(isl, nodes=4) == "LBS_ERR_INVALID_ARG"
+    assert lbs.setup_status(isl, graphs=2) == "LBS_ERR_INVALID_ARG"

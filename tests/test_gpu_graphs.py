@@ -1,0 +1,84 @@
+"""GMRES iterations replayed from captured HIP graphs give exactly the
+results of kernel-by-kernel launches: the same kernels run in the same
+order, and no floating-point reduction depends on timing.  Each solve
+with graphs is repeated, with eager work and synchronizations in between,
+so later calls replay graphs captured by earlier ones."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1306_0612_amd import lbs
+    lbs.load()
+    return torch, lbs
+
+
+def _t(torch, a):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
+
+
+def _data(sol, isls, nrhs, seed):
+    xyz = sol.nodes().cpu().numpy()
+    no = sol.node_offsets
+    G = np.zeros((nrhs, sol.n_nodes))
+    for q, isl in enumerate(isls):
+        for r in range(nrhs):
+            G[r, no[q]:no[q + 1]] = synth.exact_harmonic(
+                xyz[no[q]:no[q + 1]], isl.center,
+                synth.random_data_coeffs(seed + 10 * q + r, isl))
+    return G
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_single_geometry_solve(env, prec):
+    torch, lbs = env
+    isl = synth.star_islands(91, 8, (0.05, 0.15), nodes=96)
+    eager = lbs.Solver(isl, leaf_max=16, graphs=0)
+    graph = lbs.Solver(isl, leaf_max=16, graphs=1)
+    g = _t(torch, _data(eager, [isl], 1, 5)[0])
+    s0, a0, i0 = eager.solve(g, tol=1e-12, precision=prec)
+    for rep in range(3):
+        s1, a1, i1 = graph.solve(g, tol=1e-12, precision=prec)
+        assert i1["iters"] == i0["iters"]
+        assert torch.equal(s1, s0) and torch.equal(a1, a0), rep
+        # eager work between replays
+        graph.matvec(s1, "iplusk", prec)
+        torch.cuda.synchronize()
+
+
+def test_batch_solve(env):
+    torch, lbs = env
+    isls = [synth.star_islands(92, 5, (0.08, 0.15), nodes=64),
+            synth.star_islands(93, 9, (0.05, 0.1), nodes=80)]
+    eager = lbs.Solver(isls, leaf_max=12, graphs=0)
+    graph = lbs.Solver(isls, leaf_max=12, graphs=1)
+    G = _t(torch, _data(eager, isls, 3, 7))
+    s0, a0, _ = eager.solve(G, tol=1e-12, precision="mixed")
+    for rep in range(2):
+        s1, a1, _ = graph.solve(G, tol=1e-12, precision="mixed")
+        assert torch.equal(s1, s0) and torch.equal(a1, a0), rep
+        # a single-column solve in between captures other graphs
+        graph.solve(G[0:1].contiguous(), tol=1e-10, precision="fp64")
+        torch.cuda.synchronize()
+
+
+def test_transposed_solve(env):
+    torch, lbs = env
+    isl = synth.star_islands(94, 6, (0.06, 0.15), nodes=80)
+    eager = lbs.Solver(isl, leaf_max=12, graphs=0)
+    graph = lbs.Solver(isl, leaf_max=12, graphs=1)
+    rng = np.random.default_rng(3)
+    rs = _t(torch, rng.standard_normal(eager.n_nodes))
+    ra = _t(torch, rng.standard_normal(eager.n_islands))
+    l0, m0, _ = eager.solve_T(rs, ra, tol=1e-12)
+    for rep in range(2):
+        l1, m1, _ = graph.solve_T(rs, ra, tol=1e-12)
+        assert torch.equal(l1, l0) and torch.equal(m1, m0), rep
+        graph.solve(rs, tol=1e-10)
+        torch.cuda.synchronize()
