@@ -239,6 +239,38 @@ lbs_status lbs_shape_vjp(lbs_handle h, const double *sigma, const double *A,
                          const double *xyz_targets, const double *w,
                          double *dcoef, void *stream);
 
+/* Change the expansion orders of a handle (p64 in 20, 24, 30, 36, 40, 48;
+ * p32 in 12, 16, 20, 24) without rebuilding its quadtree.  Drops the
+ * cached evaluation plans and captured GMRES iterations.  Synchronous. */
+lbs_status lbs_set_orders(lbs_handle h, int32_t p64, int32_t p32,
+                          void *stream);
+
+/* One measured setting of lbs_autotune: leaf size, the order that was
+ * varied (p32 for a mixed application, p64 for an FP64 one, the other 0),
+ * milliseconds per (I + K) application and its relative error
+ * max|y - y_ref| / max|y_ref| against an FP64 order-48 reference. */
+typedef struct {
+  int32_t leaf_max, p32, p64;
+  double ms, err;
+} lbs_tune_entry;
+
+/* Autotuner of the FMM schedule for one geometry (arguments as lbs_setup):
+ * for leaf sizes 24, 32, 48, 64, 96, 128 and orders p32 in 12..24 and p64
+ * in 20..36 it times (I + K) on a fixed pseudo-random density and returns
+ * in *best_host the base options (defaults if NULL) with the leaf size and
+ * p32 of the fastest mixed application whose error is <= tol_mixed, and the
+ * p64 of the fastest FP64 application on that leaf size with error
+ * <= tol_fp64.  Every measured setting is written to entries_host (up to
+ * max_entries; n_entries_host receives the count; both may be NULL).
+ * LBS_ERR_UNSUPPORTED when no setting meets a tolerance.  Synchronous;
+ * builds and destroys one handle per leaf size. */
+lbs_status lbs_autotune(const lbs_island *islands_host, int32_t n_islands,
+                        const int32_t *nodes_per_curve_host,
+                        const lbs_options *base_host, double tol_mixed,
+                        double tol_fp64, void *stream, lbs_options *best_host,
+                        lbs_tune_entry *entries_host, int32_t max_entries,
+                        int32_t *n_entries_host);
+
 /* Per-stage GPU timing of operator applications.  With enable != 0 every
  * stage of every later lbs_matvec / lbs_solve call is bracketed by a pair
  * of HIP events recorded on the call's stream; lbs_stage_times waits for

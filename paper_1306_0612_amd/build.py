@@ -30,6 +30,9 @@ def _compile(src):
     cmd = [HIPCC] + COMMON
     if src.endswith(".hip"):
         cmd += DEVICE
+    else:
+        # host-only sources: no device pass for any other target
+        cmd += ["--offload-arch=" + ARCH]
     cmd += ["-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

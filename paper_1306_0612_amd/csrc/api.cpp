@@ -965,6 +965,10 @@ void eval_T_field(lbs_ctx &c, EvalPlan &ep, const double *w, double *pcw, double
 
 }  // namespace
 
+namespace lbs {
+void set_last_error(const std::string &msg) { g_err = msg; }
+}  // namespace lbs
+
 extern "C" {
 
 void lbs_default_options(lbs_options *o) {
@@ -1311,6 +1315,31 @@ lbs_status lbs_shape_vjp(lbs_handle h, const double *sigma, const double *A, con
     launch_sum(g.M, A, sums + 1, s);
     launch_shape_vjp(g, sigma, lam_s, Fl, dFl, dFp, Fw, dFw, LSd, sums, sums + 1, sums + 2,
                      dcoef, s);
+    LBS_HIP(hipStreamSynchronize(s));
+  });
+}
+
+lbs_status lbs_set_orders(lbs_handle h, int32_t p64, int32_t p32, void *stream) {
+  return guard([&] {
+    check_handle(h);
+    if (!p64_ok(p64)) fail(LBS_ERR_UNSUPPORTED, "p64 must be 20/24/30/36/40/48");
+    if (!p32_ok(p32)) fail(LBS_ERR_UNSUPPORTED, "p32 must be 12/16/20/24");
+    lbs_ctx &c = *h;
+    hipStream_t s = (hipStream_t)stream;
+    LBS_HIP(hipStreamSynchronize(s));
+    if (p64 != c.opt.p64) build_tables(c.tab64, p64, s);
+    if (p32 != c.opt.p32) build_tables(c.tab32, p32, s);
+    c.opt.p64 = p64;
+    c.opt.p32 = p32;
+    // expansion buffers are sized by the orders: reallocate on next use
+    const int cap = std::max(1, c.ws.nrhs_cap);
+    c.ws.nrhs_cap = 0;
+    ensure_ws(c, cap);
+    c.evf.reset();
+    c.evt.reset();
+    // captured iterations hold the old tables and kernels
+    c.graphs.clear();
+    c.graphs.sig.clear();
     LBS_HIP(hipStreamSynchronize(s));
   });
 }

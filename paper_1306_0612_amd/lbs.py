@@ -63,6 +63,15 @@ class TreeStats(ctypes.Structure):
                 if f != "reserved"}
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("leaf_max", ctypes.c_int32), ("p32", ctypes.c_int32),
+                ("p64", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("err", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class LBSError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s: %s" % (STATUS.get(code, code), msg))
@@ -129,12 +138,19 @@ def load():
                                 vp, vp, ctypes.POINTER(SolveInfo), vp]
     lib.lbs_shape_vjp.argtypes = [H, vp, vp, vp, ctypes.c_int64, vp, vp, vp,
                                   vp]
+    lib.lbs_set_orders.argtypes = [H, ctypes.c_int32, ctypes.c_int32, vp]
+    lib.lbs_autotune.argtypes = [ctypes.POINTER(Island), ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(Options), ctypes.c_double,
+                                 ctypes.c_double, vp, ctypes.POINTER(Options),
+                                 ctypes.POINTER(TuneEntry), ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_int32)]
     for name in ("lbs_setup", "lbs_sizes", "lbs_nodes", "lbs_matvec",
                  "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
                  "lbs_stage_timing", "lbs_stage_times", "lbs_setup_batch",
                  "lbs_batch_info", "lbs_eval_batch",
                  "lbs_check_tree_host", "lbs_eval_T", "lbs_solve_T",
-                 "lbs_shape_vjp"):
+                 "lbs_shape_vjp", "lbs_set_orders", "lbs_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -347,6 +363,11 @@ class Solver:
                                     _dev(out), _stream()))
         return out
 
+    def set_orders(self, p64, p32):
+        """Change the expansion orders without rebuilding the tree."""
+        _check(load().lbs_set_orders(self._h, int(p64), int(p32), _stream()))
+        self.options.p64, self.options.p32 = int(p64), int(p32)
+
     def stage_timing(self, enable=True):
         _check(load().lbs_stage_timing(self._h, 1 if enable else 0))
 
@@ -361,6 +382,24 @@ class Solver:
         st = TreeStats()
         _check(load().lbs_tree_info(self._h, ctypes.byref(st)))
         return st.as_dict()
+
+
+def autotune(islands, tol_mixed=1e-6, tol_fp64=1e-10, nodes=None, **kw):
+    """lbs_autotune: (best Options, [measured settings as dicts])."""
+    lib = load()
+    arr = islands_array(islands)
+    m = len(islands.r0)
+    n = islands.n if nodes is None else nodes
+    nn = (ctypes.c_int32 * m)(*[int(v) for v in
+                                (n if hasattr(n, "__len__") else [n] * m)])
+    base = default_options(**kw)
+    best = Options()
+    ent = (TuneEntry * 64)()
+    cnt = ctypes.c_int32()
+    _check(lib.lbs_autotune(arr, m, nn, ctypes.byref(base), float(tol_mixed),
+                            float(tol_fp64), _stream(), ctypes.byref(best),
+                            ent, 64, ctypes.byref(cnt)))
+    return best, [ent[i].as_dict() for i in range(min(cnt.value, 64))]
 
 
 def check_tree_host(x, y, leaf_max):
