@@ -77,36 +77,78 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
   pl.n_leaf_t = (int)leaf_t.size();
   pl.n_m2l = (int)m2l.size();
   pl.leaf_t_host = leaf_t;
-  // per-level work lists of the upward and downward passes
-  std::vector<int32_t> xb, mpar, l2lb, l2lpq;
-  std::vector<int4> mkids;
-  pl.m2m_lptr.assign(1, 0);
-  pl.l2l_lptr.assign(1, 0);
-  for (int l = 0; l < T.nlevels; ++l) {
-    for (int b : by_level[l]) {
-      if (!T.leaf[b] && T.s1[b] > T.s0[b]) {
-        int ks[4] = {-1, -1, -1, -1}, nk = 0;
-        for (int c = T.child0[b]; c < T.child0[b] + T.nchild[b]; ++c)
-          if (T.s1[c] > T.s0[c]) ks[nk++] = (c << 2) | quad[c];
-        mpar.push_back(b);
-        mkids.push_back(make_int4(ks[0], ks[1], ks[2], ks[3]));
+  // subtree heaps of the fused upward / downward passes (see DevPlan)
+  std::vector<int32_t> xb;
+  {
+    auto kid = [&](int b, int q, bool src) -> int {
+      if (T.leaf[b]) return -1;
+      for (int c = T.child0[b]; c < T.child0[b] + T.nchild[b]; ++c)
+        if (quad[c] == q && (src ? T.s1[c] > T.s0[c] : has_tgt[c])) return c;
+      return -1;
+    };
+    auto inner = [&](int b, bool src) {
+      if (b < 0 || T.leaf[b]) return false;
+      for (int q = 0; q < 4; ++q)
+        if (kid(b, q, src) >= 0) return true;
+      return false;
+    };
+    std::vector<int32_t> ub, um, db;
+    std::vector<int4> ud;
+    std::vector<int> roots;
+    for (int r = 2; r < std::max(T.nlevels, 2); r += 3) roots.push_back(r);
+    pl.up_gptr.assign(1, 0);
+    for (auto it = roots.rbegin(); it != roots.rend(); ++it) {
+      for (int b : by_level[*it]) {
+        if (!(T.s1[b] > T.s0[b]) || !inner(b, true)) continue;
+        int32_t sl[21];
+        std::fill(sl, sl + 21, -1);
+        int32_t mask = 1;
+        sl[0] = b;
+        for (int s1 = 0; s1 < 5; ++s1) {
+          if (sl[s1] < 0) continue;
+          for (int q = 0; q < 4; ++q) {
+            const int c = kid(sl[s1], q, true);
+            const int sc = 4 * s1 + 1 + q;
+            if (c < 0) continue;
+            sl[sc] = c;
+            if (inner(c, true)) mask |= 1 << sc;
+          }
+        }
+        for (int g = 5; g < 21; ++g) {
+          int ks[4] = {-1, -1, -1, -1};
+          if (sl[g] >= 0 && (mask >> g & 1))
+            for (int q = 0; q < 4; ++q) ks[q] = kid(sl[g], q, true);
+          ud.push_back(make_int4(ks[0], ks[1], ks[2], ks[3]));
+        }
+        ub.insert(ub.end(), sl, sl + 21);
+        um.push_back(mask);
       }
-      if (l >= 3 && has_tgt[b]) {
-        l2lb.push_back(b);
-        l2lpq.push_back((T.parent[b] << 2) | quad[b]);
-      }
+      pl.up_gptr.push_back((int32_t)um.size());
     }
-    pl.m2m_lptr.push_back((int32_t)mpar.size());
-    pl.l2l_lptr.push_back((int32_t)l2lb.size());
+    pl.dn_gptr.assign(1, 0);
+    for (int r : roots) {
+      for (int b : by_level[r]) {
+        if (!has_tgt[b] || !inner(b, false)) continue;
+        int32_t sl[85];
+        std::fill(sl, sl + 85, -1);
+        sl[0] = b;
+        for (int s1 = 0; s1 < 21; ++s1) {
+          if (sl[s1] < 0) continue;
+          for (int q = 0; q < 4; ++q) sl[4 * s1 + 1 + q] = kid(sl[s1], q, false);
+        }
+        db.insert(db.end(), sl, sl + 85);
+      }
+      pl.dn_gptr.push_back((int32_t)(db.size() / 85));
+    }
+    pl.up_box.upload(ub, s);
+    pl.up_mask.upload(um, s);
+    pl.up_deep.upload(ud, s);
+    pl.dn_box.upload(db, s);
   }
   for (int b = 0; b < nb; ++b)
     if (T.x_ptr[b + 1] > T.x_ptr[b]) xb.push_back(b);
   pl.n_x = (int)xb.size();
   pl.x_box.upload(xb, s);
-  pl.m2m_par.upload(mpar, s);
-  pl.m2m_kids.upload(mkids, s);
-  pl.l2l_box.upload(l2lb, s);
-  pl.l2l_pq.upload(l2lpq, s);
   pl.cx.upload(T.cx, s);
   pl.cy.upload(T.cy, s);
   pl.rad.upload(T.rad, s);

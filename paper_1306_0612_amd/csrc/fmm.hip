@@ -47,27 +47,21 @@ static void cpow_host(double x, double y, int n, double &ox, double &oy) {
 
 void build_tables(Tables &t, int P, hipStream_t s) {
   t.P = P;
-  std::vector<double> m2m(4 * P * P * 2, 0.0), l2l(4 * P * P * 2, 0.0);
+  // M2M and L2L as real binomial weights times powers of the quadrant
+  // offset delta = (+-1, +-1):
+  //   M2M[q][lo][k] = C(lo, k) 2^-(lo+1) delta^(lo-k)   (k <= lo)
+  //   L2L[q][m][l]  = C(l, m) 2^-l delta^(l-m)          (l >= m)
+  // Binomials up to C(47, 23) and the components of delta^n (0 or a power
+  // of two) are exact, so the products equal the full tables bit for bit.
+  std::vector<double> bm(P * P, 0.0), bl(P * P, 0.0), dpw(4 * P * 2, 0.0);
+  for (int lo = 0; lo < P; ++lo)
+    for (int k = 0; k <= lo; ++k) {
+      bm[lo * P + k] = binom(lo, k) * std::ldexp(1.0, -(lo + 1));
+      bl[k * P + lo] = binom(lo, k) * std::ldexp(1.0, -lo);
+    }
   for (int q = 0; q < 4; ++q) {
-    double dx = (q & 1) ? 1.0 : -1.0, dy = (q & 2) ? 1.0 : -1.0;
-    for (int lo = 0; lo < P; ++lo)
-      for (int ki = 0; ki <= lo; ++ki) {
-        double px, py;
-        cpow_host(dx, dy, lo - ki, px, py);
-        double c = binom(lo, ki) * std::ldexp(1.0, -(lo + 1));
-        size_t at = ((size_t)(q * P + lo) * P + ki) * 2;
-        m2m[at] = c * px;
-        m2m[at + 1] = c * py;
-      }
-    for (int m = 0; m < P; ++m)
-      for (int l = m; l < P; ++l) {
-        double px, py;
-        cpow_host(dx, dy, l - m, px, py);
-        double c = binom(l, m) * std::ldexp(1.0, -l);
-        size_t at = ((size_t)(q * P + m) * P + l) * 2;
-        l2l[at] = c * px;
-        l2l[at + 1] = c * py;
-      }
+    const double dx = (q & 1) ? 1.0 : -1.0, dy = (q & 2) ? 1.0 : -1.0;
+    for (int n = 0; n < P; ++n) cpow_host(dx, dy, n, dpw[2 * (q * P + n)], dpw[2 * (q * P + n) + 1]);
   }
   std::vector<double> h(P * P);
   for (int l = 0; l < P; ++l)
@@ -92,12 +86,14 @@ void build_tables(Tables &t, int P, hipStream_t s) {
   auto to32 = [](const std::vector<double> &v) {
     return std::vector<float>(v.begin(), v.end());
   };
-  t.m2m64.upload(m2m, s);
-  t.l2l64.upload(l2l, s);
+  t.bm64.upload(bm, s);
+  t.bl64.upload(bl, s);
+  t.dp64.upload(dpw, s);
   t.h64.upload(h, s);
   t.itp64.upload(itp, s);
-  t.m2m32.upload(to32(m2m), s);
-  t.l2l32.upload(to32(l2l), s);
+  t.bm32.upload(to32(bm), s);
+  t.bl32.upload(to32(bl), s);
+  t.dp32.upload(to32(dpw), s);
   t.h32.upload(to32(h), s);
   t.itp32.upload(to32(itp), s);
   LBS_HIP(hipStreamSynchronize(s));
@@ -200,50 +196,179 @@ __global__ void __launch_bounds__(64)
   if (lane < P) M[((int64_t)r * nbox + b) * P + lane] = T(ir) * acc;
 }
 
-// M2M for the parents of one level: thread (parent i, coefficient lo);
-// kids[i] packs up to four (child << 2 | quadrant) entries, -1 = none.
+// Upward pass over three levels per launch: one work-group per root, whose
+// subtree is the heap described with DevPlan.  All operands are first
+// staged in LDS with every load in flight at once (the binomial weights,
+// the powers of delta, the multipoles of the grandchildren's children and
+// of the childless slots); then step 1 forms the multipoles of the
+// grandchildren that have children, step 2 those of the children, step 3
+// the root's, reading only LDS.  M2M of a child in quadrant q:
+//   A_lo = sum_{k <= lo} C(lo, k) 2^-(lo+1) delta_q^(lo-k) a_k.
 template <typename T, int P>
-__global__ void k_m2m(int n, const int32_t *__restrict__ par,
-                      const int4 *__restrict__ kids,
-                      const cx<T> *__restrict__ tab, cx<T> *__restrict__ M,
-                      int nbox) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = gid / P, lo = gid % P;
-  const int r = blockIdx.y;
-  if (i >= n) return;
-  const int b = par[i];
-  const int4 kd = kids[i];
-  const int ks[4] = {kd.x, kd.y, kd.z, kd.w};
-  cx<T> acc{T(0), T(0)};
+__global__ void __launch_bounds__(256)
+    k_m2m3(const int32_t *__restrict__ box, const int32_t *__restrict__ mask,
+           const int4 *__restrict__ deep, const T *__restrict__ Bm,
+           const cx<T> *__restrict__ Dp, cx<T> *__restrict__ M, int nbox) {
+  constexpr int NT = 256, NE = 84 * P, IT = (NE + NT - 1) / NT;
+  __shared__ T sB[P * P];
+  __shared__ cx<T> sD[4 * P];
+  __shared__ cx<T> sK[64 * P];  // children of grandchild j, quadrant q: 4 j + q
+  __shared__ cx<T> sm[21 * P];  // expansions of the heap slots
+  const int root = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const int32_t *bx = box + (int64_t)root * 21;
+  const int msk = mask[root];
+  const int4 *dp = deep + (int64_t)root * 16;
+  cx<T> *Mr = M + (int64_t)r * nbox * P;
+  for (int i = tid; i < P * P; i += NT) sB[i] = Bm[i];
+  for (int i = tid; i < 4 * P; i += NT) sD[i] = Dp[i];
+  cx<T> v[IT];
 #pragma unroll
-  for (int q4 = 0; q4 < 4; ++q4) {
-    const int e = ks[q4];
-    if (e < 0) continue;
-    const cx<T> *a = M + ((int64_t)r * nbox + (e >> 2)) * P;
-    const cx<T> *row = tab + ((size_t)(e & 3) * P + lo) * P;
-    for (int ki = 0; ki <= lo; ++ki) acc = acc + row[ki] * a[ki];
+  for (int i = 0; i < IT; ++i) {
+    const int e = tid + i * NT;
+    v[i] = cx<T>{T(0), T(0)};
+    if (e < 64 * P) {
+      const int jq = e / P, k = e % P, j = jq >> 2, q = jq & 3;
+      if ((msk >> (5 + j)) & 1) {
+        const int4 kd = dp[j];
+        const int c = q == 0 ? kd.x : q == 1 ? kd.y : q == 2 ? kd.z : kd.w;
+        if (c >= 0) v[i] = Mr[(int64_t)c * P + k];
+      }
+    } else if (e < NE) {
+      const int slot = 1 + (e - 64 * P) / P, k = (e - 64 * P) % P;
+      const int b = bx[slot];
+      if (b >= 0 && !((msk >> slot) & 1)) v[i] = Mr[(int64_t)b * P + k];
+    }
   }
-  M[((int64_t)r * nbox + b) * P + lo] = acc;
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = tid + i * NT;
+    if (e < 64 * P) sK[e] = v[i];
+    else if (e < NE) sm[P + (e - 64 * P)] = v[i];
+  }
+  __syncthreads();
+  // sum over the four quadrants of M2M(src[q]) at coefficient lo; the
+  // weights are exactly 0 for k > lo, so the fixed-length loop adds exact
+  // zeros there and its LDS reads can all be issued ahead
+  auto m2m = [&](const cx<T> *src, int stride, int present, int lo) {
+    cx<T> acc{T(0), T(0)};
+    const T *bw = sB + lo * P;
+    for (int q = 0; q < 4; ++q) {
+      if (!((present >> q) & 1)) continue;
+      const cx<T> *a = src + q * stride;
+      const cx<T> *dq = sD + q * P;
+#pragma unroll
+      for (int k = 0; k < P; ++k) acc = acc + (bw[k] * dq[max(lo - k, 0)]) * a[k];
+    }
+    return acc;
+  };
+  for (int it = tid; it < 16 * P; it += NT) {
+    const int j = it / P, lo = it % P, slot = 5 + j;
+    if (!((msk >> slot) & 1)) continue;
+    const int4 kd = dp[j];
+    const int present = (kd.x >= 0) | ((kd.y >= 0) << 1) | ((kd.z >= 0) << 2) | ((kd.w >= 0) << 3);
+    const cx<T> a = m2m(sK + 4 * j * P, P, present, lo);
+    sm[slot * P + lo] = a;
+    Mr[(int64_t)bx[slot] * P + lo] = a;
+  }
+  __syncthreads();
+  for (int it = tid; it < 4 * P; it += NT) {
+    const int j = it / P, lo = it % P, slot = 1 + j;
+    if (!((msk >> slot) & 1)) continue;
+    const int g0 = 4 * slot + 1;
+    const int present = (bx[g0] >= 0) | ((bx[g0 + 1] >= 0) << 1) |
+                        ((bx[g0 + 2] >= 0) << 2) | ((bx[g0 + 3] >= 0) << 3);
+    const cx<T> a = m2m(sm + g0 * P, P, present, lo);
+    sm[slot * P + lo] = a;
+    Mr[(int64_t)bx[slot] * P + lo] = a;
+  }
+  __syncthreads();
+  for (int lo = tid; lo < P; lo += NT) {
+    const int present = (bx[1] >= 0) | ((bx[2] >= 0) << 1) | ((bx[3] >= 0) << 2) |
+                        ((bx[4] >= 0) << 3);
+    Mr[(int64_t)bx[0] * P + lo] = m2m(sm + P, P, present, lo);
+  }
 }
 
-// L2L for the boxes of one level: thread (box i, coefficient m);
-// pq[i] packs (parent << 2 | quadrant of the box).
+// Downward pass over three levels per launch: one work-group per root (its
+// local expansion complete).  The expansions of the root, children and
+// grandchildren (their own parts, from M2L and P2L) are staged in LDS, and
+// those of the 64 great-grandchild slots in the registers of the threads
+// that finish them, with every load in flight at once; then the translated
+// parent expansion is added level by level.  L2L into a child in quadrant q:
+//   b'_m = sum_{l >= m} C(l, m) 2^-l delta_q^(l-m) b_l
+// (weights exactly 0 for l < m, as in the fixed-length loop below).
 template <typename T, int P>
-__global__ void k_l2l(int n, const int32_t *__restrict__ box,
-                      const int32_t *__restrict__ pq,
-                      const cx<T> *__restrict__ tab, cx<T> *__restrict__ L,
-                      int nbox) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = gid / P, m = gid % P;
-  const int r = blockIdx.y;
-  if (i >= n) return;
-  const int b = box[i], e = pq[i];
-  const cx<T> *bp = L + ((int64_t)r * nbox + (e >> 2)) * P;
-  const cx<T> *row = tab + ((size_t)(e & 3) * P + m) * P;
-  cx<T> acc{T(0), T(0)};
-  for (int l = m; l < P; ++l) acc = acc + row[l] * bp[l];
-  cx<T> *dst = L + ((int64_t)r * nbox + b) * P + m;
-  *dst = *dst + acc;
+__global__ void __launch_bounds__(256)
+    k_l2l3(const int32_t *__restrict__ box, const T *__restrict__ Bl,
+           const cx<T> *__restrict__ Dp, cx<T> *__restrict__ L, int nbox) {
+  constexpr int NT = 256, N1 = 21 * P, I1 = (N1 + NT - 1) / NT;
+  constexpr int N3 = 64 * P, I3 = (N3 + NT - 1) / NT;
+  __shared__ T sB[P * P];
+  __shared__ cx<T> sD[4 * P];
+  __shared__ cx<T> sl[21 * P];
+  const int root = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const int32_t *bx = box + (int64_t)root * 85;
+  cx<T> *Lr = L + (int64_t)r * nbox * P;
+  for (int i = tid; i < P * P; i += NT) sB[i] = Bl[i];
+  for (int i = tid; i < 4 * P; i += NT) sD[i] = Dp[i];
+  cx<T> v[I1], w[I3];
+#pragma unroll
+  for (int i = 0; i < I1; ++i) {
+    const int e = tid + i * NT;
+    v[i] = cx<T>{T(0), T(0)};
+    if (e < N1) {
+      const int b = bx[e / P];
+      if (b >= 0) v[i] = Lr[(int64_t)b * P + e % P];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < I3; ++i) {
+    const int e = tid + i * NT;
+    w[i] = cx<T>{T(0), T(0)};
+    if (e < N3) {
+      const int b = bx[21 + e / P];
+      if (b >= 0) w[i] = Lr[(int64_t)b * P + e % P];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < I1; ++i) {
+    const int e = tid + i * NT;
+    if (e < N1) sl[e] = v[i];
+  }
+  __syncthreads();
+  auto l2l = [&](int s, int m) {
+    const int ps = (s - 1) >> 2, q = (s - 1) & 3;
+    const cx<T> *bp = sl + ps * P;
+    const cx<T> *dq = sD + q * P;
+    const T *bw = sB + m * P;
+    cx<T> acc{T(0), T(0)};
+#pragma unroll
+    for (int l = 0; l < P; ++l) acc = acc + (bw[l] * dq[max(l - m, 0)]) * bp[l];
+    return acc;
+  };
+  // children (slots 1..4), then grandchildren (5..20): results kept in LDS
+  int first = 1, count = 4;
+  for (int d = 1; d <= 2; ++d) {
+    for (int it = tid; it < count * P; it += NT) {
+      const int s = first + it / P, m = it % P, b = bx[s];
+      if (b < 0) continue;
+      const cx<T> val = sl[s * P + m] + l2l(s, m);
+      sl[s * P + m] = val;
+      Lr[(int64_t)b * P + m] = val;
+    }
+    __syncthreads();
+    first += count;
+    count *= 4;
+  }
+  // great-grandchildren (21..84): own parts from registers
+#pragma unroll
+  for (int i = 0; i < I3; ++i) {
+    const int e = tid + i * NT;
+    if (e >= N3) continue;
+    const int s = 21 + e / P, m = e % P, b = bx[s];
+    if (b < 0) continue;
+    Lr[(int64_t)b * P + m] = w[i] + l2l(s, m);
+  }
 }
 
 template <int P>
@@ -668,18 +793,20 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
                       const cx<T> *p, cx<T> *M, cx<T> *L, int nrhs,
                       hipStream_t s) {
   StageTimer *tm = ws.timer;
-  const cx<T> *m2m, *l2l, *itp;
-  const T *H;
+  const cx<T> *itp, *dpw;
+  const T *H, *bm, *bl;
   if constexpr (sizeof(T) == 8) {
-    m2m = (const cx<T> *)tb.m2m64.p;
-    l2l = (const cx<T> *)tb.l2l64.p;
     itp = (const cx<T> *)tb.itp64.p;
     H = (const T *)tb.h64.p;
+    bm = (const T *)tb.bm64.p;
+    bl = (const T *)tb.bl64.p;
+    dpw = (const cx<T> *)tb.dp64.p;
   } else {
-    m2m = (const cx<T> *)tb.m2m32.p;
-    l2l = (const cx<T> *)tb.l2l32.p;
     itp = (const cx<T> *)tb.itp32.p;
     H = (const T *)tb.h32.p;
+    bm = (const T *)tb.bm32.p;
+    bl = (const T *)tb.bl32.p;
+    dpw = (const cx<T> *)tb.dp32.p;
   }
   {
     TimerScope ts(tm, ST_UPWARD, s);
@@ -687,14 +814,12 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
       hipLaunchKernelGGL((k_p2m<T, P>), dim3(pl.n_leaf_s, nrhs), dim3(64), 0,
                          s, pl.leaf_s.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p,
                          pl.rad.p, pl.sx.p, pl.sy.p, p, pl.ns, M, pl.nbox);
-    const int nl = (int)pl.m2m_lptr.size() - 1;
-    for (int l = nl - 1; l >= 2; --l) {
-      const int a0 = pl.m2m_lptr[l], a1 = pl.m2m_lptr[l + 1];
-      const int threads = (a1 - a0) * P;
-      if (threads <= 0) continue;
-      hipLaunchKernelGGL((k_m2m<T, P>), dim3((threads + 255) / 256, nrhs),
-                         dim3(256), 0, s, a1 - a0, pl.m2m_par.p + a0,
-                         pl.m2m_kids.p + a0, m2m, M, pl.nbox);
+    for (size_t g = 0; g + 1 < pl.up_gptr.size(); ++g) {
+      const int a0 = pl.up_gptr[g], n = pl.up_gptr[g + 1] - a0;
+      if (n <= 0) continue;
+      hipLaunchKernelGGL((k_m2m3<T, P>), dim3(n, nrhs), dim3(256), 0, s,
+                         pl.up_box.p + (int64_t)a0 * 21, pl.up_mask.p + a0,
+                         pl.up_deep.p + (int64_t)a0 * 16, bm, dpw, M, pl.nbox);
     }
   }
   if (pl.n_m2l > 0) {
@@ -718,14 +843,11 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
                        L, pl.nbox);
   }
   TimerScope ts(tm, ST_L2L, s);
-  const int nl = (int)pl.l2l_lptr.size() - 1;
-  for (int l = 3; l < nl; ++l) {
-    const int a0 = pl.l2l_lptr[l], a1 = pl.l2l_lptr[l + 1];
-    const int threads = (a1 - a0) * P;
-    if (threads <= 0) continue;
-    hipLaunchKernelGGL((k_l2l<T, P>), dim3((threads + 255) / 256, nrhs),
-                       dim3(256), 0, s, a1 - a0, pl.l2l_box.p + a0,
-                       pl.l2l_pq.p + a0, l2l, L, pl.nbox);
+  for (size_t g = 0; g + 1 < pl.dn_gptr.size(); ++g) {
+    const int a0 = pl.dn_gptr[g], n = pl.dn_gptr[g + 1] - a0;
+    if (n <= 0) continue;
+    hipLaunchKernelGGL((k_l2l3<T, P>), dim3(n, nrhs), dim3(256), 0, s,
+                       pl.dn_box.p + (int64_t)a0 * 85, bl, dpw, L, pl.nbox);
   }
 }
 

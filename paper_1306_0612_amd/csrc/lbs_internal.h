@@ -92,10 +92,18 @@ struct DevPlan {
   DBuf<int32_t> leaf_t, leaf_s, m2l_box;     // work lists
   int n_x = 0;
   DBuf<int32_t> x_box;                       // boxes with an X list
-  std::vector<int32_t> m2m_lptr, l2l_lptr;   // per-level ranges (host)
-  DBuf<int32_t> m2m_par;                     // parents with sources
-  DBuf<int4> m2m_kids;                       // (child << 2 | quadrant) x 4
-  DBuf<int32_t> l2l_box, l2l_pq;             // boxes with targets, level>=3
+  // Upward (M2M) and downward (L2L) passes, three levels per launch: one
+  // work-group per root box holding its subtree as a 4-ary heap (slot 0 the
+  // root, 4 s + 1 + q the child in quadrant q of slot s; -1 = absent).
+  // Upward roots: boxes with sources and children at levels 2, 5, 8, ...;
+  // slots 0..20 (box, bit s of up_mask set when slot s has children) and,
+  // for the grandchildren, their children by quadrant (box or -1).
+  // Downward roots: boxes with targets and children at the same levels;
+  // slots 0..84 (boxes with targets).  Launch order: up_gptr bottom-up,
+  // dn_gptr top-down (host ranges of roots).
+  std::vector<int32_t> up_gptr, dn_gptr;
+  DBuf<int32_t> up_box, up_mask, dn_box;
+  DBuf<int4> up_deep;
   // points in tree order
   DBuf<double> sx, sy, tx, ty;
   DBuf<float> sxh, sxl, syh, syl, txh, txl, tyh, tyl;  // FP32 hi/lo
@@ -106,8 +114,10 @@ struct DevPlan {
 // Translation tables for expansions of P terms (see fmm.hip).
 struct Tables {
   int P = 0;
-  DBuf<double> m2m64, l2l64, h64, itp64;  // complex pairs interleaved
-  DBuf<float> m2m32, l2l32, h32, itp32;
+  // M2M / L2L binomial weights (P x P, real) and powers of the quadrant
+  // offsets (4 x P, complex); M2L matrix H and inverse powers (itp)
+  DBuf<double> bm64, bl64, dp64, h64, itp64;
+  DBuf<float> bm32, bl32, dp32, h32, itp32;
 };
 // Per-stage GPU timing with HIP events recorded on the launch stream.
 enum Stage {
