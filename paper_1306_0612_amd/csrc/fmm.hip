@@ -158,8 +158,25 @@ __device__ __forceinline__ int64_t locate(int q, int cnt, const int64_t *rs,
   return rs[lo] + (q - pre[lo]);
 }
 
+// Lanes g P + l (g < 64 / P) hold partial sums of coefficient l; returns
+// their total in lane l.  Every lane takes part in the shuffles.
+template <typename T, int P>
+__device__ __forceinline__ cx<T> group_sum(cx<T> acc, int lane) {
+  constexpr int G = 64 / P;
+  const int l = lane % P;
+  cx<T> tot = acc;
+#pragma unroll
+  for (int gg = 1; gg < G; ++gg) {
+    const int src = l + gg * P;
+    const T x = __shfl(acc.x, src, 64), y = __shfl(acc.y, src, 64);
+    tot = tot + cx<T>{x, y};
+  }
+  return tot;
+}
+
 // Leaf multipoles, one 64-lane block per leaf: lane j forms the powers
-// p_j w_j^k of its source in LDS, lane k sums column k.
+// p_j w_j^k of its source in LDS; the 64 / P lane groups sum every
+// (64 / P)-th row of column k, then the groups are added.
 template <typename T, int P>
 __global__ void __launch_bounds__(64)
     k_p2m(const int32_t *__restrict__ leaves, const int64_t *__restrict__ s0,
@@ -168,17 +185,20 @@ __global__ void __launch_bounds__(64)
           const double *__restrict__ sx, const double *__restrict__ sy,
           const cx<T> *__restrict__ p, int64_t ns, cx<T> *__restrict__ M,
           int nbox) {
-  __shared__ cx<T> buf[64][P + 1];
+  constexpr int TS = sizeof(T) == 8 ? 32 : 64;  // sources per LDS tile
+  __shared__ cx<T> buf[TS][P + 1];
   const int b = leaves[blockIdx.x];
   const int r = blockIdx.y;
   const int lane = threadIdx.x;
   const double c_x = cxv[b], c_y = cyv[b], ir = 1.0 / rad[b];
   const cx<T> *pr = p + (int64_t)r * ns;
+  constexpr int G = 64 / P;
+  const int g = lane / P, l = lane % P;
   cx<T> acc{T(0), T(0)};
   const int64_t e0 = s0[b], e1 = s1[b];
-  for (int64_t jb = e0; jb < e1; jb += 64) {
+  for (int64_t jb = e0; jb < e1; jb += TS) {
     const int64_t j = jb + lane;
-    const int n = (int)min<int64_t>(64, e1 - jb);
+    const int n = (int)min<int64_t>(TS, e1 - jb);
     if (lane < n) {
       cx<T> w{T((sx[j] - c_x) * ir), T((sy[j] - c_y) * ir)};
       cx<T> pw = pr[j];
@@ -189,10 +209,11 @@ __global__ void __launch_bounds__(64)
       }
     }
     __syncthreads();
-    if (lane < P)
-      for (int q = 0; q < n; ++q) acc = acc + buf[q][lane];
+    if (g < G)
+      for (int q = g; q < n; q += G) acc = acc + buf[q][l];
     __syncthreads();
   }
+  acc = group_sum<T, P>(acc, lane);
   if (lane < P) M[((int64_t)r * nbox + b) * P + lane] = T(ir) * acc;
 }
 
@@ -509,7 +530,8 @@ __global__ void __launch_bounds__(256)
 
 // P2L over the X list of one box per 64-lane block: the sources of all its
 // X leaves are gathered; lane q forms t_q (r/u_q)^l, t_q = -p_q / u_q
-// (u_q = z_q - c) in LDS, lane l sums column l; added to the M2L result.
+// (u_q = z_q - c) in LDS, lane groups sum column l as in P2M; added to the
+// M2L result.
 template <typename T, int P>
 __global__ void __launch_bounds__(64)
     k_p2l(const int32_t *__restrict__ boxes, const int32_t *__restrict__ x_ptr,
@@ -519,7 +541,8 @@ __global__ void __launch_bounds__(64)
           const double *__restrict__ sx, const double *__restrict__ sy,
           const cx<T> *__restrict__ p, int64_t ns, cx<T> *__restrict__ L,
           int nbox) {
-  __shared__ cx<T> buf[64][P + 1];
+  constexpr int TS = sizeof(T) == 8 ? 32 : 64;  // sources per LDS tile
+  __shared__ cx<T> buf[TS][P + 1];
   __shared__ int64_t rs[64];
   __shared__ int pre[65];
   const int b = boxes[blockIdx.x];
@@ -528,14 +551,16 @@ __global__ void __launch_bounds__(64)
   const double cxb = cxv[b], cyb = cyv[b];
   const T rb = T(rad[b]);
   const cx<T> *pr = p + (int64_t)r * ns;
+  constexpr int G = 64 / P;
+  const int g = lane / P, l = lane % P;
   cx<T> acc{T(0), T(0)};
   const int xb = x_ptr[b], xe = x_ptr[b + 1];
   for (int eb = xb; eb < xe; eb += 64) {
     const int cnt = min(64, xe - eb);
     const int total = gather_ranges(x_src, eb, cnt, s0, s1, rs, pre);
-    for (int q0 = 0; q0 < total; q0 += 64) {
+    for (int q0 = 0; q0 < total; q0 += TS) {
       const int q = q0 + lane;
-      if (q < total) {
+      if (lane < TS && q < total) {
         const int64_t j = locate(q, cnt, rs, pre);
         const cx<T> iu = cinv(cx<T>{T(sx[j] - cxb), T(sy[j] - cyb)});
         const cx<T> rho = rb * iu;
@@ -548,12 +573,13 @@ __global__ void __launch_bounds__(64)
         }
       }
       __syncthreads();
-      const int n = min(64, total - q0);
-      if (lane < P)
-        for (int qq = 0; qq < n; ++qq) acc = acc + buf[qq][lane];
+      const int n = min(TS, total - q0);
+      if (g < G)
+        for (int qq = g; qq < n; qq += G) acc = acc + buf[qq][l];
       __syncthreads();
     }
   }
+  acc = group_sum<T, P>(acc, lane);
   if (lane < P) {
     cx<T> *dst = L + ((int64_t)r * nbox + b) * P + lane;
     *dst = *dst + acc;
@@ -765,9 +791,12 @@ __global__ void __launch_bounds__(64)
             const float2 p2 = sp[q];
             const float dx = (zxh - s4.x) + (zxl - s4.y);
             const float dy = (zyh - s4.z) + (zyl - s4.w);
-            const float d2 = dx * dx + dy * dy;
-            const float inv = d2 > 0.f ? __builtin_amdgcn_rcpf(d2) : 0.f;
-            field += (p2.x * dx + p2.y * dy) * inv;
+            // |d|^2 + 1e-30: a target's own source (d = 0) contributes
+            // 0 * rcp(1e-30) = 0; the bias leaves any |d|^2 above 2e-23
+            // (node spacings above 5e-12) unchanged in FP32
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
+            const float inv = __builtin_amdgcn_rcpf(d2);
+            field += fmaf(p2.x, dx, p2.y * dy) * inv;
           }
         }
         __syncthreads();
