@@ -259,6 +259,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="default FMM schedule instead of lbs_autotune's")
     ap.add_argument("--batch-geoms", type=int, default=64)
     ap.add_argument("--batch-rhs", type=int, default=16)
     ap.add_argument("--cpu-rows", type=int, default=512)
@@ -293,7 +295,17 @@ def main():
     log("generating islands", args.workload)
     islands = synth.config_islands(args.workload)
     t0 = time.perf_counter()
-    sol = lbs.Solver(islands)
+    tuned = None
+    opts = lbs.default_options()
+    if not args.no_tune:
+        tt = time.perf_counter()
+        opts, entries = lbs.autotune(islands, tol_mixed=1e-6, tol_fp64=1e-10)
+        tuned = {"leaf_max": opts.leaf_max, "p32": opts.p32, "p64": opts.p64,
+                 "tune_s": time.perf_counter() - tt,
+                 "settings_timed": len(entries)}
+        log("autotune", tuned)
+        t0 = time.perf_counter()
+    sol = lbs.Solver(islands, options=opts)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     N, M = sol.n_nodes, sol.n_islands
@@ -316,9 +328,11 @@ def main():
     rl32 = stage_roofline(tree, N, P32, st32, False)
     rl64 = stage_roofline(tree, N, P64, st64, True)
     dom = max(st32, key=st32.get)
-    kname = {"leaf": "k_leaf32<16>", "m2l": "k_m2l_mfma16",
-             "p2l": "k_p2l<float,16>", "upward": "k_p2m/k_m2m<float,16>",
-             "l2l": "k_l2l<float,16>"}.get(dom, dom)
+    kname = {"leaf": "k_leaf32<%d>" % P32,
+             "m2l": "k_m2l_mfma16" if P32 == 16 else "k_m2l<float,%d>" % P32,
+             "p2l": "k_p2l<float,%d>" % P32,
+             "upward": "k_p2m/k_m2m3<float,%d>" % P32,
+             "l2l": "k_l2l3<float,%d>" % P32}.get(dom, dom)
     r = rl32.get(dom, {})
     roofline = {"bound": r.get("bound", "alu"), "kernel": kname,
                 "achieved": r.get("achieved"),
@@ -341,7 +355,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2000 star islands x 512 nodes (1,024,000 "
                                "nodes), (I+K) sigma by FMM, FP32 far and "
-                               "near field p=16, FP64 assembly",
+                               "near field, FP64 assembly",
                    "islands": M, "nodes": N, "p32": P32, "p64": P64,
                    "leaf_max": sol.options.leaf_max},
         "fp64_matvecs_per_s": k64 / dt64,
@@ -351,6 +365,7 @@ def main():
         "stages_ms_mixed": st32,
         "stages_ms_fp64": st64,
         "tree": tree,
+        "tuned": tuned,
         "roofline": roofline,
         "roofline_stages_mixed": rl32,
         "roofline_stages_fp64": rl64,
@@ -365,7 +380,13 @@ def main():
         exact = synth.exact_harmonic(tg, islands.center, coeffs)
         tgd = torch.tensor(tg, dtype=torch.float64, device=dev)
         for prec in ("mixed", "fp64"):
+            # the first solve captures the GMRES iterations as HIP graphs;
+            # the second, timed one replays them
             torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sol.solve(g, tol=1e-10, precision=prec, check=False)
+            torch.cuda.synchronize()
+            out["solve_s_cold_" + prec] = time.perf_counter() - t0
             t0 = time.perf_counter()
             s, a, info = sol.solve(g, tol=1e-10, precision=prec, check=False)
             torch.cuda.synchronize()

@@ -47,21 +47,26 @@ static void cpow_host(double x, double y, int n, double &ox, double &oy) {
 
 void build_tables(Tables &t, int P, hipStream_t s) {
   t.P = P;
-  // M2M and L2L as real binomial weights times powers of the quadrant
-  // offset delta = (+-1, +-1):
-  //   M2M[q][lo][k] = C(lo, k) 2^-(lo+1) delta^(lo-k)   (k <= lo)
-  //   L2L[q][m][l]  = C(l, m) 2^-l delta^(l-m)          (l >= m)
-  // Binomials up to C(47, 23) and the components of delta^n (0 or a power
-  // of two) are exact, so the products equal the full tables bit for bit.
-  std::vector<double> bm(P * P, 0.0), bl(P * P, 0.0), dpw(4 * P * 2, 0.0);
-  for (int lo = 0; lo < P; ++lo)
-    for (int k = 0; k <= lo; ++k) {
-      bm[lo * P + k] = binom(lo, k) * std::ldexp(1.0, -(lo + 1));
-      bl[k * P + lo] = binom(lo, k) * std::ldexp(1.0, -lo);
-    }
+  // M2M and L2L factorized as scale x Pascal x scale (quadrant offset
+  // delta = (+-1, +-1), |delta|^2 = 2):
+  //   M2M: A_lo = 1/2 (delta/2)^lo sum_{k <= lo} C(lo, k) (conj(delta)/2)^k a_k
+  //   L2L: b'_m = (conj(delta)/2)^m sum_{l >= m} C(l, m) (delta/2)^l b_l
+  // Tables: C (P x P, zero above the diagonal), pre[q][n] =
+  // (conj(delta_q)/2)^n and post[q][n] = (delta_q/2)^n.
+  std::vector<double> bc(P * P, 0.0), pre(4 * P * 2), post(4 * P * 2);
+  for (int n = 0; n < P; ++n)
+    for (int k = 0; k <= n; ++k) bc[n * P + k] = binom(n, k);
   for (int q = 0; q < 4; ++q) {
     const double dx = (q & 1) ? 1.0 : -1.0, dy = (q & 2) ? 1.0 : -1.0;
-    for (int n = 0; n < P; ++n) cpow_host(dx, dy, n, dpw[2 * (q * P + n)], dpw[2 * (q * P + n) + 1]);
+    for (int n = 0; n < P; ++n) {
+      double ax, ay, bx, by;
+      cpow_host(0.5 * dx, -0.5 * dy, n, ax, ay);
+      cpow_host(0.5 * dx, 0.5 * dy, n, bx, by);
+      pre[2 * (q * P + n)] = ax;
+      pre[2 * (q * P + n) + 1] = ay;
+      post[2 * (q * P + n)] = bx;
+      post[2 * (q * P + n) + 1] = by;
+    }
   }
   std::vector<double> h(P * P);
   for (int l = 0; l < P; ++l)
@@ -86,14 +91,14 @@ void build_tables(Tables &t, int P, hipStream_t s) {
   auto to32 = [](const std::vector<double> &v) {
     return std::vector<float>(v.begin(), v.end());
   };
-  t.bm64.upload(bm, s);
-  t.bl64.upload(bl, s);
-  t.dp64.upload(dpw, s);
+  t.bc64.upload(bc, s);
+  t.pre64.upload(pre, s);
+  t.post64.upload(post, s);
   t.h64.upload(h, s);
   t.itp64.upload(itp, s);
-  t.bm32.upload(to32(bm), s);
-  t.bl32.upload(to32(bl), s);
-  t.dp32.upload(to32(dpw), s);
+  t.bc32.upload(to32(bc), s);
+  t.pre32.upload(to32(pre), s);
+  t.post32.upload(to32(post), s);
   t.h32.upload(to32(h), s);
   t.itp32.upload(to32(itp), s);
   LBS_HIP(hipStreamSynchronize(s));
@@ -219,29 +224,29 @@ __global__ void __launch_bounds__(64)
 
 // Upward pass over three levels per launch: one work-group per root, whose
 // subtree is the heap described with DevPlan.  All operands are first
-// staged in LDS with every load in flight at once (the binomial weights,
-// the powers of delta, the multipoles of the grandchildren's children and
-// of the childless slots); then step 1 forms the multipoles of the
-// grandchildren that have children, step 2 those of the children, step 3
-// the root's, reading only LDS.  M2M of a child in quadrant q:
-//   A_lo = sum_{k <= lo} C(lo, k) 2^-(lo+1) delta_q^(lo-k) a_k.
+// staged in LDS with every load in flight at once (the multipoles of the
+// grandchildren's children and of the childless slots), each pre-scaled by
+// (conj(delta_q)/2)^k for the quadrant q it occupies under its parent; then
+// step 1 forms the multipoles of the grandchildren that have children,
+// step 2 those of the children, step 3 the root's, from LDS only:
+//   A_lo = sum_q 1/2 (delta_q/2)^lo sum_{k <= lo} C(lo, k) a~_{q,k}
+// (C is zero above the diagonal, so the fixed-length sums add exact zeros).
 template <typename T, int P>
 __global__ void __launch_bounds__(256)
     k_m2m3(const int32_t *__restrict__ box, const int32_t *__restrict__ mask,
-           const int4 *__restrict__ deep, const T *__restrict__ Bm,
-           const cx<T> *__restrict__ Dp, cx<T> *__restrict__ M, int nbox) {
+           const int4 *__restrict__ deep, const T *__restrict__ Cb,
+           const cx<T> *__restrict__ Pre, const cx<T> *__restrict__ Post,
+           cx<T> *__restrict__ M, int nbox) {
   constexpr int NT = 256, NE = 84 * P, IT = (NE + NT - 1) / NT;
-  __shared__ T sB[P * P];
-  __shared__ cx<T> sD[4 * P];
+  __shared__ T sC[P * P];
+  __shared__ cx<T> sPre[4 * P], sPost[4 * P];
   __shared__ cx<T> sK[64 * P];  // children of grandchild j, quadrant q: 4 j + q
-  __shared__ cx<T> sm[21 * P];  // expansions of the heap slots
+  __shared__ cx<T> sm[21 * P];  // pre-scaled expansions of the heap slots
   const int root = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
   const int32_t *bx = box + (int64_t)root * 21;
   const int msk = mask[root];
   const int4 *dp = deep + (int64_t)root * 16;
   cx<T> *Mr = M + (int64_t)r * nbox * P;
-  for (int i = tid; i < P * P; i += NT) sB[i] = Bm[i];
-  for (int i = tid; i < 4 * P; i += NT) sD[i] = Dp[i];
   cx<T> v[IT];
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
@@ -260,35 +265,44 @@ __global__ void __launch_bounds__(256)
       if (b >= 0 && !((msk >> slot) & 1)) v[i] = Mr[(int64_t)b * P + k];
     }
   }
+  for (int i = tid; i < P * P; i += NT) sC[i] = Cb[i];
+  for (int i = tid; i < 4 * P; i += NT) {
+    sPre[i] = Pre[i];
+    sPost[i] = Post[i];
+  }
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const int e = tid + i * NT;
-    if (e < 64 * P) sK[e] = v[i];
-    else if (e < NE) sm[P + (e - 64 * P)] = v[i];
+    if (e < 64 * P) {
+      sK[e] = v[i] * sPre[((e / P) & 3) * P + e % P];
+    } else if (e < NE) {
+      const int e2 = e - 64 * P, slot = 1 + e2 / P;
+      sm[P + e2] = v[i] * sPre[((slot - 1) & 3) * P + e2 % P];
+    }
   }
   __syncthreads();
-  // sum over the four quadrants of M2M(src[q]) at coefficient lo; the
-  // weights are exactly 0 for k > lo, so the fixed-length loop adds exact
-  // zeros there and its LDS reads can all be issued ahead
-  auto m2m = [&](const cx<T> *src, int stride, int present, int lo) {
+  // A_lo from the four pre-scaled children at src + q * P
+  auto m2m = [&](const cx<T> *src, int present, int lo) {
     cx<T> acc{T(0), T(0)};
-    const T *bw = sB + lo * P;
+    const T *c = sC + lo * P;
     for (int q = 0; q < 4; ++q) {
       if (!((present >> q) & 1)) continue;
-      const cx<T> *a = src + q * stride;
-      const cx<T> *dq = sD + q * P;
+      const cx<T> *a = src + q * P;
+      cx<T> sum{T(0), T(0)};
 #pragma unroll
-      for (int k = 0; k < P; ++k) acc = acc + (bw[k] * dq[max(lo - k, 0)]) * a[k];
+      for (int k = 0; k < P; ++k) sum = sum + c[k] * a[k];
+      acc = acc + sPost[q * P + lo] * sum;
     }
-    return acc;
+    return T(0.5) * acc;
   };
   for (int it = tid; it < 16 * P; it += NT) {
     const int j = it / P, lo = it % P, slot = 5 + j;
     if (!((msk >> slot) & 1)) continue;
     const int4 kd = dp[j];
     const int present = (kd.x >= 0) | ((kd.y >= 0) << 1) | ((kd.z >= 0) << 2) | ((kd.w >= 0) << 3);
-    const cx<T> a = m2m(sK + 4 * j * P, P, present, lo);
-    sm[slot * P + lo] = a;
+    const cx<T> a = m2m(sK + 4 * j * P, present, lo);
+    sm[slot * P + lo] = a * sPre[((slot - 1) & 3) * P + lo];
     Mr[(int64_t)bx[slot] * P + lo] = a;
   }
   __syncthreads();
@@ -298,47 +312,49 @@ __global__ void __launch_bounds__(256)
     const int g0 = 4 * slot + 1;
     const int present = (bx[g0] >= 0) | ((bx[g0 + 1] >= 0) << 1) |
                         ((bx[g0 + 2] >= 0) << 2) | ((bx[g0 + 3] >= 0) << 3);
-    const cx<T> a = m2m(sm + g0 * P, P, present, lo);
-    sm[slot * P + lo] = a;
+    const cx<T> a = m2m(sm + g0 * P, present, lo);
+    sm[slot * P + lo] = a * sPre[j * P + lo];
     Mr[(int64_t)bx[slot] * P + lo] = a;
   }
   __syncthreads();
   for (int lo = tid; lo < P; lo += NT) {
     const int present = (bx[1] >= 0) | ((bx[2] >= 0) << 1) | ((bx[3] >= 0) << 2) |
                         ((bx[4] >= 0) << 3);
-    Mr[(int64_t)bx[0] * P + lo] = m2m(sm + P, P, present, lo);
+    Mr[(int64_t)bx[0] * P + lo] = m2m(sm + P, present, lo);
   }
 }
 
 // Downward pass over three levels per launch: one work-group per root (its
-// local expansion complete).  The expansions of the root, children and
-// grandchildren (their own parts, from M2L and P2L) are staged in LDS, and
-// those of the 64 great-grandchild slots in the registers of the threads
-// that finish them, with every load in flight at once; then the translated
-// parent expansion is added level by level.  L2L into a child in quadrant q:
-//   b'_m = sum_{l >= m} C(l, m) 2^-l delta_q^(l-m) b_l
-// (weights exactly 0 for l < m, as in the fixed-length loop below).
+// local expansion complete).  The own expansions (from M2L and P2L) of the
+// children and grandchildren are staged in LDS and those of the 64
+// great-grandchild slots in the registers of the threads that finish them,
+// with every load in flight at once.  Level by level, each finished parent
+// expansion b is written in four versions (delta_q/2)^l b_l, one per child
+// quadrant q, and a child's coefficient m takes
+//   b'_m = own_m + (conj(delta_q)/2)^m sum_{l >= m} C(l, m) c_{q,l}
+// (C zero below the diagonal: the fixed-length sums add exact zeros).
 template <typename T, int P>
 __global__ void __launch_bounds__(256)
-    k_l2l3(const int32_t *__restrict__ box, const T *__restrict__ Bl,
-           const cx<T> *__restrict__ Dp, cx<T> *__restrict__ L, int nbox) {
-  constexpr int NT = 256, N1 = 21 * P, I1 = (N1 + NT - 1) / NT;
+    k_l2l3(const int32_t *__restrict__ box, const T *__restrict__ Cb,
+           const cx<T> *__restrict__ Pre, const cx<T> *__restrict__ Post,
+           cx<T> *__restrict__ L, int nbox) {
+  constexpr int NT = 256, N1 = 20 * P, I1 = (N1 + NT - 1) / NT;
   constexpr int N3 = 64 * P, I3 = (N3 + NT - 1) / NT;
-  __shared__ T sB[P * P];
-  __shared__ cx<T> sD[4 * P];
-  __shared__ cx<T> sl[21 * P];
+  __shared__ T sC[P * P];
+  __shared__ cx<T> sPre[4 * P], sPost[4 * P];
+  __shared__ cx<T> sl[20 * P];  // own expansions of slots 1..20
+  __shared__ cx<T> sp[64 * P];  // scaled parent versions: (parent, q)
   const int root = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
   const int32_t *bx = box + (int64_t)root * 85;
   cx<T> *Lr = L + (int64_t)r * nbox * P;
-  for (int i = tid; i < P * P; i += NT) sB[i] = Bl[i];
-  for (int i = tid; i < 4 * P; i += NT) sD[i] = Dp[i];
-  cx<T> v[I1], w[I3];
+  cx<T> v[I1], w[I3], b0{T(0), T(0)};
+  if (tid < P) b0 = Lr[(int64_t)bx[0] * P + tid];
 #pragma unroll
   for (int i = 0; i < I1; ++i) {
     const int e = tid + i * NT;
     v[i] = cx<T>{T(0), T(0)};
     if (e < N1) {
-      const int b = bx[e / P];
+      const int b = bx[1 + e / P];
       if (b >= 0) v[i] = Lr[(int64_t)b * P + e % P];
     }
   }
@@ -351,44 +367,67 @@ __global__ void __launch_bounds__(256)
       if (b >= 0) w[i] = Lr[(int64_t)b * P + e % P];
     }
   }
+  for (int i = tid; i < P * P; i += NT) sC[i] = Cb[i];
+  for (int i = tid; i < 4 * P; i += NT) {
+    sPre[i] = Pre[i];
+    sPost[i] = Post[i];
+  }
 #pragma unroll
   for (int i = 0; i < I1; ++i) {
     const int e = tid + i * NT;
     if (e < N1) sl[e] = v[i];
   }
   __syncthreads();
-  auto l2l = [&](int s, int m) {
-    const int ps = (s - 1) >> 2, q = (s - 1) & 3;
-    const cx<T> *bp = sl + ps * P;
-    const cx<T> *dq = sD + q * P;
-    const T *bw = sB + m * P;
-    cx<T> acc{T(0), T(0)};
+  // root: four scaled versions
+  if (tid < P)
+    for (int q = 0; q < 4; ++q) sp[q * P + tid] = sPost[q * P + tid] * b0;
+  __syncthreads();
+  // translated parent expansion at coefficient m of a child in quadrant q
+  // whose parent's scaled versions start at sp + pi * 4 P
+  auto l2l = [&](int pi, int q, int m) {
+    const cx<T> *c = sp + (pi * 4 + q) * P;
+    cx<T> sum{T(0), T(0)};
 #pragma unroll
-    for (int l = 0; l < P; ++l) acc = acc + (bw[l] * dq[max(l - m, 0)]) * bp[l];
-    return acc;
+    for (int l = 0; l < P; ++l) sum = sum + sC[l * P + m] * c[l];
+    return sPre[q * P + m] * sum;
   };
-  // children (slots 1..4), then grandchildren (5..20): results kept in LDS
+  // children (slots 1..4) and grandchildren (5..20); a parent's versions
+  // sit at its index among its own level's slots
   int first = 1, count = 4;
   for (int d = 1; d <= 2; ++d) {
-    for (int it = tid; it < count * P; it += NT) {
+    cx<T> res[(16 * P + NT - 1) / NT];
+    int nres = 0;
+    for (int it = tid; it < count * P; it += NT, ++nres) {
       const int s = first + it / P, m = it % P, b = bx[s];
+      res[nres] = cx<T>{T(0), T(0)};
       if (b < 0) continue;
-      const cx<T> val = sl[s * P + m] + l2l(s, m);
-      sl[s * P + m] = val;
+      const int ps = (s - 1) >> 2, q = (s - 1) & 3;
+      // parents of this level start at slot (first - 1) / 4 (0, 1)
+      const cx<T> val = sl[(s - 1) * P + m] + l2l(ps - (first - 1) / 4, q, m);
       Lr[(int64_t)b * P + m] = val;
+      res[nres] = val;
+    }
+    __syncthreads();  // every read of sp for this level is done
+    nres = 0;
+    for (int it = tid; it < count * P; it += NT, ++nres) {
+      const int s = first + it / P, m = it % P;
+      if (bx[s] < 0) continue;
+      const int si = s - first;  // index of s among this level's slots
+      for (int q = 0; q < 4; ++q) sp[(si * 4 + q) * P + m] = sPost[q * P + m] * res[nres];
     }
     __syncthreads();
     first += count;
     count *= 4;
   }
-  // great-grandchildren (21..84): own parts from registers
+  // great-grandchildren (21..84): parents are the grandchildren (from 5)
 #pragma unroll
   for (int i = 0; i < I3; ++i) {
     const int e = tid + i * NT;
     if (e >= N3) continue;
     const int s = 21 + e / P, m = e % P, b = bx[s];
     if (b < 0) continue;
-    Lr[(int64_t)b * P + m] = w[i] + l2l(s, m);
+    const int ps = (s - 1) >> 2, q = (s - 1) & 3;
+    Lr[(int64_t)b * P + m] = w[i] + l2l(ps - 5, q, m);
   }
 }
 
@@ -822,20 +861,20 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
                       const cx<T> *p, cx<T> *M, cx<T> *L, int nrhs,
                       hipStream_t s) {
   StageTimer *tm = ws.timer;
-  const cx<T> *itp, *dpw;
-  const T *H, *bm, *bl;
+  const cx<T> *itp, *pre, *post;
+  const T *H, *bc;
   if constexpr (sizeof(T) == 8) {
     itp = (const cx<T> *)tb.itp64.p;
     H = (const T *)tb.h64.p;
-    bm = (const T *)tb.bm64.p;
-    bl = (const T *)tb.bl64.p;
-    dpw = (const cx<T> *)tb.dp64.p;
+    bc = (const T *)tb.bc64.p;
+    pre = (const cx<T> *)tb.pre64.p;
+    post = (const cx<T> *)tb.post64.p;
   } else {
     itp = (const cx<T> *)tb.itp32.p;
     H = (const T *)tb.h32.p;
-    bm = (const T *)tb.bm32.p;
-    bl = (const T *)tb.bl32.p;
-    dpw = (const cx<T> *)tb.dp32.p;
+    bc = (const T *)tb.bc32.p;
+    pre = (const cx<T> *)tb.pre32.p;
+    post = (const cx<T> *)tb.post32.p;
   }
   {
     TimerScope ts(tm, ST_UPWARD, s);
@@ -848,7 +887,8 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
       if (n <= 0) continue;
       hipLaunchKernelGGL((k_m2m3<T, P>), dim3(n, nrhs), dim3(256), 0, s,
                          pl.up_box.p + (int64_t)a0 * 21, pl.up_mask.p + a0,
-                         pl.up_deep.p + (int64_t)a0 * 16, bm, dpw, M, pl.nbox);
+                         pl.up_deep.p + (int64_t)a0 * 16, bc, pre, post, M,
+                         pl.nbox);
     }
   }
   if (pl.n_m2l > 0) {
@@ -876,7 +916,8 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
     const int a0 = pl.dn_gptr[g], n = pl.dn_gptr[g + 1] - a0;
     if (n <= 0) continue;
     hipLaunchKernelGGL((k_l2l3<T, P>), dim3(n, nrhs), dim3(256), 0, s,
-                       pl.dn_box.p + (int64_t)a0 * 85, bl, dpw, L, pl.nbox);
+                       pl.dn_box.p + (int64_t)a0 * 85, bc, pre, post, L,
+                       pl.nbox);
   }
 }
 

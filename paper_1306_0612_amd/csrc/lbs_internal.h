@@ -114,10 +114,10 @@ struct DevPlan {
 // Translation tables for expansions of P terms (see fmm.hip).
 struct Tables {
   int P = 0;
-  // M2M / L2L binomial weights (P x P, real) and powers of the quadrant
-  // offsets (4 x P, complex); M2L matrix H and inverse powers (itp)
-  DBuf<double> bm64, bl64, dp64, h64, itp64;
-  DBuf<float> bm32, bl32, dp32, h32, itp32;
+  // M2M / L2L: binomials (P x P, real) and the pre/post scale powers
+  // (4 x P, complex); M2L matrix H and inverse powers (itp)
+  DBuf<double> bc64, pre64, post64, h64, itp64;
+  DBuf<float> bc32, pre32, post32, h32, itp32;
 };
 // Per-stage GPU timing with HIP events recorded on the launch stream.
 enum Stage {
