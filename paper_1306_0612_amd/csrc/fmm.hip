@@ -508,9 +508,13 @@ __global__ void __launch_bounds__(256)
                  const cx<float> *__restrict__ M, cx<float> *__restrict__ L,
                  int nbox) {
   constexpr int P = 16, NP = 2 * P + 1;
+  // the 49 x (2P + 1) table of tau^-n, read by every pair, in LDS
+  __shared__ cx<float> sItp[49 * NP];
+  for (int i = threadIdx.x; i < 49 * NP; i += 256) sItp[i] = itp[i];
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wv >= nb) return;  // uniform per wave
+  if (wv >= nb) return;  // uniform per wave, after the block's barrier
   const int r = blockIdx.y;
   const int col = lane & 15, kq = lane >> 4;
   const int vslot = col >> 1, part = col & 1;
@@ -530,7 +534,7 @@ __global__ void __launch_bounds__(256)
       code = v_code[vb + v];
     }
     const cx<float> *ms = Mr + (int64_t)src * P;
-    const cx<float> *ip = itp + code * NP;
+    const cx<float> *ip = sItp + code * NP;
     v4f d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
