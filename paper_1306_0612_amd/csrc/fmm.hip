@@ -752,7 +752,7 @@ __global__ void __launch_bounds__(64)
 // FP32 variant: near-field differences on hi/lo coordinate pairs,
 // d = (hi_i - hi_j) + (lo_i - lo_j), arithmetic in FP32.
 template <int P>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64, 8)
     k_leaf32(const int32_t *__restrict__ leaves,
              const int32_t *__restrict__ lev,
              const int64_t *__restrict__ t0, const int64_t *__restrict__ t1,
@@ -777,6 +777,7 @@ __global__ void __launch_bounds__(64)
   __shared__ float2 sp[kStage];
   __shared__ int64_t rs[64];
   __shared__ int pre[65];
+  constexpr int NC = 2;  // sub-chunks of <= 32 targets per pass over U
   const int b = leaves[blockIdx.x];
   const int r = blockIdx.y;
   const int lane = threadIdx.x;
@@ -784,77 +785,123 @@ __global__ void __launch_bounds__(64)
   const cx<float> *Mr = M + (int64_t)r * nbox * P;
   const cx<float> *Lr = L + (int64_t)r * nbox * P;
   const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
-  const int tp = ntb <= 32 ? pow2_at_least((int)ntb) : 64;
-  const int S = 64 / tp, tl = lane % tp, sl = lane / tp;
   const int ub = u_ptr[b], ue = u_ptr[b + 1];
   const int wb = w_ptr[b], we = w_ptr[b + 1];
   const bool has_local = lev[b] >= 2;
-  for (int64_t tc = 0; tc < ntb; tc += tp) {
-    const int64_t i = tb0 + tc + tl;
-    const bool act = tc + tl < ntb;
-    const double zx = act ? tx[i] : 0.0, zy = act ? ty[i] : 0.0;
-    const float zxh = act ? txh[i] : 0.f, zxl = act ? txl[i] : 0.f;
-    const float zyh = act ? tyh[i] : 0.f, zyl = act ? tyl[i] : 0.f;
-    float field = 0.f;
-    if (act) {
-      if (sl == 0 && has_local) {
-        const double ir = 1.0 / rad[b];
-        const cx<float> w{float((zx - cxv[b]) * ir), float((zy - cyv[b]) * ir)};
+  const double ir_b = 1.0 / rad[b];
+  for (int64_t tc0 = 0; tc0 < ntb; tc0 += 32 * NC) {
+    const int nt = (int)min<int64_t>(32 * NC, ntb - tc0);
+    const int nch = (nt + 31) / 32;
+    // sub-chunk c: targets [32 c, min(32 c + 32, nt)) on tp_c lanes times
+    // S_c = 64 / tp_c source slices, tp_c = min(32, next power of two)
+    int S[NC], sl[NC];
+    bool act[NC];
+    int ti[NC];  // target offset within the leaf
+    float zxh[NC], zxl[NC], zyh[NC], zyl[NC], fld[NC];
+    int Smax = 1;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      S[c] = 64;
+      sl[c] = 0;
+      act[c] = false;
+      ti[c] = 0;
+      zxh[c] = zxl[c] = zyh[c] = zyl[c] = fld[c] = 0.f;
+      if (c >= nch) continue;  // uniform
+      const int rem = nt - 32 * c;
+      const int tp = rem >= 32 ? 32 : pow2_at_least(rem);
+      S[c] = 64 / tp;
+      Smax = max(Smax, S[c]);
+      const int tl = lane % tp;
+      sl[c] = lane / tp;
+      act[c] = 32 * c + tl < nt;
+      ti[c] = (int)tc0 + 32 * c + tl;
+      if (!act[c]) continue;
+      const int64_t i = tb0 + ti[c];
+      zxh[c] = txh[i];
+      zxl[c] = txl[i];
+      zyh[c] = tyh[i];
+      zyl[c] = tyl[i];
+      const double zx = tx[i], zy = ty[i];
+      float field = 0.f;
+      if (sl[c] == 0 && has_local) {
+        const cx<float> w{float((zx - cxv[b]) * ir_b), float((zy - cyv[b]) * ir_b)};
         const cx<float> *La = Lr + (int64_t)b * P;
         cx<float> acc = La[P - 1];
         for (int l = P - 2; l >= 0; --l) acc = acc * w + La[l];
         field += acc.x;
       }
-      for (int e = wb + sl; e < we; e += S) {
-        const int c = w_src[e];
-        const double dx = zx - cxv[c], dy = zy - cyv[c];
-        const double id = rad[c] / (dx * dx + dy * dy);
+      for (int e = wb + sl[c]; e < we; e += S[c]) {
+        const int cw = w_src[e];
+        const double dx = zx - cxv[cw], dy = zy - cyv[cw];
+        const double id = rad[cw] / (dx * dx + dy * dy);
         cx<float> rho{float(dx * id), float(-dy * id)};
-        const cx<float> *a = Mr + (int64_t)c * P;
+        const cx<float> *a = Mr + (int64_t)cw * P;
         cx<float> acc = a[P - 1];
         for (int k = P - 2; k >= 0; --k) acc = acc * rho + a[k];
         field += (acc * rho).x;
       }
+      fld[c] = field;
     }
     for (int eb = ub; eb < ue; eb += 64) {
       const int cnt = min(64, ue - eb);
       const int total = gather_ranges(u_src, eb, cnt, s0, s1, rs, pre);
       for (int q0 = 0; q0 < total; q0 += kStage) {
         const int take = min(kStage, total - q0);
-        for (int q = lane; q < take; q += 64) {
-          const int64_t j = locate(q0 + q, cnt, rs, pre);
-          sz[q] = make_float4(sxh[j], sxl[j], syh[j], syl[j]);
-          const cx<float> pj = pr[j];
-          sp[q] = make_float2(pj.x, pj.y);
+        // pad to a multiple of Smax (<= 64, divides kStage) with sources of
+        // zero strength at the origin: they add 0 * rcp(|z|^2 + 1e-30) = 0
+        const int tpad = (take + Smax - 1) / Smax * Smax;
+        for (int q = lane; q < tpad; q += 64) {
+          if (q < take) {
+            const int64_t j = locate(q0 + q, cnt, rs, pre);
+            sz[q] = make_float4(sxh[j], sxl[j], syh[j], syl[j]);
+            const cx<float> pj = pr[j];
+            sp[q] = make_float2(pj.x, pj.y);
+          } else {
+            sz[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            sp[q] = make_float2(0.f, 0.f);
+          }
         }
         __syncthreads();
-        if (act) {
-          for (int q = sl; q < take; q += S) {
-            const float4 s4 = sz[q];
-            const float2 p2 = sp[q];
-            const float dx = (zxh - s4.x) + (zxl - s4.y);
-            const float dy = (zyh - s4.z) + (zyl - s4.w);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          if (c >= nch) continue;  // uniform
+          const int Sc = S[c], niter = tpad / Sc;
+          const float ax = zxh[c], bx = zxl[c], ay = zyh[c], by = zyl[c];
+          float f = fld[c];
+          const float4 *zq = sz + sl[c];
+          const float2 *pq = sp + sl[c];
+#pragma unroll 4
+          for (int it = 0; it < niter; ++it) {
+            const float4 s4 = zq[it * Sc];
+            const float2 p2 = pq[it * Sc];
+            const float dx = (ax - s4.x) + (bx - s4.y);
+            const float dy = (ay - s4.z) + (by - s4.w);
             // |d|^2 + 1e-30: a target's own source (d = 0) contributes
             // 0 * rcp(1e-30) = 0; the bias leaves any |d|^2 above 2e-23
             // (node spacings above 5e-12) unchanged in FP32
             const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
-            const float inv = __builtin_amdgcn_rcpf(d2);
-            field += fmaf(p2.x, dx, p2.y * dy) * inv;
+            f += fmaf(p2.x, dx, p2.y * dy) * __builtin_amdgcn_rcpf(d2);
           }
+          fld[c] = f;
         }
         __syncthreads();
       }
     }
-    for (int o = tp; o < 64; o <<= 1) field += __shfl_xor(field, o, 64);
-    if (act && sl == 0) {
-      const int64_t api = tperm[i];
-      double val = scale * (double)field;
-      if (as.sigma) {
-        const double sg = as.sigma[(int64_t)r * as.ldx + api];
-        val += (as.ident + as.tau[api]) * sg +
-               as.gamma[r * as.G + (as.geo ? as.geo[api] : 0)];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (c >= nch) continue;  // uniform
+      float field = fld[c];
+      for (int o = 64 / S[c]; o < 64; o <<= 1) field += __shfl_xor(field, o, 64);
+      if (act[c] && sl[c] == 0) {
+        const int64_t api = tperm[tb0 + ti[c]];
+        double val = scale * (double)field;
+        if (as.sigma) {
+          const double sg = as.sigma[(int64_t)r * as.ldx + api];
+          val += (as.ident + as.tau[api]) * sg +
+                 as.gamma[r * as.G + (as.geo ? as.geo[api] : 0)];
+        }
+        out[(int64_t)r * ldy + api] = val;
       }
-      out[(int64_t)r * ldy + api] = val;
     }
   }
 }
