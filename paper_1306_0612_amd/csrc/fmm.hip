@@ -653,7 +653,7 @@ constexpr int kStage = 128;  // U-list sources staged in LDS per pass
 // sum over the gathered sources of its U list (self pair excluded by
 // d == 0), then the operator row assembly in API order.  FP64 version.
 template <int P>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64, 8)
     k_leaf64(const int32_t *__restrict__ leaves,
              const int32_t *__restrict__ lev,
              const int64_t *__restrict__ t0, const int64_t *__restrict__ t1,
@@ -676,6 +676,7 @@ __global__ void __launch_bounds__(64)
   __shared__ double2 sp[kStage];
   __shared__ int64_t rs[64];
   __shared__ int pre[65];
+  constexpr int NC = 2;  // sub-chunks of <= 32 targets per pass over U
   const int b = leaves[blockIdx.x];
   const int r = blockIdx.y;
   const int lane = threadIdx.x;
@@ -683,68 +684,117 @@ __global__ void __launch_bounds__(64)
   const cx<double> *Mr = M + (int64_t)r * nbox * P;
   const cx<double> *Lr = L + (int64_t)r * nbox * P;
   const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
-  const int tp = ntb <= 32 ? pow2_at_least((int)ntb) : 64;
-  const int S = 64 / tp, tl = lane % tp, sl = lane / tp;
   const int ub = u_ptr[b], ue = u_ptr[b + 1];
   const int wb = w_ptr[b], we = w_ptr[b + 1];
   const bool has_local = lev[b] >= 2;
-  for (int64_t tc = 0; tc < ntb; tc += tp) {
-    const int64_t i = tb0 + tc + tl;
-    const bool act = tc + tl < ntb;
-    const double zx = act ? tx[i] : 0.0, zy = act ? ty[i] : 0.0;
-    double field = 0.0;
-    if (act) {
-      if (sl == 0 && has_local) {
-        const double ir = 1.0 / rad[b];
-        const cx<double> w{(zx - cxv[b]) * ir, (zy - cyv[b]) * ir};
+  const double ir_b = 1.0 / rad[b];
+  for (int64_t tc0 = 0; tc0 < ntb; tc0 += 32 * NC) {
+    const int nt = (int)min<int64_t>(32 * NC, ntb - tc0);
+    const int nch = (nt + 31) / 32;
+    // sub-chunk c: targets [32 c, min(32 c + 32, nt)) on tp_c lanes times
+    // S_c = 64 / tp_c source slices, tp_c = min(32, next power of two)
+    int S[NC], sl[NC], ti[NC];
+    bool act[NC];
+    double zxs[NC], zys[NC], fld[NC];
+    int Smax = 1;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      S[c] = 64;
+      sl[c] = 0;
+      act[c] = false;
+      ti[c] = 0;
+      zxs[c] = zys[c] = fld[c] = 0.0;
+      if (c >= nch) continue;  // uniform
+      const int rem = nt - 32 * c;
+      const int tp = rem >= 32 ? 32 : pow2_at_least(rem);
+      S[c] = 64 / tp;
+      Smax = max(Smax, S[c]);
+      const int tl = lane % tp;
+      sl[c] = lane / tp;
+      act[c] = 32 * c + tl < nt;
+      ti[c] = (int)tc0 + 32 * c + tl;
+      if (!act[c]) continue;
+      const int64_t i = tb0 + ti[c];
+      const double zx = tx[i], zy = ty[i];
+      zxs[c] = zx;
+      zys[c] = zy;
+      double field = 0.0;
+      if (sl[c] == 0 && has_local) {
+        const cx<double> w{(zx - cxv[b]) * ir_b, (zy - cyv[b]) * ir_b};
         const cx<double> *La = Lr + (int64_t)b * P;
         cx<double> acc = La[P - 1];
         for (int l = P - 2; l >= 0; --l) acc = acc * w + La[l];
         field += acc.x;
       }
-      for (int e = wb + sl; e < we; e += S) {
-        const int c = w_src[e];
-        cx<double> d{zx - cxv[c], zy - cyv[c]};
-        cx<double> rho = rad[c] * cinv(d);
-        const cx<double> *a = Mr + (int64_t)c * P;
+      for (int e = wb + sl[c]; e < we; e += S[c]) {
+        const int cw = w_src[e];
+        cx<double> d{zx - cxv[cw], zy - cyv[cw]};
+        cx<double> rho = rad[cw] * cinv(d);
+        const cx<double> *a = Mr + (int64_t)cw * P;
         cx<double> acc = a[P - 1];
         for (int k = P - 2; k >= 0; --k) acc = acc * rho + a[k];
         field += (acc * rho).x;
       }
+      fld[c] = field;
     }
     for (int eb = ub; eb < ue; eb += 64) {
       const int cnt = min(64, ue - eb);
       const int total = gather_ranges(u_src, eb, cnt, s0, s1, rs, pre);
       for (int q0 = 0; q0 < total; q0 += kStage) {
         const int take = min(kStage, total - q0);
-        for (int q = lane; q < take; q += 64) {
-          const int64_t j = locate(q0 + q, cnt, rs, pre);
-          sz[q] = make_double2(sx[j], sy[j]);
-          const cx<double> pj = pr[j];
-          sp[q] = make_double2(pj.x, pj.y);
+        // pad to a multiple of Smax with sources of zero strength at the
+        // origin: they add 0 * rcp(|z|^2 + 1e-300) = 0
+        const int tpad = (take + Smax - 1) / Smax * Smax;
+        for (int q = lane; q < tpad; q += 64) {
+          if (q < take) {
+            const int64_t j = locate(q0 + q, cnt, rs, pre);
+            sz[q] = make_double2(sx[j], sy[j]);
+            const cx<double> pj = pr[j];
+            sp[q] = make_double2(pj.x, pj.y);
+          } else {
+            sz[q] = make_double2(0.0, 0.0);
+            sp[q] = make_double2(0.0, 0.0);
+          }
         }
         __syncthreads();
-        if (act) {
-          for (int q = sl; q < take; q += S) {
-            const double dx = zx - sz[q].x, dy = zy - sz[q].y;
-            const double d2 = dx * dx + dy * dy;
-            const double inv = d2 > 0.0 ? rcp64(d2) : 0.0;
-            field += (sp[q].x * dx + sp[q].y * dy) * inv;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          if (c >= nch) continue;  // uniform
+          const int Sc = S[c], niter = tpad / Sc;
+          const double zx = zxs[c], zy = zys[c];
+          double f = fld[c];
+          const double2 *zq = sz + sl[c];
+          const double2 *pq = sp + sl[c];
+#pragma unroll 2
+          for (int it = 0; it < niter; ++it) {
+            const double2 s2 = zq[it * Sc];
+            const double2 p2 = pq[it * Sc];
+            const double dx = zx - s2.x, dy = zy - s2.y;
+            // |d|^2 + 1e-300: a target's own source (d = 0) contributes
+            // 0 * rcp(1e-300) = 0; any other |d|^2 above 1e-284 is unchanged
+            const double d2 = fma(dx, dx, fma(dy, dy, 1e-300));
+            f += fma(p2.x, dx, p2.y * dy) * rcp64(d2);
           }
+          fld[c] = f;
         }
         __syncthreads();
       }
     }
-    for (int o = tp; o < 64; o <<= 1) field += __shfl_xor(field, o, 64);
-    if (act && sl == 0) {
-      const int64_t api = tperm[i];
-      double val = scale * field;
-      if (as.sigma) {
-        const double sg = as.sigma[(int64_t)r * as.ldx + api];
-        val += (as.ident + as.tau[api]) * sg +
-               as.gamma[r * as.G + (as.geo ? as.geo[api] : 0)];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (c >= nch) continue;  // uniform
+      double field = fld[c];
+      for (int o = 64 / S[c]; o < 64; o <<= 1) field += __shfl_xor(field, o, 64);
+      if (act[c] && sl[c] == 0) {
+        const int64_t api = tperm[tb0 + ti[c]];
+        double val = scale * field;
+        if (as.sigma) {
+          const double sg = as.sigma[(int64_t)r * as.ldx + api];
+          val += (as.ident + as.tau[api]) * sg +
+                 as.gamma[r * as.G + (as.geo ? as.geo[api] : 0)];
+        }
+        out[(int64_t)r * ldy + api] = val;
       }
-      out[(int64_t)r * ldy + api] = val;
     }
   }
 }
