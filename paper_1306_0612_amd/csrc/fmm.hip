@@ -800,9 +800,12 @@ __global__ void __launch_bounds__(64, 8)
 }
 
 // FP32 variant: near-field differences on hi/lo coordinate pairs,
-// d = (hi_i - hi_j) + (lo_i - lo_j), arithmetic in FP32.
-template <int P>
-__global__ void __launch_bounds__(64, 8)
+// d = (hi_i - hi_j) + (lo_i - lo_j), arithmetic in FP32.  A block handles
+// RB right-hand sides (blockIdx.y * RB + 0 .. RB - 1, those < nrhs): each
+// pair's difference and reciprocal are formed once and applied to every
+// right-hand side of the block.
+template <int P, int RB>
+__global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
     k_leaf32(const int32_t *__restrict__ leaves,
              const int32_t *__restrict__ lev,
              const int64_t *__restrict__ t0, const int64_t *__restrict__ t1,
@@ -821,19 +824,16 @@ __global__ void __launch_bounds__(64, 8)
              const float *__restrict__ syh, const float *__restrict__ syl,
              const cx<float> *__restrict__ p, int64_t ns,
              const cx<float> *__restrict__ M, const cx<float> *__restrict__ L,
-             int nbox, double *__restrict__ out, int64_t ldy, double scale,
-             Assembly as) {
+             int nbox, int nrhs, double *__restrict__ out, int64_t ldy,
+             double scale, Assembly as) {
   __shared__ float4 sz[kStage];
-  __shared__ float2 sp[kStage];
+  __shared__ float2 sp[RB][kStage];
   __shared__ int64_t rs[64];
   __shared__ int pre[65];
   constexpr int NC = 2;  // sub-chunks of <= 32 targets per pass over U
   const int b = leaves[blockIdx.x];
-  const int r = blockIdx.y;
+  const int r0 = blockIdx.y * RB, nr = min(RB, nrhs - r0);
   const int lane = threadIdx.x;
-  const cx<float> *pr = p + (int64_t)r * ns;
-  const cx<float> *Mr = M + (int64_t)r * nbox * P;
-  const cx<float> *Lr = L + (int64_t)r * nbox * P;
   const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
   const int ub = u_ptr[b], ue = u_ptr[b + 1];
   const int wb = w_ptr[b], we = w_ptr[b + 1];
@@ -844,10 +844,10 @@ __global__ void __launch_bounds__(64, 8)
     const int nch = (nt + 31) / 32;
     // sub-chunk c: targets [32 c, min(32 c + 32, nt)) on tp_c lanes times
     // S_c = 64 / tp_c source slices, tp_c = min(32, next power of two)
-    int S[NC], sl[NC];
+    int S[NC], sl[NC], ti[NC];
     bool act[NC];
-    int ti[NC];  // target offset within the leaf
-    float zxh[NC], zxl[NC], zyh[NC], zyl[NC], fld[NC];
+    float zxh[NC], zxl[NC], zyh[NC], zyl[NC], fld[NC][RB];
+    double zxd[NC], zyd[NC];
     int Smax = 1;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -855,7 +855,10 @@ __global__ void __launch_bounds__(64, 8)
       sl[c] = 0;
       act[c] = false;
       ti[c] = 0;
-      zxh[c] = zxl[c] = zyh[c] = zyl[c] = fld[c] = 0.f;
+      zxh[c] = zxl[c] = zyh[c] = zyl[c] = 0.f;
+      zxd[c] = zyd[c] = 0.0;
+#pragma unroll
+      for (int q = 0; q < RB; ++q) fld[c][q] = 0.f;
       if (c >= nch) continue;  // uniform
       const int rem = nt - 32 * c;
       const int tp = rem >= 32 ? 32 : pow2_at_least(rem);
@@ -871,26 +874,8 @@ __global__ void __launch_bounds__(64, 8)
       zxl[c] = txl[i];
       zyh[c] = tyh[i];
       zyl[c] = tyl[i];
-      const double zx = tx[i], zy = ty[i];
-      float field = 0.f;
-      if (sl[c] == 0 && has_local) {
-        const cx<float> w{float((zx - cxv[b]) * ir_b), float((zy - cyv[b]) * ir_b)};
-        const cx<float> *La = Lr + (int64_t)b * P;
-        cx<float> acc = La[P - 1];
-        for (int l = P - 2; l >= 0; --l) acc = acc * w + La[l];
-        field += acc.x;
-      }
-      for (int e = wb + sl[c]; e < we; e += S[c]) {
-        const int cw = w_src[e];
-        const double dx = zx - cxv[cw], dy = zy - cyv[cw];
-        const double id = rad[cw] / (dx * dx + dy * dy);
-        cx<float> rho{float(dx * id), float(-dy * id)};
-        const cx<float> *a = Mr + (int64_t)cw * P;
-        cx<float> acc = a[P - 1];
-        for (int k = P - 2; k >= 0; --k) acc = acc * rho + a[k];
-        field += (acc * rho).x;
-      }
-      fld[c] = field;
+      zxd[c] = tx[i];
+      zyd[c] = ty[i];
     }
     for (int eb = ub; eb < ue; eb += 64) {
       const int cnt = min(64, ue - eb);
@@ -904,11 +889,16 @@ __global__ void __launch_bounds__(64, 8)
           if (q < take) {
             const int64_t j = locate(q0 + q, cnt, rs, pre);
             sz[q] = make_float4(sxh[j], sxl[j], syh[j], syl[j]);
-            const cx<float> pj = pr[j];
-            sp[q] = make_float2(pj.x, pj.y);
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+              const cx<float> pj = rr < nr ? p[(int64_t)(r0 + rr) * ns + j]
+                                           : cx<float>{0.f, 0.f};
+              sp[rr][q] = make_float2(pj.x, pj.y);
+            }
           } else {
             sz[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-            sp[q] = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) sp[rr][q] = make_float2(0.f, 0.f);
           }
         }
         __syncthreads();
@@ -917,40 +907,89 @@ __global__ void __launch_bounds__(64, 8)
           if (c >= nch) continue;  // uniform
           const int Sc = S[c], niter = tpad / Sc;
           const float ax = zxh[c], bx = zxl[c], ay = zyh[c], by = zyl[c];
-          float f = fld[c];
+          float f[RB];
+#pragma unroll
+          for (int q = 0; q < RB; ++q) f[q] = fld[c][q];
           const float4 *zq = sz + sl[c];
-          const float2 *pq = sp + sl[c];
+          // |d|^2 + 1e-30: a target's own source (d = 0) contributes
+          // 0 * rcp(1e-30) = 0; the bias leaves any |d|^2 above 2e-23
+          // (node spacings above 5e-12) unchanged in FP32
+          if constexpr (RB == 1) {
+            const float2 *pq = sp[0] + sl[c];
 #pragma unroll 4
-          for (int it = 0; it < niter; ++it) {
-            const float4 s4 = zq[it * Sc];
-            const float2 p2 = pq[it * Sc];
-            const float dx = (ax - s4.x) + (bx - s4.y);
-            const float dy = (ay - s4.z) + (by - s4.w);
-            // |d|^2 + 1e-30: a target's own source (d = 0) contributes
-            // 0 * rcp(1e-30) = 0; the bias leaves any |d|^2 above 2e-23
-            // (node spacings above 5e-12) unchanged in FP32
-            const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
-            f += fmaf(p2.x, dx, p2.y * dy) * __builtin_amdgcn_rcpf(d2);
+            for (int it = 0; it < niter; ++it) {
+              const float4 s4 = zq[it * Sc];
+              const float2 p2 = pq[it * Sc];
+              const float dx = (ax - s4.x) + (bx - s4.y);
+              const float dy = (ay - s4.z) + (by - s4.w);
+              const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
+              f[0] += fmaf(p2.x, dx, p2.y * dy) * __builtin_amdgcn_rcpf(d2);
+            }
+          } else {
+#pragma unroll 2
+            for (int it = 0; it < niter; ++it) {
+              const int qq = sl[c] + it * Sc;
+              const float4 s4 = zq[it * Sc];
+              const float dx = (ax - s4.x) + (bx - s4.y);
+              const float dy = (ay - s4.z) + (by - s4.w);
+              const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, fmaf(dy, dy, 1e-30f)));
+              const float ux = dx * inv, uy = dy * inv;
+#pragma unroll
+              for (int q = 0; q < RB; ++q) {
+                const float2 p2 = sp[q][qq];
+                f[q] = fmaf(p2.x, ux, fmaf(p2.y, uy, f[q]));
+              }
+            }
           }
-          fld[c] = f;
+#pragma unroll
+          for (int q = 0; q < RB; ++q) fld[c][q] = f[q];
         }
         __syncthreads();
       }
     }
+    // per right-hand side: L2P (slice 0) and this slice's share of M2P,
+    // the sum over slices, the assembled row; the accumulators of the
+    // next right-hand side rotate into fld[c][0] (constant register indices)
+#pragma unroll 1
+    for (int q = 0; q < nr; ++q) {
+      const int r = r0 + q;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      if (c >= nch) continue;  // uniform
-      float field = fld[c];
-      for (int o = 64 / S[c]; o < 64; o <<= 1) field += __shfl_xor(field, o, 64);
-      if (act[c] && sl[c] == 0) {
-        const int64_t api = tperm[tb0 + ti[c]];
-        double val = scale * (double)field;
-        if (as.sigma) {
-          const double sg = as.sigma[(int64_t)r * as.ldx + api];
-          val += (as.ident + as.tau[api]) * sg +
-                 as.gamma[r * as.G + (as.geo ? as.geo[api] : 0)];
+      for (int c = 0; c < NC; ++c) {
+        if (c >= nch) continue;  // uniform
+        float field = fld[c][0];
+        if (act[c]) {
+          const double zx = zxd[c], zy = zyd[c];
+          if (sl[c] == 0 && has_local) {
+            const cx<float> w{float((zx - cxv[b]) * ir_b), float((zy - cyv[b]) * ir_b)};
+            const cx<float> *La = L + ((int64_t)r * nbox + b) * P;
+            cx<float> acc = La[P - 1];
+            for (int l = P - 2; l >= 0; --l) acc = acc * w + La[l];
+            field += acc.x;
+          }
+          for (int e = wb + sl[c]; e < we; e += S[c]) {
+            const int cw = w_src[e];
+            const double dx = zx - cxv[cw], dy = zy - cyv[cw];
+            const double id = rad[cw] / (dx * dx + dy * dy);
+            const cx<float> rho{float(dx * id), float(-dy * id)};
+            const cx<float> *a = M + ((int64_t)r * nbox + cw) * P;
+            cx<float> acc = a[P - 1];
+            for (int k = P - 2; k >= 0; --k) acc = acc * rho + a[k];
+            field += (acc * rho).x;
+          }
         }
-        out[(int64_t)r * ldy + api] = val;
+        for (int o = 64 / S[c]; o < 64; o <<= 1) field += __shfl_xor(field, o, 64);
+        if (act[c] && sl[c] == 0) {
+          const int64_t api = tperm[tb0 + ti[c]];
+          double val = scale * (double)field;
+          if (as.sigma) {
+            const double sg = as.sigma[(int64_t)r * as.ldx + api];
+            val += (as.ident + as.tau[api]) * sg +
+                   as.gamma[r * as.G + (as.geo ? as.geo[api] : 0)];
+          }
+          out[(int64_t)r * ldy + api] = val;
+        }
+#pragma unroll
+        for (int k = 0; k + 1 < RB; ++k) fld[c][k] = fld[c][k + 1];
       }
     }
   }
@@ -1052,15 +1091,20 @@ static void run32(const DevPlan &pl, const Tables &tb, Workspace &ws,
   far_field<float, P>(pl, tb, ws, p, M, L, nrhs, s);
   if (pl.n_leaf_t > 0) {
     TimerScope ts(ws.timer, ST_LEAF, s);
-    hipLaunchKernelGGL((k_leaf32<P>), dim3(pl.n_leaf_t, nrhs), dim3(64), 0, s,
-                       pl.leaf_t.p, pl.lev.p, pl.t0.p,
-                       pl.t1.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p,
-                       pl.tx.p, pl.ty.p, pl.txh.p, pl.txl.p, pl.tyh.p,
-                       pl.tyl.p, pl.tgt_perm.p, pl.u_ptr.p, pl.u_src.p,
-                       pl.w_ptr.p, pl.w_src.p, pl.sxh.p, pl.sxl.p, pl.syh.p,
-                       pl.syl.p, (const cx<float> *)p, pl.ns,
-                       (const cx<float> *)M, (const cx<float> *)L, pl.nbox,
-                       out, ldy, scale, as);
+    auto launch = [&](auto kern, int rb) {
+      hipLaunchKernelGGL(kern, dim3(pl.n_leaf_t, (nrhs + rb - 1) / rb), dim3(64),
+                         0, s, pl.leaf_t.p, pl.lev.p, pl.t0.p, pl.t1.p, pl.s0.p,
+                         pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p, pl.tx.p, pl.ty.p,
+                         pl.txh.p, pl.txl.p, pl.tyh.p, pl.tyl.p, pl.tgt_perm.p,
+                         pl.u_ptr.p, pl.u_src.p, pl.w_ptr.p, pl.w_src.p,
+                         pl.sxh.p, pl.sxl.p, pl.syh.p, pl.syl.p,
+                         (const cx<float> *)p, pl.ns, (const cx<float> *)M,
+                         (const cx<float> *)L, pl.nbox, nrhs, out, ldy, scale,
+                         as);
+    };
+    // one right-hand side per block, or blocks of 4 sharing each pair
+    if (nrhs == 1) launch(k_leaf32<P, 1>, 1);
+    else launch(k_leaf32<P, 4>, 4);
   }
 }
 
