@@ -5,6 +5,7 @@
 #include <cmath>
 #include <numeric>
 #include <stdexcept>
+#include <thread>
 #include <unordered_map>
 
 namespace lbs {
@@ -29,25 +30,70 @@ struct Keyed {
   std::vector<int64_t> perm;
 };
 
+// fn(begin, end) over [0, n) split into contiguous ranges, one per host
+// thread (at most 16; small n runs inline).
+template <typename F>
+void parallel_for(int64_t n, F fn, int64_t grain = 4096) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nt = (int)std::min<int64_t>(std::min(hw, 16), (n + grain - 1) / grain);
+  if (nt <= 1) {
+    fn((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(nt);
+  for (int t = 0; t < nt; ++t) {
+    const int64_t a = n * t / nt, b = n * (t + 1) / nt;
+    th.emplace_back([=, &fn] { fn(a, b); });
+  }
+  for (auto &x : th) x.join();
+}
+
+// Points sorted by their Morton key (ties keep input order): keys formed
+// and chunks sorted in parallel, then merged pairwise in parallel.
 void morton_sort(const double *x, const double *y, int64_t n, double lox,
                  double loy, double scale, Keyed &out) {
   const double cells = (double)(1ull << kMaxLevel);
-  std::vector<std::pair<uint64_t, int64_t>> kv((size_t)n);
-  for (int64_t i = 0; i < n; ++i) {
-    double fx = (x[i] - lox) * scale * cells;
-    double fy = (y[i] - loy) * scale * cells;
-    int64_t qx = (int64_t)std::floor(fx), qy = (int64_t)std::floor(fy);
-    qx = std::min<int64_t>(std::max<int64_t>(qx, 0), (1ll << kMaxLevel) - 1);
-    qy = std::min<int64_t>(std::max<int64_t>(qy, 0), (1ll << kMaxLevel) - 1);
-    kv[i] = {spread_bits((uint64_t)qx) | (spread_bits((uint64_t)qy) << 1), i};
+  using KV = std::pair<uint64_t, int64_t>;
+  std::vector<KV> kv((size_t)n), tmp((size_t)n);
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nc = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(hw, 16), n / 32768));
+  std::vector<int64_t> cut(nc + 1);
+  for (int c = 0; c <= nc; ++c) cut[c] = n * c / nc;
+  parallel_for(nc, [&](int64_t c0, int64_t c1) {
+    for (int64_t c = c0; c < c1; ++c) {
+      for (int64_t i = cut[c]; i < cut[c + 1]; ++i) {
+        double fx = (x[i] - lox) * scale * cells;
+        double fy = (y[i] - loy) * scale * cells;
+        int64_t qx = (int64_t)std::floor(fx), qy = (int64_t)std::floor(fy);
+        qx = std::min<int64_t>(std::max<int64_t>(qx, 0), (1ll << kMaxLevel) - 1);
+        qy = std::min<int64_t>(std::max<int64_t>(qy, 0), (1ll << kMaxLevel) - 1);
+        kv[i] = {spread_bits((uint64_t)qx) | (spread_bits((uint64_t)qy) << 1), i};
+      }
+      std::sort(kv.begin() + cut[c], kv.begin() + cut[c + 1]);
+    }
+  }, 1);
+  for (int w = 1; w < nc; w *= 2) {
+    const int nm = (nc + 2 * w - 1) / (2 * w);
+    parallel_for(nm, [&](int64_t m0, int64_t m1) {
+      for (int64_t m = m0; m < m1; ++m) {
+        const int64_t a = cut[std::min<int64_t>(2 * w * m, nc)];
+        const int64_t b = cut[std::min<int64_t>(2 * w * m + w, nc)];
+        const int64_t e = cut[std::min<int64_t>(2 * w * m + 2 * w, nc)];
+        std::merge(kv.begin() + a, kv.begin() + b, kv.begin() + b, kv.begin() + e,
+                   tmp.begin() + a);
+      }
+    }, 1);
+    kv.swap(tmp);
   }
-  std::sort(kv.begin(), kv.end());
   out.key.resize((size_t)n);
   out.perm.resize((size_t)n);
-  for (int64_t i = 0; i < n; ++i) {
-    out.key[i] = kv[i].first;
-    out.perm[i] = kv[i].second;
-  }
+  parallel_for(n, [&](int64_t a, int64_t b) {
+    for (int64_t i = a; i < b; ++i) {
+      out.key[i] = kv[i].first;
+      out.perm[i] = kv[i].second;
+    }
+  });
 }
 
 // Sub-range of [a, b) whose keys have quadrant q at level l + 1.
@@ -172,7 +218,8 @@ void build_tree(const double *sx, const double *sy, int64_t ns,
   // V lists
   T.v_ptr.assign(nb + 1, 0);
   std::vector<std::vector<std::pair<int32_t, uint8_t>>> vl(nb);
-  for (int b = 0; b < nb; ++b) {
+  parallel_for(nb, [&](int64_t b0, int64_t b1) {
+  for (int b = (int)b0; b < (int)b1; ++b) {
     int l = T.level[b];
     if (l < 2 || !has_tgt(b)) continue;
     int p = T.parent[b];
@@ -189,10 +236,12 @@ void build_tree(const double *sx, const double *sy, int64_t ns,
         }
       }
   }
+  }, 256);
   // U (descent part) and W lists, for leaves
   std::vector<std::vector<int32_t>> ud(nb), wl(nb);
+  parallel_for(nb, [&](int64_t b0, int64_t b1) {
   std::vector<int> stack;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = (int)b0; b < (int)b1; ++b) {
     if (!T.leaf[b]) continue;
     int l = T.level[b];
     for (int dx = -1; dx <= 1; ++dx)
@@ -216,6 +265,7 @@ void build_tree(const double *sx, const double *sy, int64_t ns,
         }
       }
   }
+  }, 256);
   // U = descent part + coarser adjacent leaves; X = transpose of W
   std::vector<std::vector<int32_t>> ul(nb), xl(nb);
   for (int b = 0; b < nb; ++b)
@@ -229,24 +279,37 @@ void build_tree(const double *sx, const double *sy, int64_t ns,
   auto flatten = [&](std::vector<std::vector<int32_t>> &L,
                      std::vector<int32_t> &ptr, std::vector<int32_t> &idx,
                      auto keep_target, auto keep_source) {
+    // sort and count per box, prefix sum, fill (all but the sum parallel)
     ptr.assign(nb + 1, 0);
-    idx.clear();
-    for (int b = 0; b < nb; ++b) {
-      if (keep_target(b)) {
+    parallel_for(nb, [&](int64_t b0, int64_t b1) {
+      for (int64_t b = b0; b < b1; ++b) {
+        if (!keep_target((int)b)) continue;
         std::sort(L[b].begin(), L[b].end());
-        for (int s : L[b])
-          if (keep_source(s)) idx.push_back(s);
+        int32_t n = 0;
+        for (int s : L[b]) n += keep_source(s) ? 1 : 0;
+        ptr[b + 1] = n;
       }
-      ptr[b + 1] = (int32_t)idx.size();
-    }
+    }, 1024);
+    for (int b = 0; b < nb; ++b) ptr[b + 1] += ptr[b];
+    idx.resize((size_t)ptr[nb]);
+    parallel_for(nb, [&](int64_t b0, int64_t b1) {
+      for (int64_t b = b0; b < b1; ++b) {
+        if (!keep_target((int)b)) continue;
+        int32_t k = ptr[b];
+        for (int s : L[b])
+          if (keep_source(s)) idx[k++] = s;
+      }
+    }, 1024);
   };
   flatten(ul, T.u_ptr, T.u_src, has_tgt, has_src);
   flatten(wl, T.w_ptr, T.w_src, has_tgt, has_src);
   flatten(xl, T.x_ptr, T.x_src, has_tgt, has_src);
   T.v_src.clear();
   T.v_code.clear();
+  parallel_for(nb, [&](int64_t b0, int64_t b1) {
+    for (int64_t b = b0; b < b1; ++b) std::sort(vl[b].begin(), vl[b].end());
+  }, 1024);
   for (int b = 0; b < nb; ++b) {
-    std::sort(vl[b].begin(), vl[b].end());
     for (auto &e : vl[b]) { T.v_src.push_back(e.first); T.v_code.push_back(e.second); }
     T.v_ptr[b + 1] = (int32_t)T.v_src.size();
   }

@@ -66,6 +66,21 @@ def test_iplusk_matvec(env, case, mode, prec, tol):
     assert _rel(_np(yk), ref - sig) < tol * 4
 
 
+@pytest.mark.parametrize("leaf_max", [128, 300])
+def test_large_leaves(env, leaf_max):
+    """Leaves holding more than 64 targets take several passes of the
+    leaf kernels (64 targets each, in sub-chunks of 32)."""
+    torch, lbs = env
+    isl = synth.star_islands(35, 4, (0.15, 0.25), nodes=400)
+    cv = Curves(isl)
+    sol = lbs.Solver(isl, leaf_max=leaf_max)
+    X = np.stack([synth.random_vector(s, cv.n) for s in (41, 42, 43)])
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+        Y = _np(sol.matvec(_t(torch, X), "iplusk", prec))
+        for r in range(3):
+            assert _rel(Y[r], nystrom.apply_iplusk(cv, X[r])) < tol, (prec, r)
+
+
 def test_multi_rhs_matvec_matches_columns(env):
     """Five right-hand sides in one call: FP64 columns equal the
     single-column results exactly (one kernel per column); the mixed near
