@@ -130,7 +130,7 @@ def adjoint_leg(torch, sol, islands, dev, n_targets):
     """Gradient of L = 1/2 |u - u*|^2 at 1e5 sphere targets with respect to
     the node data and the 16 shape coefficients of every island: forward
     solve (mixed, 1e-10) and evaluation, then the transposed evaluation,
-    the transposed solve (FP64, 1e-10) and the shape VJP."""
+    the transposed solve (mixed, 1e-10) and the shape VJP."""
     M = sol.n_islands
     xyz = sol.nodes().cpu().numpy()
     import synth
@@ -157,11 +157,12 @@ def adjoint_leg(torch, sol, islands, dev, n_targets):
     u = timed("forward_eval", lambda: sol.eval(sig, A, tgd))
     w = (u - usd).contiguous()
     gs, ga = timed("eval_T", lambda: sol.eval_T(w, tgd))
-    ls, la, infoT = timed("solve_T", lambda: sol.solve_T(gs, ga, tol=1e-10,
-                                                         check=False))
+    ls, la, infoT = timed("solve_T", lambda: sol.solve_T(
+        gs, ga, tol=1e-10, precision="mixed", check=False))
     dc = timed("shape_vjp", lambda: sol.shape_vjp(sig, A, ls, w, tgd))
     res["backward_s"] = res["eval_T_s"] + res["solve_T_s"] + res["shape_vjp_s"]
-    res["solve_T"] = {k: infoT[k] for k in ("status", "iters", "rel_resid")}
+    res["solve_T"] = {k: infoT[k] for k in ("status", "iters", "outer_steps",
+                                            "rel_resid", "fp32_matvecs")}
     # u is linear in g: w . u = (2 lambda_sigma) . g up to the tolerances
     J = float(w @ u)
     res["duality_rel"] = abs(J - float(2.0 * ls @ g)) / float(
@@ -261,6 +262,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="default FMM schedule instead of lbs_autotune's")
+    ap.add_argument("--leaf-max", type=int, default=0,
+                    help="fixed schedule (skips the tuner): leaf size")
+    ap.add_argument("--p32", type=int, default=0)
+    ap.add_argument("--p64", type=int, default=0)
     ap.add_argument("--batch-geoms", type=int, default=64)
     ap.add_argument("--batch-rhs", type=int, default=16)
     ap.add_argument("--cpu-rows", type=int, default=512)
@@ -297,7 +302,11 @@ def main():
     t0 = time.perf_counter()
     tuned = None
     opts = lbs.default_options()
-    if not args.no_tune:
+    fixed = {k: v for k, v in (("leaf_max", args.leaf_max), ("p32", args.p32),
+                               ("p64", args.p64)) if v}
+    if fixed:
+        opts = lbs.default_options(**fixed)
+    elif not args.no_tune:
         tt = time.perf_counter()
         opts, entries = lbs.autotune(islands, tol_mixed=1e-6, tol_fp64=1e-10)
         tuned = {"leaf_max": opts.leaf_max, "p32": opts.p32, "p64": opts.p64,

@@ -203,8 +203,8 @@ lbs_status lbs_eval_batch(lbs_handle h, int32_t nrhs, const double *sigma,
  * beta = the 16 radius coefficients (a_1..a_8, b_1..b_8) of every island,
  * which move the nodes and with them xi, xi', xi'' (Section 3) in the
  * kernel, the log-source rows and the evaluation.  The node data g is a
- * vector held fixed when beta moves.  All in FP64 with the FMM of p64
- * terms.  Single-geometry handles (LBS_ERR_UNSUPPORTED otherwise, except
+ * vector held fixed when beta moves.  FP64 with the FMM of p64 terms
+ * (lbs_solve_T also mixed).  Single-geometry handles (LBS_ERR_UNSUPPORTED otherwise, except
  * lbs_solve_T, which takes batch handles).  Device pointers, column-major
  * as in lbs_solve; calls are stream-ordered on `stream` and return after it
  * has drained. */
@@ -220,13 +220,15 @@ lbs_status lbs_eval_T(lbs_handle h, int32_t nrhs, const double *w,
 /* Solve A^T [lam_s; lam_a] = [rhs_s; rhs_a] (rhs_s, lam_s: N x nrhs;
  * rhs_a, lam_a: M x nrhs; rhs_a may be NULL for zeros) by GMRES with the
  * transposed block preconditioner on the right, to the relative residual
- * tol of the unpreconditioned transposed system, per system.  info as in
- * lbs_solve (iters, rel_resid; fp64_matvecs counts transposed operator
- * applications).  LBS_ERR_NO_CONVERGENCE when max_iter is reached; the
- * iterate is still written. */
-lbs_status lbs_solve_T(lbs_handle h, int32_t nrhs, const double *rhs_s,
-                       const double *rhs_a, double tol, double *lam_s,
-                       double *lam_a, lbs_solve_info *info_host,
+ * tol of the unpreconditioned transposed system, per system.  precision:
+ * LBS_FP64, or LBS_MIXED (GMRES on the FP32 transposed FMM inside FP64
+ * refinement, as in lbs_solve).  info as in lbs_solve (fp64_matvecs /
+ * fp32_matvecs count transposed operator applications).
+ * LBS_ERR_NO_CONVERGENCE when max_iter is reached; the iterate is still
+ * written. */
+lbs_status lbs_solve_T(lbs_handle h, int32_t precision, int32_t nrhs,
+                       const double *rhs_s, const double *rhs_a, double tol,
+                       double *lam_s, double *lam_a, lbs_solve_info *info_host,
                        void *stream);
 
 /* dcoef (M x 16, island-major, coefficient order of lbs_island.coef) =

@@ -25,17 +25,19 @@ def _islands_with(islands, coef):
 
 
 class SolveEval(torch.autograd.Function):
-    """u = SolveEval.apply(g, coef, islands, targets, tol, options)."""
+    """u = SolveEval.apply(g, coef, islands, targets, tol, precision,
+    options)."""
 
     @staticmethod
-    def forward(ctx, g, coef, islands, targets, tol, options):
+    def forward(ctx, g, coef, islands, targets, tol, precision, options):
         sol = lbs.Solver(_islands_with(islands, coef), **options)
         sig, A, info = sol.solve(g.detach().contiguous(), tol=tol,
-                                 precision="fp64")
+                                 precision=precision)
         u = sol.eval(sig, A, targets)
         ctx.sol = sol
         ctx.targets = targets
         ctx.tol = tol
+        ctx.precision = precision
         ctx.coef_device = coef.device
         ctx.forward_info = info
         ctx.save_for_backward(sig, A)
@@ -47,17 +49,21 @@ class SolveEval(torch.autograd.Function):
         sig, A = ctx.saved_tensors
         w = w.detach().to(torch.float64).contiguous()
         gs, ga = sol.eval_T(w, targets)
-        lam_s, _, info = sol.solve_T(gs, ga, tol=ctx.tol)
+        lam_s, _, info = sol.solve_T(gs, ga, tol=ctx.tol,
+                                     precision=ctx.precision)
         ctx.adjoint_info = info
         dg = 2.0 * lam_s if ctx.needs_input_grad[0] else None
         dc = None
         if ctx.needs_input_grad[1]:
             dc = sol.shape_vjp(sig, A, lam_s, w, targets).to(ctx.coef_device)
-        return dg, dc, None, None, None, None
+        return dg, dc, None, None, None, None, None
 
 
-def solve_eval(g, coef, islands, targets, tol=1e-12, **options):
+def solve_eval(g, coef, islands, targets, tol=1e-12, precision="fp64",
+               **options):
     """u at `targets` (T x 3, float64 CUDA) for node data g (N, float64
     CUDA) on islands whose radius coefficients are `coef` (M x 16);
-    `islands` supplies center, e1, r0 and n.  Differentiable in g and coef."""
-    return SolveEval.apply(g, coef, islands, targets, tol, options)
+    `islands` supplies center, e1, r0 and n.  Differentiable in g and coef.
+    precision ("fp64" or "mixed") applies to the solve and to the
+    transposed solve of the backward pass."""
+    return SolveEval.apply(g, coef, islands, targets, tol, precision, options)

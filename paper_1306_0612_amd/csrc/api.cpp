@@ -970,23 +970,26 @@ void precond_T(lbs_ctx &c, const double *mu, double *lam, hipStream_t s) {
   launch_FT(g, lam + g.N, 1.0, mu, -1.0, lam, s);
 }
 
-// y = ident x + K^T x over the node rows (one column), FP64 FMM
-void apply_KT(lbs_ctx &c, const double *x, double *y, double ident, hipStream_t s) {
+// y = ident x + K^T x over the node rows (one column); the field by the
+// FP64 FMM or, for LBS_MIXED, the FP32 one
+void apply_KT(lbs_ctx &c, const double *x, double *y, double ident, int prec,
+              hipStream_t s) {
   Geometry &g = c.geo;
   AdjState &a = c.adj;
   launch_real_to_complex(g.N, x, a.pc.p, s);
-  fmm_apply64_full(c.plan, c.tab64, c.ws, a.pc.p, a.Fc.p, nullptr, s);
+  if (prec == LBS_MIXED) fmm_apply32_full(c.plan, c.tab32, c.ws, a.pc.p, a.Fc.p, s);
+  else fmm_apply64_full(c.plan, c.tab64, c.ws, a.pc.p, a.Fc.p, nullptr, s);
   launch_segdots(c.seg_nodes, 1, 1, a.ones.p, 0, 0, x, g.N, a.ysum.p, c.ws.red.p, s);
   launch_kT_assemble(g, x, a.Fc.p, a.ysum.p, ident, y, s);
 }
 
 // y = A^T P^-T x for R columns of length N + M
-void apply_op_T(lbs_ctx &c, int R, const double *x, double *y, hipStream_t s) {
+void apply_op_T(lbs_ctx &c, int R, const double *x, double *y, int prec, hipStream_t s) {
   Geometry &g = c.geo;
   const int64_t n = g.N + g.M;
   for (int r = 0; r < R; ++r) {
     precond_T(c, x + r * n, c.adj.lam.p, s);
-    apply_KT(c, c.adj.lam.p, y + r * n, 0.0, s);
+    apply_KT(c, c.adj.lam.p, y + r * n, 0.0, prec, s);
     launch_fill(g.M, 0.0, y + r * n + g.N, s);
   }
   launch_axpby((int64_t)R * n, 1.0, x, 1.0, y, s);
@@ -1260,14 +1263,16 @@ lbs_status lbs_eval_T(lbs_handle h, int32_t nrhs, const double *w, int64_t T, co
   });
 }
 
-lbs_status lbs_solve_T(lbs_handle h, int32_t nrhs, const double *rs, const double *ra, double tol,
-                       double *lam_s, double *lam_a, lbs_solve_info *info, void *stream) {
+lbs_status lbs_solve_T(lbs_handle h, int32_t prec, int32_t nrhs, const double *rs,
+                       const double *ra, double tol, double *lam_s, double *lam_a,
+                       lbs_solve_info *info, void *stream) {
   bool noconv = false;
   lbs_status st = guard([&] {
     check_handle(h);
     if (!rs || !lam_s || !lam_a) fail(LBS_ERR_INVALID_ARG, "null pointer argument");
     if (nrhs < 1 || nrhs > 65535) fail(LBS_ERR_INVALID_ARG, "nrhs outside [1, 65535]");
     if (!(tol > 0 && tol < 1)) fail(LBS_ERR_INVALID_ARG, "tol outside (0, 1)");
+    if (prec != LBS_FP64 && prec != LBS_MIXED) fail(LBS_ERR_INVALID_ARG, "bad precision");
     hipStream_t s = (hipStream_t)stream;
     lbs_ctx &c = *h;
     Geometry &g = c.geo;
@@ -1287,14 +1292,59 @@ lbs_status lbs_solve_T(lbs_handle h, int32_t nrhs, const double *rs, const doubl
     if (!std::isfinite(download(gm.nrm2.p, 1, s)[0]))
       fail(LBS_ERR_NOT_FINITE, "right-hand side is not finite");
     sys_norm2(c, R, gm.bvec.p, gm.bn2.p, s);
-    launch_scale_sqrt(S, tol, gm.bn2.p, gm.tol.p, s);
-    OpFn op = [&](const double *in, double *out, hipStream_t q) { apply_op_T(c, R, in, out, q); };
-    GmresOut go = gmres(c, op, 2, R, gm.bvec.p, gm.xvec.p, true, c.opt.max_iter, s);
-    inf.iters = go.iters;
-    inf.fp64_matvecs = go.iters + 1;
-    noconv = !go.conv;
+    OpFn op64 = [&](const double *in, double *out, hipStream_t q) {
+      apply_op_T(c, R, in, out, LBS_FP64, q);
+    };
+    OpFn op32 = [&](const double *in, double *out, hipStream_t q) {
+      apply_op_T(c, R, in, out, LBS_MIXED, q);
+    };
+    if (prec == LBS_FP64) {
+      launch_scale_sqrt(S, tol, gm.bn2.p, gm.tol.p, s);
+      GmresOut go = gmres(c, op64, 2, R, gm.bvec.p, gm.xvec.p, true, c.opt.max_iter, s);
+      inf.iters = go.iters;
+      inf.fp64_matvecs = go.iters;
+      noconv = !go.conv;
+    } else {
+      // refinement: r = b - A^T P^-T mu in FP64, correction from GMRES on
+      // the FP32 transposed operator, as in lbs_solve
+      launch_fill((int64_t)R * n, 0.0, gm.xvec.p, s);
+      LBS_HIP(hipMemcpyAsync(gm.rvec.p, gm.bvec.p, (size_t)R * n * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+      std::vector<double> bn2 = download(gm.bn2.p, S, s), rn2 = bn2;
+      int left = c.opt.max_iter;
+      bool conv = false;
+      for (int outer = 0;; ++outer) {
+        std::vector<double> itol(S);
+        bool all = true;
+        for (int q = 0; q < S; ++q) {
+          const double rn = std::sqrt(std::max(0.0, rn2[q])), bn = std::sqrt(std::max(0.0, bn2[q]));
+          if (rn <= tol * bn) {
+            itol[q] = rn;
+          } else {
+            all = false;
+            itol[q] = std::max(c.opt.inner_tol * rn, 0.5 * tol * bn);
+          }
+        }
+        if (all) { conv = true; break; }
+        if (outer >= c.opt.max_outer || left <= 0) break;
+        LBS_HIP(hipMemcpyAsync(gm.tol.p, itol.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
+        GmresOut go = gmres(c, op32, 3, R, gm.rvec.p, gm.dvec.p, true, left, s);
+        inf.iters += go.iters;
+        inf.fp32_matvecs += go.iters;
+        left -= go.iters;
+        launch_axpby((int64_t)R * n, 1.0, gm.dvec.p, 1.0, gm.xvec.p, s);
+        op64(gm.xvec.p, gm.rvec.p, s);
+        inf.fp64_matvecs += 1;
+        launch_axpby((int64_t)R * n, 1.0, gm.bvec.p, -1.0, gm.rvec.p, s);
+        sys_norm2(c, R, gm.rvec.p, gm.nrm2.p, s);
+        rn2 = download(gm.nrm2.p, S, s);
+        inf.outer_steps = outer + 1;
+      }
+      noconv = !conv;
+    }
     // residual of A^T lambda = b (equal to that of the right-preconditioned system)
-    op(gm.xvec.p, gm.rvec.p, s);
+    op64(gm.xvec.p, gm.rvec.p, s);
+    inf.fp64_matvecs += 1;
     launch_axpby((int64_t)R * n, 1.0, gm.bvec.p, -1.0, gm.rvec.p, s);
     sys_norm2(c, R, gm.rvec.p, gm.nrm2.p, s);
     std::vector<double> rn2 = download(gm.nrm2.p, S, s), bn2 = download(gm.bn2.p, S, s);

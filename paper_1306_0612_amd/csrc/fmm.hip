@@ -1305,4 +1305,149 @@ void fmm_apply64_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
   LBS_HIP(hipGetLastError());
 }
 
+// FP32 counterpart for the transposed operator (field only): strengths in
+// FP32, near-field differences on hi/lo coordinate pairs as in k_leaf32.
+__global__ void k_strengths_given32(int64_t ns, const int64_t *__restrict__ perm,
+                                    const double *__restrict__ pin,
+                                    cx<float> *__restrict__ p) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ns) return;
+  const int64_t a = perm[j];
+  p[j] = cx<float>{float(pin[2 * a]), float(pin[2 * a + 1])};
+}
+
+template <int P>
+__global__ void __launch_bounds__(64)
+    k_leaf32_full(const int32_t *__restrict__ leaves,
+                  const int32_t *__restrict__ lev,
+                  const int64_t *__restrict__ t0, const int64_t *__restrict__ t1,
+                  const int64_t *__restrict__ s0, const int64_t *__restrict__ s1,
+                  const double *__restrict__ cxv, const double *__restrict__ cyv,
+                  const double *__restrict__ rad,
+                  const double *__restrict__ tx, const double *__restrict__ ty,
+                  const float *__restrict__ txh, const float *__restrict__ txl,
+                  const float *__restrict__ tyh, const float *__restrict__ tyl,
+                  const int64_t *__restrict__ tperm,
+                  const int32_t *__restrict__ u_ptr,
+                  const int32_t *__restrict__ u_src,
+                  const int32_t *__restrict__ w_ptr,
+                  const int32_t *__restrict__ w_src,
+                  const float *__restrict__ sxh, const float *__restrict__ sxl,
+                  const float *__restrict__ syh, const float *__restrict__ syl,
+                  const cx<float> *__restrict__ p,
+                  const cx<float> *__restrict__ M,
+                  const cx<float> *__restrict__ L, double *__restrict__ psi) {
+  __shared__ float4 sz[kStage];
+  __shared__ float2 sp[kStage];
+  __shared__ int64_t rs[64];
+  __shared__ int pre[65];
+  const int b = leaves[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
+  const int tp = ntb <= 32 ? pow2_at_least((int)ntb) : 64;
+  const int S = 64 / tp, tl = lane % tp, sl = lane / tp;
+  const int ub = u_ptr[b], ue = u_ptr[b + 1];
+  const int wb = w_ptr[b], we = w_ptr[b + 1];
+  for (int64_t tc = 0; tc < ntb; tc += tp) {
+    const int64_t i = tb0 + tc + tl;
+    const bool act = tc + tl < ntb;
+    const double zx = act ? tx[i] : 0.0, zy = act ? ty[i] : 0.0;
+    const float zxh = act ? txh[i] : 0.f, zxl = act ? txl[i] : 0.f;
+    const float zyh = act ? tyh[i] : 0.f, zyl = act ? tyl[i] : 0.f;
+    cx<float> f{0.f, 0.f};
+    if (act) {
+      if (sl == 0 && lev[b] >= 2) {
+        const double ir = 1.0 / rad[b];
+        const cx<float> w{float((zx - cxv[b]) * ir), float((zy - cyv[b]) * ir)};
+        const cx<float> *La = L + (int64_t)b * P;
+        cx<float> acc = La[P - 1];
+        for (int l = P - 2; l >= 0; --l) acc = acc * w + La[l];
+        f = f + acc;
+      }
+      for (int e = wb + sl; e < we; e += S) {
+        const int c = w_src[e];
+        const double dx = zx - cxv[c], dy = zy - cyv[c];
+        const double id = rad[c] / (dx * dx + dy * dy);
+        const cx<float> rho{float(dx * id), float(-dy * id)};
+        const cx<float> *a = M + (int64_t)c * P;
+        cx<float> acc = a[P - 1];
+        for (int k = P - 2; k >= 0; --k) acc = acc * rho + a[k];
+        f = f + acc * rho;
+      }
+    }
+    for (int eb = ub; eb < ue; eb += 64) {
+      const int cnt = min(64, ue - eb);
+      const int total = gather_ranges(u_src, eb, cnt, s0, s1, rs, pre);
+      for (int q0 = 0; q0 < total; q0 += kStage) {
+        const int take = min(kStage, total - q0);
+        for (int q = lane; q < take; q += 64) {
+          const int64_t j = locate(q0 + q, cnt, rs, pre);
+          sz[q] = make_float4(sxh[j], sxl[j], syh[j], syl[j]);
+          const cx<float> pj = p[j];
+          sp[q] = make_float2(pj.x, pj.y);
+        }
+        __syncthreads();
+        if (act) {
+          for (int q = sl; q < take; q += S) {
+            const float4 s4 = sz[q];
+            const float2 p2 = sp[q];
+            const float dx = (zxh - s4.x) + (zxl - s4.y);
+            const float dy = (zyh - s4.z) + (zyl - s4.w);
+            // p / d = p conj(d) / |d|^2; the 1e-30 bias makes a target's own
+            // source (d = 0, in a self plan) contribute 0
+            const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, fmaf(dy, dy, 1e-30f)));
+            f.x += fmaf(p2.x, dx, p2.y * dy) * inv;
+            f.y += fmaf(p2.y, dx, -p2.x * dy) * inv;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int o = tp; o < 64; o <<= 1) {
+      f.x += __shfl_xor(f.x, o, 64);
+      f.y += __shfl_xor(f.y, o, 64);
+    }
+    if (act && sl == 0) {
+      const int64_t api = tperm[i];
+      psi[2 * api] = f.x;
+      psi[2 * api + 1] = f.y;
+    }
+  }
+}
+
+template <int P>
+static void run32_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
+                       double *psi, hipStream_t s) {
+  auto *p = (cx<float> *)ws.pstr32.p;
+  auto *M = (cx<float> *)ws.mult32.p;
+  auto *L = (cx<float> *)ws.loc32.p;
+  far_field<float, P>(pl, tb, ws, p, M, L, 1, s);
+  if (pl.n_leaf_t > 0)
+    hipLaunchKernelGGL((k_leaf32_full<P>), dim3(pl.n_leaf_t), dim3(64), 0, s,
+                       pl.leaf_t.p, pl.lev.p, pl.t0.p, pl.t1.p, pl.s0.p,
+                       pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p, pl.tx.p, pl.ty.p,
+                       pl.txh.p, pl.txl.p, pl.tyh.p, pl.tyl.p, pl.tgt_perm.p,
+                       pl.u_ptr.p, pl.u_src.p, pl.w_ptr.p, pl.w_src.p,
+                       pl.sxh.p, pl.sxl.p, pl.syh.p, pl.syl.p,
+                       (const cx<float> *)p, (const cx<float> *)M,
+                       (const cx<float> *)L, psi);
+}
+
+void fmm_apply32_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
+                      const double *pin, double *psi, hipStream_t s) {
+  if (pl.ns > 0)
+    hipLaunchKernelGGL(k_strengths_given32, dim3((unsigned)((pl.ns + 255) / 256)),
+                       dim3(256), 0, s, pl.ns, pl.src_perm.p, pin,
+                       (cx<float> *)ws.pstr32.p);
+  switch (tb.P) {
+    case 12: run32_full<12>(pl, tb, ws, psi, s); break;
+    case 16: run32_full<16>(pl, tb, ws, psi, s); break;
+    case 20: run32_full<20>(pl, tb, ws, psi, s); break;
+    case 24: run32_full<24>(pl, tb, ws, psi, s); break;
+    default:
+      throw ApiError{LBS_ERR_UNSUPPORTED, "p32 must be one of 12, 16, 20, 24"};
+  }
+  LBS_HIP(hipGetLastError());
+}
+
 }  // namespace lbs

@@ -282,6 +282,9 @@ void fmm_apply64(const DevPlan &pl, const Tables &tb, Workspace &ws,
 void fmm_apply64_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
                       const double *pin, double *psi, double *dpsi,
                       hipStream_t s);
+// The same field only, FP32 far and near field (p32 terms).
+void fmm_apply32_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
+                      const double *pin, double *psi, hipStream_t s);
 void fmm_apply32(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  const double *qfac_t, const double *sigma, int64_t ldx,
                  int nrhs, double *out, int64_t ldy, double scale,

@@ -134,8 +134,9 @@ def load():
                                         ctypes.POINTER(TreeStats)]
     lib.lbs_eval_T.argtypes = [H, ctypes.c_int32, vp, ctypes.c_int64, vp,
                                vp, vp, vp]
-    lib.lbs_solve_T.argtypes = [H, ctypes.c_int32, vp, vp, ctypes.c_double,
-                                vp, vp, ctypes.POINTER(SolveInfo), vp]
+    lib.lbs_solve_T.argtypes = [H, ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                ctypes.c_double, vp, vp,
+                                ctypes.POINTER(SolveInfo), vp]
     lib.lbs_shape_vjp.argtypes = [H, vp, vp, vp, ctypes.c_int64, vp, vp, vp,
                                   vp]
     lib.lbs_set_orders.argtypes = [H, ctypes.c_int32, ctypes.c_int32, vp]
@@ -328,7 +329,8 @@ class Solver:
                                  _dev(gs), _dev(ga), _stream()))
         return gs, ga
 
-    def solve_T(self, rhs_s, rhs_a=None, tol=1e-12, check=True):
+    def solve_T(self, rhs_s, rhs_a=None, tol=1e-12, precision="fp64",
+                check=True):
         """Solve A^T [lam_s; lam_a] = [rhs_s; rhs_a] -> (lam_s, lam_a, info)."""
         nrhs = _rhs(rhs_s, self.n_nodes)
         lead = () if rhs_s.dim() == 1 else (nrhs,)
@@ -339,7 +341,8 @@ class Solver:
         la = torch.empty(lead + (self.n_islands,), dtype=torch.float64,
                          device="cuda")
         info = SolveInfo()
-        code = load().lbs_solve_T(self._h, nrhs, _dev(rhs_s),
+        code = load().lbs_solve_T(self._h, PRECISIONS[precision], nrhs,
+                                  _dev(rhs_s),
                                   None if rhs_a is None else _dev(rhs_a),
                                   float(tol), _dev(ls), _dev(la),
                                   ctypes.byref(info), _stream())

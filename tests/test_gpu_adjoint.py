@@ -78,13 +78,17 @@ def test_eval_T_multi_rhs_and_empty(env, small):
     assert float(gs0.abs().max()) == 0.0 and float(ga0.abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("which", ["small", "medium"])
-def test_solve_T_matches_dense(env, request, which):
+def test_solve_T_matches_dense(env, request, which, prec):
     torch, lbs = env
     isl, cv, tg, w, g, sol = request.getfixturevalue(which)
     rng = np.random.default_rng(11)
     rs, ra = rng.standard_normal(cv.n), rng.standard_normal(cv.m)
-    ls, la, info = sol.solve_T(_t(torch, rs), _t(torch, ra), tol=1e-12)
+    ls, la, info = sol.solve_T(_t(torch, rs), _t(torch, ra), tol=1e-12,
+                               precision=prec)
+    if prec == "mixed":
+        assert info["fp32_matvecs"] > 0 and info["outer_steps"] >= 1
     assert info["rel_resid"] < 1e-11
     ref_s, ref_a = adjoint.adjoint_solve(cv, rs, ra)
     assert _rel(ls.cpu().numpy(), ref_s) < 1e-9
@@ -158,14 +162,16 @@ def test_cap_shape_derivative_closed_form(env):
     assert np.abs(dc - exp).max() < 1e-9 * np.abs(exp).max()
 
 
-def test_autograd_function(env, small):
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autograd_function(env, small, prec):
     torch, lbs = env
     from paper_1306_0612_amd.autograd import solve_eval
     isl, cv, tg, w, g, sol = small
     ustar = np.random.default_rng(21).standard_normal(len(tg))
     gd = _t(torch, g).requires_grad_(True)
     coef = torch.tensor(isl.coef, dtype=torch.float64, requires_grad=True)
-    u = solve_eval(gd, coef, isl, _t(torch, tg), tol=1e-13, leaf_max=12)
+    u = solve_eval(gd, coef, isl, _t(torch, tg), tol=1e-13, precision=prec,
+                   leaf_max=12)
     loss = 0.5 * ((u - _t(torch, ustar)) ** 2).sum()
     loss.backward()
     s_ref, a_ref = nystrom.solve_dense(cv, g)

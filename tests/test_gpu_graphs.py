@@ -68,7 +68,8 @@ def test_batch_solve(env):
         torch.cuda.synchronize()
 
 
-def test_transposed_solve(env):
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_transposed_solve(env, prec):
     torch, lbs = env
     isl = synth.star_islands(94, 6, (0.06, 0.15), nodes=80)
     eager = lbs.Solver(isl, leaf_max=12, graphs=0)
@@ -76,9 +77,9 @@ def test_transposed_solve(env):
     rng = np.random.default_rng(3)
     rs = _t(torch, rng.standard_normal(eager.n_nodes))
     ra = _t(torch, rng.standard_normal(eager.n_islands))
-    l0, m0, _ = eager.solve_T(rs, ra, tol=1e-12)
+    l0, m0, _ = eager.solve_T(rs, ra, tol=1e-12, precision=prec)
     for rep in range(2):
-        l1, m1, _ = graph.solve_T(rs, ra, tol=1e-12)
+        l1, m1, _ = graph.solve_T(rs, ra, tol=1e-12, precision=prec)
         assert torch.equal(l1, l0) and torch.equal(m1, m0), rep
         graph.solve(rs, tol=1e-10)
         torch.cuda.synchronize()
