@@ -151,51 +151,69 @@ void launch_dl_strengths(const Geometry &g, const double *sigma, double *out,
 // q = 2 rho'_k (a - i b) / |c_k - c_m|^2 (a, b: c_m on k's frame vectors),
 // Q_k[l] = sum_i y_i (xi'_i / rho'_k)^l, Y_k = sum_i y_i,
 // ELL_k = sum_i y_i log(1 + |xi'_i|^2); near islands directly in 3D.
-__global__ void __launch_bounds__(256)
-    k_island_moments(const int64_t *__restrict__ offs,
+//
+// Moments are stored slot-major, mom[s * M + k], so that lanes over islands
+// read them coalesced: slots 2 (l - 1), 2 (l - 1) + 1 hold Q_k[l] / l
+// (l = 1..P), slot 2 P holds Y_k and slot 2 P + 1 ELL_k.  One wave per
+// (island, half of the series): half h sums the powers h P/2 + 1 .. (h + 1)
+// P/2, starting from u^(h P/2 + 1) by repeated squaring; half 0 also forms
+// Y_k and ELL_k.
+__global__ void __launch_bounds__(64)
+    k_island_moments(int M, const int64_t *__restrict__ offs,
                      const double *__restrict__ xil,
                      const double *__restrict__ elll,
                      const double *__restrict__ rhol,
                      const double *__restrict__ y, double *__restrict__ mom) {
-  constexpr int P = kPlog;
-  __shared__ double red[4][kMomStride];
-  const int k = blockIdx.x;
-  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  constexpr int P = kPlog, PH = P / 2;
+  static_assert(2 * PH == P, "the series splits in two halves");
+  const int k = blockIdx.x, h = blockIdx.y, ln = threadIdx.x;
+  const int l0 = h * PH;
   const double ir = 1.0 / rhol[k];
-  cx<double> acc[P];
+  cx<double> acc[PH];
 #pragma unroll
-  for (int l = 0; l < P; ++l) acc[l] = cx<double>{0.0, 0.0};
+  for (int l = 0; l < PH; ++l) acc[l] = cx<double>{0.0, 0.0};
   double ys = 0.0, ys_ell = 0.0;
-  for (int64_t i = offs[k] + tid; i < offs[k + 1]; i += 256) {
+  for (int64_t i = offs[k] + ln; i < offs[k + 1]; i += 64) {
     const double yi = y[i];
-    ys += yi;
-    ys_ell += yi * elll[i];
     const cx<double> u{xil[2 * i] * ir, xil[2 * i + 1] * ir};
     cx<double> pw = yi * u;
+    if (h == 0) {
+      ys += yi;
+      ys_ell += yi * elll[i];
+    } else {
+      cx<double> base = u;  // pw = y_i u^(l0 + 1)
+      for (int e = l0; e > 0; e >>= 1) {
+        if (e & 1) pw = pw * base;
+        base = base * base;
+      }
+    }
 #pragma unroll
-    for (int l = 0; l < P; ++l) {
+    for (int l = 0; l < PH; ++l) {
       acc[l] = acc[l] + pw;
       pw = pw * u;
     }
   }
-  auto put = [&](int slot, double v) {
-    v = wsum(v);
-    if (ln == 0) red[wv][slot] = v;
-  };
 #pragma unroll
-  for (int l = 0; l < P; ++l) {
-    put(2 * l, acc[l].x);
-    put(2 * l + 1, acc[l].y);
+  for (int l = 0; l < PH; ++l) {
+    const double inv = 1.0 / (double)(l0 + l + 1);
+    const double vx = wsum(acc[l].x), vy = wsum(acc[l].y);
+    if (ln == 0) {
+      mom[(int64_t)(2 * (l0 + l)) * M + k] = vx * inv;
+      mom[(int64_t)(2 * (l0 + l) + 1) * M + k] = vy * inv;
+    }
   }
-  put(2 * P, ys);
-  put(2 * P + 1, ys_ell);
-  __syncthreads();
-  for (int s = tid; s < kMomStride; s += 256)
-    mom[(int64_t)k * kMomStride + s] = red[0][s] + red[1][s] + red[2][s] + red[3][s];
+  if (h == 0) {
+    ys = wsum(ys);
+    ys_ell = wsum(ys_ell);
+    if (ln == 0) {
+      mom[(int64_t)(2 * P) * M + k] = ys;
+      mom[(int64_t)(2 * P + 1) * M + k] = ys_ell;
+    }
+  }
 }
 
 __global__ void __launch_bounds__(256)
-    k_logsrc_T(const int32_t *__restrict__ isl_geo,
+    k_logsrc_T(int M, const int32_t *__restrict__ isl_geo,
                const int32_t *__restrict__ gisl,
                const int64_t *__restrict__ offs,
                const double *__restrict__ cxyz,
@@ -216,8 +234,8 @@ __global__ void __launch_bounds__(256)
   const int nn = nearT_ptr[m + 1] - nearT_ptr[m];
   double tot = 0.0, ysum = 0.0;
   for (int k = gisl[g] + tid; k < gisl[g + 1]; k += 256) {
-    const double *mk = mom + (int64_t)k * kMomStride;
-    ysum += mk[2 * P];
+    const double Yk = mom[(int64_t)(2 * P) * M + k];
+    ysum += Yk;
     if (in_sorted(nl, nn, k)) continue;
     const double *fr = frame + 6 * k;
     const double d0 = x0 - cxyz[3 * k], d1 = x1 - cxyz[3 * k + 1],
@@ -227,13 +245,15 @@ __global__ void __launch_bounds__(256)
     const double b = x0 * fr[3] + x1 * fr[4] + x2 * fr[5];
     const double f = 2.0 * rhol[k] / dd;
     const cx<double> q{a * f, -b * f};
-    cx<double> pw = q, ser{0.0, 0.0};
-    for (int l = 1; l <= P; ++l) {
-      const cx<double> Ql{mk[2 * (l - 1)], mk[2 * (l - 1) + 1]};
-      ser = ser + (1.0 / (double)l) * (pw * Ql);
-      pw = pw * q;
-    }
-    tot += mk[2 * P] * 0.5 * log(dd) - ser.x - 0.5 * mk[2 * P + 1];
+    // sum_l q^l Q_k[l] / l by Horner's rule over the scaled moments
+    const double *mk = mom + k;
+    cx<double> ser{mk[(int64_t)(2 * (P - 1)) * M], mk[(int64_t)(2 * (P - 1) + 1) * M]};
+#pragma unroll
+    for (int l = P - 1; l >= 1; --l)
+      ser = ser * q + cx<double>{mk[(int64_t)(2 * (l - 1)) * M],
+                                 mk[(int64_t)(2 * (l - 1) + 1) * M]};
+    ser = ser * q;
+    tot += Yk * 0.5 * log(dd) - ser.x - 0.5 * mk[(int64_t)(2 * P + 1) * M];
   }
   for (int e = 0; e < nn; ++e) {
     const int k = nl[e];
@@ -258,9 +278,9 @@ __global__ void __launch_bounds__(256)
 void launch_logsrc_T(const Geometry &g, const double *y, double *mom,
                      double alpha, double *out, hipStream_t s) {
   if (g.M == 0) return;
-  hipLaunchKernelGGL(k_island_moments, dim3(g.M), dim3(256), 0, s, g.doffs.p,
-                     g.xil.p, g.elll.p, g.rhol.p, y, mom);
-  hipLaunchKernelGGL(k_logsrc_T, dim3(g.M), dim3(256), 0, s, g.isl_geo.p,
+  hipLaunchKernelGGL(k_island_moments, dim3(g.M, 2), dim3(64), 0, s, g.M,
+                     g.doffs.p, g.xil.p, g.elll.p, g.rhol.p, y, mom);
+  hipLaunchKernelGGL(k_logsrc_T, dim3(g.M), dim3(256), 0, s, g.M, g.isl_geo.p,
                      g.dgisl.p, g.doffs.p, g.dcenter.p, g.frame.p, g.rhol.p,
                      g.xyz.p, g.nearRT_ptr.p, g.nearRT_idx.p, mom, y, alpha,
                      out);

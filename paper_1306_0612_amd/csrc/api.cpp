@@ -259,7 +259,7 @@ struct EvalPlan {
 struct AdjState {
   bool ready = false;
   DBuf<double> ones;   // max(N, M) ones (segment sums)
-  DBuf<double> mom;    // island moments, M x kMomStride
+  DBuf<double> mom;    // island moments, slot-major (kMomStride x M)
   DBuf<double> tA;     // M
   DBuf<double> lam;    // N + M
   DBuf<double> pc, Fc; // complex, N x 2

@@ -308,6 +308,7 @@ void launch_segdots(const SegPlan &sp, int R, int nvec, const double *a,
                     double *out, double *scratch, hipStream_t s);
 
 // log sources and constraint rows (solver.hip)
+// out += alpha E z
 void launch_logsrc_apply(const Geometry &g, Workspace &ws, const double *z,
                          int64_t ldz, int nrhs, double *out, int64_t ldo,
                          double alpha, hipStream_t s);
@@ -362,7 +363,7 @@ void launch_scale_sqrt(int S, double t, const double *nrm2, double *out,
                        hipStream_t s);
 
 // transposed operators and shape derivatives (adjoint.hip)
-constexpr int kMomStride = 2 * kPlog + 2;  // island moments per island
+constexpr int kMomStride = 2 * kPlog + 2;  // moment slots per island
 void launch_kT_assemble(const Geometry &g, const double *y, const double *F,
                         const double *ysum, double ident, double *out,
                         hipStream_t s);

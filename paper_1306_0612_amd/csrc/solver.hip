@@ -15,10 +15,13 @@ namespace lbs {
 constexpr double kInvPi = 0.31830988618379067154;
 constexpr double kLog2 = 0.69314718055994530942;
 
-__device__ __forceinline__ double wave_sum(double v) {
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+
+__device__ __forceinline__ double tlog(double x) { return log(x); }
 
 // ------------------------------------------------------------ log sources
 // (E z)_i = sum_m 2 z_m G(x_i, c_m),  G(x, y) = -(1/2pi) log|x - y| + log2/4pi
@@ -41,7 +44,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 // frame an island is a disk of radius about tan(r/2) at the origin, so the
 // near lists hold only the neighbouring islands wherever the island lies
 // on the sphere.
-constexpr int kLogStride = 2 * (kPlog + 1) + 2;
+//
+// kPlog = 30 terms ((1/3)^30 ~ 5e-15), in FP64: the block preconditioner
+// multiplies E by z = S^-1 (...), whose entries are large and cancel in
+// E z, so FP32 sums here perturb P^-1 well beyond FP32 rounding (measured:
+// more refinement steps).  Per island the coefficients are stored as
+// [L0, 0, L1, ..., LP, Z_far, Z_total] (2 (P + 1) + 2 values of type T).
+template <int P>
+constexpr int log_stride() { return 2 * (P + 1) + 2; }
 
 __device__ __forceinline__ bool in_sorted(const int32_t *a, int n, int x) {
   int lo = 0, hi = n;
@@ -53,7 +63,12 @@ __device__ __forceinline__ bool in_sorted(const int32_t *a, int n, int x) {
   return lo < n && a[lo] == x;
 }
 
-// L_k for every island k (block per island, threads over the centres)
+// L_k for every island k (blocks per island, threads over the centres);
+// centre geometry in FP64, the series and the sums in T.  The P series
+// terms are split over H blocks (blockIdx.z) of PH = P / H terms each, to
+// bound the accumulator registers; block h starts from z q^(h PH + 1) by
+// repeated squaring, and block 0 also forms L0, Z_far and Z_total.
+template <typename T, int P, int H>
 __global__ void __launch_bounds__(128)
     k_logsrc_local(int M, const int32_t *__restrict__ isl_geo,
                    const int32_t *__restrict__ gisl,
@@ -63,10 +78,13 @@ __global__ void __launch_bounds__(128)
                    const int32_t *__restrict__ near_ptr,
                    const int32_t *__restrict__ near_idx,
                    const double *__restrict__ z, int64_t ldz,
-                   double *__restrict__ Lout) {
-  constexpr int P = kPlog;
-  __shared__ double red[2][kLogStride];
-  const int k = blockIdx.x, r = blockIdx.y;
+                   T *__restrict__ Lout) {
+  constexpr int stride = log_stride<P>();
+  constexpr int PH = P / H;
+  static_assert(PH * H == P, "terms must split evenly");
+  __shared__ T red[2][stride];
+  const int k = blockIdx.x, r = blockIdx.y, h = blockIdx.z;
+  const int l0 = h * PH;  // first term (power l0 + 1) of this block
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
   const int g = isl_geo[k];
   const int m0 = gisl[g], m1 = gisl[g + 1];
@@ -76,12 +94,12 @@ __global__ void __launch_bounds__(128)
   const int32_t *nl = near_idx + near_ptr[k];
   const int nn = near_ptr[k + 1] - near_ptr[k];
   const double *zr = z + (int64_t)r * ldz;
-  cx<double> acc[P];
+  cx<T> acc[PH];
 #pragma unroll
-  for (int l = 0; l < P; ++l) acc[l] = cx<double>{0.0, 0.0};
-  double a0 = 0.0, zf = 0.0, zt = 0.0;
+  for (int l = 0; l < PH; ++l) acc[l] = cx<T>{T(0), T(0)};
+  T a0 = 0, zf = 0, zt = 0;
   for (int m = m0 + tid; m < m1; m += 128) {
-    const double zm = zr[m];
+    const T zm = T(zr[m]);
     zt += zm;
     if (in_sorted(nl, nn, m)) continue;
     const double x0 = cxyz[3 * m], x1 = cxyz[3 * m + 1], x2 = cxyz[3 * m + 2];
@@ -89,39 +107,52 @@ __global__ void __launch_bounds__(128)
     const double dd = d0 * d0 + d1 * d1 + d2 * d2;
     const double a = x0 * fr[0] + x1 * fr[1] + x2 * fr[2];
     const double b = x0 * fr[3] + x1 * fr[4] + x2 * fr[5];
-    zf += zm;
-    a0 += zm * 0.5 * log(dd);
     const double f = rk2 / dd;
-    const cx<double> q{a * f, -b * f};
-    cx<double> pw = zm * q;
+    const cx<T> q{T(a * f), T(-b * f)};
+    cx<T> pw = zm * q;
+    if (h == 0) {
+      zf += zm;
+      a0 += zm * T(0.5) * tlog(T(dd));
+    } else {
+      cx<T> base = q;  // pw = zm q^(l0 + 1)
+      for (int e = l0; e > 0; e >>= 1) {
+        if (e & 1) pw = pw * base;
+        base = base * base;
+      }
+    }
 #pragma unroll
-    for (int l = 0; l < P; ++l) {
+    for (int l = 0; l < PH; ++l) {
       acc[l] = acc[l] + pw;
       pw = pw * q;
     }
   }
-  auto put = [&](int slot, double v) {
+  auto put = [&](int slot, T v) {
     v = wave_sum(v);
     if (ln == 0) red[wv][slot] = v;
   };
-  put(0, a0);
-  put(1, 0.0);
-#pragma unroll
-  for (int l = 0; l < P; ++l) {
-    put(2 * (l + 1), acc[l].x);
-    put(2 * (l + 1) + 1, acc[l].y);
+  if (h == 0) {
+    put(0, a0);
+    put(1, T(0));
+    put(2 * (P + 1), zf);
+    put(2 * (P + 1) + 1, zt);
   }
-  put(2 * (P + 1), zf);
-  put(2 * (P + 1) + 1, zt);
+#pragma unroll
+  for (int l = 0; l < PH; ++l) {
+    put(2 * (l0 + l + 1), acc[l].x);
+    put(2 * (l0 + l + 1) + 1, acc[l].y);
+  }
   __syncthreads();
-  double *out = Lout + ((int64_t)r * M + k) * kLogStride;
-  for (int s = tid; s < kLogStride; s += 128) {
-    double v = red[0][s] + red[1][s];
-    if (s >= 2 && s < 2 * (P + 1)) v *= -1.0 / (double)(s / 2);  // -q^l / l
+  T *out = Lout + ((int64_t)r * M + k) * stride;
+  for (int s = tid; s < stride; s += 128) {
+    const bool term = s >= 2 && s < 2 * (P + 1);
+    if (term ? (s / 2 - 1) / PH != h : h != 0) continue;  // another block's
+    T v = red[0][s] + red[1][s];
+    if (term) v *= T(-1) / T(s / 2);  // -q^l / l
     out[s] = v;
   }
 }
 
+template <typename T, int P>
 __global__ void k_logsrc_node(int64_t N, int M, const int32_t *__restrict__ island,
                               const double *__restrict__ xil,
                               const double *__restrict__ xyz,
@@ -131,29 +162,30 @@ __global__ void k_logsrc_node(int64_t N, int M, const int32_t *__restrict__ isla
                               const int32_t *__restrict__ near_ptr,
                               const int32_t *__restrict__ near_idx,
                               const double *__restrict__ z, int64_t ldz,
-                              const double *__restrict__ Lc,
+                              const T *__restrict__ Lc,
                               double *__restrict__ out, int64_t ldo,
                               double alpha) {
-  constexpr int P = kPlog;
+  constexpr int stride = log_stride<P>();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (i >= N) return;
   const int k = island[i];
-  const double *L = Lc + ((int64_t)r * M + k) * kLogStride;
+  const T *L = Lc + ((int64_t)r * M + k) * stride;
   const double ir = 1.0 / rhol[k];
-  const cx<double> u{xil[2 * i] * ir, xil[2 * i + 1] * ir};
-  cx<double> s{L[2 * P], L[2 * P + 1]};
-  for (int l = P - 1; l >= 0; --l) s = s * u + cx<double>{L[2 * l], L[2 * l + 1]};
-  double tot = s.x - 0.5 * L[2 * (P + 1)] * elll[i];
+  const cx<T> u{T(xil[2 * i] * ir), T(xil[2 * i + 1] * ir)};
+  cx<T> s{L[2 * P], L[2 * P + 1]};
+  for (int l = P - 1; l >= 0; --l) s = s * u + cx<T>{L[2 * l], L[2 * l + 1]};
+  T tot = s.x - T(0.5) * L[2 * (P + 1)] * T(elll[i]);
   const double x0 = xyz[3 * i], x1 = xyz[3 * i + 1], x2 = xyz[3 * i + 2];
   const double *zr = z + (int64_t)r * ldz;
   for (int e = near_ptr[k]; e < near_ptr[k + 1]; ++e) {
     const int m = near_idx[e];
     const double d0 = x0 - cxyz[3 * m], d1 = x1 - cxyz[3 * m + 1],
                  d2 = x2 - cxyz[3 * m + 2];
-    tot += zr[m] * 0.5 * log(d0 * d0 + d1 * d1 + d2 * d2);
+    tot += T(zr[m]) * T(0.5) * tlog(T(d0 * d0 + d1 * d1 + d2 * d2));
   }
-  const double ez = -kInvPi * tot + kLog2 * 0.5 * kInvPi * L[2 * (P + 1) + 1];
+  const double ez = -kInvPi * (double)tot +
+                    kLog2 * 0.5 * kInvPi * (double)L[2 * (P + 1) + 1];
   out[(int64_t)r * ldo + i] += alpha * ez;
 }
 
@@ -175,7 +207,8 @@ __global__ void __launch_bounds__(256)
                          const double *__restrict__ z,
                          double *__restrict__ Lout) {
   constexpr int P = kPlog;
-  __shared__ double red[4][kLogStride];
+  constexpr int stride = log_stride<kPlog>();
+  __shared__ double red[4][stride];
   const int k = blockIdx.x;
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
   const int g = isl_geo[k];
@@ -218,8 +251,8 @@ __global__ void __launch_bounds__(256)
   put(2 * (P + 1), zf);
   put(2 * (P + 1) + 1, zt);
   __syncthreads();
-  double *out = Lout + (int64_t)k * kLogStride;
-  for (int s = tid; s < kLogStride; s += 256) {
+  double *out = Lout + (int64_t)k * stride;
+  for (int s = tid; s < stride; s += 256) {
     double v = red[0][s] + red[1][s] + red[2][s] + red[3][s];
     if (s >= 2 && s < 2 * (P + 1)) v *= -1.0 / (double)(s / 2);
     out[s] = v;
@@ -236,17 +269,28 @@ void launch_logsrc_local(const Geometry &g, Workspace &ws, const double *z,
   LBS_HIP(hipGetLastError());
 }
 
+template <typename T, int P, int H>
+static void logsrc_apply(const Geometry &g, T *Lbuf, const double *z,
+                         int64_t ldz, int nrhs, double *out, int64_t ldo,
+                         double alpha, hipStream_t s) {
+  hipLaunchKernelGGL((k_logsrc_local<T, P, H>), dim3(g.M, nrhs, H), dim3(128),
+                     0, s,
+                     g.M, g.isl_geo.p, g.dgisl.p, g.dcenter.p, g.frame.p,
+                     g.rhol.p, g.nearR_ptr.p, g.nearR_idx.p, z, ldz, Lbuf);
+  hipLaunchKernelGGL((k_logsrc_node<T, P>),
+                     dim3((unsigned)((g.N + 255) / 256), nrhs), dim3(256), 0,
+                     s, g.N, g.M, g.island.p, g.xil.p, g.xyz.p, g.elll.p,
+                     g.rhol.p, g.dcenter.p, g.nearR_ptr.p, g.nearR_idx.p, z,
+                     ldz, Lbuf, out, ldo, alpha);
+}
+
 void launch_logsrc_apply(const Geometry &g, Workspace &ws, const double *z,
                          int64_t ldz, int nrhs, double *out, int64_t ldo,
                          double alpha, hipStream_t s) {
   if (g.M == 0 || g.N == 0) return;
-  hipLaunchKernelGGL(k_logsrc_local, dim3(g.M, nrhs), dim3(128), 0, s, g.M,
-                     g.isl_geo.p, g.dgisl.p, g.dcenter.p, g.frame.p, g.rhol.p,
-                     g.nearR_ptr.p, g.nearR_idx.p, z, ldz, ws.logL.p);
-  hipLaunchKernelGGL(k_logsrc_node, dim3((unsigned)((g.N + 255) / 256), nrhs),
-                     dim3(256), 0, s, g.N, g.M, g.island.p, g.xil.p, g.xyz.p,
-                     g.elll.p, g.rhol.p, g.dcenter.p, g.nearR_ptr.p,
-                     g.nearR_idx.p, z, ldz, ws.logL.p, out, ldo, alpha);
+  // two blocks of 15 terms per island: 114 instead of 192 VGPRs
+  logsrc_apply<double, kPlog, 2>(g, ws.logL.p, z, ldz, nrhs, out, ldo, alpha,
+                                 s);
   LBS_HIP(hipGetLastError());
 }
 

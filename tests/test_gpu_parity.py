@@ -118,6 +118,9 @@ def test_system_and_preconditioned_ops(env):
     ref = x + np.concatenate([zs, za])
     y = _np(sol.matvec(_t(torch, x), "precond", "fp64"))
     assert _rel(y, ref) < 1e-10
+    # mixed: K by the FP32 FMM, P^-1 in FP64
+    y = _np(sol.matvec(_t(torch, x), "precond", "mixed"))
+    assert _rel(y, ref) < 1e-6
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
