@@ -212,67 +212,119 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// (E^T y)_m for a tile of TM consecutive centres m per block: threads over
+// the islands k of the geometry, the series ratios q_km and h_km from the
+// dense table Geometry::farT_*, each moment Q_k[l] read once and applied to
+// the TM Horner chains; k near m (m's transposed near list, ascending) is
+// left to the direct sum over its nodes.
+template <int TM>
 __global__ void __launch_bounds__(256)
     k_logsrc_T(int M, const int32_t *__restrict__ isl_geo,
                const int32_t *__restrict__ gisl,
                const int64_t *__restrict__ offs,
                const double *__restrict__ cxyz,
-               const double *__restrict__ frame,
-               const double *__restrict__ rhol,
                const double *__restrict__ xyz,
                const int32_t *__restrict__ nearT_ptr,
                const int32_t *__restrict__ nearT_idx,
+               const int64_t *__restrict__ farT_ofs,
+               const double *__restrict__ farT_q,
+               const double *__restrict__ farT_h,
                const double *__restrict__ mom, const double *__restrict__ y,
                double alpha, double *__restrict__ out) {
   constexpr int P = kPlog;
-  __shared__ double red[4];
-  const int m = blockIdx.x;
-  const int tid = threadIdx.x, ln = tid & 63;
-  const int g = isl_geo[m];
-  const double x0 = cxyz[3 * m], x1 = cxyz[3 * m + 1], x2 = cxyz[3 * m + 2];
-  const int32_t *nl = nearT_idx + nearT_ptr[m];
-  const int nn = nearT_ptr[m + 1] - nearT_ptr[m];
-  double tot = 0.0, ysum = 0.0;
-  for (int k = gisl[g] + tid; k < gisl[g + 1]; k += 256) {
-    const double Yk = mom[(int64_t)(2 * P) * M + k];
-    ysum += Yk;
-    if (in_sorted(nl, nn, k)) continue;
-    const double *fr = frame + 6 * k;
-    const double d0 = x0 - cxyz[3 * k], d1 = x1 - cxyz[3 * k + 1],
-                 d2 = x2 - cxyz[3 * k + 2];
-    const double dd = d0 * d0 + d1 * d1 + d2 * d2;
-    const double a = x0 * fr[0] + x1 * fr[1] + x2 * fr[2];
-    const double b = x0 * fr[3] + x1 * fr[4] + x2 * fr[5];
-    const double f = 2.0 * rhol[k] / dd;
-    const cx<double> q{a * f, -b * f};
-    // sum_l q^l Q_k[l] / l by Horner's rule over the scaled moments
-    const double *mk = mom + k;
-    cx<double> ser{mk[(int64_t)(2 * (P - 1)) * M], mk[(int64_t)(2 * (P - 1) + 1) * M]};
+  __shared__ double red[4][2 * TM];
+  const int mb = blockIdx.x * TM;
+  const int tid = threadIdx.x, ln = tid & 63, wv = tid >> 6;
+  // the tile's centres: geometry ranges, table rows, near-list cursors
+  int ka[TM], kb[TM], np[TM], ne[TM];
+  int64_t row[TM];
+  int klo = M, khi = 0;
 #pragma unroll
-    for (int l = P - 1; l >= 1; --l)
-      ser = ser * q + cx<double>{mk[(int64_t)(2 * (l - 1)) * M],
-                                 mk[(int64_t)(2 * (l - 1) + 1) * M]};
-    ser = ser * q;
-    tot += Yk * 0.5 * log(dd) - ser.x - 0.5 * mk[(int64_t)(2 * P + 1) * M];
-  }
-  for (int e = 0; e < nn; ++e) {
-    const int k = nl[e];
-    for (int64_t i = offs[k] + tid; i < offs[k + 1]; i += 256) {
-      const double d0 = xyz[3 * i] - x0, d1 = xyz[3 * i + 1] - x1,
-                   d2 = xyz[3 * i + 2] - x2;
-      tot += y[i] * 0.5 * log(d0 * d0 + d1 * d1 + d2 * d2);
+  for (int t = 0; t < TM; ++t) {
+    const int m = mb + t;
+    if (m < M) {
+      const int g = isl_geo[m];
+      ka[t] = gisl[g];
+      kb[t] = gisl[g + 1];
+      row[t] = farT_ofs[g] + (int64_t)(m - ka[t]) * (kb[t] - ka[t]) - ka[t];
+      np[t] = nearT_ptr[m];
+      ne[t] = nearT_ptr[m + 1];
+      klo = min(klo, ka[t]);
+      khi = max(khi, kb[t]);
+    } else {
+      ka[t] = kb[t] = 0;
+      row[t] = 0;
+      np[t] = ne[t] = 0;
     }
   }
-  tot = wsum(tot);
-  ysum = wsum(ysum);
-  if (ln == 0) red[tid >> 6] = tot;
+  double tot[TM], ysum[TM];
+#pragma unroll
+  for (int t = 0; t < TM; ++t) tot[t] = ysum[t] = 0.0;
+  for (int k = klo + tid; k < khi; k += 256) {
+    const double *mk = mom + k;
+    const double Yk = mk[(int64_t)(2 * P) * M], Ek = mk[(int64_t)(2 * P + 1) * M];
+    cx<double> q[TM], ser[TM];
+    double hk[TM], w[TM];
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const bool in = k >= ka[t] && k < kb[t];
+      if (in) ysum[t] += Yk;
+      while (np[t] < ne[t] && nearT_idx[np[t]] < k) ++np[t];
+      const bool far = in && !(np[t] < ne[t] && nearT_idx[np[t]] == k);
+      const int64_t e = far ? row[t] + k : 0;
+      q[t] = far ? cx<double>{farT_q[2 * e], farT_q[2 * e + 1]} : cx<double>{0.0, 0.0};
+      hk[t] = far ? farT_h[e] : 0.0;
+      w[t] = far ? 1.0 : 0.0;
+      ser[t] = cx<double>{mk[(int64_t)(2 * (P - 1)) * M], mk[(int64_t)(2 * (P - 1) + 1) * M]};
+    }
+    // sum_l q^l Q_k[l] / l by Horner's rule over the scaled moments
+#pragma unroll
+    for (int l = P - 1; l >= 1; --l) {
+      const cx<double> Ql{mk[(int64_t)(2 * (l - 1)) * M], mk[(int64_t)(2 * (l - 1) + 1) * M]};
+#pragma unroll
+      for (int t = 0; t < TM; ++t) ser[t] = cfma(ser[t], q[t], Ql);
+    }
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+      tot[t] += w[t] * (Yk * hk[t] - (ser[t] * q[t]).x - 0.5 * Ek);
+  }
+#pragma unroll
+  for (int t = 0; t < TM; ++t) {
+    const double a = wsum(tot[t]), b = wsum(ysum[t]);
+    if (ln == 0) {
+      red[wv][2 * t] = a;
+      red[wv][2 * t + 1] = b;
+    }
+  }
   __syncthreads();
-  double t4 = red[0] + red[1] + red[2] + red[3];
-  __syncthreads();
-  if (ln == 0) red[tid >> 6] = ysum;
-  __syncthreads();
-  const double ys4 = red[0] + red[1] + red[2] + red[3];
-  if (tid == 0) out[m] = alpha * (-kInvPi_ * t4 + 0.5 * kInvPi_ * kLog2_ * ys4);
+  // near islands directly, one centre after another
+#pragma unroll 1
+  for (int t = 0; t < TM; ++t) {
+    const int m = mb + t;
+    if (m >= M) break;  // block-uniform
+    const double x0 = cxyz[3 * m], x1 = cxyz[3 * m + 1], x2 = cxyz[3 * m + 2];
+    double acc = 0.0;
+    for (int e = nearT_ptr[m]; e < nearT_ptr[m + 1]; ++e) {
+      const int k = nearT_idx[e];
+      for (int64_t i = offs[k] + tid; i < offs[k + 1]; i += 256) {
+        const double d0 = xyz[3 * i] - x0, d1 = xyz[3 * i + 1] - x1,
+                     d2 = xyz[3 * i + 2] - x2;
+        acc += y[i] * 0.5 * log(d0 * d0 + d1 * d1 + d2 * d2);
+      }
+    }
+    acc = wsum(acc);
+    __shared__ double rn[4];
+    if (ln == 0) rn[wv] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      const double t4 = red[0][2 * t] + red[1][2 * t] + red[2][2 * t] + red[3][2 * t] +
+                        rn[0] + rn[1] + rn[2] + rn[3];
+      const double ys4 = red[0][2 * t + 1] + red[1][2 * t + 1] + red[2][2 * t + 1] +
+                         red[3][2 * t + 1];
+      out[m] = alpha * (-kInvPi_ * t4 + 0.5 * kInvPi_ * kLog2_ * ys4);
+    }
+    __syncthreads();
+  }
 }
 
 void launch_logsrc_T(const Geometry &g, const double *y, double *mom,
@@ -280,10 +332,11 @@ void launch_logsrc_T(const Geometry &g, const double *y, double *mom,
   if (g.M == 0) return;
   hipLaunchKernelGGL(k_island_moments, dim3(g.M, 2), dim3(64), 0, s, g.M,
                      g.doffs.p, g.xil.p, g.elll.p, g.rhol.p, y, mom);
-  hipLaunchKernelGGL(k_logsrc_T, dim3(g.M), dim3(256), 0, s, g.M, g.isl_geo.p,
-                     g.dgisl.p, g.doffs.p, g.dcenter.p, g.frame.p, g.rhol.p,
-                     g.xyz.p, g.nearRT_ptr.p, g.nearRT_idx.p, mom, y, alpha,
-                     out);
+  constexpr int TM = 4;
+  hipLaunchKernelGGL(k_logsrc_T<TM>, dim3((g.M + TM - 1) / TM), dim3(256), 0, s,
+                     g.M, g.isl_geo.p, g.dgisl.p, g.doffs.p, g.dcenter.p,
+                     g.xyz.p, g.nearRT_ptr.p, g.nearRT_idx.p, g.farT_ofs.p,
+                     g.farT_q.p, g.farT_h.p, mom, y, alpha, out);
   LBS_HIP(hipGetLastError());
 }
 

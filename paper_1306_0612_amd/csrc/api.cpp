@@ -570,6 +570,144 @@ void check_handle(lbs_handle h) {
   if (!h) fail(LBS_ERR_INVALID_ARG, "null handle");
 }
 
+// Terms P of the far-field log series that keep its tail
+// sum_{l > P} r^l / l <= r^(P + 1) / ((P + 1)(1 - r)) below 2.5e-16 (the
+// bound of the full kPlog terms at the far limit r = 1/3).
+int log_terms(double r) {
+  if (!(r > 0)) return 1;
+  double t = r * r / (2.0 * (1.0 - r));
+  int P = 1;
+  while (t > 2.5e-16 && P < kPlog) {
+    t *= r * (double)(P + 1) / (double)(P + 2);
+    ++P;
+  }
+  return P;
+}
+
+// Far lists of the island-frame log-source expansions (see Geometry):
+// every pair (k, m) of a geometry with m not in k's near list rp/ri.
+void build_far_lists(Geometry &g, const std::vector<int32_t> &isl_geo,
+                     const std::vector<double> &rl, const std::vector<double> &fr,
+                     const std::vector<int32_t> &rp, const std::vector<int32_t> &ri,
+                     hipStream_t s) {
+  const int M = g.M;
+  std::vector<int64_t> fp(M + 1, 0);
+  for (int k = 0; k < M; ++k) {
+    const int q = isl_geo[k];
+    fp[k + 1] = fp[k] + (g.gisl[q + 1] - g.gisl[q]) - (rp[k + 1] - rp[k]);
+  }
+  const int64_t nf = fp[M];
+  std::vector<int32_t> fidx(nf);
+  std::vector<double> fq(2 * nf), fh(nf), fa(nf);
+  parallel_for(
+      M,
+      [&](int64_t k0, int64_t k1) {
+        std::vector<int64_t> ord;
+        std::vector<int32_t> ti;
+        std::vector<double> tq, th, ta;
+        for (int64_t k = k0; k < k1; ++k) {
+          const int q = isl_geo[k];
+          const double *ck = &g.cxyz[3 * k], *f = &fr[6 * k];
+          const double rk2 = 2.0 * rl[k];
+          int64_t e = fp[k];
+          int32_t ne = rp[k];
+          for (int m = g.gisl[q]; m < g.gisl[q + 1]; ++m) {
+            if (ne < rp[k + 1] && ri[ne] == m) {  // near lists ascend in m
+              ++ne;
+              continue;
+            }
+            const double x0 = g.cxyz[3 * m], x1 = g.cxyz[3 * m + 1], x2 = g.cxyz[3 * m + 2];
+            const double d0 = x0 - ck[0], d1 = x1 - ck[1], d2 = x2 - ck[2];
+            const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+            const double a = x0 * f[0] + x1 * f[1] + x2 * f[2];
+            const double b = x0 * f[3] + x1 * f[4] + x2 * f[5];
+            const double ff = rk2 / dd;
+            fidx[e] = m;
+            fq[2 * e] = a * ff;
+            fq[2 * e + 1] = -b * ff;
+            fh[e] = 0.5 * std::log(dd);
+            fa[e] = std::hypot(a * ff, b * ff);
+            ++e;
+          }
+          const int64_t a0 = fp[k], n = fp[k + 1] - a0;
+          ord.resize(n);
+          for (int64_t i = 0; i < n; ++i) ord[i] = a0 + i;
+          std::sort(ord.begin(), ord.end(), [&](int64_t u, int64_t v) {
+            return fa[u] != fa[v] ? fa[u] > fa[v] : fidx[u] < fidx[v];
+          });
+          ti.resize(n);
+          tq.resize(2 * n);
+          th.resize(n);
+          ta.resize(n);
+          for (int64_t i = 0; i < n; ++i) {
+            ti[i] = fidx[ord[i]];
+            tq[2 * i] = fq[2 * ord[i]];
+            tq[2 * i + 1] = fq[2 * ord[i] + 1];
+            th[i] = fh[ord[i]];
+            ta[i] = fa[ord[i]];
+          }
+          std::copy(ti.begin(), ti.end(), fidx.begin() + a0);
+          std::copy(tq.begin(), tq.end(), fq.begin() + 2 * a0);
+          std::copy(th.begin(), th.end(), fh.begin() + a0);
+          std::copy(ta.begin(), ta.end(), fa.begin() + a0);
+        }
+      },
+      64);
+  auto chunks = [&](const std::vector<int64_t> &ptr, const std::vector<double> &mag,
+                    std::vector<int64_t> &cptr, std::vector<int32_t> &nt) {
+    cptr.assign(M + 1, 0);
+    for (int k = 0; k < M; ++k)
+      cptr[k + 1] = cptr[k] + (ptr[k + 1] - ptr[k] + kLogChunk - 1) / kLogChunk;
+    nt.assign(cptr[M], 0);
+    for (int k = 0; k < M; ++k)
+      for (int64_t c = cptr[k]; c < cptr[k + 1]; ++c)
+        nt[c] = log_terms(mag[ptr[k] + (c - cptr[k]) * kLogChunk]);
+  };
+  std::vector<int64_t> fc;
+  std::vector<int32_t> fnt;
+  chunks(fp, fa, fc, fnt);
+  // dense per geometry, row m: (q_km, h_km) for every island k of m's
+  // geometry (near pairs included; the transposed kernel skips them)
+  std::vector<int64_t> tofs(g.G + 1, 0);
+  for (int q = 0; q < g.G; ++q) {
+    const int64_t mq = g.gisl[q + 1] - g.gisl[q];
+    tofs[q + 1] = tofs[q] + mq * mq;
+  }
+  const int64_t nt = tofs[g.G];
+  std::vector<double> tq(2 * nt), th(nt);
+  parallel_for(
+      M,
+      [&](int64_t m0, int64_t m1) {
+        for (int64_t m = m0; m < m1; ++m) {
+          const int q = isl_geo[m], a = g.gisl[q];
+          const int64_t mq = g.gisl[q + 1] - a, row = tofs[q] + (m - a) * mq;
+          const double x0 = g.cxyz[3 * m], x1 = g.cxyz[3 * m + 1], x2 = g.cxyz[3 * m + 2];
+          for (int k = a; k < g.gisl[q + 1]; ++k) {
+            const double *ck = &g.cxyz[3 * k], *f = &fr[6 * k];
+            const double d0 = x0 - ck[0], d1 = x1 - ck[1], d2 = x2 - ck[2];
+            const double dd = std::max(d0 * d0 + d1 * d1 + d2 * d2, 1e-300);
+            const double ff = 2.0 * rl[k] / dd;
+            const int64_t e = row + (k - a);
+            tq[2 * e] = (x0 * f[0] + x1 * f[1] + x2 * f[2]) * ff;
+            tq[2 * e + 1] = -(x0 * f[3] + x1 * f[4] + x2 * f[5]) * ff;
+            th[e] = 0.5 * std::log(dd);
+          }
+        }
+      },
+      64);
+  g.far_ptr.upload(fp, s);
+  g.far_cptr.upload(fc, s);
+  g.far_nt.upload(fnt, s);
+  g.far_idx.upload(fidx, s);
+  g.far_q.upload(fq, s);
+  g.far_h.upload(fh, s);
+  g.farT_ofs.upload(tofs, s);
+  g.farT_q.upload(tq, s);
+  g.farT_h.upload(th, s);
+  // the host vectors must outlive the asynchronous copies
+  LBS_HIP(hipStreamSynchronize(s));
+}
+
 void validate_options(const lbs_options &o) {
   if (!p64_ok(o.p64)) fail(LBS_ERR_UNSUPPORTED, "p64 must be 20/24/30/36/40/48");
   if (!p32_ok(o.p32)) fail(LBS_ERR_UNSUPPORTED, "p32 must be 12/16/20/24");
@@ -772,6 +910,7 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl,
     std::vector<int32_t> fill(tp.begin(), tp.end() - 1);
     for (int k = 0; k < M; ++k)
       for (int e = rp[k]; e < rp[k + 1]; ++e) ti[fill[ri[e]]++] = k;
+    build_far_lists(g, isl_geo, rl, fr, rp, ri, s);
     g.rhol.upload(rl, s);
     g.frame.upload(fr, s);
     g.nearR_ptr.upload(rp, s);

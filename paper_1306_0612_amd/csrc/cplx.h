@@ -29,6 +29,19 @@ template <typename T>
 __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) {
   return cx<T>{s * a.x, s * a.y};
 }
+__device__ __forceinline__ float tfma(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+__device__ __forceinline__ double tfma(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+// a * b + c in four fused multiply-adds, x = a.x b.x + (c.x - a.y b.y),
+// y = a.x b.y + (c.y + a.y b.x): the step of a complex Horner scheme
+template <typename T>
+__device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> c) {
+  return cx<T>{tfma(a.x, b.x, tfma(-a.y, b.y, c.x)),
+               tfma(a.x, b.y, tfma(a.y, b.x, c.y))};
+}
 template <typename T>
 __device__ __forceinline__ cx<T> cinv(cx<T> a) {
   T d = T(1) / (a.x * a.x + a.y * a.y);

@@ -723,7 +723,7 @@ __global__ void __launch_bounds__(64, 8)
         const cx<double> w{(zx - cxv[b]) * ir_b, (zy - cyv[b]) * ir_b};
         const cx<double> *La = Lr + (int64_t)b * P;
         cx<double> acc = La[P - 1];
-        for (int l = P - 2; l >= 0; --l) acc = acc * w + La[l];
+        for (int l = P - 2; l >= 0; --l) acc = cfma(acc, w, La[l]);
         field += acc.x;
       }
       for (int e = wb + sl[c]; e < we; e += S[c]) {
@@ -732,7 +732,7 @@ __global__ void __launch_bounds__(64, 8)
         cx<double> rho = rad[cw] * cinv(d);
         const cx<double> *a = Mr + (int64_t)cw * P;
         cx<double> acc = a[P - 1];
-        for (int k = P - 2; k >= 0; --k) acc = acc * rho + a[k];
+        for (int k = P - 2; k >= 0; --k) acc = cfma(acc, rho, a[k]);
         field += (acc * rho).x;
       }
       fld[c] = field;
@@ -963,7 +963,7 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
             const cx<float> w{float((zx - cxv[b]) * ir_b), float((zy - cyv[b]) * ir_b)};
             const cx<float> *La = L + ((int64_t)r * nbox + b) * P;
             cx<float> acc = La[P - 1];
-            for (int l = P - 2; l >= 0; --l) acc = acc * w + La[l];
+            for (int l = P - 2; l >= 0; --l) acc = cfma(acc, w, La[l]);
             field += acc.x;
           }
           for (int e = wb + sl[c]; e < we; e += S[c]) {
@@ -973,7 +973,7 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
             const cx<float> rho{float(dx * id), float(-dy * id)};
             const cx<float> *a = M + ((int64_t)r * nbox + cw) * P;
             cx<float> acc = a[P - 1];
-            for (int k = P - 2; k >= 0; --k) acc = acc * rho + a[k];
+            for (int k = P - 2; k >= 0; --k) acc = cfma(acc, rho, a[k]);
             field += (acc * rho).x;
           }
         }
@@ -1208,10 +1208,10 @@ __global__ void __launch_bounds__(64)
       const cx<double> *Lb = L + (int64_t)b * P;
       cx<double> acc = Lb[P - 1], dacc = (double)(P - 1) * Lb[P - 1];
       for (int l = P - 2; l >= 1; --l) {
-        acc = acc * w + Lb[l];
+        acc = cfma(acc, w, Lb[l]);
         dacc = dacc * w + (double)l * Lb[l];
       }
-      acc = acc * w + Lb[0];
+      acc = cfma(acc, w, Lb[0]);
       f = f + acc;
       df = df + ir * dacc;
     }
@@ -1223,7 +1223,7 @@ __global__ void __launch_bounds__(64)
         const cx<double> *a = M + (int64_t)c * P;
         cx<double> acc = a[P - 1], dacc = (double)P * a[P - 1];
         for (int k = P - 2; k >= 0; --k) {
-          acc = acc * rho + a[k];
+          acc = cfma(acc, rho, a[k]);
           dacc = dacc * rho + (double)(k + 1) * a[k];
         }
         f = f + acc * rho;
@@ -1361,7 +1361,7 @@ __global__ void __launch_bounds__(64)
         const cx<float> w{float((zx - cxv[b]) * ir), float((zy - cyv[b]) * ir)};
         const cx<float> *La = L + (int64_t)b * P;
         cx<float> acc = La[P - 1];
-        for (int l = P - 2; l >= 0; --l) acc = acc * w + La[l];
+        for (int l = P - 2; l >= 0; --l) acc = cfma(acc, w, La[l]);
         f = f + acc;
       }
       for (int e = wb + sl; e < we; e += S) {
@@ -1371,7 +1371,7 @@ __global__ void __launch_bounds__(64)
         const cx<float> rho{float(dx * id), float(-dy * id)};
         const cx<float> *a = M + (int64_t)c * P;
         cx<float> acc = a[P - 1];
-        for (int k = P - 2; k >= 0; --k) acc = acc * rho + a[k];
+        for (int k = P - 2; k >= 0; --k) acc = cfma(acc, rho, a[k]);
         f = f + acc * rho;
       }
     }

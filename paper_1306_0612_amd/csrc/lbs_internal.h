@@ -216,6 +216,17 @@ struct Geometry {
   // transposed lists (islands having a centre as near), sorted
   DBuf<double> xil, elll, rhol, frame;
   DBuf<int32_t> nearR_ptr, nearR_idx, nearRT_ptr, nearRT_idx;
+  // far pairs (k, m) of the same geometry, m not near k, with the series
+  // ratio q_km = 2 rho'_k (a - i b) / |c_k - c_m|^2 (interleaved complex)
+  // and h_km = log|c_k - c_m|^2 / 2.  Grouped by k (far_*), each group
+  // sorted by |q| (largest first, ties by m), with per chunk of kLogChunk
+  // entries the number of series terms its first |q| needs (far_nt, chunk
+  // offsets far_cptr).  farT_*: dense per geometry (offset farT_ofs[g]),
+  // row m holding (q_km, h_km) for every island k of the geometry, near
+  // pairs included (their values are finite and unused).
+  DBuf<int64_t> far_ptr, far_cptr, farT_ofs;
+  DBuf<int32_t> far_idx, far_nt;
+  DBuf<double> far_q, far_h, farT_q, farT_h;
   DBuf<lbs_island> disl;             // island parameters
   DBuf<double> dsign;                // orientation sign per island
   DBuf<double> Sinv;                 // block-diagonal inverse Schur complement
@@ -245,6 +256,7 @@ struct Workspace {
 };
 
 constexpr int kPlog = 30;  // terms of the per-island log-source expansions
+constexpr int kLogChunk = 64;  // far-list entries per wave step
 
 // ----- launchers (HIP files) ------------------------------------------
 void build_tables(Tables &t, int P, hipStream_t s);

@@ -15,13 +15,10 @@ namespace lbs {
 constexpr double kInvPi = 0.31830988618379067154;
 constexpr double kLog2 = 0.69314718055994530942;
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
+__device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
-
-__device__ __forceinline__ double tlog(double x) { return log(x); }
 
 // ------------------------------------------------------------ log sources
 // (E z)_i = sum_m 2 z_m G(x_i, c_m),  G(x, y) = -(1/2pi) log|x - y| + log2/4pi
@@ -49,7 +46,7 @@ __device__ __forceinline__ double tlog(double x) { return log(x); }
 // multiplies E by z = S^-1 (...), whose entries are large and cancel in
 // E z, so FP32 sums here perturb P^-1 well beyond FP32 rounding (measured:
 // more refinement steps).  Per island the coefficients are stored as
-// [L0, 0, L1, ..., LP, Z_far, Z_total] (2 (P + 1) + 2 values of type T).
+// [L0, 0, L1, ..., LP, Z_far, Z_total] (2 (P + 1) + 2 doubles).
 template <int P>
 constexpr int log_stride() { return 2 * (P + 1) + 2; }
 
@@ -63,96 +60,119 @@ __device__ __forceinline__ bool in_sorted(const int32_t *a, int n, int x) {
   return lo < n && a[lo] == x;
 }
 
-// L_k for every island k (blocks per island, threads over the centres);
-// centre geometry in FP64, the series and the sums in T.  The P series
-// terms are split over H blocks (blockIdx.z) of PH = P / H terms each, to
-// bound the accumulator registers; block h starts from z q^(h PH + 1) by
-// repeated squaring, and block 0 also forms L0, Z_far and Z_total.
-template <typename T, int P, int H>
-__global__ void __launch_bounds__(128)
+// L_k for every island k from its far list (Geometry::far_*: the pairs,
+// q = rho'_k / eta' and log|c_k - c_m|, sorted by |q|, largest first).
+// One wave per (island, half of the series): half h sums the terms
+// h P/2 + 1 .. (h + 1) P/2 of every chunk whose |q| needs them, starting
+// from z q^(h P/2 + 1) by repeated squaring; half 0 also forms L0, Z_far
+// and Z_total.  A chunk needs the terms that keep the series tail below
+// the bound of the full P terms at the far limit |q| = 1/3.
+__global__ void __launch_bounds__(64)
     k_logsrc_local(int M, const int32_t *__restrict__ isl_geo,
                    const int32_t *__restrict__ gisl,
-                   const double *__restrict__ cxyz,
-                   const double *__restrict__ frame,
-                   const double *__restrict__ rhol,
-                   const int32_t *__restrict__ near_ptr,
-                   const int32_t *__restrict__ near_idx,
+                   const int64_t *__restrict__ far_ptr,
+                   const int64_t *__restrict__ far_cptr,
+                   const int32_t *__restrict__ far_nt,
+                   const int32_t *__restrict__ far_idx,
+                   const double *__restrict__ far_q,
+                   const double *__restrict__ far_h,
                    const double *__restrict__ z, int64_t ldz,
-                   T *__restrict__ Lout) {
-  constexpr int stride = log_stride<P>();
-  constexpr int PH = P / H;
-  static_assert(PH * H == P, "terms must split evenly");
-  __shared__ T red[2][stride];
+                   double *__restrict__ Lout) {
+  constexpr int P = kPlog, PH = P / 2, stride = log_stride<P>();
+  static_assert(2 * PH == P, "the series splits in two halves");
   const int k = blockIdx.x, r = blockIdx.y, h = blockIdx.z;
-  const int l0 = h * PH;  // first term (power l0 + 1) of this block
-  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
-  const int g = isl_geo[k];
-  const int m0 = gisl[g], m1 = gisl[g + 1];
-  const double c0 = cxyz[3 * k], c1 = cxyz[3 * k + 1], c2 = cxyz[3 * k + 2];
-  const double *fr = frame + 6 * k;
-  const double rk2 = 2.0 * rhol[k];
-  const int32_t *nl = near_idx + near_ptr[k];
-  const int nn = near_ptr[k + 1] - near_ptr[k];
+  const int ln = threadIdx.x;
+  const int l0 = h * PH;  // this half: powers l0 + 1 .. l0 + PH
   const double *zr = z + (int64_t)r * ldz;
-  cx<T> acc[PH];
+  double *out = Lout + ((int64_t)r * M + k) * stride;
+  const int64_t e0 = far_ptr[k], e1 = far_ptr[k + 1];
+  const int32_t *ntc = far_nt + far_cptr[k];
+  if (h > 0 && (e1 == e0 || ntc[0] <= l0)) {  // no chunk reaches this half
+    if (ln < PH) {
+      out[2 * (l0 + ln + 1)] = 0.0;
+      out[2 * (l0 + ln + 1) + 1] = 0.0;
+    }
+    return;
+  }
+  cx<double> acc[PH];
 #pragma unroll
-  for (int l = 0; l < PH; ++l) acc[l] = cx<T>{T(0), T(0)};
-  T a0 = 0, zf = 0, zt = 0;
-  for (int m = m0 + tid; m < m1; m += 128) {
-    const T zm = T(zr[m]);
-    zt += zm;
-    if (in_sorted(nl, nn, m)) continue;
-    const double x0 = cxyz[3 * m], x1 = cxyz[3 * m + 1], x2 = cxyz[3 * m + 2];
-    const double d0 = x0 - c0, d1 = x1 - c1, d2 = x2 - c2;
-    const double dd = d0 * d0 + d1 * d1 + d2 * d2;
-    const double a = x0 * fr[0] + x1 * fr[1] + x2 * fr[2];
-    const double b = x0 * fr[3] + x1 * fr[4] + x2 * fr[5];
-    const double f = rk2 / dd;
-    const cx<T> q{T(a * f), T(-b * f)};
-    cx<T> pw = zm * q;
-    if (h == 0) {
-      zf += zm;
-      a0 += zm * T(0.5) * tlog(T(dd));
-    } else {
-      cx<T> base = q;  // pw = zm q^(l0 + 1)
-      for (int e = l0; e > 0; e >>= 1) {
-        if (e & 1) pw = pw * base;
-        base = base * base;
+  for (int l = 0; l < PH; ++l) acc[l] = cx<double>{0.0, 0.0};
+  double a0 = 0.0, zf = 0.0;
+  const int nch = (int)((e1 - e0 + kLogChunk - 1) / kLogChunk);
+  // U chunks per step, their loads issued before any of them is used
+  constexpr int U = 8;
+  for (int c0 = 0; c0 < nch; c0 += U) {
+    int nt[U];
+    cx<double> q[U];
+    double hh[U], zm[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      // indices clamped into the list (nch >= 1 here); entries past the
+      // end or of chunks without terms for this half get zero weight
+      const int64_t j = e0 + (int64_t)(c0 + u) * kLogChunk + ln;
+      const int64_t jc = j < e1 ? j : e1 - 1;
+      const int nc = ntc[c0 + u < nch ? c0 + u : nch - 1] - l0;
+      nt[u] = c0 + u < nch ? nc : 0;  // wave-uniform
+      const bool ok = nt[u] > 0 && j < e1;
+      const int mi = far_idx[jc];
+      const cx<double> qi{far_q[2 * jc], far_q[2 * jc + 1]};
+      const double hi = far_h[jc], zi = zr[mi];
+      q[u] = ok ? qi : cx<double>{0.0, 0.0};
+      hh[u] = ok ? hi : 0.0;
+      zm[u] = ok ? zi : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (nt[u] <= 0) continue;  // wave-uniform
+      cx<double> pw = zm[u] * q[u];
+      if (h == 0) {
+        zf += zm[u];
+        a0 += zm[u] * hh[u];
+      } else {
+        cx<double> base = q[u];
+        for (int p = l0; p > 0; p >>= 1) {
+          if (p & 1) pw = pw * base;
+          base = base * base;
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < PH; ++l) {
+        if (l < nt[u]) {
+          acc[l] = acc[l] + pw;
+          pw = pw * q[u];
+        }
       }
     }
-#pragma unroll
-    for (int l = 0; l < PH; ++l) {
-      acc[l] = acc[l] + pw;
-      pw = pw * q;
-    }
-  }
-  auto put = [&](int slot, T v) {
-    v = wave_sum(v);
-    if (ln == 0) red[wv][slot] = v;
-  };
-  if (h == 0) {
-    put(0, a0);
-    put(1, T(0));
-    put(2 * (P + 1), zf);
-    put(2 * (P + 1) + 1, zt);
+    if (nt[U - 1] <= 0) break;  // later chunks need no more terms
   }
 #pragma unroll
   for (int l = 0; l < PH; ++l) {
-    put(2 * (l0 + l + 1), acc[l].x);
-    put(2 * (l0 + l + 1) + 1, acc[l].y);
+    const double sc = -1.0 / (double)(l0 + l + 1);  // -q^l / l
+    const double vx = wave_sum(acc[l].x), vy = wave_sum(acc[l].y);
+    if (ln == 0) {
+      out[2 * (l0 + l + 1)] = vx * sc;
+      out[2 * (l0 + l + 1) + 1] = vy * sc;
+    }
   }
-  __syncthreads();
-  T *out = Lout + ((int64_t)r * M + k) * stride;
-  for (int s = tid; s < stride; s += 128) {
-    const bool term = s >= 2 && s < 2 * (P + 1);
-    if (term ? (s / 2 - 1) / PH != h : h != 0) continue;  // another block's
-    T v = red[0][s] + red[1][s];
-    if (term) v *= T(-1) / T(s / 2);  // -q^l / l
-    out[s] = v;
+  if (h == 0) {
+    double zt = 0.0;
+    const int g = isl_geo[k];
+    for (int m = gisl[g] + ln; m < gisl[g + 1]; m += 64) zt += zr[m];
+    a0 = wave_sum(a0);
+    zf = wave_sum(zf);
+    zt = wave_sum(zt);
+    if (ln == 0) {
+      out[0] = a0;
+      out[1] = 0.0;
+      out[2 * (P + 1)] = zf;
+      out[2 * (P + 1) + 1] = zt;
+    }
   }
 }
 
-template <typename T, int P>
+// (E z)_i: the island's expansion at u = xi'_i / rho'_k (all P terms; the
+// coefficients beyond those its far list needs are zero), plus its near
+// centres directly
 __global__ void k_logsrc_node(int64_t N, int M, const int32_t *__restrict__ island,
                               const double *__restrict__ xil,
                               const double *__restrict__ xyz,
@@ -162,30 +182,30 @@ __global__ void k_logsrc_node(int64_t N, int M, const int32_t *__restrict__ isla
                               const int32_t *__restrict__ near_ptr,
                               const int32_t *__restrict__ near_idx,
                               const double *__restrict__ z, int64_t ldz,
-                              const T *__restrict__ Lc,
+                              const double *__restrict__ Lc,
                               double *__restrict__ out, int64_t ldo,
                               double alpha) {
-  constexpr int stride = log_stride<P>();
+  constexpr int P = kPlog, stride = log_stride<P>();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (i >= N) return;
   const int k = island[i];
-  const T *L = Lc + ((int64_t)r * M + k) * stride;
+  const double *L = Lc + ((int64_t)r * M + k) * stride;
   const double ir = 1.0 / rhol[k];
-  const cx<T> u{T(xil[2 * i] * ir), T(xil[2 * i + 1] * ir)};
-  cx<T> s{L[2 * P], L[2 * P + 1]};
-  for (int l = P - 1; l >= 0; --l) s = s * u + cx<T>{L[2 * l], L[2 * l + 1]};
-  T tot = s.x - T(0.5) * L[2 * (P + 1)] * T(elll[i]);
+  const cx<double> u{xil[2 * i] * ir, xil[2 * i + 1] * ir};
+  cx<double> s{L[2 * P], L[2 * P + 1]};
+#pragma unroll
+  for (int l = P - 1; l >= 0; --l) s = cfma(s, u, cx<double>{L[2 * l], L[2 * l + 1]});
+  double tot = s.x - 0.5 * L[2 * (P + 1)] * elll[i];
   const double x0 = xyz[3 * i], x1 = xyz[3 * i + 1], x2 = xyz[3 * i + 2];
   const double *zr = z + (int64_t)r * ldz;
   for (int e = near_ptr[k]; e < near_ptr[k + 1]; ++e) {
     const int m = near_idx[e];
     const double d0 = x0 - cxyz[3 * m], d1 = x1 - cxyz[3 * m + 1],
                  d2 = x2 - cxyz[3 * m + 2];
-    tot += T(zr[m]) * T(0.5) * tlog(T(d0 * d0 + d1 * d1 + d2 * d2));
+    tot += zr[m] * 0.5 * log(d0 * d0 + d1 * d1 + d2 * d2);
   }
-  const double ez = -kInvPi * (double)tot +
-                    kLog2 * 0.5 * kInvPi * (double)L[2 * (P + 1) + 1];
+  const double ez = -kInvPi * tot + kLog2 * 0.5 * kInvPi * L[2 * (P + 1) + 1];
   out[(int64_t)r * ldo + i] += alpha * ez;
 }
 
@@ -269,28 +289,18 @@ void launch_logsrc_local(const Geometry &g, Workspace &ws, const double *z,
   LBS_HIP(hipGetLastError());
 }
 
-template <typename T, int P, int H>
-static void logsrc_apply(const Geometry &g, T *Lbuf, const double *z,
-                         int64_t ldz, int nrhs, double *out, int64_t ldo,
-                         double alpha, hipStream_t s) {
-  hipLaunchKernelGGL((k_logsrc_local<T, P, H>), dim3(g.M, nrhs, H), dim3(128),
-                     0, s,
-                     g.M, g.isl_geo.p, g.dgisl.p, g.dcenter.p, g.frame.p,
-                     g.rhol.p, g.nearR_ptr.p, g.nearR_idx.p, z, ldz, Lbuf);
-  hipLaunchKernelGGL((k_logsrc_node<T, P>),
-                     dim3((unsigned)((g.N + 255) / 256), nrhs), dim3(256), 0,
-                     s, g.N, g.M, g.island.p, g.xil.p, g.xyz.p, g.elll.p,
-                     g.rhol.p, g.dcenter.p, g.nearR_ptr.p, g.nearR_idx.p, z,
-                     ldz, Lbuf, out, ldo, alpha);
-}
-
 void launch_logsrc_apply(const Geometry &g, Workspace &ws, const double *z,
                          int64_t ldz, int nrhs, double *out, int64_t ldo,
                          double alpha, hipStream_t s) {
   if (g.M == 0 || g.N == 0) return;
-  // two blocks of 15 terms per island: 114 instead of 192 VGPRs
-  logsrc_apply<double, kPlog, 2>(g, ws.logL.p, z, ldz, nrhs, out, ldo, alpha,
-                                 s);
+  hipLaunchKernelGGL(k_logsrc_local, dim3(g.M, nrhs, 2), dim3(64), 0, s, g.M,
+                     g.isl_geo.p, g.dgisl.p, g.far_ptr.p, g.far_cptr.p,
+                     g.far_nt.p, g.far_idx.p, g.far_q.p, g.far_h.p, z, ldz,
+                     ws.logL.p);
+  hipLaunchKernelGGL(k_logsrc_node, dim3((unsigned)((g.N + 255) / 256), nrhs),
+                     dim3(256), 0, s, g.N, g.M, g.island.p, g.xil.p, g.xyz.p,
+                     g.elll.p, g.rhol.p, g.dcenter.p, g.nearR_ptr.p,
+                     g.nearR_idx.p, z, ldz, ws.logL.p, out, ldo, alpha);
   LBS_HIP(hipGetLastError());
 }
 

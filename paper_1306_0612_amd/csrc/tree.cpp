@@ -30,25 +30,6 @@ struct Keyed {
   std::vector<int64_t> perm;
 };
 
-// fn(begin, end) over [0, n) split into contiguous ranges, one per host
-// thread (at most 16; small n runs inline).
-template <typename F>
-void parallel_for(int64_t n, F fn, int64_t grain = 4096) {
-  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-  const int nt = (int)std::min<int64_t>(std::min(hw, 16), (n + grain - 1) / grain);
-  if (nt <= 1) {
-    fn((int64_t)0, n);
-    return;
-  }
-  std::vector<std::thread> th;
-  th.reserve(nt);
-  for (int t = 0; t < nt; ++t) {
-    const int64_t a = n * t / nt, b = n * (t + 1) / nt;
-    th.emplace_back([=, &fn] { fn(a, b); });
-  }
-  for (auto &x : th) x.join();
-}
-
 // Points sorted by their Morton key (ties keep input order): keys formed
 // and chunks sorted in parallel, then merged pairwise in parallel.
 void morton_sort(const double *x, const double *y, int64_t n, double lox,

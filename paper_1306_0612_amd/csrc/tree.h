@@ -10,10 +10,31 @@
 //         while their parent is                               -> M2P
 //   X(b)  leaves c with b in W(c)                              -> P2L
 #pragma once
+#include <algorithm>
 #include <cstdint>
+#include <thread>
 #include <vector>
 
 namespace lbs {
+
+// fn(begin, end) over [0, n) split into contiguous ranges, one per host
+// thread (at most 16; small n runs inline).
+template <typename F>
+void parallel_for(int64_t n, F fn, int64_t grain = 4096) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nt = (int)std::min<int64_t>(std::min(hw, 16), (n + grain - 1) / grain);
+  if (nt <= 1) {
+    fn((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(nt);
+  for (int t = 0; t < nt; ++t) {
+    const int64_t a = n * t / nt, b = n * (t + 1) / nt;
+    th.emplace_back([=, &fn] { fn(a, b); });
+  }
+  for (auto &x : th) x.join();
+}
 
 constexpr int kMaxLevel = 29;   // Morton keys of 29 bits per axis
 
