@@ -29,6 +29,9 @@ METRIC = ("FMM matvecs/s & GMRES solve s at 1M nodes, FP32-mixed vs FP64, "
           "1e-10 err")
 WORKLOAD = "stars2000x512"
 PEAK_FP32_TFLOPS = 157.3
+# FP32 vector peak without packed (two-wide) FP32 instructions, which the
+# HIP sources are compiled without: 256 CUs x 64 lanes x 2 FLOP x 2.4 GHz
+PEAK_FP32_NOPK_TFLOPS = 78.6
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # algorithmic FLOP counts (see the roofline section of the design notes)
@@ -104,13 +107,14 @@ def stage_roofline(tree, n_nodes, P, stages_ms, fp64):
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when the summary is missing or was taken on other kernel
-    sources than the ones built now."""
+    """(HBM bytes, fetched HBM bytes) per launch of `kernel` from the
+    committed counter summary; None for what it lacks, and both None when
+    it is missing or was taken on other kernel sources than the ones built
+    now."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_stars2000x512.txt")
     src = os.path.join(ROOT, "paper_1306_0612_amd", "csrc", "fmm.hip")
     if not os.path.exists(path):
-        return None
+        return None, None
     rec, sha = {}, None
     with open(path) as f:
         for line in f:
@@ -118,12 +122,16 @@ def measured_traffic(kernel):
                 sha = line.split()[1]
             if line.startswith("kernel "):
                 kv = dict(t.split("=", 1) for t in line.split()[1:])
-                rec[kv["name"]] = float(kv["bytes_per_launch"])
+                rec[kv["name"]] = kv
     with open(src, "rb") as f:
         now = hashlib.sha256(f.read()).hexdigest()
-    if sha != now:
-        return None
-    return rec.get(kernel)
+    kv = rec.get(kernel)
+    if sha != now or kv is None:
+        return None, None
+    total = kv.get("bytes_per_launch")
+    fetch = kv.get("fetch_bytes_per_launch")
+    return (None if total is None else float(total),
+            None if fetch is None else float(fetch))
 
 
 def adjoint_leg(torch, sol, islands, dev, n_targets):
@@ -337,17 +345,24 @@ def main():
     rl32 = stage_roofline(tree, N, P32, st32, False)
     rl64 = stage_roofline(tree, N, P64, st64, True)
     dom = max(st32, key=st32.get)
-    kname = {"leaf": "k_leaf32<%d>" % P32,
+    kname = {"leaf": "k_leaf32<%d,1>" % P32,
              "m2l": "k_m2l_mfma16" if P32 == 16 else "k_m2l<float,%d>" % P32,
              "p2l": "k_p2l<float,%d>" % P32,
-             "upward": "k_p2m/k_m2m3<float,%d>" % P32,
+             "upward": "k_m2m3<float,%d>" % P32,
              "l2l": "k_l2l3<float,%d>" % P32}.get(dom, dom)
     r = rl32.get(dom, {})
     roofline = {"bound": r.get("bound", "alu"), "kernel": kname,
                 "achieved": r.get("achieved"),
                 "peak": r.get("peak", PEAK_FP32_TFLOPS),
                 "unit": r.get("unit", "TFLOP/s"), "frac": r.get("frac"),
-                "traffic": measured_traffic(kname), "avg_ms": st32[dom]}
+                "traffic": None, "avg_ms": st32[dom]}
+    roofline["traffic"], fetched = measured_traffic(kname)
+    if fetched is not None:
+        roofline["hbm_fetch_bytes"] = fetched
+    if roofline["unit"] == "TFLOP/s" and roofline["achieved"]:
+        roofline["peak_no_packed_fp32"] = PEAK_FP32_NOPK_TFLOPS
+        roofline["frac_no_packed_fp32"] = (roofline["achieved"]
+                                           / PEAK_FP32_NOPK_TFLOPS)
 
     out = {
         "metric": METRIC,

@@ -157,8 +157,9 @@ lbs_status lbs_nodes(lbs_handle h, double *xyz, void *stream);
 /* Apply an operator of the discrete system (eq. matrix_eqns) to nrhs
  * vectors.  op is one of LBS_OP_*; precision LBS_FP64 evaluates the far
  * field with p64 terms in FP64, LBS_MIXED with p32 terms in FP32 (FP32
- * near field on hi/lo coordinates); the log-source and constraint rows are
- * always FP64.  x and y are device (n x nrhs), n = N or N + M by op. */
+ * near field on differences of FP64 coordinates rounded to FP32); the
+ * log-source and constraint rows are always FP64.  x and y are device
+ * (n x nrhs), n = N or N + M by op. */
 lbs_status lbs_matvec(lbs_handle h, int32_t op, int32_t precision,
                       int32_t nrhs, const double *x, double *y,
                       void *stream);

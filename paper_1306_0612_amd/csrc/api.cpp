@@ -169,34 +169,21 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
   pl.leaf_t.upload(leaf_t, s);
   pl.leaf_s.upload(leaf_s, s);
   pl.m2l_box.upload(m2l, s);
-  auto split = [](double v, float &hi, float &lo) {
-    hi = (float)v;
-    lo = (float)(v - (double)hi);
-  };
   auto points = [&](const std::vector<int64_t> &perm, const double *ax,
-                    const double *ay, DBuf<double> &dx, DBuf<double> &dy,
-                    DBuf<float> &xh, DBuf<float> &xl, DBuf<float> &yh,
-                    DBuf<float> &yl) {
+                    const double *ay, DBuf<double> &dx, DBuf<double> &dy) {
     const int64_t n = (int64_t)perm.size();
     std::vector<double> x(n), y(n);
-    std::vector<float> a(n), b(n), c(n), d(n);
     for (int64_t j = 0; j < n; ++j) {
       x[j] = ax[perm[j]];
       y[j] = ay[perm[j]];
-      split(x[j], a[j], b[j]);
-      split(y[j], c[j], d[j]);
     }
     dx.upload(x, s);
     dy.upload(y, s);
-    xh.upload(a, s);
-    xl.upload(b, s);
-    yh.upload(c, s);
-    yl.upload(d, s);
+    LBS_HIP(hipStreamSynchronize(s));  // x, y are released on return
   };
-  points(T.src_perm, sx, sy, pl.sx, pl.sy, pl.sxh, pl.sxl, pl.syh, pl.syl);
+  points(T.src_perm, sx, sy, pl.sx, pl.sy);
   pl.src_perm.upload(T.src_perm, s);
-  points(T.tgt_perm, T.self ? sx : tx, T.self ? sy : ty, pl.tx, pl.ty, pl.txh,
-         pl.txl, pl.tyh, pl.tyl);
+  points(T.tgt_perm, T.self ? sx : tx, T.self ? sy : ty, pl.tx, pl.ty);
   std::vector<int64_t> perm(T.tgt_perm.size());
   for (size_t j = 0; j < perm.size(); ++j)
     perm[j] = tgt_index ? (*tgt_index)[T.tgt_perm[j]] : T.tgt_perm[j];

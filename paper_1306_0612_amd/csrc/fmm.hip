@@ -799,8 +799,52 @@ __global__ void __launch_bounds__(64, 8)
   }
 }
 
-// FP32 variant: near-field differences on hi/lo coordinate pairs,
-// d = (hi_i - hi_j) + (lo_i - lo_j), arithmetic in FP32.  A block handles
+// A staged U-list source of the FP32 leaf kernel: position (FP64) and the
+// FP32 strengths of RB right-hand sides, 16-byte aligned so that one
+// address serves both reads.
+template <int RB>
+struct alignas(16) Src32 {
+  double2 z;
+  float2 p[RB];
+};
+
+// Direct sums of one target lane over the staged sources zq[0], zq[S],
+// ..., zq[(niter - 1) S] (S compile-time, so the unrolled reads take
+// immediate offsets): f[q] += Re(p_q conj(d)) / |d|^2, d = z_t - z_j formed
+// in FP64 and rounded once.  |d|^2 + 1e-30: a target's own source (d = 0)
+// contributes 0 * rcp(1e-30) = 0; the bias leaves any |d|^2 above 2e-23
+// (node spacings above 5e-12) unchanged in FP32.
+template <int S, int RB>
+__device__ __forceinline__ void near_sums32(const Src32<RB> *__restrict__ zq,
+                                            int niter, double ax, double ay,
+                                            float (&f)[RB]) {
+  if constexpr (RB == 1) {
+#pragma unroll 4
+    for (int it = 0; it < niter; ++it) {
+      const Src32<1> &e = zq[it * S];
+      const float dx = (float)(ax - e.z.x);
+      const float dy = (float)(ay - e.z.y);
+      const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
+      f[0] += fmaf(e.p[0].x, dx, e.p[0].y * dy) * __builtin_amdgcn_rcpf(d2);
+    }
+  } else {
+#pragma unroll 2
+    for (int it = 0; it < niter; ++it) {
+      const Src32<RB> &e = zq[it * S];
+      const float dx = (float)(ax - e.z.x);
+      const float dy = (float)(ay - e.z.y);
+      const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, fmaf(dy, dy, 1e-30f)));
+      const float ux = dx * inv, uy = dy * inv;
+#pragma unroll
+      for (int q = 0; q < RB; ++q) f[q] = fmaf(e.p[q].x, ux, fmaf(e.p[q].y, uy, f[q]));
+    }
+  }
+}
+
+// FP32 variant: each pair's difference d = z_i - z_j is formed in FP64
+// and rounded once to FP32 (one FP64 add and one conversion per
+// coordinate, at the FP32 rate on this chip), the rest in FP32.  A block
+// handles
 // RB right-hand sides (blockIdx.y * RB + 0 .. RB - 1, those < nrhs): each
 // pair's difference and reciprocal are formed once and applied to every
 // right-hand side of the block.
@@ -813,21 +857,17 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
              const double *__restrict__ cxv, const double *__restrict__ cyv,
              const double *__restrict__ rad,
              const double *__restrict__ tx, const double *__restrict__ ty,
-             const float *__restrict__ txh, const float *__restrict__ txl,
-             const float *__restrict__ tyh, const float *__restrict__ tyl,
              const int64_t *__restrict__ tperm,
              const int32_t *__restrict__ u_ptr,
              const int32_t *__restrict__ u_src,
              const int32_t *__restrict__ w_ptr,
              const int32_t *__restrict__ w_src,
-             const float *__restrict__ sxh, const float *__restrict__ sxl,
-             const float *__restrict__ syh, const float *__restrict__ syl,
+             const double *__restrict__ sx, const double *__restrict__ sy,
              const cx<float> *__restrict__ p, int64_t ns,
              const cx<float> *__restrict__ M, const cx<float> *__restrict__ L,
              int nbox, int nrhs, double *__restrict__ out, int64_t ldy,
              double scale, Assembly as) {
-  __shared__ float4 sz[kStage];
-  __shared__ float2 sp[RB][kStage];
+  __shared__ Src32<RB> sz[kStage];
   __shared__ int64_t rs[64];
   __shared__ int pre[65];
   constexpr int NC = 2;  // sub-chunks of <= 32 targets per pass over U
@@ -846,7 +886,7 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
     // S_c = 64 / tp_c source slices, tp_c = min(32, next power of two)
     int S[NC], sl[NC], ti[NC];
     bool act[NC];
-    float zxh[NC], zxl[NC], zyh[NC], zyl[NC], fld[NC][RB];
+    float fld[NC][RB];
     double zxd[NC], zyd[NC];
     int Smax = 1;
 #pragma unroll
@@ -855,7 +895,6 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
       sl[c] = 0;
       act[c] = false;
       ti[c] = 0;
-      zxh[c] = zxl[c] = zyh[c] = zyl[c] = 0.f;
       zxd[c] = zyd[c] = 0.0;
 #pragma unroll
       for (int q = 0; q < RB; ++q) fld[c][q] = 0.f;
@@ -870,10 +909,6 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
       ti[c] = (int)tc0 + 32 * c + tl;
       if (!act[c]) continue;
       const int64_t i = tb0 + ti[c];
-      zxh[c] = txh[i];
-      zxl[c] = txl[i];
-      zyh[c] = tyh[i];
-      zyl[c] = tyl[i];
       zxd[c] = tx[i];
       zyd[c] = ty[i];
     }
@@ -888,17 +923,17 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
         for (int q = lane; q < tpad; q += 64) {
           if (q < take) {
             const int64_t j = locate(q0 + q, cnt, rs, pre);
-            sz[q] = make_float4(sxh[j], sxl[j], syh[j], syl[j]);
+            sz[q].z = make_double2(sx[j], sy[j]);
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr) {
               const cx<float> pj = rr < nr ? p[(int64_t)(r0 + rr) * ns + j]
                                            : cx<float>{0.f, 0.f};
-              sp[rr][q] = make_float2(pj.x, pj.y);
+              sz[q].p[rr] = make_float2(pj.x, pj.y);
             }
           } else {
-            sz[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            sz[q].z = make_double2(0.0, 0.0);
 #pragma unroll
-            for (int rr = 0; rr < RB; ++rr) sp[rr][q] = make_float2(0.f, 0.f);
+            for (int rr = 0; rr < RB; ++rr) sz[q].p[rr] = make_float2(0.f, 0.f);
           }
         }
         __syncthreads();
@@ -906,40 +941,18 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
         for (int c = 0; c < NC; ++c) {
           if (c >= nch) continue;  // uniform
           const int Sc = S[c], niter = tpad / Sc;
-          const float ax = zxh[c], bx = zxl[c], ay = zyh[c], by = zyl[c];
+          const double ax = zxd[c], ay = zyd[c];
           float f[RB];
 #pragma unroll
           for (int q = 0; q < RB; ++q) f[q] = fld[c][q];
-          const float4 *zq = sz + sl[c];
-          // |d|^2 + 1e-30: a target's own source (d = 0) contributes
-          // 0 * rcp(1e-30) = 0; the bias leaves any |d|^2 above 2e-23
-          // (node spacings above 5e-12) unchanged in FP32
-          if constexpr (RB == 1) {
-            const float2 *pq = sp[0] + sl[c];
-#pragma unroll 4
-            for (int it = 0; it < niter; ++it) {
-              const float4 s4 = zq[it * Sc];
-              const float2 p2 = pq[it * Sc];
-              const float dx = (ax - s4.x) + (bx - s4.y);
-              const float dy = (ay - s4.z) + (by - s4.w);
-              const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
-              f[0] += fmaf(p2.x, dx, p2.y * dy) * __builtin_amdgcn_rcpf(d2);
-            }
-          } else {
-#pragma unroll 2
-            for (int it = 0; it < niter; ++it) {
-              const int qq = sl[c] + it * Sc;
-              const float4 s4 = zq[it * Sc];
-              const float dx = (ax - s4.x) + (bx - s4.y);
-              const float dy = (ay - s4.z) + (by - s4.w);
-              const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, fmaf(dy, dy, 1e-30f)));
-              const float ux = dx * inv, uy = dy * inv;
-#pragma unroll
-              for (int q = 0; q < RB; ++q) {
-                const float2 p2 = sp[q][qq];
-                f[q] = fmaf(p2.x, ux, fmaf(p2.y, uy, f[q]));
-              }
-            }
+          const Src32<RB> *zq = sz + sl[c];
+          switch (Sc) {  // wave-uniform
+            case 2: near_sums32<2, RB>(zq, niter, ax, ay, f); break;
+            case 4: near_sums32<4, RB>(zq, niter, ax, ay, f); break;
+            case 8: near_sums32<8, RB>(zq, niter, ax, ay, f); break;
+            case 16: near_sums32<16, RB>(zq, niter, ax, ay, f); break;
+            case 32: near_sums32<32, RB>(zq, niter, ax, ay, f); break;
+            default: near_sums32<64, RB>(zq, niter, ax, ay, f); break;
           }
 #pragma unroll
           for (int q = 0; q < RB; ++q) fld[c][q] = f[q];
@@ -1095,9 +1108,9 @@ static void run32(const DevPlan &pl, const Tables &tb, Workspace &ws,
       hipLaunchKernelGGL(kern, dim3(pl.n_leaf_t, (nrhs + rb - 1) / rb), dim3(64),
                          0, s, pl.leaf_t.p, pl.lev.p, pl.t0.p, pl.t1.p, pl.s0.p,
                          pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p, pl.tx.p, pl.ty.p,
-                         pl.txh.p, pl.txl.p, pl.tyh.p, pl.tyl.p, pl.tgt_perm.p,
+                         pl.tgt_perm.p,
                          pl.u_ptr.p, pl.u_src.p, pl.w_ptr.p, pl.w_src.p,
-                         pl.sxh.p, pl.sxl.p, pl.syh.p, pl.syl.p,
+                         pl.sx.p, pl.sy.p,
                          (const cx<float> *)p, pl.ns, (const cx<float> *)M,
                          (const cx<float> *)L, pl.nbox, nrhs, out, ldy, scale,
                          as);
@@ -1306,7 +1319,7 @@ void fmm_apply64_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
 }
 
 // FP32 counterpart for the transposed operator (field only): strengths in
-// FP32, near-field differences on hi/lo coordinate pairs as in k_leaf32.
+// FP32, near-field differences formed in FP64 as in k_leaf32.
 __global__ void k_strengths_given32(int64_t ns, const int64_t *__restrict__ perm,
                                     const double *__restrict__ pin,
                                     cx<float> *__restrict__ p) {
@@ -1325,19 +1338,16 @@ __global__ void __launch_bounds__(64)
                   const double *__restrict__ cxv, const double *__restrict__ cyv,
                   const double *__restrict__ rad,
                   const double *__restrict__ tx, const double *__restrict__ ty,
-                  const float *__restrict__ txh, const float *__restrict__ txl,
-                  const float *__restrict__ tyh, const float *__restrict__ tyl,
                   const int64_t *__restrict__ tperm,
                   const int32_t *__restrict__ u_ptr,
                   const int32_t *__restrict__ u_src,
                   const int32_t *__restrict__ w_ptr,
                   const int32_t *__restrict__ w_src,
-                  const float *__restrict__ sxh, const float *__restrict__ sxl,
-                  const float *__restrict__ syh, const float *__restrict__ syl,
+                  const double *__restrict__ sx, const double *__restrict__ sy,
                   const cx<float> *__restrict__ p,
                   const cx<float> *__restrict__ M,
                   const cx<float> *__restrict__ L, double *__restrict__ psi) {
-  __shared__ float4 sz[kStage];
+  __shared__ double2 sz[kStage];
   __shared__ float2 sp[kStage];
   __shared__ int64_t rs[64];
   __shared__ int pre[65];
@@ -1352,8 +1362,6 @@ __global__ void __launch_bounds__(64)
     const int64_t i = tb0 + tc + tl;
     const bool act = tc + tl < ntb;
     const double zx = act ? tx[i] : 0.0, zy = act ? ty[i] : 0.0;
-    const float zxh = act ? txh[i] : 0.f, zxl = act ? txl[i] : 0.f;
-    const float zyh = act ? tyh[i] : 0.f, zyl = act ? tyl[i] : 0.f;
     cx<float> f{0.f, 0.f};
     if (act) {
       if (sl == 0 && lev[b] >= 2) {
@@ -1382,17 +1390,17 @@ __global__ void __launch_bounds__(64)
         const int take = min(kStage, total - q0);
         for (int q = lane; q < take; q += 64) {
           const int64_t j = locate(q0 + q, cnt, rs, pre);
-          sz[q] = make_float4(sxh[j], sxl[j], syh[j], syl[j]);
+          sz[q] = make_double2(sx[j], sy[j]);
           const cx<float> pj = p[j];
           sp[q] = make_float2(pj.x, pj.y);
         }
         __syncthreads();
         if (act) {
           for (int q = sl; q < take; q += S) {
-            const float4 s4 = sz[q];
+            const double2 s2 = sz[q];
             const float2 p2 = sp[q];
-            const float dx = (zxh - s4.x) + (zxl - s4.y);
-            const float dy = (zyh - s4.z) + (zyl - s4.w);
+            const float dx = (float)(zx - s2.x);
+            const float dy = (float)(zy - s2.y);
             // p / d = p conj(d) / |d|^2; the 1e-30 bias makes a target's own
             // source (d = 0, in a self plan) contribute 0
             const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, fmaf(dy, dy, 1e-30f)));
@@ -1426,9 +1434,9 @@ static void run32_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
     hipLaunchKernelGGL((k_leaf32_full<P>), dim3(pl.n_leaf_t), dim3(64), 0, s,
                        pl.leaf_t.p, pl.lev.p, pl.t0.p, pl.t1.p, pl.s0.p,
                        pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p, pl.tx.p, pl.ty.p,
-                       pl.txh.p, pl.txl.p, pl.tyh.p, pl.tyl.p, pl.tgt_perm.p,
+                       pl.tgt_perm.p,
                        pl.u_ptr.p, pl.u_src.p, pl.w_ptr.p, pl.w_src.p,
-                       pl.sxh.p, pl.sxl.p, pl.syh.p, pl.syl.p,
+                       pl.sx.p, pl.sy.p,
                        (const cx<float> *)p, (const cx<float> *)M,
                        (const cx<float> *)L, psi);
 }

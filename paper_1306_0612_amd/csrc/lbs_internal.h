@@ -106,7 +106,6 @@ struct DevPlan {
   DBuf<int4> up_deep;
   // points in tree order
   DBuf<double> sx, sy, tx, ty;
-  DBuf<float> sxh, sxl, syh, syl, txh, txl, tyh, tyl;  // FP32 hi/lo
   DBuf<int64_t> src_perm, tgt_perm;
   Tree host;                                  // host tree (statistics)
 };
