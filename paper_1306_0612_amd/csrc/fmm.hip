@@ -513,61 +513,86 @@ __global__ void __launch_bounds__(256)
   for (int i = threadIdx.x; i < 49 * NP; i += 256) sItp[i] = itp[i];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wv >= nb) return;  // uniform per wave, after the block's barrier
   const int r = blockIdx.y;
   const int col = lane & 15, kq = lane >> 4;
   const int vslot = col >> 1, part = col & 1;
   float a[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) a[s] = H[col * P + 4 * s + kq];
-  const int b = boxes[wv];
-  const int vb = v_ptr[b], nv = v_ptr[b + 1] - vb;
-  const cx<float> *Mr = M + (int64_t)r * nbox * P;
-  float accr[4] = {0.f, 0.f, 0.f, 0.f}, acci[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int base = 0; base < nv; base += 8) {
-    const int v = base + vslot;
-    const bool ok = v < nv;
-    int src = 0, code = 0;
-    if (ok) {
-      src = v_src[vb + v];
-      code = v_code[vb + v];
+  // each wave takes every (4 gridDim.x)-th box, so that the table above is
+  // read once per block for several boxes
+  for (int wv = blockIdx.x * 4 + (threadIdx.x >> 6); wv < nb;
+       wv += 4 * gridDim.x) {
+    const int b = boxes[wv];
+    const int vb = v_ptr[b], nv = v_ptr[b + 1] - vb;
+    const cx<float> *Mr = M + (int64_t)r * nbox * P;
+    // the box's list entries, lane e holding entry e (a V list has at most
+    // 27 entries; any beyond 64 are read directly)
+    int esrc = 0, ecode = 0;
+    if (lane < nv) {
+      esrc = v_src[vb + lane];
+      ecode = v_code[vb + lane];
     }
-    const cx<float> *ms = Mr + (int64_t)src * P;
-    const cx<float> *ip = sItp + code * NP;
-    v4f d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int k = 4 * s + kq;
-      float bv = 0.f;
-      if (ok) {
-        const cx<float> y = ip[k + 1] * ms[k];
-        bv = part ? y.y : y.x;
+    // multipole coefficients k = 4 s + kq of the batch's source vslot
+    auto fetch = [&](int base, cx<float> (&mv)[4], int &code, bool &ok) {
+      const int v = base + vslot;
+      ok = v < nv;
+      int src = __shfl(esrc, v & 63, 64);
+      code = __shfl(ecode, v & 63, 64);
+      if (ok && v >= 64) {
+        src = v_src[vb + v];
+        code = v_code[vb + v];
       }
-      d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bv, d, 0, 0, 0);
+      if (!ok) src = code = 0;
+      const cx<float> *ms = Mr + (int64_t)src * P;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) mv[s] = ok ? ms[4 * s + kq] : cx<float>{0.f, 0.f};
+    };
+    float accr[4] = {0.f, 0.f, 0.f, 0.f}, acci[4] = {0.f, 0.f, 0.f, 0.f};
+    cx<float> mcur[4], mnxt[4];
+    int ccur, cnxt = 0;
+    bool okc, oknx = false;
+    fetch(0, mcur, ccur, okc);
+    for (int base = 0; base < nv; base += 8) {
+      // the next batch's loads go out before this batch's products
+      if (base + 8 < nv) fetch(base + 8, mnxt, cnxt, oknx);  // wave-uniform
+      const bool ok = okc;
+      const cx<float> *ip = sItp + ccur * NP;
+      v4f d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + kq;
+        const cx<float> y = ip[k + 1] * mcur[s];
+        const float bv = ok ? (part ? y.y : y.x) : 0.f;
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bv, d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float mine = d[j];
+        const float other = __shfl_xor(mine, 1, 64);
+        if (ok && part == 0) {
+          const cx<float> t = ip[4 * kq + j] * cx<float>{mine, other};
+          accr[j] += t.x;
+          acci[j] += t.y;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) mcur[s] = mnxt[s];
+      ccur = cnxt;
+      okc = oknx;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float mine = d[j];
-      const float other = __shfl_xor(mine, 1, 64);
-      if (ok && part == 0) {
-        const cx<float> t = ip[4 * kq + j] * cx<float>{mine, other};
-        accr[j] += t.x;
-        acci[j] += t.y;
+      for (int off = 2; off < 16; off <<= 1) {
+        accr[j] += __shfl_xor(accr[j], off, 64);
+        acci[j] += __shfl_xor(acci[j], off, 64);
       }
     }
-  }
+    if (col == 0) {
+      cx<float> *dst = L + ((int64_t)r * nbox + b) * P + 4 * kq;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    for (int off = 2; off < 16; off <<= 1) {
-      accr[j] += __shfl_xor(accr[j], off, 64);
-      acci[j] += __shfl_xor(acci[j], off, 64);
+      for (int j = 0; j < 4; ++j) dst[j] = cx<float>{accr[j], acci[j]};
     }
-  }
-  if (col == 0) {
-    cx<float> *dst = L + ((int64_t)r * nbox + b) * P + 4 * kq;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) dst[j] = cx<float>{accr[j], acci[j]};
   }
 }
 
@@ -1047,7 +1072,7 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
   if (pl.n_m2l > 0) {
     TimerScope ts(tm, ST_M2L, s);
     if constexpr (sizeof(T) == 4 && P == 16) {
-      hipLaunchKernelGGL(k_m2l_mfma16, dim3((pl.n_m2l + 3) / 4, nrhs),
+      hipLaunchKernelGGL(k_m2l_mfma16, dim3(std::min((pl.n_m2l + 3) / 4, 2048), nrhs),
                          dim3(256), 0, s, pl.n_m2l, pl.m2l_box.p, pl.v_ptr.p,
                          pl.v_src.p, pl.v_code.p, H, itp, (const cx<T> *)M, L,
                          pl.nbox);
