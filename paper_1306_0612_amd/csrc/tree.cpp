@@ -30,51 +30,71 @@ struct Keyed {
   std::vector<int64_t> perm;
 };
 
-// Points sorted by their Morton key (ties keep input order): keys formed
-// and chunks sorted in parallel, then merged pairwise in parallel.
+// Points sorted by their Morton key (ties keep input order): keys formed in
+// parallel, then a stable least-significant-digit radix sort of the
+// 2 kMaxLevel key bits, 11 bits per pass, with one histogram per chunk of
+// points so that each pass scatters in parallel.
 void morton_sort(const double *x, const double *y, int64_t n, double lox,
                  double loy, double scale, Keyed &out) {
   const double cells = (double)(1ull << kMaxLevel);
-  using KV = std::pair<uint64_t, int64_t>;
-  std::vector<KV> kv((size_t)n), tmp((size_t)n);
+  std::vector<uint64_t> key((size_t)n), tk((size_t)n);
+  std::vector<int64_t> val((size_t)n), tv((size_t)n);
   const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
   const int nc = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(hw, 16), n / 32768));
   std::vector<int64_t> cut(nc + 1);
   for (int c = 0; c <= nc; ++c) cut[c] = n * c / nc;
   parallel_for(nc, [&](int64_t c0, int64_t c1) {
-    for (int64_t c = c0; c < c1; ++c) {
-      for (int64_t i = cut[c]; i < cut[c + 1]; ++i) {
-        double fx = (x[i] - lox) * scale * cells;
-        double fy = (y[i] - loy) * scale * cells;
-        int64_t qx = (int64_t)std::floor(fx), qy = (int64_t)std::floor(fy);
-        qx = std::min<int64_t>(std::max<int64_t>(qx, 0), (1ll << kMaxLevel) - 1);
-        qy = std::min<int64_t>(std::max<int64_t>(qy, 0), (1ll << kMaxLevel) - 1);
-        kv[i] = {spread_bits((uint64_t)qx) | (spread_bits((uint64_t)qy) << 1), i};
-      }
-      std::sort(kv.begin() + cut[c], kv.begin() + cut[c + 1]);
+    for (int64_t i = cut[c0]; i < cut[c1]; ++i) {
+      double fx = (x[i] - lox) * scale * cells;
+      double fy = (y[i] - loy) * scale * cells;
+      int64_t qx = (int64_t)std::floor(fx), qy = (int64_t)std::floor(fy);
+      qx = std::min<int64_t>(std::max<int64_t>(qx, 0), (1ll << kMaxLevel) - 1);
+      qy = std::min<int64_t>(std::max<int64_t>(qy, 0), (1ll << kMaxLevel) - 1);
+      key[i] = spread_bits((uint64_t)qx) | (spread_bits((uint64_t)qy) << 1);
+      val[i] = i;
     }
   }, 1);
-  for (int w = 1; w < nc; w *= 2) {
-    const int nm = (nc + 2 * w - 1) / (2 * w);
-    parallel_for(nm, [&](int64_t m0, int64_t m1) {
-      for (int64_t m = m0; m < m1; ++m) {
-        const int64_t a = cut[std::min<int64_t>(2 * w * m, nc)];
-        const int64_t b = cut[std::min<int64_t>(2 * w * m + w, nc)];
-        const int64_t e = cut[std::min<int64_t>(2 * w * m + 2 * w, nc)];
-        std::merge(kv.begin() + a, kv.begin() + b, kv.begin() + b, kv.begin() + e,
-                   tmp.begin() + a);
+  constexpr int D = 11, NB = 1 << D;
+  std::vector<int64_t> off((size_t)nc * NB);
+  for (int sh = 0; sh < 2 * kMaxLevel; sh += D) {
+    std::fill(off.begin(), off.end(), 0);
+    parallel_for(nc, [&](int64_t c0, int64_t c1) {
+      for (int64_t c = c0; c < c1; ++c) {
+        int64_t *h = &off[(size_t)c * NB];
+        for (int64_t i = cut[c]; i < cut[c + 1]; ++i) ++h[(key[i] >> sh) & (NB - 1)];
       }
     }, 1);
-    kv.swap(tmp);
-  }
-  out.key.resize((size_t)n);
-  out.perm.resize((size_t)n);
-  parallel_for(n, [&](int64_t a, int64_t b) {
-    for (int64_t i = a; i < b; ++i) {
-      out.key[i] = kv[i].first;
-      out.perm[i] = kv[i].second;
+    // start of (digit, chunk) in digit-major, chunk-minor order; a pass in
+    // which every key has the same digit leaves the order as it is
+    int64_t run = 0;
+    bool trivial = false;
+    for (int d = 0; d < NB && !trivial; ++d) {
+      int64_t tot = 0;
+      for (int c = 0; c < nc; ++c) tot += off[(size_t)c * NB + d];
+      trivial = tot == n;
     }
-  });
+    if (trivial) continue;
+    for (int d = 0; d < NB; ++d)
+      for (int c = 0; c < nc; ++c) {
+        const int64_t h = off[(size_t)c * NB + d];
+        off[(size_t)c * NB + d] = run;
+        run += h;
+      }
+    parallel_for(nc, [&](int64_t c0, int64_t c1) {
+      for (int64_t c = c0; c < c1; ++c) {
+        int64_t *o = &off[(size_t)c * NB];
+        for (int64_t i = cut[c]; i < cut[c + 1]; ++i) {
+          const int64_t pos = o[(key[i] >> sh) & (NB - 1)]++;
+          tk[pos] = key[i];
+          tv[pos] = val[i];
+        }
+      }
+    }, 1);
+    key.swap(tk);
+    val.swap(tv);
+  }
+  out.key.swap(key);
+  out.perm.swap(val);
 }
 
 // Sub-range of [a, b) whose keys have quadrant q at level l + 1.
