@@ -429,12 +429,16 @@ std::vector<const void *> graph_signature(lbs_ctx &c) {
 
 // Lockstep GMRES(m) for the R * G systems op(x) = b (columns of length
 // n = N + M), per-system absolute tolerances c.gm.tol.  x_zero: start from
-// x = 0.  CGS2 orthogonalisation, Givens rotations, one 4-byte read of the
-// number of active systems per iteration.  With graph_id >= 0 (and graphs
-// enabled, stage timing off) the body of iteration k is captured once as a
-// HIP graph under the key (graph_id, R, k) and replayed afterwards.
+// x = 0.  Classical Gram-Schmidt with `passes` passes (2: CGS2; 1 serves
+// the inner solves of mixed-precision refinement, which stop at a loose
+// tolerance and whose errors the FP64 outer residual corrects), Givens
+// rotations, one 4-byte read of the number of active systems per
+// iteration.  With graph_id >= 0 (and graphs enabled, stage timing off)
+// the body of iteration k is captured once as a HIP graph under the key
+// (graph_id, R, k) and replayed afterwards; a graph_id always comes with
+// the same number of passes.
 GmresOut gmres(lbs_ctx &c, const OpFn &op, int graph_id, int R, const double *b,
-               double *x, bool x_zero, int max_iter, hipStream_t s) {
+               double *x, bool x_zero, int max_iter, hipStream_t s, int passes) {
   GmresState &st = c.gm;
   const int64_t n = st.n;
   const int m = st.m, G = c.geo.G, S = R * G;
@@ -480,11 +484,14 @@ GmresOut gmres(lbs_ctx &c, const OpFn &op, int graph_id, int R, const double *b,
         op(vk, w, q);
         launch_segdots(c.seg_sys, R, k + 1, V, ldv, n, w, n, st.h1.p, c.ws.red.p, q);
         launch_maxpy_seg(n, R, G, k + 1, rg, V, ldv, st.h1.p, w, q);
-        launch_segdots(c.seg_sys, R, k + 1, V, ldv, n, w, n, st.h2.p, c.ws.red.p, q);
-        launch_maxpy_seg(n, R, G, k + 1, rg, V, ldv, st.h2.p, w, q);
+        if (passes > 1) {
+          launch_segdots(c.seg_sys, R, k + 1, V, ldv, n, w, n, st.h2.p, c.ws.red.p, q);
+          launch_maxpy_seg(n, R, G, k + 1, rg, V, ldv, st.h2.p, w, q);
+        }
         launch_segdots(c.seg_sys, R, 1, w, 0, n, w, n, st.nrm2.p, c.ws.red.p, q);
         launch_fill_int(1, 0, st.count.p, q);
-        launch_givens_seg(S, k, m, st.h1.p, st.h2.p, st.nrm2.p, st.tol.p, st.H.p,
+        launch_givens_seg(S, k, m, st.h1.p, passes > 1 ? st.h2.p : nullptr, st.nrm2.p,
+                          st.tol.p, st.H.p,
                           st.cs.p, st.sn.p, st.gv.p, st.resid.p, st.active.p,
                           st.kused.p, st.count.p, q);
         launch_normalize_seg(n, R, G, rg, st.nrm2.p, st.active.p, w, w, q);
@@ -537,7 +544,7 @@ GmresOut gmres(lbs_ctx &c, int prec, int R, const double *b, double *x,
       [&](const double *in, double *out, hipStream_t q) {
         apply_precond_op(c, prec, R, in, out, q);
       },
-      prec, R, b, x, x_zero, max_iter, s);
+      prec, R, b, x, x_zero, max_iter, s, prec == LBS_MIXED ? 1 : 2);
 }
 
 // Per-system 2-norms^2 of R columns of length N + M into out (S values).
@@ -1426,7 +1433,7 @@ lbs_status lbs_solve_T(lbs_handle h, int32_t prec, int32_t nrhs, const double *r
     };
     if (prec == LBS_FP64) {
       launch_scale_sqrt(S, tol, gm.bn2.p, gm.tol.p, s);
-      GmresOut go = gmres(c, op64, 2, R, gm.bvec.p, gm.xvec.p, true, c.opt.max_iter, s);
+      GmresOut go = gmres(c, op64, 2, R, gm.bvec.p, gm.xvec.p, true, c.opt.max_iter, s, 2);
       inf.iters = go.iters;
       inf.fp64_matvecs = go.iters;
       noconv = !go.conv;
@@ -1454,7 +1461,7 @@ lbs_status lbs_solve_T(lbs_handle h, int32_t prec, int32_t nrhs, const double *r
         if (all) { conv = true; break; }
         if (outer >= c.opt.max_outer || left <= 0) break;
         LBS_HIP(hipMemcpyAsync(gm.tol.p, itol.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
-        GmresOut go = gmres(c, op32, 3, R, gm.rvec.p, gm.dvec.p, true, left, s);
+        GmresOut go = gmres(c, op32, 3, R, gm.rvec.p, gm.dvec.p, true, left, s, 1);
         inf.iters += go.iters;
         inf.fp32_matvecs += go.iters;
         left -= go.iters;

@@ -842,7 +842,7 @@ __global__ void k_givens_seg(int S, int k, int m, const double *__restrict__ h1,
   double *h = H + (int64_t)s * (m + 1) * m + (int64_t)k * (m + 1);
   double *c = cs + (int64_t)s * m, *sg = sn + (int64_t)s * m;
   double *gg = g + (int64_t)s * (m + 1);
-  for (int j = 0; j <= k; ++j) h[j] = h1[j * S + s] + h2[j * S + s];
+  for (int j = 0; j <= k; ++j) h[j] = h1[j * S + s] + (h2 ? h2[j * S + s] : 0.0);
   h[k + 1] = sqrt(fmax(nrm2[s], 0.0));
   for (int j = 0; j < k; ++j) {
     const double t = c[j] * h[j] + sg[j] * h[j + 1];
