@@ -732,10 +732,11 @@ __global__ void __launch_bounds__(64, 8)
       if (c >= nch) continue;  // uniform
       const int rem = nt - 32 * c;
       const int tp = rem >= 32 ? 32 : pow2_at_least(rem);
-      S[c] = 64 / tp;
+      const int lg = __builtin_ctz(tp);  // tp is a power of two
+      S[c] = 64 >> lg;
       Smax = max(Smax, S[c]);
-      const int tl = lane % tp;
-      sl[c] = lane / tp;
+      const int tl = lane & (tp - 1);
+      sl[c] = lane >> lg;
       act[c] = 32 * c + tl < nt;
       ti[c] = (int)tc0 + 32 * c + tl;
       if (!act[c]) continue;
@@ -769,7 +770,7 @@ __global__ void __launch_bounds__(64, 8)
         const int take = min(kStage, total - q0);
         // pad to a multiple of Smax with sources of zero strength at the
         // origin: they add 0 * rcp(|z|^2 + 1e-300) = 0
-        const int tpad = (take + Smax - 1) / Smax * Smax;
+        const int tpad = (take + Smax - 1) & ~(Smax - 1);  // Smax: power of two
         for (int q = lane; q < tpad; q += 64) {
           if (q < take) {
             const int64_t j = locate(q0 + q, cnt, rs, pre);
@@ -785,7 +786,7 @@ __global__ void __launch_bounds__(64, 8)
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           if (c >= nch) continue;  // uniform
-          const int Sc = S[c], niter = tpad / Sc;
+          const int Sc = S[c], niter = tpad >> __builtin_ctz(Sc);
           const double zx = zxs[c], zy = zys[c];
           double f = fld[c];
           const double2 *zq = sz + sl[c];
@@ -809,7 +810,7 @@ __global__ void __launch_bounds__(64, 8)
     for (int c = 0; c < NC; ++c) {
       if (c >= nch) continue;  // uniform
       double field = fld[c];
-      for (int o = 64 / S[c]; o < 64; o <<= 1) field += __shfl_xor(field, o, 64);
+      for (int o = 64 >> __builtin_ctz(S[c]); o < 64; o <<= 1) field += __shfl_xor(field, o, 64);
       if (act[c] && sl[c] == 0) {
         const int64_t api = tperm[tb0 + ti[c]];
         double val = scale * field;
@@ -926,10 +927,11 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
       if (c >= nch) continue;  // uniform
       const int rem = nt - 32 * c;
       const int tp = rem >= 32 ? 32 : pow2_at_least(rem);
-      S[c] = 64 / tp;
+      const int lg = __builtin_ctz(tp);  // tp is a power of two
+      S[c] = 64 >> lg;
       Smax = max(Smax, S[c]);
-      const int tl = lane % tp;
-      sl[c] = lane / tp;
+      const int tl = lane & (tp - 1);
+      sl[c] = lane >> lg;
       act[c] = 32 * c + tl < nt;
       ti[c] = (int)tc0 + 32 * c + tl;
       if (!act[c]) continue;
@@ -944,7 +946,7 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
         const int take = min(kStage, total - q0);
         // pad to a multiple of Smax (<= 64, divides kStage) with sources of
         // zero strength at the origin: they add 0 * rcp(|z|^2 + 1e-30) = 0
-        const int tpad = (take + Smax - 1) / Smax * Smax;
+        const int tpad = (take + Smax - 1) & ~(Smax - 1);  // Smax: power of two
         for (int q = lane; q < tpad; q += 64) {
           if (q < take) {
             const int64_t j = locate(q0 + q, cnt, rs, pre);
@@ -965,7 +967,7 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           if (c >= nch) continue;  // uniform
-          const int Sc = S[c], niter = tpad / Sc;
+          const int Sc = S[c], niter = tpad >> __builtin_ctz(Sc);
           const double ax = zxd[c], ay = zyd[c];
           float f[RB];
 #pragma unroll
@@ -1015,7 +1017,7 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
             field += (acc * rho).x;
           }
         }
-        for (int o = 64 / S[c]; o < 64; o <<= 1) field += __shfl_xor(field, o, 64);
+        for (int o = 64 >> __builtin_ctz(S[c]); o < 64; o <<= 1) field += __shfl_xor(field, o, 64);
         if (act[c] && sl[c] == 0) {
           const int64_t api = tperm[tb0 + ti[c]];
           double val = scale * (double)field;

@@ -216,3 +216,43 @@ def test_adjoint_duality_at_scale(env):
     f = {s: J_at(b0 + s * h) for s in (-2, -1, 1, 2)}
     fd = (8 * (f[1] - f[-1]) - (f[2] - f[-2])) / (12 * h)
     assert abs(dc[k, q] - fd) < 1e-6 * np.abs(dc).max()
+
+
+def test_adjoint_full_size(env):
+    """The benchmark's adjoint workload (2000 islands x 512 nodes, 1e5
+    targets, leaf size 64, mixed forward and transposed solves): duality
+    w . u(g) = (2 lambda_sigma) . g, and a central difference of the GPU
+    forward in one shape coefficient against lbs_shape_vjp."""
+    torch, lbs = env
+    isl = synth.config_islands("stars2000x512")
+    sol = lbs.Solver(isl, leaf_max=64)
+    xyz = sol.nodes().cpu().numpy()
+    g = synth.exact_harmonic(xyz, isl.center, synth.random_data_coeffs(61, isl))
+    tg = synth.sphere_targets(62, 100000, isl)
+    w = np.random.default_rng(63).standard_normal(len(tg))
+    gd, tgd, wd = _t(torch, g), _t(torch, tg), _t(torch, w)
+    sig, A, _ = sol.solve(gd, tol=1e-12, precision="mixed")
+    J = float(wd @ sol.eval(sig, A, tgd))
+    gs, ga = sol.eval_T(wd, tgd)
+    ls, _, info = sol.solve_T(gs, ga, tol=1e-12, precision="mixed")
+    assert info["status"] == "LBS_OK" and info["rel_resid"] < 1e-11
+    # both solves stop at a relative residual of 1e-12
+    assert abs(J - float(2.0 * ls @ gd)) < 1e-9 * float((wd.abs()).sum())
+    dc = sol.shape_vjp(sig, A, ls, wd, tgd).cpu().numpy()
+    assert dc.shape == (isl.m, 16) and np.isfinite(dc).all()
+    k, q, h = 1234, 5, 1e-4
+
+    def J_at(v):
+        isl2 = isl.subset(np.arange(isl.m))
+        isl2.coef[k, q] = v
+        s2 = lbs.Solver(isl2, leaf_max=64)
+        a, b, _ = s2.solve(gd, tol=1e-12, precision="mixed")
+        u = s2.eval(a, b, tgd)
+        s2.close()
+        return float(wd @ u)
+
+    b0 = isl.coef[k, q]
+    f = {s: J_at(b0 + s * h) for s in (-2, -1, 1, 2)}
+    fd = (8 * (f[1] - f[-1]) - (f[2] - f[-2])) / (12 * h)
+    assert abs(dc[k, q] - fd) < 1e-5 * np.abs(dc).max()
+    sol.close()
