@@ -687,8 +687,8 @@ __global__ void __launch_bounds__(64, 8)
              const double *__restrict__ rad,
              const double *__restrict__ tx, const double *__restrict__ ty,
              const int64_t *__restrict__ tperm,
-             const int32_t *__restrict__ u_ptr,
-             const int32_t *__restrict__ u_src,
+             const int64_t *__restrict__ uf_ptr,
+             const int32_t *__restrict__ uf_idx,
              const int32_t *__restrict__ w_ptr,
              const int32_t *__restrict__ w_src,
              const double *__restrict__ sx, const double *__restrict__ sy,
@@ -699,8 +699,6 @@ __global__ void __launch_bounds__(64, 8)
              Assembly as) {
   __shared__ double2 sz[kStage];
   __shared__ double2 sp[kStage];
-  __shared__ int64_t rs[64];
-  __shared__ int pre[65];
   constexpr int NC = 2;  // sub-chunks of <= 32 targets per pass over U
   const int b = leaves[blockIdx.x];
   const int r = blockIdx.y;
@@ -709,7 +707,8 @@ __global__ void __launch_bounds__(64, 8)
   const cx<double> *Mr = M + (int64_t)r * nbox * P;
   const cx<double> *Lr = L + (int64_t)r * nbox * P;
   const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
-  const int ub = u_ptr[b], ue = u_ptr[b + 1];
+  const int64_t uf0 = uf_ptr[b];
+  const int utot = (int)(uf_ptr[b + 1] - uf0);  // U-list sources of the leaf
   const int wb = w_ptr[b], we = w_ptr[b + 1];
   const bool has_local = lev[b] >= 2;
   const double ir_b = 1.0 / rad[b];
@@ -763,9 +762,8 @@ __global__ void __launch_bounds__(64, 8)
       }
       fld[c] = field;
     }
-    for (int eb = ub; eb < ue; eb += 64) {
-      const int cnt = min(64, ue - eb);
-      const int total = gather_ranges(u_src, eb, cnt, s0, s1, rs, pre);
+    {  // the leaf's U-list sources, kStage at a time
+      const int total = utot;
       for (int q0 = 0; q0 < total; q0 += kStage) {
         const int take = min(kStage, total - q0);
         // pad to a multiple of Smax with sources of zero strength at the
@@ -773,7 +771,7 @@ __global__ void __launch_bounds__(64, 8)
         const int tpad = (take + Smax - 1) & ~(Smax - 1);  // Smax: power of two
         for (int q = lane; q < tpad; q += 64) {
           if (q < take) {
-            const int64_t j = locate(q0 + q, cnt, rs, pre);
+            const int64_t j = uf_idx[uf0 + q0 + q];
             sz[q] = make_double2(sx[j], sy[j]);
             const cx<double> pj = pr[j];
             sp[q] = make_double2(pj.x, pj.y);
@@ -884,8 +882,8 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
              const double *__restrict__ rad,
              const double *__restrict__ tx, const double *__restrict__ ty,
              const int64_t *__restrict__ tperm,
-             const int32_t *__restrict__ u_ptr,
-             const int32_t *__restrict__ u_src,
+             const int64_t *__restrict__ uf_ptr,
+             const int32_t *__restrict__ uf_idx,
              const int32_t *__restrict__ w_ptr,
              const int32_t *__restrict__ w_src,
              const double *__restrict__ sx, const double *__restrict__ sy,
@@ -894,14 +892,13 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
              int nbox, int nrhs, double *__restrict__ out, int64_t ldy,
              double scale, Assembly as) {
   __shared__ Src32<RB> sz[kStage];
-  __shared__ int64_t rs[64];
-  __shared__ int pre[65];
   constexpr int NC = 2;  // sub-chunks of <= 32 targets per pass over U
   const int b = leaves[blockIdx.x];
   const int r0 = blockIdx.y * RB, nr = min(RB, nrhs - r0);
   const int lane = threadIdx.x;
   const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
-  const int ub = u_ptr[b], ue = u_ptr[b + 1];
+  const int64_t uf0 = uf_ptr[b];
+  const int utot = (int)(uf_ptr[b + 1] - uf0);  // U-list sources of the leaf
   const int wb = w_ptr[b], we = w_ptr[b + 1];
   const bool has_local = lev[b] >= 2;
   const double ir_b = 1.0 / rad[b];
@@ -939,9 +936,8 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
       zxd[c] = tx[i];
       zyd[c] = ty[i];
     }
-    for (int eb = ub; eb < ue; eb += 64) {
-      const int cnt = min(64, ue - eb);
-      const int total = gather_ranges(u_src, eb, cnt, s0, s1, rs, pre);
+    {  // the leaf's U-list sources, kStage at a time
+      const int total = utot;
       for (int q0 = 0; q0 < total; q0 += kStage) {
         const int take = min(kStage, total - q0);
         // pad to a multiple of Smax (<= 64, divides kStage) with sources of
@@ -949,7 +945,7 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
         const int tpad = (take + Smax - 1) & ~(Smax - 1);  // Smax: power of two
         for (int q = lane; q < tpad; q += 64) {
           if (q < take) {
-            const int64_t j = locate(q0 + q, cnt, rs, pre);
+            const int64_t j = uf_idx[uf0 + q0 + q];
             sz[q].z = make_double2(sx[j], sy[j]);
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr) {
@@ -1114,8 +1110,8 @@ static void run64(const DevPlan &pl, const Tables &tb, Workspace &ws,
     hipLaunchKernelGGL((k_leaf64<P>), dim3(pl.n_leaf_t, nrhs), dim3(64), 0, s,
                        pl.leaf_t.p, pl.lev.p, pl.t0.p,
                        pl.t1.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p,
-                       pl.tx.p, pl.ty.p, pl.tgt_perm.p, pl.u_ptr.p,
-                       pl.u_src.p, pl.w_ptr.p, pl.w_src.p, pl.sx.p, pl.sy.p,
+                       pl.tx.p, pl.ty.p, pl.tgt_perm.p, pl.uf_ptr.p,
+                       pl.uf_idx.p, pl.w_ptr.p, pl.w_src.p, pl.sx.p, pl.sy.p,
                        (const cx<double> *)p, pl.ns, (const cx<double> *)M,
                        (const cx<double> *)L, pl.nbox, out, ldy, scale, as);
   }
@@ -1136,7 +1132,7 @@ static void run32(const DevPlan &pl, const Tables &tb, Workspace &ws,
                          0, s, pl.leaf_t.p, pl.lev.p, pl.t0.p, pl.t1.p, pl.s0.p,
                          pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p, pl.tx.p, pl.ty.p,
                          pl.tgt_perm.p,
-                         pl.u_ptr.p, pl.u_src.p, pl.w_ptr.p, pl.w_src.p,
+                         pl.uf_ptr.p, pl.uf_idx.p, pl.w_ptr.p, pl.w_src.p,
                          pl.sx.p, pl.sy.p,
                          (const cx<float> *)p, pl.ns, (const cx<float> *)M,
                          (const cx<float> *)L, pl.nbox, nrhs, out, ldy, scale,
@@ -1219,8 +1215,8 @@ __global__ void __launch_bounds__(64)
                   const double *__restrict__ rad,
                   const double *__restrict__ tx, const double *__restrict__ ty,
                   const int64_t *__restrict__ tperm,
-                  const int32_t *__restrict__ u_ptr,
-                  const int32_t *__restrict__ u_src,
+                  const int64_t *__restrict__ uf_ptr,
+                  const int32_t *__restrict__ uf_idx,
                   const int32_t *__restrict__ w_ptr,
                   const int32_t *__restrict__ w_src,
                   const double *__restrict__ sx, const double *__restrict__ sy,
@@ -1230,12 +1226,11 @@ __global__ void __launch_bounds__(64)
                   double *__restrict__ psi, double *__restrict__ dpsi) {
   __shared__ double2 sz[kStage];
   __shared__ double2 sp[kStage];
-  __shared__ int64_t rs[64];
-  __shared__ int pre[65];
   const int b = leaves[blockIdx.x];
   const int lane = threadIdx.x;
   const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
-  const int ub = u_ptr[b], ue = u_ptr[b + 1];
+  const int64_t uf0 = uf_ptr[b];
+  const int utot = (int)(uf_ptr[b + 1] - uf0);  // U-list sources of the leaf
   const int wb = w_ptr[b], we = w_ptr[b + 1];
   for (int64_t tc = 0; tc < ntb; tc += 64) {
     const int64_t i = tb0 + tc + lane;
@@ -1271,13 +1266,12 @@ __global__ void __launch_bounds__(64)
         df = df - d;
       }
     }
-    for (int eb = ub; eb < ue; eb += 64) {
-      const int cnt = min(64, ue - eb);
-      const int total = gather_ranges(u_src, eb, cnt, s0, s1, rs, pre);
+    {  // the leaf's U-list sources, kStage at a time
+      const int total = utot;
       for (int q0 = 0; q0 < total; q0 += kStage) {
         const int take = min(kStage, total - q0);
         for (int q = lane; q < take; q += 64) {
-          const int64_t j = locate(q0 + q, cnt, rs, pre);
+          const int64_t j = uf_idx[uf0 + q0 + q];
           sz[q] = make_double2(sx[j], sy[j]);
           sp[q] = make_double2(p[j].x, p[j].y);
         }
@@ -1318,7 +1312,7 @@ static void run64_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
     hipLaunchKernelGGL((k_leaf64_full<P>), dim3(pl.n_leaf_t), dim3(64), 0, s,
                        pl.leaf_t.p, pl.lev.p, pl.t0.p, pl.t1.p, pl.s0.p,
                        pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p, pl.tx.p, pl.ty.p,
-                       pl.tgt_perm.p, pl.u_ptr.p, pl.u_src.p, pl.w_ptr.p,
+                       pl.tgt_perm.p, pl.uf_ptr.p, pl.uf_idx.p, pl.w_ptr.p,
                        pl.w_src.p, pl.sx.p, pl.sy.p, (const cx<double> *)p,
                        (const cx<double> *)M, (const cx<double> *)L, psi,
                        dpsi);
@@ -1366,8 +1360,8 @@ __global__ void __launch_bounds__(64)
                   const double *__restrict__ rad,
                   const double *__restrict__ tx, const double *__restrict__ ty,
                   const int64_t *__restrict__ tperm,
-                  const int32_t *__restrict__ u_ptr,
-                  const int32_t *__restrict__ u_src,
+                  const int64_t *__restrict__ uf_ptr,
+                  const int32_t *__restrict__ uf_idx,
                   const int32_t *__restrict__ w_ptr,
                   const int32_t *__restrict__ w_src,
                   const double *__restrict__ sx, const double *__restrict__ sy,
@@ -1376,14 +1370,13 @@ __global__ void __launch_bounds__(64)
                   const cx<float> *__restrict__ L, double *__restrict__ psi) {
   __shared__ double2 sz[kStage];
   __shared__ float2 sp[kStage];
-  __shared__ int64_t rs[64];
-  __shared__ int pre[65];
   const int b = leaves[blockIdx.x];
   const int lane = threadIdx.x;
   const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
   const int tp = ntb <= 32 ? pow2_at_least((int)ntb) : 64;
   const int S = 64 / tp, tl = lane % tp, sl = lane / tp;
-  const int ub = u_ptr[b], ue = u_ptr[b + 1];
+  const int64_t uf0 = uf_ptr[b];
+  const int utot = (int)(uf_ptr[b + 1] - uf0);  // U-list sources of the leaf
   const int wb = w_ptr[b], we = w_ptr[b + 1];
   for (int64_t tc = 0; tc < ntb; tc += tp) {
     const int64_t i = tb0 + tc + tl;
@@ -1410,13 +1403,12 @@ __global__ void __launch_bounds__(64)
         f = f + acc * rho;
       }
     }
-    for (int eb = ub; eb < ue; eb += 64) {
-      const int cnt = min(64, ue - eb);
-      const int total = gather_ranges(u_src, eb, cnt, s0, s1, rs, pre);
+    {  // the leaf's U-list sources, kStage at a time
+      const int total = utot;
       for (int q0 = 0; q0 < total; q0 += kStage) {
         const int take = min(kStage, total - q0);
         for (int q = lane; q < take; q += 64) {
-          const int64_t j = locate(q0 + q, cnt, rs, pre);
+          const int64_t j = uf_idx[uf0 + q0 + q];
           sz[q] = make_double2(sx[j], sy[j]);
           const cx<float> pj = p[j];
           sp[q] = make_float2(pj.x, pj.y);
@@ -1462,7 +1454,7 @@ static void run32_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
                        pl.leaf_t.p, pl.lev.p, pl.t0.p, pl.t1.p, pl.s0.p,
                        pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p, pl.tx.p, pl.ty.p,
                        pl.tgt_perm.p,
-                       pl.u_ptr.p, pl.u_src.p, pl.w_ptr.p, pl.w_src.p,
+                       pl.uf_ptr.p, pl.uf_idx.p, pl.w_ptr.p, pl.w_src.p,
                        pl.sx.p, pl.sy.p,
                        (const cx<float> *)p, (const cx<float> *)M,
                        (const cx<float> *)L, psi);

@@ -87,7 +87,11 @@ struct DevPlan {
   DBuf<int32_t> parent, child0, nchild, quad, lev;
   DBuf<int64_t> s0, s1, t0, t1;
   DBuf<uint8_t> leaf, has_tgt;
-  DBuf<int32_t> v_ptr, v_src, x_ptr, x_src, u_ptr, u_src, w_ptr, w_src;
+  DBuf<int32_t> v_ptr, v_src, x_ptr, x_src, w_ptr, w_src;
+  // per box, the sources of its U list concatenated in list order (tree
+  // order indices; offsets uf_ptr[b] .. uf_ptr[b + 1])
+  DBuf<int64_t> uf_ptr;
+  DBuf<int32_t> uf_idx;
   DBuf<uint8_t> v_code;
   DBuf<int32_t> leaf_t, leaf_s, m2l_box;     // work lists
   int n_x = 0;
