@@ -160,28 +160,30 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
   pl.v_ptr.upload(T.v_ptr, s);
   pl.v_src.upload(T.v_src, s);
   pl.v_code.upload(T.v_code, s);
-  pl.x_ptr.upload(T.x_ptr, s);
-  pl.x_src.upload(T.x_src, s);
-  {
+  // U and X lists as per-box concatenations of their boxes' source points
+  auto flat_sources = [&](const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+                          DBuf<int64_t> &dptr, DBuf<int32_t> &didx) {
     std::vector<int64_t> fp((size_t)nb + 1, 0);
     for (int b = 0; b < nb; ++b) {
       int64_t c = 0;
-      for (int k = T.u_ptr[b]; k < T.u_ptr[b + 1]; ++k) c += T.s1[T.u_src[k]] - T.s0[T.u_src[k]];
+      for (int k = ptr[b]; k < ptr[b + 1]; ++k) c += T.s1[idx[k]] - T.s0[idx[k]];
       fp[b + 1] = fp[b] + c;
     }
-    if (fp[nb] > INT32_MAX) fail(LBS_ERR_UNSUPPORTED, "U-list source table over 2^31 entries");
+    if (fp[nb] > INT32_MAX) fail(LBS_ERR_UNSUPPORTED, "list source table over 2^31 entries");
     std::vector<int32_t> fi((size_t)fp[nb]);
     parallel_for(nb, [&](int64_t b0, int64_t b1) {
       for (int64_t b = b0; b < b1; ++b) {
         int64_t e = fp[b];
-        for (int k = T.u_ptr[b]; k < T.u_ptr[b + 1]; ++k)
-          for (int64_t j = T.s0[T.u_src[k]]; j < T.s1[T.u_src[k]]; ++j) fi[e++] = (int32_t)j;
+        for (int k = ptr[b]; k < ptr[b + 1]; ++k)
+          for (int64_t j = T.s0[idx[k]]; j < T.s1[idx[k]]; ++j) fi[e++] = (int32_t)j;
       }
     }, 1024);
-    pl.uf_ptr.upload(fp, s);
-    pl.uf_idx.upload(fi, s);
+    dptr.upload(fp, s);
+    didx.upload(fi, s);
     LBS_HIP(hipStreamSynchronize(s));  // fp, fi are released on return
-  }
+  };
+  flat_sources(T.u_ptr, T.u_src, pl.uf_ptr, pl.uf_idx);
+  flat_sources(T.x_ptr, T.x_src, pl.xf_ptr, pl.xf_idx);
   pl.w_ptr.upload(T.w_ptr, s);
   pl.w_src.upload(T.w_src, s);
   pl.leaf_t.upload(leaf_t, s);

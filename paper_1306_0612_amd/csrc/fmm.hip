@@ -120,49 +120,6 @@ __global__ void k_strengths(int64_t ns, const int64_t *__restrict__ perm,
   p[(int64_t)r * ns + j] = cx<T>{T(qy * s), T(-qx * s)};
 }
 
-// Concatenated point ranges of list entries: for the (<= 64) entries
-// lst[e0 .. e0 + cnt) of a one-wave block, rs[e] = first point of entry e
-// and pre[e] = points before it; returns the total.  locate(q) maps a
-// position q of the concatenation to its point index.
-__device__ __forceinline__ int gather_ranges(const int32_t *__restrict__ lst,
-                                             int e0, int cnt,
-                                             const int64_t *__restrict__ s0,
-                                             const int64_t *__restrict__ s1,
-                                             int64_t *rs, int *pre) {
-  const int lane = threadIdx.x & 63;
-  int n = 0;
-  int64_t st = 0;
-  if (lane < cnt) {
-    const int c = lst[e0 + lane];
-    st = s0[c];
-    n = (int)(s1[c] - st);
-  }
-  int v = n;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
-  __syncthreads();
-  if (lane < cnt) {
-    rs[lane] = st;
-    pre[lane + 1] = v;
-  }
-  if (lane == 0) pre[0] = 0;
-  __syncthreads();
-  return pre[cnt];
-}
-
-__device__ __forceinline__ int64_t locate(int q, int cnt, const int64_t *rs,
-                                          const int *pre) {
-  int lo = 0, hi = cnt;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (pre[mid] <= q) lo = mid;
-    else hi = mid;
-  }
-  return rs[lo] + (q - pre[lo]);
-}
-
 // Lanes g P + l (g < 64 / P) hold partial sums of coefficient l; returns
 // their total in lane l.  Every lane takes part in the shuffles.
 template <typename T, int P>
@@ -602,8 +559,8 @@ __global__ void __launch_bounds__(256)
 // M2L result.
 template <typename T, int P>
 __global__ void __launch_bounds__(64)
-    k_p2l(const int32_t *__restrict__ boxes, const int32_t *__restrict__ x_ptr,
-          const int32_t *__restrict__ x_src, const double *__restrict__ cxv,
+    k_p2l(const int32_t *__restrict__ boxes, const int64_t *__restrict__ xf_ptr,
+          const int32_t *__restrict__ xf_idx, const double *__restrict__ cxv,
           const double *__restrict__ cyv, const double *__restrict__ rad,
           const int64_t *__restrict__ s0, const int64_t *__restrict__ s1,
           const double *__restrict__ sx, const double *__restrict__ sy,
@@ -611,8 +568,6 @@ __global__ void __launch_bounds__(64)
           int nbox) {
   constexpr int TS = sizeof(T) == 8 ? 32 : 64;  // sources per LDS tile
   __shared__ cx<T> buf[TS][P + 1];
-  __shared__ int64_t rs[64];
-  __shared__ int pre[65];
   const int b = boxes[blockIdx.x];
   const int r = blockIdx.y;
   const int lane = threadIdx.x;
@@ -622,14 +577,14 @@ __global__ void __launch_bounds__(64)
   constexpr int G = 64 / P;
   const int g = lane / P, l = lane % P;
   cx<T> acc{T(0), T(0)};
-  const int xb = x_ptr[b], xe = x_ptr[b + 1];
-  for (int eb = xb; eb < xe; eb += 64) {
-    const int cnt = min(64, xe - eb);
-    const int total = gather_ranges(x_src, eb, cnt, s0, s1, rs, pre);
+  // the sources of the box's X list, concatenated at set-up
+  const int64_t xf0 = xf_ptr[b];
+  const int total = (int)(xf_ptr[b + 1] - xf0);
+  {
     for (int q0 = 0; q0 < total; q0 += TS) {
       const int q = q0 + lane;
       if (lane < TS && q < total) {
-        const int64_t j = locate(q, cnt, rs, pre);
+        const int64_t j = xf_idx[xf0 + q];
         const cx<T> iu = cinv(cx<T>{T(sx[j] - cxb), T(sy[j] - cyb)});
         const cx<T> rho = rb * iu;
         cx<T> t = pr[j] * iu;
@@ -1083,7 +1038,7 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
   if (pl.n_x > 0) {
     TimerScope ts(tm, ST_P2L, s);
     hipLaunchKernelGGL((k_p2l<T, P>), dim3(pl.n_x, nrhs), dim3(64), 0, s,
-                       pl.x_box.p, pl.x_ptr.p, pl.x_src.p, pl.cx.p, pl.cy.p,
+                       pl.x_box.p, pl.xf_ptr.p, pl.xf_idx.p, pl.cx.p, pl.cy.p,
                        pl.rad.p, pl.s0.p, pl.s1.p, pl.sx.p, pl.sy.p, p, pl.ns,
                        L, pl.nbox);
   }

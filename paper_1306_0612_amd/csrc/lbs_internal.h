@@ -87,7 +87,10 @@ struct DevPlan {
   DBuf<int32_t> parent, child0, nchild, quad, lev;
   DBuf<int64_t> s0, s1, t0, t1;
   DBuf<uint8_t> leaf, has_tgt;
-  DBuf<int32_t> v_ptr, v_src, x_ptr, x_src, w_ptr, w_src;
+  DBuf<int32_t> v_ptr, v_src, w_ptr, w_src;
+  // per box, the sources of its X list concatenated (as uf_* for U)
+  DBuf<int64_t> xf_ptr;
+  DBuf<int32_t> xf_idx;
   // per box, the sources of its U list concatenated in list order (tree
   // order indices; offsets uf_ptr[b] .. uf_ptr[b + 1])
   DBuf<int64_t> uf_ptr;
