@@ -105,21 +105,6 @@ void build_tables(Tables &t, int P, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------- kernels
-// Strengths in tree order: p_j = -i qfac_j sigma_j.
-template <typename T>
-__global__ void k_strengths(int64_t ns, const int64_t *__restrict__ perm,
-                            const double *__restrict__ qfac_t,
-                            const double *__restrict__ sigma, int64_t ldx,
-                            cx<T> *__restrict__ p) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int r = blockIdx.y;
-  if (j >= ns) return;
-  double s = sigma[(int64_t)r * ldx + perm[j]];
-  double qx = qfac_t[2 * j], qy = qfac_t[2 * j + 1];
-  // -i (qx + i qy) s = (qy - i qx) s
-  p[(int64_t)r * ns + j] = cx<T>{T(qy * s), T(-qx * s)};
-}
-
 // Lanes g P + l (g < 64 / P) hold partial sums of coefficient l; returns
 // their total in lane l.  Every lane takes part in the shuffles.
 template <typename T, int P>
@@ -136,17 +121,29 @@ __device__ __forceinline__ cx<T> group_sum(cx<T> acc, int lane) {
   return tot;
 }
 
-// Leaf multipoles, one 64-lane block per leaf: lane j forms the powers
-// p_j w_j^k of its source in LDS; the 64 / P lane groups sum every
-// (64 / P)-th row of column k, then the groups are added.
+// Where the leaf multipole pass finds its strengths: with sigma set it
+// forms p_j = -i q_j sigma_j itself (q-factor qfac_t in tree order, sigma in
+// API order through perm, stride ldx per right-hand side) and stores them
+// for the near field and P2L; otherwise it reads p as given.
+struct StrengthSrc {
+  const int64_t *perm = nullptr;
+  const double *qfac_t = nullptr;
+  const double *sigma = nullptr;
+  int64_t ldx = 0;
+};
+
+// Leaf multipoles, one 64-lane block per leaf (every source lies in one
+// leaf): lane j forms the powers p_j w_j^k of its source in LDS; the
+// 64 / P lane groups sum every (64 / P)-th row of column k, then the groups
+// are added.
 template <typename T, int P>
 __global__ void __launch_bounds__(64)
     k_p2m(const int32_t *__restrict__ leaves, const int64_t *__restrict__ s0,
           const int64_t *__restrict__ s1, const double *__restrict__ cxv,
           const double *__restrict__ cyv, const double *__restrict__ rad,
           const double *__restrict__ sx, const double *__restrict__ sy,
-          const cx<T> *__restrict__ p, int64_t ns, cx<T> *__restrict__ M,
-          int nbox) {
+          cx<T> *__restrict__ p, int64_t ns, cx<T> *__restrict__ M,
+          int nbox, StrengthSrc ss) {
   constexpr int TS = sizeof(T) == 8 ? 32 : 64;  // sources per LDS tile
   __shared__ cx<T> buf[TS][P + 1];
   const int b = leaves[blockIdx.x];
@@ -163,7 +160,15 @@ __global__ void __launch_bounds__(64)
     const int n = (int)min<int64_t>(TS, e1 - jb);
     if (lane < n) {
       cx<T> w{T((sx[j] - c_x) * ir), T((sy[j] - c_y) * ir)};
-      cx<T> pw = pr[j];
+      cx<T> pw;
+      if (ss.sigma) {  // form the strength here: p_j = -i q_j sigma_j
+        const double sg = ss.sigma[(int64_t)r * ss.ldx + ss.perm[j]];
+        const double qx = ss.qfac_t[2 * j], qy = ss.qfac_t[2 * j + 1];
+        pw = cx<T>{T(qy * sg), T(-qx * sg)};
+        p[(int64_t)r * ns + j] = pw;
+      } else {
+        pw = pr[j];
+      }
 #pragma unroll
       for (int k = 0; k < P; ++k) {
         buf[lane][k] = pw;
@@ -989,8 +994,8 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
 // ---------------------------------------------------------------- drivers
 template <typename T, int P>
 static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
-                      const cx<T> *p, cx<T> *M, cx<T> *L, int nrhs,
-                      hipStream_t s) {
+                      cx<T> *p, cx<T> *M, cx<T> *L, int nrhs,
+                      hipStream_t s, StrengthSrc ss = StrengthSrc{}) {
   StageTimer *tm = ws.timer;
   const cx<T> *itp, *pre, *post;
   const T *H, *bc;
@@ -1012,7 +1017,8 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
     if (pl.n_leaf_s > 0)
       hipLaunchKernelGGL((k_p2m<T, P>), dim3(pl.n_leaf_s, nrhs), dim3(64), 0,
                          s, pl.leaf_s.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p,
-                         pl.rad.p, pl.sx.p, pl.sy.p, p, pl.ns, M, pl.nbox);
+                         pl.rad.p, pl.sx.p, pl.sy.p, p, pl.ns, M, pl.nbox,
+                         ss);
     for (size_t g = 0; g + 1 < pl.up_gptr.size(); ++g) {
       const int a0 = pl.up_gptr[g], n = pl.up_gptr[g + 1] - a0;
       if (n <= 0) continue;
@@ -1055,11 +1061,11 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
 template <int P>
 static void run64(const DevPlan &pl, const Tables &tb, Workspace &ws,
                   int nrhs, double *out, int64_t ldy, double scale,
-                  const Assembly &as, hipStream_t s) {
+                  const Assembly &as, hipStream_t s, const StrengthSrc &ss) {
   auto *p = (cx<double> *)ws.pstr64.p;
   auto *M = (cx<double> *)ws.mult64.p;
   auto *L = (cx<double> *)ws.loc64.p;
-  far_field<double, P>(pl, tb, ws, p, M, L, nrhs, s);
+  far_field<double, P>(pl, tb, ws, p, M, L, nrhs, s, ss);
   if (pl.n_leaf_t > 0) {
     TimerScope ts(ws.timer, ST_LEAF, s);
     hipLaunchKernelGGL((k_leaf64<P>), dim3(pl.n_leaf_t, nrhs), dim3(64), 0, s,
@@ -1075,11 +1081,11 @@ static void run64(const DevPlan &pl, const Tables &tb, Workspace &ws,
 template <int P>
 static void run32(const DevPlan &pl, const Tables &tb, Workspace &ws,
                   int nrhs, double *out, int64_t ldy, double scale,
-                  const Assembly &as, hipStream_t s) {
+                  const Assembly &as, hipStream_t s, const StrengthSrc &ss) {
   auto *p = (cx<float> *)ws.pstr32.p;
   auto *M = (cx<float> *)ws.mult32.p;
   auto *L = (cx<float> *)ws.loc32.p;
-  far_field<float, P>(pl, tb, ws, p, M, L, nrhs, s);
+  far_field<float, P>(pl, tb, ws, p, M, L, nrhs, s, ss);
   if (pl.n_leaf_t > 0) {
     TimerScope ts(ws.timer, ST_LEAF, s);
     auto launch = [&](auto kern, int rb) {
@@ -1103,20 +1109,15 @@ void fmm_apply64(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  const double *qfac_t, const double *sigma, int64_t ldx,
                  int nrhs, double *out, int64_t ldy, double scale,
                  const Assembly &as, hipStream_t s) {
-  if (pl.ns > 0) {
-    TimerScope ts(ws.timer, ST_STRENGTHS, s);
-    dim3 grid((unsigned)((pl.ns + 255) / 256), nrhs);
-    hipLaunchKernelGGL((k_strengths<double>), grid, dim3(256), 0, s, pl.ns,
-                       pl.src_perm.p, qfac_t, sigma, ldx,
-                       (cx<double> *)ws.pstr64.p);
-  }
+  // the strengths p_j = -i q_j sigma_j are formed by the leaf multipole pass
+  const StrengthSrc ss{pl.src_perm.p, qfac_t, sigma, ldx};
   switch (tb.P) {
-    case 20: run64<20>(pl, tb, ws, nrhs, out, ldy, scale, as, s); break;
-    case 24: run64<24>(pl, tb, ws, nrhs, out, ldy, scale, as, s); break;
-    case 30: run64<30>(pl, tb, ws, nrhs, out, ldy, scale, as, s); break;
-    case 36: run64<36>(pl, tb, ws, nrhs, out, ldy, scale, as, s); break;
-    case 40: run64<40>(pl, tb, ws, nrhs, out, ldy, scale, as, s); break;
-    case 48: run64<48>(pl, tb, ws, nrhs, out, ldy, scale, as, s); break;
+    case 20: run64<20>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
+    case 24: run64<24>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
+    case 30: run64<30>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
+    case 36: run64<36>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
+    case 40: run64<40>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
+    case 48: run64<48>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
     default:
       throw ApiError{LBS_ERR_UNSUPPORTED,
                      "p64 must be one of 20, 24, 30, 36, 40, 48"};
@@ -1128,18 +1129,13 @@ void fmm_apply32(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  const double *qfac_t, const double *sigma, int64_t ldx,
                  int nrhs, double *out, int64_t ldy, double scale,
                  const Assembly &as, hipStream_t s) {
-  if (pl.ns > 0) {
-    TimerScope ts(ws.timer, ST_STRENGTHS, s);
-    dim3 grid((unsigned)((pl.ns + 255) / 256), nrhs);
-    hipLaunchKernelGGL((k_strengths<float>), grid, dim3(256), 0, s, pl.ns,
-                       pl.src_perm.p, qfac_t, sigma, ldx,
-                       (cx<float> *)ws.pstr32.p);
-  }
+  // the strengths p_j = -i q_j sigma_j are formed by the leaf multipole pass
+  const StrengthSrc ss{pl.src_perm.p, qfac_t, sigma, ldx};
   switch (tb.P) {
-    case 12: run32<12>(pl, tb, ws, nrhs, out, ldy, scale, as, s); break;
-    case 16: run32<16>(pl, tb, ws, nrhs, out, ldy, scale, as, s); break;
-    case 20: run32<20>(pl, tb, ws, nrhs, out, ldy, scale, as, s); break;
-    case 24: run32<24>(pl, tb, ws, nrhs, out, ldy, scale, as, s); break;
+    case 12: run32<12>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
+    case 16: run32<16>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
+    case 20: run32<20>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
+    case 24: run32<24>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
     default:
       throw ApiError{LBS_ERR_UNSUPPORTED, "p32 must be one of 12, 16, 20, 24"};
   }
