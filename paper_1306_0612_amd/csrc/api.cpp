@@ -77,6 +77,7 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
   pl.n_leaf_t = (int)leaf_t.size();
   pl.n_m2l = (int)m2l.size();
   pl.leaf_t_host = leaf_t;
+  pl.leaf_s_host = leaf_s;
   // subtree heaps of the fused upward / downward passes (see DevPlan)
   std::vector<int32_t> xb;
   {
@@ -225,6 +226,13 @@ void Workspace::ensure(const DevPlan &pl, int P64, int P32, int nrhs,
   mult32.alloc((size_t)pl.nbox * P32 * nrhs * 2);
   loc32.alloc((size_t)pl.nbox * P32 * nrhs * 2);
   gam.alloc((size_t)std::max(nrhs, 1) * G);
+  gpart.alloc((size_t)std::max(pl.n_leaf_s, 1) * nrhs);
+  {
+    const int nch = (std::max(pl.n_leaf_s, 1) + 2047) / 2048;  // bound for every geometry
+    gcsum.alloc((size_t)nch * G * nrhs);
+    gcnt.alloc((size_t)G * nrhs);
+    LBS_HIP(hipMemset(gcnt.p, 0, gcnt.n * sizeof(int32_t)));
+  }
   tmpM.alloc((size_t)std::max(M, 1) * nrhs);
   logL.alloc((size_t)std::max(M, 1) * nrhs * (2 * (Plog + 1) + 2));
   // reduction scratch: plain dots (512 x nrhs) and segmented dots of up to
@@ -321,11 +329,6 @@ void apply_K(lbs_ctx &c, int prec, int nrhs, const double *x, int64_t ldx,
              double *y, int64_t ldy, double ident, hipStream_t s) {
   Geometry &g = c.geo;
   ensure_ws(c, nrhs);
-  {
-    TimerScope ts(c.ws.timer, ST_GAMMA, s);
-    launch_segdots(c.seg_nodes, nrhs, 1, g.gw.p, 0, 0, x, ldx, c.ws.gam.p,
-                   c.ws.red.p, s);
-  }
   Assembly as;
   as.sigma = x;
   as.tau = g.tau.p;
@@ -334,15 +337,28 @@ void apply_K(lbs_ctx &c, int prec, int nrhs, const double *x, int64_t ldx,
   as.G = g.G;
   as.ident = ident;
   as.ldx = ldx;
+  // gamma: by a segmented dot product for the direct sum, inside the FMM
+  // (partial sums of the leaf multipole pass) otherwise
+  GammaFused gf;
+  gf.gw_t = g.gw_t.p;
+  gf.gl_ptr = g.gleaf_ptr.p;
+  gf.gamma = c.ws.gam.p;
+  gf.G = g.G;
+  gf.nchunk = g.gleaf_chunks;
   if (c.opt.matvec == LBS_MATVEC_DIRECT) {
+    {
+      TimerScope ts(c.ws.timer, ST_GAMMA, s);
+      launch_segdots(c.seg_nodes, nrhs, 1, g.gw.p, 0, 0, x, ldx, c.ws.gam.p,
+                     c.ws.red.p, s);
+    }
     TimerScope ts(c.ws.timer, ST_LEAF, s);
     direct_apply64(g.N, g.xi.p, g.qfac.p, x, ldx, nrhs, y, ldy, as, s);
   } else if (prec == LBS_FP64) {
     fmm_apply64(c.plan, c.tab64, c.ws, g.qfac_t.p, x, ldx, nrhs, y, ldy, 1.0,
-                as, s);
+                as, s, &gf);
   } else {
     fmm_apply32(c.plan, c.tab32, c.ws, g.qfac_t.p, x, ldx, nrhs, y, ldy, 1.0,
-                as, s);
+                as, s, &gf);
   }
 }
 
@@ -443,7 +459,7 @@ std::vector<const void *> graph_signature(lbs_ctx &c) {
   return {st.V.p, st.H.p, st.cs.p, st.sn.p, st.gv.p, st.h1.p, st.h2.p, st.nrm2.p,
           st.tol.p, st.resid.p, st.active.p, st.kused.p, st.count.p, w.pstr64.p,
           w.mult64.p, w.loc64.p, w.pstr32.p, w.mult32.p, w.loc32.p, w.gam.p,
-          w.red.p, w.tmpM.p, w.logL.p, a.mom.p, a.tA.p, a.lam.p, a.pc.p, a.Fc.p,
+          w.gpart.p, w.gcsum.p, w.gcnt.p, w.red.p, w.tmpM.p, w.logL.p, a.mom.p, a.tA.p, a.lam.p, a.pc.p, a.Fc.p,
           a.ysum.p, c.geo.SinvT.p};
 }
 
@@ -958,6 +974,30 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl,
               ctx->plan, s);
   g.qfac_t.alloc(2 * N);
   launch_permute_complex(N, ctx->plan.src_perm.p, g.qfac.p, g.qfac_t.p, s);
+  {
+    // gamma weights in tree order, and each geometry's source leaves
+    const Tree &F = ctx->plan.host;
+    std::vector<double> gw = g.gw.download(s), gwt(N);
+    for (int64_t j = 0; j < N; ++j) gwt[j] = gw[F.src_perm[j]];
+    g.gw_t.upload(gwt, s);
+    // (the forest holds each geometry's tree in turn, so its leaves are
+    // contiguous in the leaf list)
+    const std::vector<int32_t> &ls = ctx->plan.leaf_s_host;
+    std::vector<int32_t> gp(G + 1, 0);
+    int prev = 0;
+    for (size_t i = 0; i < ls.size(); ++i) {
+      const int q = node_geo[F.src_perm[F.s0[ls[i]]]];
+      if (q < prev) fail(LBS_ERR_GEOMETRY, "source leaves not grouped by geometry");
+      prev = q;
+      ++gp[q + 1];
+    }
+    for (int q = 0; q < G; ++q) gp[q + 1] += gp[q];
+    g.gleaf_chunks = 1;
+    for (int q = 0; q < G; ++q)
+      g.gleaf_chunks = std::max(g.gleaf_chunks, (gp[q + 1] - gp[q] + 2047) / 2048);
+    g.gleaf_ptr.upload(gp, s);
+    LBS_HIP(hipStreamSynchronize(s));
+  }
   build_tables(ctx->tab64, o.p64, s);
   build_tables(ctx->tab32, o.p32, s);
   // segments for the per-geometry reductions

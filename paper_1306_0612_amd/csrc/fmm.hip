@@ -130,6 +130,10 @@ struct StrengthSrc {
   const double *qfac_t = nullptr;
   const double *sigma = nullptr;
   int64_t ldx = 0;
+  // with gpart set: gpart[r * (#leaves) + leaf] = sum over the leaf's
+  // sources of gw_t[j] sigma_j (FP64), for GammaFused
+  const double *gw_t = nullptr;
+  double *gpart = nullptr;
 };
 
 // Leaf multipoles, one 64-lane block per leaf (every source lies in one
@@ -154,6 +158,7 @@ __global__ void __launch_bounds__(64)
   constexpr int G = 64 / P;
   const int g = lane / P, l = lane % P;
   cx<T> acc{T(0), T(0)};
+  double gsum = 0.0;
   const int64_t e0 = s0[b], e1 = s1[b];
   for (int64_t jb = e0; jb < e1; jb += TS) {
     const int64_t j = jb + lane;
@@ -166,6 +171,7 @@ __global__ void __launch_bounds__(64)
         const double qx = ss.qfac_t[2 * j], qy = ss.qfac_t[2 * j + 1];
         pw = cx<T>{T(qy * sg), T(-qx * sg)};
         p[(int64_t)r * ns + j] = pw;
+        if (ss.gpart) gsum += ss.gw_t[j] * sg;
       } else {
         pw = pr[j];
       }
@@ -182,6 +188,49 @@ __global__ void __launch_bounds__(64)
   }
   acc = group_sum<T, P>(acc, lane);
   if (lane < P) M[((int64_t)r * nbox + b) * P + lane] = T(ir) * acc;
+  if (ss.gpart) {  // block-uniform
+    for (int o = 32; o > 0; o >>= 1) gsum += __shfl_xor(gsum, o, 64);
+    if (lane == 0) ss.gpart[(int64_t)r * gridDim.x + blockIdx.x] = gsum;
+  }
+}
+
+// gamma[r G + g] = the sum of the partial sums of geometry g's source
+// leaves, positions gl_ptr[g] .. gl_ptr[g + 1] of the plan's leaf list.
+// Block (c, g, r) sums chunk c of that range into csum; the last block of
+// (g, r) to finish (a device-scope counter) adds the chunk sums in index
+// order and resets the counter for the next application, so the result
+// does not depend on the order in which blocks run.
+constexpr int kGammaChunk = 2048;
+__global__ void __launch_bounds__(256)
+    k_gamma_reduce(const int32_t *__restrict__ gl_ptr,
+                   const double *__restrict__ gpart, int nls, int G,
+                   double *__restrict__ csum, int32_t *__restrict__ cnt,
+                   double *__restrict__ gamma) {
+  __shared__ double red[4];
+  __shared__ bool last;
+  const int c = blockIdx.x, g = blockIdx.y, r = blockIdx.z, tid = threadIdx.x;
+  const int nch = gridDim.x, slot = r * G + g;
+  const int a = gl_ptr[g] + c * kGammaChunk, b = min(gl_ptr[g + 1], a + kGammaChunk);
+  double v = 0.0;
+  for (int e = a + tid; e < b; e += 256) v += gpart[(int64_t)r * nls + e];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    csum[(int64_t)slot * nch + c] = red[0] + red[1] + red[2] + red[3];
+    __threadfence();
+    last = atomicAdd(&cnt[slot], 1) == nch - 1;
+  }
+  __syncthreads();
+  if (last && tid == 0) {
+    __threadfence();
+    double t = 0.0;
+    for (int k = 0; k < nch; ++k)
+      t += __hip_atomic_load(&csum[(int64_t)slot * nch + k], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    gamma[slot] = t;
+    cnt[slot] = 0;
+  }
 }
 
 // Upward pass over three levels per launch: one work-group per root, whose
@@ -1061,11 +1110,18 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
 template <int P>
 static void run64(const DevPlan &pl, const Tables &tb, Workspace &ws,
                   int nrhs, double *out, int64_t ldy, double scale,
-                  const Assembly &as, hipStream_t s, const StrengthSrc &ss) {
+                  const Assembly &as, hipStream_t s, const StrengthSrc &ss,
+                  const GammaFused *gf) {
   auto *p = (cx<double> *)ws.pstr64.p;
   auto *M = (cx<double> *)ws.mult64.p;
   auto *L = (cx<double> *)ws.loc64.p;
   far_field<double, P>(pl, tb, ws, p, M, L, nrhs, s, ss);
+  if (gf && pl.n_leaf_s > 0) {
+    TimerScope ts(ws.timer, ST_GAMMA, s);
+    hipLaunchKernelGGL(k_gamma_reduce, dim3(gf->nchunk, gf->G, nrhs), dim3(256), 0,
+                       s, gf->gl_ptr, ws.gpart.p, pl.n_leaf_s, gf->G, ws.gcsum.p,
+                       ws.gcnt.p, gf->gamma);
+  }
   if (pl.n_leaf_t > 0) {
     TimerScope ts(ws.timer, ST_LEAF, s);
     hipLaunchKernelGGL((k_leaf64<P>), dim3(pl.n_leaf_t, nrhs), dim3(64), 0, s,
@@ -1081,11 +1137,18 @@ static void run64(const DevPlan &pl, const Tables &tb, Workspace &ws,
 template <int P>
 static void run32(const DevPlan &pl, const Tables &tb, Workspace &ws,
                   int nrhs, double *out, int64_t ldy, double scale,
-                  const Assembly &as, hipStream_t s, const StrengthSrc &ss) {
+                  const Assembly &as, hipStream_t s, const StrengthSrc &ss,
+                  const GammaFused *gf) {
   auto *p = (cx<float> *)ws.pstr32.p;
   auto *M = (cx<float> *)ws.mult32.p;
   auto *L = (cx<float> *)ws.loc32.p;
   far_field<float, P>(pl, tb, ws, p, M, L, nrhs, s, ss);
+  if (gf && pl.n_leaf_s > 0) {
+    TimerScope ts(ws.timer, ST_GAMMA, s);
+    hipLaunchKernelGGL(k_gamma_reduce, dim3(gf->nchunk, gf->G, nrhs), dim3(256), 0,
+                       s, gf->gl_ptr, ws.gpart.p, pl.n_leaf_s, gf->G, ws.gcsum.p,
+                       ws.gcnt.p, gf->gamma);
+  }
   if (pl.n_leaf_t > 0) {
     TimerScope ts(ws.timer, ST_LEAF, s);
     auto launch = [&](auto kern, int rb) {
@@ -1108,16 +1171,18 @@ static void run32(const DevPlan &pl, const Tables &tb, Workspace &ws,
 void fmm_apply64(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  const double *qfac_t, const double *sigma, int64_t ldx,
                  int nrhs, double *out, int64_t ldy, double scale,
-                 const Assembly &as, hipStream_t s) {
-  // the strengths p_j = -i q_j sigma_j are formed by the leaf multipole pass
-  const StrengthSrc ss{pl.src_perm.p, qfac_t, sigma, ldx};
+                 const Assembly &as, hipStream_t s, const GammaFused *gf) {
+  // the strengths p_j = -i q_j sigma_j (and with gf the partial gamma
+  // sums) are formed by the leaf multipole pass
+  const StrengthSrc ss{pl.src_perm.p, qfac_t, sigma, ldx, gf ? gf->gw_t : nullptr,
+                       gf ? ws.gpart.p : nullptr};
   switch (tb.P) {
-    case 20: run64<20>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
-    case 24: run64<24>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
-    case 30: run64<30>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
-    case 36: run64<36>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
-    case 40: run64<40>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
-    case 48: run64<48>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
+    case 20: run64<20>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss, gf); break;
+    case 24: run64<24>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss, gf); break;
+    case 30: run64<30>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss, gf); break;
+    case 36: run64<36>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss, gf); break;
+    case 40: run64<40>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss, gf); break;
+    case 48: run64<48>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss, gf); break;
     default:
       throw ApiError{LBS_ERR_UNSUPPORTED,
                      "p64 must be one of 20, 24, 30, 36, 40, 48"};
@@ -1128,14 +1193,16 @@ void fmm_apply64(const DevPlan &pl, const Tables &tb, Workspace &ws,
 void fmm_apply32(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  const double *qfac_t, const double *sigma, int64_t ldx,
                  int nrhs, double *out, int64_t ldy, double scale,
-                 const Assembly &as, hipStream_t s) {
-  // the strengths p_j = -i q_j sigma_j are formed by the leaf multipole pass
-  const StrengthSrc ss{pl.src_perm.p, qfac_t, sigma, ldx};
+                 const Assembly &as, hipStream_t s, const GammaFused *gf) {
+  // the strengths p_j = -i q_j sigma_j (and with gf the partial gamma
+  // sums) are formed by the leaf multipole pass
+  const StrengthSrc ss{pl.src_perm.p, qfac_t, sigma, ldx, gf ? gf->gw_t : nullptr,
+                       gf ? ws.gpart.p : nullptr};
   switch (tb.P) {
-    case 12: run32<12>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
-    case 16: run32<16>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
-    case 20: run32<20>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
-    case 24: run32<24>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss); break;
+    case 12: run32<12>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss, gf); break;
+    case 16: run32<16>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss, gf); break;
+    case 20: run32<20>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss, gf); break;
+    case 24: run32<24>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss, gf); break;
     default:
       throw ApiError{LBS_ERR_UNSUPPORTED, "p32 must be one of 12, 16, 20, 24"};
   }

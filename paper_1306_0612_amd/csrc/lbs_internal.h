@@ -82,6 +82,7 @@ struct DevPlan {
   bool self = true;
   std::vector<int32_t> level_ptr;            // host copy
   std::vector<int32_t> leaf_t_host;          // leaves with targets
+  std::vector<int32_t> leaf_s_host;          // leaves with sources
   int n_leaf_t = 0, n_leaf_s = 0, n_m2l = 0;
   DBuf<double> cx, cy, rad;
   DBuf<int32_t> parent, child0, nchild, quad, lev;
@@ -212,6 +213,9 @@ struct Geometry {
   DBuf<int32_t> node_geo, isl_geo;   // geometry of each node / island
   DBuf<int32_t> row_geo;             // geometry of each unknown (N + M)
   DBuf<double> qfac_t;               // qfac in tree order
+  DBuf<double> gw_t;                 // gamma weights in tree order
+  DBuf<int32_t> gleaf_ptr;           // per geometry: range in leaf_s
+  int gleaf_chunks = 1;              // most 2048-leaf chunks of a geometry
   DBuf<double> dcenter, deta, drho, dellc;  // centres, eta, rho, log(1+|eta|^2)
   DBuf<int64_t> doffs, dgnode, dgsinv;
   DBuf<int32_t> dgisl;
@@ -255,6 +259,9 @@ struct Workspace {
   DBuf<double> pstr64, mult64, loc64;
   DBuf<float> pstr32, mult32, loc32;
   DBuf<double> gam;       // per (rhs, geometry)
+  DBuf<double> gpart;     // per (rhs, source leaf): partial gamma sums
+  DBuf<double> gcsum;     // per (rhs, geometry, chunk): chunk sums of gpart
+  DBuf<int32_t> gcnt;     // per (rhs, geometry): finished chunks (kept 0)
   DBuf<double> red;       // reduction scratch
   DBuf<double> tmpM, logL;
   void ensure(const DevPlan &pl, int P64, int P32, int nrhs, int64_t N,
@@ -290,10 +297,22 @@ struct Assembly {
   double ident = 0.0;             // coefficient of sigma (1 for I + K)
   int64_t ldx = 0;
 };
+// The correction constants gamma[r G + g] = sum_j gw_j sigma_j over the
+// nodes of geometry g, formed inside the FMM from per-leaf partial sums of
+// the leaf multipole pass (gw_t in tree order; geometry g's leaves are
+// positions gl_ptr[g] .. gl_ptr[g + 1] of the plan's source-leaf list,
+// nchunk = the most chunks of 2048 leaves a geometry has).
+struct GammaFused {
+  const double *gw_t = nullptr;
+  const int32_t *gl_ptr = nullptr;
+  double *gamma = nullptr;
+  int G = 1, nchunk = 1;
+};
 void fmm_apply64(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  const double *qfac_t, const double *sigma, int64_t ldx,
                  int nrhs, double *out, int64_t ldy, double scale,
-                 const Assembly &as, hipStream_t s);
+                 const Assembly &as, hipStream_t s,
+                 const GammaFused *gf = nullptr);
 // Psi(z) = sum_j p_j / (z - z_j) and Psi'(z) (complex, FP64) at the plan's
 // targets for complex strengths pin (API order of the plan's sources);
 // outputs in the targets' API order, dpsi may be null.  One column.
@@ -306,7 +325,8 @@ void fmm_apply32_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
 void fmm_apply32(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  const double *qfac_t, const double *sigma, int64_t ldx,
                  int nrhs, double *out, int64_t ldy, double scale,
-                 const Assembly &as, hipStream_t s);
+                 const Assembly &as, hipStream_t s,
+                 const GammaFused *gf = nullptr);
 // direct O(N^2) sums (single-geometry handles)
 void direct_apply64(int64_t N, const double *xi, const double *qfac,
                     const double *sigma, int64_t ldx, int nrhs, double *out,
