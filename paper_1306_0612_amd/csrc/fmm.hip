@@ -105,20 +105,84 @@ void build_tables(Tables &t, int P, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------- kernels
-// Lanes g P + l (g < 64 / P) hold partial sums of coefficient l; returns
-// their total in lane l.  Every lane takes part in the shuffles.
-template <typename T, int P>
-__device__ __forceinline__ cx<T> group_sum(cx<T> acc, int lane) {
-  constexpr int G = 64 / P;
-  const int l = lane % P;
-  cx<T> tot = acc;
+// v[0 .. NV) summed over the 64 lanes of a wave by recursive halving: at
+// step s (partner lane ^ (32 >> s)) a lane keeps the upper half of its
+// values when that lane bit is set, else the lower half, and adds its
+// partner's copy of the half it keeps; once a single value is left the
+// remaining steps add it whole.  Lane i returns the total of value
+// i >> (6 - log2 NV); NV - 1 + 6 - log2 NV shuffles in all.
+template <typename T, int NV, int S = 0>
+__device__ __forceinline__ void halving_steps(T (&v)[NV], int lane) {
+  if constexpr (S < 6) {
+    constexpr int o = 32 >> S, h = NV >> (S + 1);
+    if constexpr (h >= 1) {
+      const bool up = (lane & o) != 0;
 #pragma unroll
-  for (int gg = 1; gg < G; ++gg) {
-    const int src = l + gg * P;
-    const T x = __shfl(acc.x, src, 64), y = __shfl(acc.y, src, 64);
-    tot = tot + cx<T>{x, y};
+      for (int k = 0; k < h; ++k) {
+        const T send = up ? v[k] : v[k + h];
+        const T keep = up ? v[k + h] : v[k];
+        v[k] = keep + __shfl_xor(send, o, 64);
+      }
+    } else {
+      v[0] += __shfl_xor(v[0], o, 64);
+    }
+    halving_steps<T, NV, S + 1>(v, lane);
   }
-  return tot;
+}
+
+template <typename T, int NV>
+__device__ __forceinline__ T halving_sum(T (&v)[NV], int lane) {
+  static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0,
+                "a power of two up to the wave size");
+  halving_steps<T, NV>(v, lane);
+  return v[0];
+}
+
+constexpr int pow2_ceil(int n) { return n <= 1 ? 1 : 2 * pow2_ceil((n + 1) / 2); }
+constexpr int log2_exact(int n) { return n <= 1 ? 0 : 1 + log2_exact(n / 2); }
+
+// Coefficients per register pass of the P2M and P2L sums: 2 KB real
+// accumulators per lane (KB of 16 FP64 or 32 FP32 terms keeps them within
+// 64 registers); an order above KB takes several passes over the sources.
+template <typename T, int P>
+constexpr int kChunk() {
+  return P < (sizeof(T) == 8 ? 16 : 32) ? P : (sizeof(T) == 8 ? 16 : 32);
+}
+
+// P2L sum of one box (centre (cxb, cyb), half-width rb) over the sources
+// of its X list, xf_idx[x0 .. x0 + total) (concatenated at set-up), for
+// coefficients K0 .. K0 + KB - 1: lane q accumulates t_q (r/u_q)^l,
+// t_q = -p_q / u_q, u_q = z_q - c, for sources q, q + 64, ... in registers
+// (parts of coefficient K0 + l as values 2l, 2l + 1); one halving sum.
+// Lane i returns the total of value i >> (6 - log2 NV), NV = pow2 >= 2 KB.
+template <typename T, int P, int K0, int KB>
+__device__ __forceinline__ T p2l_sum(int64_t x0, int total,
+                                     const int32_t *__restrict__ xf_idx,
+                                     double cxb, double cyb, T rb,
+                                     const double *__restrict__ sx,
+                                     const double *__restrict__ sy,
+                                     const cx<T> *__restrict__ pr, int lane) {
+  constexpr int NV = pow2_ceil(2 * KB);
+  T acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = T(0);
+  for (int q = lane; q < total; q += 64) {
+    const int64_t j = xf_idx[x0 + q];
+    const cx<T> iu = cinv(cx<T>{T(sx[j] - cxb), T(sy[j] - cyb)});
+    const cx<T> rho = rb * iu;
+    cx<T> t = pr[j] * iu;
+    t = cx<T>{-t.x, -t.y};
+    if (K0 > 0) t = t * cpow(rho, K0);
+#pragma unroll
+    for (int l = 0; l < KB; ++l) {
+      if (K0 + l < P) {
+        acc[2 * l] += t.x;
+        acc[2 * l + 1] += t.y;
+        t = t * rho;
+      }
+    }
+  }
+  return halving_sum<T, NV>(acc, lane);
 }
 
 // Where the leaf multipole pass finds its strengths: with sigma set it
@@ -136,10 +200,12 @@ struct StrengthSrc {
   double *gpart = nullptr;
 };
 
-// Leaf multipoles, one 64-lane block per leaf (every source lies in one
-// leaf): lane j forms the powers p_j w_j^k of its source in LDS; the
-// 64 / P lane groups sum every (64 / P)-th row of column k, then the groups
-// are added.
+// Leaf multipoles, one wave per leaf (every source lies in one leaf): lane
+// j accumulates p_j w_j^k of sources j, j + 64, ... in registers, KB
+// coefficients per pass (real and imaginary parts as values 2k, 2k + 1 of
+// NV = pow2 >= 2 KB), and one halving sum per pass leaves the parts of
+// coefficient k in lanes (2k + c) << SH.  The first pass forms the
+// strengths (when asked to); later passes read them back.
 template <typename T, int P>
 __global__ void __launch_bounds__(64)
     k_p2m(const int32_t *__restrict__ leaves, const int64_t *__restrict__ s0,
@@ -148,46 +214,48 @@ __global__ void __launch_bounds__(64)
           const double *__restrict__ sx, const double *__restrict__ sy,
           cx<T> *__restrict__ p, int64_t ns, cx<T> *__restrict__ M,
           int nbox, StrengthSrc ss) {
-  constexpr int TS = sizeof(T) == 8 ? 32 : 64;  // sources per LDS tile
-  __shared__ cx<T> buf[TS][P + 1];
+  constexpr int KB = kChunk<T, P>(), NV = pow2_ceil(2 * KB),
+                SH = 6 - log2_exact(NV);
   const int b = leaves[blockIdx.x];
   const int r = blockIdx.y;
   const int lane = threadIdx.x;
   const double c_x = cxv[b], c_y = cyv[b], ir = 1.0 / rad[b];
-  const cx<T> *pr = p + (int64_t)r * ns;
-  constexpr int G = 64 / P;
-  const int g = lane / P, l = lane % P;
-  cx<T> acc{T(0), T(0)};
+  cx<T> *pr = p + (int64_t)r * ns;
+  T *Mb = reinterpret_cast<T *>(M + ((int64_t)r * nbox + b) * P);
   double gsum = 0.0;
   const int64_t e0 = s0[b], e1 = s1[b];
-  for (int64_t jb = e0; jb < e1; jb += TS) {
-    const int64_t j = jb + lane;
-    const int n = (int)min<int64_t>(TS, e1 - jb);
-    if (lane < n) {
-      cx<T> w{T((sx[j] - c_x) * ir), T((sy[j] - c_y) * ir)};
+  const int vi = lane >> SH;
+  const bool writer = (lane & ((1 << SH) - 1)) == 0;
+#pragma unroll
+  for (int k0 = 0; k0 < P; k0 += KB) {
+    T acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = T(0);
+    for (int64_t j = e0 + lane; j < e1; j += 64) {
+      const cx<T> w{T((sx[j] - c_x) * ir), T((sy[j] - c_y) * ir)};
       cx<T> pw;
-      if (ss.sigma) {  // form the strength here: p_j = -i q_j sigma_j
+      if (k0 == 0 && ss.sigma) {  // form the strength: p_j = -i q_j sigma_j
         const double sg = ss.sigma[(int64_t)r * ss.ldx + ss.perm[j]];
         const double qx = ss.qfac_t[2 * j], qy = ss.qfac_t[2 * j + 1];
         pw = cx<T>{T(qy * sg), T(-qx * sg)};
-        p[(int64_t)r * ns + j] = pw;
+        pr[j] = pw;
         if (ss.gpart) gsum += ss.gw_t[j] * sg;
       } else {
         pw = pr[j];
       }
+      if (k0 > 0) pw = pw * cpow(w, k0);
 #pragma unroll
-      for (int k = 0; k < P; ++k) {
-        buf[lane][k] = pw;
-        pw = pw * w;
+      for (int k = 0; k < KB; ++k) {
+        if (k0 + k < P) {
+          acc[2 * k] += pw.x;
+          acc[2 * k + 1] += pw.y;
+          pw = pw * w;
+        }
       }
     }
-    __syncthreads();
-    if (g < G)
-      for (int q = g; q < n; q += G) acc = acc + buf[q][l];
-    __syncthreads();
+    const T tot = halving_sum<T, NV>(acc, lane);
+    if (writer && vi < 2 * KB && 2 * k0 + vi < 2 * P) Mb[2 * k0 + vi] = T(ir) * tot;
   }
-  acc = group_sum<T, P>(acc, lane);
-  if (lane < P) M[((int64_t)r * nbox + b) * P + lane] = T(ir) * acc;
   if (ss.gpart) {  // block-uniform
     for (int o = 32; o > 0; o >>= 1) gsum += __shfl_xor(gsum, o, 64);
     if (lane == 0) ss.gpart[(int64_t)r * gridDim.x + blockIdx.x] = gsum;
@@ -501,14 +569,26 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-// M2L for FP32 expansions of 16 terms on the matrix cores.  One wave per
-// target box.  For 8 V-list sources at a time the wave forms
+// M2L for FP32 expansions of 16 terms on the matrix cores, followed by the
+// box's P2L sum (p2l_sum).  One wave per target box.  For 8 V-list sources
+// at a time the wave forms
 // Y[k][2v + part] = part(tau_v^-(k+1) a_{v,k+1}) (16 x 16), multiplies
 // Z = H Y with four v_mfma_f32_16x16x4f32 (H: 16 x 16, real), then scales
 // column pair (2v, 2v+1) of Z by tau_v^-l and accumulates.  Lane layout of
 // the 16x16x4 instruction: A[i][k] in lane i + 16 k, B[k][j] in lane
 // j + 16 k, D[i][j] in lane j + 16 (i / 4), register i % 4.
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// The X-list sources of the boxes for the P2L sums folded into the FP32
+// M2L (per-box ranges xf_ptr into the concatenated source indices xf_idx;
+// box centres (bx, by) and half-widths rad).
+struct XListSrc {
+  const int64_t *xf_ptr;
+  const int32_t *xf_idx;
+  const double *bx, *by, *rad, *sx, *sy;
+  const cx<float> *p;
+  int64_t ns;
+};
 
 __global__ void __launch_bounds__(256)
     k_m2l_mfma16(int nb, const int32_t *__restrict__ boxes,
@@ -517,7 +597,7 @@ __global__ void __launch_bounds__(256)
                  const uint8_t *__restrict__ v_code,
                  const float *__restrict__ H, const cx<float> *__restrict__ itp,
                  const cx<float> *__restrict__ M, cx<float> *__restrict__ L,
-                 int nbox) {
+                 int nbox, XListSrc xs) {
   constexpr int P = 16, NP = 2 * P + 1;
   // the 49 x (2P + 1) table of tau^-n, read by every pair, in LDS
   __shared__ cx<float> sItp[49 * NP];
@@ -599,6 +679,21 @@ __global__ void __launch_bounds__(256)
         acci[j] += __shfl_xor(acci[j], off, 64);
       }
     }
+    // P2L over the box's X list: the real part of coefficient l ends in
+    // lane 4 l, the imaginary part in lane 4 l + 2
+    const int64_t x0 = xs.xf_ptr[b];
+    const int xt = (int)(xs.xf_ptr[b + 1] - x0);
+    if (xt > 0) {  // wave-uniform
+      const float v = p2l_sum<float, P, 0, P>(x0, xt, xs.xf_idx, xs.bx[b],
+                                              xs.by[b], float(xs.rad[b]),
+                                              xs.sx, xs.sy,
+                                              xs.p + (int64_t)r * xs.ns, lane);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        accr[j] += __shfl(v, (lane & 48) + 4 * j, 64);
+        acci[j] += __shfl(v, (lane & 48) + 4 * j + 2, 64);
+      }
+    }
     if (col == 0) {
       cx<float> *dst = L + ((int64_t)r * nbox + b) * P + 4 * kq;
 #pragma unroll
@@ -607,60 +702,44 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// P2L over the X list of one box per 64-lane block: the sources of all its
-// X leaves are gathered; lane q forms t_q (r/u_q)^l, t_q = -p_q / u_q
-// (u_q = z_q - c) in LDS, lane groups sum column l as in P2M; added to the
-// M2L result.
+// P2L over the X list of one box per wave (p2l_sum, KB coefficients per
+// pass), added to the M2L result.
+template <typename T, int P, int K0>
+__device__ __forceinline__ void p2l_pass(int64_t xf0, int total,
+                                         const int32_t *__restrict__ xf_idx,
+                                         double cxb, double cyb, T rb,
+                                         const double *__restrict__ sx,
+                                         const double *__restrict__ sy,
+                                         const cx<T> *__restrict__ pr,
+                                         T *__restrict__ Lb, int lane) {
+  if constexpr (K0 < P) {
+    constexpr int KB = kChunk<T, P>(), NV = pow2_ceil(2 * KB),
+                  SH = 6 - log2_exact(NV);
+    const T tot = p2l_sum<T, P, K0, KB>(xf0, total, xf_idx, cxb, cyb, rb, sx,
+                                        sy, pr, lane);
+    const int vi = lane >> SH;
+    if ((lane & ((1 << SH) - 1)) == 0 && vi < 2 * KB && 2 * K0 + vi < 2 * P)
+      Lb[2 * K0 + vi] += tot;
+    p2l_pass<T, P, K0 + KB>(xf0, total, xf_idx, cxb, cyb, rb, sx, sy, pr, Lb,
+                            lane);
+  }
+}
+
 template <typename T, int P>
 __global__ void __launch_bounds__(64)
     k_p2l(const int32_t *__restrict__ boxes, const int64_t *__restrict__ xf_ptr,
           const int32_t *__restrict__ xf_idx, const double *__restrict__ cxv,
           const double *__restrict__ cyv, const double *__restrict__ rad,
-          const int64_t *__restrict__ s0, const int64_t *__restrict__ s1,
           const double *__restrict__ sx, const double *__restrict__ sy,
           const cx<T> *__restrict__ p, int64_t ns, cx<T> *__restrict__ L,
           int nbox) {
-  constexpr int TS = sizeof(T) == 8 ? 32 : 64;  // sources per LDS tile
-  __shared__ cx<T> buf[TS][P + 1];
   const int b = boxes[blockIdx.x];
   const int r = blockIdx.y;
-  const int lane = threadIdx.x;
-  const double cxb = cxv[b], cyb = cyv[b];
-  const T rb = T(rad[b]);
-  const cx<T> *pr = p + (int64_t)r * ns;
-  constexpr int G = 64 / P;
-  const int g = lane / P, l = lane % P;
-  cx<T> acc{T(0), T(0)};
-  // the sources of the box's X list, concatenated at set-up
   const int64_t xf0 = xf_ptr[b];
-  const int total = (int)(xf_ptr[b + 1] - xf0);
-  {
-    for (int q0 = 0; q0 < total; q0 += TS) {
-      const int q = q0 + lane;
-      if (lane < TS && q < total) {
-        const int64_t j = xf_idx[xf0 + q];
-        const cx<T> iu = cinv(cx<T>{T(sx[j] - cxb), T(sy[j] - cyb)});
-        const cx<T> rho = rb * iu;
-        cx<T> t = pr[j] * iu;
-        t = cx<T>{-t.x, -t.y};
-#pragma unroll
-        for (int l = 0; l < P; ++l) {
-          buf[lane][l] = t;
-          t = t * rho;
-        }
-      }
-      __syncthreads();
-      const int n = min(TS, total - q0);
-      if (g < G)
-        for (int qq = g; qq < n; qq += G) acc = acc + buf[qq][l];
-      __syncthreads();
-    }
-  }
-  acc = group_sum<T, P>(acc, lane);
-  if (lane < P) {
-    cx<T> *dst = L + ((int64_t)r * nbox + b) * P + lane;
-    *dst = *dst + acc;
-  }
+  p2l_pass<T, P, 0>(xf0, (int)(xf_ptr[b + 1] - xf0), xf_idx, cxv[b], cyv[b],
+                    T(rad[b]), sx, sy, p + (int64_t)r * ns,
+                    reinterpret_cast<T *>(L + ((int64_t)r * nbox + b) * P),
+                    (int)threadIdx.x);
 }
 
 __device__ __forceinline__ double rcp64(double d) {
@@ -1077,25 +1156,30 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
                          pl.nbox);
     }
   }
+  // the FP32 MFMA M2L also forms the P2L sums of its boxes: every box with
+  // an X list whose local expansion is used (level >= 2, with targets) is
+  // one of its boxes
+  constexpr bool p2l_in_m2l = sizeof(T) == 4 && P == 16;
   if (pl.n_m2l > 0) {
     TimerScope ts(tm, ST_M2L, s);
-    if constexpr (sizeof(T) == 4 && P == 16) {
+    if constexpr (p2l_in_m2l) {
+      const XListSrc xs{pl.xf_ptr.p, pl.xf_idx.p, pl.cx.p, pl.cy.p, pl.rad.p,
+                        pl.sx.p, pl.sy.p, (const cx<float> *)p, pl.ns};
       hipLaunchKernelGGL(k_m2l_mfma16, dim3(std::min((pl.n_m2l + 3) / 4, 2048), nrhs),
                          dim3(256), 0, s, pl.n_m2l, pl.m2l_box.p, pl.v_ptr.p,
                          pl.v_src.p, pl.v_code.p, H, itp, (const cx<T> *)M, L,
-                         pl.nbox);
+                         pl.nbox, xs);
     } else {
       hipLaunchKernelGGL((k_m2l<T, P>), dim3(pl.n_m2l, nrhs), dim3(64), 0, s,
                          pl.m2l_box.p, pl.v_ptr.p, pl.v_src.p, pl.v_code.p, H,
                          itp, (const cx<T> *)M, L, pl.nbox);
     }
   }
-  if (pl.n_x > 0) {
+  if (pl.n_x > 0 && !p2l_in_m2l) {
     TimerScope ts(tm, ST_P2L, s);
     hipLaunchKernelGGL((k_p2l<T, P>), dim3(pl.n_x, nrhs), dim3(64), 0, s,
                        pl.x_box.p, pl.xf_ptr.p, pl.xf_idx.p, pl.cx.p, pl.cy.p,
-                       pl.rad.p, pl.s0.p, pl.s1.p, pl.sx.p, pl.sy.p, p, pl.ns,
-                       L, pl.nbox);
+                       pl.rad.p, pl.sx.p, pl.sy.p, p, pl.ns, L, pl.nbox);
   }
   TimerScope ts(tm, ST_L2L, s);
   for (size_t g = 0; g + 1 < pl.dn_gptr.size(); ++g) {
