@@ -76,6 +76,31 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
   pl.n_leaf_s = (int)leaf_s.size();
   pl.n_leaf_t = (int)leaf_t.size();
   pl.n_m2l = (int)m2l.size();
+  {
+    // leaf kernels: one wave per target leaf, launched heaviest octave of
+    // near-field work first (box order kept within an octave), so that the
+    // waves still running at the end of a launch are short ones.  Work: the
+    // leaf's U-list sources times its target lanes (32-target sub-chunks
+    // rounded up to powers of two, as the kernels lay them out).
+    std::vector<int> oct(nb, 0);
+    for (int b : leaf_t) {
+      int64_t us = 0;
+      for (int e = T.u_ptr[b]; e < T.u_ptr[b + 1]; ++e) us += T.s1[T.u_src[e]] - T.s0[T.u_src[e]];
+      int64_t lanes = 0;
+      for (int64_t c0 = 0, nt = T.t1[b] - T.t0[b]; c0 < nt; c0 += 32) {
+        int64_t tp = 1;
+        while (tp < std::min<int64_t>(32, nt - c0)) tp <<= 1;
+        lanes += tp;
+      }
+      int64_t w = std::max<int64_t>(1, us * lanes);
+      while (w > 1) {
+        w >>= 1;
+        ++oct[b];
+      }
+    }
+    std::stable_sort(leaf_t.begin(), leaf_t.end(),
+                     [&](int a, int b) { return oct[a] > oct[b]; });
+  }
   pl.leaf_t_host = leaf_t;
   pl.leaf_s_host = leaf_s;
   // subtree heaps of the fused upward / downward passes (see DevPlan)
