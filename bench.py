@@ -87,9 +87,22 @@ def stage_work(tree, n_nodes, P, fp64):
 
 
 def stage_roofline(tree, n_nodes, P, stages_ms, fp64):
+    """Achieved rate per timed stage.  A stage the library folds into
+    another launch has no time of its own: the FP32 M2L kernel also forms
+    the P2L sums and the correction sums, so its work then counts the P2L
+    FLOPs as well (the correction's 16 B per node are left out of a FLOP
+    figure) and the entry lists what it includes."""
     peak_flops = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
+    work = stage_work(tree, n_nodes, P, fp64)
+    folded = {}
+    if "m2l" in stages_ms:
+        for name in ("p2l", "gamma"):
+            if name not in stages_ms:
+                folded[name] = work[name]
+    if "p2l" in folded:
+        work["m2l"] = (work["m2l"][0], work["m2l"][1] + folded["p2l"][1])
     out = {}
-    for name, (bound, work) in stage_work(tree, n_nodes, P, fp64).items():
+    for name, (bound, work) in work.items():
         ms = stages_ms.get(name)
         if not ms:
             continue
@@ -103,6 +116,8 @@ def stage_roofline(tree, n_nodes, P, stages_ms, fp64):
             out[name] = {"bound": bound, "achieved": ach, "peak": peak_flops,
                          "unit": "TFLOP/s", "frac": ach / peak_flops,
                          "avg_ms": ms, "flop_per_launch": work}
+    if folded and "m2l" in out:
+        out["m2l"]["includes"] = sorted(folded)
     return out
 
 

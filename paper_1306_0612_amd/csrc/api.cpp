@@ -101,6 +101,27 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
     std::stable_sort(leaf_t.begin(), leaf_t.end(),
                      [&](int a, int b) { return oct[a] > oct[b]; });
   }
+  {
+    // M2L boxes: the FP32 kernel's waves take every W-th box (W = 4 x its
+    // work-groups); with the boxes sorted by estimated work (V-list batches
+    // of 8, X-list passes of 64 sources) and every other stride of W
+    // reversed, each wave's share comes out even.
+    const int64_t n = (int64_t)m2l.size();
+    std::vector<int32_t> mw = m2l;  // the FP64 kernel keeps box order
+    std::vector<int64_t> w(nb, 0);
+    for (int b : mw) {
+      int64_t nx = 0;
+      for (int e = T.x_ptr[b]; e < T.x_ptr[b + 1]; ++e) nx += T.s1[T.x_src[e]] - T.s0[T.x_src[e]];
+      const int64_t nv = T.v_ptr[b + 1] - T.v_ptr[b];
+      w[b] = 4 + 2 * ((nv + 7) / 8) + (nx > 0 ? 4 + 3 * ((nx + 63) / 64) : 0);
+    }
+    std::stable_sort(mw.begin(), mw.end(), [&](int a, int b) { return w[a] > w[b]; });
+    const int64_t W = 4 * std::min<int64_t>((n + 3) / 4, kM2LGroups);
+    for (int64_t a = W; a < n; a += 2 * W)
+      std::reverse(mw.begin() + a, mw.begin() + std::min(n, a + W));
+    pl.m2l_wave.upload(mw, s);
+    LBS_HIP(hipStreamSynchronize(s));  // mw is released on return
+  }
   pl.leaf_t_host = leaf_t;
   pl.leaf_s_host = leaf_s;
   // subtree heaps of the fused upward / downward passes (see DevPlan)

@@ -269,15 +269,16 @@ __global__ void __launch_bounds__(64)
 // order and resets the counter for the next application, so the result
 // does not depend on the order in which blocks run.
 constexpr int kGammaChunk = 2048;
-__global__ void __launch_bounds__(256)
-    k_gamma_reduce(const int32_t *__restrict__ gl_ptr,
-                   const double *__restrict__ gpart, int nls, int G,
-                   double *__restrict__ csum, int32_t *__restrict__ cnt,
-                   double *__restrict__ gamma) {
+__device__ __forceinline__ void gamma_chunk(int c, int g, int r, int nch,
+                                            const int32_t *__restrict__ gl_ptr,
+                                            const double *__restrict__ gpart,
+                                            int nls, int G,
+                                            double *__restrict__ csum,
+                                            int32_t *__restrict__ cnt,
+                                            double *__restrict__ gamma) {
   __shared__ double red[4];
   __shared__ bool last;
-  const int c = blockIdx.x, g = blockIdx.y, r = blockIdx.z, tid = threadIdx.x;
-  const int nch = gridDim.x, slot = r * G + g;
+  const int tid = threadIdx.x, slot = r * G + g;
   const int a = gl_ptr[g] + c * kGammaChunk, b = min(gl_ptr[g + 1], a + kGammaChunk);
   double v = 0.0;
   for (int e = a + tid; e < b; e += 256) v += gpart[(int64_t)r * nls + e];
@@ -300,6 +301,27 @@ __global__ void __launch_bounds__(256)
     cnt[slot] = 0;
   }
 }
+
+__global__ void __launch_bounds__(256)
+    k_gamma_reduce(const int32_t *__restrict__ gl_ptr,
+                   const double *__restrict__ gpart, int nls, int G,
+                   double *__restrict__ csum, int32_t *__restrict__ cnt,
+                   double *__restrict__ gamma) {
+  gamma_chunk(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gl_ptr, gpart,
+              nls, G, csum, cnt, gamma);
+}
+
+// The correction sums of GammaFused for a kernel that takes them as extra
+// work-groups: group x >= first (x - first = g nchunk + c) reduces chunk c
+// of geometry g for right-hand side blockIdx.y.
+struct GammaGroups {
+  const int32_t *gl_ptr = nullptr;
+  const double *gpart = nullptr;
+  double *csum = nullptr;
+  int32_t *cnt = nullptr;
+  double *gamma = nullptr;
+  int nls = 0, G = 0, nchunk = 0, first = 0;
+};
 
 // Upward pass over three levels per launch: one work-group per root, whose
 // subtree is the heap described with DevPlan.  All operands are first
@@ -597,8 +619,14 @@ __global__ void __launch_bounds__(256)
                  const uint8_t *__restrict__ v_code,
                  const float *__restrict__ H, const cx<float> *__restrict__ itp,
                  const cx<float> *__restrict__ M, cx<float> *__restrict__ L,
-                 int nbox, XListSrc xs) {
+                 int nbox, XListSrc xs, GammaGroups gg) {
   constexpr int P = 16, NP = 2 * P + 1;
+  if ((int)blockIdx.x >= gg.first) {  // block-uniform: a correction chunk
+    const int x = blockIdx.x - gg.first;
+    gamma_chunk(x % gg.nchunk, x / gg.nchunk, blockIdx.y, gg.nchunk, gg.gl_ptr,
+                gg.gpart, gg.nls, gg.G, gg.csum, gg.cnt, gg.gamma);
+    return;
+  }
   // the 49 x (2P + 1) table of tau^-n, read by every pair, in LDS
   __shared__ cx<float> sItp[49 * NP];
   for (int i = threadIdx.x; i < 49 * NP; i += 256) sItp[i] = itp[i];
@@ -610,10 +638,10 @@ __global__ void __launch_bounds__(256)
   float a[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) a[s] = H[col * P + 4 * s + kq];
-  // each wave takes every (4 gridDim.x)-th box, so that the table above is
-  // read once per block for several boxes
+  // each wave takes every (4 x #M2L groups)-th box, so that the table
+  // above is read once per block for several boxes
   for (int wv = blockIdx.x * 4 + (threadIdx.x >> 6); wv < nb;
-       wv += 4 * gridDim.x) {
+       wv += 4 * gg.first) {
     const int b = boxes[wv];
     const int vb = v_ptr[b], nv = v_ptr[b + 1] - vb;
     const cx<float> *Mr = M + (int64_t)r * nbox * P;
@@ -1120,10 +1148,14 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
 }
 
 // ---------------------------------------------------------------- drivers
+// Returns whether the correction sums of gf were formed too (by the FP32
+// MFMA M2L launch).
 template <typename T, int P>
-static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
+static bool far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
                       cx<T> *p, cx<T> *M, cx<T> *L, int nrhs,
-                      hipStream_t s, StrengthSrc ss = StrengthSrc{}) {
+                      hipStream_t s, StrengthSrc ss = StrengthSrc{},
+                      const GammaFused *gf = nullptr) {
+  bool gamma_done = false;
   StageTimer *tm = ws.timer;
   const cx<T> *itp, *pre, *post;
   const T *H, *bc;
@@ -1165,10 +1197,19 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
     if constexpr (p2l_in_m2l) {
       const XListSrc xs{pl.xf_ptr.p, pl.xf_idx.p, pl.cx.p, pl.cy.p, pl.rad.p,
                         pl.sx.p, pl.sy.p, (const cx<float> *)p, pl.ns};
-      hipLaunchKernelGGL(k_m2l_mfma16, dim3(std::min((pl.n_m2l + 3) / 4, 2048), nrhs),
-                         dim3(256), 0, s, pl.n_m2l, pl.m2l_box.p, pl.v_ptr.p,
-                         pl.v_src.p, pl.v_code.p, H, itp, (const cx<T> *)M, L,
-                         pl.nbox, xs);
+      GammaGroups gg;
+      gg.first = std::min((pl.n_m2l + 3) / 4, kM2LGroups);
+      int groups = gg.first;
+      if (gf && pl.n_leaf_s > 0) {  // the correction sums ride along
+        gg = GammaGroups{gf->gl_ptr, ws.gpart.p, ws.gcsum.p, ws.gcnt.p, gf->gamma,
+                         pl.n_leaf_s, gf->G, gf->nchunk, gg.first};
+        groups += gf->nchunk * gf->G;
+        gamma_done = true;
+      }
+      hipLaunchKernelGGL(k_m2l_mfma16, dim3(groups, nrhs), dim3(256), 0, s,
+                         pl.n_m2l, pl.m2l_wave.p, pl.v_ptr.p, pl.v_src.p,
+                         pl.v_code.p, H, itp, (const cx<T> *)M, L, pl.nbox, xs,
+                         gg);
     } else {
       hipLaunchKernelGGL((k_m2l<T, P>), dim3(pl.n_m2l, nrhs), dim3(64), 0, s,
                          pl.m2l_box.p, pl.v_ptr.p, pl.v_src.p, pl.v_code.p, H,
@@ -1189,6 +1230,7 @@ static void far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
                        pl.dn_box.p + (int64_t)a0 * 85, bc, pre, post, L,
                        pl.nbox);
   }
+  return gamma_done;
 }
 
 template <int P>
@@ -1226,8 +1268,8 @@ static void run32(const DevPlan &pl, const Tables &tb, Workspace &ws,
   auto *p = (cx<float> *)ws.pstr32.p;
   auto *M = (cx<float> *)ws.mult32.p;
   auto *L = (cx<float> *)ws.loc32.p;
-  far_field<float, P>(pl, tb, ws, p, M, L, nrhs, s, ss);
-  if (gf && pl.n_leaf_s > 0) {
+  const bool gamma_done = far_field<float, P>(pl, tb, ws, p, M, L, nrhs, s, ss, gf);
+  if (gf && pl.n_leaf_s > 0 && !gamma_done) {
     TimerScope ts(ws.timer, ST_GAMMA, s);
     hipLaunchKernelGGL(k_gamma_reduce, dim3(gf->nchunk, gf->G, nrhs), dim3(256), 0,
                        s, gf->gl_ptr, ws.gpart.p, pl.n_leaf_s, gf->G, ws.gcsum.p,

@@ -98,6 +98,7 @@ struct DevPlan {
   DBuf<int32_t> uf_idx;
   DBuf<uint8_t> v_code;
   DBuf<int32_t> leaf_t, leaf_s, m2l_box;     // work lists
+  DBuf<int32_t> m2l_wave;  // M2L boxes in the FP32 kernel's wave order
   int n_x = 0;
   DBuf<int32_t> x_box;                       // boxes with an X list
   // Upward (M2M) and downward (L2L) passes, three levels per launch: one
@@ -270,6 +271,9 @@ struct Workspace {
 
 constexpr int kPlog = 30;  // terms of the per-island log-source expansions
 constexpr int kLogChunk = 64;  // far-list entries per wave step
+// work-groups (4 waves each) of the FP32 M2L kernel at most; its waves
+// stride over the M2L boxes
+constexpr int kM2LGroups = 2048;
 
 // ----- launchers (HIP files) ------------------------------------------
 void build_tables(Tables &t, int P, hipStream_t s);
