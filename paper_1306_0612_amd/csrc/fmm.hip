@@ -168,7 +168,14 @@ __device__ __forceinline__ T p2l_sum(int64_t x0, int total,
   for (int k = 0; k < NV; ++k) acc[k] = T(0);
   for (int q = lane; q < total; q += 64) {
     const int64_t j = xf_idx[x0 + q];
-    const cx<T> iu = cinv(cx<T>{T(sx[j] - cxb), T(sy[j] - cyb)});
+    const cx<T> u{T(sx[j] - cxb), T(sy[j] - cyb)};
+    cx<T> iu;
+    if constexpr (sizeof(T) == 4) {  // FP32 expansions: hardware reciprocal
+      const float d = __builtin_amdgcn_rcpf(u.x * u.x + u.y * u.y);
+      iu = cx<T>{u.x * d, -u.y * d};
+    } else {
+      iu = cinv(u);
+    }
     const cx<T> rho = rb * iu;
     cx<T> t = pr[j] * iu;
     t = cx<T>{-t.x, -t.y};
@@ -639,18 +646,34 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int s = 0; s < 4; ++s) a[s] = H[col * P + 4 * s + kq];
   // each wave takes every (4 x #M2L groups)-th box, so that the table
-  // above is read once per block for several boxes
-  for (int wv = blockIdx.x * 4 + (threadIdx.x >> 6); wv < nb;
-       wv += 4 * gg.first) {
-    const int b = boxes[wv];
-    const int vb = v_ptr[b], nv = v_ptr[b + 1] - vb;
+  // above is read once per block for several boxes; the next box's id and
+  // list offsets are loaded while this box is worked on (box ids two
+  // ahead, offsets one ahead; past the end, box 0 stands in)
+  const int stride = 4 * gg.first;
+  int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
+  int b = wv < nb ? boxes[wv] : 0;
+  int bn = wv + stride < nb ? boxes[wv + stride] : 0;
+  int vb = v_ptr[b], ve = v_ptr[b + 1];
+  int64_t xb0 = xs.xf_ptr[b], xb1 = xs.xf_ptr[b + 1];
+  for (; wv < nb; wv += stride) {
+    const int nv = ve - vb;
+    const int64_t x0 = xb0;
+    const int xt = (int)(xb1 - xb0);
+    const int bc = b;
+    b = bn;
+    bn = wv + 2 * stride < nb ? boxes[wv + 2 * stride] : 0;
+    const int vbc = vb;
+    vb = v_ptr[b];
+    ve = v_ptr[b + 1];
+    xb0 = xs.xf_ptr[b];
+    xb1 = xs.xf_ptr[b + 1];
     const cx<float> *Mr = M + (int64_t)r * nbox * P;
     // the box's list entries, lane e holding entry e (a V list has at most
     // 27 entries; any beyond 64 are read directly)
     int esrc = 0, ecode = 0;
     if (lane < nv) {
-      esrc = v_src[vb + lane];
-      ecode = v_code[vb + lane];
+      esrc = v_src[vbc + lane];
+      ecode = v_code[vbc + lane];
     }
     // multipole coefficients k = 4 s + kq of the batch's source vslot
     auto fetch = [&](int base, cx<float> (&mv)[4], int &code, bool &ok) {
@@ -659,8 +682,8 @@ __global__ void __launch_bounds__(256)
       int src = __shfl(esrc, v & 63, 64);
       code = __shfl(ecode, v & 63, 64);
       if (ok && v >= 64) {
-        src = v_src[vb + v];
-        code = v_code[vb + v];
+        src = v_src[vbc + v];
+        code = v_code[vbc + v];
       }
       if (!ok) src = code = 0;
       const cx<float> *ms = Mr + (int64_t)src * P;
@@ -709,11 +732,9 @@ __global__ void __launch_bounds__(256)
     }
     // P2L over the box's X list: the real part of coefficient l ends in
     // lane 4 l, the imaginary part in lane 4 l + 2
-    const int64_t x0 = xs.xf_ptr[b];
-    const int xt = (int)(xs.xf_ptr[b + 1] - x0);
     if (xt > 0) {  // wave-uniform
-      const float v = p2l_sum<float, P, 0, P>(x0, xt, xs.xf_idx, xs.bx[b],
-                                              xs.by[b], float(xs.rad[b]),
+      const float v = p2l_sum<float, P, 0, P>(x0, xt, xs.xf_idx, xs.bx[bc],
+                                              xs.by[bc], float(xs.rad[bc]),
                                               xs.sx, xs.sy,
                                               xs.p + (int64_t)r * xs.ns, lane);
 #pragma unroll
@@ -723,7 +744,7 @@ __global__ void __launch_bounds__(256)
       }
     }
     if (col == 0) {
-      cx<float> *dst = L + ((int64_t)r * nbox + b) * P + 4 * kq;
+      cx<float> *dst = L + ((int64_t)r * nbox + bc) * P + 4 * kq;
 #pragma unroll
       for (int j = 0; j < 4; ++j) dst[j] = cx<float>{accr[j], acci[j]};
     }
