@@ -235,6 +235,19 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
   pl.w_src.upload(T.w_src, s);
   pl.leaf_t.upload(leaf_t, s);
   pl.leaf_s.upload(leaf_s, s);
+  {
+    std::vector<int64_t> rng(2 * leaf_s.size());
+    std::vector<double4> geo(leaf_s.size());
+    for (size_t i = 0; i < leaf_s.size(); ++i) {
+      const int b = leaf_s[i];
+      rng[2 * i] = T.s0[b];
+      rng[2 * i + 1] = T.s1[b];
+      geo[i] = make_double4(T.cx[b], T.cy[b], 1.0 / T.rad[b], 0.0);
+    }
+    pl.ls_rng.upload(rng, s);
+    pl.ls_geo.upload(geo, s);
+    LBS_HIP(hipStreamSynchronize(s));  // rng, geo are released on return
+  }
   pl.m2l_box.upload(m2l, s);
   auto points = [&](const std::vector<int64_t> &perm, const double *ax,
                     const double *ay, DBuf<double> &dx, DBuf<double> &dy) {

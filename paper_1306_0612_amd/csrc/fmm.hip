@@ -19,6 +19,7 @@
 //   P2L  b_l = -sum_j (p_j/u_j) (r/u_j)^l, u_j = z_j - c
 //   M2P  Psi(z) = sum_k a_k (r_w/(z - c_w))^k
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "cplx.h"
@@ -215,22 +216,24 @@ struct StrengthSrc {
 // strengths (when asked to); later passes read them back.
 template <typename T, int P>
 __global__ void __launch_bounds__(64)
-    k_p2m(const int32_t *__restrict__ leaves, const int64_t *__restrict__ s0,
-          const int64_t *__restrict__ s1, const double *__restrict__ cxv,
-          const double *__restrict__ cyv, const double *__restrict__ rad,
+    k_p2m(const int32_t *__restrict__ leaves,
+          const int64_t *__restrict__ ls_rng,
+          const double4 *__restrict__ ls_geo,
           const double *__restrict__ sx, const double *__restrict__ sy,
           cx<T> *__restrict__ p, int64_t ns, cx<T> *__restrict__ M,
           int nbox, StrengthSrc ss) {
   constexpr int KB = kChunk<T, P>(), NV = pow2_ceil(2 * KB),
                 SH = 6 - log2_exact(NV);
+  // the leaf's source range and frame by work-group (one load level less
+  // than through its box id, which only the final store needs)
   const int b = leaves[blockIdx.x];
   const int r = blockIdx.y;
   const int lane = threadIdx.x;
-  const double c_x = cxv[b], c_y = cyv[b], ir = 1.0 / rad[b];
+  const double4 geo = ls_geo[blockIdx.x];
+  const double c_x = geo.x, c_y = geo.y, ir = geo.z;
   cx<T> *pr = p + (int64_t)r * ns;
-  T *Mb = reinterpret_cast<T *>(M + ((int64_t)r * nbox + b) * P);
   double gsum = 0.0;
-  const int64_t e0 = s0[b], e1 = s1[b];
+  const int64_t e0 = ls_rng[2 * blockIdx.x], e1 = ls_rng[2 * blockIdx.x + 1];
   const int vi = lane >> SH;
   const bool writer = (lane & ((1 << SH) - 1)) == 0;
 #pragma unroll
@@ -261,6 +264,7 @@ __global__ void __launch_bounds__(64)
       }
     }
     const T tot = halving_sum<T, NV>(acc, lane);
+    T *Mb = reinterpret_cast<T *>(M + ((int64_t)r * nbox + b) * P);
     if (writer && vi < 2 * KB && 2 * k0 + vi < 2 * P) Mb[2 * k0 + vi] = T(ir) * tot;
   }
   if (ss.gpart) {  // block-uniform
@@ -500,33 +504,39 @@ __global__ void __launch_bounds__(256)
     return sPre[q * P + m] * sum;
   };
   // children (slots 1..4) and grandchildren (5..20); a parent's versions
-  // sit at its index among its own level's slots
-  int first = 1, count = 4;
-  for (int d = 1; d <= 2; ++d) {
-    cx<T> res[(16 * P + NT - 1) / NT];
-    int nres = 0;
-    for (int it = tid; it < count * P; it += NT, ++nres) {
+  // sit at its index among its own level's slots.  FIRST and COUNT are
+  // compile-time constants so that res stays in registers.
+  auto level = [&](auto first_c, auto count_c) {
+    constexpr int first = decltype(first_c)::value, count = decltype(count_c)::value;
+    constexpr int NR = (count * P + NT - 1) / NT;
+    cx<T> res[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int it = tid + i * NT;
+      res[i] = cx<T>{T(0), T(0)};
+      if (it >= count * P) continue;
       const int s = first + it / P, m = it % P, b = bx[s];
-      res[nres] = cx<T>{T(0), T(0)};
       if (b < 0) continue;
       const int ps = (s - 1) >> 2, q = (s - 1) & 3;
       // parents of this level start at slot (first - 1) / 4 (0, 1)
       const cx<T> val = sl[(s - 1) * P + m] + l2l(ps - (first - 1) / 4, q, m);
       Lr[(int64_t)b * P + m] = val;
-      res[nres] = val;
+      res[i] = val;
     }
     __syncthreads();  // every read of sp for this level is done
-    nres = 0;
-    for (int it = tid; it < count * P; it += NT, ++nres) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int it = tid + i * NT;
+      if (it >= count * P) continue;
       const int s = first + it / P, m = it % P;
       if (bx[s] < 0) continue;
       const int si = s - first;  // index of s among this level's slots
-      for (int q = 0; q < 4; ++q) sp[(si * 4 + q) * P + m] = sPost[q * P + m] * res[nres];
+      for (int q = 0; q < 4; ++q) sp[(si * 4 + q) * P + m] = sPost[q * P + m] * res[i];
     }
     __syncthreads();
-    first += count;
-    count *= 4;
-  }
+  };
+  level(std::integral_constant<int, 1>{}, std::integral_constant<int, 4>{});
+  level(std::integral_constant<int, 5>{}, std::integral_constant<int, 16>{});
   // great-grandchildren (21..84): parents are the grandchildren (from 5)
 #pragma unroll
   for (int i = 0; i < I3; ++i) {
@@ -1197,9 +1207,8 @@ static bool far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
     TimerScope ts(tm, ST_UPWARD, s);
     if (pl.n_leaf_s > 0)
       hipLaunchKernelGGL((k_p2m<T, P>), dim3(pl.n_leaf_s, nrhs), dim3(64), 0,
-                         s, pl.leaf_s.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p,
-                         pl.rad.p, pl.sx.p, pl.sy.p, p, pl.ns, M, pl.nbox,
-                         ss);
+                         s, pl.leaf_s.p, pl.ls_rng.p, pl.ls_geo.p, pl.sx.p,
+                         pl.sy.p, p, pl.ns, M, pl.nbox, ss);
     for (size_t g = 0; g + 1 < pl.up_gptr.size(); ++g) {
       const int a0 = pl.up_gptr[g], n = pl.up_gptr[g + 1] - a0;
       if (n <= 0) continue;

@@ -98,6 +98,9 @@ struct DevPlan {
   DBuf<int32_t> uf_idx;
   DBuf<uint8_t> v_code;
   DBuf<int32_t> leaf_t, leaf_s, m2l_box;     // work lists
+  // per entry of leaf_s: its source range (s0, s1) and (cx, cy, 1/rad, 0)
+  DBuf<int64_t> ls_rng;
+  DBuf<double4> ls_geo;
   DBuf<int32_t> m2l_wave;  // M2L boxes in the FP32 kernel's wave order
   int n_x = 0;
   DBuf<int32_t> x_box;                       // boxes with an X list
