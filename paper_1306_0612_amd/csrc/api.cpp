@@ -209,7 +209,7 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
   pl.v_code.upload(T.v_code, s);
   // U and X lists as per-box concatenations of their boxes' source points
   auto flat_sources = [&](const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
-                          DBuf<int64_t> &dptr, DBuf<int32_t> &didx) {
+                          DBuf<int64_t> &dptr, DBuf<int32_t> &didx) -> std::vector<int64_t> {
     std::vector<int64_t> fp((size_t)nb + 1, 0);
     for (int b = 0; b < nb; ++b) {
       int64_t c = 0;
@@ -227,9 +227,31 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
     }, 1024);
     dptr.upload(fp, s);
     didx.upload(fi, s);
-    LBS_HIP(hipStreamSynchronize(s));  // fp, fi are released on return
+    LBS_HIP(hipStreamSynchronize(s));  // fi is released on return
+    return fp;
   };
-  flat_sources(T.u_ptr, T.u_src, pl.uf_ptr, pl.uf_idx);
+  {
+    const std::vector<int64_t> ufp = flat_sources(T.u_ptr, T.u_src, pl.uf_ptr, pl.uf_idx);
+    std::vector<LeafHdr> hd(leaf_t.size());
+    for (size_t i = 0; i < leaf_t.size(); ++i) {
+      const int b = leaf_t[i];
+      LeafHdr &h = hd[i];
+      h.t0 = T.t0[b];
+      h.nt = T.t1[b] - T.t0[b];
+      h.uf0 = ufp[b];
+      h.uf1 = ufp[b + 1];
+      h.wb = T.w_ptr[b];
+      h.we = T.w_ptr[b + 1];
+      h.b = b;
+      h.lev = T.level[b];
+      h.cx = T.cx[b];
+      h.cy = T.cy[b];
+      h.ir = 1.0 / T.rad[b];
+      h.pad = 0.0;
+    }
+    pl.lt_hdr.upload(hd, s);
+    LBS_HIP(hipStreamSynchronize(s));  // hd is released on return
+  }
   flat_sources(T.x_ptr, T.x_src, pl.xf_ptr, pl.xf_idx);
   pl.w_ptr.upload(T.w_ptr, s);
   pl.w_src.upload(T.w_src, s);

@@ -826,17 +826,12 @@ constexpr int kStage = 128;  // U-list sources staged in LDS per pass
 // d == 0), then the operator row assembly in API order.  FP64 version.
 template <int P>
 __global__ void __launch_bounds__(64, 8)
-    k_leaf64(const int32_t *__restrict__ leaves,
-             const int32_t *__restrict__ lev,
-             const int64_t *__restrict__ t0, const int64_t *__restrict__ t1,
-             const int64_t *__restrict__ s0, const int64_t *__restrict__ s1,
+    k_leaf64(const LeafHdr *__restrict__ hdr,
              const double *__restrict__ cxv, const double *__restrict__ cyv,
              const double *__restrict__ rad,
              const double *__restrict__ tx, const double *__restrict__ ty,
              const int64_t *__restrict__ tperm,
-             const int64_t *__restrict__ uf_ptr,
              const int32_t *__restrict__ uf_idx,
-             const int32_t *__restrict__ w_ptr,
              const int32_t *__restrict__ w_src,
              const double *__restrict__ sx, const double *__restrict__ sy,
              const cx<double> *__restrict__ p, int64_t ns,
@@ -847,18 +842,19 @@ __global__ void __launch_bounds__(64, 8)
   __shared__ double2 sz[kStage];
   __shared__ double2 sp[kStage];
   constexpr int NC = 2;  // sub-chunks of <= 32 targets per pass over U
-  const int b = leaves[blockIdx.x];
+  const LeafHdr &hd = hdr[blockIdx.x];
+  const int b = hd.b;
   const int r = blockIdx.y;
   const int lane = threadIdx.x;
   const cx<double> *pr = p + (int64_t)r * ns;
   const cx<double> *Mr = M + (int64_t)r * nbox * P;
   const cx<double> *Lr = L + (int64_t)r * nbox * P;
-  const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
-  const int64_t uf0 = uf_ptr[b];
-  const int utot = (int)(uf_ptr[b + 1] - uf0);  // U-list sources of the leaf
-  const int wb = w_ptr[b], we = w_ptr[b + 1];
-  const bool has_local = lev[b] >= 2;
-  const double ir_b = 1.0 / rad[b];
+  const int64_t tb0 = hd.t0, ntb = hd.nt;
+  const int64_t uf0 = hd.uf0;
+  const int utot = (int)(hd.uf1 - uf0);  // U-list sources of the leaf
+  const int wb = hd.wb, we = hd.we;
+  const bool has_local = hd.lev >= 2;
+  const double ir_b = hd.ir, cx_b = hd.cx, cy_b = hd.cy;
   for (int64_t tc0 = 0; tc0 < ntb; tc0 += 32 * NC) {
     const int nt = (int)min<int64_t>(32 * NC, ntb - tc0);
     const int nch = (nt + 31) / 32;
@@ -892,7 +888,7 @@ __global__ void __launch_bounds__(64, 8)
       zys[c] = zy;
       double field = 0.0;
       if (sl[c] == 0 && has_local) {
-        const cx<double> w{(zx - cxv[b]) * ir_b, (zy - cyv[b]) * ir_b};
+        const cx<double> w{(zx - cx_b) * ir_b, (zy - cy_b) * ir_b};
         const cx<double> *La = Lr + (int64_t)b * P;
         cx<double> acc = La[P - 1];
         for (int l = P - 2; l >= 0; --l) acc = cfma(acc, w, La[l]);
@@ -1021,17 +1017,12 @@ __device__ __forceinline__ void near_sums32(const Src32<RB> *__restrict__ zq,
 // right-hand side of the block.
 template <int P, int RB>
 __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
-    k_leaf32(const int32_t *__restrict__ leaves,
-             const int32_t *__restrict__ lev,
-             const int64_t *__restrict__ t0, const int64_t *__restrict__ t1,
-             const int64_t *__restrict__ s0, const int64_t *__restrict__ s1,
+    k_leaf32(const LeafHdr *__restrict__ hdr,
              const double *__restrict__ cxv, const double *__restrict__ cyv,
              const double *__restrict__ rad,
              const double *__restrict__ tx, const double *__restrict__ ty,
              const int64_t *__restrict__ tperm,
-             const int64_t *__restrict__ uf_ptr,
              const int32_t *__restrict__ uf_idx,
-             const int32_t *__restrict__ w_ptr,
              const int32_t *__restrict__ w_src,
              const double *__restrict__ sx, const double *__restrict__ sy,
              const cx<float> *__restrict__ p, int64_t ns,
@@ -1040,15 +1031,16 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
              double scale, Assembly as) {
   __shared__ Src32<RB> sz[kStage];
   constexpr int NC = 2;  // sub-chunks of <= 32 targets per pass over U
-  const int b = leaves[blockIdx.x];
+  const LeafHdr &hd = hdr[blockIdx.x];
+  const int b = hd.b;
   const int r0 = blockIdx.y * RB, nr = min(RB, nrhs - r0);
   const int lane = threadIdx.x;
-  const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
-  const int64_t uf0 = uf_ptr[b];
-  const int utot = (int)(uf_ptr[b + 1] - uf0);  // U-list sources of the leaf
-  const int wb = w_ptr[b], we = w_ptr[b + 1];
-  const bool has_local = lev[b] >= 2;
-  const double ir_b = 1.0 / rad[b];
+  const int64_t tb0 = hd.t0, ntb = hd.nt;
+  const int64_t uf0 = hd.uf0;
+  const int utot = (int)(hd.uf1 - uf0);  // U-list sources of the leaf
+  const int wb = hd.wb, we = hd.we;
+  const bool has_local = hd.lev >= 2;
+  const double ir_b = hd.ir, cx_b = hd.cx, cy_b = hd.cy;
   for (int64_t tc0 = 0; tc0 < ntb; tc0 += 32 * NC) {
     const int nt = (int)min<int64_t>(32 * NC, ntb - tc0);
     const int nch = (nt + 31) / 32;
@@ -1143,7 +1135,7 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
         if (act[c]) {
           const double zx = zxd[c], zy = zyd[c];
           if (sl[c] == 0 && has_local) {
-            const cx<float> w{float((zx - cxv[b]) * ir_b), float((zy - cyv[b]) * ir_b)};
+            const cx<float> w{float((zx - cx_b) * ir_b), float((zy - cy_b) * ir_b)};
             const cx<float> *La = L + ((int64_t)r * nbox + b) * P;
             cx<float> acc = La[P - 1];
             for (int l = P - 2; l >= 0; --l) acc = cfma(acc, w, La[l]);
@@ -1281,10 +1273,9 @@ static void run64(const DevPlan &pl, const Tables &tb, Workspace &ws,
   if (pl.n_leaf_t > 0) {
     TimerScope ts(ws.timer, ST_LEAF, s);
     hipLaunchKernelGGL((k_leaf64<P>), dim3(pl.n_leaf_t, nrhs), dim3(64), 0, s,
-                       pl.leaf_t.p, pl.lev.p, pl.t0.p,
-                       pl.t1.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p,
-                       pl.tx.p, pl.ty.p, pl.tgt_perm.p, pl.uf_ptr.p,
-                       pl.uf_idx.p, pl.w_ptr.p, pl.w_src.p, pl.sx.p, pl.sy.p,
+                       pl.lt_hdr.p, pl.cx.p, pl.cy.p, pl.rad.p,
+                       pl.tx.p, pl.ty.p, pl.tgt_perm.p, pl.uf_idx.p,
+                       pl.w_src.p, pl.sx.p, pl.sy.p,
                        (const cx<double> *)p, pl.ns, (const cx<double> *)M,
                        (const cx<double> *)L, pl.nbox, out, ldy, scale, as);
   }
@@ -1309,10 +1300,10 @@ static void run32(const DevPlan &pl, const Tables &tb, Workspace &ws,
     TimerScope ts(ws.timer, ST_LEAF, s);
     auto launch = [&](auto kern, int rb) {
       hipLaunchKernelGGL(kern, dim3(pl.n_leaf_t, (nrhs + rb - 1) / rb), dim3(64),
-                         0, s, pl.leaf_t.p, pl.lev.p, pl.t0.p, pl.t1.p, pl.s0.p,
-                         pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p, pl.tx.p, pl.ty.p,
+                         0, s, pl.lt_hdr.p, pl.cx.p, pl.cy.p, pl.rad.p, pl.tx.p,
+                         pl.ty.p,
                          pl.tgt_perm.p,
-                         pl.uf_ptr.p, pl.uf_idx.p, pl.w_ptr.p, pl.w_src.p,
+                         pl.uf_idx.p, pl.w_src.p,
                          pl.sx.p, pl.sy.p,
                          (const cx<float> *)p, pl.ns, (const cx<float> *)M,
                          (const cx<float> *)L, pl.nbox, nrhs, out, ldy, scale,

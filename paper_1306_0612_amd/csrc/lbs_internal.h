@@ -76,6 +76,15 @@ struct DBuf {
 };
 
 // Quadtree and lists on the device (one FMM plan).
+// A target leaf as the leaf kernels see it (one per work-group): its
+// target range, the range of its flattened U-list sources, its W-list
+// range, box id, level, centre and 1 / half-width.
+struct LeafHdr {
+  int64_t t0, nt, uf0, uf1;
+  int32_t wb, we, b, lev;
+  double cx, cy, ir, pad;
+};
+
 struct DevPlan {
   int nbox = 0, nlevels = 0;
   int64_t ns = 0, nt = 0;
@@ -98,6 +107,8 @@ struct DevPlan {
   DBuf<int32_t> uf_idx;
   DBuf<uint8_t> v_code;
   DBuf<int32_t> leaf_t, leaf_s, m2l_box;     // work lists
+  // per entry of leaf_t: what the leaf kernels read about the leaf
+  DBuf<LeafHdr> lt_hdr;
   // per entry of leaf_s: its source range (s0, s1) and (cx, cy, 1/rad, 0)
   DBuf<int64_t> ls_rng;
   DBuf<double4> ls_geo;
