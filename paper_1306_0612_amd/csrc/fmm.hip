@@ -402,8 +402,13 @@ __global__ void __launch_bounds__(256)
       if (!((present >> q) & 1)) continue;
       const cx<T> *a = src + q * P;
       cx<T> sum{T(0), T(0)};
+      if constexpr (sizeof(T) == 4) {  // partly unrolled: fewer live registers
+#pragma unroll 8
+        for (int k = 0; k < P; ++k) sum = sum + c[k] * a[k];
+      } else {
 #pragma unroll
-      for (int k = 0; k < P; ++k) sum = sum + c[k] * a[k];
+        for (int k = 0; k < P; ++k) sum = sum + c[k] * a[k];
+      }
       acc = acc + sPost[q * P + lo] * sum;
     }
     return T(0.5) * acc;
