@@ -286,8 +286,9 @@ struct Workspace {
 constexpr int kPlog = 30;  // terms of the per-island log-source expansions
 constexpr int kLogChunk = 64;  // far-list entries per wave step
 // work-groups (4 waves each) of the FP32 M2L kernel at most; its waves
-// stride over the M2L boxes
-constexpr int kM2LGroups = 2048;
+// stride over the M2L boxes.  4096 waves are one resident round on 256
+// CUs at the kernel's occupancy of 4 waves per SIMD.
+constexpr int kM2LGroups = 1024;
 
 // ----- launchers (HIP files) ------------------------------------------
 void build_tables(Tables &t, int P, hipStream_t s);
