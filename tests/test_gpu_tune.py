@@ -72,3 +72,20 @@ def test_autotune_meets_tolerances(env, geom):
     for lm in (24, 128):
         errs = [e["err"] for e in entries if e["leaf_max"] == lm and e["p64"]]
         assert errs[-1] < errs[0]
+
+
+@pytest.mark.parametrize("p64,p32", [(20, 12), (24, 16), (30, 20), (40, 24), (48, 24)])
+def test_every_order_against_oracle(env, geom, p64, p32):
+    """Each supported expansion order, through the P2M / P2L register
+    passes it takes (FP64 orders above 16 and FP32 orders above 16 use
+    several passes or wider sums), against the oracle's direct sum: a wrong
+    pass would give O(1) errors; the orders the library defaults to and
+    above meet the production tolerances."""
+    torch, lbs = env
+    isl, cv, x, ref = geom
+    sol = lbs.Solver(isl, leaf_max=16, p64=p64, p32=p32)
+    xd = _t(torch, x)
+    e64 = _rel(sol.matvec(xd, "iplusk", "fp64").cpu().numpy(), ref)
+    e32 = _rel(sol.matvec(xd, "iplusk", "mixed").cpu().numpy(), ref)
+    assert e64 < (1e-10 if p64 >= 30 else 1e-5), e64
+    assert e32 < (1e-6 if p32 >= 16 else 1e-4), e32
