@@ -112,11 +112,26 @@ void build_tables(Tables &t, int P, hipStream_t s) {
 // partner's copy of the half it keeps; once a single value is left the
 // remaining steps add it whole.  Lane i returns the total of value
 // i >> (6 - log2 NV); NV - 1 + 6 - log2 NV shuffles in all.
-template <typename T, int NV, int S = 0>
+// One halving step at lane offset 32 or 16 for the pair (a, b): the
+// permlane swaps exchange the upper 32 lanes of a with the lower 32 of b
+// (the odd 16-lane rows of a with the even rows of b), after which a + b is,
+// in every lane, its own plus its partner's copy of the value it keeps.
+template <int O>
+__device__ __forceinline__ float swap_add(float a, float b) {
+  static_assert(O == 32 || O == 16, "lane offsets with a swap instruction");
+  const auto r = O == 32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false)
+                         : __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+template <typename T, int NV, bool SWAP, int S = 0>
 __device__ __forceinline__ void halving_steps(T (&v)[NV], int lane) {
   if constexpr (S < 6) {
     constexpr int o = 32 >> S, h = NV >> (S + 1);
-    if constexpr (h >= 1) {
+    if constexpr (SWAP && h >= 1 && sizeof(T) == 4 && o >= 16) {
+#pragma unroll
+      for (int k = 0; k < h; ++k) v[k] = swap_add<o>(v[k], v[k + h]);
+    } else if constexpr (h >= 1) {
       const bool up = (lane & o) != 0;
 #pragma unroll
       for (int k = 0; k < h; ++k) {
@@ -127,15 +142,17 @@ __device__ __forceinline__ void halving_steps(T (&v)[NV], int lane) {
     } else {
       v[0] += __shfl_xor(v[0], o, 64);
     }
-    halving_steps<T, NV, S + 1>(v, lane);
+    halving_steps<T, NV, SWAP, S + 1>(v, lane);
   }
 }
 
-template <typename T, int NV>
+// SWAP: the steps at lane offsets 32 and 16 of FP32 values by permlane
+// swaps (swap_add) instead of selects and a cross-lane read.
+template <typename T, int NV, bool SWAP = true>
 __device__ __forceinline__ T halving_sum(T (&v)[NV], int lane) {
   static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0,
                 "a power of two up to the wave size");
-  halving_steps<T, NV>(v, lane);
+  halving_steps<T, NV, SWAP>(v, lane);
   return v[0];
 }
 
@@ -263,7 +280,7 @@ __global__ void __launch_bounds__(64)
         }
       }
     }
-    const T tot = halving_sum<T, NV>(acc, lane);
+    const T tot = halving_sum<T, NV, false>(acc, lane);
     T *Mb = reinterpret_cast<T *>(M + ((int64_t)r * nbox + b) * P);
     if (writer && vi < 2 * KB && 2 * k0 + vi < 2 * P) Mb[2 * k0 + vi] = T(ir) * tot;
   }
