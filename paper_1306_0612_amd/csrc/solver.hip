@@ -172,41 +172,44 @@ __global__ void __launch_bounds__(64)
 
 // (E z)_i: the island's expansion at u = xi'_i / rho'_k (all P terms; the
 // coefficients beyond those its far list needs are zero), plus its near
-// centres directly
-__global__ void k_logsrc_node(int64_t N, int M, const int32_t *__restrict__ island,
-                              const double *__restrict__ xil,
-                              const double *__restrict__ xyz,
-                              const double *__restrict__ elll,
-                              const double *__restrict__ rhol,
-                              const double *__restrict__ cxyz,
-                              const int32_t *__restrict__ near_ptr,
-                              const int32_t *__restrict__ near_idx,
-                              const double *__restrict__ z, int64_t ldz,
-                              const double *__restrict__ Lc,
-                              double *__restrict__ out, int64_t ldo,
-                              double alpha) {
+// centres directly.  One work-group per (island, right-hand side): the
+// island's coefficients and near centres are the same for every lane, so
+// they are read with scalar loads.
+__global__ void __launch_bounds__(256)
+    k_logsrc_node(int M, const int64_t *__restrict__ offs,
+                  const double *__restrict__ xil,
+                  const double *__restrict__ xyz,
+                  const double *__restrict__ elll,
+                  const double *__restrict__ rhol,
+                  const double *__restrict__ cxyz,
+                  const int32_t *__restrict__ near_ptr,
+                  const int32_t *__restrict__ near_idx,
+                  const double *__restrict__ z, int64_t ldz,
+                  const double *__restrict__ Lc,
+                  double *__restrict__ out, int64_t ldo, double alpha) {
   constexpr int P = kPlog, stride = log_stride<P>();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (i >= N) return;
-  const int k = island[i];
+  const int k = blockIdx.x, r = blockIdx.y;
   const double *L = Lc + ((int64_t)r * M + k) * stride;
   const double ir = 1.0 / rhol[k];
-  const cx<double> u{xil[2 * i] * ir, xil[2 * i + 1] * ir};
-  cx<double> s{L[2 * P], L[2 * P + 1]};
-#pragma unroll
-  for (int l = P - 1; l >= 0; --l) s = cfma(s, u, cx<double>{L[2 * l], L[2 * l + 1]});
-  double tot = s.x - 0.5 * L[2 * (P + 1)] * elll[i];
-  const double x0 = xyz[3 * i], x1 = xyz[3 * i + 1], x2 = xyz[3 * i + 2];
   const double *zr = z + (int64_t)r * ldz;
-  for (int e = near_ptr[k]; e < near_ptr[k + 1]; ++e) {
-    const int m = near_idx[e];
-    const double d0 = x0 - cxyz[3 * m], d1 = x1 - cxyz[3 * m + 1],
-                 d2 = x2 - cxyz[3 * m + 2];
-    tot += zr[m] * 0.5 * log(d0 * d0 + d1 * d1 + d2 * d2);
+  const int e0 = near_ptr[k], e1 = near_ptr[k + 1];
+  const int64_t i1 = offs[k + 1];
+  for (int64_t i = offs[k] + threadIdx.x; i < i1; i += 256) {
+    const cx<double> u{xil[2 * i] * ir, xil[2 * i + 1] * ir};
+    cx<double> s{L[2 * P], L[2 * P + 1]};
+#pragma unroll
+    for (int l = P - 1; l >= 0; --l) s = cfma(s, u, cx<double>{L[2 * l], L[2 * l + 1]});
+    double tot = s.x - 0.5 * L[2 * (P + 1)] * elll[i];
+    const double x0 = xyz[3 * i], x1 = xyz[3 * i + 1], x2 = xyz[3 * i + 2];
+    for (int e = e0; e < e1; ++e) {
+      const int m = near_idx[e];
+      const double d0 = x0 - cxyz[3 * m], d1 = x1 - cxyz[3 * m + 1],
+                   d2 = x2 - cxyz[3 * m + 2];
+      tot += zr[m] * 0.5 * log(d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    const double ez = -kInvPi * tot + kLog2 * 0.5 * kInvPi * L[2 * (P + 1) + 1];
+    out[(int64_t)r * ldo + i] += alpha * ez;
   }
-  const double ez = -kInvPi * tot + kLog2 * 0.5 * kInvPi * L[2 * (P + 1) + 1];
-  out[(int64_t)r * ldo + i] += alpha * ez;
 }
 
 // The same expansion about the planar centre eta_k of the common projection
@@ -297,10 +300,10 @@ void launch_logsrc_apply(const Geometry &g, Workspace &ws, const double *z,
                      g.isl_geo.p, g.dgisl.p, g.far_ptr.p, g.far_cptr.p,
                      g.far_nt.p, g.far_idx.p, g.far_q.p, g.far_h.p, z, ldz,
                      ws.logL.p);
-  hipLaunchKernelGGL(k_logsrc_node, dim3((unsigned)((g.N + 255) / 256), nrhs),
-                     dim3(256), 0, s, g.N, g.M, g.island.p, g.xil.p, g.xyz.p,
-                     g.elll.p, g.rhol.p, g.dcenter.p, g.nearR_ptr.p,
-                     g.nearR_idx.p, z, ldz, ws.logL.p, out, ldo, alpha);
+  hipLaunchKernelGGL(k_logsrc_node, dim3(g.M, nrhs), dim3(256), 0, s, g.M,
+                     g.doffs.p, g.xil.p, g.xyz.p, g.elll.p, g.rhol.p,
+                     g.dcenter.p, g.nearR_ptr.p, g.nearR_idx.p, z, ldz,
+                     ws.logL.p, out, ldo, alpha);
   LBS_HIP(hipGetLastError());
 }
 
