@@ -560,9 +560,18 @@ __global__ void __launch_bounds__(256)
   const int m0 = gisl[g], Mg = gisl[g + 1] - m0;
   const double *xr = x + (int64_t)r * ldx + m0;
   const double *a = A + gsinv[g] + (int64_t)(row - m0) * Mg;
-  double acc = 0.0;
-  for (int j = ln; j < Mg; j += 64) acc += a[j] * xr[j];
-  acc = wave_sum(acc);
+  // four independent partial sums, so that four coalesced row loads per
+  // lane are in flight at once (the kernel streams the whole matrix)
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  int j = ln;
+  for (; j + 192 < Mg; j += 256) {
+    acc0 += a[j] * xr[j];
+    acc1 += a[j + 64] * xr[j + 64];
+    acc2 += a[j + 128] * xr[j + 128];
+    acc3 += a[j + 192] * xr[j + 192];
+  }
+  for (; j < Mg; j += 64) acc0 += a[j] * xr[j];
+  const double acc = wave_sum((acc0 + acc1) + (acc2 + acc3));
   if (ln == 0) y[(int64_t)r * ldy + row] = alpha * acc;
 }
 
