@@ -99,8 +99,9 @@ __global__ void __launch_bounds__(64)
   for (int l = 0; l < PH; ++l) acc[l] = cx<double>{0.0, 0.0};
   double a0 = 0.0, zf = 0.0;
   const int nch = (int)((e1 - e0 + kLogChunk - 1) / kLogChunk);
-  // U chunks per step, their loads issued before any of them is used
-  constexpr int U = 8;
+  // U chunks per step, their loads issued before any of them is used (4:
+  // few enough registers for four waves per SIMD)
+  constexpr int U = 4;
   for (int c0 = 0; c0 < nch; c0 += U) {
     int nt[U];
     cx<double> q[U];
