@@ -25,20 +25,40 @@ inline uint64_t hkey(int l, int64_t ix, int64_t iy) {
   return ((uint64_t)l << 58) | ((uint64_t)ix << 29) | (uint64_t)iy;
 }
 
+// Allocator that leaves new elements uninitialised, so that the sort's
+// large arrays are first touched (page-faulted) by the parallel loops that
+// write them rather than zero-filled by one thread.
+template <typename T>
+struct NoInit : std::allocator<T> {
+  template <typename U>
+  struct rebind { using other = NoInit<U>; };
+  NoInit() = default;
+  template <typename U>
+  NoInit(const NoInit<U> &) {}
+  template <typename U>
+  void construct(U *p) { ::new ((void *)p) U; }
+  template <typename U, typename... A>
+  void construct(U *p, A &&...a) { ::new ((void *)p) U(std::forward<A>(a)...); }
+};
+template <typename T>
+using raw_vector = std::vector<T, NoInit<T>>;
+
 struct Keyed {
-  std::vector<uint64_t> key;
-  std::vector<int64_t> perm;
+  raw_vector<uint64_t> key;
+  raw_vector<int64_t> perm;
 };
 
 // Points sorted by their Morton key (ties keep input order): keys formed in
-// parallel, then a stable least-significant-digit radix sort of the
-// 2 kMaxLevel key bits, 11 bits per pass, with one histogram per chunk of
-// points so that each pass scatters in parallel.
+// parallel, then a stable least-significant-digit radix sort of the top 44
+// of the 2 kMaxLevel key bits (four passes of 11 bits, one histogram per
+// chunk of points so that each pass scatters in parallel), then each run of
+// points whose top bits agree (points closer than 2^-22 of the root box)
+// stably sorted by the full key: the same order as a full stable sort.
 void morton_sort(const double *x, const double *y, int64_t n, double lox,
                  double loy, double scale, Keyed &out) {
   const double cells = (double)(1ull << kMaxLevel);
-  std::vector<uint64_t> key((size_t)n), tk((size_t)n);
-  std::vector<int64_t> val((size_t)n), tv((size_t)n);
+  raw_vector<uint64_t> key((size_t)n), tk((size_t)n);
+  raw_vector<int64_t> val((size_t)n), tv((size_t)n);
   const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
   const int nc = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(hw, 16), n / 32768));
   std::vector<int64_t> cut(nc + 1);
@@ -54,9 +74,10 @@ void morton_sort(const double *x, const double *y, int64_t n, double lox,
       val[i] = i;
     }
   }, 1);
-  constexpr int D = 11, NB = 1 << D;
+  constexpr int D = 11, NB = 1 << D, LOW = 2 * kMaxLevel - 4 * D;
+  static_assert(LOW >= 0, "four digits cover the top key bits");
   std::vector<int64_t> off((size_t)nc * NB);
-  for (int sh = 0; sh < 2 * kMaxLevel; sh += D) {
+  for (int sh = LOW; sh < 2 * kMaxLevel; sh += D) {
     std::fill(off.begin(), off.end(), 0);
     parallel_for(nc, [&](int64_t c0, int64_t c1) {
       for (int64_t c = c0; c < c1; ++c) {
@@ -93,12 +114,32 @@ void morton_sort(const double *x, const double *y, int64_t n, double lox,
     key.swap(tk);
     val.swap(tv);
   }
+  if (LOW > 0) {
+    // runs of equal top bits, by the remaining low bits: insertion sort,
+    // which moves an entry only past strictly larger keys (stable)
+    for (int64_t a = 0; a < n;) {
+      int64_t b = a + 1;
+      while (b < n && (key[b] >> LOW) == (key[a] >> LOW)) ++b;
+      for (int64_t i = a + 1; i < b; ++i) {
+        const uint64_t kk = key[i];
+        const int64_t vv = val[i];
+        int64_t j = i;
+        for (; j > a && key[j - 1] > kk; --j) {
+          key[j] = key[j - 1];
+          val[j] = val[j - 1];
+        }
+        key[j] = kk;
+        val[j] = vv;
+      }
+      a = b;
+    }
+  }
   out.key.swap(key);
   out.perm.swap(val);
 }
 
 // Sub-range of [a, b) whose keys have quadrant q at level l + 1.
-inline void child_range(const std::vector<uint64_t> &key, int64_t a,
+inline void child_range(const raw_vector<uint64_t> &key, int64_t a,
                         int64_t b, int l, int q, int64_t &ca, int64_t &cb) {
   if (a >= b) { ca = cb = a; return; }
   int shift = 2 * (kMaxLevel - l - 1);
@@ -152,8 +193,8 @@ void build_tree(const double *sx, const double *sy, int64_t ns,
   morton_sort(sx, sy, ns, lox, loy, scale, ks);
   if (!self) morton_sort(tx, ty, nt, lox, loy, scale, kt);
   const Keyed &kt_ref = self ? ks : kt;
-  T.src_perm = ks.perm;
-  T.tgt_perm = kt_ref.perm;
+  T.src_perm.assign(ks.perm.begin(), ks.perm.end());
+  T.tgt_perm.assign(kt_ref.perm.begin(), kt_ref.perm.end());
 
   auto add_box = [&](int l, int64_t ix, int64_t iy, int par, int64_t s0,
                      int64_t s1, int64_t t0, int64_t t1) {
