@@ -346,15 +346,21 @@ void build_tree(const double *sx, const double *sy, int64_t ns,
   flatten(ul, T.u_ptr, T.u_src, has_tgt, has_src);
   flatten(wl, T.w_ptr, T.w_src, has_tgt, has_src);
   flatten(xl, T.x_ptr, T.x_src, has_tgt, has_src);
-  T.v_src.clear();
-  T.v_code.clear();
   parallel_for(nb, [&](int64_t b0, int64_t b1) {
     for (int64_t b = b0; b < b1; ++b) std::sort(vl[b].begin(), vl[b].end());
   }, 1024);
-  for (int b = 0; b < nb; ++b) {
-    for (auto &e : vl[b]) { T.v_src.push_back(e.first); T.v_code.push_back(e.second); }
-    T.v_ptr[b + 1] = (int32_t)T.v_src.size();
-  }
+  for (int b = 0; b < nb; ++b) T.v_ptr[b + 1] = T.v_ptr[b] + (int32_t)vl[b].size();
+  T.v_src.resize((size_t)T.v_ptr[nb]);
+  T.v_code.resize((size_t)T.v_ptr[nb]);
+  parallel_for(nb, [&](int64_t b0, int64_t b1) {
+    for (int64_t b = b0; b < b1; ++b) {
+      int32_t k = T.v_ptr[b];
+      for (auto &e : vl[b]) {
+        T.v_src[k] = e.first;
+        T.v_code[k++] = e.second;
+      }
+    }
+  }, 1024);
   T.p2p_pairs = T.m2p_evals = T.p2l_evals = 0;
   for (int b = 0; b < nb; ++b) {
     const int64_t ntb = T.t1[b] - T.t0[b];
