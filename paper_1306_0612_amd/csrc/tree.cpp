@@ -309,7 +309,23 @@ void build_tree(const double *sx, const double *sy, int64_t ns,
   }
   }, 256);
   // U = descent part + coarser adjacent leaves; X = transpose of W
+  // (each list sized first, so that the appends below allocate once)
   std::vector<std::vector<int32_t>> ul(nb), xl(nb);
+  {
+    std::vector<int32_t> nu(nb, 0), nx(nb, 0);
+    for (int b = 0; b < nb; ++b) {
+      nu[b] += (int32_t)ud[b].size();
+      for (int c : ud[b])
+        if (T.level[c] > T.level[b]) ++nu[c];
+      for (int d : wl[b]) ++nx[d];
+    }
+    parallel_for(nb, [&](int64_t b0, int64_t b1) {
+      for (int64_t b = b0; b < b1; ++b) {
+        ul[b].reserve(nu[b]);
+        xl[b].reserve(nx[b]);
+      }
+    }, 1024);
+  }
   for (int b = 0; b < nb; ++b)
     for (int c : ud[b]) {
       ul[b].push_back(c);
