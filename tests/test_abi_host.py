@@ -74,6 +74,21 @@ def test_quadtree_depth_grows_with_clustering(lbs):
     assert deep["levels"] > shallow["levels"] + 10
 
 
+def test_quadtree_with_near_coincident_clusters(lbs):
+    """Clusters of points closer than 2^-22 of the domain share the leading
+    Morton key bits that the radix passes sort by; the runs they form are
+    ordered by the remaining bits.  Coverage of every leaf pair stays exact
+    and the clusters force the deepest levels."""
+    rng = np.random.default_rng(4)
+    base = rng.random((300, 2))
+    clusters = [base[i] + 1e-8 * rng.random((12, 2)) for i in range(0, 300, 25)]
+    pts = np.concatenate([base] + clusters)
+    pts = pts[rng.permutation(len(pts))]
+    bad, st = lbs.check_tree_host(pts[:, 0], pts[:, 1], 8)
+    assert bad == 0, st
+    assert st["levels"] >= 20
+
+
 def _bad_islands(kind):
     isl = synth.star_islands(3, 4, (0.1, 0.2), nodes=32)
     if kind == "overlap":
