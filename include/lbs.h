@@ -75,7 +75,9 @@ enum { LBS_FP64 = 0, LBS_MIXED = 1 };            /* precision            */
 enum { LBS_OP_IPLUSK = 0,  /* y = (I + K) sigma            (x, y: N)      */
        LBS_OP_K = 1,       /* y = K sigma                  (x, y: N)      */
        LBS_OP_SYSTEM = 2,  /* [y_s; y_a] = A [sigma; A]    (x, y: N + M)  */
-       LBS_OP_PRECOND = 3  /* [y_s; y_a] = P^-1 A [sigma; A] (N + M)      */
+       LBS_OP_PRECOND = 3, /* [y_s; y_a] = P^-1 A [sigma; A] (N + M)      */
+       LBS_OP_IPLUSK_T = 4 /* y = (I + K)^T x, the transpose of the       */
+                           /* Nystrom matrix of eq. disc_sphere (x, y: N) */
 };
 enum { LBS_MATVEC_FMM = 0, LBS_MATVEC_DIRECT = 1 }; /* far-field method   */
 
@@ -94,15 +96,26 @@ typedef struct {
                      /* stream and replayed on the caller's stream; 0:     */
                      /* launched kernel by kernel.  Ignored while stage    */
                      /* timing is enabled.                                 */
+  int32_t precond;   /* 1 (default): GMRES on the left-preconditioned      */
+                     /* system P^-1 A of eq. matrix_eqns_c (block          */
+                     /* preconditioner P = [[I, E], [F, D]] through its    */
+                     /* Schur complement); 0: GMRES on A itself (eq.       */
+                     /* matrix_eqns), whose condition number grows with N  */
+                     /* (Section 6, Example 1, Table 1).  lbs_solve only.  */
 } lbs_options;
 
 typedef struct {
   int32_t iters;          /* total GMRES iterations (all restarts, inner)  */
   int32_t outer_steps;    /* refinement steps (mixed precision), else 0    */
-  double rel_resid;       /* final |P^-1 (b - A x)| / |P^-1 b|, FP64       */
+  double rel_resid;       /* final relative residual of the system GMRES   */
+                          /* ran on, FP64 operator, worst system:          */
+                          /* |P^-1 (b - A x)| / |P^-1 b| (precond = 1) or  */
+                          /* |b - A x| / |b| (precond = 0)                 */
   double ms_solve;        /* wall time of the call                         */
   int32_t fp64_matvecs;   /* FMM applications in FP64                      */
   int32_t fp32_matvecs;   /* FMM applications with the FP32 far field      */
+  double true_rel_resid;  /* |b - A x| / |b| of eq. matrix_eqns, b =       */
+                          /* [2 g; 0], FP64 operator, worst system         */
 } lbs_solve_info;
 
 /* Fill *opt with the defaults listed above. */
@@ -166,7 +179,9 @@ lbs_status lbs_matvec(lbs_handle h, int32_t op, int32_t precision,
 
 /* Solve the system for Dirichlet data g (device, N x nrhs, API order):
  * GMRES(restart) on P^-1 A [sigma; A] = P^-1 [2g; 0] from x0 = 0 until the
- * preconditioned relative residual is <= tol (Section 5, Section 6).
+ * preconditioned relative residual is <= tol (Section 5, Section 6); with
+ * opt.precond = 0, GMRES on A [sigma; A] = [2g; 0] until its relative
+ * residual is <= tol.
  * precision LBS_FP64: every matvec in FP64.  LBS_MIXED: iterative
  * refinement, outer residual with the FP64 operator, inner GMRES with the
  * FP32 far field to opt.inner_tol.  Writes sigma (N x nrhs) and the
@@ -293,6 +308,18 @@ enum { LBS_STAGE_STRENGTHS = 0, /* p_j = -i q_j sigma_j, tree order       */
 lbs_status lbs_stage_timing(lbs_handle h, int32_t enable);
 lbs_status lbs_stage_times(lbs_handle h, double *ms_host,
                            int64_t *launches_host, int32_t n);
+
+/* Host-only step of the mixed-precision refinement of lbs_solve and
+ * lbs_solve_T (no GPU needed): from the squared FP64 residual norms rn2 and
+ * right-hand-side norms bn2 of S systems, the inner GMRES tolerance of each
+ * system (itol: rn for a system with rn <= tol bn, which the inner solve
+ * then skips; else max(inner_tol rn, tol bn / 2)) and *all_converged = 1
+ * when every system meets tol.  LBS_ERR_NOT_FINITE when a norm is NaN, Inf
+ * or negative: such a system is never taken as converged. */
+lbs_status lbs_refine_tolerances_host(int32_t S, const double *rn2_host,
+                                      const double *bn2_host, double tol,
+                                      double inner_tol, double *itol_host,
+                                      int32_t *all_converged_host);
 
 /* Release a handle and its device memory.  NULL is accepted. */
 lbs_status lbs_destroy(lbs_handle h);

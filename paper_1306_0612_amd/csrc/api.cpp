@@ -653,15 +653,19 @@ GmresOut gmres(lbs_ctx &c, const OpFn &op, int graph_id, int R, const double *b,
   }
 }
 
-// GMRES on P^-1 A with the FMM of the given precision.
-GmresOut gmres(lbs_ctx &c, int prec, int R, const double *b, double *x,
-               bool x_zero, int max_iter, hipStream_t s) {
-  return gmres(
-      c,
-      [&](const double *in, double *out, hipStream_t q) {
-        apply_precond_op(c, prec, R, in, out, q);
-      },
-      prec, R, b, x, x_zero, max_iter, s, prec == LBS_MIXED ? 1 : 2);
+// Operators of the forward solve: P^-1 A (left-preconditioned, eq.
+// matrix_eqns_c) or A itself (eq. matrix_eqns), with the FMM of the given
+// precision.  Graph ids: 0/1 preconditioned FP64/mixed, 2/3 transposed,
+// 4/5 unpreconditioned.
+OpFn forward_op(lbs_ctx &c, int prec, int R, bool precond) {
+  lbs_ctx *pc = &c;
+  if (precond)
+    return [pc, prec, R](const double *in, double *out, hipStream_t q) {
+      apply_precond_op(*pc, prec, R, in, out, q);
+    };
+  return [pc, prec, R](const double *in, double *out, hipStream_t q) {
+    apply_system(*pc, prec, R, in, out, q);
+  };
 }
 
 // Per-system 2-norms^2 of R columns of length N + M into out (S values).
@@ -679,6 +683,91 @@ std::vector<double> download(const double *p, size_t n, hipStream_t s) {
 
 void check_handle(lbs_handle h) {
   if (!h) fail(LBS_ERR_INVALID_ARG, "null handle");
+}
+
+// b = [2 g; 0] for nrhs columns (g: ld N; b: ld N + M), the right-hand side
+// of eq. matrix_eqns.
+void system_rhs(lbs_ctx &c, int nrhs, const double *gdat, double *b, hipStream_t s) {
+  Geometry &g = c.geo;
+  const int64_t n = g.N + g.M;
+  launch_copy_cols(g.N, nrhs, 2.0, gdat, g.N, b, n, s);
+  for (int r = 0; r < nrhs; ++r) launch_fill(g.M, 0.0, b + (int64_t)r * n + g.N, s);
+}
+
+// x <- P^-1 x in place for nrhs columns of length N + M, with the block
+// preconditioner P = [[I, E], [F, D]] of eq. matrix_eqns_c:
+// z_a = S^-1 (x_a - F x_s), z_s = x_s - E z_a.
+void apply_precond_inverse(lbs_ctx &c, int nrhs, double *x, hipStream_t s) {
+  Geometry &g = c.geo;
+  const int64_t n = g.N + g.M;
+  ensure_ws(c, nrhs);
+  double *tmp = c.ws.tmpM.p;
+  launch_island_sums(g, x, n, nrhs, tmp, g.M, s);
+  for (int r = 0; r < nrhs; ++r)
+    launch_axpby(g.M, 1.0, x + (int64_t)r * n + g.N, -1.0, tmp + (int64_t)r * g.M, s);
+  launch_gemv_blocks(g, tmp, g.M, nrhs, x + g.N, n, 1.0, s);
+  launch_logsrc_apply(g, c.ws, x + g.N, n, nrhs, x, n, -1.0, s);
+}
+
+// Per-system relative residuals sqrt(rn2 / bn2) (0 where bn2 = 0) and their
+// maximum; a NaN or Inf norm is an error, never a converged system.
+double worst_relative(const std::vector<double> &rn2, const std::vector<double> &bn2,
+                      const char *what) {
+  double worst = 0;
+  for (size_t q = 0; q < rn2.size(); ++q) {
+    if (!std::isfinite(rn2[q]) || !std::isfinite(bn2[q]))
+      fail(LBS_ERR_NOT_FINITE, std::string(what) + " is not finite (system " +
+                                   std::to_string(q) + ")");
+    if (bn2[q] > 0) worst = std::max(worst, std::sqrt(rn2[q] / bn2[q]));
+  }
+  return worst;
+}
+
+// Solve op(x) = b for the R * G systems (b in gm.bvec, x into gm.xvec) to
+// the relative residual tol per system.  FP64: GMRES on op64 (two
+// Gram-Schmidt passes).  Mixed: iterative refinement, the residual
+// b - op64(x) in FP64 and the correction from GMRES on op32 (one pass) to
+// the tolerances lbs_refine_tolerances_host describes.  Returns whether every
+// system converged; throws LBS_ERR_NOT_FINITE on a non-finite residual.
+bool solve_core(lbs_ctx &c, int prec, int R, const OpFn &op64, int gid64, const OpFn &op32,
+                int gid32, double tol, lbs_solve_info &inf, hipStream_t s) {
+  GmresState &gm = c.gm;
+  const int S = R * c.geo.G;
+  const int64_t n = c.geo.N + c.geo.M;
+  sys_norm2(c, R, gm.bvec.p, gm.bn2.p, s);
+  if (prec == LBS_FP64) {
+    launch_scale_sqrt(S, tol, gm.bn2.p, gm.tol.p, s);
+    GmresOut go = gmres(c, op64, gid64, R, gm.bvec.p, gm.xvec.p, true, c.opt.max_iter, s, 2);
+    inf.iters = go.iters;
+    inf.fp64_matvecs = go.iters;
+    return go.conv;
+  }
+  launch_fill((int64_t)R * n, 0.0, gm.xvec.p, s);
+  LBS_HIP(hipMemcpyAsync(gm.rvec.p, gm.bvec.p, (size_t)R * n * sizeof(double),
+                         hipMemcpyDeviceToDevice, s));
+  const std::vector<double> bn2 = download(gm.bn2.p, S, s);
+  std::vector<double> rn2 = bn2, itol(S);
+  int left = c.opt.max_iter;
+  for (int outer = 0;; ++outer) {
+    int32_t all = 0;
+    const lbs_status st = lbs_refine_tolerances_host(S, rn2.data(), bn2.data(), tol,
+                                                     c.opt.inner_tol, itol.data(), &all);
+    if (st != LBS_OK) fail(st, "refinement residual is not finite");
+    if (all) return true;
+    if (outer >= c.opt.max_outer || left <= 0) return false;
+    LBS_HIP(hipMemcpyAsync(gm.tol.p, itol.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
+    GmresOut go = gmres(c, op32, gid32, R, gm.rvec.p, gm.dvec.p, true, left, s, 1);
+    inf.iters += go.iters;
+    inf.fp32_matvecs += go.iters;
+    left -= go.iters;
+    launch_axpby((int64_t)R * n, 1.0, gm.dvec.p, 1.0, gm.xvec.p, s);
+    op64(gm.xvec.p, gm.rvec.p, s);
+    inf.fp64_matvecs += 1;
+    launch_axpby((int64_t)R * n, 1.0, gm.bvec.p, -1.0, gm.rvec.p, s);
+    sys_norm2(c, R, gm.rvec.p, gm.nrm2.p, s);
+    rn2 = download(gm.nrm2.p, S, s);
+    inf.outer_steps = outer + 1;
+  }
 }
 
 // Terms P of the far-field log series that keep its tail
@@ -828,6 +917,7 @@ void validate_options(const lbs_options &o) {
   if (!(o.inner_tol > 0 && o.inner_tol < 1)) fail(LBS_ERR_INVALID_ARG, "inner_tol outside (0, 1)");
   if (o.matvec != LBS_MATVEC_FMM && o.matvec != LBS_MATVEC_DIRECT) fail(LBS_ERR_INVALID_ARG, "bad matvec mode");
   if (o.graphs != 0 && o.graphs != 1) fail(LBS_ERR_INVALID_ARG, "graphs must be 0 or 1");
+  if (o.precond != 0 && o.precond != 1) fail(LBS_ERR_INVALID_ARG, "precond must be 0 or 1");
 }
 
 // Set-up of G geometries (islands and node counts concatenated
@@ -1302,6 +1392,33 @@ void lbs_default_options(lbs_options *o) {
   o->inner_tol = 1e-5;
   o->matvec = LBS_MATVEC_FMM;
   o->graphs = 1;
+  o->precond = 1;
+}
+
+lbs_status lbs_refine_tolerances_host(int32_t S, const double *rn2, const double *bn2,
+                                      double tol, double inner_tol, double *itol,
+                                      int32_t *all_converged) {
+  if (S < 0 || (S > 0 && (!rn2 || !bn2 || !itol)) || !all_converged) {
+    g_err = "null pointer or negative count";
+    return LBS_ERR_INVALID_ARG;
+  }
+  bool all = true;
+  for (int q = 0; q < S; ++q) {
+    if (!std::isfinite(rn2[q]) || !std::isfinite(bn2[q]) || rn2[q] < 0 || bn2[q] < 0) {
+      g_err = "residual norm of system " + std::to_string(q) + " is not finite";
+      *all_converged = 0;
+      return LBS_ERR_NOT_FINITE;
+    }
+    const double rn = std::sqrt(rn2[q]), bn = std::sqrt(bn2[q]);
+    if (rn <= tol * bn) {
+      itol[q] = rn;  // converged: inactive in the inner solve
+    } else {
+      all = false;
+      itol[q] = std::max(inner_tol * rn, 0.5 * tol * bn);
+    }
+  }
+  *all_converged = all ? 1 : 0;
+  return LBS_OK;
 }
 
 const char *lbs_last_error(void) { return g_err.c_str(); }
@@ -1378,6 +1495,11 @@ lbs_status lbs_matvec(lbs_handle h, int32_t op, int32_t prec, int32_t nrhs, cons
       case LBS_OP_PRECOND:
         apply_precond_op(c, prec, nrhs, x, y, s);
         break;
+      case LBS_OP_IPLUSK_T:
+        ensure_adj(c);
+        for (int r = 0; r < nrhs; ++r)
+          apply_KT(c, x + (int64_t)r * c.geo.N, y + (int64_t)r * c.geo.N, 1.0, prec, s);
+        break;
       default:
         fail(LBS_ERR_INVALID_ARG, "bad op");
     }
@@ -1396,8 +1518,9 @@ lbs_status lbs_solve(lbs_handle h, int32_t prec, int32_t nrhs, const double *gda
     hipStream_t s = (hipStream_t)stream;
     lbs_ctx &c = *h;
     Geometry &g = c.geo;
-    const int R = nrhs, G = g.G, S = R * G;
+    const int R = nrhs, S = R * g.G;
     const int64_t n = g.N + g.M;
+    const bool pre = c.opt.precond != 0;
     auto t0 = std::chrono::steady_clock::now();
     ensure_ws(c, R);
     ensure_gmres(c, R);
@@ -1406,64 +1529,32 @@ lbs_status lbs_solve(lbs_handle h, int32_t prec, int32_t nrhs, const double *gda
     // finite data check
     launch_dots((int64_t)g.N * R, 1, gdat, 0, gdat, 0, gm.nrm2.p, c.ws.red.p, s);
     if (!std::isfinite(download(gm.nrm2.p, 1, s)[0])) fail(LBS_ERR_NOT_FINITE, "data g is not finite");
-    precond_rhs(c, R, gdat, gm.bvec.p, s);
-    sys_norm2(c, R, gm.bvec.p, gm.bn2.p, s);
-    if (prec == LBS_FP64) {
-      launch_scale_sqrt(S, tol, gm.bn2.p, gm.tol.p, s);
-      GmresOut go = gmres(c, LBS_FP64, R, gm.bvec.p, gm.xvec.p, true, c.opt.max_iter, s);
-      inf.iters = go.iters;
-      inf.fp64_matvecs = go.iters;
-      noconv = !go.conv;
-    } else {
-      launch_fill((int64_t)R * n, 0.0, gm.xvec.p, s);
-      LBS_HIP(hipMemcpyAsync(gm.rvec.p, gm.bvec.p, (size_t)R * n * sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
-      std::vector<double> bn2 = download(gm.bn2.p, S, s);
-      std::vector<double> rn2 = bn2;
-      int left = c.opt.max_iter;
-      bool conv = false;
-      for (int outer = 0;; ++outer) {
-        std::vector<double> itol(S);
-        bool all = true;
-        for (int q = 0; q < S; ++q) {
-          const double rn = std::sqrt(std::max(0.0, rn2[q])), bn = std::sqrt(std::max(0.0, bn2[q]));
-          if (rn <= tol * bn) {
-            itol[q] = rn;  // converged: inactive in the inner solve
-          } else {
-            all = false;
-            itol[q] = std::max(c.opt.inner_tol * rn, 0.5 * tol * bn);
-          }
-        }
-        if (all) { conv = true; break; }
-        if (outer >= c.opt.max_outer || left <= 0) break;
-        LBS_HIP(hipMemcpyAsync(gm.tol.p, itol.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
-        GmresOut go = gmres(c, LBS_MIXED, R, gm.rvec.p, gm.dvec.p, true, left, s);
-        inf.iters += go.iters;
-        inf.fp32_matvecs += go.iters;
-        left -= go.iters;
-        launch_axpby((int64_t)R * n, 1.0, gm.dvec.p, 1.0, gm.xvec.p, s);
-        apply_precond_op(c, LBS_FP64, R, gm.xvec.p, gm.rvec.p, s);
-        inf.fp64_matvecs += 1;
-        launch_axpby((int64_t)R * n, 1.0, gm.bvec.p, -1.0, gm.rvec.p, s);
-        sys_norm2(c, R, gm.rvec.p, gm.nrm2.p, s);
-        rn2 = download(gm.nrm2.p, S, s);
-        inf.outer_steps = outer + 1;
-      }
-      noconv = !conv;
-    }
-    // final residual of the preconditioned systems with the FP64 operator
-    apply_precond_op(c, LBS_FP64, R, gm.xvec.p, gm.rvec.p, s);
+    if (pre) precond_rhs(c, R, gdat, gm.bvec.p, s);
+    else system_rhs(c, R, gdat, gm.bvec.p, s);
+    const int gid = pre ? 0 : 4;
+    noconv = !solve_core(c, prec, R, forward_op(c, LBS_FP64, R, pre), gid,
+                         forward_op(c, LBS_MIXED, R, pre), gid + 1, tol, inf, s);
+    // final residuals with the FP64 operator: r = [2 g; 0] - A x (true), and
+    // P^-1 r (preconditioned) relative to P^-1 [2 g; 0]
+    system_rhs(c, R, gdat, gm.dvec.p, s);
+    apply_system(c, LBS_FP64, R, gm.xvec.p, gm.rvec.p, s);
     inf.fp64_matvecs += 1;
-    launch_axpby((int64_t)R * n, 1.0, gm.bvec.p, -1.0, gm.rvec.p, s);
+    launch_axpby((int64_t)R * n, 1.0, gm.dvec.p, -1.0, gm.rvec.p, s);
     sys_norm2(c, R, gm.rvec.p, gm.nrm2.p, s);
-    std::vector<double> rn2 = download(gm.nrm2.p, S, s), bn2 = download(gm.bn2.p, S, s);
-    double worst = 0;
-    for (int q = 0; q < S; ++q)
-      if (bn2[q] > 0) worst = std::max(worst, std::sqrt(rn2[q] / bn2[q]));
+    sys_norm2(c, R, gm.dvec.p, gm.h2.p, s);
+    inf.true_rel_resid = worst_relative(download(gm.nrm2.p, S, s), download(gm.h2.p, S, s),
+                                        "true residual");
+    if (pre) {
+      apply_precond_inverse(c, R, gm.rvec.p, s);
+      sys_norm2(c, R, gm.rvec.p, gm.nrm2.p, s);
+      inf.rel_resid = worst_relative(download(gm.nrm2.p, S, s), download(gm.bn2.p, S, s),
+                                     "preconditioned residual");
+    } else {
+      inf.rel_resid = inf.true_rel_resid;
+    }
     launch_copy_cols(g.N, R, 1.0, gm.xvec.p, n, sigma, g.N, s);
     launch_copy_cols(g.M, R, 1.0, gm.xvec.p + g.N, n, A, g.M, s);
     LBS_HIP(hipStreamSynchronize(s));
-    inf.rel_resid = worst;
     inf.ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;
   });
@@ -1565,71 +1656,26 @@ lbs_status lbs_solve_T(lbs_handle h, int32_t prec, int32_t nrhs, const double *r
     launch_dots((int64_t)R * n, 1, gm.bvec.p, 0, gm.bvec.p, 0, gm.nrm2.p, c.ws.red.p, s);
     if (!std::isfinite(download(gm.nrm2.p, 1, s)[0]))
       fail(LBS_ERR_NOT_FINITE, "right-hand side is not finite");
-    sys_norm2(c, R, gm.bvec.p, gm.bn2.p, s);
     OpFn op64 = [&](const double *in, double *out, hipStream_t q) {
       apply_op_T(c, R, in, out, LBS_FP64, q);
     };
     OpFn op32 = [&](const double *in, double *out, hipStream_t q) {
       apply_op_T(c, R, in, out, LBS_MIXED, q);
     };
-    if (prec == LBS_FP64) {
-      launch_scale_sqrt(S, tol, gm.bn2.p, gm.tol.p, s);
-      GmresOut go = gmres(c, op64, 2, R, gm.bvec.p, gm.xvec.p, true, c.opt.max_iter, s, 2);
-      inf.iters = go.iters;
-      inf.fp64_matvecs = go.iters;
-      noconv = !go.conv;
-    } else {
-      // refinement: r = b - A^T P^-T mu in FP64, correction from GMRES on
-      // the FP32 transposed operator, as in lbs_solve
-      launch_fill((int64_t)R * n, 0.0, gm.xvec.p, s);
-      LBS_HIP(hipMemcpyAsync(gm.rvec.p, gm.bvec.p, (size_t)R * n * sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
-      std::vector<double> bn2 = download(gm.bn2.p, S, s), rn2 = bn2;
-      int left = c.opt.max_iter;
-      bool conv = false;
-      for (int outer = 0;; ++outer) {
-        std::vector<double> itol(S);
-        bool all = true;
-        for (int q = 0; q < S; ++q) {
-          const double rn = std::sqrt(std::max(0.0, rn2[q])), bn = std::sqrt(std::max(0.0, bn2[q]));
-          if (rn <= tol * bn) {
-            itol[q] = rn;
-          } else {
-            all = false;
-            itol[q] = std::max(c.opt.inner_tol * rn, 0.5 * tol * bn);
-          }
-        }
-        if (all) { conv = true; break; }
-        if (outer >= c.opt.max_outer || left <= 0) break;
-        LBS_HIP(hipMemcpyAsync(gm.tol.p, itol.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
-        GmresOut go = gmres(c, op32, 3, R, gm.rvec.p, gm.dvec.p, true, left, s, 1);
-        inf.iters += go.iters;
-        inf.fp32_matvecs += go.iters;
-        left -= go.iters;
-        launch_axpby((int64_t)R * n, 1.0, gm.dvec.p, 1.0, gm.xvec.p, s);
-        op64(gm.xvec.p, gm.rvec.p, s);
-        inf.fp64_matvecs += 1;
-        launch_axpby((int64_t)R * n, 1.0, gm.bvec.p, -1.0, gm.rvec.p, s);
-        sys_norm2(c, R, gm.rvec.p, gm.nrm2.p, s);
-        rn2 = download(gm.nrm2.p, S, s);
-        inf.outer_steps = outer + 1;
-      }
-      noconv = !conv;
-    }
+    noconv = !solve_core(c, prec, R, op64, 2, op32, 3, tol, inf, s);
     // residual of A^T lambda = b (equal to that of the right-preconditioned system)
     op64(gm.xvec.p, gm.rvec.p, s);
     inf.fp64_matvecs += 1;
     launch_axpby((int64_t)R * n, 1.0, gm.bvec.p, -1.0, gm.rvec.p, s);
     sys_norm2(c, R, gm.rvec.p, gm.nrm2.p, s);
-    std::vector<double> rn2 = download(gm.nrm2.p, S, s), bn2 = download(gm.bn2.p, S, s);
-    double worst = 0;
-    for (int q = 0; q < S; ++q)
-      if (bn2[q] > 0) worst = std::max(worst, std::sqrt(rn2[q] / bn2[q]));
+    const double worst = worst_relative(download(gm.nrm2.p, S, s), download(gm.bn2.p, S, s),
+                                        "residual");
     for (int r = 0; r < R; ++r) precond_T(c, gm.xvec.p + r * n, gm.dvec.p + r * n, s);
     launch_copy_cols(g.N, R, 1.0, gm.dvec.p, n, lam_s, g.N, s);
     launch_copy_cols(g.M, R, 1.0, gm.dvec.p + g.N, n, lam_a, g.M, s);
     LBS_HIP(hipStreamSynchronize(s));
     inf.rel_resid = worst;
+    inf.true_rel_resid = worst;
     inf.ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;
   });

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbs.so")
 
 LBS_FP64, LBS_MIXED = 0, 1
-OPS = {"iplusk": 0, "k": 1, "system": 2, "precond": 3}
+OPS = {"iplusk": 0, "k": 1, "system": 2, "precond": 3, "iplusk_t": 4}
 PRECISIONS = {"fp64": LBS_FP64, "mixed": LBS_MIXED, "fp32": LBS_MIXED}
 STATUS = {0: "LBS_OK", 1: "LBS_ERR_INVALID_ARG", 2: "LBS_ERR_GEOMETRY",
           3: "LBS_ERR_NO_CONVERGENCE", 4: "LBS_ERR_NOT_FINITE",
@@ -37,14 +37,15 @@ class Options(ctypes.Structure):
                 ("leaf_max", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("matvec", ctypes.c_int32),
-                ("graphs", ctypes.c_int32)]
+                ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("outer_steps", ctypes.c_int32),
                 ("rel_resid", ctypes.c_double), ("ms_solve", ctypes.c_double),
                 ("fp64_matvecs", ctypes.c_int32),
-                ("fp32_matvecs", ctypes.c_int32)]
+                ("fp32_matvecs", ctypes.c_int32),
+                ("true_rel_resid", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -146,8 +147,11 @@ def load():
                                  ctypes.c_double, vp, ctypes.POINTER(Options),
                                  ctypes.POINTER(TuneEntry), ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_int32)]
-    for name in ("lbs_setup", "lbs_sizes", "lbs_nodes", "lbs_matvec",
-                 "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
+    lib.lbs_refine_tolerances_host.argtypes = [
+        ctypes.c_int32, c_double_p, c_double_p, ctypes.c_double,
+        ctypes.c_double, c_double_p, ctypes.POINTER(ctypes.c_int32)]
+    for name in ("lbs_refine_tolerances_host", "lbs_setup", "lbs_sizes",
+                 "lbs_nodes", "lbs_matvec", "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
                  "lbs_stage_timing", "lbs_stage_times", "lbs_setup_batch",
                  "lbs_batch_info", "lbs_eval_batch",
                  "lbs_check_tree_host", "lbs_eval_T", "lbs_solve_T",
@@ -416,6 +420,21 @@ def check_tree_host(x, y, leaf_max):
         x.ctypes.data_as(c_double_p), y.ctypes.data_as(c_double_p),
         x.shape[0], int(leaf_max), ctypes.byref(bad), ctypes.byref(st)))
     return bad.value, st.as_dict()
+
+
+def refine_tolerances(rn2, bn2, tol, inner_tol):
+    """Host-only refinement step (see lbs_refine_tolerances_host):
+    (inner tolerances, all converged)."""
+    import numpy as np
+    rn2 = np.ascontiguousarray(rn2, dtype=np.float64)
+    bn2 = np.ascontiguousarray(bn2, dtype=np.float64)
+    itol = np.zeros_like(rn2)
+    allc = ctypes.c_int32()
+    _check(load().lbs_refine_tolerances_host(
+        rn2.shape[0], rn2.ctypes.data_as(c_double_p),
+        bn2.ctypes.data_as(c_double_p), float(tol), float(inner_tol),
+        itol.ctypes.data_as(c_double_p), ctypes.byref(allc)))
+    return itol, bool(allc.value)
 
 
 def setup_status(islands, nodes=None, **kw):

@@ -7,11 +7,11 @@ besides sampling is the closed-form boundary data of the paper's examples
 (Section 6, eq. exact_bcs), which both sides receive as an input.
 """
 from .islands import (IslandSet, cap_island, star_islands, config_islands,
-                      batch_geometries, CONFIGS)
+                      batch_geometries, deep_tree_islands, CONFIGS)
 from .data import (exact_harmonic, paper_data_coeffs, random_data_coeffs,
                    sphere_targets, random_vector)
 
 __all__ = ["IslandSet", "cap_island", "star_islands", "config_islands",
-           "batch_geometries", "CONFIGS", "exact_harmonic",
+           "batch_geometries", "deep_tree_islands", "CONFIGS", "exact_harmonic",
            "paper_data_coeffs", "random_data_coeffs", "sphere_targets",
            "random_vector"]

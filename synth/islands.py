@@ -139,6 +139,34 @@ def star_islands(seed, m, r0_range, k_range=(3, 7), nodes=256, amp=0.3,
     return IslandSet(centers, e1, r0, coef, nodes.astype(np.int32), meta)
 
 
+def deep_tree_islands(nodes=128, amp=0.3):
+    """Seven star islands from near the north pole to within 1e-3 rad of the
+    south pole, their radii shrinking from 0.25 to 2e-5 rad.  Stereographic
+    projection magnifies the northern ones and shrinks the southern ones
+    (the distortion the paper points to in Section 6, Example 3), so the
+    quadtree over their images needs 20 or more levels."""
+    spec = [  # (colatitude, longitude, r0, k)
+        (0.45, 0.0, 0.25, 3),
+        (1.2, 1.0, 0.15, 5),
+        (2.0, 2.5, 0.08, 4),
+        (2.8, 4.0, 0.02, 6),
+        (3.1, 0.5, 0.002, 3),
+        (3.1365, 2.0, 1e-4, 5),
+        (3.1405, 4.5, 2e-5, 3),
+    ]
+    m = len(spec)
+    c = np.array([[np.sin(t) * np.cos(p), np.sin(t) * np.sin(p), np.cos(t)]
+                  for t, p, _, _ in spec])
+    e1 = np.stack([_frame(c[i], 0.3 * i) for i in range(m)])
+    r0 = np.array([sp[2] for sp in spec])
+    coef = np.zeros((m, 16))
+    for i, sp in enumerate(spec):
+        coef[i, sp[3] - 1] = amp
+    nodes = np.broadcast_to(np.asarray(nodes, np.int64), (m,)).copy()
+    return IslandSet(c, e1, r0, coef, nodes.astype(np.int32),
+                     {"kind": "deep"})
+
+
 # Workload recipes (sizes and distributions of the paper's examples, with
 # star curves standing in for its ellipses).
 CONFIGS = {

@@ -41,7 +41,33 @@ def test_default_options(lbs):
     o = lbs.default_options()
     assert (o.p64, o.p32, o.restart) == (30, 16, 50)
     assert o.inner_tol == 1e-5
-    assert (o.matvec, o.graphs) == (0, 1)
+    assert (o.matvec, o.graphs, o.precond) == (0, 1, 1)
+
+
+def test_refinement_step_rejects_non_finite_residuals(lbs):
+    """The refinement step of the mixed-precision solves never takes a NaN
+    or Inf residual for a converged system (it reports LBS_ERR_NOT_FINITE),
+    and otherwise sets each system's inner tolerance."""
+    tol, itol_frac = 1e-10, 1e-5
+    bn2 = np.array([4.0, 9.0, 1.0])
+    rn2 = np.array([4.0 * 1e-22, 9.0 * 1e-8, 1.0])
+    itol, done = lbs.refine_tolerances(rn2, bn2, tol, itol_frac)
+    assert not done
+    assert itol[0] == pytest.approx(np.sqrt(rn2[0]))       # converged: kept
+    assert itol[1] == pytest.approx(itol_frac * np.sqrt(rn2[1]))
+    assert itol[2] == pytest.approx(itol_frac * 1.0)
+    # the floor: half the outer target
+    itol, _ = lbs.refine_tolerances([1e-10], [1.0], 1e-6, 1e-5)
+    assert itol[0] == pytest.approx(0.5e-6)
+    itol, done = lbs.refine_tolerances(rn2 * 1e-30, bn2, tol, itol_frac)
+    assert done
+    for bad in (np.nan, np.inf, -1.0):
+        with pytest.raises(lbs.LBSError) as e:
+            lbs.refine_tolerances([1e-30, bad], [1.0, 1.0], tol, itol_frac)
+        assert e.value.status == "LBS_ERR_NOT_FINITE"
+    with pytest.raises(lbs.LBSError) as e:
+        lbs.refine_tolerances([1e-30], [np.nan], tol, itol_frac)
+    assert e.value.status == "LBS_ERR_NOT_FINITE"
 
 
 @pytest.mark.parametrize("case", ["uniform", "curves", "clustered", "tiny"])
@@ -118,3 +144,14 @@ def test_setup_rejects_bad_options(lbs):
     assert lbs.setup_status(isl, restart=0) == "LBS_ERR_INVALID_ARG"
     assert lbs.setup_status(isl, nodes=4) == "LBS_ERR_INVALID_ARG"
     assert lbs.setup_status(isl, graphs=2) == "LBS_ERR_INVALID_ARG"
+
+
+def test_deep_tree_geometry_levels_and_coverage(lbs):
+    """The projection-distorted geometry (islands from near the north pole
+    to near the south pole) needs 20+ quadtree levels, and its lists still
+    cover every point pair exactly once."""
+    cv = Curves(synth.deep_tree_islands(128))
+    for lm in (16, 48):
+        bad, st = lbs.check_tree_host(cv.xi.real, cv.xi.imag, lm)
+        assert bad == 0
+        assert st["levels"] >= 21, st

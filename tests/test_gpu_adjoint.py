@@ -254,5 +254,7 @@ def test_adjoint_full_size(env):
     b0 = isl.coef[k, q]
     f = {s: J_at(b0 + s * h) for s in (-2, -1, 1, 2)}
     fd = (8 * (f[1] - f[-1]) - (f[2] - f[-2])) / (12 * h)
-    assert abs(dc[k, q] - fd) < 1e-5 * np.abs(dc).max()
+    # the gradient bar (1e-6 relative); the difference quotient's own error
+    # (fourth order in h, plus the 1e-12 solve tolerance over h) is far below
+    assert abs(dc[k, q] - fd) < 1e-6 * np.abs(dc).max()
     sol.close()
