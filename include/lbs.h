@@ -102,6 +102,16 @@ typedef struct {
                      /* Schur complement); 0: GMRES on A itself (eq.       */
                      /* matrix_eqns), whose condition number grows with N  */
                      /* (Section 6, Example 1, Table 1).  lbs_solve only.  */
+  int32_t close_eval;/* 1 (default): lbs_eval replaces the trapezoidal     */
+                     /* Cauchy sum of an island by the compensated rule    */
+                     /* for exterior Cauchy integrals at targets in the    */
+                     /* island's close zone (the cap of angular radius     */
+                     /* max node distance from the centre + 8 node         */
+                     /* spacings), accurate at any distance from the       */
+                     /* curve; 0: the trapezoidal rule of eq. disc_sphere  */
+                     /* everywhere.  lbs_eval_T / lbs_shape_vjp cover the  */
+                     /* trapezoidal rule only and reject close targets     */
+                     /* while it is 1.                                     */
 } lbs_options;
 
 typedef struct {
@@ -194,9 +204,15 @@ lbs_status lbs_solve(lbs_handle h, int32_t precision, int32_t nrhs,
 /* Evaluate psi = W sigma + sum_m A_m G(x, c_m) (eq. eqn:u_multi) at
  * n_targets sphere points xyz_targets (device, T x 3 row-major) for nrhs
  * density/strength columns; u is device (T x nrhs).  Targets must lie in
- * the domain, a few node spacings away from every curve (the trapezoidal
- * rule is used as is); the north pole is allowed.  Synchronous (builds a
- * target tree on the host). */
+ * the domain (outside every island; a target on a node is not supported);
+ * the north pole is allowed.  The double layer is summed by the
+ * trapezoidal rule of eq. disc_sphere, except at targets in an island's
+ * close zone while opt.close_eval = 1, where that island's Cauchy sum is
+ * taken by the compensated rule (Ioakimidis, Papadakis and Perdios 1991;
+ * Helsing and Ojala 2008): v(z) = sum_j V_j a_j / (sum_j a_j - 2 pi i s_k),
+ * a_j = h xi'_j / (xi_j - z), V the exterior boundary values of the Cauchy
+ * integral.  Synchronous (builds a target tree and the close pairs on the
+ * host; both are kept for the next call with the same targets). */
 lbs_status lbs_eval(lbs_handle h, int32_t nrhs, const double *sigma,
                     const double *A, int64_t n_targets,
                     const double *xyz_targets, double *u, void *stream);

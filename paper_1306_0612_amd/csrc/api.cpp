@@ -11,6 +11,7 @@
 #include <memory>
 #include <tuple>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "lbs_internal.h"
@@ -349,6 +350,8 @@ struct EvalPlan {
   DBuf<double> qt;              // forward: qfac in the plan's source order
   DBuf<int64_t> didx;           // transposed: idx on the device
   DBuf<int32_t> dtgeo;
+  ClosePlan close;              // targets in close zones (close_eval on)
+  DBuf<double> closeV;          // boundary values, 2 N per column
 };
 
 // Buffers of the transposed operators (one column).
@@ -392,6 +395,10 @@ struct lbs_ctx {
   AdjState adj;
   std::unique_ptr<EvalPlan> evf, evt;  // cached forward / transposed plans
   GraphCache graphs;
+  // island centres hashed by (geometry, cell of the unit cube) for the
+  // close-zone search of evaluations; built on first use
+  std::unordered_map<uint64_t, std::vector<int32_t>> igrid;
+  double icell = 0.0;
   int32_t *count_host = nullptr;
   ~lbs_ctx() {
     if (count_host) (void)hipHostFree(count_host);
@@ -908,6 +915,104 @@ void build_far_lists(Geometry &g, const std::vector<int32_t> &isl_geo,
   LBS_HIP(hipStreamSynchronize(s));
 }
 
+// Close-evaluation zones: island k's zone is the cap about its centre of
+// angular radius (largest node distance from the centre) + 8 (largest
+// chord between consecutive nodes); beyond it the trapezoidal rule is
+// accurate to rounding (its error decays like exp(-2 pi d / spacing)).
+void set_close_zones(Geometry &g, const std::vector<double> &xyz) {
+  g.zone_cos.assign(g.M, 1.0);
+  for (int k = 0; k < g.M; ++k) {
+    const double *c = &g.cxyz[3 * k];
+    double bound = 0.0, ell = 0.0;
+    for (int64_t i = g.offs[k]; i < g.offs[k + 1]; ++i) {
+      const double *x = &xyz[3 * i];
+      const double d = std::max(-1.0, std::min(1.0, x[0] * c[0] + x[1] * c[1] + x[2] * c[2]));
+      bound = std::max(bound, std::acos(d));
+      const int64_t j = i + 1 < g.offs[k + 1] ? i + 1 : g.offs[k];
+      const double *y = &xyz[3 * j];
+      ell = std::max(ell, std::sqrt((x[0] - y[0]) * (x[0] - y[0]) + (x[1] - y[1]) * (x[1] - y[1]) +
+                                    (x[2] - y[2]) * (x[2] - y[2])));
+    }
+    g.zone_cos[k] = std::cos(std::min(bound + 8.0 * ell, M_PI));
+  }
+}
+
+// Close pairs of an evaluation: every non-pole target with the islands of
+// its geometry whose close zone holds it (host, from the cached targets).
+void build_close(lbs_ctx &c, EvalPlan &ep, const std::vector<double> &hx, hipStream_t s) {
+  Geometry &g = c.geo;
+  if (c.igrid.empty()) {
+    double cell = 1e-4;
+    for (int k = 0; k < g.M; ++k)
+      cell = std::max(cell, std::sqrt(std::max(0.0, 2.0 - 2.0 * g.zone_cos[k])));
+    c.icell = cell;
+    std::vector<int32_t> isl_geo(g.M);
+    for (int q = 0; q < g.G; ++q)
+      for (int k = g.gisl[q]; k < g.gisl[q + 1]; ++k) isl_geo[k] = q;
+    for (int k = 0; k < g.M; ++k) {
+      const double *ck = &g.cxyz[3 * k];
+      uint64_t key = (uint64_t)isl_geo[k] << 48;
+      for (int a = 0; a < 3; ++a)
+        key |= (uint64_t)std::floor((ck[a] + 1.0) / cell) << (32 - 16 * a);
+      c.igrid[key].push_back(k);
+    }
+  }
+  const double cell = c.icell;
+  const int64_t n = (int64_t)ep.idx.size();
+  std::vector<std::vector<int32_t>> near(n);
+  parallel_for(n, [&](int64_t c0, int64_t c1) {
+    for (int64_t q = c0; q < c1; ++q) {
+      const int64_t t = ep.idx[q];
+      const double *x = &hx[3 * t];
+      int64_t cc[3];
+      for (int a = 0; a < 3; ++a) cc[a] = (int64_t)std::floor((x[a] + 1.0) / cell);
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dz = -1; dz <= 1; ++dz) {
+            const int64_t ix = cc[0] + dx, iy = cc[1] + dy, iz = cc[2] + dz;
+            if (ix < 0 || iy < 0 || iz < 0) continue;
+            const uint64_t key = ((uint64_t)ep.tgeo[t] << 48) | ((uint64_t)ix << 32) |
+                                 ((uint64_t)iy << 16) | (uint64_t)iz;
+            auto it = c.igrid.find(key);
+            if (it == c.igrid.end()) continue;
+            for (int32_t k : it->second) {
+              const double *ck = &g.cxyz[3 * k];
+              if (x[0] * ck[0] + x[1] * ck[1] + x[2] * ck[2] > g.zone_cos[k]) near[q].push_back(k);
+            }
+          }
+      std::sort(near[q].begin(), near[q].end());
+    }
+  }, 2048);
+  std::vector<double> z;
+  std::vector<int64_t> out;
+  std::vector<int32_t> ptr(1, 0), isl;
+  std::vector<uint8_t> used(g.M, 0);
+  for (int64_t q = 0; q < n; ++q) {
+    if (near[q].empty()) continue;
+    z.push_back(ep.tx[q]);
+    z.push_back(ep.ty[q]);
+    out.push_back(ep.idx[q]);
+    for (int32_t k : near[q]) {
+      isl.push_back(k);
+      used[k] = 1;
+    }
+    ptr.push_back((int32_t)isl.size());
+  }
+  std::vector<int32_t> act;
+  for (int k = 0; k < g.M; ++k)
+    if (used[k]) act.push_back(k);
+  ClosePlan &cp = ep.close;
+  cp.n_tgt = (int)out.size();
+  cp.n_act = (int)act.size();
+  if (cp.n_tgt == 0) return;
+  cp.z.upload(z, s);
+  cp.out.upload(out, s);
+  cp.ptr.upload(ptr, s);
+  cp.isl.upload(isl, s);
+  cp.act.upload(act, s);
+  LBS_HIP(hipStreamSynchronize(s));  // the host vectors are released on return
+}
+
 void validate_options(const lbs_options &o) {
   if (!p64_ok(o.p64)) fail(LBS_ERR_UNSUPPORTED, "p64 must be 20/24/30/36/40/48");
   if (!p32_ok(o.p32)) fail(LBS_ERR_UNSUPPORTED, "p32 must be 12/16/20/24");
@@ -918,6 +1023,7 @@ void validate_options(const lbs_options &o) {
   if (o.matvec != LBS_MATVEC_FMM && o.matvec != LBS_MATVEC_DIRECT) fail(LBS_ERR_INVALID_ARG, "bad matvec mode");
   if (o.graphs != 0 && o.graphs != 1) fail(LBS_ERR_INVALID_ARG, "graphs must be 0 or 1");
   if (o.precond != 0 && o.precond != 1) fail(LBS_ERR_INVALID_ARG, "precond must be 0 or 1");
+  if (o.close_eval != 0 && o.close_eval != 1) fail(LBS_ERR_INVALID_ARG, "close_eval must be 0 or 1");
 }
 
 // Set-up of G geometries (islands and node counts concatenated
@@ -1037,6 +1143,7 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl,
     g.sign[k] = area > 0 ? 1.0 : -1.0;
   }
   g.dsign.upload(g.sign, s);
+  set_close_zones(g, xyz);
   g.qfac.alloc(2 * N);
   g.tau.alloc(N);
   g.gw.alloc(N);
@@ -1257,6 +1364,7 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
     ep->ws.ensure(ep->pl, c.opt.p64, c.opt.p32, 1, g.N, g.M, G, kPlog);
     ep->tree = true;
   }
+  if (c.opt.close_eval && n > 0) build_close(c, *ep, hx, s);
   LBS_HIP(hipStreamSynchronize(s));
   ep->key = std::move(hx);
   slot = std::move(ep);
@@ -1297,7 +1405,20 @@ void eval_impl(lbs_ctx &c, int nrhs, const double *sigma, const double *A,
   launch_segdots(c.seg_nodes, nrhs, 1, g.gw.p, 0, 0, sigma, g.N, c.ws.gam.p, c.ws.red.p, s);
   launch_axpby((int64_t)nrhs * G, 0.0, c.ws.gam.p, 0.5, c.ws.gam.p, s);
   launch_eval_logsrc(g, T, txyz, ep.dtgeo.p, A, g.M, nrhs, c.ws.gam.p, u, T, s);
+  if (ep.close.n_tgt > 0) {
+    if (ep.closeV.n < (size_t)2 * g.N * nrhs) ep.closeV.alloc((size_t)2 * g.N * nrhs);
+    launch_close_eval(g, ep.close, nrhs, sigma, g.N, ep.closeV.p, u, T, s);
+  }
   LBS_HIP(hipStreamSynchronize(s));
+}
+
+// The transposed evaluation and the shape derivative cover the trapezoidal
+// rule only.
+void reject_close(const EvalPlan &ep, const char *what) {
+  if (ep.close.n_tgt > 0)
+    fail(LBS_ERR_UNSUPPORTED, std::string(what) + ": " + std::to_string(ep.close.n_tgt) +
+                                  " targets lie in the close-evaluation zone of a curve "
+                                  "(set close_eval = 0 for the trapezoidal rule)");
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -1393,6 +1514,7 @@ void lbs_default_options(lbs_options *o) {
   o->matvec = LBS_MATVEC_FMM;
   o->graphs = 1;
   o->precond = 1;
+  o->close_eval = 1;
 }
 
 lbs_status lbs_refine_tolerances_host(int32_t S, const double *rn2, const double *bn2,
@@ -1614,6 +1736,7 @@ lbs_status lbs_eval_T(lbs_handle h, int32_t nrhs, const double *w, int64_t T, co
     ensure_ws(c, 1);
     ensure_adj(c);
     EvalPlan &ep = eval_plan(c, true, {0, T}, txyz, s);
+    reject_close(ep, "lbs_eval_T");
     DBuf<double> pcw, wsum;
     pcw.alloc((size_t)2 * std::max<size_t>(ep.idx.size(), 1));
     wsum.alloc(1);
@@ -1715,6 +1838,7 @@ lbs_status lbs_shape_vjp(lbs_handle h, const double *sigma, const double *A, con
     DBuf<double> pcw;
     if (T > 0) {
       EvalPlan &ep = eval_plan(c, true, {0, T}, txyz, s);
+      reject_close(ep, "lbs_shape_vjp");
       pcw.alloc((size_t)2 * std::max<size_t>(ep.idx.size(), 1));
       eval_T_field(c, ep, w, pcw.p, Fw, dFw, s);
       launch_sum(T, w, sums + 2, s);

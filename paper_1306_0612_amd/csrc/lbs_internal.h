@@ -256,6 +256,20 @@ struct Geometry {
   DBuf<double> dsign;                // orientation sign per island
   DBuf<double> Sinv;                 // block-diagonal inverse Schur complement
   DBuf<double> SinvT;                // its transpose (adjoint; made on first use)
+  // close-evaluation zone per island: cos of its angular radius (the
+  // largest node distance from the centre plus ten node spacings)
+  std::vector<double> zone_cos;
+};
+
+// Targets of an evaluation that lie in the close zone of one or more
+// islands (close.hip): planar position and output index per close target,
+// its islands in CSR form, and the islands that occur at all.
+struct ClosePlan {
+  int n_tgt = 0, n_act = 0;
+  DBuf<double> z;          // 2 per close target
+  DBuf<int64_t> out;       // target's position in the output
+  DBuf<int32_t> ptr, isl;  // islands of close target t: isl[ptr[t] .. ptr[t+1])
+  DBuf<int32_t> act;       // islands with a close target
 };
 
 // Segments of rows for segmented dot products: each segment is a union of
@@ -354,6 +368,12 @@ void direct_eval64(int64_t N, const double *xi, const double *qfac,
                    const double *sigma, int64_t ldx, int64_t T,
                    const double *txi, const uint8_t *pole, int nrhs,
                    double *out, int64_t ldy, double scale, hipStream_t s);
+
+// u += close-evaluation corrections for the targets of cp (nrhs columns;
+// V: 2 N nrhs doubles of scratch for the boundary values).
+void launch_close_eval(const Geometry &g, const ClosePlan &cp, int nrhs,
+                       const double *sigma, int64_t ldx, double *V, double *u,
+                       int64_t ldu, hipStream_t s);
 
 // dot products: out[r] = sum_i a[r*lda + i] * b[r*ldb + i], i < n
 void launch_dots(int64_t n, int nrhs, const double *a, int64_t lda,

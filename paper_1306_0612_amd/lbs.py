@@ -37,7 +37,8 @@ class Options(ctypes.Structure):
                 ("leaf_max", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("matvec", ctypes.c_int32),
-                ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("close_eval", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

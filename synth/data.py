@@ -88,3 +88,30 @@ def sphere_targets(seed, count, islands, far_factor=1.3, far_nodes=10.0,
         out.append(v)
         got += v.shape[0]
     return np.concatenate(out)[:count]
+
+
+def near_curve_targets(islands, seed, dists, per=3):
+    """Sphere points just outside the curves: for every island k and every
+    d in dists, `per` points on the geodesic ray of a random parameter t
+    (between nodes) at polar radius r(t) + d r0_k about the centre.
+    Returns (points (n, 3), d of each point)."""
+    rng = np.random.default_rng(seed)
+    pts, tag = [], []
+    nn = np.arange(1, 9)
+    for k in range(islands.m):
+        c = islands.center[k]
+        e1 = islands.e1[k]
+        e2 = np.cross(e1, c)
+        n = int(islands.n[k])
+        for d in dists:
+            t = (rng.integers(n, size=per) + rng.uniform(0.1, 0.9, per)) \
+                * 2 * np.pi / n
+            a, b = islands.coef[k, :8], islands.coef[k, 8:]
+            r = islands.r0[k] * (1.0 + (a[:, None] * np.cos(nn[:, None] * t)
+                                        + b[:, None] * np.sin(nn[:, None] * t)
+                                        ).sum(0))
+            rr = r + d * islands.r0[k]
+            u = np.cos(t)[:, None] * e1 + np.sin(t)[:, None] * e2
+            pts.append(np.cos(rr)[:, None] * c + np.sin(rr)[:, None] * u)
+            tag += [d] * per
+    return np.concatenate(pts), np.array(tag)

@@ -10,28 +10,7 @@ import pytest
 import synth
 from oracle import nystrom, evaluate
 from oracle.close import evaluate_close, spectral_derivative
-from oracle.geometry import Curves, radius_derivs
-
-
-def near_targets(isl, seed, dists, per=3):
-    """Points outside island k's curve on the ray of parameter t* (between
-    nodes) at geodesic polar radius r(t*) + d r0_k, for every island."""
-    rng = np.random.default_rng(seed)
-    pts, tag = [], []
-    for k in range(isl.m):
-        c = isl.center[k]
-        e1 = isl.e1[k]
-        e2 = np.cross(e1, c)
-        n = int(isl.n[k])
-        for d in dists:
-            t = (rng.integers(n, size=per) + rng.uniform(0.1, 0.9, per)) \
-                * 2 * np.pi / n
-            r, _, _ = radius_derivs(isl.r0[k], isl.coef[k], t)
-            rr = r + d * isl.r0[k]
-            u = np.cos(t)[:, None] * e1 + np.sin(t)[:, None] * e2
-            pts.append(np.cos(rr)[:, None] * c + np.sin(rr)[:, None] * u)
-            tag += [d] * per
-    return np.concatenate(pts), np.array(tag)
+from oracle.geometry import Curves
 
 
 @pytest.fixture(scope="module")
@@ -60,7 +39,7 @@ def test_close_targets_reach_the_exact_solution(solved):
     plain trapezoidal rule loses all accuracy."""
     isl, cv, coeffs, g, s, a = solved
     dists = [1e-1, 1e-2, 1e-3, 1e-4, 1e-6]
-    tg, tag = near_targets(isl, 14, dists)
+    tg, tag = synth.near_curve_targets(isl, 14, dists)
     exact = synth.exact_harmonic(tg, isl.center, coeffs)
     scale = np.abs(exact).max()
     u = evaluate_close(cv, s, a, tg)
