@@ -8,23 +8,50 @@ xi, d xi/dt and d^2 xi/dt^2 at the nodes.  Everything here is FP64.
 import numpy as np
 
 
-class Curves:
-    """All nodes of all islands, curve-major (island 0's nodes first)."""
+class SampledIslands:
+    """Islands given by their node samples only (Section 6, Example 2):
+    a point c_k inside each curve (its log source) and the node counts."""
 
-    def __init__(self, islands):
+    def __init__(self, centers, nodes):
+        self.center = np.asarray(centers, float)
+        self.n = np.asarray(nodes, np.int64)
+
+    @property
+    def m(self):
+        return int(self.center.shape[0])
+
+
+class Curves:
+    """All nodes of all islands, curve-major (island 0's nodes first).
+
+    Either analytic islands (`islands`: centre, frame, radius function), or
+    `samples` = (x, x_t, x_tt, centers, nodes_per_curve): the nodes of
+    every curve at t_j = 2 pi j / N_k of its own parameter, with the first
+    and second t-derivatives, curve-major."""
+
+    def __init__(self, islands=None, samples=None):
+        if samples is not None:
+            x, xt, xtt, centers, nodes = samples
+            islands = SampledIslands(centers, nodes)
+            self.x = np.asarray(x, float)
+            self.xt = np.asarray(xt, float)
+            self.xtt = np.asarray(xtt, float)
         self.islands = islands
         m = islands.m
         xs, xts, xtts, isl, hs = [], [], [], [], []
         for k in range(m):
             n = int(islands.n[k])
-            x, xt, xtt = curve_on_sphere(islands.center[k], islands.e1[k],
-                                         islands.r0[k], islands.coef[k], n)
-            xs.append(x), xts.append(xt), xtts.append(xtt)
+            if samples is None:
+                x, xt, xtt = curve_on_sphere(islands.center[k],
+                                             islands.e1[k], islands.r0[k],
+                                             islands.coef[k], n)
+                xs.append(x), xts.append(xt), xtts.append(xtt)
             isl.append(np.full(n, k))
             hs.append(np.full(n, 2 * np.pi / n))
-        self.x = np.concatenate(xs)
-        self.xt = np.concatenate(xts)
-        self.xtt = np.concatenate(xtts)
+        if samples is None:
+            self.x = np.concatenate(xs)
+            self.xt = np.concatenate(xts)
+            self.xtt = np.concatenate(xtts)
         self.island = np.concatenate(isl)
         self.h = np.concatenate(hs)
         self.xi, self.dxi, self.ddxi = stereographic(self.x, self.xt, self.xtt)
