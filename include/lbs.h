@@ -146,6 +146,45 @@ lbs_status lbs_setup(const lbs_island *islands_host, int32_t n_islands,
                      const lbs_options *opt_host, void *stream,
                      lbs_handle *out_host);
 
+/* Set-up from sampled curves: the caller gives every node of every curve
+ * with its first and second derivatives with respect to the curve's own
+ * parameter t, at t_j = 2 pi j / N_k, j = 0..N_k-1 (x_host, xt_host,
+ * xtt_host: N x 3 each, row-major, curve-major as the API order), and a
+ * point inside each curve (centers_host: M x 3 unit vectors; it is the
+ * island's log source c_k of eq. eqn:u_multi).  The trapezoidal rule of
+ * eq. disc_sphere then runs over that parameter, as Section 6, Example 2
+ * does with coastlines resampled at points equally spaced in arclength
+ * (lbs_resample_curve_host).  Nodes must be unit vectors (to 1e-9) in the
+ * open hemisphere about their centre, each curve must wind once about its
+ * centre, and bounding caps (largest node distance from the centre plus
+ * the largest chord between neighbouring nodes) follow the rules of
+ * lbs_setup.  Everything else is as lbs_setup; the handle has no shape
+ * coefficients (lbs_shape_vjp returns LBS_ERR_UNSUPPORTED).  Synchronous;
+ * the host arrays are read during the call only. */
+lbs_status lbs_setup_sampled(const double *x_host, const double *xt_host,
+                             const double *xtt_host,
+                             const double *centers_host, int32_t n_islands,
+                             const int32_t *nodes_per_curve_host,
+                             const lbs_options *opt_host, void *stream,
+                             lbs_handle *out_host);
+
+/* Host-only (no GPU needed): n_out points equally spaced in arclength on
+ * the closed curve through the n_in >= 8 samples x_host (n_in x 3 unit
+ * vectors at equispaced values of some parameter), starting at the first
+ * sample, with x, x_t, x_tt for the parameter t = 2 pi s / L (x_out,
+ * xt_out, xtt_out: n_out x 3, caller-allocated) and the length L.  The
+ * curve is the trigonometric interpolant, with the modes |k| <= n_modes
+ * (0: all below n_in / 2; fewer smooth the data), of the samples'
+ * stereographic images from the antipode of center_host, a unit vector
+ * inside the curve (Section 6, Example 2 smooths and resamples coastlines
+ * this way before eq. disc_sphere).  LBS_ERR_GEOMETRY for a sample that is
+ * not finite or lies opposite the centre. */
+lbs_status lbs_resample_curve_host(int32_t n_in, const double *x_host,
+                                   const double *center_host, int32_t n_modes,
+                                   int32_t n_out, double *x_out_host,
+                                   double *xt_out_host, double *xtt_out_host,
+                                   double *length_host);
+
 /* Batch of n_geoms independent geometries in one handle (one FMM forest;
  * every FMM stage is launched once for all geometries and right-hand
  * sides).  islands_host and nodes_per_curve_host are concatenated

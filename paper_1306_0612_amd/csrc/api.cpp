@@ -1028,9 +1028,81 @@ void validate_options(const lbs_options &o) {
 
 // Set-up of G geometries (islands and node counts concatenated
 // geometry-major; isl_per_geom[g] islands each).
-lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl,
+// Curves given as node samples (lbs_setup_sampled): x, x', x'' per node
+// (N x 3 each, host) and a point inside each curve (M x 3, host).
+struct Samples {
+  const double *x = nullptr, *xt = nullptr, *xtt = nullptr, *centers = nullptr;
+};
+
+// Validate sampled curves and describe them as islands without shape
+// coefficients (centre, a frame vector e1, r0 = 0); their bounding radii
+// into `bound`.  offs: node offsets per island.
+std::vector<lbs_island> sampled_islands(const Samples &sm, int M,
+                                        const std::vector<int64_t> &offs,
+                                        std::vector<double> &bound) {
+  std::vector<lbs_island> isl(M);
+  bound.assign(M, 0.0);
+  for (int k = 0; k < M; ++k) {
+    const std::string tag = "island " + std::to_string(k) + ": ";
+    const double *c = sm.centers + 3 * k;
+    if (!std::isfinite(c[0]) || !std::isfinite(c[1]) || !std::isfinite(c[2]))
+      fail(LBS_ERR_GEOMETRY, tag + "non-finite centre");
+    if (std::fabs(c[0] * c[0] + c[1] * c[1] + c[2] * c[2] - 1.0) > 2e-10)
+      fail(LBS_ERR_GEOMETRY, tag + "centre is not a unit vector");
+    lbs_island &I = isl[k];
+    std::memset(&I, 0, sizeof(I));
+    double e1[3] = {-c[1], c[0], 0.0};
+    if (std::hypot(e1[0], e1[1]) < 1e-12) e1[0] = 1.0, e1[1] = 0.0;
+    const double d = e1[0] * c[0] + e1[1] * c[1] + e1[2] * c[2];
+    for (int a = 0; a < 3; ++a) e1[a] -= d * c[a];
+    const double nn = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (int a = 0; a < 3; ++a) {
+      I.center[a] = c[a];
+      I.e1[a] = e1[a] / nn;
+    }
+    const double e2[3] = {I.e1[1] * c[2] - I.e1[2] * c[1], I.e1[2] * c[0] - I.e1[0] * c[2],
+                          I.e1[0] * c[1] - I.e1[1] * c[0]};
+    // node checks, bounding radius (largest node distance plus the largest
+    // chord between neighbours) and the winding number of the curve about
+    // the centre in the centre's own stereographic frame
+    double ang = 0.0, ell = 0.0, wind = 0.0, pa = 0.0, pb = 0.0;
+    for (int64_t i = offs[k]; i < offs[k + 1]; ++i) {
+      const double *x = sm.x + 3 * i, *xt = sm.xt + 3 * i, *xtt = sm.xtt + 3 * i;
+      for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(x[a]) || !std::isfinite(xt[a]) || !std::isfinite(xtt[a]))
+          fail(LBS_ERR_GEOMETRY, tag + "non-finite node sample");
+      if (std::fabs(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] - 1.0) > 1e-9)
+        fail(LBS_ERR_GEOMETRY, tag + "node " + std::to_string(i) + " is not on the unit sphere");
+      const double h = x[0] * c[0] + x[1] * c[1] + x[2] * c[2];
+      if (!(h > 0.0)) fail(LBS_ERR_GEOMETRY, tag + "curve reaches the centre's hemisphere boundary");
+      ang = std::max(ang, std::acos(std::min(1.0, h)));
+      const int64_t j = i + 1 < offs[k + 1] ? i + 1 : offs[k];
+      const double *y = sm.x + 3 * j;
+      ell = std::max(ell, std::sqrt((x[0] - y[0]) * (x[0] - y[0]) + (x[1] - y[1]) * (x[1] - y[1]) +
+                                    (x[2] - y[2]) * (x[2] - y[2])));
+      const double a = (x[0] * I.e1[0] + x[1] * I.e1[1] + x[2] * I.e1[2]) / (1.0 + h);
+      const double b = (x[0] * e2[0] + x[1] * e2[1] + x[2] * e2[2]) / (1.0 + h);
+      if (i > offs[k]) wind += std::atan2(pa * b - pb * a, pa * a + pb * b);
+      pa = a;
+      pb = b;
+    }
+    {
+      const double *x = sm.x + 3 * offs[k];
+      const double h = x[0] * c[0] + x[1] * c[1] + x[2] * c[2];
+      const double a = (x[0] * I.e1[0] + x[1] * I.e1[1] + x[2] * I.e1[2]) / (1.0 + h);
+      const double b = (x[0] * e2[0] + x[1] * e2[1] + x[2] * e2[2]) / (1.0 + h);
+      wind += std::atan2(pa * b - pb * a, pa * a + pb * b);
+    }
+    if (std::fabs(std::fabs(wind) - 2.0 * M_PI) > 0.5)
+      fail(LBS_ERR_GEOMETRY, tag + "the centre is not inside the curve");
+    bound[k] = ang + ell;
+  }
+  return isl;
+}
+
+lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl_in,
                     const int32_t *nodes, const lbs_options *opt,
-                    hipStream_t s) {
+                    hipStream_t s, const Samples *sm = nullptr) {
   auto ctx = std::make_unique<lbs_ctx>();
   lbs_default_options(&ctx->opt);
   if (opt) ctx->opt = *opt;
@@ -1054,9 +1126,26 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl,
   std::vector<double> bound(M);
   g.cxyz.resize(3 * M);
   for (int k = 0; k < M; ++k) {
-    const lbs_island &I = isl[k];
     if (nodes[k] < 8) fail(LBS_ERR_INVALID_ARG, "island " + std::to_string(k) + ": fewer than 8 nodes");
     g.offs[k + 1] = g.offs[k] + nodes[k];
+  }
+  std::vector<lbs_island> smp_isl;
+  if (sm) {
+    smp_isl = sampled_islands(*sm, M, g.offs, bound);
+    g.sampled = true;
+  }
+  const lbs_island *isl = sm ? smp_isl.data() : isl_in;
+  for (int k = 0; k < M; ++k) {
+    const lbs_island &I = isl[k];
+    if (sm) {
+      for (int a = 0; a < 3; ++a) g.cxyz[3 * k + a] = I.center[a];
+      if (bound[k] >= 0.5 * M_PI)
+        fail(LBS_ERR_GEOMETRY, "island " + std::to_string(k) + ": bounding radius >= pi/2");
+      const double pole_ang = std::acos(std::max(-1.0, std::min(1.0, I.center[2])));
+      if (pole_ang <= bound[k] * (1 + 1e-9) + 1e-9)
+        fail(LBS_ERR_GEOMETRY, "island " + std::to_string(k) + ": north pole inside or on the bounding cap");
+      continue;
+    }
     double cs = 0, es = 0, dot = 0, amp = 0;
     bool fin = std::isfinite(I.r0);
     for (int a = 0; a < 3; ++a) {
@@ -1126,7 +1215,16 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl,
   g.xi.alloc(2 * N);
   g.dxi.alloc(2 * N);
   g.ddxi.alloc(2 * N);
-  launch_geometry(g.disl.p, M, g.doffs.p, g.island.p, N, g.xyz.p, g.xi.p, g.dxi.p, g.ddxi.p, s);
+  if (sm) {
+    DBuf<double> dx, dxt, dxtt;
+    dx.upload(std::vector<double>(sm->x, sm->x + 3 * N), s);
+    dxt.upload(std::vector<double>(sm->xt, sm->xt + 3 * N), s);
+    dxtt.upload(std::vector<double>(sm->xtt, sm->xtt + 3 * N), s);
+    launch_geometry_sampled(N, dx.p, dxt.p, dxtt.p, g.xyz.p, g.xi.p, g.dxi.p, g.ddxi.p, s);
+    LBS_HIP(hipStreamSynchronize(s));  // the samples are released on return
+  } else {
+    launch_geometry(g.disl.p, M, g.doffs.p, g.island.p, N, g.xyz.p, g.xi.p, g.dxi.p, g.ddxi.p, s);
+  }
   std::vector<double> xyz = g.xyz.download(s), xi = g.xi.download(s), dxi = g.dxi.download(s);
   for (int64_t i = 0; i < N; ++i) {
     if (!std::isfinite(xi[2 * i]) || !std::isfinite(xi[2 * i + 1]) || !std::isfinite(dxi[2 * i]) ||
@@ -1556,6 +1654,23 @@ lbs_status lbs_setup(const lbs_island *isl, int32_t M, const int32_t *nodes,
   });
 }
 
+lbs_status lbs_setup_sampled(const double *x, const double *xt, const double *xtt,
+                             const double *centers, int32_t M, const int32_t *nodes,
+                             const lbs_options *opt, void *stream, lbs_handle *out) {
+  return guard([&] {
+    if (!out) fail(LBS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!x || !xt || !xtt || !centers || !nodes) fail(LBS_ERR_INVALID_ARG, "null pointer argument");
+    if (M < 1) fail(LBS_ERR_INVALID_ARG, "n_islands < 1");
+    Samples sm;
+    sm.x = x;
+    sm.xt = xt;
+    sm.xtt = xtt;
+    sm.centers = centers;
+    *out = setup_impl(1, &M, nullptr, nodes, opt, (hipStream_t)stream, &sm);
+  });
+}
+
 lbs_status lbs_setup_batch(int32_t G, const int32_t *isl_per_geom, const lbs_island *isl,
                            const int32_t *nodes, const lbs_options *opt, void *stream,
                            lbs_handle *out) {
@@ -1817,6 +1932,7 @@ lbs_status lbs_shape_vjp(lbs_handle h, const double *sigma, const double *A, con
     lbs_ctx &c = *h;
     Geometry &g = c.geo;
     if (g.G != 1) fail(LBS_ERR_UNSUPPORTED, "adjoint entry points serve single-geometry handles");
+    if (g.sampled) fail(LBS_ERR_UNSUPPORTED, "a sampled-curve handle has no shape coefficients");
     if (T < 0) fail(LBS_ERR_INVALID_ARG, "n_targets < 0");
     if (!sigma || !A || !lam_s || !dcoef || (T > 0 && (!w || !txyz)))
       fail(LBS_ERR_INVALID_ARG, "null pointer argument");

@@ -7,6 +7,27 @@
 
 namespace lbs {
 
+// Stereographic image xi = w / d, w = x1 + i x2, d = 1 - x3, of a curve
+// point and its first two parameter derivatives by the quotient rule.
+__device__ __forceinline__ void stereo_derivs(
+    double x0, double x1, double x2, double xt0, double xt1, double xt2,
+    double xtt0, double xtt1, double xtt2, double *xi, double *dxi,
+    double *ddxi) {
+  const double d = 1.0 - x2, id = 1.0 / d;
+  const double wr = x0, wi = x1, wtr = xt0, wti = xt1, wttr = xtt0,
+               wtti = xtt1;
+  const double z3t = xt2, z3tt = xtt2;
+  xi[0] = wr * id;
+  xi[1] = wi * id;
+  const double id2 = id * id, id3 = id2 * id;
+  dxi[0] = wtr * id + wr * z3t * id2;
+  dxi[1] = wti * id + wi * z3t * id2;
+  ddxi[0] = wttr * id + 2.0 * wtr * z3t * id2 + wr * z3tt * id2 +
+            2.0 * wr * z3t * z3t * id3;
+  ddxi[1] = wtti * id + 2.0 * wti * z3t * id2 + wi * z3tt * id2 +
+            2.0 * wi * z3t * z3t * id3;
+}
+
 // One thread per node.  Island k's node j sits at t = 2 pi j / N_k on the
 // curve x(t) = cos r c + sin r u(t), u = cos t e1 + sin t e2, e2 = e1 x c,
 // r(t) = r0 (1 + sum_n a_n cos nt + b_n sin nt).  Outputs x, and
@@ -64,20 +85,36 @@ __global__ void k_geometry(const lbs_island *__restrict__ isl,
   xyz[3 * i] = x0;
   xyz[3 * i + 1] = x1;
   xyz[3 * i + 2] = x2;
-  // stereographic image and derivatives
-  const double d = 1.0 - x2, id = 1.0 / d;
-  const double wr = x0, wi = x1, wtr = xt0, wti = xt1, wttr = xtt0,
-               wtti = xtt1;
-  const double z3t = xt2, z3tt = xtt2;
-  xi[2 * i] = wr * id;
-  xi[2 * i + 1] = wi * id;
-  const double id2 = id * id, id3 = id2 * id;
-  dxi[2 * i] = wtr * id + wr * z3t * id2;
-  dxi[2 * i + 1] = wti * id + wi * z3t * id2;
-  ddxi[2 * i] = wttr * id + 2.0 * wtr * z3t * id2 + wr * z3tt * id2 +
-                2.0 * wr * z3t * z3t * id3;
-  ddxi[2 * i + 1] = wtti * id + 2.0 * wti * z3t * id2 + wi * z3tt * id2 +
-                    2.0 * wi * z3t * z3t * id3;
+  stereo_derivs(x0, x1, x2, xt0, xt1, xt2, xtt0, xtt1, xtt2, xi + 2 * i,
+                dxi + 2 * i, ddxi + 2 * i);
+}
+
+// Nodes given as samples x, x', x'' (N x 3 each): copy x, and the
+// stereographic image with its derivatives.
+__global__ void k_geometry_sampled(int64_t N, const double *__restrict__ x,
+                                   const double *__restrict__ xt,
+                                   const double *__restrict__ xtt,
+                                   double *__restrict__ xyz,
+                                   double *__restrict__ xi,
+                                   double *__restrict__ dxi,
+                                   double *__restrict__ ddxi) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double *p = x + 3 * i, *q = xt + 3 * i, *r = xtt + 3 * i;
+  xyz[3 * i] = p[0];
+  xyz[3 * i + 1] = p[1];
+  xyz[3 * i + 2] = p[2];
+  stereo_derivs(p[0], p[1], p[2], q[0], q[1], q[2], r[0], r[1], r[2],
+                xi + 2 * i, dxi + 2 * i, ddxi + 2 * i);
+}
+
+void launch_geometry_sampled(int64_t N, const double *x, const double *xt,
+                             const double *xtt, double *xyz, double *xi,
+                             double *dxi, double *ddxi, hipStream_t s) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_geometry_sampled, dim3((unsigned)((N + 255) / 256)),
+                     dim3(256), 0, s, N, x, xt, xtt, xyz, xi, dxi, ddxi);
+  LBS_HIP(hipGetLastError());
 }
 
 void launch_geometry(const lbs_island *isl_dev, int M,

@@ -259,6 +259,8 @@ struct Geometry {
   // close-evaluation zone per island: cos of its angular radius (the
   // largest node distance from the centre plus ten node spacings)
   std::vector<double> zone_cos;
+  bool sampled = false;              // nodes given as samples (no shape
+                                     // coefficients)
 };
 
 // Targets of an evaluation that lie in the close zone of one or more
@@ -304,11 +306,16 @@ constexpr int kLogChunk = 64;  // far-list entries per wave step
 // CUs at the kernel's occupancy of 4 waves per SIMD.
 constexpr int kM2LGroups = 1024;
 
+void set_last_error(const std::string &msg);  // message of lbs_last_error
+
 // ----- launchers (HIP files) ------------------------------------------
 void build_tables(Tables &t, int P, hipStream_t s);
 void launch_geometry(const lbs_island *isl_dev, int M, const int64_t *offs_dev,
                      const int32_t *island_dev, int64_t N, double *xyz,
                      double *xi, double *dxi, double *ddxi, hipStream_t s);
+void launch_geometry_sampled(int64_t N, const double *x, const double *xt,
+                             const double *xtt, double *xyz, double *xi,
+                             double *dxi, double *ddxi, hipStream_t s);
 void launch_node_coeffs(int64_t N, const int32_t *island, const double *sign,
                         const int64_t *offs, const double *xi,
                         const double *dxi, const double *ddxi, double *qfac,

@@ -148,10 +148,19 @@ def load():
                                  ctypes.c_double, vp, ctypes.POINTER(Options),
                                  ctypes.POINTER(TuneEntry), ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_int32)]
+    lib.lbs_setup_sampled.argtypes = [c_double_p, c_double_p, c_double_p,
+                                      c_double_p, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(Options), vp,
+                                      ctypes.POINTER(H)]
+    lib.lbs_resample_curve_host.argtypes = [
+        ctypes.c_int32, c_double_p, c_double_p, ctypes.c_int32,
+        ctypes.c_int32, c_double_p, c_double_p, c_double_p, c_double_p]
     lib.lbs_refine_tolerances_host.argtypes = [
         ctypes.c_int32, c_double_p, c_double_p, ctypes.c_double,
         ctypes.c_double, c_double_p, ctypes.POINTER(ctypes.c_int32)]
-    for name in ("lbs_refine_tolerances_host", "lbs_setup", "lbs_sizes",
+    for name in ("lbs_refine_tolerances_host", "lbs_setup_sampled",
+                 "lbs_resample_curve_host", "lbs_setup", "lbs_sizes",
                  "lbs_nodes", "lbs_matvec", "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
                  "lbs_stage_timing", "lbs_stage_times", "lbs_setup_batch",
                  "lbs_batch_info", "lbs_eval_batch",
@@ -211,16 +220,37 @@ def _rhs(t, n):
     return t.shape[0]
 
 
-class Solver:
-    """Island geometries on the GPU (lbs_setup / lbs_setup_batch ...
-    lbs_destroy).  `islands` is one island set, or a list of them for a
-    batch handle (geometry-major node and island numbering)."""
+def _host(a, shape):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != shape:
+        raise ValueError("shape %s, expected %s" % (a.shape, shape))
+    return a
 
-    def __init__(self, islands, nodes=None, options=None, **kw):
+
+class Solver:
+    """Island geometries on the GPU (lbs_setup / lbs_setup_batch /
+    lbs_setup_sampled ... lbs_destroy).  `islands` is one island set, or a
+    list of them for a batch handle (geometry-major node and island
+    numbering); or pass islands=None and samples=(x, x_t, x_tt, centers,
+    nodes_per_curve) (host arrays) for sampled curves."""
+
+    def __init__(self, islands=None, nodes=None, options=None, samples=None,
+                 **kw):
         lib = load()
         self.options = options if options is not None else default_options(**kw)
         h = ctypes.c_void_p()
-        if isinstance(islands, (list, tuple)):
+        if samples is not None:
+            x, xt, xtt, cen, nn = samples
+            m = len(nn)
+            n = int(sum(int(v) for v in nn))
+            keep = [_host(x, (n, 3)), _host(xt, (n, 3)), _host(xtt, (n, 3)),
+                    _host(cen, (m, 3))]
+            cn = (ctypes.c_int32 * m)(*[int(v) for v in nn])
+            _check(lib.lbs_setup_sampled(
+                *[k.ctypes.data_as(c_double_p) for k in keep], m, cn,
+                ctypes.byref(self.options), _stream(), ctypes.byref(h)))
+        elif isinstance(islands, (list, tuple)):
             sets = list(islands)
             g = len(sets)
             per = (ctypes.c_int32 * g)(*[len(s.r0) for s in sets])
@@ -421,6 +451,24 @@ def check_tree_host(x, y, leaf_max):
         x.ctypes.data_as(c_double_p), y.ctypes.data_as(c_double_p),
         x.shape[0], int(leaf_max), ctypes.byref(bad), ctypes.byref(st)))
     return bad.value, st.as_dict()
+
+
+def resample_curve(x, center, n_out, n_modes=0):
+    """Host-only arclength resampling (lbs_resample_curve_host):
+    (x, x_t, x_tt, L) at n_out nodes."""
+    import numpy as np
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    c = np.ascontiguousarray(center, dtype=np.float64)
+    xo = np.empty((n_out, 3))
+    xto = np.empty((n_out, 3))
+    xtto = np.empty((n_out, 3))
+    L = ctypes.c_double()
+    _check(load().lbs_resample_curve_host(
+        x.shape[0], x.ctypes.data_as(c_double_p), c.ctypes.data_as(c_double_p),
+        int(n_modes), int(n_out), xo.ctypes.data_as(c_double_p),
+        xto.ctypes.data_as(c_double_p), xtto.ctypes.data_as(c_double_p),
+        ctypes.byref(L)))
+    return xo, xto, xtto, L.value
 
 
 def refine_tolerances(rn2, bn2, tol, inner_tol):
