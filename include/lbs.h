@@ -264,6 +264,31 @@ lbs_status lbs_eval_batch(lbs_handle h, int32_t nrhs, const double *sigma,
                           const int64_t *target_offsets_host,
                           const double *xyz_targets, double *u, void *stream);
 
+/* ----------------------------------------------------------- point vortices
+ * Section 6, Example 2 places point vortices of strengths Gamma_j at points
+ * v_j of the domain and decomposes the stream function as
+ *   psi = psi* + sum_j Gamma_j G(x, v_j),
+ * G the generalized fundamental solution (Section 1.1, eq.
+ * eqn:greens_func), where psi* solves the Dirichlet problem with the data
+ * g - sum_j Gamma_j G(x, v_j).  The flow is lbs_vortex_data -> lbs_solve ->
+ * lbs_eval -> lbs_vortex_field.  The vortex sums are direct (FP64,
+ * O(points x vortices)).  xyz_vortices: device (n_vortices x 3) unit
+ * vectors; gamma: device (n_vortices x nrhs), one column of strengths per
+ * right-hand side.  Single-geometry handles. */
+
+/* g_star (N x nrhs) = g - sum_j Gamma_j G(x_i, v_j) at the nodes (g and
+ * g_star may be the same array). */
+lbs_status lbs_vortex_data(lbs_handle h, int32_t nrhs, const double *g,
+                           int32_t n_vortices, const double *xyz_vortices,
+                           const double *gamma, double *g_star, void *stream);
+
+/* u (n_targets x nrhs) += sum_j Gamma_j G(x_t, v_j) at sphere targets
+ * xyz_targets (n_targets x 3); a target on a vortex gives Inf. */
+lbs_status lbs_vortex_field(lbs_handle h, int32_t nrhs, int32_t n_vortices,
+                            const double *xyz_vortices, const double *gamma,
+                            int64_t n_targets, const double *xyz_targets,
+                            double *u, void *stream);
+
 /* ---------------------------------------------------------------- adjoint
  * Derivatives of a scalar L(u) of the solution u = T x at targets, where
  * x = [sigma; A] solves the system of eqs. matrix_eqns with right-hand side

@@ -412,15 +412,15 @@ void ensure_ws(lbs_ctx &c, int nrhs) {
               kPlog);
 }
 
-// y = ident x + K x for the node rows (ld x / y given)
-void apply_K(lbs_ctx &c, int prec, int nrhs, const double *x, int64_t ldx,
-             double *y, int64_t ldy, double ident, hipStream_t s) {
+// y = ident x + K x for the node rows (ld x / y given), with the FMM
+// buffers of workspace w (sized for nrhs columns by the caller)
+void apply_K_ws(lbs_ctx &c, Workspace &w, int prec, int nrhs, const double *x, int64_t ldx,
+                double *y, int64_t ldy, double ident, hipStream_t s) {
   Geometry &g = c.geo;
-  ensure_ws(c, nrhs);
   Assembly as;
   as.sigma = x;
   as.tau = g.tau.p;
-  as.gamma = c.ws.gam.p;
+  as.gamma = w.gam.p;
   as.geo = g.node_geo.p;
   as.G = g.G;
   as.ident = ident;
@@ -430,56 +430,74 @@ void apply_K(lbs_ctx &c, int prec, int nrhs, const double *x, int64_t ldx,
   GammaFused gf;
   gf.gw_t = g.gw_t.p;
   gf.gl_ptr = g.gleaf_ptr.p;
-  gf.gamma = c.ws.gam.p;
+  gf.gamma = w.gam.p;
   gf.G = g.G;
   gf.nchunk = g.gleaf_chunks;
   if (c.opt.matvec == LBS_MATVEC_DIRECT) {
     {
-      TimerScope ts(c.ws.timer, ST_GAMMA, s);
-      launch_segdots(c.seg_nodes, nrhs, 1, g.gw.p, 0, 0, x, ldx, c.ws.gam.p,
-                     c.ws.red.p, s);
+      TimerScope ts(w.timer, ST_GAMMA, s);
+      launch_segdots(c.seg_nodes, nrhs, 1, g.gw.p, 0, 0, x, ldx, w.gam.p,
+                     w.red.p, s);
     }
-    TimerScope ts(c.ws.timer, ST_LEAF, s);
+    TimerScope ts(w.timer, ST_LEAF, s);
     direct_apply64(g.N, g.xi.p, g.qfac.p, x, ldx, nrhs, y, ldy, as, s);
   } else if (prec == LBS_FP64) {
-    fmm_apply64(c.plan, c.tab64, c.ws, g.qfac_t.p, x, ldx, nrhs, y, ldy, 1.0,
+    fmm_apply64(c.plan, c.tab64, w, g.qfac_t.p, x, ldx, nrhs, y, ldy, 1.0,
                 as, s, &gf);
   } else {
-    fmm_apply32(c.plan, c.tab32, c.ws, g.qfac_t.p, x, ldx, nrhs, y, ldy, 1.0,
+    fmm_apply32(c.plan, c.tab32, w, g.qfac_t.p, x, ldx, nrhs, y, ldy, 1.0,
                 as, s, &gf);
   }
 }
 
+void apply_K(lbs_ctx &c, int prec, int nrhs, const double *x, int64_t ldx,
+             double *y, int64_t ldy, double ident, hipStream_t s) {
+  ensure_ws(c, nrhs);
+  apply_K_ws(c, c.ws, prec, nrhs, x, ldx, y, ldy, ident, s);
+}
+
 // y = P^-1 A x = x + P^-1 [K x_s; 0]   (x, y: nrhs columns of length N + M)
-void apply_precond_op(lbs_ctx &c, int prec, int nrhs, const double *x,
-                      double *y, hipStream_t s) {
+void apply_precond_op_ws(lbs_ctx &c, Workspace &w, int prec, int nrhs, const double *x,
+                         double *y, hipStream_t s) {
   Geometry &g = c.geo;
   const int64_t n = g.N + g.M;
-  apply_K(c, prec, nrhs, x, n, y, n, 0.0, s);
+  apply_K_ws(c, w, prec, nrhs, x, n, y, n, 0.0, s);
   {
-    TimerScope ts(c.ws.timer, ST_CONSTRAINT, s);
-    launch_island_sums(g, y, n, nrhs, c.ws.tmpM.p, g.M, s);
-    launch_gemv_blocks(g, c.ws.tmpM.p, g.M, nrhs, y + g.N, n, -1.0, s);
+    TimerScope ts(w.timer, ST_CONSTRAINT, s);
+    launch_island_sums(g, y, n, nrhs, w.tmpM.p, g.M, s);
+    launch_gemv_blocks(g, w.tmpM.p, g.M, nrhs, y + g.N, n, -1.0, s);
   }
   {
-    TimerScope ts(c.ws.timer, ST_LOGSRC, s);
-    launch_logsrc_apply(g, c.ws, y + g.N, n, nrhs, y, n, -1.0, s);
+    TimerScope ts(w.timer, ST_LOGSRC, s);
+    launch_logsrc_apply(g, w, y + g.N, n, nrhs, y, n, -1.0, s);
   }
   launch_axpby(n * nrhs, 1.0, x, 1.0, y, s);
 }
 
+void apply_precond_op(lbs_ctx &c, int prec, int nrhs, const double *x,
+                      double *y, hipStream_t s) {
+  ensure_ws(c, nrhs);
+  apply_precond_op_ws(c, c.ws, prec, nrhs, x, y, s);
+}
+
 // [y_s; y_a] = [ (I+K) x_s + E x_a ; F x_s + D x_a ]
-void apply_system(lbs_ctx &c, int prec, int nrhs, const double *x, double *y,
-                  hipStream_t s) {
+void apply_system_ws(lbs_ctx &c, Workspace &w, int prec, int nrhs, const double *x, double *y,
+                     hipStream_t s) {
   Geometry &g = c.geo;
   const int64_t n = g.N + g.M;
-  apply_K(c, prec, nrhs, x, n, y, n, 1.0, s);
+  apply_K_ws(c, w, prec, nrhs, x, n, y, n, 1.0, s);
   {
-    TimerScope ts(c.ws.timer, ST_LOGSRC, s);
-    launch_logsrc_apply(g, c.ws, x + g.N, n, nrhs, y, n, 1.0, s);
+    TimerScope ts(w.timer, ST_LOGSRC, s);
+    launch_logsrc_apply(g, w, x + g.N, n, nrhs, y, n, 1.0, s);
   }
-  TimerScope ts(c.ws.timer, ST_CONSTRAINT, s);
+  TimerScope ts(w.timer, ST_CONSTRAINT, s);
   launch_constraint_rows(g, x, n, x + g.N, n, nrhs, y + g.N, n, s);
+}
+
+void apply_system(lbs_ctx &c, int prec, int nrhs, const double *x, double *y,
+                  hipStream_t s) {
+  ensure_ws(c, nrhs);
+  apply_system_ws(c, c.ws, prec, nrhs, x, y, s);
 }
 
 // b = P^-1 [2 g; 0] for nrhs columns (g: ld N; b: ld N + M)
@@ -1595,6 +1613,7 @@ void eval_T_field(lbs_ctx &c, EvalPlan &ep, const double *w, double *pcw, double
 
 namespace lbs {
 void set_last_error(const std::string &msg) { g_err = msg; }
+
 }  // namespace lbs
 
 extern "C" {
@@ -1971,6 +1990,25 @@ lbs_status lbs_shape_vjp(lbs_handle h, const double *sigma, const double *A, con
   });
 }
 
+// Vortex positions: finite unit vectors (host check of a device array).
+void check_vortices(int32_t nv, const double *xyz_v, const double *gamma, int nrhs,
+                    hipStream_t s) {
+  if (nv < 1 || nv > (1 << 24)) fail(LBS_ERR_INVALID_ARG, "n_vortices outside [1, 2^24]");
+  if (!xyz_v || !gamma) fail(LBS_ERR_INVALID_ARG, "null pointer argument");
+  std::vector<double> v(3 * (size_t)nv), gm((size_t)nv * nrhs);
+  LBS_HIP(hipMemcpyAsync(v.data(), xyz_v, v.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipMemcpyAsync(gm.data(), gamma, gm.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipStreamSynchronize(s));
+  for (int32_t j = 0; j < nv; ++j) {
+    const double *p = &v[3 * (size_t)j];
+    if (!std::isfinite(p[0]) || !std::isfinite(p[1]) || !std::isfinite(p[2]) ||
+        std::fabs(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] - 1.0) > 1e-9)
+      fail(LBS_ERR_GEOMETRY, "vortex " + std::to_string(j) + " is not a finite unit vector");
+  }
+  for (double x : gm)
+    if (!std::isfinite(x)) fail(LBS_ERR_NOT_FINITE, "vortex strength is not finite");
+}
+
 lbs_status lbs_set_orders(lbs_handle h, int32_t p64, int32_t p32, void *stream) {
   return guard([&] {
     check_handle(h);
@@ -1993,6 +2031,37 @@ lbs_status lbs_set_orders(lbs_handle h, int32_t p64, int32_t p32, void *stream) 
     c.graphs.clear();
     c.graphs.sig.clear();
     LBS_HIP(hipStreamSynchronize(s));
+  });
+}
+
+lbs_status lbs_vortex_data(lbs_handle h, int32_t nrhs, const double *g, int32_t nv,
+                           const double *xyz_v, const double *gamma, double *g_star,
+                           void *stream) {
+  return guard([&] {
+    check_handle(h);
+    if (h->geo.G != 1) fail(LBS_ERR_UNSUPPORTED, "point vortices serve single-geometry handles");
+    if (nrhs < 1 || nrhs > 65535) fail(LBS_ERR_INVALID_ARG, "nrhs outside [1, 65535]");
+    if (!g || !g_star) fail(LBS_ERR_INVALID_ARG, "null pointer argument");
+    hipStream_t s = (hipStream_t)stream;
+    check_vortices(nv, xyz_v, gamma, nrhs, s);
+    const Geometry &geo = h->geo;
+    launch_vortex_field(geo.N, geo.xyz.p, nv, xyz_v, gamma, nrhs, -1.0, g, geo.N, 1.0, g_star,
+                        geo.N, s);
+  });
+}
+
+lbs_status lbs_vortex_field(lbs_handle h, int32_t nrhs, int32_t nv, const double *xyz_v,
+                            const double *gamma, int64_t T, const double *txyz, double *u,
+                            void *stream) {
+  return guard([&] {
+    check_handle(h);
+    if (nrhs < 1 || nrhs > 65535) fail(LBS_ERR_INVALID_ARG, "nrhs outside [1, 65535]");
+    if (T < 0) fail(LBS_ERR_INVALID_ARG, "n_targets < 0");
+    if (T == 0) return;
+    if (!txyz || !u) fail(LBS_ERR_INVALID_ARG, "null pointer argument");
+    hipStream_t s = (hipStream_t)stream;
+    check_vortices(nv, xyz_v, gamma, nrhs, s);
+    launch_vortex_field(T, txyz, nv, xyz_v, gamma, nrhs, 1.0, u, T, 1.0, u, T, s);
   });
 }
 

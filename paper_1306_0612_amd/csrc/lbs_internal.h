@@ -30,18 +30,27 @@ struct ApiError {
   } while (0)
 
 // Device buffer with RAII release.
+// A view (view()) borrows memory it does not free.
 template <typename T>
 struct DBuf {
   T *p = nullptr;
   size_t n = 0;
+  bool own = true;
   DBuf() = default;
   DBuf(const DBuf &) = delete;
   DBuf &operator=(const DBuf &) = delete;
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && own) (void)hipFree(p);
     p = nullptr;
     n = 0;
+    own = true;
+  }
+  void view(T *q, size_t count) {
+    release();
+    p = q;
+    n = count;
+    own = false;
   }
   void alloc(size_t count) {
     release();
@@ -381,6 +390,13 @@ void direct_eval64(int64_t N, const double *xi, const double *qfac,
 void launch_close_eval(const Geometry &g, const ClosePlan &cp, int nrhs,
                        const double *sigma, int64_t ldx, double *V, double *u,
                        int64_t ldu, hipStream_t s);
+
+// out = beta in + alpha sum_j gamma_j G(x, v_j) at n points x (vortex.hip;
+// gamma: nv x nrhs; in, out: ld per column; in may be null)
+void launch_vortex_field(int64_t n, const double *x, int nv, const double *v,
+                         const double *gamma, int nrhs, double alpha,
+                         const double *in, int64_t ldi, double beta,
+                         double *out, int64_t ldo, hipStream_t s);
 
 // dot products: out[r] = sum_i a[r*lda + i] * b[r*ldb + i], i < n
 void launch_dots(int64_t n, int nrhs, const double *a, int64_t lda,

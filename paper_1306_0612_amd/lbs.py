@@ -156,10 +156,15 @@ def load():
     lib.lbs_resample_curve_host.argtypes = [
         ctypes.c_int32, c_double_p, c_double_p, ctypes.c_int32,
         ctypes.c_int32, c_double_p, c_double_p, c_double_p, c_double_p]
+    lib.lbs_vortex_data.argtypes = [H, ctypes.c_int32, vp, ctypes.c_int32,
+                                    vp, vp, vp, vp]
+    lib.lbs_vortex_field.argtypes = [H, ctypes.c_int32, ctypes.c_int32, vp,
+                                     vp, ctypes.c_int64, vp, vp, vp]
     lib.lbs_refine_tolerances_host.argtypes = [
         ctypes.c_int32, c_double_p, c_double_p, ctypes.c_double,
         ctypes.c_double, c_double_p, ctypes.POINTER(ctypes.c_int32)]
     for name in ("lbs_refine_tolerances_host", "lbs_setup_sampled",
+                 "lbs_vortex_data", "lbs_vortex_field",
                  "lbs_resample_curve_host", "lbs_setup", "lbs_sizes",
                  "lbs_nodes", "lbs_matvec", "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
                  "lbs_stage_timing", "lbs_stage_times", "lbs_setup_batch",
@@ -400,6 +405,29 @@ class Solver:
                                     _dev(lam_s), t, _dev(targets), _dev(w),
                                     _dev(out), _stream()))
         return out
+
+    # ------------------------------------------------------ point vortices
+    def vortex_data(self, g, xyz_v, gamma):
+        """g - sum_j gamma_j G(x, v_j) at the nodes (lbs_vortex_data);
+        gamma: (nv,) or (nrhs, nv) like g's columns."""
+        nrhs = _rhs(g, self.n_nodes)
+        nv = xyz_v.shape[0]
+        _rhs(gamma, nv)
+        out = torch.empty_like(g)
+        _check(load().lbs_vortex_data(self._h, nrhs, _dev(g), nv, _dev(xyz_v),
+                                      _dev(gamma), _dev(out), _stream()))
+        return out
+
+    def vortex_field(self, u, xyz_v, gamma, targets):
+        """u += sum_j gamma_j G(x_t, v_j) in place (lbs_vortex_field)."""
+        t = targets.shape[0]
+        nrhs = _rhs(u, t)
+        nv = xyz_v.shape[0]
+        _rhs(gamma, nv)
+        _check(load().lbs_vortex_field(self._h, nrhs, nv, _dev(xyz_v),
+                                       _dev(gamma), t, _dev(targets), _dev(u),
+                                       _stream()))
+        return u
 
     def set_orders(self, p64, p32):
         """Change the expansion orders without rebuilding the tree."""

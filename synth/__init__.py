@@ -9,9 +9,10 @@ besides sampling is the closed-form boundary data of the paper's examples
 from .islands import (IslandSet, cap_island, star_islands, config_islands,
                       batch_geometries, deep_tree_islands, CONFIGS)
 from .data import (exact_harmonic, paper_data_coeffs, random_data_coeffs,
-                   sphere_targets, random_vector, near_curve_targets)
+                   sphere_targets, random_vector, near_curve_targets,
+                   point_vortices)
 
 __all__ = ["IslandSet", "cap_island", "star_islands", "config_islands",
            "batch_geometries", "deep_tree_islands", "CONFIGS", "exact_harmonic",
            "paper_data_coeffs", "random_data_coeffs", "sphere_targets",
-           "random_vector", "near_curve_targets"]
+           "random_vector", "near_curve_targets", "point_vortices"]

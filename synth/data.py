@@ -115,3 +115,12 @@ def near_curve_targets(islands, seed, dists, per=3):
             pts.append(np.cos(rr)[:, None] * c + np.sin(rr)[:, None] * u)
             tag += [d] * per
     return np.concatenate(pts), np.array(tag)
+
+
+def point_vortices(seed, count, islands):
+    """Vortex positions in the domain (sphere_targets' rejection rule) and
+    strengths uniform on (-2 pi, 2 pi), the range of Section 6, Example 2."""
+    xyz = sphere_targets(seed, count, islands)
+    gamma = np.random.default_rng(seed + 1).uniform(-2 * np.pi, 2 * np.pi,
+                                                    count)
+    return xyz, gamma
