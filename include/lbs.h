@@ -226,6 +226,22 @@ lbs_status lbs_matvec(lbs_handle h, int32_t op, int32_t precision,
                       int32_t nrhs, const double *x, double *y,
                       void *stream);
 
+/* lbs_matvec for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same operators and kernels (op LBS_OP_IPLUSK, K, SYSTEM
+ * or PRECOND; LBS_OP_IPLUSK_T returns LBS_ERR_UNSUPPORTED), with every
+ * buffer beyond x and y (FMM strengths and expansions, partial sums,
+ * completion counters, reduction space) in one static device array of
+ * 128 MiB per GPU, which each GPU the library runs on holds until the
+ * process ends.  An application that needs more (about 62 MB for one FP64
+ * column at 1,024,000 nodes, 21 MB mixed) returns LBS_ERR_UNSUPPORTED.
+ * The call allocates nothing.  Every call on a GPU shares that GPU's
+ * array and leaves its contents behind: calls that overlap on one GPU (on
+ * different streams or host threads) race. */
+lbs_status lbs_matvec_noalloc(lbs_handle h, int32_t op, int32_t precision,
+                              int32_t nrhs, const double *x, double *y,
+                              void *stream);
+
 /* Solve the system for Dirichlet data g (device, N x nrhs, API order):
  * GMRES(restart) on P^-1 A [sigma; A] = P^-1 [2g; 0] from x0 = 0 until the
  * preconditioned relative residual is <= tol (Section 5, Section 6); with

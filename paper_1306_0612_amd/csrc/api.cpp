@@ -11,6 +11,7 @@
 #include <memory>
 #include <tuple>
 #include <string>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -1614,6 +1615,88 @@ void eval_T_field(lbs_ctx &c, EvalPlan &ep, const double *w, double *pcw, double
 namespace lbs {
 void set_last_error(const std::string &msg) { g_err = msg; }
 
+// Workspace of one operator application (op, precision, nrhs) carved from
+// base in 256-byte aligned pieces (base = nullptr: sizes only); returns the
+// bytes it takes.  The same buffers Workspace::ensure allocates, for the
+// precision in use only.
+size_t carve_workspace(const lbs_ctx &c, int op, int prec, int nrhs, char *base,
+                       Workspace &w) {
+  const DevPlan &pl = c.plan;
+  const Geometry &g = c.geo;
+  size_t off = 0;
+  auto take = [&](auto &buf, size_t count) {
+    using T = std::remove_pointer_t<decltype(buf.p)>;
+    off = (off + 255) & ~(size_t)255;
+    if (base) buf.view((T *)(base + off), count);
+    off += count * sizeof(T);
+  };
+  const size_t R = (size_t)nrhs;
+  if (c.opt.matvec != LBS_MATVEC_DIRECT) {
+    if (prec == LBS_FP64) {
+      take(w.pstr64, (size_t)pl.ns * R * 2);
+      take(w.mult64, (size_t)pl.nbox * c.opt.p64 * R * 2);
+      take(w.loc64, (size_t)pl.nbox * c.opt.p64 * R * 2);
+    } else {
+      take(w.pstr32, (size_t)pl.ns * R * 2);
+      take(w.mult32, (size_t)pl.nbox * c.opt.p32 * R * 2);
+      take(w.loc32, (size_t)pl.nbox * c.opt.p32 * R * 2);
+    }
+    const size_t nls = (size_t)std::max(pl.n_leaf_s, 1);
+    take(w.gpart, nls * R);
+    take(w.gcsum, ((nls + 2047) / 2048) * g.G * R);
+    take(w.gcnt, (size_t)g.G * R);
+  }
+  take(w.gam, R * g.G);
+  const size_t chunks = (size_t)((g.N + g.M) / 2048 + 2 * g.G + 4);
+  take(w.red, std::max<size_t>((size_t)512 * std::max<size_t>(R, 128), (size_t)128 * R * chunks));
+  if (op == LBS_OP_SYSTEM || op == LBS_OP_PRECOND) {
+    take(w.tmpM, (size_t)std::max(g.M, 1) * R);
+    take(w.logL, (size_t)std::max(g.M, 1) * R * (2 * (kPlog + 1) + 2));
+  }
+  return off;
+}
+
+// lbs_matvec with every buffer beyond x and y in the caller's scratch
+// memory (bytes at base, device), no allocation.
+lbs_status matvec_in_scratch(lbs_handle h, int32_t op, int32_t prec, int32_t nrhs,
+                             const double *x, double *y, void *stream, char *base,
+                             size_t bytes) {
+  return guard([&] {
+    check_handle(h);
+    if (!x || !y) fail(LBS_ERR_INVALID_ARG, "x or y is NULL");
+    if (nrhs < 1 || nrhs > 65535) fail(LBS_ERR_INVALID_ARG, "nrhs outside [1, 65535]");
+    if (prec != LBS_FP64 && prec != LBS_MIXED) fail(LBS_ERR_INVALID_ARG, "bad precision");
+    if (op == LBS_OP_IPLUSK_T)
+      fail(LBS_ERR_UNSUPPORTED, "the transposed operator is not served without allocation");
+    if (op != LBS_OP_IPLUSK && op != LBS_OP_K && op != LBS_OP_SYSTEM && op != LBS_OP_PRECOND)
+      fail(LBS_ERR_INVALID_ARG, "bad op");
+    lbs_ctx &c = *h;
+    Workspace w;
+    const size_t need = carve_workspace(c, op, prec, nrhs, nullptr, w);
+    if (need > bytes)
+      fail(LBS_ERR_UNSUPPORTED, "this application needs " + std::to_string(need) +
+                                    " bytes of scratch; the static scratch holds " +
+                                    std::to_string(bytes));
+    carve_workspace(c, op, prec, nrhs, base, w);
+    hipStream_t s = (hipStream_t)stream;
+    // the correction sums' completion counters start at zero
+    if (w.gcnt.p) launch_fill_int((int64_t)w.gcnt.n, 0, w.gcnt.p, s);
+    switch (op) {
+      case LBS_OP_IPLUSK:
+        apply_K_ws(c, w, prec, nrhs, x, c.geo.N, y, c.geo.N, 1.0, s);
+        break;
+      case LBS_OP_K:
+        apply_K_ws(c, w, prec, nrhs, x, c.geo.N, y, c.geo.N, 0.0, s);
+        break;
+      case LBS_OP_SYSTEM:
+        apply_system_ws(c, w, prec, nrhs, x, y, s);
+        break;
+      default:
+        apply_precond_op_ws(c, w, prec, nrhs, x, y, s);
+        break;
+    }
+  });
+}
 }  // namespace lbs
 
 extern "C" {

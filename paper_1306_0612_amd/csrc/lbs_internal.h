@@ -316,6 +316,11 @@ constexpr int kLogChunk = 64;  // far-list entries per wave step
 constexpr int kM2LGroups = 1024;
 
 void set_last_error(const std::string &msg);  // message of lbs_last_error
+// lbs_matvec with its scratch buffers in `bytes` of device memory at base
+// (api.cpp; the entry point without allocation passes its static scratch)
+lbs_status matvec_in_scratch(lbs_handle h, int32_t op, int32_t prec, int32_t nrhs,
+                             const double *x, double *y, void *stream, char *base,
+                             size_t bytes);
 
 // ----- launchers (HIP files) ------------------------------------------
 void build_tables(Tables &t, int P, hipStream_t s);

@@ -156,6 +156,8 @@ def load():
     lib.lbs_resample_curve_host.argtypes = [
         ctypes.c_int32, c_double_p, c_double_p, ctypes.c_int32,
         ctypes.c_int32, c_double_p, c_double_p, c_double_p, c_double_p]
+    lib.lbs_matvec_noalloc.argtypes = [H, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, vp, vp, vp]
     lib.lbs_vortex_data.argtypes = [H, ctypes.c_int32, vp, ctypes.c_int32,
                                     vp, vp, vp, vp]
     lib.lbs_vortex_field.argtypes = [H, ctypes.c_int32, ctypes.c_int32, vp,
@@ -164,7 +166,7 @@ def load():
         ctypes.c_int32, c_double_p, c_double_p, ctypes.c_double,
         ctypes.c_double, c_double_p, ctypes.POINTER(ctypes.c_int32)]
     for name in ("lbs_refine_tolerances_host", "lbs_setup_sampled",
-                 "lbs_vortex_data", "lbs_vortex_field",
+                 "lbs_vortex_data", "lbs_vortex_field", "lbs_matvec_noalloc",
                  "lbs_resample_curve_host", "lbs_setup", "lbs_sizes",
                  "lbs_nodes", "lbs_matvec", "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
                  "lbs_stage_timing", "lbs_stage_times", "lbs_setup_batch",
@@ -318,6 +320,17 @@ class Solver:
         y = torch.empty_like(x) if out is None else out
         _check(load().lbs_matvec(self._h, OPS[op], PRECISIONS[precision], nrhs,
                                  _dev(x), _dev(y), _stream()))
+        return y
+
+    def matvec_noalloc(self, x, op="iplusk", precision="fp64", out=None):
+        """lbs_matvec_noalloc: as matvec, scratch in the static array."""
+        n = self.n_nodes + (self.n_islands if op in ("system", "precond")
+                            else 0)
+        nrhs = _rhs(x, n)
+        y = torch.empty_like(x) if out is None else out
+        _check(load().lbs_matvec_noalloc(self._h, OPS[op],
+                                         PRECISIONS[precision], nrhs, _dev(x),
+                                         _dev(y), _stream()))
         return y
 
     def solve(self, g, tol=1e-12, precision="fp64", check=True):
