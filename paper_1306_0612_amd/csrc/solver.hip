@@ -403,109 +403,229 @@ void launch_build_schur(const Geometry &g, double *S, hipStream_t s) {
   LBS_HIP(hipGetLastError());
 }
 
-// Gauss-Jordan elimination with partial pivoting on [S_g | I] for every
-// geometry's block at once; step c touches the blocks with M_g > c.
-// Grid: blockIdx.z = geometry.
-__device__ __forceinline__ bool gj_block(const int32_t *gisl, int g, int c,
-                                         int &Mg) {
-  Mg = gisl[g + 1] - gisl[g];
-  return c < Mg;
-}
+// Blocked Gauss-Jordan inversion with partial pivoting of every geometry's
+// block S_g at once, on the augmented rows [A | B] = [S_g | I] (B becomes
+// S_g^-1).  Panel J = columns j0 .. j0 + nb - 1 (nb <= kGJ):
+//  1. k_gj_panel (one work-group per geometry): copy the column block
+//     A[:, J] column-major twice (P, C), factor P[j0:, :] = Pi L U by
+//     partial pivoting (the row swaps applied to C as well), and form
+//     Binv = (L U)^-1 of the nb x nb pivot block;
+//  2. k_gj_swap: apply the panel's row swaps to the other columns of
+//     [A | B];
+//  3. k_gj_w: W = Binv [A | B][J, :] (the new pivot rows);
+//  4. k_gj_update: rows J <- W, every other row i -= C_i W (C_i: row i of
+//     the swapped column block, its elimination factors).
+// The columns of A before the panel are identity columns already and are
+// left alone; the update is a rank-nb product over the remaining columns
+// (2 M_g^3 flops in all).  Grid z = geometry; geometries with M_g <= j0
+// return at once.
+constexpr int kGJ = 32;
 
-__global__ void __launch_bounds__(256)
-    k_gj_pivot(int c, const int32_t *__restrict__ gisl,
-               const int64_t *__restrict__ gsinv,
-               const double *__restrict__ A, int *__restrict__ piv) {
-  __shared__ double bv[256];
-  __shared__ int bi[256];
-  const int g = blockIdx.z;
-  int Mg;
-  if (!gj_block(gisl, g, c, Mg)) return;
+__global__ void __launch_bounds__(1024)
+    k_gj_panel(int j0, const int32_t *__restrict__ gisl,
+               const int64_t *__restrict__ gsinv, const double *__restrict__ A,
+               double *__restrict__ Pc, double *__restrict__ C,
+               int *__restrict__ piv, double *__restrict__ Binv, int maxM) {
+  __shared__ double bv[16];
+  __shared__ int bi[17];
+  __shared__ double prow[kGJ];
+  __shared__ double lu[kGJ][kGJ + 1];
+  const int g = blockIdx.x;
+  const int Mg = gisl[g + 1] - gisl[g];
+  if (j0 >= Mg) return;
+  const int nb = min(kGJ, Mg - j0);
+  const int tid = threadIdx.x;
   const double *Ag = A + gsinv[g];
-  double best = -1.0;
-  int at = c;
-  for (int r = c + threadIdx.x; r < Mg; r += 256) {
-    double v = fabs(Ag[(int64_t)r * Mg + c]);
-    if (v > best) { best = v; at = r; }
+  // the column block, column-major (entry (r, k) at k maxM + r), twice: P
+  // is factored, C keeps the values (both get the row swaps)
+  double *P = Pc + (int64_t)g * kGJ * maxM;
+  double *Cg = C + (int64_t)g * kGJ * maxM;
+  for (int64_t e = tid; e < (int64_t)Mg * nb; e += 1024) {
+    const int r = (int)(e / nb), k = (int)(e % nb);
+    const double v = Ag[(int64_t)r * Mg + j0 + k];
+    P[(int64_t)k * maxM + r] = v;
+    Cg[(int64_t)k * maxM + r] = v;
   }
-  bv[threadIdx.x] = best;
-  bi[threadIdx.x] = at;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      double o = bv[threadIdx.x + w];
-      int oi = bi[threadIdx.x + w];
-      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
-        bv[threadIdx.x] = o;
-        bi[threadIdx.x] = oi;
+  for (int k = 0; k < nb; ++k) {
+    const int c = j0 + k;
+    const double *Pk = P + (int64_t)k * maxM;
+    double best = -1.0;
+    int at = c;
+    for (int r = c + tid; r < Mg; r += 1024) {
+      const double v = fabs(Pk[r]);
+      if (v > best) {
+        best = v;
+        at = r;
       }
+    }
+    // largest |P[r][k]| (smallest r on ties): within each wave by
+    // shuffles, then across the 16 waves by the first wave
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(at, o, 64);
+      if (ov > best || (ov == best && oi < at)) {
+        best = ov;
+        at = oi;
+      }
+    }
+    if ((tid & 63) == 0) {
+      bv[tid >> 6] = best;
+      bi[tid >> 6] = at;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      best = tid < 16 ? bv[tid] : -1.0;
+      at = tid < 16 ? bi[tid] : Mg;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(at, o, 64);
+        if (ov > best || (ov == best && oi < at)) {
+          best = ov;
+          at = oi;
+        }
+      }
+      if (tid == 0) bi[16] = at;
+    }
+    __syncthreads();
+    const int p = bi[16];
+    if (tid < nb) {  // swap rows c and p (thread = column), keep the pivot row
+      double *Pq = P + (int64_t)tid * maxM, *Cq = Cg + (int64_t)tid * maxM;
+      const double a = Pq[c], b = Pq[p];
+      Pq[c] = b;
+      Pq[p] = a;
+      prow[tid] = b;
+      const double ca = Cq[c];
+      Cq[c] = Cq[p];
+      Cq[p] = ca;
+    }
+    if (tid == 0) piv[g * kGJ + k] = p;
+    __syncthreads();
+    const double inv = 1.0 / prow[k];
+    for (int r = c + 1 + tid; r < Mg; r += 1024) {
+      const double l = P[(int64_t)k * maxM + r] * inv;
+      P[(int64_t)k * maxM + r] = l;
+      for (int q = k + 1; q < nb; ++q) P[(int64_t)q * maxM + r] -= l * prow[q];
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) piv[g] = bi[0];
+  // Binv = U^-1 L^-1 of the pivot block (unit lower L, upper U)
+  for (int e = tid; e < nb * nb; e += 1024) {
+    const int i = e / nb, q = e % nb;
+    lu[i][q] = P[(int64_t)q * maxM + j0 + i];
+  }
+  __syncthreads();
+  if (tid < nb) {
+    const int col = tid;
+    double y[kGJ];
+    for (int i = 0; i < nb; ++i) {  // L y = e_col
+      double v = (i == col) ? 1.0 : 0.0;
+      for (int q = 0; q < i; ++q) v -= lu[i][q] * y[q];
+      y[i] = v;
+    }
+    for (int i = nb - 1; i >= 0; --i) {  // U x = y
+      double v = y[i];
+      for (int q = i + 1; q < nb; ++q) v -= lu[i][q] * y[q];
+      y[i] = v / lu[i][i];
+    }
+    for (int i = 0; i < nb; ++i) Binv[((int64_t)g * kGJ + i) * kGJ + col] = y[i];
+  }
 }
 
-__global__ void k_gj_swap(int c, const int32_t *__restrict__ gisl,
-                          const int64_t *__restrict__ gsinv,
-                          double *__restrict__ A, double *__restrict__ B,
-                          const int *__restrict__ piv) {
+// column c of [A | B] (c < M_g: A, else B): the panel's swaps in order;
+// the panel's own columns are already swapped
+__global__ void __launch_bounds__(256)
+    k_gj_swap(int j0, const int32_t *__restrict__ gisl,
+              const int64_t *__restrict__ gsinv, double *__restrict__ A,
+              double *__restrict__ B, const int *__restrict__ piv) {
   const int g = blockIdx.z;
-  int Mg;
-  if (!gj_block(gisl, g, c, Mg)) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = piv[g];
-  if (j >= Mg || p == c) return;
-  double *Ag = A + gsinv[g], *Bg = B + gsinv[g];
-  double t = Ag[(int64_t)c * Mg + j];
-  Ag[(int64_t)c * Mg + j] = Ag[(int64_t)p * Mg + j];
-  Ag[(int64_t)p * Mg + j] = t;
-  t = Bg[(int64_t)c * Mg + j];
-  Bg[(int64_t)c * Mg + j] = Bg[(int64_t)p * Mg + j];
-  Bg[(int64_t)p * Mg + j] = t;
+  const int Mg = gisl[g + 1] - gisl[g];
+  if (j0 >= Mg) return;
+  const int nb = min(kGJ, Mg - j0);
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= 2 * Mg || (c >= j0 && c < j0 + nb)) return;
+  double *X = (c < Mg ? A : B) + gsinv[g];
+  const int cc = c < Mg ? c : c - Mg;
+  for (int k = 0; k < nb; ++k) {
+    const int p = piv[g * kGJ + k];
+    if (p == j0 + k) continue;
+    const double t = X[(int64_t)(j0 + k) * Mg + cc];
+    X[(int64_t)(j0 + k) * Mg + cc] = X[(int64_t)p * Mg + cc];
+    X[(int64_t)p * Mg + cc] = t;
+  }
 }
 
-// Column-c factors of the other rows, then the pivot row scaled by the
-// inverse pivot (its diagonal entry is set to 1 by k_gj_fix).
-__global__ void k_gj_norm(int c, const int32_t *__restrict__ gisl,
-                          const int64_t *__restrict__ gsinv,
-                          double *__restrict__ A, double *__restrict__ B,
-                          double *__restrict__ f, int fstride) {
+// W[k][c] = sum_q Binv[k][q] [A | B][j0 + q][c] for the columns still to
+// update (A: c >= j0 + nb; B: all).
+__global__ void __launch_bounds__(256)
+    k_gj_w(int j0, const int32_t *__restrict__ gisl,
+           const int64_t *__restrict__ gsinv, const double *__restrict__ A,
+           const double *__restrict__ B, const double *__restrict__ Binv,
+           double *__restrict__ W, int maxM) {
+  __shared__ double bl[kGJ][kGJ + 1];
   const int g = blockIdx.z;
-  int Mg;
-  if (!gj_block(gisl, g, c, Mg)) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= Mg) return;
-  double *Ag = A + gsinv[g], *Bg = B + gsinv[g];
-  const double inv = 1.0 / Ag[(int64_t)c * Mg + c];
-  f[(int64_t)g * fstride + j] = (j == c) ? 0.0 : Ag[(int64_t)j * Mg + c];
-  if (j != c) Ag[(int64_t)c * Mg + j] *= inv;
-  Bg[(int64_t)c * Mg + j] *= inv;
+  const int Mg = gisl[g + 1] - gisl[g];
+  if (j0 >= Mg) return;
+  const int nb = min(kGJ, Mg - j0);
+  for (int e = threadIdx.x; e < kGJ * kGJ; e += 256)
+    bl[e / kGJ][e % kGJ] = Binv[(int64_t)g * kGJ * kGJ + e];
+  __syncthreads();
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= 2 * Mg || t < j0 + nb) return;
+  const double *X = (t < Mg ? A : B) + gsinv[g];
+  const int cc = t < Mg ? t : t - Mg;
+  double col[kGJ];
+  for (int q = 0; q < nb; ++q) col[q] = X[(int64_t)(j0 + q) * Mg + cc];
+  double *Wg = W + (int64_t)g * kGJ * 2 * maxM;
+  for (int k = 0; k < nb; ++k) {
+    double v = 0.0;
+    for (int q = 0; q < nb; ++q) v += bl[k][q] * col[q];
+    Wg[(int64_t)k * 2 * maxM + t] = v;
+  }
 }
 
-__global__ void k_gj_fix(int c, const int32_t *__restrict__ gisl,
-                         const int64_t *__restrict__ gsinv,
-                         double *__restrict__ A) {
+// Tiles of 64 rows x 64 columns of [A | B], 4 x 4 per thread: rows of the
+// panel take W, every other row r subtracts C_r W.
+__global__ void __launch_bounds__(256)
+    k_gj_update(int j0, const int32_t *__restrict__ gisl,
+                const int64_t *__restrict__ gsinv, double *__restrict__ A,
+                double *__restrict__ B, const double *__restrict__ W,
+                const double *__restrict__ F, int maxM) {
+  __shared__ double fs[64][kGJ + 1];
+  __shared__ double ws[kGJ][64 + 1];
   const int g = blockIdx.z;
-  int Mg;
-  if (!gj_block(gisl, g, c, Mg)) return;
-  if (threadIdx.x == 0) A[gsinv[g] + (int64_t)c * Mg + c] = 1.0;
-}
-
-__global__ void k_gj_eliminate(int c, const int32_t *__restrict__ gisl,
-                               const int64_t *__restrict__ gsinv,
-                               double *__restrict__ A, double *__restrict__ B,
-                               const double *__restrict__ f, int fstride) {
-  const int g = blockIdx.z;
-  int Mg;
-  if (!gj_block(gisl, g, c, Mg)) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (j >= Mg || r >= Mg || r == c) return;
-  const double fr = f[(int64_t)g * fstride + r];
-  if (fr == 0.0) return;
-  double *Ag = A + gsinv[g], *Bg = B + gsinv[g];
-  if (j > c) Ag[(int64_t)r * Mg + j] -= fr * Ag[(int64_t)c * Mg + j];
-  Bg[(int64_t)r * Mg + j] -= fr * Bg[(int64_t)c * Mg + j];
+  const int Mg = gisl[g + 1] - gisl[g];
+  if (j0 >= Mg) return;
+  const int nb = min(kGJ, Mg - j0);
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  if (c0 >= 2 * Mg || r0 >= Mg || c0 + 64 <= j0 + nb) return;
+  const double *Fg = F + (int64_t)g * maxM * kGJ;
+  const double *Wg = W + (int64_t)g * kGJ * 2 * maxM;
+  for (int e = threadIdx.x; e < 64 * kGJ; e += 256) {
+    const int r = e / kGJ, k = e % kGJ;
+    fs[r][k] = (r0 + r < Mg && k < nb) ? Fg[(int64_t)k * maxM + r0 + r] : 0.0;
+    const int kk = e / 64, c = e % 64;
+    ws[kk][c] = (kk < nb && c0 + c < 2 * Mg && c0 + c >= j0 + nb)
+                    ? Wg[(int64_t)kk * 2 * maxM + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
+  double acc[4][4] = {};
+  for (int k = 0; k < nb; ++k)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) acc[i][j] += fs[tr + i][k] * ws[k][tc + j];
+  for (int i = 0; i < 4; ++i) {
+    const int r = r0 + tr + i;
+    if (r >= Mg) continue;
+    const bool pivot_row = r >= j0 && r < j0 + nb;
+    for (int j = 0; j < 4; ++j) {
+      const int c = c0 + tc + j;
+      if (c >= 2 * Mg || c < j0 + nb) continue;
+      double *X = (c < Mg ? A : B) + gsinv[g] + (int64_t)r * Mg + (c < Mg ? c : c - Mg);
+      if (pivot_row) *X = ws[r - j0][tc + j];
+      else *X -= acc[i][j];
+    }
+  }
 }
 
 __global__ void k_gj_identity(const int32_t *__restrict__ gisl,
@@ -522,23 +642,25 @@ void invert_blocks(const Geometry &g, double *S, double *Sinv, hipStream_t s) {
   if (g.M == 0) return;
   const int G = g.G, maxM = g.maxM;
   DBuf<int> piv;
-  piv.alloc(G);
-  DBuf<double> f;
-  f.alloc((size_t)G * maxM);
-  const unsigned nb = (maxM + 255) / 256;
-  hipLaunchKernelGGL(k_gj_identity, dim3(nb, maxM, G), dim3(256), 0, s,
+  piv.alloc((size_t)G * kGJ);
+  DBuf<double> P, C, W, Bi;
+  P.alloc((size_t)G * maxM * kGJ);
+  C.alloc((size_t)G * maxM * kGJ);
+  W.alloc((size_t)G * kGJ * 2 * maxM);
+  Bi.alloc((size_t)G * kGJ * kGJ);
+  hipLaunchKernelGGL(k_gj_identity, dim3((maxM + 255) / 256, maxM, G), dim3(256), 0, s,
                      g.dgisl.p, g.dgsinv.p, Sinv);
-  for (int c = 0; c < maxM; ++c) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1, 1, G), dim3(256), 0, s, c, g.dgisl.p,
-                       g.dgsinv.p, S, piv.p);
-    hipLaunchKernelGGL(k_gj_swap, dim3(nb, 1, G), dim3(256), 0, s, c, g.dgisl.p,
+  const unsigned ncol = (2 * maxM + 255) / 256, ntile = (2 * maxM + 63) / 64,
+                 nrow = (maxM + 63) / 64;
+  for (int j0 = 0; j0 < maxM; j0 += kGJ) {
+    hipLaunchKernelGGL(k_gj_panel, dim3(G), dim3(1024), 0, s, j0, g.dgisl.p, g.dgsinv.p,
+                       S, P.p, C.p, piv.p, Bi.p, maxM);
+    hipLaunchKernelGGL(k_gj_swap, dim3(ncol, 1, G), dim3(256), 0, s, j0, g.dgisl.p,
                        g.dgsinv.p, S, Sinv, piv.p);
-    hipLaunchKernelGGL(k_gj_norm, dim3(nb, 1, G), dim3(256), 0, s, c, g.dgisl.p,
-                       g.dgsinv.p, S, Sinv, f.p, maxM);
-    hipLaunchKernelGGL(k_gj_fix, dim3(1, 1, G), dim3(64), 0, s, c, g.dgisl.p,
-                       g.dgsinv.p, S);
-    hipLaunchKernelGGL(k_gj_eliminate, dim3(nb, maxM, G), dim3(256), 0, s, c,
-                       g.dgisl.p, g.dgsinv.p, S, Sinv, f.p, maxM);
+    hipLaunchKernelGGL(k_gj_w, dim3(ncol, 1, G), dim3(256), 0, s, j0, g.dgisl.p,
+                       g.dgsinv.p, S, Sinv, Bi.p, W.p, maxM);
+    hipLaunchKernelGGL(k_gj_update, dim3(ntile, nrow, G), dim3(256), 0, s, j0, g.dgisl.p,
+                       g.dgsinv.p, S, Sinv, W.p, C.p, maxM);
   }
   LBS_HIP(hipGetLastError());
   LBS_HIP(hipStreamSynchronize(s));
