@@ -112,6 +112,11 @@ typedef struct {
                      /* everywhere.  lbs_eval_T / lbs_shape_vjp cover the  */
                      /* trapezoidal rule only and reject close targets     */
                      /* while it is 1.                                     */
+  int32_t gpu_tree;  /* 1 (default): single-geometry handles build their  */
+                     /* quadtrees and lists (set-up and evaluation plans)  */
+                     /* with HIP kernels; 0: with host threads.  Batch     */
+                     /* handles always use the host builder.  Both give    */
+                     /* the same tree (lbs_compare_trees).                 */
 } lbs_options;
 
 typedef struct {
@@ -445,6 +450,17 @@ lbs_status lbs_check_tree_host(const double *x_host, const double *y_host,
                                int64_t n, int32_t leaf_max,
                                int64_t *bad_pairs_host,
                                lbs_tree_stats *stats_host);
+
+/* Check of the GPU quadtree builder (needs a GPU): builds the tree and the
+ * U, V, W, X lists for n device points (x, y) (and nt device targets
+ * (tx, ty), or nt = 0 for targets = sources) with HIP kernels and with the
+ * host builder, and sets *mismatches_host to the number of differing
+ * entries over every box field, list and permutation (0: identical) and
+ * *levels_host (may be NULL) to the depth.  Synchronous. */
+lbs_status lbs_compare_trees(const double *x, const double *y, int64_t n,
+                             const double *tx, const double *ty, int64_t nt,
+                             int32_t leaf_max, int64_t *mismatches_host,
+                             int32_t *levels_host, void *stream);
 
 #ifdef __cplusplus
 }

@@ -1043,6 +1043,7 @@ void validate_options(const lbs_options &o) {
   if (o.graphs != 0 && o.graphs != 1) fail(LBS_ERR_INVALID_ARG, "graphs must be 0 or 1");
   if (o.precond != 0 && o.precond != 1) fail(LBS_ERR_INVALID_ARG, "precond must be 0 or 1");
   if (o.close_eval != 0 && o.close_eval != 1) fail(LBS_ERR_INVALID_ARG, "close_eval must be 0 or 1");
+  if (o.gpu_tree != 0 && o.gpu_tree != 1) fail(LBS_ERR_INVALID_ARG, "gpu_tree must be 0 or 1");
 }
 
 // Set-up of G geometries (islands and node counts concatenated
@@ -1353,15 +1354,19 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl_in
   {
     Tree &F = ctx->plan.host;
     F = Tree();
-    for (int q = 0; q < G; ++q) {
-      const int64_t a = g.gnode[q], n = g.gnode[q + 1] - a;
-      Tree t;
-      build_tree(ctx->xi_x.data() + a, ctx->xi_y.data() + a, n, nullptr, nullptr, 0, true,
-                 o.leaf_max, t);
-      if (G == 1) {
-        F = std::move(t);
-      } else {
-        append_tree(F, t, a, a, a, a);
+    if (G == 1 && o.gpu_tree) {
+      gpu_build_tree(g.xi.p, g.xi.p + 1, 2, N, nullptr, nullptr, 0, 0, true, o.leaf_max, F, s);
+    } else {
+      for (int q = 0; q < G; ++q) {
+        const int64_t a = g.gnode[q], n = g.gnode[q + 1] - a;
+        Tree t;
+        build_tree(ctx->xi_x.data() + a, ctx->xi_y.data() + a, n, nullptr, nullptr, 0, true,
+                   o.leaf_max, t);
+        if (G == 1) {
+          F = std::move(t);
+        } else {
+          append_tree(F, t, a, a, a, a);
+        }
       }
     }
   }
@@ -1454,19 +1459,29 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
   const int64_t n = (int64_t)ep->idx.size();
   if (n > 0 && (transposed || c.opt.matvec != LBS_MATVEC_DIRECT)) {
     Tree &F = ep->pl.host;
-    for (int q = 0; q < G; ++q) {
-      const int64_t a = g.gnode[q], nn = g.gnode[q + 1] - a;
-      const int64_t ta = qoff[q], tn = qoff[q + 1] - ta;
-      Tree t;
+    if (G == 1 && c.opt.gpu_tree) {
+      DBuf<double> dtx, dty;
+      dtx.upload(ep->tx, s);
+      dty.upload(ep->ty, s);
       if (transposed)
-        build_tree(ep->tx.data() + ta, ep->ty.data() + ta, tn, c.xi_x.data() + a,
-                   c.xi_y.data() + a, nn, false, c.opt.leaf_max, t);
+        gpu_build_tree(dtx.p, dty.p, 1, n, g.xi.p, g.xi.p + 1, 2, g.N, false, c.opt.leaf_max, F, s);
       else
-        build_tree(c.xi_x.data() + a, c.xi_y.data() + a, nn, ep->tx.data() + ta,
-                   ep->ty.data() + ta, tn, false, c.opt.leaf_max, t);
-      if (G == 1) F = std::move(t);
-      else if (transposed) append_tree(F, t, ta, a, ta, a);
-      else append_tree(F, t, a, ta, a, ta);
+        gpu_build_tree(g.xi.p, g.xi.p + 1, 2, g.N, dtx.p, dty.p, 1, n, false, c.opt.leaf_max, F, s);
+    } else {
+      for (int q = 0; q < G; ++q) {
+        const int64_t a = g.gnode[q], nn = g.gnode[q + 1] - a;
+        const int64_t ta = qoff[q], tn = qoff[q + 1] - ta;
+        Tree t;
+        if (transposed)
+          build_tree(ep->tx.data() + ta, ep->ty.data() + ta, tn, c.xi_x.data() + a,
+                     c.xi_y.data() + a, nn, false, c.opt.leaf_max, t);
+        else
+          build_tree(c.xi_x.data() + a, c.xi_y.data() + a, nn, ep->tx.data() + ta,
+                     ep->ty.data() + ta, tn, false, c.opt.leaf_max, t);
+        if (G == 1) F = std::move(t);
+        else if (transposed) append_tree(F, t, ta, a, ta, a);
+        else append_tree(F, t, a, ta, a, ta);
+      }
     }
     if (transposed) {
       upload_plan(F, ep->tx.data(), ep->ty.data(), c.xi_x.data(), c.xi_y.data(), nullptr,
@@ -1715,6 +1730,7 @@ void lbs_default_options(lbs_options *o) {
   o->graphs = 1;
   o->precond = 1;
   o->close_eval = 1;
+  o->gpu_tree = 1;
 }
 
 lbs_status lbs_refine_tolerances_host(int32_t S, const double *rn2, const double *bn2,
@@ -2197,6 +2213,49 @@ lbs_status lbs_tree_info(lbs_handle h, lbs_tree_stats *st) {
     check_handle(h);
     if (!st) fail(LBS_ERR_INVALID_ARG, "stats is NULL");
     fill_stats(h->plan.host, st);
+  });
+}
+
+lbs_status lbs_compare_trees(const double *x, const double *y, int64_t n, const double *tx,
+                             const double *ty, int64_t nt, int32_t leaf_max, int64_t *mismatch,
+                             int32_t *levels, void *stream) {
+  return guard([&] {
+    if (!x || !y || !mismatch || (nt > 0 && (!tx || !ty)))
+      fail(LBS_ERR_INVALID_ARG, "null pointer argument");
+    if (n < 1 || nt < 0 || leaf_max < 1) fail(LBS_ERR_INVALID_ARG, "n, nt or leaf_max out of range");
+    hipStream_t s = (hipStream_t)stream;
+    const bool self = nt == 0;
+    Tree G;
+    gpu_build_tree(x, y, 1, n, tx, ty, 1, nt, self, leaf_max, G, s);
+    std::vector<double> hx = download(x, n, s), hy = download(y, n, s), htx, hty;
+    if (!self) {
+      htx = download(tx, nt, s);
+      hty = download(ty, nt, s);
+    }
+    Tree H;
+    build_tree(hx.data(), hy.data(), n, self ? nullptr : htx.data(), self ? nullptr : hty.data(),
+               nt, self, leaf_max, H);
+    int64_t bad = 0;
+    auto cmp = [&](const auto &a, const auto &b) {
+      if (a.size() != b.size()) {
+        bad += 1 + (int64_t)std::max(a.size(), b.size());
+        return;
+      }
+      for (size_t i = 0; i < a.size(); ++i) bad += a[i] != b[i];
+    };
+    cmp(G.cx, H.cx); cmp(G.cy, H.cy); cmp(G.rad, H.rad); cmp(G.level, H.level);
+    cmp(G.parent, H.parent); cmp(G.child0, H.child0); cmp(G.nchild, H.nchild);
+    cmp(G.ix, H.ix); cmp(G.iy, H.iy); cmp(G.s0, H.s0); cmp(G.s1, H.s1); cmp(G.t0, H.t0);
+    cmp(G.t1, H.t1); cmp(G.leaf, H.leaf); cmp(G.level_ptr, H.level_ptr);
+    cmp(G.v_ptr, H.v_ptr); cmp(G.v_src, H.v_src); cmp(G.v_code, H.v_code);
+    cmp(G.x_ptr, H.x_ptr); cmp(G.x_src, H.x_src); cmp(G.u_ptr, H.u_ptr); cmp(G.u_src, H.u_src);
+    cmp(G.w_ptr, H.w_ptr); cmp(G.w_src, H.w_src); cmp(G.src_perm, H.src_perm);
+    cmp(G.tgt_perm, H.tgt_perm);
+    bad += G.nlevels != H.nlevels;
+    bad += G.x0 != H.x0 || G.y0 != H.y0 || G.R0 != H.R0;
+    bad += G.p2p_pairs != H.p2p_pairs || G.m2p_evals != H.m2p_evals || G.p2l_evals != H.p2l_evals;
+    *mismatch = bad;
+    if (levels) *levels = G.nlevels;
   });
 }
 

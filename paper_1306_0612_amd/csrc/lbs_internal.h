@@ -316,6 +316,11 @@ constexpr int kLogChunk = 64;  // far-list entries per wave step
 constexpr int kM2LGroups = 1024;
 
 void set_last_error(const std::string &msg);  // message of lbs_last_error
+// build_tree on the GPU (gtree.hip): device coordinates x[i stride],
+// y[i stride]; the same Tree as the host builder.  Synchronous.
+void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t ns,
+                    const double *tx, const double *ty, int64_t tstride, int64_t nt, bool self,
+                    int leaf_max, Tree &T, hipStream_t s);
 // lbs_matvec with its scratch buffers in `bytes` of device memory at base
 // (api.cpp; the entry point without allocation passes its static scratch)
 lbs_status matvec_in_scratch(lbs_handle h, int32_t op, int32_t prec, int32_t nrhs,

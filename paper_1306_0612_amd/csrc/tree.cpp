@@ -377,6 +377,11 @@ void build_tree(const double *sx, const double *sy, int64_t ns,
       }
     }
   }, 1024);
+  tree_statistics(T);
+}
+
+void tree_statistics(Tree &T) {
+  const int nb = T.nbox();
   T.p2p_pairs = T.m2p_evals = T.p2l_evals = 0;
   for (int b = 0; b < nb; ++b) {
     const int64_t ntb = T.t1[b] - T.t0[b];

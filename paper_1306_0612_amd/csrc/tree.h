@@ -70,6 +70,9 @@ void build_tree(const double *sx, const double *sy, int64_t ns,
                 const double *tx, const double *ty, int64_t nt, bool self,
                 int leaf_max, Tree &T);
 
+// Pair and evaluation counts of the lists (p2p_pairs, m2p_evals, p2l_evals).
+void tree_statistics(Tree &T);
+
 // Append tree t to the forest F: box indices shift by F's box count, point
 // ranges by src_base / tgt_base, permutation entries by the index bases.
 void append_tree(Tree &F, const Tree &t, int64_t src_base, int64_t tgt_base,

@@ -38,7 +38,7 @@ class Options(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("matvec", ctypes.c_int32),
                 ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("close_eval", ctypes.c_int32)]
+                ("close_eval", ctypes.c_int32), ("gpu_tree", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -162,11 +162,16 @@ def load():
                                     vp, vp, vp, vp]
     lib.lbs_vortex_field.argtypes = [H, ctypes.c_int32, ctypes.c_int32, vp,
                                      vp, ctypes.c_int64, vp, vp, vp]
+    lib.lbs_compare_trees.argtypes = [vp, vp, ctypes.c_int64, vp, vp,
+                                      ctypes.c_int64, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int32), vp]
     lib.lbs_refine_tolerances_host.argtypes = [
         ctypes.c_int32, c_double_p, c_double_p, ctypes.c_double,
         ctypes.c_double, c_double_p, ctypes.POINTER(ctypes.c_int32)]
     for name in ("lbs_refine_tolerances_host", "lbs_setup_sampled",
                  "lbs_vortex_data", "lbs_vortex_field", "lbs_matvec_noalloc",
+                 "lbs_compare_trees",
                  "lbs_resample_curve_host", "lbs_setup", "lbs_sizes",
                  "lbs_nodes", "lbs_matvec", "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
                  "lbs_stage_timing", "lbs_stage_times", "lbs_setup_batch",
@@ -479,6 +484,18 @@ def autotune(islands, tol_mixed=1e-6, tol_fp64=1e-10, nodes=None, **kw):
                             float(tol_fp64), _stream(), ctypes.byref(best),
                             ent, 64, ctypes.byref(cnt)))
     return best, [ent[i].as_dict() for i in range(min(cnt.value, 64))]
+
+
+def compare_trees(x, y, leaf_max, tx=None, ty=None):
+    """lbs_compare_trees on device tensors: (mismatching entries, levels)."""
+    bad = ctypes.c_int64()
+    lev = ctypes.c_int32()
+    nt = 0 if tx is None else tx.shape[0]
+    _check(load().lbs_compare_trees(
+        _dev(x), _dev(y), x.shape[0], None if tx is None else _dev(tx),
+        None if ty is None else _dev(ty), nt, int(leaf_max), ctypes.byref(bad),
+        ctypes.byref(lev), _stream()))
+    return bad.value, lev.value
 
 
 def check_tree_host(x, y, leaf_max):
