@@ -451,6 +451,18 @@ lbs_status lbs_check_tree_host(const double *x_host, const double *y_host,
                                int64_t *bad_pairs_host,
                                lbs_tree_stats *stats_host);
 
+/* Host-only check of the upward (M2M) and downward (L2L) pass programs (no
+ * GPU needed): builds the tree of n planar points as lbs_check_tree_host
+ * does, cuts its work boxes into components of at most cap LDS expansion
+ * slots (16 .. 1024) and runs both programs on the host with scalar
+ * stand-ins for the expansions (a multipole holds its box's source count, a
+ * local its box's level).  *bad_host gets the number of wrong or
+ * out-of-order results; rounds_host (may be NULL) the launches of the
+ * upward and the downward pass. */
+lbs_status lbs_check_passes_host(const double *x_host, const double *y_host,
+                                 int64_t n, int32_t leaf_max, int32_t cap,
+                                 int64_t *bad_host, int32_t *rounds_host);
+
 /* Check of the GPU quadtree builder (needs a GPU): builds the tree and the
  * U, V, W, X lists for n device points (x, y) (and nt device targets
  * (tx, ty), or nt = 0 for targets = sources) with HIP kernels and with the

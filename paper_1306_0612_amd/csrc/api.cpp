@@ -64,16 +64,13 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
   pl.self = T.self;
   pl.ns = (int64_t)T.src_perm.size();
   pl.nt = (int64_t)T.tgt_perm.size();
-  std::vector<int32_t> quad(nb), leaf_s, leaf_t, m2l;
+  std::vector<int32_t> leaf_s, leaf_t, m2l;
   std::vector<uint8_t> has_tgt(nb);
-  std::vector<std::vector<int32_t>> by_level(std::max(1, T.nlevels));
   for (int b = 0; b < nb; ++b) {
-    quad[b] = (T.ix[b] & 1) | ((T.iy[b] & 1) << 1);
     has_tgt[b] = T.t1[b] > T.t0[b];
     if (T.leaf[b] && T.s1[b] > T.s0[b]) leaf_s.push_back(b);
     if (T.leaf[b] && has_tgt[b]) leaf_t.push_back(b);
     if (T.level[b] >= 2 && has_tgt[b]) m2l.push_back(b);
-    by_level[T.level[b]].push_back(b);
   }
   pl.n_leaf_s = (int)leaf_s.size();
   pl.n_leaf_t = (int)leaf_t.size();
@@ -126,74 +123,7 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
   }
   pl.leaf_t_host = leaf_t;
   pl.leaf_s_host = leaf_s;
-  // subtree heaps of the fused upward / downward passes (see DevPlan)
   std::vector<int32_t> xb;
-  {
-    auto kid = [&](int b, int q, bool src) -> int {
-      if (T.leaf[b]) return -1;
-      for (int c = T.child0[b]; c < T.child0[b] + T.nchild[b]; ++c)
-        if (quad[c] == q && (src ? T.s1[c] > T.s0[c] : has_tgt[c])) return c;
-      return -1;
-    };
-    auto inner = [&](int b, bool src) {
-      if (b < 0 || T.leaf[b]) return false;
-      for (int q = 0; q < 4; ++q)
-        if (kid(b, q, src) >= 0) return true;
-      return false;
-    };
-    std::vector<int32_t> ub, um, db;
-    std::vector<int4> ud;
-    std::vector<int> roots;
-    for (int r = 2; r < std::max(T.nlevels, 2); r += 3) roots.push_back(r);
-    pl.up_gptr.assign(1, 0);
-    for (auto it = roots.rbegin(); it != roots.rend(); ++it) {
-      for (int b : by_level[*it]) {
-        if (!(T.s1[b] > T.s0[b]) || !inner(b, true)) continue;
-        int32_t sl[21];
-        std::fill(sl, sl + 21, -1);
-        int32_t mask = 1;
-        sl[0] = b;
-        for (int s1 = 0; s1 < 5; ++s1) {
-          if (sl[s1] < 0) continue;
-          for (int q = 0; q < 4; ++q) {
-            const int c = kid(sl[s1], q, true);
-            const int sc = 4 * s1 + 1 + q;
-            if (c < 0) continue;
-            sl[sc] = c;
-            if (inner(c, true)) mask |= 1 << sc;
-          }
-        }
-        for (int g = 5; g < 21; ++g) {
-          int ks[4] = {-1, -1, -1, -1};
-          if (sl[g] >= 0 && (mask >> g & 1))
-            for (int q = 0; q < 4; ++q) ks[q] = kid(sl[g], q, true);
-          ud.push_back(make_int4(ks[0], ks[1], ks[2], ks[3]));
-        }
-        ub.insert(ub.end(), sl, sl + 21);
-        um.push_back(mask);
-      }
-      pl.up_gptr.push_back((int32_t)um.size());
-    }
-    pl.dn_gptr.assign(1, 0);
-    for (int r : roots) {
-      for (int b : by_level[r]) {
-        if (!has_tgt[b] || !inner(b, false)) continue;
-        int32_t sl[85];
-        std::fill(sl, sl + 85, -1);
-        sl[0] = b;
-        for (int s1 = 0; s1 < 21; ++s1) {
-          if (sl[s1] < 0) continue;
-          for (int q = 0; q < 4; ++q) sl[4 * s1 + 1 + q] = kid(sl[s1], q, false);
-        }
-        db.insert(db.end(), sl, sl + 85);
-      }
-      pl.dn_gptr.push_back((int32_t)(db.size() / 85));
-    }
-    pl.up_box.upload(ub, s);
-    pl.up_mask.upload(um, s);
-    pl.up_deep.upload(ud, s);
-    pl.dn_box.upload(db, s);
-  }
   for (int b = 0; b < nb; ++b)
     if (T.x_ptr[b + 1] > T.x_ptr[b]) xb.push_back(b);
   pl.n_x = (int)xb.size();
@@ -293,6 +223,26 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
     perm[j] = tgt_index ? (*tgt_index)[T.tgt_perm[j]] : T.tgt_perm[j];
   pl.tgt_perm.upload(perm, s);
   LBS_HIP(hipStreamSynchronize(s));
+}
+
+// Upward / downward pass programs of the plan's tree for FP32 order p32
+// and FP64 order p64 (the LDS capacity of the pass kernels depends on it).
+void build_passes(DevPlan &pl, int p32, int p64, hipStream_t s) {
+  for (int k = 0; k < 2; ++k) {
+    const int cap = k == 0 ? pass_cap(p32, 8) : pass_cap(p64, 16);
+    for (int d = 0; d < 2; ++d) {
+      PassProgram pp;
+      build_pass_program(pl.host, d == 1, cap, pp);
+      DevPass &dp = d ? pl.dn[k] : pl.up[k];
+      dp.cap = cap;
+      dp.round_ptr = pp.round_ptr;
+      dp.hdr.upload(pp.hdr, s);
+      dp.ext.upload(pp.ext, s);
+      dp.par.upload(pp.par, s);
+      dp.stp.upload(pp.stp, s);
+      LBS_HIP(hipStreamSynchronize(s));  // pp is released on return
+    }
+  }
 }
 
 }  // namespace
@@ -1372,6 +1322,7 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl_in
   }
   upload_plan(ctx->plan.host, ctx->xi_x.data(), ctx->xi_y.data(), nullptr, nullptr, nullptr,
               ctx->plan, s);
+  build_passes(ctx->plan, o.p32, o.p64, s);
   g.qfac_t.alloc(2 * N);
   launch_permute_complex(N, ctx->plan.src_perm.p, g.qfac.p, g.qfac_t.p, s);
   {
@@ -1486,10 +1437,12 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
     if (transposed) {
       upload_plan(F, ep->tx.data(), ep->ty.data(), c.xi_x.data(), c.xi_y.data(), nullptr,
                   ep->pl, s);
+      build_passes(ep->pl, c.opt.p32, c.opt.p64, s);
       ep->didx.upload(ep->idx, s);
     } else {
       upload_plan(F, c.xi_x.data(), c.xi_y.data(), ep->tx.data(), ep->ty.data(), &ep->idx,
                   ep->pl, s);
+      build_passes(ep->pl, c.opt.p32, c.opt.p64, s);
       ep->qt.alloc(2 * g.N);
       launch_permute_complex(g.N, ep->pl.src_perm.p, g.qfac.p, ep->qt.p, s);
     }
@@ -2120,6 +2073,7 @@ lbs_status lbs_set_orders(lbs_handle h, int32_t p64, int32_t p32, void *stream) 
     if (p32 != c.opt.p32) build_tables(c.tab32, p32, s);
     c.opt.p64 = p64;
     c.opt.p32 = p32;
+    build_passes(c.plan, p32, p64, s);
     // expansion buffers are sized by the orders: reallocate on next use
     const int cap = std::max(1, c.ws.nrhs_cap);
     c.ws.nrhs_cap = 0;
@@ -2268,6 +2222,24 @@ lbs_status lbs_check_tree_host(const double *x, const double *y, int64_t n, int3
     build_tree(x, y, n, nullptr, nullptr, 0, true, leaf_max, T);
     *bad = check_coverage(T);
     if (st) fill_stats(T, st);
+  });
+}
+
+lbs_status lbs_check_passes_host(const double *x, const double *y, int64_t n, int32_t leaf_max,
+                                 int32_t cap, int64_t *bad, int32_t *rounds) {
+  return guard([&] {
+    if (!x || !y || !bad) fail(LBS_ERR_INVALID_ARG, "null pointer argument");
+    if (n < 1 || leaf_max < 1) fail(LBS_ERR_INVALID_ARG, "n or leaf_max < 1");
+    if (cap < 16 || cap > 1024) fail(LBS_ERR_INVALID_ARG, "cap outside 16 .. 1024");
+    Tree T;
+    build_tree(x, y, n, nullptr, nullptr, 0, true, leaf_max, T);
+    *bad = 0;
+    for (int d = 0; d < 2; ++d) {
+      PassProgram pp;
+      build_pass_program(T, d == 1, cap, pp);
+      *bad += check_pass_program(T, pp);
+      if (rounds) rounds[d] = (int32_t)pp.round_ptr.size() - 1;
+    }
   });
 }
 

@@ -351,223 +351,158 @@ struct GammaGroups {
   int nls = 0, G = 0, nchunk = 0, first = 0;
 };
 
-// Upward pass over three levels per launch: one work-group per root, whose
-// subtree is the heap described with DevPlan.  All operands are first
-// staged in LDS with every load in flight at once (the multipoles of the
-// grandchildren's children and of the childless slots), each pre-scaled by
-// (conj(delta_q)/2)^k for the quadrant q it occupies under its parent; then
-// step 1 forms the multipoles of the grandchildren that have children,
-// step 2 those of the children, step 3 the root's, from LDS only:
-//   A_lo = sum_q 1/2 (delta_q/2)^lo sum_{k <= lo} C(lo, k) a~_{q,k}
-// (C is zero above the diagonal, so the fixed-length sums add exact zeros).
-template <typename T, int P>
-__global__ void __launch_bounds__(256)
-    k_m2m3(const int32_t *__restrict__ box, const int32_t *__restrict__ mask,
-           const int4 *__restrict__ deep, const T *__restrict__ Cb,
-           const cx<T> *__restrict__ Pre, const cx<T> *__restrict__ Post,
-           cx<T> *__restrict__ M, int nbox) {
-  constexpr int NT = 256, NE = 84 * P, IT = (NE + NT - 1) / NT;
-  __shared__ T sC[P * P];
-  __shared__ cx<T> sPre[4 * P], sPost[4 * P];
-  __shared__ cx<T> sK[64 * P];  // children of grandchild j, quadrant q: 4 j + q
-  __shared__ cx<T> sm[21 * P];  // pre-scaled expansions of the heap slots
-  const int root = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
-  const int32_t *bx = box + (int64_t)root * 21;
-  const int msk = mask[root];
-  const int4 *dp = deep + (int64_t)root * 16;
-  cx<T> *Mr = M + (int64_t)r * nbox * P;
-  cx<T> v[IT];
-#pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int e = tid + i * NT;
-    v[i] = cx<T>{T(0), T(0)};
-    if (e < 64 * P) {
-      const int jq = e / P, k = e % P, j = jq >> 2, q = jq & 3;
-      if ((msk >> (5 + j)) & 1) {
-        const int4 kd = dp[j];
-        const int c = q == 0 ? kd.x : q == 1 ? kd.y : q == 2 ? kd.z : kd.w;
-        if (c >= 0) v[i] = Mr[(int64_t)c * P + k];
-      }
-    } else if (e < NE) {
-      const int slot = 1 + (e - 64 * P) / P, k = (e - 64 * P) % P;
-      const int b = bx[slot];
-      if (b >= 0 && !((msk >> slot) & 1)) v[i] = Mr[(int64_t)b * P + k];
-    }
-  }
-  for (int i = tid; i < P * P; i += NT) sC[i] = Cb[i];
-  for (int i = tid; i < 4 * P; i += NT) {
-    sPre[i] = Pre[i];
-    sPost[i] = Post[i];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int e = tid + i * NT;
-    if (e < 64 * P) {
-      sK[e] = v[i] * sPre[((e / P) & 3) * P + e % P];
-    } else if (e < NE) {
-      const int e2 = e - 64 * P, slot = 1 + e2 / P;
-      sm[P + e2] = v[i] * sPre[((slot - 1) & 3) * P + e2 % P];
-    }
-  }
-  __syncthreads();
-  // A_lo from the four pre-scaled children at src + q * P
-  auto m2m = [&](const cx<T> *src, int present, int lo) {
-    cx<T> acc{T(0), T(0)};
-    const T *c = sC + lo * P;
-    for (int q = 0; q < 4; ++q) {
-      if (!((present >> q) & 1)) continue;
-      const cx<T> *a = src + q * P;
-      cx<T> sum{T(0), T(0)};
-      if constexpr (sizeof(T) == 4) {  // partly unrolled: fewer live registers
-#pragma unroll 8
-        for (int k = 0; k < P; ++k) sum = sum + c[k] * a[k];
-      } else {
-#pragma unroll
-        for (int k = 0; k < P; ++k) sum = sum + c[k] * a[k];
-      }
-      acc = acc + sPost[q * P + lo] * sum;
-    }
-    return T(0.5) * acc;
-  };
-  for (int it = tid; it < 16 * P; it += NT) {
-    const int j = it / P, lo = it % P, slot = 5 + j;
-    if (!((msk >> slot) & 1)) continue;
-    const int4 kd = dp[j];
-    const int present = (kd.x >= 0) | ((kd.y >= 0) << 1) | ((kd.z >= 0) << 2) | ((kd.w >= 0) << 3);
-    const cx<T> a = m2m(sK + 4 * j * P, present, lo);
-    sm[slot * P + lo] = a * sPre[((slot - 1) & 3) * P + lo];
-    Mr[(int64_t)bx[slot] * P + lo] = a;
-  }
-  __syncthreads();
-  for (int it = tid; it < 4 * P; it += NT) {
-    const int j = it / P, lo = it % P, slot = 1 + j;
-    if (!((msk >> slot) & 1)) continue;
-    const int g0 = 4 * slot + 1;
-    const int present = (bx[g0] >= 0) | ((bx[g0 + 1] >= 0) << 1) |
-                        ((bx[g0 + 2] >= 0) << 2) | ((bx[g0 + 3] >= 0) << 3);
-    const cx<T> a = m2m(sm + g0 * P, present, lo);
-    sm[slot * P + lo] = a * sPre[j * P + lo];
-    Mr[(int64_t)bx[slot] * P + lo] = a;
-  }
-  __syncthreads();
-  for (int lo = tid; lo < P; lo += NT) {
-    const int present = (bx[1] >= 0) | ((bx[2] >= 0) << 1) | ((bx[3] >= 0) << 2) |
-                        ((bx[4] >= 0) << 3);
-    Mr[(int64_t)bx[0] * P + lo] = m2m(sm + P, present, lo);
+// ------------------------------------------------ upward / downward passes
+template <typename T>
+struct Chunk16;
+template <>
+struct Chunk16<float> {
+  using type = float4;
+};
+template <>
+struct Chunk16<double> {
+  using type = double2;
+};
+
+// v (coefficients k, k + 1 in FP32; k in FP64) times tab[k], tab[k + 1]
+template <typename T>
+__device__ __forceinline__ void scale_chunk(typename Chunk16<T>::type &v, const cx<T> *tab,
+                                            int k) {
+  if constexpr (sizeof(T) == 4) {
+    const cx<T> a = cx<T>{v.x, v.y} * tab[k], b = cx<T>{v.z, v.w} * tab[k + 1];
+    v = make_float4(a.x, a.y, b.x, b.y);
+  } else {
+    const cx<T> a = cx<T>{v.x, v.y} * tab[k];
+    v = make_double2(a.x, a.y);
   }
 }
 
-// Downward pass over three levels per launch: one work-group per root (its
-// local expansion complete).  The own expansions (from M2L and P2L) of the
-// children and grandchildren are staged in LDS and those of the 64
-// great-grandchild slots in the registers of the threads that finish them,
-// with every load in flight at once.  Level by level, each finished parent
-// expansion b is written in four versions (delta_q/2)^l b_l, one per child
-// quadrant q, and a child's coefficient m takes
-//   b'_m = own_m + (conj(delta_q)/2)^m sum_{l >= m} C(l, m) c_{q,l}
-// (C zero below the diagonal: the fixed-length sums add exact zeros).
-template <typename T, int P>
-__global__ void __launch_bounds__(256)
-    k_l2l3(const int32_t *__restrict__ box, const T *__restrict__ Cb,
-           const cx<T> *__restrict__ Pre, const cx<T> *__restrict__ Post,
-           cx<T> *__restrict__ L, int nbox) {
-  constexpr int NT = 256, N1 = 20 * P, I1 = (N1 + NT - 1) / NT;
-  constexpr int N3 = 64 * P, I3 = (N3 + NT - 1) / NT;
-  __shared__ T sC[P * P];
+// One component of a pass program per work-group (PassProgram in tree.h),
+// for right-hand side blockIdx.y.  Its inputs are staged in LDS with every
+// load in flight at once, scaled as the program says; then its work boxes
+// are finished level by level from LDS only, each also written to E:
+//   upward    A_lo = 1/2 sum_q post[q][lo] sum_{k <= lo} C(lo, k) a~_{q,k},
+//             a~ a child's multipole times pre[q_child]; the result is kept
+//             times pre[q_box] for the box's parent
+//   downward  b_m = own_m + pre[q][m] sum_{l >= m} C(l, m) c_l, c the
+//             parent's local times post[q]; the result is passed on times
+//             post[q_child] to each child of the component
+// (C is zero off its triangle, so the fixed-length sums add exact zeros).
+// Upward, an absent child reads a slot of zeros (slot CAP), so that the
+// four quadrant sums run side by side without branches.
+constexpr int kPassThreads = 1024;
+template <typename T, int P, bool DOWN>
+__global__ void __launch_bounds__(kPassThreads)
+    k_pass(const int32_t *__restrict__ hdr, const int2 *__restrict__ ext,
+           const int4 *__restrict__ par, const int32_t *__restrict__ stp,
+           const T *__restrict__ Cb, const cx<T> *__restrict__ Pre,
+           const cx<T> *__restrict__ Post, cx<T> *__restrict__ E, int nbox) {
+  using V = typename Chunk16<T>::type;
+  constexpr int NT = kPassThreads, CAP = pass_cap(P, (int)sizeof(cx<T>));
+  static_assert(P * (int)sizeof(cx<T>) % 16 == 0, "expansions of whole 16-byte chunks");
+  constexpr int CH = P * (int)sizeof(cx<T>) / 16, IT = (CAP * CH + NT - 1) / NT;
+  constexpr int CPC = 16 / (int)sizeof(cx<T>);  // coefficients per chunk
+  __shared__ __align__(16) cx<T> sl[(CAP + 1) * P];  // expansion slots + zeros
+  __shared__ int4 spd[CAP];                          // work boxes in step order
+  __shared__ int32_t sst[kPassMaxSteps + 1];
+  __shared__ T sC[P * P];  // upward C(lo, k) at k P + lo; downward C(l, m) at l P + m
   __shared__ cx<T> sPre[4 * P], sPost[4 * P];
-  __shared__ cx<T> sl[20 * P];  // own expansions of slots 1..20
-  __shared__ cx<T> sp[64 * P];  // scaled parent versions: (parent, q)
-  const int root = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
-  const int32_t *bx = box + (int64_t)root * 85;
-  cx<T> *Lr = L + (int64_t)r * nbox * P;
-  cx<T> v[I1], w[I3], b0{T(0), T(0)};
-  if (tid < P) b0 = Lr[(int64_t)bx[0] * P + tid];
+  const int tid = threadIdx.x;
+  const int32_t *h = hdr + 8 * (int64_t)blockIdx.x;
+  const int e0 = h[0], ne = h[1], p0 = h[2], np = h[3], s0 = h[4], ns = h[5];
+  cx<T> *Er = E + (int64_t)blockIdx.y * nbox * P;
+  int2 d[IT];
+  V v[IT];
 #pragma unroll
-  for (int i = 0; i < I1; ++i) {
+  for (int i = 0; i < IT; ++i) {
     const int e = tid + i * NT;
-    v[i] = cx<T>{T(0), T(0)};
-    if (e < N1) {
-      const int b = bx[1 + e / P];
-      if (b >= 0) v[i] = Lr[(int64_t)b * P + e % P];
-    }
+    d[i] = e < ne * CH ? ext[e0 + e / CH] : make_int2(0, 0);
   }
 #pragma unroll
-  for (int i = 0; i < I3; ++i) {
+  for (int i = 0; i < IT; ++i) {
     const int e = tid + i * NT;
-    w[i] = cx<T>{T(0), T(0)};
-    if (e < N3) {
-      const int b = bx[21 + e / P];
-      if (b >= 0) w[i] = Lr[(int64_t)b * P + e % P];
-    }
+    if (e < ne * CH) v[i] = reinterpret_cast<const V *>(Er + (int64_t)d[i].x * P)[e % CH];
   }
-  for (int i = tid; i < P * P; i += NT) sC[i] = Cb[i];
+  for (int i = tid; i < np; i += NT) spd[i] = par[p0 + i];
+  for (int i = tid; i <= ns; i += NT) sst[i] = stp[s0 + i];
+  for (int i = tid; i < P * P; i += NT) sC[i] = DOWN ? Cb[i] : Cb[(i % P) * P + i / P];
   for (int i = tid; i < 4 * P; i += NT) {
     sPre[i] = Pre[i];
     sPost[i] = Post[i];
   }
+  if (tid < P) sl[CAP * P + tid] = cx<T>{T(0), T(0)};
+  __syncthreads();
 #pragma unroll
-  for (int i = 0; i < I1; ++i) {
+  for (int i = 0; i < IT; ++i) {
     const int e = tid + i * NT;
-    if (e < N1) sl[e] = v[i];
+    if (e < ne * CH) {  // slot e / CH, chunk e % CH
+      const int mode = d[i].y & 3, q = d[i].y >> 2, k = (e % CH) * CPC;
+      if (mode == 1) scale_chunk<T>(v[i], sPre + q * P, k);
+      else if (mode == 2) scale_chunk<T>(v[i], sPost + q * P, k);
+      reinterpret_cast<V *>(sl)[e] = v[i];
+    }
   }
   __syncthreads();
-  // root: four scaled versions
-  if (tid < P)
-    for (int q = 0; q < 4; ++q) sp[q * P + tid] = sPost[q * P + tid] * b0;
-  __syncthreads();
-  // translated parent expansion at coefficient m of a child in quadrant q
-  // whose parent's scaled versions start at sp + pi * 4 P
-  auto l2l = [&](int pi, int q, int m) {
-    const cx<T> *c = sp + (pi * 4 + q) * P;
-    cx<T> sum{T(0), T(0)};
+  for (int st = 0; st < ns; ++st) {
+    const int a = sst[st], b = sst[st + 1];
+    for (int it = tid; it < (b - a) * P; it += NT) {
+      const int j = a + it / P, m = it % P;
+      const int4 pd = spd[j];
+      const int box = pd.x & 0x3FFFFFFF, q = (int)((uint32_t)pd.x >> 30);
+      int s4[4] = {pd.z & 0xFFFF, (int)((uint32_t)pd.z >> 16), pd.w & 0xFFFF,
+                   (int)((uint32_t)pd.w >> 16)};
+      if constexpr (!DOWN) {
+        cx<T> sum[4];
+        const cx<T> *ak[4];
 #pragma unroll
-    for (int l = 0; l < P; ++l) sum = sum + sC[l * P + m] * c[l];
-    return sPre[q * P + m] * sum;
-  };
-  // children (slots 1..4) and grandchildren (5..20); a parent's versions
-  // sit at its index among its own level's slots.  FIRST and COUNT are
-  // compile-time constants so that res stays in registers.
-  auto level = [&](auto first_c, auto count_c) {
-    constexpr int first = decltype(first_c)::value, count = decltype(count_c)::value;
-    constexpr int NR = (count * P + NT - 1) / NT;
-    cx<T> res[NR];
+        for (int qq = 0; qq < 4; ++qq) {
+          ak[qq] = sl + (s4[qq] == kPassNone ? CAP : s4[qq]) * P;
+          sum[qq] = cx<T>{T(0), T(0)};
+        }
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      const int it = tid + i * NT;
-      res[i] = cx<T>{T(0), T(0)};
-      if (it >= count * P) continue;
-      const int s = first + it / P, m = it % P, b = bx[s];
-      if (b < 0) continue;
-      const int ps = (s - 1) >> 2, q = (s - 1) & 3;
-      // parents of this level start at slot (first - 1) / 4 (0, 1)
-      const cx<T> val = sl[(s - 1) * P + m] + l2l(ps - (first - 1) / 4, q, m);
-      Lr[(int64_t)b * P + m] = val;
-      res[i] = val;
-    }
-    __syncthreads();  // every read of sp for this level is done
+        for (int k = 0; k < P; ++k) {
+          const T c = sC[k * P + m];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      const int it = tid + i * NT;
-      if (it >= count * P) continue;
-      const int s = first + it / P, m = it % P;
-      if (bx[s] < 0) continue;
-      const int si = s - first;  // index of s among this level's slots
-      for (int q = 0; q < 4; ++q) sp[(si * 4 + q) * P + m] = sPost[q * P + m] * res[i];
+          for (int qq = 0; qq < 4; ++qq) sum[qq] = sum[qq] + c * ak[qq][k];
+        }
+        cx<T> acc = sPost[m] * sum[0];
+#pragma unroll
+        for (int qq = 1; qq < 4; ++qq) acc = acc + sPost[qq * P + m] * sum[qq];
+        const cx<T> A = T(0.5) * acc;
+        Er[(int64_t)box * P + m] = A;
+        sl[(ne + j) * P + m] = A * sPre[q * P + m];
+      } else {
+        const int own = pd.y & 0xFFFF, ver = (int)((uint32_t)pd.y >> 16);
+        cx<T> val = sl[own * P + m];
+        if (ver != kPassNone) {
+          const cx<T> *cl = sl + ver * P;
+          cx<T> s2[2] = {cx<T>{T(0), T(0)}, cx<T>{T(0), T(0)}};
+#pragma unroll
+          for (int l = 0; l < P; ++l) s2[l & 1] = s2[l & 1] + sC[l * P + m] * cl[l];
+          val = val + sPre[q * P + m] * (s2[0] + s2[1]);
+        }
+        Er[(int64_t)box * P + m] = val;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+          if (s4[qq] != kPassNone) sl[s4[qq] * P + m] = sPost[qq * P + m] * val;
+      }
     }
     __syncthreads();
-  };
-  level(std::integral_constant<int, 1>{}, std::integral_constant<int, 4>{});
-  level(std::integral_constant<int, 5>{}, std::integral_constant<int, 16>{});
-  // great-grandchildren (21..84): parents are the grandchildren (from 5)
-#pragma unroll
-  for (int i = 0; i < I3; ++i) {
-    const int e = tid + i * NT;
-    if (e >= N3) continue;
-    const int s = 21 + e / P, m = e % P, b = bx[s];
-    if (b < 0) continue;
-    const int ps = (s - 1) >> 2, q = (s - 1) & 3;
-    Lr[(int64_t)b * P + m] = w[i] + l2l(ps - 5, q, m);
+  }
+}
+
+// The rounds of a pass program, one launch each.
+template <typename T, int P, bool DOWN>
+static void run_pass(const DevPass &pg, const T *bc, const cx<T> *pre, const cx<T> *post,
+                     cx<T> *E, int nbox, int nrhs, hipStream_t s) {
+  if (pg.cap != pass_cap(P, (int)sizeof(cx<T>)))
+    throw ApiError{LBS_ERR_UNSUPPORTED, "pass program built for another expansion order"};
+  for (size_t k = 0; k + 1 < pg.round_ptr.size(); ++k) {
+    const int a = pg.round_ptr[k], n = pg.round_ptr[k + 1] - a;
+    if (n <= 0) continue;
+    hipLaunchKernelGGL((k_pass<T, P, DOWN>), dim3(n, nrhs), dim3(kPassThreads), 0, s,
+                       pg.hdr.p + 8 * (int64_t)a, reinterpret_cast<const int2 *>(pg.ext.p),
+                       reinterpret_cast<const int4 *>(pg.par.p), pg.stp.p, bc, pre, post, E,
+                       nbox);
   }
 }
 
@@ -1223,14 +1158,7 @@ static bool far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
       hipLaunchKernelGGL((k_p2m<T, P>), dim3(pl.n_leaf_s, nrhs), dim3(64), 0,
                          s, pl.leaf_s.p, pl.ls_rng.p, pl.ls_geo.p, pl.sx.p,
                          pl.sy.p, p, pl.ns, M, pl.nbox, ss);
-    for (size_t g = 0; g + 1 < pl.up_gptr.size(); ++g) {
-      const int a0 = pl.up_gptr[g], n = pl.up_gptr[g + 1] - a0;
-      if (n <= 0) continue;
-      hipLaunchKernelGGL((k_m2m3<T, P>), dim3(n, nrhs), dim3(256), 0, s,
-                         pl.up_box.p + (int64_t)a0 * 21, pl.up_mask.p + a0,
-                         pl.up_deep.p + (int64_t)a0 * 16, bc, pre, post, M,
-                         pl.nbox);
-    }
+    run_pass<T, P, false>(pl.up[sizeof(T) == 8], bc, pre, post, M, pl.nbox, nrhs, s);
   }
   // the FP32 MFMA M2L also forms the P2L sums of its boxes: every box with
   // an X list whose local expansion is used (level >= 2, with targets) is
@@ -1267,13 +1195,7 @@ static bool far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
                        pl.rad.p, pl.sx.p, pl.sy.p, p, pl.ns, L, pl.nbox);
   }
   TimerScope ts(tm, ST_L2L, s);
-  for (size_t g = 0; g + 1 < pl.dn_gptr.size(); ++g) {
-    const int a0 = pl.dn_gptr[g], n = pl.dn_gptr[g + 1] - a0;
-    if (n <= 0) continue;
-    hipLaunchKernelGGL((k_l2l3<T, P>), dim3(n, nrhs), dim3(256), 0, s,
-                       pl.dn_box.p + (int64_t)a0 * 85, bc, pre, post, L,
-                       pl.nbox);
-  }
+  run_pass<T, P, true>(pl.dn[sizeof(T) == 8], bc, pre, post, L, pl.nbox, nrhs, s);
   return gamma_done;
 }
 

@@ -84,6 +84,14 @@ struct DBuf {
   }
 };
 
+// A pass program on the device (PassProgram in tree.h): its LDS capacity,
+// the host ranges of the rounds and the component tables.
+struct DevPass {
+  int cap = 0;
+  std::vector<int32_t> round_ptr;
+  DBuf<int32_t> hdr, ext, par, stp;
+};
+
 // Quadtree and lists on the device (one FMM plan).
 // A target leaf as the leaf kernels see it (one per work-group): its
 // target range, the range of its flattened U-list sources, its W-list
@@ -124,18 +132,9 @@ struct DevPlan {
   DBuf<int32_t> m2l_wave;  // M2L boxes in the FP32 kernel's wave order
   int n_x = 0;
   DBuf<int32_t> x_box;                       // boxes with an X list
-  // Upward (M2M) and downward (L2L) passes, three levels per launch: one
-  // work-group per root box holding its subtree as a 4-ary heap (slot 0 the
-  // root, 4 s + 1 + q the child in quadrant q of slot s; -1 = absent).
-  // Upward roots: boxes with sources and children at levels 2, 5, 8, ...;
-  // slots 0..20 (box, bit s of up_mask set when slot s has children) and,
-  // for the grandchildren, their children by quadrant (box or -1).
-  // Downward roots: boxes with targets and children at the same levels;
-  // slots 0..84 (boxes with targets).  Launch order: up_gptr bottom-up,
-  // dn_gptr top-down (host ranges of roots).
-  std::vector<int32_t> up_gptr, dn_gptr;
-  DBuf<int32_t> up_box, up_mask, dn_box;
-  DBuf<int4> up_deep;
+  // Upward (M2M) and downward (L2L) pass programs (PassProgram in tree.h)
+  // for the FP32 ([0]) and FP64 ([1]) expansion orders of the handle.
+  DevPass up[2], dn[2];
   // points in tree order
   DBuf<double> sx, sy, tx, ty;
   DBuf<int64_t> src_perm, tgt_perm;

@@ -82,4 +82,44 @@ void append_tree(Tree &F, const Tree &t, int64_t src_base, int64_t tgt_base,
 // covered zero or several times by U, V, W and X.  O(leaves^2 depth).
 int64_t check_coverage(const Tree &T);
 
+// Program of the upward (M2M) or downward (L2L) pass (passes.cpp): the
+// work boxes cut into components of at most `cap` LDS expansion slots, one
+// work-group each, launched round by round.
+//   hdr  8 per component: ext offset, #ext, par offset, #par, stp offset,
+//        #steps, root box, round
+//   ext  2 per input slot (slots 0, 1, ...): box, mode | q << 2; the input
+//        is the box's expansion, times pre[q] (mode 1), post[q] (mode 2)
+//        or as it is (mode 0)
+//   par  4 per work box, in step order: box | quadrant << 30, then
+//        upward:   0, and the slots of its children by quadrant (16 bits
+//                  each, kPassNone absent); its own result goes to slot
+//                  #ext + its index
+//        downward: own-part slot | parent-version slot << 16, and the
+//                  slots its children's parent versions go to, by quadrant
+//   stp  per component, #steps + 1 offsets into its par entries (one step
+//        per level: deepest first upward, shallowest first downward)
+constexpr int kPassNone = 0xFFFF;
+constexpr int kPassMaxSteps = 31;
+struct PassProgram {
+  int cap = 0, ncomp = 0;
+  bool down = false;
+  std::vector<int32_t> round_ptr;  // components of round k: [rp[k], rp[k+1])
+  std::vector<int32_t> hdr, ext, par, stp;
+};
+void build_pass_program(const Tree &T, bool down, int cap, PassProgram &pp);
+
+// Errors found by running the program on the host with scalar stand-ins
+// for the expansions (0: every work box computed once, from inputs that
+// were final or written by then, with the right result).
+int64_t check_pass_program(const Tree &T, const PassProgram &pp);
+
+// LDS expansion slots per work-group of the pass kernels for expansions of
+// P coefficients of cbytes bytes each (8: FP32, 16: FP64), within 60 KB with
+// the binomial and scale tables and the step descriptors.
+constexpr int pass_cap(int P, int cbytes) {
+  const int fixed = P * P * (cbytes / 2) + 9 * P * cbytes + 128;  // + a slot of zeros
+  const int c = (61440 - fixed) / (P * cbytes + 16);
+  return (c > 1024 ? 1024 : c) & ~7;
+}
+
 }  // namespace lbs

@@ -162,6 +162,11 @@ def load():
                                     vp, vp, vp, vp]
     lib.lbs_vortex_field.argtypes = [H, ctypes.c_int32, ctypes.c_int32, vp,
                                      vp, ctypes.c_int64, vp, vp, vp]
+    lib.lbs_check_passes_host.argtypes = [c_double_p, c_double_p,
+                                          ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int32)]
     lib.lbs_compare_trees.argtypes = [vp, vp, ctypes.c_int64, vp, vp,
                                       ctypes.c_int64, ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_int64),
@@ -171,7 +176,7 @@ def load():
         ctypes.c_double, c_double_p, ctypes.POINTER(ctypes.c_int32)]
     for name in ("lbs_refine_tolerances_host", "lbs_setup_sampled",
                  "lbs_vortex_data", "lbs_vortex_field", "lbs_matvec_noalloc",
-                 "lbs_compare_trees",
+                 "lbs_compare_trees", "lbs_check_passes_host",
                  "lbs_resample_curve_host", "lbs_setup", "lbs_sizes",
                  "lbs_nodes", "lbs_matvec", "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
                  "lbs_stage_timing", "lbs_stage_times", "lbs_setup_batch",
@@ -496,6 +501,19 @@ def compare_trees(x, y, leaf_max, tx=None, ty=None):
         None if ty is None else _dev(ty), nt, int(leaf_max), ctypes.byref(bad),
         ctypes.byref(lev), _stream()))
     return bad.value, lev.value
+
+
+def check_passes_host(x, y, leaf_max, cap):
+    """lbs_check_passes_host: (errors, (upward rounds, downward rounds))."""
+    import numpy as np
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    bad = ctypes.c_int64()
+    rounds = (ctypes.c_int32 * 2)()
+    _check(load().lbs_check_passes_host(
+        x.ctypes.data_as(c_double_p), y.ctypes.data_as(c_double_p), len(x),
+        int(leaf_max), int(cap), ctypes.byref(bad), rounds))
+    return bad.value, (rounds[0], rounds[1])
 
 
 def check_tree_host(x, y, leaf_max):

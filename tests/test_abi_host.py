@@ -41,7 +41,7 @@ def test_default_options(lbs):
     o = lbs.default_options()
     assert (o.p64, o.p32, o.restart) == (30, 16, 50)
     assert o.inner_tol == 1e-5
-    assert (o.matvec, o.graphs, o.precond, o.close_eval) == (0, 1, 1, 1)
+    assert (o.matvec, o.graphs, o.precond, o.close_eval, o.gpu_tree) == (0, 1, 1, 1, 1)
 
 
 def test_refinement_step_rejects_non_finite_residuals(lbs):
@@ -155,3 +155,38 @@ def test_deep_tree_geometry_levels_and_coverage(lbs):
         bad, st = lbs.check_tree_host(cv.xi.real, cv.xi.imag, lm)
         assert bad == 0
         assert st["levels"] >= 21, st
+
+
+@pytest.mark.parametrize("case", ["stars", "deep", "uniform", "coincident"])
+def test_pass_programs_compute_every_box_once_in_order(lbs, case):
+    """The upward / downward pass programs (components of at most `cap` LDS
+    slots, launched round by round) run on the host with scalar stand-ins:
+    every multipole ends as its box's source count, every local as its
+    box's level, from inputs that were final or written by then; the
+    capacities 16 .. 408 span the FP64 and FP32 kernels' (40 .. 408)."""
+    if case == "stars":
+        xi = Curves(synth.star_islands(40, 30, (0.05, 0.2), nodes=128)).xi
+        x, y = xi.real, xi.imag
+    elif case == "deep":
+        xi = Curves(synth.deep_tree_islands(128)).xi
+        x, y = xi.real, xi.imag
+    elif case == "uniform":
+        x, y = np.random.default_rng(1).uniform(-1, 1, (2, 20000))
+    else:  # five coincident points: a chain of boxes to the deepest level
+        x = np.array([0.25] * 5 + [-0.5])
+        y = np.array([0.75] * 5 + [0.1])
+    for lm in (1, 8, 64):
+        for cap in (16, 40, 96, 408):
+            bad, rounds = lbs.check_passes_host(x, y, lm, cap)
+            assert bad == 0, (lm, cap)
+            assert min(rounds) >= 1
+
+
+def test_pass_programs_need_few_rounds(lbs):
+    """Larger components take fewer launches: at the FP32 kernel's capacity
+    a clustered star geometry needs at most two rounds each way, fewer than
+    its quadtree has levels by far."""
+    xi = Curves(synth.star_islands(40, 30, (0.05, 0.2), nodes=128)).xi
+    _, st = lbs.check_tree_host(xi.real[:2000], xi.imag[:2000], 1)
+    bad, rounds = lbs.check_passes_host(xi.real, xi.imag, 1, 408)
+    assert bad == 0 and max(rounds) <= 2 and st["levels"] >= 8
