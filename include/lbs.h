@@ -451,6 +451,14 @@ lbs_status lbs_check_tree_host(const double *x_host, const double *y_host,
                                int64_t *bad_pairs_host,
                                lbs_tree_stats *stats_host);
 
+/* Check of the Schur-complement inverse of the preconditioner (eq.
+ * matrix_eqns_c): rebuilds every geometry's block S_g and returns in
+ * *err_host the largest |S_g (S_g^-1 e_j) - e_j| over ncols unit vectors
+ * e_j spread evenly over each block's columns (the GPU inverse from the
+ * blocked Gauss-Jordan elimination of set-up).  Synchronous. */
+lbs_status lbs_schur_residual(lbs_handle h, int32_t ncols, double *err_host,
+                              void *stream);
+
 /* Host-only check of the upward (M2M) and downward (L2L) pass programs (no
  * GPU needed): builds the tree of n planar points as lbs_check_tree_host
  * does, cuts its work boxes into components of at most cap LDS expansion

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -16,6 +18,26 @@
 #include <vector>
 
 #include "lbs_internal.h"
+
+// Wall-clock phases of the host-side set-up work, printed to stderr when
+// the environment variable LBS_HOST_TIMING is set (a plan's phases, in ms).
+namespace {
+bool host_timing() {
+  static const bool on = std::getenv("LBS_HOST_TIMING") != nullptr;
+  return on;
+}
+struct HostPhase {
+  const char *name;
+  std::chrono::steady_clock::time_point t0;
+  explicit HostPhase(const char *n) : name(n), t0(std::chrono::steady_clock::now()) {}
+  ~HostPhase() {
+    if (!host_timing()) return;
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    std::fprintf(stderr, "[lbs host] %-28s %9.3f ms\n", name, ms);
+  }
+};
+}  // namespace
 
 using namespace lbs;
 
@@ -58,6 +80,7 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
                  const double *tx, const double *ty,
                  const std::vector<int64_t> *tgt_index, DevPlan &pl,
                  hipStream_t s) {
+  HostPhase ph_plan("upload_plan");
   const int nb = T.nbox();
   pl.nbox = nb;
   pl.nlevels = T.nlevels;
@@ -163,6 +186,7 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
     return fp;
   };
   {
+    HostPhase ph("upload_plan U sources");
     const std::vector<int64_t> ufp = flat_sources(T.u_ptr, T.u_src, pl.uf_ptr, pl.uf_idx);
     std::vector<LeafHdr> hd(leaf_t.size());
     for (size_t i = 0; i < leaf_t.size(); ++i) {
@@ -228,6 +252,7 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
 // Upward / downward pass programs of the plan's tree for FP32 order p32
 // and FP64 order p64 (the LDS capacity of the pass kernels depends on it).
 void build_passes(DevPlan &pl, int p32, int p64, hipStream_t s) {
+  HostPhase ph("pass programs");
   for (int k = 0; k < 2; ++k) {
     const int cap = k == 0 ? pass_cap(p32, 8) : pass_cap(p64, 16);
     for (int d = 0; d < 2; ++d) {
@@ -1073,6 +1098,7 @@ std::vector<lbs_island> sampled_islands(const Samples &sm, int M,
 lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl_in,
                     const int32_t *nodes, const lbs_options *opt,
                     hipStream_t s, const Samples *sm = nullptr) {
+  HostPhase ph_all("setup (all)");
   auto ctx = std::make_unique<lbs_ctx>();
   lbs_default_options(&ctx->opt);
   if (opt) ctx->opt = *opt;
@@ -1295,6 +1321,7 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl_in
     g.nearRT_idx.upload(ti, s);
   }
   // quadtree forest over the node images (one tree per geometry)
+  HostPhase ph_tree("setup tree + plan");
   ctx->xi_x.resize(N);
   ctx->xi_y.resize(N);
   for (int64_t i = 0; i < N; ++i) {
@@ -1367,8 +1394,10 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl_in
     DBuf<double> S;
     S.alloc((size_t)g.gsinv[G]);
     g.Sinv.alloc((size_t)g.gsinv[G]);
+    HostPhase ph("setup Schur + inverse");
     launch_build_schur(g, S.p, s);
     invert_blocks(g, S.p, g.Sinv.p, s);
+    if (host_timing()) LBS_HIP(hipStreamSynchronize(s));
   }
   ensure_ws(*ctx, 1);
   LBS_HIP(hipHostMalloc((void **)&ctx->count_host, 2 * sizeof(int32_t), hipHostMallocDefault));
@@ -1382,6 +1411,7 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
   Geometry &g = c.geo;
   const int G = g.G;
   const int64_t T = toff[G];
+  HostPhase ph_all("eval plan (all)");
   std::vector<double> hx(3 * T);
   LBS_HIP(hipMemcpyAsync(hx.data(), txyz, 3 * T * sizeof(double), hipMemcpyDeviceToHost, s));
   LBS_HIP(hipStreamSynchronize(s));
@@ -1411,6 +1441,7 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
   if (n > 0 && (transposed || c.opt.matvec != LBS_MATVEC_DIRECT)) {
     Tree &F = ep->pl.host;
     if (G == 1 && c.opt.gpu_tree) {
+      HostPhase ph("eval plan tree (GPU)");
       DBuf<double> dtx, dty;
       dtx.upload(ep->tx, s);
       dty.upload(ep->ty, s);
@@ -1434,6 +1465,7 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
         else append_tree(F, t, a, ta, a, ta);
       }
     }
+    HostPhase ph_up("eval plan upload");
     if (transposed) {
       upload_plan(F, ep->tx.data(), ep->ty.data(), c.xi_x.data(), c.xi_y.data(), nullptr,
                   ep->pl, s);
@@ -1449,7 +1481,10 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
     ep->ws.ensure(ep->pl, c.opt.p64, c.opt.p32, 1, g.N, g.M, G, kPlog);
     ep->tree = true;
   }
-  if (c.opt.close_eval && n > 0) build_close(c, *ep, hx, s);
+  if (c.opt.close_eval && n > 0) {
+    HostPhase ph("eval plan close pairs");
+    build_close(c, *ep, hx, s);
+  }
   LBS_HIP(hipStreamSynchronize(s));
   ep->key = std::move(hx);
   slot = std::move(ep);
@@ -2167,6 +2202,40 @@ lbs_status lbs_tree_info(lbs_handle h, lbs_tree_stats *st) {
     check_handle(h);
     if (!st) fail(LBS_ERR_INVALID_ARG, "stats is NULL");
     fill_stats(h->plan.host, st);
+  });
+}
+
+lbs_status lbs_schur_residual(lbs_handle h, int32_t ncols, double *err, void *stream) {
+  return guard([&] {
+    check_handle(h);
+    if (!err || ncols < 1) fail(LBS_ERR_INVALID_ARG, "err is NULL or ncols < 1");
+    hipStream_t s = (hipStream_t)stream;
+    const Geometry &g = h->geo;
+    *err = 0.0;
+    if (g.M == 0) return;
+    // X: column r holds, in every geometry block, the unit vector of local
+    // island (r * Mg) / ncols; Y = S (Sinv X) - X
+    std::vector<double> X((size_t)g.M * ncols, 0.0);
+    for (int r = 0; r < ncols; ++r)
+      for (int q = 0; q < g.G; ++q) {
+        const int m0 = g.gisl[q], Mg = g.gisl[q + 1] - m0;
+        X[(size_t)r * g.M + m0 + (int)((int64_t)r * Mg / ncols)] = 1.0;
+      }
+    DBuf<double> S, dX, Y1, Y2;
+    S.alloc((size_t)g.gsinv[g.G]);
+    launch_build_schur(g, S.p, s);
+    dX.upload(X, s);
+    Y1.alloc(X.size());
+    Y2.alloc(X.size());
+    launch_gemv_blocks_with(g, g.Sinv.p, dX.p, g.M, ncols, Y1.p, g.M, 1.0, s);
+    launch_gemv_blocks_with(g, S.p, Y1.p, g.M, ncols, Y2.p, g.M, 1.0, s);
+    const std::vector<double> y = Y2.download(s);
+    double e = 0.0;
+    for (size_t i = 0; i < y.size(); ++i) {
+      const double d = std::fabs(y[i] - X[i]);
+      if (!(d <= e)) e = d;  // NaN propagates
+    }
+    *err = e;
   });
 }
 

@@ -6,8 +6,10 @@
 // numbered geometry-major, and every operator below acts on each geometry
 // separately (a block-diagonal system).
 #include <cmath>
+#include <type_traits>
 
 #include "cplx.h"
+
 #include "lbs_internal.h"
 
 namespace lbs {
@@ -403,265 +405,393 @@ void launch_build_schur(const Geometry &g, double *S, hipStream_t s) {
   LBS_HIP(hipGetLastError());
 }
 
-// Blocked Gauss-Jordan inversion with partial pivoting of every geometry's
-// block S_g at once, on the augmented rows [A | B] = [S_g | I] (B becomes
-// S_g^-1).  Panel J = columns j0 .. j0 + nb - 1 (nb <= kGJ):
-//  1. k_gj_panel (one work-group per geometry): copy the column block
-//     A[:, J] column-major twice (P, C), factor P[j0:, :] = Pi L U by
-//     partial pivoting (the row swaps applied to C as well), and form
-//     Binv = (L U)^-1 of the nb x nb pivot block;
-//  2. k_gj_swap: apply the panel's row swaps to the other columns of
-//     [A | B];
-//  3. k_gj_w: W = Binv [A | B][J, :] (the new pivot rows);
-//  4. k_gj_update: rows J <- W, every other row i -= C_i W (C_i: row i of
-//     the swapped column block, its elimination factors).
-// The columns of A before the panel are identity columns already and are
-// left alone; the update is a rank-nb product over the remaining columns
-// (2 M_g^3 flops in all).  Grid z = geometry; geometries with M_g <= j0
-// return at once.
-constexpr int kGJ = 32;
+// Blocked Gauss-Jordan inversion with partial pivoting, in place, of every
+// geometry's block S_g at once (grid z or x = geometry).  Panel J = rows and
+// columns j0 .. j0 + nb - 1 of the rows not yet eliminated:
+//  1. k_gjp_panel (one work-group per geometry, the panel rows j0.. held in
+//     registers, RPT rows per thread): LU with partial pivoting of
+//     S[j0:, J], of which the pivot rows are kept, then Binv = S_JJ^-1 of
+//     the pivoted block by Gauss-Jordan elimination without further
+//     interchanges (its pivots are those of the LU);
+//  2. k_gjp_swap: the pivot rows exchanged over whole rows;
+//  3. k_gjp_rows: R = S[J, :] (the pivot rows as they are) and W = Binv R;
+//     k_gjp_cols: Cn_i = -S[i, J] Binv for the rows i outside J;
+//  4. k_gjp_update: S_ij += Cn_i R_j (i, j outside J), S_iJ = Cn_i,
+//     S_Jj = W_j, S_JJ = Binv.
+// After the last panel, S holds (Pi S)^-1 for the row interchanges Pi, and
+// the inverse is its columns permuted back (k_gjp_unpermute).  The panel
+// width is 32 / RPT so that each thread keeps 32 values; RPT = 1, 2, 4 or
+// 8 serves panels of up to 1024 RPT rows (at most 8192 islands).
+constexpr int kGJ = 32;     // widest panel
+constexpr int kGJT = 1024;  // threads of the panel kernel
 
-__global__ void __launch_bounds__(1024)
-    k_gj_panel(int j0, const int32_t *__restrict__ gisl,
-               const int64_t *__restrict__ gsinv, const double *__restrict__ A,
-               double *__restrict__ Pc, double *__restrict__ C,
-               int *__restrict__ piv, double *__restrict__ Binv, int maxM) {
-  __shared__ double bv[16];
-  __shared__ int bi[17];
-  __shared__ double prow[kGJ];
-  __shared__ double lu[kGJ][kGJ + 1];
+// Pivot key of row r (offset ro = r - j0 < 8192) with value a = |v|: the
+// bits of a with the low 13 replaced by 8191 - ro, so that the largest key
+// is the largest |v| (compared to 39 bits of its mantissa), the lowest row
+// among those.  Bit 13 is set so that every candidate's key exceeds the 0
+// of the rows that are not candidates.
+__device__ __forceinline__ unsigned long long pivot_key(double a, int ro) {
+  return ((unsigned long long)__double_as_longlong(a) & ~0x1FFFull) | (1ull << 13) |
+         (unsigned long long)(8191 - ro);
+}
+
+// Largest value over the 64 lanes of a wave, by the device library's wave
+// reduction (DPP row and cross-row steps; the header declares it only with
+// the optional 64-bit warp-sync types enabled).
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_max_u64(
+    unsigned long long);
+
+// Binv (kGJ x kGJ, entries past nb 0) = S_JJ^-1 of the pivoted block whose
+// rows came from rows blk_row[0:nb] of S (columns j0..), by Gauss-Jordan
+// elimination without interchanges, one entry per thread (its pivots are
+// those the panel LU chose).  Kept out of line so that the panel loop's
+// registers are not shared with it.
+template <int NB>
+__device__ __noinline__ void pivot_block_inverse(const double *__restrict__ Sg, int Mg, int j0,
+                                                 int nb, const int *blk_row,
+                                                 double (*bl)[NB + 1],
+                                                 double *__restrict__ Binv) {
+  const int tid = threadIdx.x;
+  const int bi = tid / NB, bj = tid % NB;  // NB <= 32: threads past NB^2 idle
+  const bool live = tid < NB * NB && bi < nb && bj < nb;
+  if (tid < NB * NB) bl[bi][bj] = live ? Sg[(int64_t)blk_row[bi] * Mg + j0 + bj] : 0.0;
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    double x = 0.0;
+    if (live) {
+      const double pinv = 1.0 / bl[k][k];
+      x = bl[bi][bj];
+      if (bi == k && bj == k) x = pinv;
+      else if (bi == k) x = x * pinv;
+      else if (bj == k) x = -x * pinv;
+      else x = x - bl[bi][k] * bl[k][bj] * pinv;
+    }
+    __syncthreads();
+    if (live) bl[bi][bj] = x;
+    __syncthreads();
+  }
+  if (tid < kGJ * kGJ) {
+    const int a = tid / kGJ, b = tid % kGJ;
+    Binv[a * kGJ + b] = (a < nb && b < nb) ? bl[a][b] : 0.0;
+  }
+}
+
+template <int RPT>
+__global__ void __launch_bounds__(kGJT)
+    k_gjp_panel(int j0, const int32_t *__restrict__ gisl, const int64_t *__restrict__ gsinv,
+                const double *__restrict__ S, int *__restrict__ piv,
+                double *__restrict__ Binv, int maxM) {
+  constexpr int NB = kGJ / RPT;
+  __shared__ unsigned long long wk[16];
+  __shared__ double prow[NB], crow[NB];
+  __shared__ int prow_id, crow_id, blk_row[NB];
+  __shared__ double bl[NB][NB + 1];
   const int g = blockIdx.x;
   const int Mg = gisl[g + 1] - gisl[g];
   if (j0 >= Mg) return;
-  const int nb = min(kGJ, Mg - j0);
-  const int tid = threadIdx.x;
-  const double *Ag = A + gsinv[g];
-  // the column block, column-major (entry (r, k) at k maxM + r), twice: P
-  // is factored, C keeps the values (both get the row swaps)
-  double *P = Pc + (int64_t)g * kGJ * maxM;
-  double *Cg = C + (int64_t)g * kGJ * maxM;
-  for (int64_t e = tid; e < (int64_t)Mg * nb; e += 1024) {
-    const int r = (int)(e / nb), k = (int)(e % nb);
-    const double v = Ag[(int64_t)r * Mg + j0 + k];
-    P[(int64_t)k * maxM + r] = v;
-    Cg[(int64_t)k * maxM + r] = v;
+  const int nb = min(NB, Mg - j0), tid = threadIdx.x;
+  const double *Sg = S + gsinv[g];
+  int orig[RPT];  // the row of S each register row started as
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) orig[i] = j0 + tid + kGJT * i;
+  // v[i][q]: row j0 + tid + kGJT i, column k + q of the panel at step k
+  // (finished columns are shifted out, so that every index into v is a
+  // compile-time constant and v stays in registers)
+  double v[RPT][NB];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = j0 + tid + kGJT * i;
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+      v[i][q] = (r < Mg && q < nb) ? Sg[(int64_t)r * Mg + j0 + q] : 0.0;
   }
-  __syncthreads();
+#pragma unroll 1
   for (int k = 0; k < nb; ++k) {
     const int c = j0 + k;
-    const double *Pk = P + (int64_t)k * maxM;
-    double best = -1.0;
-    int at = c;
-    for (int r = c + tid; r < Mg; r += 1024) {
-      const double v = fabs(Pk[r]);
-      if (v > best) {
-        best = v;
-        at = r;
+    unsigned long long key = 0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = j0 + tid + kGJT * i;
+      if (r >= c && r < Mg) {
+        const unsigned long long kk = pivot_key(fabs(v[i][0]), r - j0);
+        key = kk > key ? kk : key;
       }
     }
-    // largest |P[r][k]| (smallest r on ties): within each wave by
-    // shuffles, then across the 16 waves by the first wave
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(at, o, 64);
-      if (ov > best || (ov == best && oi < at)) {
-        best = ov;
-        at = oi;
+    key = __ockl_wfred_max_u64(key);
+    if ((tid & 63) == 0) wk[tid >> 6] = key;
+    __syncthreads();
+    // every wave reduces the 16 wave maxima itself
+    key = __ockl_wfred_max_u64(wk[tid & 15]);
+    const int p = j0 + 8191 - (int)(key & 0x1FFFull);
+    // exchange rows c and p through LDS
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = j0 + tid + kGJT * i;
+      if (r == p) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) prow[q] = v[i][q];
+        prow_id = orig[i];
+      }
+      if (r == c) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) crow[q] = v[i][q];
+        crow_id = orig[i];
       }
     }
-    if ((tid & 63) == 0) {
-      bv[tid >> 6] = best;
-      bi[tid >> 6] = at;
-    }
     __syncthreads();
-    if (tid < 64) {
-      best = tid < 16 ? bv[tid] : -1.0;
-      at = tid < 16 ? bi[tid] : Mg;
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(at, o, 64);
-        if (ov > best || (ov == best && oi < at)) {
-          best = ov;
-          at = oi;
-        }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = j0 + tid + kGJT * i;
+      if (r == p && r != c) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) v[i][q] = crow[q];
+        orig[i] = crow_id;
+      } else if (r == c) {
+        orig[i] = prow_id;
       }
-      if (tid == 0) bi[16] = at;
     }
-    __syncthreads();
-    const int p = bi[16];
-    if (tid < nb) {  // swap rows c and p (thread = column), keep the pivot row
-      double *Pq = P + (int64_t)tid * maxM, *Cq = Cg + (int64_t)tid * maxM;
-      const double a = Pq[c], b = Pq[p];
-      Pq[c] = b;
-      Pq[p] = a;
-      prow[tid] = b;
-      const double ca = Cq[c];
-      Cq[c] = Cq[p];
-      Cq[p] = ca;
+    // eliminate below the pivot and shift the column out (prow, crow and
+    // wk are rewritten only after the next column's first barrier)
+    const double inv = 1.0 / prow[0];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = j0 + tid + kGJT * i;
+      if (r > c && r < Mg) {
+        const double l = v[i][0] * inv;
+#pragma unroll
+        for (int q = 1; q < NB; ++q) v[i][q] -= l * prow[q];
+      }
+#pragma unroll
+      for (int q = 0; q + 1 < NB; ++q) v[i][q] = v[i][q + 1];
     }
-    if (tid == 0) piv[g * kGJ + k] = p;
-    __syncthreads();
-    const double inv = 1.0 / prow[k];
-    for (int r = c + 1 + tid; r < Mg; r += 1024) {
-      const double l = P[(int64_t)k * maxM + r] * inv;
-      P[(int64_t)k * maxM + r] = l;
-      for (int q = k + 1; q < nb; ++q) P[(int64_t)q * maxM + r] -= l * prow[q];
-    }
-    __syncthreads();
+    if (tid == 0) piv[(int64_t)g * maxM + c] = p;
   }
-  // Binv = U^-1 L^-1 of the pivot block (unit lower L, upper U)
-  for (int e = tid; e < nb * nb; e += 1024) {
-    const int i = e / nb, q = e % nb;
-    lu[i][q] = P[(int64_t)q * maxM + j0 + i];
+  // Binv = S_JJ^-1 of the pivoted block, read from the rows of S it came
+  // from, by Gauss-Jordan elimination without interchanges (one entry per
+  // thread; its pivots are those just chosen)
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = j0 + tid + kGJT * i;
+    if (r < j0 + nb) blk_row[r - j0] = orig[i];
   }
   __syncthreads();
-  if (tid < nb) {
-    const int col = tid;
-    double y[kGJ];
-    for (int i = 0; i < nb; ++i) {  // L y = e_col
-      double v = (i == col) ? 1.0 : 0.0;
-      for (int q = 0; q < i; ++q) v -= lu[i][q] * y[q];
-      y[i] = v;
-    }
-    for (int i = nb - 1; i >= 0; --i) {  // U x = y
-      double v = y[i];
-      for (int q = i + 1; q < nb; ++q) v -= lu[i][q] * y[q];
-      y[i] = v / lu[i][i];
-    }
-    for (int i = 0; i < nb; ++i) Binv[((int64_t)g * kGJ + i) * kGJ + col] = y[i];
-  }
+  pivot_block_inverse<NB>(Sg, Mg, j0, nb, blk_row, bl, Binv + (int64_t)g * kGJ * kGJ);
 }
 
-// column c of [A | B] (c < M_g: A, else B): the panel's swaps in order;
-// the panel's own columns are already swapped
+// column c of S_g: the panel's row interchanges in order
 __global__ void __launch_bounds__(256)
-    k_gj_swap(int j0, const int32_t *__restrict__ gisl,
-              const int64_t *__restrict__ gsinv, double *__restrict__ A,
-              double *__restrict__ B, const int *__restrict__ piv) {
+    k_gjp_swap(int j0, int NB, const int32_t *__restrict__ gisl,
+               const int64_t *__restrict__ gsinv, double *__restrict__ S,
+               const int *__restrict__ piv, int maxM) {
   const int g = blockIdx.z;
   const int Mg = gisl[g + 1] - gisl[g];
   if (j0 >= Mg) return;
-  const int nb = min(kGJ, Mg - j0);
+  const int nb = min(NB, Mg - j0);
   const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= 2 * Mg || (c >= j0 && c < j0 + nb)) return;
-  double *X = (c < Mg ? A : B) + gsinv[g];
-  const int cc = c < Mg ? c : c - Mg;
+  if (c >= Mg) return;
+  double *X = S + gsinv[g];
   for (int k = 0; k < nb; ++k) {
-    const int p = piv[g * kGJ + k];
+    const int p = piv[(int64_t)g * maxM + j0 + k];
     if (p == j0 + k) continue;
-    const double t = X[(int64_t)(j0 + k) * Mg + cc];
-    X[(int64_t)(j0 + k) * Mg + cc] = X[(int64_t)p * Mg + cc];
-    X[(int64_t)p * Mg + cc] = t;
+    const double t = X[(int64_t)(j0 + k) * Mg + c];
+    X[(int64_t)(j0 + k) * Mg + c] = X[(int64_t)p * Mg + c];
+    X[(int64_t)p * Mg + c] = t;
   }
 }
 
-// W[k][c] = sum_q Binv[k][q] [A | B][j0 + q][c] for the columns still to
-// update (A: c >= j0 + nb; B: all).
+// Work-group of 32 columns c: R[k][c] = S[j0 + k][c] (the pivot rows as
+// they are) and W[k][c] = sum_q Binv[k][q] R[q][c], k < nb.
 __global__ void __launch_bounds__(256)
-    k_gj_w(int j0, const int32_t *__restrict__ gisl,
-           const int64_t *__restrict__ gsinv, const double *__restrict__ A,
-           const double *__restrict__ B, const double *__restrict__ Binv,
-           double *__restrict__ W, int maxM) {
+    k_gjp_rows(int j0, int NB, const int32_t *__restrict__ gisl,
+               const int64_t *__restrict__ gsinv, const double *__restrict__ S,
+               const double *__restrict__ Binv, double *__restrict__ R,
+               double *__restrict__ W, int maxM) {
   __shared__ double bl[kGJ][kGJ + 1];
+  __shared__ double rt[kGJ][33];
   const int g = blockIdx.z;
   const int Mg = gisl[g + 1] - gisl[g];
   if (j0 >= Mg) return;
-  const int nb = min(kGJ, Mg - j0);
+  const int nb = min(NB, Mg - j0);
+  const int c0 = blockIdx.x * 32;
+  if (c0 >= Mg) return;
+  const double *X = S + gsinv[g];
+  for (int e = threadIdx.x; e < kGJ * kGJ; e += 256) {
+    const int a = e / kGJ, b = e % kGJ, c = c0 + b;
+    rt[a][b] = (a < nb && c < Mg) ? X[(int64_t)(j0 + a) * Mg + c] : 0.0;
+  }
   for (int e = threadIdx.x; e < kGJ * kGJ; e += 256)
     bl[e / kGJ][e % kGJ] = Binv[(int64_t)g * kGJ * kGJ + e];
   __syncthreads();
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= 2 * Mg || t < j0 + nb) return;
-  const double *X = (t < Mg ? A : B) + gsinv[g];
-  const int cc = t < Mg ? t : t - Mg;
-  double col[kGJ];
-  for (int q = 0; q < nb; ++q) col[q] = X[(int64_t)(j0 + q) * Mg + cc];
-  double *Wg = W + (int64_t)g * kGJ * 2 * maxM;
-  for (int k = 0; k < nb; ++k) {
-    double v = 0.0;
-    for (int q = 0; q < nb; ++q) v += bl[k][q] * col[q];
-    Wg[(int64_t)k * 2 * maxM + t] = v;
+  double *Rg = R + (int64_t)g * kGJ * maxM, *Wg = W + (int64_t)g * kGJ * maxM;
+  for (int e = threadIdx.x; e < nb * 32; e += 256) {
+    const int k = e / 32, cl = e % 32, c = c0 + cl;
+    if (c >= Mg) continue;
+    double t = 0.0;
+    for (int q = 0; q < nb; ++q) t += bl[k][q] * rt[q][cl];
+    Rg[(int64_t)k * maxM + c] = rt[k][cl];
+    Wg[(int64_t)k * maxM + c] = t;
   }
 }
 
-// Tiles of 64 rows x 64 columns of [A | B], 4 x 4 per thread: rows of the
-// panel take W, every other row r subtracts C_r W.
+// Work-group of 32 rows i outside J: Cn[k][i] = -sum_q S[i][j0 + q] Binv[q][k].
 __global__ void __launch_bounds__(256)
-    k_gj_update(int j0, const int32_t *__restrict__ gisl,
-                const int64_t *__restrict__ gsinv, double *__restrict__ A,
-                double *__restrict__ B, const double *__restrict__ W,
-                const double *__restrict__ F, int maxM) {
-  __shared__ double fs[64][kGJ + 1];
-  __shared__ double ws[kGJ][64 + 1];
+    k_gjp_cols(int j0, int NB, const int32_t *__restrict__ gisl,
+               const int64_t *__restrict__ gsinv, const double *__restrict__ S,
+               const double *__restrict__ Binv, double *__restrict__ Cn, int maxM) {
+  __shared__ double bl[kGJ][kGJ + 1];
+  __shared__ double at[32][kGJ + 1];
   const int g = blockIdx.z;
   const int Mg = gisl[g + 1] - gisl[g];
   if (j0 >= Mg) return;
-  const int nb = min(kGJ, Mg - j0);
+  const int nb = min(NB, Mg - j0);
+  const int i0 = blockIdx.x * 32;
+  if (i0 >= Mg) return;
+  const double *X = S + gsinv[g];
+  for (int e = threadIdx.x; e < kGJ * kGJ; e += 256) {
+    const int a = e / kGJ, b = e % kGJ, i = i0 + a;
+    at[a][b] = (b < nb && i < Mg) ? X[(int64_t)i * Mg + j0 + b] : 0.0;
+  }
+  for (int e = threadIdx.x; e < kGJ * kGJ; e += 256)
+    bl[e / kGJ][e % kGJ] = Binv[(int64_t)g * kGJ * kGJ + e];
+  __syncthreads();
+  double *Cg = Cn + (int64_t)g * kGJ * maxM;
+  for (int e = threadIdx.x; e < nb * 32; e += 256) {
+    const int k = e / 32, il = e % 32, i = i0 + il;
+    if (i >= Mg || (i >= j0 && i < j0 + nb)) continue;
+    double t = 0.0;
+    for (int q = 0; q < nb; ++q) t += at[il][q] * bl[q][k];
+    Cg[(int64_t)k * maxM + i] = -t;
+  }
+}
+
+// Tiles of 64 x 64 entries of S_g, 4 x 4 per thread (see above for what
+// each part of the tile takes).
+__global__ void __launch_bounds__(256)
+    k_gjp_update(int j0, int NB, const int32_t *__restrict__ gisl,
+                 const int64_t *__restrict__ gsinv, double *__restrict__ S,
+                 const double *__restrict__ Cn, const double *__restrict__ R,
+                 const double *__restrict__ W, const double *__restrict__ Binv, int maxM) {
+  __shared__ double cs[64][kGJ + 1];
+  __shared__ double rs[kGJ][64 + 1];
+  const int g = blockIdx.z;
+  const int Mg = gisl[g + 1] - gisl[g];
+  if (j0 >= Mg) return;
+  const int nb = min(NB, Mg - j0);
   const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
-  if (c0 >= 2 * Mg || r0 >= Mg || c0 + 64 <= j0 + nb) return;
-  const double *Fg = F + (int64_t)g * maxM * kGJ;
-  const double *Wg = W + (int64_t)g * kGJ * 2 * maxM;
+  if (c0 >= Mg || r0 >= Mg) return;
+  const double *Cg = Cn + (int64_t)g * kGJ * maxM, *Rg = R + (int64_t)g * kGJ * maxM;
+  const double *Wg = W + (int64_t)g * kGJ * maxM;
+  double *Sg = S + gsinv[g];
+  const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
+  double old[4][4];  // this thread's entries, loaded before the tile is staged
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = r0 + tr + i, c = c0 + tc + j;
+      old[i][j] = (r < Mg && c < Mg) ? Sg[(int64_t)r * Mg + c] : 0.0;
+    }
   for (int e = threadIdx.x; e < 64 * kGJ; e += 256) {
-    const int r = e / kGJ, k = e % kGJ;
-    fs[r][k] = (r0 + r < Mg && k < nb) ? Fg[(int64_t)k * maxM + r0 + r] : 0.0;
-    const int kk = e / 64, c = e % 64;
-    ws[kk][c] = (kk < nb && c0 + c < 2 * Mg && c0 + c >= j0 + nb)
-                    ? Wg[(int64_t)kk * 2 * maxM + c0 + c] : 0.0;
+    const int k = e / 64, t = e % 64;
+    const int r = r0 + t, c = c0 + t;
+    const bool rin = r >= j0 && r < j0 + nb, cin = c >= j0 && c < j0 + nb;
+    cs[t][k] = (k < nb && r < Mg && !rin) ? Cg[(int64_t)k * maxM + r] : 0.0;
+    rs[k][t] = (k < nb && c < Mg && !cin) ? Rg[(int64_t)k * maxM + c] : 0.0;
   }
   __syncthreads();
-  const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
   double acc[4][4] = {};
   for (int k = 0; k < nb; ++k)
+#pragma unroll
     for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) acc[i][j] += fs[tr + i][k] * ws[k][tc + j];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] += cs[tr + i][k] * rs[k][tc + j];
+#pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int r = r0 + tr + i;
     if (r >= Mg) continue;
-    const bool pivot_row = r >= j0 && r < j0 + nb;
+    const bool rin = r >= j0 && r < j0 + nb;
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = c0 + tc + j;
-      if (c >= 2 * Mg || c < j0 + nb) continue;
-      double *X = (c < Mg ? A : B) + gsinv[g] + (int64_t)r * Mg + (c < Mg ? c : c - Mg);
-      if (pivot_row) *X = ws[r - j0][tc + j];
-      else *X -= acc[i][j];
+      if (c >= Mg) continue;
+      const bool cin = c >= j0 && c < j0 + nb;
+      double *X = Sg + (int64_t)r * Mg + c;
+      if (rin && cin) *X = Binv[((int64_t)g * kGJ + (r - j0)) * kGJ + (c - j0)];
+      else if (rin) *X = Wg[(int64_t)(r - j0) * maxM + c];
+      else if (cin) *X = Cg[(int64_t)(c - j0) * maxM + r];
+      else *X = old[i][j] + acc[i][j];
     }
   }
 }
 
-__global__ void k_gj_identity(const int32_t *__restrict__ gisl,
-                              const int64_t *__restrict__ gsinv,
-                              double *__restrict__ B) {
-  const int g = blockIdx.z;
-  const int Mg = gisl[g + 1] - gisl[g];
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (j < Mg && r < Mg) B[gsinv[g] + (int64_t)r * Mg + j] = (r == j) ? 1.0 : 0.0;
+// Sinv_g[i][j] = X_g[i][col_of[j]], one work-group per row
+__global__ void __launch_bounds__(256)
+    k_gjp_unpermute(const int32_t *__restrict__ isl_geo, const int32_t *__restrict__ gisl,
+                    const int64_t *__restrict__ gsinv, const double *__restrict__ X,
+                    const int *__restrict__ col_of, double *__restrict__ Sinv, int maxM) {
+  const int row = blockIdx.x;
+  const int g = isl_geo[row];
+  const int Mg = gisl[g + 1] - gisl[g], rl = row - gisl[g];
+  const double *xr = X + gsinv[g] + (int64_t)rl * Mg;
+  double *yr = Sinv + gsinv[g] + (int64_t)rl * Mg;
+  const int *cm = col_of + (int64_t)g * maxM;
+  for (int j = threadIdx.x; j < Mg; j += 256) yr[j] = xr[cm[j]];
+}
+
+template <int RPT>
+static void gj_panel(int j0, const Geometry &g, double *S, int *piv, double *Bi, int maxM,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_gjp_panel<RPT>, dim3(g.G), dim3(kGJT), 0, s, j0, g.dgisl.p, g.dgsinv.p, S,
+                     piv, Bi, maxM);
 }
 
 void invert_blocks(const Geometry &g, double *S, double *Sinv, hipStream_t s) {
   if (g.M == 0) return;
   const int G = g.G, maxM = g.maxM;
-  DBuf<int> piv;
-  piv.alloc((size_t)G * kGJ);
-  DBuf<double> P, C, W, Bi;
-  P.alloc((size_t)G * maxM * kGJ);
-  C.alloc((size_t)G * maxM * kGJ);
-  W.alloc((size_t)G * kGJ * 2 * maxM);
+  if (maxM > 8 * kGJT)
+    throw ApiError{LBS_ERR_UNSUPPORTED, "more than 8192 islands in one geometry"};
+  DBuf<int> piv, colmap;
+  piv.alloc((size_t)G * maxM);
+  colmap.alloc((size_t)G * maxM);
+  DBuf<double> R, W, Cn, Bi;
+  R.alloc((size_t)G * kGJ * maxM);
+  W.alloc((size_t)G * kGJ * maxM);
+  Cn.alloc((size_t)G * kGJ * maxM);
   Bi.alloc((size_t)G * kGJ * kGJ);
-  hipLaunchKernelGGL(k_gj_identity, dim3((maxM + 255) / 256, maxM, G), dim3(256), 0, s,
-                     g.dgisl.p, g.dgsinv.p, Sinv);
-  const unsigned ncol = (2 * maxM + 255) / 256, ntile = (2 * maxM + 63) / 64,
-                 nrow = (maxM + 63) / 64;
-  for (int j0 = 0; j0 < maxM; j0 += kGJ) {
-    hipLaunchKernelGGL(k_gj_panel, dim3(G), dim3(1024), 0, s, j0, g.dgisl.p, g.dgsinv.p,
-                       S, P.p, C.p, piv.p, Bi.p, maxM);
-    hipLaunchKernelGGL(k_gj_swap, dim3(ncol, 1, G), dim3(256), 0, s, j0, g.dgisl.p,
-                       g.dgsinv.p, S, Sinv, piv.p);
-    hipLaunchKernelGGL(k_gj_w, dim3(ncol, 1, G), dim3(256), 0, s, j0, g.dgisl.p,
-                       g.dgsinv.p, S, Sinv, Bi.p, W.p, maxM);
-    hipLaunchKernelGGL(k_gj_update, dim3(ntile, nrow, G), dim3(256), 0, s, j0, g.dgisl.p,
-                       g.dgsinv.p, S, Sinv, W.p, C.p, maxM);
+  const unsigned ncol = (maxM + 255) / 256, ntile = (maxM + 63) / 64, n32 = (maxM + 31) / 32;
+  for (int j0 = 0; j0 < maxM;) {
+    // rows still to eliminate in the largest geometry: maxM - j0
+    const int h = maxM - j0;
+    const int rpt = h <= kGJT ? 1 : h <= 2 * kGJT ? 2 : h <= 4 * kGJT ? 4 : 8;
+    const int NB = kGJ / rpt;
+    switch (rpt) {
+      case 1: gj_panel<1>(j0, g, S, piv.p, Bi.p, maxM, s); break;
+      case 2: gj_panel<2>(j0, g, S, piv.p, Bi.p, maxM, s); break;
+      case 4: gj_panel<4>(j0, g, S, piv.p, Bi.p, maxM, s); break;
+      default: gj_panel<8>(j0, g, S, piv.p, Bi.p, maxM, s); break;
+    }
+    hipLaunchKernelGGL(k_gjp_swap, dim3(ncol, 1, G), dim3(256), 0, s, j0, NB, g.dgisl.p,
+                       g.dgsinv.p, S, piv.p, maxM);
+    hipLaunchKernelGGL(k_gjp_rows, dim3(n32, 1, G), dim3(256), 0, s, j0, NB, g.dgisl.p,
+                       g.dgsinv.p, S, Bi.p, R.p, W.p, maxM);
+    hipLaunchKernelGGL(k_gjp_cols, dim3(n32, 1, G), dim3(256), 0, s, j0, NB, g.dgisl.p,
+                       g.dgsinv.p, S, Bi.p, Cn.p, maxM);
+    hipLaunchKernelGGL(k_gjp_update, dim3(ntile, ntile, G), dim3(256), 0, s, j0, NB, g.dgisl.p,
+                       g.dgsinv.p, S, Cn.p, R.p, W.p, Bi.p, maxM);
+    j0 += NB;
   }
+  // the column map on the host: the row interchanges undone, last first
+  std::vector<int> hp = piv.download(s), cm((size_t)G * maxM, 0);
+  for (int q = 0; q < G; ++q) {
+    const int Mg = g.gisl[q + 1] - g.gisl[q];
+    int *c = cm.data() + (size_t)q * maxM;
+    const int *pq = hp.data() + (size_t)q * maxM;
+    for (int j = 0; j < Mg; ++j) c[j] = j;
+    for (int k = Mg - 1; k >= 0; --k) std::swap(c[k], c[pq[k]]);
+  }
+  colmap.upload(cm, s);
+  hipLaunchKernelGGL(k_gjp_unpermute, dim3(g.M), dim3(256), 0, s, g.isl_geo.p, g.dgisl.p,
+                     g.dgsinv.p, S, colmap.p, Sinv, maxM);
   LBS_HIP(hipGetLastError());
   LBS_HIP(hipStreamSynchronize(s));
 }

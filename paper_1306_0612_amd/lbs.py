@@ -162,6 +162,8 @@ def load():
                                     vp, vp, vp, vp]
     lib.lbs_vortex_field.argtypes = [H, ctypes.c_int32, ctypes.c_int32, vp,
                                      vp, ctypes.c_int64, vp, vp, vp]
+    lib.lbs_schur_residual.argtypes = [vp, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_double), vp]
     lib.lbs_check_passes_host.argtypes = [c_double_p, c_double_p,
                                           ctypes.c_int64, ctypes.c_int32,
                                           ctypes.c_int32,
@@ -177,6 +179,7 @@ def load():
     for name in ("lbs_refine_tolerances_host", "lbs_setup_sampled",
                  "lbs_vortex_data", "lbs_vortex_field", "lbs_matvec_noalloc",
                  "lbs_compare_trees", "lbs_check_passes_host",
+                 "lbs_schur_residual",
                  "lbs_resample_curve_host", "lbs_setup", "lbs_sizes",
                  "lbs_nodes", "lbs_matvec", "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
                  "lbs_stage_timing", "lbs_stage_times", "lbs_setup_batch",
@@ -466,6 +469,13 @@ class Solver:
         cnt = (ctypes.c_int64 * len(STAGES))()
         _check(load().lbs_stage_times(self._h, ms, cnt, len(STAGES)))
         return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
+
+    def schur_residual(self, ncols=64):
+        """Largest |S (S^-1 e_j) - e_j| over ncols sampled columns."""
+        e = ctypes.c_double()
+        _check(load().lbs_schur_residual(self._h, int(ncols), ctypes.byref(e),
+                                         _stream()))
+        return e.value
 
     def tree_info(self):
         st = TreeStats()
