@@ -240,13 +240,13 @@ def test_adjoint_full_size(env):
     assert abs(J - float(2.0 * ls @ gd)) < 1e-9 * float((wd.abs()).sum())
     dc = sol.shape_vjp(sig, A, ls, wd, tgd).cpu().numpy()
     assert dc.shape == (isl.m, 16) and np.isfinite(dc).all()
-    k, q, h = 1234, 5, 1e-4
+    k, q, h = 1234, 5, 1e-3
 
     def J_at(v):
         isl2 = isl.subset(np.arange(isl.m))
         isl2.coef[k, q] = v
         s2 = lbs.Solver(isl2, leaf_max=64)
-        a, b, _ = s2.solve(gd, tol=1e-12, precision="mixed")
+        a, b, _ = s2.solve(gd, tol=1e-12, precision="fp64")
         u = s2.eval(a, b, tgd)
         s2.close()
         return float(wd @ u)
@@ -254,7 +254,11 @@ def test_adjoint_full_size(env):
     b0 = isl.coef[k, q]
     f = {s: J_at(b0 + s * h) for s in (-2, -1, 1, 2)}
     fd = (8 * (f[1] - f[-1]) - (f[2] - f[-2])) / (12 * h)
-    # the gradient bar (1e-6 relative); the difference quotient's own error
-    # (fourth order in h, plus the 1e-12 solve tolerance over h) is far below
+    # the gradient bar (1e-6 relative).  The difference quotient's own error
+    # is O(h^4) plus the solves' error over h: a mixed solve of a perturbed
+    # geometry may stop an inner iteration earlier or later than its
+    # neighbour (J moves by ~1e-9, 2e-5 in the quotient at h = 1e-4), so the
+    # reference takes FP64 solves, whose stopping points agree, and h = 1e-3
+    # (its error then ~1e-8, three orders below the bar)
     assert abs(dc[k, q] - fd) < 1e-6 * np.abs(dc).max()
     sol.close()
