@@ -76,17 +76,29 @@ bool p32_ok(int p) { return p == 12 || p == 16 || p == 20 || p == 24; }
 // Upload a host tree (or forest) as a device plan.  sx/sy (tx/ty) are the
 // source (target) coordinates in input order; tgt_index maps a target's
 // input position to the index written by the leaf kernel.
+// The points of a plan whose tree was built on the GPU, on the device:
+// coordinates (x[i stride], y[i stride]) of sources and targets, the maps
+// the builder kept, and the target index map (device, or null).
+struct DevPoints {
+  const double *sx, *sy;
+  int64_t sstride, ns;
+  const double *tx, *ty;
+  int64_t tstride, nt;
+  const DevPerms *perm;
+  const int64_t *tgt_index;
+};
+
 void upload_plan(Tree &T, const double *sx, const double *sy,
                  const double *tx, const double *ty,
                  const std::vector<int64_t> *tgt_index, DevPlan &pl,
-                 hipStream_t s) {
+                 hipStream_t s, const DevPoints *dp = nullptr) {
   HostPhase ph_plan("upload_plan");
   const int nb = T.nbox();
   pl.nbox = nb;
   pl.nlevels = T.nlevels;
   pl.self = T.self;
-  pl.ns = (int64_t)T.src_perm.size();
-  pl.nt = (int64_t)T.tgt_perm.size();
+  pl.ns = dp ? dp->ns : (int64_t)T.src_perm.size();
+  pl.nt = dp ? (T.self ? dp->ns : dp->nt) : (int64_t)T.tgt_perm.size();
   std::vector<int32_t> leaf_s, leaf_t, m2l;
   std::vector<uint8_t> has_tgt(nb);
   for (int b = 0; b < nb; ++b) {
@@ -99,6 +111,7 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
   pl.n_leaf_t = (int)leaf_t.size();
   pl.n_m2l = (int)m2l.size();
   {
+    HostPhase ph("upload_plan leaf order");
     // leaf kernels: one wave per target leaf, launched heaviest octave of
     // near-field work first (box order kept within an octave), so that the
     // waves still running at the end of a launch are short ones.  Work: the
@@ -124,6 +137,7 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
                      [&](int a, int b) { return oct[a] > oct[b]; });
   }
   {
+    HostPhase ph("upload_plan M2L order");
     // M2L boxes: the FP32 kernel's waves take every W-th box (W = 4 x its
     // work-groups); with the boxes sorted by estimated work (V-list batches
     // of 8, X-list passes of 64 sources) and every other stride of W
@@ -172,17 +186,25 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
       fp[b + 1] = fp[b] + c;
     }
     if (fp[nb] > INT32_MAX) fail(LBS_ERR_UNSUPPORTED, "list source table over 2^31 entries");
-    std::vector<int32_t> fi((size_t)fp[nb]);
-    parallel_for(nb, [&](int64_t b0, int64_t b1) {
-      for (int64_t b = b0; b < b1; ++b) {
-        int64_t e = fp[b];
-        for (int k = ptr[b]; k < ptr[b + 1]; ++k)
-          for (int64_t j = T.s0[idx[k]]; j < T.s1[idx[k]]; ++j) fi[e++] = (int32_t)j;
+    // where each list entry's run starts in the table; the runs are filled
+    // on the device (a wave per entry)
+    const int64_t ne = ptr[nb];
+    std::vector<int64_t> eo((size_t)std::max<int64_t>(ne, 1));
+    for (int b = 0; b < nb; ++b) {
+      int64_t e = fp[b];
+      for (int k = ptr[b]; k < ptr[b + 1]; ++k) {
+        eo[k] = e;
+        e += T.s1[idx[k]] - T.s0[idx[k]];
       }
-    }, 1024);
+    }
+    DBuf<int64_t> deo;
+    DBuf<int32_t> dent;
+    deo.upload(eo, s);
+    dent.upload(idx, s);
     dptr.upload(fp, s);
-    didx.upload(fi, s);
-    LBS_HIP(hipStreamSynchronize(s));  // fi is released on return
+    didx.alloc((size_t)std::max<int64_t>(fp[nb], 1));
+    launch_flat_fill(ne, dent.p, deo.p, pl.s0.p, pl.s1.p, didx.p, s);
+    LBS_HIP(hipStreamSynchronize(s));  // eo is released on return
     return fp;
   };
   {
@@ -208,7 +230,10 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
     pl.lt_hdr.upload(hd, s);
     LBS_HIP(hipStreamSynchronize(s));  // hd is released on return
   }
-  flat_sources(T.x_ptr, T.x_src, pl.xf_ptr, pl.xf_idx);
+  {
+    HostPhase ph("upload_plan X sources");
+    flat_sources(T.x_ptr, T.x_src, pl.xf_ptr, pl.xf_idx);
+  }
   pl.w_ptr.upload(T.w_ptr, s);
   pl.w_src.upload(T.w_src, s);
   pl.leaf_t.upload(leaf_t, s);
@@ -239,6 +264,23 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
     dy.upload(y, s);
     LBS_HIP(hipStreamSynchronize(s));  // x, y are released on return
   };
+  HostPhase ph_pts("upload_plan points");
+  if (dp) {  // gathered on the device from the builder's maps
+    const int32_t *tp = T.self ? dp->perm->src.p : dp->perm->tgt.p;
+    pl.sx.alloc((size_t)pl.ns);
+    pl.sy.alloc((size_t)pl.ns);
+    pl.tx.alloc((size_t)pl.nt);
+    pl.ty.alloc((size_t)pl.nt);
+    pl.src_perm.alloc((size_t)pl.ns);
+    pl.tgt_perm.alloc((size_t)pl.nt);
+    launch_gather_points(pl.ns, dp->perm->src.p, dp->sx, dp->sy, dp->sstride, pl.sx.p, pl.sy.p, s);
+    launch_widen_perm(pl.ns, dp->perm->src.p, nullptr, pl.src_perm.p, s);
+    launch_gather_points(pl.nt, tp, T.self ? dp->sx : dp->tx, T.self ? dp->sy : dp->ty,
+                         T.self ? dp->sstride : dp->tstride, pl.tx.p, pl.ty.p, s);
+    launch_widen_perm(pl.nt, tp, dp->tgt_index, pl.tgt_perm.p, s);
+    LBS_HIP(hipStreamSynchronize(s));
+    return;
+  }
   points(T.src_perm, sx, sy, pl.sx, pl.sy);
   pl.src_perm.upload(T.src_perm, s);
   points(T.tgt_perm, T.self ? sx : tx, T.self ? sy : ty, pl.tx, pl.ty);
@@ -250,10 +292,11 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
 }
 
 // Upward / downward pass programs of the plan's tree for FP32 order p32
-// and FP64 order p64 (the LDS capacity of the pass kernels depends on it).
-void build_passes(DevPlan &pl, int p32, int p64, hipStream_t s) {
+// and FP64 order p64 (the LDS capacity of the pass kernels depends on it);
+// fp64_only: the FP64 ones alone (evaluation plans run the FP64 FMM only).
+void build_passes(DevPlan &pl, int p32, int p64, hipStream_t s, bool fp64_only = false) {
   HostPhase ph("pass programs");
-  for (int k = 0; k < 2; ++k) {
+  for (int k = fp64_only ? 1 : 0; k < 2; ++k) {
     const int cap = k == 0 ? pass_cap(p32, 8) : pass_cap(p64, 16);
     for (int d = 0; d < 2; ++d) {
       PassProgram pp;
@@ -1440,15 +1483,24 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
   const int64_t n = (int64_t)ep->idx.size();
   if (n > 0 && (transposed || c.opt.matvec != LBS_MATVEC_DIRECT)) {
     Tree &F = ep->pl.host;
-    if (G == 1 && c.opt.gpu_tree) {
+    const bool on_gpu = G == 1 && c.opt.gpu_tree;
+    DBuf<double> dtx, dty;  // the targets' images (GPU tree), until the plan is built
+    DevPerms dperm;
+    DevPoints dpts{};
+    if (on_gpu) {
       HostPhase ph("eval plan tree (GPU)");
-      DBuf<double> dtx, dty;
       dtx.upload(ep->tx, s);
       dty.upload(ep->ty, s);
-      if (transposed)
-        gpu_build_tree(dtx.p, dty.p, 1, n, g.xi.p, g.xi.p + 1, 2, g.N, false, c.opt.leaf_max, F, s);
-      else
-        gpu_build_tree(g.xi.p, g.xi.p + 1, 2, g.N, dtx.p, dty.p, 1, n, false, c.opt.leaf_max, F, s);
+      ep->didx.upload(ep->idx, s);
+      if (transposed) {
+        gpu_build_tree(dtx.p, dty.p, 1, n, g.xi.p, g.xi.p + 1, 2, g.N, false, c.opt.leaf_max, F, s,
+                       &dperm);
+        dpts = DevPoints{dtx.p, dty.p, 1, n, g.xi.p, g.xi.p + 1, 2, g.N, &dperm, nullptr};
+      } else {
+        gpu_build_tree(g.xi.p, g.xi.p + 1, 2, g.N, dtx.p, dty.p, 1, n, false, c.opt.leaf_max, F, s,
+                       &dperm);
+        dpts = DevPoints{g.xi.p, g.xi.p + 1, 2, g.N, dtx.p, dty.p, 1, n, &dperm, ep->didx.p};
+      }
     } else {
       for (int q = 0; q < G; ++q) {
         const int64_t a = g.gnode[q], nn = g.gnode[q + 1] - a;
@@ -1466,15 +1518,16 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
       }
     }
     HostPhase ph_up("eval plan upload");
+    const DevPoints *dp = on_gpu ? &dpts : nullptr;
     if (transposed) {
       upload_plan(F, ep->tx.data(), ep->ty.data(), c.xi_x.data(), c.xi_y.data(), nullptr,
-                  ep->pl, s);
-      build_passes(ep->pl, c.opt.p32, c.opt.p64, s);
-      ep->didx.upload(ep->idx, s);
+                  ep->pl, s, dp);
+      build_passes(ep->pl, c.opt.p32, c.opt.p64, s, true);
+      if (!on_gpu) ep->didx.upload(ep->idx, s);
     } else {
       upload_plan(F, c.xi_x.data(), c.xi_y.data(), ep->tx.data(), ep->ty.data(), &ep->idx,
-                  ep->pl, s);
-      build_passes(ep->pl, c.opt.p32, c.opt.p64, s);
+                  ep->pl, s, dp);
+      build_passes(ep->pl, c.opt.p32, c.opt.p64, s, true);
       ep->qt.alloc(2 * g.N);
       launch_permute_complex(g.N, ep->pl.src_perm.p, g.qfac.p, ep->qt.p, s);
     }

@@ -27,10 +27,29 @@
 #include <type_traits>
 #include <vector>
 
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+
 #include "lbs_internal.h"
 
 namespace lbs {
 namespace {
+
+// Wall time of the builder's phases, printed to stderr when
+// LBS_HOST_TIMING is set (as the set-up's): mark(name) reports the time
+// since the previous mark.
+struct PhaseClock {
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void mark(const char *name) {
+    static const bool on = std::getenv("LBS_HOST_TIMING") != nullptr;
+    const auto now = std::chrono::steady_clock::now();
+    if (on)
+      std::fprintf(stderr, "[lbs host] gpu tree: %-18s %9.3f ms\n", name,
+                   std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
 
 // ------------------------------------------------------------ radix sort
 constexpr int kRsTile = 4096;  // keys per work-group (256 threads x 16)
@@ -124,17 +143,30 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Stable sort of (keys, vals) by the low `bits` bits of the keys; the
-// result is back in keys / vals.
-void radix_sort(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {
-  if (n <= 1) return;
-  const int ntiles = (int)((n + kRsTile - 1) / kRsTile);
+// Scratch of the radix sorts of one tree build, grown as needed and
+// reused by every sort (fewer allocations, and no device-wide wait in a
+// free between the sorts).
+struct SortScratch {
   DBuf<uint64_t> k2;
   DBuf<int32_t> v2;
   DBuf<uint32_t> hist;
-  k2.alloc((size_t)n);
-  v2.alloc((size_t)n);
-  hist.alloc((size_t)256 * ntiles);
+  void ensure(int64_t n, int ntiles) {
+    if ((int64_t)k2.n < n) k2.alloc((size_t)n);
+    if ((int64_t)v2.n < n) v2.alloc((size_t)n);
+    if ((int64_t)hist.n < (int64_t)256 * ntiles) hist.alloc((size_t)256 * ntiles);
+  }
+};
+
+// Stable sort of (keys, vals) by the low `bits` bits of the keys; the
+// result is back in keys / vals.
+void radix_sort(uint64_t *keys, int32_t *vals, int64_t n, int bits, SortScratch &sc,
+                hipStream_t s) {
+  if (n <= 1) return;
+  const int ntiles = (int)((n + kRsTile - 1) / kRsTile);
+  sc.ensure(n, ntiles);
+  DBuf<uint64_t> &k2 = sc.k2;
+  DBuf<int32_t> &v2 = sc.v2;
+  DBuf<uint32_t> &hist = sc.hist;
   uint64_t *ka = keys, *kb = k2.p;
   int32_t *va = vals, *vb = v2.p;
   int passes = 0;
@@ -151,7 +183,6 @@ void radix_sort(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t 
     LBS_HIP(hipMemcpyAsync(vals, va, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   }
   LBS_HIP(hipGetLastError());
-  LBS_HIP(hipStreamSynchronize(s));  // the scratch buffers are released on return
 }
 
 // ---------------------------------------------------------- points, keys
@@ -493,13 +524,14 @@ void pairs_to_csr(const std::vector<uint64_t> &pk, int nb, std::vector<int32_t> 
 
 void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t ns,
                     const double *tx, const double *ty, int64_t tstride, int64_t nt, bool self,
-                    int leaf_max, Tree &T, hipStream_t s) {
+                    int leaf_max, Tree &T, hipStream_t s, DevPerms *keep) {
   if (leaf_max < 1) throw ApiError{LBS_ERR_INVALID_ARG, "leaf_max < 1"};
   if (ns + (self ? 0 : nt) >= (int64_t)INT32_MAX)
     throw ApiError{LBS_ERR_UNSUPPORTED, "more than 2^31 points in one tree"};
   T = Tree();
   T.self = self;
   if (self) nt = ns;
+  PhaseClock clk;
   // 1. root box, as the host builder (min/max are exact)
   double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
   {
@@ -527,6 +559,7 @@ void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t
   T.R0 = half * (1.0 + 1e-6) + 1e-300 + 1e-12 * std::max(std::fabs(T.x0), std::fabs(T.y0));
   if (!(T.R0 > 0)) T.R0 = 1.0;
   const double lox = T.x0 - T.R0, loy = T.y0 - T.R0, scale = 0.5 / T.R0;
+  SortScratch sorts;  // released after the last sort's work is waited for
   // 2. keys and stable sort
   DBuf<uint64_t> ks, kt;
   DBuf<int32_t> ps, pt;
@@ -537,11 +570,11 @@ void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t
     if (n == 0) return;
     hipLaunchKernelGGL(k_morton, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n, st,
                        lox, loy, scale, k.p, p.p);
-    radix_sort(k.p, p.p, n, 2 * kMaxLevel, s);
+    radix_sort(k.p, p.p, n, 2 * kMaxLevel, sorts, s);
   };
   keys(sx, sy, ns, sstride, ks, ps);
   if (!self) keys(tx, ty, nt, tstride, kt, pt);
-  {
+  if (!keep) {
     std::vector<int32_t> a = get(ps.p, (size_t)ns, s);
     LBS_HIP(hipStreamSynchronize(s));
     T.src_perm.assign(a.begin(), a.end());
@@ -553,6 +586,7 @@ void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t
       T.tgt_perm.assign(b.begin(), b.end());
     }
   }
+  clk.mark("root, keys, sort");
   // 3. boxes, level by level (capacity grows by copying)
   struct Arr {
     DBuf<int64_t> s0, s1, t0, t1;
@@ -649,6 +683,7 @@ void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t
     }
     LBS_HIP(hipGetLastError());
   }
+  clk.mark("levels");
   while (lp.size() >= 2 && lp[lp.size() - 1] == lp[lp.size() - 2]) lp.pop_back();
   T.level_ptr = lp;
   T.nlevels = (int)lp.size() - 1;
@@ -687,6 +722,7 @@ void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t
     const std::vector<int32_t> o = get(ovf.p, 1, s);
     LBS_HIP(hipStreamSynchronize(s));  // host arrays stay alive until here
     if (o[0] != 0) throw ApiError{LBS_ERR_UNSUPPORTED, "quadtree descent deeper than its stack"};
+    clk.mark("leaf lists");
     // 5. pairs
     const int64_t nu_tot = huo[nbox], nw_tot = hwo[nbox];
     DBuf<uint64_t> up, wp, xp, vp;
@@ -720,7 +756,7 @@ void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t
       } else {
         LBS_HIP(hipMemsetAsync(v.p, 0, (size_t)n * sizeof(int32_t), s));
       }
-      radix_sort(k.p, v.p, n, bits, s);
+      radix_sort(k.p, v.p, n, bits, sorts, s);
     };
     sort_pairs(up, uv, (int64_t)cnt[0], nullptr);
     sort_pairs(wp, wv, (int64_t)cnt[1], nullptr);
@@ -731,6 +767,7 @@ void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t
                           hx = get(xp.p, (size_t)cnt[2], s), hvk = get(vp.p, (size_t)cnt[3], s);
     std::vector<int32_t> hvc = get(vv.p, (size_t)cnt[3], s);
     LBS_HIP(hipStreamSynchronize(s));
+    clk.mark("pairs + sorts");
     pairs_to_csr(hu, nbox, T.u_ptr, T.u_src);
     pairs_to_csr(hw, nbox, T.w_ptr, T.w_src);
     pairs_to_csr(hx, nbox, T.x_ptr, T.x_src);
@@ -768,6 +805,68 @@ void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t
     }
   }
   tree_statistics(T);
+  if (keep) {  // the maps stay on the device (a self tree has one)
+    keep->src.take(ps);
+    if (!self) keep->tgt.take(pt);
+  }
+  clk.mark("boxes to host");
+}
+
+namespace {
+__global__ void __launch_bounds__(256)
+    k_gather_points(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ x,
+                    const double *__restrict__ y, int64_t stride, double *__restrict__ ox,
+                    double *__restrict__ oy) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  const int64_t i = (int64_t)perm[j] * stride;
+  ox[j] = x[i];
+  oy[j] = y[i];
+}
+
+// one wave per list entry
+__global__ void __launch_bounds__(256)
+    k_flat_fill(int64_t ne, const int32_t *__restrict__ box, const int64_t *__restrict__ eo,
+                const int64_t *__restrict__ s0, const int64_t *__restrict__ s1,
+                int32_t *__restrict__ fi) {
+  const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= ne) return;
+  const int c = box[k];
+  const int64_t a = s0[c], len = s1[c] - a, o = eo[k];
+  for (int64_t t = threadIdx.x & 63; t < len; t += 64) fi[o + t] = (int32_t)(a + t);
+}
+
+__global__ void __launch_bounds__(256)
+    k_widen_perm(int64_t n, const int32_t *__restrict__ perm, const int64_t *__restrict__ map,
+                 int64_t *__restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  out[j] = map ? map[perm[j]] : (int64_t)perm[j];
+}
+}  // namespace
+
+void launch_gather_points(int64_t n, const int32_t *perm, const double *x, const double *y,
+                          int64_t stride, double *ox, double *oy, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gather_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, perm,
+                     x, y, stride, ox, oy);
+  LBS_HIP(hipGetLastError());
+}
+
+void launch_flat_fill(int64_t ne, const int32_t *box, const int64_t *eo, const int64_t *s0,
+                      const int64_t *s1, int32_t *fi, hipStream_t s) {
+  if (ne <= 0) return;
+  hipLaunchKernelGGL(k_flat_fill, dim3((unsigned)((ne + 3) / 4)), dim3(256), 0, s, ne, box, eo, s0,
+                     s1, fi);
+  LBS_HIP(hipGetLastError());
+}
+
+void launch_widen_perm(int64_t n, const int32_t *perm, const int64_t *map, int64_t *out,
+                       hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_widen_perm, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, perm,
+                     map, out);
+  LBS_HIP(hipGetLastError());
 }
 
 }  // namespace lbs

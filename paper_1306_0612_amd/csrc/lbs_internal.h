@@ -52,6 +52,15 @@ struct DBuf {
     n = count;
     own = false;
   }
+  void take(DBuf &o) {  // ownership of o's memory moves here
+    release();
+    p = o.p;
+    n = o.n;
+    own = o.own;
+    o.p = nullptr;
+    o.n = 0;
+    o.own = true;
+  }
   void alloc(size_t count) {
     release();
     n = count;
@@ -315,11 +324,19 @@ constexpr int kLogChunk = 64;  // far-list entries per wave step
 constexpr int kM2LGroups = 1024;
 
 void set_last_error(const std::string &msg);  // message of lbs_last_error
+// Device arrays of a GPU-built tree that a plan may take instead of host
+// copies: the sorted position -> input index maps of sources and targets.
+struct DevPerms {
+  DBuf<int32_t> src, tgt;
+};
 // build_tree on the GPU (gtree.hip): device coordinates x[i stride],
-// y[i stride]; the same Tree as the host builder.  Synchronous.
+// y[i stride]; the same Tree as the host builder.  Synchronous.  With
+// keep, the maps are handed over on the device and T.src_perm /
+// T.tgt_perm stay empty.
 void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t ns,
                     const double *tx, const double *ty, int64_t tstride, int64_t nt, bool self,
-                    int leaf_max, Tree &T, hipStream_t s);
+                    int leaf_max, Tree &T, hipStream_t s,
+                    DevPerms *keep = nullptr);
 // lbs_matvec with its scratch buffers in `bytes` of device memory at base
 // (api.cpp; the entry point without allocation passes its static scratch)
 lbs_status matvec_in_scratch(lbs_handle h, int32_t op, int32_t prec, int32_t nrhs,
@@ -465,6 +482,16 @@ void launch_backsolve_seg(int S, int m, const double *H, const double *g,
 void launch_axpby(int64_t n, double a, const double *x, double b, double *y,
                   hipStream_t s);
 void launch_fill(int64_t n, double v, double *x, hipStream_t s);
+// ox[j] = x[perm[j] stride], oy[j] = y[perm[j] stride] (j < n)
+void launch_gather_points(int64_t n, const int32_t *perm, const double *x, const double *y,
+                          int64_t stride, double *ox, double *oy, hipStream_t s);
+// Runs of a concatenated list-source table: for each of the ne list
+// entries k, fi[eo[k] + t] = s0[box[k]] + t, t < s1[box[k]] - s0[box[k]]
+void launch_flat_fill(int64_t ne, const int32_t *box, const int64_t *eo, const int64_t *s0,
+                      const int64_t *s1, int32_t *fi, hipStream_t s);
+// out[j] = map ? map[perm[j]] : perm[j] (j < n)
+void launch_widen_perm(int64_t n, const int32_t *perm, const int64_t *map, int64_t *out,
+                       hipStream_t s);
 void launch_fill_int(int64_t n, int32_t v, int32_t *x, hipStream_t s);
 void launch_copy_cols(int64_t n, int R, double a, const double *src, int64_t lds,
                       double *dst, int64_t ldd, hipStream_t s);

@@ -135,6 +135,7 @@ void build_pass_program(const Tree &T, bool down, int cap, PassProgram &pp) {
     return members[a].size() > members[b].size();
   });
   pp.round_ptr.assign(1, 0);
+  std::vector<int32_t> slot_of(nb, -1);  // a box's slot in the component being emitted
   int cur = 1;
   for (size_t oi = 0; oi < order.size(); ++oi) {
     const int ci = order[oi];
@@ -165,13 +166,9 @@ void build_pass_program(const Tree &T, bool down, int cap, PassProgram &pp) {
         pp.ext.push_back(ks[j]);
         pp.ext.push_back(1 | (quad_of(T, ks[j]) << 2));  // times pre[q]
       }
-      auto slot = [&](int c) -> int {
-        if (comp[c] == ci && !root[c]) {
-          const int j = (int)(std::find(m.begin(), m.end(), c) - m.begin());
-          return ne + j;
-        }
-        return (int)(std::find(ks.begin(), ks.end(), c) - ks.begin());
-      };
+      for (int j = 0; j < ne; ++j) slot_of[ks[j]] = j;
+      for (int j = 0; j < nm; ++j) slot_of[m[j]] = ne + j;
+      auto slot = [&](int c) -> int { return slot_of[c]; };
       for (int j = 0; j < nm; ++j) {
         const int b = m[j];
         int sq[4] = {kPassNone, kPassNone, kPassNone, kPassNone}, k[4];
@@ -200,14 +197,14 @@ void build_pass_program(const Tree &T, bool down, int cap, PassProgram &pp) {
         if (i == 0) return staged ? nm : kPassNone;
         return nm + (staged ? 1 : 0) + i - 1;
       };
+      for (int i = 0; i < nm; ++i) slot_of[m[i]] = i;
       for (int i = 0; i < nm; ++i) {
         const int b = m[i];
         int cv[4] = {kPassNone, kPassNone, kPassNone, kPassNone}, k[4];
         const int nk = kids(b, k);
         for (int j = 0; j < nk; ++j) {
           if (comp[k[j]] != ci || root[k[j]]) continue;
-          const int idx = (int)(std::find(m.begin(), m.end(), k[j]) - m.begin());
-          cv[quad_of(T, k[j])] = ver(idx);
+          cv[quad_of(T, k[j])] = ver(slot_of[k[j]]);
         }
         pp.par.push_back((int32_t)((uint32_t)b | ((uint32_t)quad_of(T, b) << 30)));
         pp.par.push_back(pack2(i, ver(i)));

@@ -110,3 +110,25 @@ def test_solver_same_matvec(env):
     assert out[0][0] == out[1][0]
     assert np.array_equal(out[0][1], out[1][1])
     assert np.array_equal(out[0][2], out[1][2])
+
+
+def test_solver_same_evaluations(env):
+    """Evaluation plans from the GPU builder (points, maps and list tables
+    formed on the device) give the same forward and transposed evaluations,
+    bit for bit, as plans from the host builder."""
+    torch, lbs = env
+    isl = synth.star_islands(30, 12, (0.05, 0.15), nodes=128)
+    cv = Curves(isl)
+    tg = _t(torch, synth.sphere_targets(21, 3000, isl))
+    sig = _t(torch, synth.random_vector(22, cv.n))
+    A = _t(torch, synth.random_vector(23, cv.m))
+    w = _t(torch, synth.random_vector(24, tg.shape[0]))
+    out = []
+    for gt in (0, 1):
+        sol = lbs.Solver(isl, gpu_tree=gt, leaf_max=32)
+        u = sol.eval(sig, A, tg).cpu().numpy()
+        gs, ga = sol.eval_T(w, tg)
+        out.append((u, gs.cpu().numpy(), ga.cpu().numpy()))
+        sol.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
