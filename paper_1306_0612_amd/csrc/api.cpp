@@ -418,6 +418,10 @@ struct lbs_ctx {
   // close-zone search of evaluations; built on first use
   std::unordered_map<uint64_t, std::vector<int32_t>> igrid;
   double icell = 0.0;
+  // the same bins on the device: sorted cell keys, islands per cell, zones
+  DBuf<uint64_t> cg_keys;
+  DBuf<int32_t> cg_ptr, cg_isl;
+  DBuf<double> cg_zone;
   int32_t *count_host = nullptr;
   ~lbs_ctx() {
     if (count_host) (void)hipHostFree(count_host);
@@ -975,8 +979,94 @@ void set_close_zones(Geometry &g, const std::vector<double> &xyz) {
 }
 
 // Close pairs of an evaluation: every non-pole target with the islands of
-// its geometry whose close zone holds it (host, from the cached targets).
-void build_close(lbs_ctx &c, EvalPlan &ep, const std::vector<double> &hx, hipStream_t s) {
+// its geometry whose close zone holds it.  On the device (close.hip) from
+// the sorted cell table of the handle's islands; on the host, from the
+// cached targets, when a target lies in more zones than the device pass
+// lists.
+void build_close_host(lbs_ctx &c, EvalPlan &ep, const std::vector<double> &hx, hipStream_t s);
+
+void build_close(lbs_ctx &c, EvalPlan &ep, const std::vector<double> &hx, const double *txyz,
+                 hipStream_t s) {
+  Geometry &g = c.geo;
+  if (c.cg_keys.n == 0) {  // the islands binned by the cell of their centre
+    double cell = 1e-4;
+    for (int k = 0; k < g.M; ++k)
+      cell = std::max(cell, std::sqrt(std::max(0.0, 2.0 - 2.0 * g.zone_cos[k])));
+    c.icell = cell;
+    std::vector<std::pair<uint64_t, int32_t>> ki((size_t)g.M);
+    for (int q = 0; q < g.G; ++q)
+      for (int k = g.gisl[q]; k < g.gisl[q + 1]; ++k) {
+        const double *ck = &g.cxyz[3 * k];
+        uint64_t key = (uint64_t)q << 48;
+        for (int a = 0; a < 3; ++a)
+          key |= (uint64_t)std::floor((ck[a] + 1.0) / cell) << (32 - 16 * a);
+        ki[k] = {key, k};
+      }
+    std::sort(ki.begin(), ki.end());
+    std::vector<uint64_t> keys;
+    std::vector<int32_t> ptr, isl;
+    for (size_t e = 0; e < ki.size(); ++e) {
+      if (e == 0 || ki[e].first != ki[e - 1].first) {
+        keys.push_back(ki[e].first);
+        ptr.push_back((int32_t)e);
+      }
+      isl.push_back(ki[e].second);
+    }
+    ptr.push_back((int32_t)ki.size());
+    c.cg_keys.upload(keys, s);
+    c.cg_ptr.upload(ptr, s);
+    c.cg_isl.upload(isl, s);
+    c.cg_zone.upload(g.zone_cos, s);
+    LBS_HIP(hipStreamSynchronize(s));  // the host tables are released on return
+  }
+  const int64_t n = (int64_t)ep.idx.size();
+  const CloseGridView G{c.cg_keys.p, c.cg_ptr.p, c.cg_isl.p, g.dcenter.p, c.cg_zone.p, c.icell,
+                        (int)c.cg_keys.n};
+  if (ep.didx.n != (size_t)n) ep.didx.upload(ep.idx, s);
+  DBuf<int32_t> cnt;
+  cnt.alloc((size_t)n);
+  launch_close_count(n, ep.didx.p, txyz, ep.dtgeo.p, G, cnt.p, s);
+  const std::vector<int32_t> hc = cnt.download(s);
+  std::vector<int32_t> pos((size_t)n, -1), ptr(1, 0);
+  for (int64_t q = 0; q < n; ++q) {
+    if (hc[q] == 0) continue;
+    if (hc[q] > close_list_max()) {
+      build_close_host(c, ep, hx, s);
+      return;
+    }
+    pos[q] = (int32_t)(ptr.size() - 1);
+    ptr.push_back(ptr.back() + hc[q]);
+  }
+  ClosePlan &cp = ep.close;
+  cp.n_tgt = (int)(ptr.size() - 1);
+  if (cp.n_tgt == 0) {
+    cp.n_act = 0;
+    return;
+  }
+  DBuf<int32_t> dpos;
+  DBuf<double> dtx, dty;
+  DBuf<uint8_t> used;
+  dpos.upload(pos, s);
+  cp.ptr.upload(ptr, s);
+  dtx.upload(ep.tx, s);
+  dty.upload(ep.ty, s);
+  cp.z.alloc((size_t)2 * cp.n_tgt);
+  cp.out.alloc((size_t)cp.n_tgt);
+  cp.isl.alloc((size_t)ptr.back());
+  used.alloc((size_t)g.M);
+  LBS_HIP(hipMemsetAsync(used.p, 0, (size_t)g.M, s));
+  launch_close_fill(n, ep.didx.p, txyz, ep.dtgeo.p, dtx.p, dty.p, dpos.p, cp.ptr.p, G, cp.z.p,
+                    cp.out.p, cp.isl.p, used.p, s);
+  const std::vector<uint8_t> hu = used.download(s);
+  std::vector<int32_t> act;
+  for (int k = 0; k < g.M; ++k)
+    if (hu[k]) act.push_back(k);
+  cp.n_act = (int)act.size();
+  cp.act.upload(act, s);
+  LBS_HIP(hipStreamSynchronize(s));  // the host vectors are released on return
+}
+
+void build_close_host(lbs_ctx &c, EvalPlan &ep, const std::vector<double> &hx, hipStream_t s) {
   Geometry &g = c.geo;
   if (c.igrid.empty()) {
     double cell = 1e-4;
@@ -1536,7 +1626,7 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
   }
   if (c.opt.close_eval && n > 0) {
     HostPhase ph("eval plan close pairs");
-    build_close(c, *ep, hx, s);
+    build_close(c, *ep, hx, txyz, s);
   }
   LBS_HIP(hipStreamSynchronize(s));
   ep->key = std::move(hx);

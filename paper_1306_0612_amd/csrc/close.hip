@@ -179,4 +179,114 @@ void launch_close_eval(const Geometry &g, const ClosePlan &cp, int nrhs,
   LBS_HIP(hipGetLastError());
 }
 
+
+// ----------------------------------------------------------- close pairs
+// The (target, island) pairs of an evaluation whose island's close zone
+// holds the target, found on the device: islands are binned by the cell of
+// their centre in a uniform 3D grid (cell side >= every zone's chord
+// radius, keys (geometry << 48 | ix << 32 | iy << 16 | iz) sorted), and a
+// target looks at the 27 cells around its own.
+namespace {
+
+__device__ __forceinline__ int64_t find_cell(const uint64_t *keys, int nk, uint64_t key) {
+  int a = 0, b = nk;
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (keys[m] < key) a = m + 1;
+    else b = m;
+  }
+  return (a < nk && keys[a] == key) ? a : -1;
+}
+
+// The islands whose zone holds target position q, ascending in out[0:n]
+// (n <= kCloseMax, else the count only); returns the count.
+constexpr int kCloseMax = 32;
+template <bool FILL>
+__device__ int close_islands(const double *x, int geo, const CloseGridView &G, int *out) {
+  int n = 0;
+  const int64_t cx = (int64_t)floor((x[0] + 1.0) / G.cell);
+  const int64_t cy = (int64_t)floor((x[1] + 1.0) / G.cell);
+  const int64_t cz = (int64_t)floor((x[2] + 1.0) / G.cell);
+  for (int dx = -1; dx <= 1; ++dx)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dz = -1; dz <= 1; ++dz) {
+        const int64_t ix = cx + dx, iy = cy + dy, iz = cz + dz;
+        if (ix < 0 || iy < 0 || iz < 0) continue;
+        const uint64_t key = ((uint64_t)geo << 48) | ((uint64_t)ix << 32) | ((uint64_t)iy << 16) |
+                             (uint64_t)iz;
+        const int64_t c = find_cell(G.keys, G.nkeys, key);
+        if (c < 0) continue;
+        for (int e = G.ptr[c]; e < G.ptr[c + 1]; ++e) {
+          const int k = G.isl[e];
+          const double *ck = G.center + 3 * k;
+          if (x[0] * ck[0] + x[1] * ck[1] + x[2] * ck[2] > G.zone_cos[k]) {
+            if (FILL && n < kCloseMax) {  // insertion in ascending order
+              int j = n;
+              while (j > 0 && out[j - 1] > k) {
+                out[j] = out[j - 1];
+                --j;
+              }
+              out[j] = k;
+            }
+            ++n;
+          }
+        }
+      }
+  return n;
+}
+
+__global__ void __launch_bounds__(256)
+    k_close_count(int64_t n, const int64_t *__restrict__ idx, const double *__restrict__ txyz,
+                  const int32_t *__restrict__ tgeo, CloseGridView G, int32_t *__restrict__ cnt) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  const int64_t t = idx[q];
+  cnt[q] = close_islands<false>(txyz + 3 * t, tgeo[t], G, nullptr);
+}
+
+// close target q (pos[q] >= 0): its image, output row and islands
+__global__ void __launch_bounds__(256)
+    k_close_fill(int64_t n, const int64_t *__restrict__ idx, const double *__restrict__ txyz,
+                 const int32_t *__restrict__ tgeo, const double *__restrict__ tx,
+                 const double *__restrict__ ty, const int32_t *__restrict__ pos,
+                 const int32_t *__restrict__ ptr, CloseGridView G, double *__restrict__ z,
+                 int64_t *__restrict__ out, int32_t *__restrict__ isl,
+                 uint8_t *__restrict__ used) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= n || pos[q] < 0) return;
+  const int64_t t = idx[q];
+  int list[kCloseMax];
+  const int m = close_islands<true>(txyz + 3 * t, tgeo[t], G, list);
+  const int p = pos[q];
+  z[2 * p] = tx[q];
+  z[2 * p + 1] = ty[q];
+  out[p] = t;
+  for (int i = 0; i < m && i < kCloseMax; ++i) {
+    isl[ptr[p] + i] = list[i];
+    used[list[i]] = 1;  // every writer stores the same value
+  }
+}
+
+}  // namespace
+
+void launch_close_count(int64_t n, const int64_t *idx, const double *txyz, const int32_t *tgeo,
+                        const CloseGridView &G, int32_t *cnt, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_close_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, idx,
+                     txyz, tgeo, G, cnt);
+  LBS_HIP(hipGetLastError());
+}
+
+void launch_close_fill(int64_t n, const int64_t *idx, const double *txyz, const int32_t *tgeo,
+                       const double *tx, const double *ty, const int32_t *pos, const int32_t *ptr,
+                       const CloseGridView &G, double *z, int64_t *out, int32_t *isl,
+                       uint8_t *used, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_close_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, idx,
+                     txyz, tgeo, tx, ty, pos, ptr, G, z, out, isl, used);
+  LBS_HIP(hipGetLastError());
+}
+
+int close_list_max() { return kCloseMax; }
+
 }  // namespace lbs

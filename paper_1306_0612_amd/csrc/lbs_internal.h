@@ -411,6 +411,25 @@ void direct_eval64(int64_t N, const double *xi, const double *qfac,
                    const double *txi, const uint8_t *pole, int nrhs,
                    double *out, int64_t ldy, double scale, hipStream_t s);
 
+// The islands of a handle binned for the close-pair search (close.hip).
+struct CloseGridView {
+  const uint64_t *keys;     // sorted cell keys
+  const int32_t *ptr, *isl;  // islands of cell c: isl[ptr[c] .. ptr[c + 1])
+  const double *center, *zone_cos;
+  double cell;
+  int nkeys;
+};
+// cnt[q] = number of islands whose close zone holds target idx[q]
+void launch_close_count(int64_t n, const int64_t *idx, const double *txyz, const int32_t *tgeo,
+                        const CloseGridView &G, int32_t *cnt, hipStream_t s);
+// for the targets with pos[q] >= 0: z, out and their islands (ascending) at
+// ptr[pos[q]]; used[k] = 1 for every island met
+void launch_close_fill(int64_t n, const int64_t *idx, const double *txyz, const int32_t *tgeo,
+                       const double *tx, const double *ty, const int32_t *pos, const int32_t *ptr,
+                       const CloseGridView &G, double *z, int64_t *out, int32_t *isl,
+                       uint8_t *used, hipStream_t s);
+int close_list_max();  // islands per target the fill pass lists
+
 // u += close-evaluation corrections for the targets of cp (nrhs columns;
 // V: 2 N nrhs doubles of scratch for the boundary values).
 void launch_close_eval(const Geometry &g, const ClosePlan &cp, int nrhs,
