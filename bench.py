@@ -272,26 +272,30 @@ def traffic_profile():
     return rec, fresh
 
 
-STAGE_KERNELS32 = {  # stage -> kernels of one mixed application (launches)
-    "upward": [("k_p2m<float,16>", 1), ("k_m2m3<float,16>", 4)],
-    "m2l": [("k_m2l_mfma16", 1)],
-    "l2l": [("k_l2l3<float,16>", 4)],
-    "leaf": [("k_leaf32<16,1>", 1)],
+STAGE_KERNELS32 = {  # stage -> kernels of one mixed application
+    "upward": ["k_p2m<float,16>", "k_pass<float,16,false>"],
+    "m2l": ["k_m2l_mfma16"],
+    "l2l": ["k_pass<float,16,true>"],
+    "leaf": ["k_leaf32<16,1>"],
 }
 
 
 def stage_fetch(rec, fresh):
+    """HBM bytes each stage's kernels fetch per application: a kernel's
+    mean per launch times its launches per application (the summary's
+    `per_app`, its dispatches over those of the leaf kernel, which runs
+    once per application)."""
     if not fresh:
         return None
     out = {}
     for st, ks in STAGE_KERNELS32.items():
         tot = 0.0
-        for k, n in ks:
+        for k in ks:
             kv = rec.get(k)
             if kv is None or "fetch_bytes_per_launch" not in kv:
                 tot = None
                 break
-            tot += n * float(kv["fetch_bytes_per_launch"])
+            tot += float(kv.get("per_app", 1)) * float(kv["fetch_bytes_per_launch"])
         if tot:
             out[st] = tot
     return out
@@ -585,8 +589,8 @@ def main():
     kname = {"leaf": "k_leaf32<%d,1>" % P32,
              "m2l": "k_m2l_mfma16" if P32 == 16 else "k_m2l<float,%d>" % P32,
              "p2l": "k_p2l<float,%d>" % P32,
-             "upward": "k_m2m3<float,%d>" % P32,
-             "l2l": "k_l2l3<float,%d>" % P32}.get(dom, dom)
+             "upward": "k_pass<float,%d,false>" % P32,
+             "l2l": "k_pass<float,%d,true>" % P32}.get(dom, dom)
     r = rl32.get(dom, {})
     roofline = {"bound": r.get("bound", "alu"), "kernel": kname,
                 "achieved": r.get("achieved"),

@@ -184,6 +184,25 @@ def test_autograd_function(env, small, prec):
     assert np.abs(coef.grad.numpy() - fd).max() < 1e-7 * np.abs(fd).max()
 
 
+def test_autograd_reuses_the_handle(env, small):
+    """Calls on the same geometry and options share one handle; a new
+    geometry gets its own (and u stays linear in g across the calls)."""
+    torch, lbs = env
+    from paper_1306_0612_amd import autograd as ag
+    isl, cv, tg, w, g, sol = small
+    coef = torch.tensor(isl.coef, dtype=torch.float64)
+    gd, tgd = _t(torch, g), _t(torch, tg)
+    u1 = ag.solve_eval(gd, coef, isl, tgd, tol=1e-13, leaf_max=12)
+    h1 = ag._LAST["sol"]
+    u2 = ag.solve_eval(2.0 * gd, coef, isl, tgd, tol=1e-13, leaf_max=12)
+    assert ag._LAST["sol"] is h1
+    assert _rel(u2.cpu().numpy(), 2.0 * u1.cpu().numpy()) < 1e-10
+    c2 = coef.clone()
+    c2[0, 0] += 1e-3
+    ag.solve_eval(gd, c2, isl, tgd, tol=1e-13, leaf_max=12)
+    assert ag._LAST["sol"] is not h1
+
+
 def test_adjoint_duality_at_scale(env):
     """w . u(g) = (2 lambda_sigma) . g for the 20,480-node geometry (the map
     g -> u is linear), and a central difference of the GPU forward in one
