@@ -117,6 +117,14 @@ typedef struct {
                      /* with HIP kernels; 0: with host threads.  Batch     */
                      /* handles always use the host builder.  Both give    */
                      /* the same tree (lbs_compare_trees).                 */
+  int32_t eval_tree; /* 0 (default): lbs_eval places each target in the   */
+                     /* deepest box of the handle's own quadtree that      */
+                     /* holds it and sums the box's local expansion, the   */
+                     /* multipoles and nodes of its colleagues' subtrees   */
+                     /* and the coarser adjacent leaves (no tree per       */
+                     /* target set); 1: lbs_eval builds a quadtree over    */
+                     /* the nodes and the targets, as lbs_eval_T does.     */
+                     /* Both are the FMM of Section 5 at the same order.   */
 } lbs_options;
 
 typedef struct {

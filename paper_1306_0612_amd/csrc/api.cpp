@@ -369,6 +369,13 @@ struct EvalPlan {
   DBuf<double> qt;              // forward: qfac in the plan's source order
   DBuf<int64_t> didx;           // transposed: idx on the device
   DBuf<int32_t> dtgeo;
+  // forward, targets located in the handle's own tree (no tree of their
+  // own): sorted by the deepest box holding them, with that box (-1:
+  // outside the root square), their tree's root and their API index
+  bool located = false;
+  DBuf<double> ltx, lty;
+  DBuf<int32_t> lbox, lroot;
+  DBuf<int64_t> lidx;
   ClosePlan close;              // targets in close zones (close_eval on)
   DBuf<double> closeV;          // boundary values, 2 N per column
 };
@@ -1152,6 +1159,7 @@ void validate_options(const lbs_options &o) {
   if (o.precond != 0 && o.precond != 1) fail(LBS_ERR_INVALID_ARG, "precond must be 0 or 1");
   if (o.close_eval != 0 && o.close_eval != 1) fail(LBS_ERR_INVALID_ARG, "close_eval must be 0 or 1");
   if (o.gpu_tree != 0 && o.gpu_tree != 1) fail(LBS_ERR_INVALID_ARG, "gpu_tree must be 0 or 1");
+  if (o.eval_tree != 0 && o.eval_tree != 1) fail(LBS_ERR_INVALID_ARG, "eval_tree must be 0 or 1");
 }
 
 // Set-up of G geometries (islands and node counts concatenated
@@ -1538,6 +1546,22 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl_in
   return ctx.release();
 }
 
+// The tree links (parent, children, leaf flags) and each geometry's root
+// box of a plan on the device, uploaded on first use.
+void ensure_links(DevPlan &pl, hipStream_t s) {
+  if (pl.roots.n > 0 || pl.nbox == 0) return;
+  const Tree &T = pl.host;
+  pl.parent.upload(T.parent, s);
+  pl.child0.upload(T.child0, s);
+  pl.nchild.upload(T.nchild, s);
+  pl.leaf.upload(T.leaf, s);
+  std::vector<int32_t> r;  // a forest holds its geometries' trees in turn
+  for (int b = 0; b < pl.nbox; ++b)
+    if (T.parent[b] < 0) r.push_back(b);
+  pl.roots.upload(r, s);
+  LBS_HIP(hipStreamSynchronize(s));  // r is released on return
+}
+
 // The evaluation plan for these targets (cached on the handle).
 EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &toff,
                     const double *txyz, hipStream_t s) {
@@ -1571,7 +1595,25 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
   }
   ep->dtgeo.upload(ep->tgeo, s);
   const int64_t n = (int64_t)ep->idx.size();
-  if (n > 0 && (transposed || c.opt.matvec != LBS_MATVEC_DIRECT)) {
+  const bool located = !transposed && c.opt.matvec != LBS_MATVEC_DIRECT && !c.opt.eval_tree;
+  if (n > 0 && located) {
+    HostPhase ph("eval plan locate");
+    if ((int)g.gnode.size() != G + 1) fail(LBS_ERR_INVALID_ARG, "geometry table");
+    ensure_links(c.plan, s);
+    if ((int64_t)c.plan.roots.n != G) fail(LBS_ERR_GEOMETRY, "one tree per geometry expected");
+    DBuf<double> dtx, dty;
+    dtx.upload(ep->tx, s);
+    dty.upload(ep->ty, s);
+    ep->didx.upload(ep->idx, s);
+    ep->ltx.alloc((size_t)n);
+    ep->lty.alloc((size_t)n);
+    ep->lbox.alloc((size_t)n);
+    ep->lroot.alloc((size_t)n);
+    ep->lidx.alloc((size_t)n);
+    launch_locate_targets(n, dtx.p, dty.p, ep->didx.p, G > 1 ? ep->dtgeo.p : nullptr, c.plan,
+                          ep->ltx.p, ep->lty.p, ep->lbox.p, ep->lroot.p, ep->lidx.p, s);
+    ep->located = true;
+  } else if (n > 0 && (transposed || c.opt.matvec != LBS_MATVEC_DIRECT)) {
     Tree &F = ep->pl.host;
     const bool on_gpu = G == 1 && c.opt.gpu_tree;
     DBuf<double> dtx, dty;  // the targets' images (GPU tree), until the plan is built
@@ -1659,6 +1701,21 @@ void eval_impl(lbs_ctx &c, int nrhs, const double *sigma, const double *A,
       dpole.upload(pole, s);
       direct_eval64(g.N, g.xi.p, g.qfac.p, sigma, g.N, T, dtxi.p, dpole.p, nrhs, u, T, 0.5, s);
       LBS_HIP(hipStreamSynchronize(s));
+    } else if (ep.located) {
+      // the handle's own FP64 far field, then each target from its box
+      ensure_ws(c, nrhs);
+      StageTimer *keep = c.ws.timer;  // not one of the operator's stages
+      c.ws.timer = nullptr;
+      try {
+        fmm_far64(c.plan, c.tab64, c.ws, g.qfac_t.p, sigma, g.N, nrhs, s);
+      } catch (...) {
+        c.ws.timer = keep;
+        throw;
+      }
+      c.ws.timer = keep;
+      launch_eval_points(c.tab64.P, (int64_t)ep.idx.size(), ep.ltx.p, ep.lty.p, ep.lbox.p,
+                         ep.lroot.p, ep.lidx.p, c.plan, c.ws.pstr64.p, c.ws.mult64.p,
+                         c.ws.loc64.p, nrhs, u, T, 0.5, s);
     } else {
       ep.ws.ensure(ep.pl, c.opt.p64, c.opt.p32, nrhs, g.N, g.M, G, kPlog);
       fmm_apply64(ep.pl, c.tab64, ep.ws, ep.qt.p, sigma, g.N, nrhs, u, T, 0.5, Assembly{}, s);
@@ -1862,6 +1919,7 @@ void lbs_default_options(lbs_options *o) {
   o->precond = 1;
   o->close_eval = 1;
   o->gpu_tree = 1;
+  o->eval_tree = 0;
 }
 
 lbs_status lbs_refine_tolerances_host(int32_t S, const double *rn2, const double *bn2,

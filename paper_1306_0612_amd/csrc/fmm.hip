@@ -1281,6 +1281,26 @@ void fmm_apply64(const DevPlan &pl, const Tables &tb, Workspace &ws,
   LBS_HIP(hipGetLastError());
 }
 
+void fmm_far64(const DevPlan &pl, const Tables &tb, Workspace &ws, const double *qfac_t,
+               const double *sigma, int64_t ldx, int nrhs, hipStream_t s) {
+  const StrengthSrc ss{pl.src_perm.p, qfac_t, sigma, ldx, nullptr, nullptr};
+  auto *p = (cx<double> *)ws.pstr64.p;
+  auto *M = (cx<double> *)ws.mult64.p;
+  auto *L = (cx<double> *)ws.loc64.p;
+  switch (tb.P) {
+    case 20: far_field<double, 20>(pl, tb, ws, p, M, L, nrhs, s, ss); break;
+    case 24: far_field<double, 24>(pl, tb, ws, p, M, L, nrhs, s, ss); break;
+    case 30: far_field<double, 30>(pl, tb, ws, p, M, L, nrhs, s, ss); break;
+    case 36: far_field<double, 36>(pl, tb, ws, p, M, L, nrhs, s, ss); break;
+    case 40: far_field<double, 40>(pl, tb, ws, p, M, L, nrhs, s, ss); break;
+    case 48: far_field<double, 48>(pl, tb, ws, p, M, L, nrhs, s, ss); break;
+    default:
+      throw ApiError{LBS_ERR_UNSUPPORTED,
+                     "p64 must be one of 20, 24, 30, 36, 40, 48"};
+  }
+  LBS_HIP(hipGetLastError());
+}
+
 void fmm_apply32(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  const double *qfac_t, const double *sigma, int64_t ldx,
                  int nrhs, double *out, int64_t ldy, double scale,

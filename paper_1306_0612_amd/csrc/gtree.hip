@@ -861,6 +861,12 @@ void launch_flat_fill(int64_t ne, const int32_t *box, const int64_t *eo, const i
   LBS_HIP(hipGetLastError());
 }
 
+void sort_by_key(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {
+  SortScratch sc;
+  radix_sort(keys, vals, n, bits, sc, s);
+  LBS_HIP(hipStreamSynchronize(s));  // the scratch is released on return
+}
+
 void launch_widen_perm(int64_t n, const int32_t *perm, const int64_t *map, int64_t *out,
                        hipStream_t s) {
   if (n <= 0) return;

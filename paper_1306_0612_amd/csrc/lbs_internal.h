@@ -121,6 +121,7 @@ struct DevPlan {
   int n_leaf_t = 0, n_leaf_s = 0, n_m2l = 0;
   DBuf<double> cx, cy, rad;
   DBuf<int32_t> parent, child0, nchild, quad, lev;
+  DBuf<int32_t> roots;                       // root box of each geometry
   DBuf<int64_t> s0, s1, t0, t1;
   DBuf<uint8_t> leaf, has_tgt;
   DBuf<int32_t> v_ptr, v_src, w_ptr, w_src;
@@ -388,6 +389,11 @@ void fmm_apply64(const DevPlan &pl, const Tables &tb, Workspace &ws,
                  int nrhs, double *out, int64_t ldy, double scale,
                  const Assembly &as, hipStream_t s,
                  const GammaFused *gf = nullptr);
+// The FP64 far field alone: strengths p_j = -i q_j sigma_j (ws.pstr64),
+// multipoles (ws.mult64) and local expansions (ws.loc64) of every box of
+// level >= 2 that holds sources or targets.
+void fmm_far64(const DevPlan &pl, const Tables &tb, Workspace &ws, const double *qfac_t,
+               const double *sigma, int64_t ldx, int nrhs, hipStream_t s);
 // Psi(z) = sum_j p_j / (z - z_j) and Psi'(z) (complex, FP64) at the plan's
 // targets for complex strengths pin (API order of the plan's sources);
 // outputs in the targets' API order, dpsi may be null.  One column.
@@ -512,6 +518,22 @@ void launch_flat_fill(int64_t ne, const int32_t *box, const int64_t *eo, const i
 void launch_widen_perm(int64_t n, const int32_t *perm, const int64_t *map, int64_t *out,
                        hipStream_t s);
 void launch_fill_int(int64_t n, int32_t v, int32_t *x, hipStream_t s);
+// Stable sort of (keys, vals) by the low `bits` bits of the keys (gtree.hip)
+void sort_by_key(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
+// Targets located in a plan's tree (evalpts.hip): the n targets (tx, ty;
+// API index idx; geometry tgeo[idx] or 0) sorted by the deepest box whose
+// square holds them (-1 outside the root square), with their roots and
+// API indices.  The plan needs its tree links and roots on the device.
+void launch_locate_targets(int64_t n, const double *tx, const double *ty, const int64_t *idx,
+                           const int32_t *tgeo, const DevPlan &pl, double *ox, double *oy,
+                           int32_t *obox, int32_t *oroot, int64_t *oidx, hipStream_t s);
+// out[r ldy + tidx[i]] = scale Re sum_j p_j / (z_i - z_j) for located
+// targets, from the plan's FP64 expansions M, L (order P) and strengths
+// pstr of its sources (far_field already run for the nrhs right-hand sides).
+void launch_eval_points(int P, int64_t n, const double *tx, const double *ty, const int32_t *tbox,
+                        const int32_t *troot, const int64_t *tidx, const DevPlan &pl,
+                        const double *pstr, const double *M, const double *L, int nrhs,
+                        double *out, int64_t ldy, double scale, hipStream_t s);
 void launch_copy_cols(int64_t n, int R, double a, const double *src, int64_t lds,
                       double *dst, int64_t ldd, hipStream_t s);
 void launch_scale_sqrt(int S, double t, const double *nrm2, double *out,

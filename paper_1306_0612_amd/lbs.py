@@ -38,7 +38,8 @@ class Options(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("matvec", ctypes.c_int32),
                 ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("close_eval", ctypes.c_int32), ("gpu_tree", ctypes.c_int32)]
+                ("close_eval", ctypes.c_int32), ("gpu_tree", ctypes.c_int32),
+                ("eval_tree", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
