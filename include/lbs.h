@@ -121,9 +121,10 @@ typedef struct {
                      /* deepest box of the handle's own quadtree that      */
                      /* holds it and sums the box's local expansion, the   */
                      /* multipoles and nodes of its colleagues' subtrees   */
-                     /* and the coarser adjacent leaves (no tree per       */
-                     /* target set); 1: lbs_eval builds a quadtree over    */
-                     /* the nodes and the targets, as lbs_eval_T does.     */
+                     /* and the coarser adjacent leaves; lbs_eval_T and    */
+                     /* lbs_shape_vjp apply the transpose of that sum (no  */
+                     /* tree per target set); 1: these build a quadtree    */
+                     /* over the nodes and the targets per target set.     */
                      /* Both are the FMM of Section 5 at the same order.   */
 } lbs_options;
 

@@ -376,6 +376,9 @@ struct EvalPlan {
   DBuf<double> ltx, lty;
   DBuf<int32_t> lbox, lroot;
   DBuf<int64_t> lidx;
+  // transposed, the located targets as sources of the handle's own FMM
+  bool located_src = false;
+  PointSources src;
   ClosePlan close;              // targets in close zones (close_eval on)
   DBuf<double> closeV;          // boundary values, 2 N per column
 };
@@ -1595,7 +1598,10 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
   }
   ep->dtgeo.upload(ep->tgeo, s);
   const int64_t n = (int64_t)ep->idx.size();
-  const bool located = !transposed && c.opt.matvec != LBS_MATVEC_DIRECT && !c.opt.eval_tree;
+  // located in the handle's own tree: forward always, transposed for one
+  // geometry (the adjoint entry points serve no batch)
+  const bool located = c.opt.matvec != LBS_MATVEC_DIRECT && !c.opt.eval_tree &&
+                       (!transposed || G == 1);
   if (n > 0 && located) {
     HostPhase ph("eval plan locate");
     if ((int)g.gnode.size() != G + 1) fail(LBS_ERR_INVALID_ARG, "geometry table");
@@ -1612,7 +1618,12 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
     ep->lidx.alloc((size_t)n);
     launch_locate_targets(n, dtx.p, dty.p, ep->didx.p, G > 1 ? ep->dtgeo.p : nullptr, c.plan,
                           ep->ltx.p, ep->lty.p, ep->lbox.p, ep->lroot.p, ep->lidx.p, s);
-    ep->located = true;
+    if (transposed) {
+      build_point_sources(c.plan, n, ep->ltx.p, ep->lty.p, ep->lbox.p, ep->lroot.p, ep->src, s);
+      ep->located_src = true;
+    } else {
+      ep->located = true;
+    }
   } else if (n > 0 && (transposed || c.opt.matvec != LBS_MATVEC_DIRECT)) {
     Tree &F = ep->pl.host;
     const bool on_gpu = G == 1 && c.opt.gpu_tree;
@@ -1804,6 +1815,11 @@ void apply_op_T(lbs_ctx &c, int R, const double *x, double *y, int prec, hipStre
 void eval_T_field(lbs_ctx &c, EvalPlan &ep, const double *w, double *pcw, double *psi,
                   double *dpsi, hipStream_t s) {
   const int64_t N = c.geo.N;
+  if (ep.located_src) {  // the targets as sources of the handle's own FMM
+    launch_gather_complex(ep.src.n, ep.lidx.p, w, pcw, s);
+    fmm_sources64_full(c.plan, c.tab64, c.ws, ep.src, pcw, psi, dpsi, s);
+    return;
+  }
   if (!ep.tree) {
     launch_fill(2 * N, 0.0, psi, s);
     if (dpsi) launch_fill(2 * N, 0.0, dpsi, s);

@@ -122,13 +122,13 @@ __device__ __forceinline__ double multipole_at(double x, double y, int b, const 
   return (acc * rho).x;
 }
 
-// The sources of c's subtree at z, walked depth first without a stack
-// (children are contiguous, so the next box is the next sibling or an
-// ancestor's).  Levels 0 and 1 carry no multipoles and are always opened.
-template <int P>
-__device__ double subtree_at(double x, double y, int c, const TreeView &t,
-                             const cx<double> *__restrict__ p, const cx<double> *__restrict__ M) {
-  double f = 0.0;
+// c's subtree as seen from z, walked depth first without a stack (children
+// are contiguous, so the next box is the next sibling or an ancestor's):
+// v.far(b) for a box whose 3 x 3 neighbourhood does not hold z (taken by
+// its multipole), v.direct(b) for a leaf whose neighbourhood does.  Levels
+// 0 and 1 carry no multipoles and are always opened.
+template <class Vis>
+__device__ void walk_subtree(double x, double y, int c, const TreeView &t, Vis &v) {
   int b = c;
   for (;;) {
     const double h3 = 3.0 * t.rad[b];
@@ -137,9 +137,10 @@ __device__ double subtree_at(double x, double y, int c, const TreeView &t,
       b = t.child0[b];
       continue;
     }
-    f += open ? direct_sum(x, y, t.s0[b], t.s1[b], t.sx, t.sy, p) : multipole_at<P>(x, y, b, t, M);
+    if (open) v.direct(b);
+    else v.far(b);
     for (;;) {
-      if (b == c) return f;
+      if (b == c) return;
       const int pa = t.parent[b];
       if (b + 1 < t.child0[pa] + t.nchild[pa]) {
         ++b;
@@ -149,6 +150,48 @@ __device__ double subtree_at(double x, double y, int c, const TreeView &t,
     }
   }
 }
+
+// The sources the local expansion of B leaves out, for z in B (B < 0: z
+// outside the root square, or B the root: every source): the subtrees of
+// B's colleagues and the coarser leaves adjacent to B.
+template <class Vis>
+__device__ void walk_near(double x, double y, int B, int root, const TreeView &t, Vis &v) {
+  if (B < 0 || t.lev[B] == 0) {
+    walk_subtree(x, y, root, t, v);
+    return;
+  }
+  const int l = t.lev[B];
+  const double h = t.rad[B], bx = t.cx[B], by = t.cy[B];
+  walk_subtree(x, y, B, t, v);
+  int coarse[8];  // at most one per neighbour square
+  int nco = 0;
+  for (int o = 0; o < 9; ++o) {
+    if (o == 4) continue;  // B itself
+    const double qx = bx + 2.0 * h * (double)(o % 3 - 1);
+    const double qy = by + 2.0 * h * (double)(o / 3 - 1);
+    const int c = descend(qx, qy, root, l, t.cx, t.cy, t.rad, t.lev, t.child0, t.nchild, t.leaf);
+    if (c < 0) continue;
+    if (t.lev[c] == l) {  // a colleague
+      walk_subtree(x, y, c, t, v);
+      continue;
+    }
+    if (!t.leaf[c]) continue;  // no nodes in that square
+    bool seen = false;         // a coarser leaf adjacent to B
+    for (int k = 0; k < nco; ++k) seen = seen || coarse[k] == c;
+    if (seen) continue;
+    coarse[nco++] = c;
+    v.direct(c);
+  }
+}
+
+template <int P>
+struct SumVisitor {
+  double x, y, f;
+  TreeView t;
+  const cx<double> *p, *M;
+  __device__ void far(int b) { f += multipole_at<P>(x, y, b, t, M); }
+  __device__ void direct(int b) { f += direct_sum(x, y, t.s0[b], t.s1[b], t.sx, t.sy, p); }
+};
 
 // One thread per target (targets sorted by their box), right-hand side
 // blockIdx.y: out[r ldy + idx] = scale Re Psi(z).
@@ -162,46 +205,132 @@ __global__ void __launch_bounds__(64)
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int r = blockIdx.y;
-  const cx<double> *pr = p + (int64_t)r * ns;
-  const cx<double> *Mr = M + (int64_t)r * nbox * P;
   const double x = tx[i], y = ty[i];
   const int B = tbox[i], root = troot[i];
-  double f = 0.0;
-  if (B < 0 || t.lev[B] == 0) {
-    f = subtree_at<P>(x, y, root, t, pr, Mr);
-  } else {
-    const int l = t.lev[B];
-    const double h = t.rad[B], bx = t.cx[B], by = t.cy[B];
-    if (l >= 2) {
-      const double ir = 1.0 / h;
-      const cx<double> w{(x - bx) * ir, (y - by) * ir};
-      const cx<double> *Lb = L + ((int64_t)r * nbox + B) * P;
-      cx<double> acc = Lb[P - 1];
-      for (int k = P - 2; k >= 0; --k) acc = cfma(acc, w, Lb[k]);
-      f = acc.x;
-    }
-    f += subtree_at<P>(x, y, B, t, pr, Mr);
-    int coarse[8];  // at most one per neighbour square
-    int nco = 0;
-    for (int o = 0; o < 9; ++o) {
-      if (o == 4) continue;  // B itself
-      const double qx = bx + 2.0 * h * (double)(o % 3 - 1);
-      const double qy = by + 2.0 * h * (double)(o / 3 - 1);
-      const int c = descend(qx, qy, root, l, t.cx, t.cy, t.rad, t.lev, t.child0, t.nchild, t.leaf);
-      if (c < 0) continue;
-      if (t.lev[c] == l) {  // a colleague
-        f += subtree_at<P>(x, y, c, t, pr, Mr);
-        continue;
-      }
-      if (!t.leaf[c]) continue;  // no nodes in that square
-      bool seen = false;         // a coarser leaf adjacent to B
-      for (int k = 0; k < nco; ++k) seen = seen || coarse[k] == c;
-      if (seen) continue;
-      coarse[nco++] = c;
-      f += direct_sum(x, y, t.s0[c], t.s1[c], t.sx, t.sy, pr);
-    }
+  SumVisitor<P> v{x, y, 0.0, t, p + (int64_t)r * ns, M + (int64_t)r * nbox * P};
+  if (B >= 0 && t.lev[B] >= 2) {
+    const double ir = 1.0 / t.rad[B];
+    const cx<double> w{(x - t.cx[B]) * ir, (y - t.cy[B]) * ir};
+    const cx<double> *Lb = L + ((int64_t)r * nbox + B) * P;
+    cx<double> acc = Lb[P - 1];
+    for (int k = P - 2; k >= 0; --k) acc = cfma(acc, w, Lb[k]);
+    v.f = acc.x;
   }
-  out[(int64_t)r * ldy + tidx[i]] = scale * f;
+  walk_near(x, y, B, root, t, v);
+  out[(int64_t)r * ldy + tidx[i]] = scale * v.f;
+}
+
+// ---------------------------------------------- sources at arbitrary points
+// The transpose of the evaluation above: sources c_t at the located points
+// t, the field at the tree's own points.  Transposing each step, a point t
+// in box B enters
+//   the multipole of B and of each ancestor of level >= 2 (the transpose of
+//     B's local expansion at t and of the L2L steps that formed it),
+//   the local expansion of every box its walk takes by multipole (the
+//     transpose of that multipole's value at t),
+//   the direct sums of every leaf its walk sums directly;
+// then the tree's V lists (M2L), the downward pass, and at the leaves the
+// local expansions, the W lists (the transpose of the X-list P2L) and the
+// direct sums complete the field.  This kernel counts (FILL = false) or
+// writes those (box, point) pairs: multipole, local, direct.
+struct CountVisitor {
+  uint32_t nl = 0, nd = 0;
+  __device__ void far(int) { ++nl; }
+  __device__ void direct(int) { ++nd; }
+};
+struct FillVisitor {
+  int32_t *lb, *lt, *db, *dt;
+  uint32_t lo, dof;
+  int32_t ti;
+  __device__ void far(int b) {
+    lb[lo] = b;
+    lt[lo++] = ti;
+  }
+  __device__ void direct(int b) {
+    db[dof] = b;
+    dt[dof++] = ti;
+  }
+};
+
+template <bool FILL>
+__global__ void __launch_bounds__(64)
+    k_source_pairs(int64_t n, const double *__restrict__ tx, const double *__restrict__ ty,
+                   const int32_t *__restrict__ tbox, const int32_t *__restrict__ troot,
+                   TreeView t, uint32_t *__restrict__ cm, uint32_t *__restrict__ cl,
+                   uint32_t *__restrict__ cd, int32_t *__restrict__ mb, int32_t *__restrict__ mt,
+                   int32_t *__restrict__ lb, int32_t *__restrict__ lt, int32_t *__restrict__ db,
+                   int32_t *__restrict__ dt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = tx[i], y = ty[i];
+  const int B = tbox[i], root = troot[i];
+  uint32_t nm = 0;
+  uint32_t mo = FILL ? cm[i] : 0u;
+  for (int a = B; a >= 0 && t.lev[a] >= 2; a = t.parent[a]) {
+    if constexpr (FILL) {
+      mb[mo] = a;
+      mt[mo++] = (int32_t)i;
+    }
+    ++nm;
+  }
+  if constexpr (FILL) {
+    FillVisitor v{lb, lt, db, dt, cl[i], cd[i], (int32_t)i};
+    walk_near(x, y, B, root, t, v);
+  } else {
+    CountVisitor v;
+    walk_near(x, y, B, root, t, v);
+    cm[i] = nm;
+    cl[i] = v.nl;
+    cd[i] = v.nd;
+  }
+}
+
+// ptr[b] = the first position of sorted keys with key >= b (b <= nbox)
+__global__ void __launch_bounds__(256)
+    k_csr_ptr(int64_t n, const uint64_t *__restrict__ keys, int nbox, int64_t *__restrict__ ptr) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > n) return;
+  const int64_t lo = k == 0 ? -1 : (int64_t)keys[k - 1];
+  const int64_t hi = k == n ? (int64_t)nbox : (int64_t)keys[k];
+  for (int64_t b = lo + 1; b <= hi; ++b) ptr[b] = k;
+}
+
+// Per entry e of the multipole list (box b = list[e]): its range of the
+// box-sorted multipole pairs and its frame; the pairs' coordinates.
+__global__ void __launch_bounds__(256)
+    k_mlist(int n, const int32_t *__restrict__ list, const int64_t *__restrict__ ptr,
+            const double *__restrict__ cxv, const double *__restrict__ cyv,
+            const double *__restrict__ rad, int64_t *__restrict__ rng, double4 *__restrict__ geo) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int b = list[e];
+  rng[2 * e] = ptr[b];
+  rng[2 * e + 1] = ptr[b + 1];
+  geo[e] = make_double4(cxv[b], cyv[b], 1.0 / rad[b], 0.0);
+}
+
+__global__ void __launch_bounds__(256)
+    k_gather_xy(int64_t n, const int32_t *__restrict__ idx, const double *__restrict__ x,
+                const double *__restrict__ y, double *__restrict__ ox, double *__restrict__ oy) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  ox[k] = x[idx[k]];
+  oy[k] = y[idx[k]];
+}
+
+__global__ void __launch_bounds__(256)
+    k_gather_cx(int64_t n, const int32_t *__restrict__ idx, const double2 *__restrict__ in,
+                double2 *__restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  out[k] = in[idx[k]];
+}
+
+__global__ void __launch_bounds__(256)
+    k_widen_keys(int64_t n, const int32_t *__restrict__ box, uint64_t *__restrict__ key) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  key[k] = (uint64_t)box[k];
 }
 
 }  // namespace
@@ -256,6 +385,108 @@ void launch_eval_points(int P, int64_t n, const double *tx, const double *ty, co
   }
 #undef LBS_EVAL_POINTS
   LBS_HIP(hipGetLastError());
+}
+
+
+void launch_gather_cx(int64_t n, const int32_t *idx, const double *in, double *out,
+                      hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gather_cx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, idx,
+                     (const double2 *)in, (double2 *)out);
+  LBS_HIP(hipGetLastError());
+}
+
+namespace {
+// (box, point) pairs sorted by box (stable, so points keep their order
+// within a box) and their CSR offsets over the plan's boxes.
+void pairs_by_box(int64_t n, DBuf<int32_t> &box, DBuf<int32_t> &pt, int nbox, DBuf<int64_t> &ptr,
+                  hipStream_t s) {
+  ptr.alloc((size_t)nbox + 1);
+  DBuf<uint64_t> key;
+  key.alloc((size_t)std::max<int64_t>(n, 1));
+  const unsigned g = (unsigned)((n + 256) / 256);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_widen_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, box.p,
+                       key.p);
+    int bits = 1;
+    while ((1ll << bits) <= (int64_t)nbox) ++bits;
+    sort_by_key(key.p, pt.p, n, bits, s);
+  }
+  hipLaunchKernelGGL(k_csr_ptr, dim3(g), dim3(256), 0, s, n, key.p, nbox, ptr.p);
+  LBS_HIP(hipGetLastError());
+  LBS_HIP(hipStreamSynchronize(s));  // key is released on return
+  box.release();
+}
+}  // namespace
+
+void build_point_sources(const DevPlan &pl, int64_t n, const double *x, const double *y,
+                         const int32_t *box, const int32_t *root, PointSources &ps,
+                         hipStream_t s) {
+  ps.n = n;
+  ps.x = x;
+  ps.y = y;
+  ps.n_m = ps.n_l = 0;
+  ps.nm = 0;
+  if (n <= 0) return;
+  if (n >= (int64_t)INT32_MAX) throw ApiError{LBS_ERR_UNSUPPORTED, "more than 2^31 points"};
+  const TreeView t{pl.cx.p, pl.cy.p, pl.rad.p, pl.lev.p, pl.parent.p, pl.child0.p, pl.nchild.p,
+                   pl.leaf.p, pl.s0.p, pl.s1.p, pl.sx.p, pl.sy.p};
+  DBuf<uint32_t> cm, cl, cd;
+  for (DBuf<uint32_t> *c : {&cm, &cl, &cd}) {
+    c->alloc((size_t)n + 1);
+    LBS_HIP(hipMemsetAsync(c->p, 0, ((size_t)n + 1) * sizeof(uint32_t), s));
+  }
+  const unsigned g = (unsigned)((n + 63) / 64);
+  hipLaunchKernelGGL(k_source_pairs<false>, dim3(g), dim3(64), 0, s, n, x, y, box, root, t, cm.p,
+                     cl.p, cd.p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  for (DBuf<uint32_t> *c : {&cm, &cl, &cd}) scan_u32(c->p, n + 1, s);
+  uint32_t tot[3] = {0, 0, 0};
+  LBS_HIP(hipMemcpyAsync(&tot[0], cm.p + n, 4, hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipMemcpyAsync(&tot[1], cl.p + n, 4, hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipMemcpyAsync(&tot[2], cd.p + n, 4, hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipStreamSynchronize(s));
+  const int64_t nm = tot[0], nl = tot[1], nd = tot[2];
+  DBuf<int32_t> mb, lb, db;
+  mb.alloc((size_t)std::max<int64_t>(nm, 1));
+  ps.m_t.alloc((size_t)std::max<int64_t>(nm, 1));
+  lb.alloc((size_t)std::max<int64_t>(nl, 1));
+  ps.l_t.alloc((size_t)std::max<int64_t>(nl, 1));
+  db.alloc((size_t)std::max<int64_t>(nd, 1));
+  ps.d_t.alloc((size_t)std::max<int64_t>(nd, 1));
+  hipLaunchKernelGGL(k_source_pairs<true>, dim3(g), dim3(64), 0, s, n, x, y, box, root, t, cm.p,
+                     cl.p, cd.p, mb.p, ps.m_t.p, lb.p, ps.l_t.p, db.p, ps.d_t.p);
+  LBS_HIP(hipGetLastError());
+  DBuf<int64_t> mptr;
+  pairs_by_box(nm, mb, ps.m_t, pl.nbox, mptr, s);
+  pairs_by_box(nl, lb, ps.l_t, pl.nbox, ps.l_ptr, s);
+  pairs_by_box(nd, db, ps.d_t, pl.nbox, ps.d_ptr, s);
+  ps.nm = nm;
+  // multipoles: every box of level >= 2 (boxes without points get zeros)
+  std::vector<int32_t> ml;
+  for (int b = 0; b < pl.nbox; ++b)
+    if (pl.host.level[b] >= 2) ml.push_back(b);
+  ps.n_m = (int)ml.size();
+  ps.m_list.upload(ml, s);
+  ps.m_rng.alloc((size_t)2 * std::max(ps.n_m, 1));
+  ps.m_geo.alloc((size_t)std::max(ps.n_m, 1));
+  if (ps.n_m > 0)
+    hipLaunchKernelGGL(k_mlist, dim3((unsigned)((ps.n_m + 255) / 256)), dim3(256), 0, s, ps.n_m,
+                       ps.m_list.p, mptr.p, pl.cx.p, pl.cy.p, pl.rad.p, ps.m_rng.p, ps.m_geo.p);
+  ps.m_x.alloc((size_t)std::max<int64_t>(nm, 1));
+  ps.m_y.alloc((size_t)std::max<int64_t>(nm, 1));
+  ps.m_p.alloc((size_t)2 * std::max<int64_t>(nm, 1));
+  if (nm > 0)
+    hipLaunchKernelGGL(k_gather_xy, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, nm,
+                       ps.m_t.p, x, y, ps.m_x.p, ps.m_y.p);
+  // local expansions: the boxes with pairs
+  std::vector<int64_t> lp = ps.l_ptr.download(s);
+  std::vector<int32_t> lbx;
+  for (int b = 0; b < pl.nbox; ++b)
+    if (lp[b + 1] > lp[b]) lbx.push_back(b);
+  ps.n_l = (int)lbx.size();
+  ps.l_box.upload(lbx, s);
+  LBS_HIP(hipGetLastError());
+  LBS_HIP(hipStreamSynchronize(s));  // host lists and counts are released on return
 }
 
 }  // namespace lbs

@@ -1468,6 +1468,57 @@ void fmm_apply64_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
   LBS_HIP(hipGetLastError());
 }
 
+template <int P>
+static void run64_sources(const DevPlan &pl, const Tables &tb, Workspace &ws,
+                          PointSources &ps, const cx<double> *pin, double *psi, double *dpsi,
+                          hipStream_t s) {
+  auto *M = (cx<double> *)ws.mult64.p;
+  auto *L = (cx<double> *)ws.loc64.p;
+  const auto *H = (const double *)tb.h64.p;
+  const auto *itp = (const cx<double> *)tb.itp64.p;
+  // multipoles of every box of level >= 2 from the points it holds
+  launch_gather_cx(ps.nm, ps.m_t.p, (const double *)pin, ps.m_p.p, s);
+  if (ps.n_m > 0)
+    hipLaunchKernelGGL((k_p2m<double, P>), dim3(ps.n_m, 1), dim3(64), 0, s, ps.m_list.p,
+                       ps.m_rng.p, ps.m_geo.p, ps.m_x.p, ps.m_y.p, (cx<double> *)ps.m_p.p,
+                       ps.nm, M, pl.nbox, StrengthSrc{});
+  // the tree's V lists, then the points' own local-expansion terms
+  if (pl.n_m2l > 0)
+    hipLaunchKernelGGL((k_m2l<double, P>), dim3(pl.n_m2l, 1), dim3(64), 0, s, pl.m2l_box.p,
+                       pl.v_ptr.p, pl.v_src.p, pl.v_code.p, H, itp, (const cx<double> *)M, L,
+                       pl.nbox);
+  if (ps.n_l > 0)
+    hipLaunchKernelGGL((k_p2l<double, P>), dim3(ps.n_l, 1), dim3(64), 0, s, ps.l_box.p,
+                       ps.l_ptr.p, ps.l_t.p, pl.cx.p, pl.cy.p, pl.rad.p, ps.x, ps.y, pin, ps.n,
+                       L, pl.nbox);
+  run_pass<double, P, true>(pl.dn[1], (const double *)tb.bc64.p, (const cx<double> *)tb.pre64.p,
+                            (const cx<double> *)tb.post64.p, L, pl.nbox, 1, s);
+  // at the plan's targets: local expansions, W lists, direct sums
+  if (pl.n_leaf_t > 0)
+    hipLaunchKernelGGL((k_leaf64_full<P>), dim3(pl.n_leaf_t), dim3(64), 0, s, pl.leaf_t.p,
+                       pl.lev.p, pl.t0.p, pl.t1.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p,
+                       pl.tx.p, pl.ty.p, pl.tgt_perm.p, ps.d_ptr.p, ps.d_t.p, pl.w_ptr.p,
+                       pl.w_src.p, ps.x, ps.y, pin, (const cx<double> *)M,
+                       (const cx<double> *)L, psi, dpsi);
+}
+
+void fmm_sources64_full(const DevPlan &pl, const Tables &tb, Workspace &ws, PointSources &ps,
+                        const double *pin, double *psi, double *dpsi, hipStream_t s) {
+  const auto *pc = (const cx<double> *)pin;
+  switch (tb.P) {
+    case 20: run64_sources<20>(pl, tb, ws, ps, pc, psi, dpsi, s); break;
+    case 24: run64_sources<24>(pl, tb, ws, ps, pc, psi, dpsi, s); break;
+    case 30: run64_sources<30>(pl, tb, ws, ps, pc, psi, dpsi, s); break;
+    case 36: run64_sources<36>(pl, tb, ws, ps, pc, psi, dpsi, s); break;
+    case 40: run64_sources<40>(pl, tb, ws, ps, pc, psi, dpsi, s); break;
+    case 48: run64_sources<48>(pl, tb, ws, ps, pc, psi, dpsi, s); break;
+    default:
+      throw ApiError{LBS_ERR_UNSUPPORTED,
+                     "p64 must be one of 20, 24, 30, 36, 40, 48"};
+  }
+  LBS_HIP(hipGetLastError());
+}
+
 // FP32 counterpart for the transposed operator (field only): strengths in
 // FP32, near-field differences formed in FP64 as in k_leaf32.
 __global__ void k_strengths_given32(int64_t ns, const int64_t *__restrict__ perm,

@@ -861,6 +861,12 @@ void launch_flat_fill(int64_t ne, const int32_t *box, const int64_t *eo, const i
   LBS_HIP(hipGetLastError());
 }
 
+void scan_u32(uint32_t *a, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, a, n);
+  LBS_HIP(hipGetLastError());
+}
+
 void sort_by_key(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {
   SortScratch sc;
   radix_sort(keys, vals, n, bits, sc, s);

@@ -518,6 +518,37 @@ void launch_flat_fill(int64_t ne, const int32_t *box, const int64_t *eo, const i
 void launch_widen_perm(int64_t n, const int32_t *perm, const int64_t *map, int64_t *out,
                        hipStream_t s);
 void launch_fill_int(int64_t n, int32_t v, int32_t *x, hipStream_t s);
+// In-place exclusive scan of a[0 .. n) (gtree.hip)
+void scan_u32(uint32_t *a, int64_t n, hipStream_t s);
+// out[k] = in[idx[k]] for complex (double2) entries (evalpts.hip)
+void launch_gather_cx(int64_t n, const int32_t *idx, const double *in, double *out,
+                      hipStream_t s);
+// Sources at n arbitrary points (x, y) located in a plan's tree (box: the
+// deepest box whose square holds the point, -1 outside the root square;
+// root: its tree's root), as (box, point) pairs sorted by box: the
+// multipole of every box of level >= 2 holding the point (list m_list,
+// ranges m_rng into the pair-ordered coordinates m_x, m_y), the local
+// expansions its walk takes by multipole (l_box; offsets l_ptr over the
+// plan's boxes into l_t), the leaves its walk sums directly (d_ptr, d_t).
+// The plan needs its tree links on the device.  (evalpts.hip)
+struct PointSources {
+  int64_t n = 0, nm = 0;
+  const double *x = nullptr, *y = nullptr;  // not owned
+  int n_m = 0, n_l = 0;
+  DBuf<int32_t> m_list, m_t, l_box, l_t, d_t;
+  DBuf<int64_t> m_rng, l_ptr, d_ptr;
+  DBuf<double4> m_geo;
+  DBuf<double> m_x, m_y, m_p;  // m_p: the pairs' strengths of a call
+};
+void build_point_sources(const DevPlan &pl, int64_t n, const double *x, const double *y,
+                         const int32_t *box, const int32_t *root, PointSources &ps,
+                         hipStream_t s);
+// Psi(z) = sum_t c_t / (z - z_t) and Psi'(z) (complex, FP64) at the plan's
+// targets (API order; dpsi may be null) from complex strengths pin of the
+// located point sources (their order), through the plan's own expansions
+// (ws.mult64, ws.loc64, one column).  (fmm.hip)
+void fmm_sources64_full(const DevPlan &pl, const Tables &tb, Workspace &ws, PointSources &ps,
+                        const double *pin, double *psi, double *dpsi, hipStream_t s);
 // Stable sort of (keys, vals) by the low `bits` bits of the keys (gtree.hip)
 void sort_by_key(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
 // Targets located in a plan's tree (evalpts.hip): the n targets (tx, ty;

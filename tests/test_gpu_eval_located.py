@@ -4,7 +4,9 @@ evaluation and against the evaluation over a quadtree of nodes and targets
 (eval_tree = 1): targets away from the curves, in quadrants without nodes,
 far outside the nodes' root square (near the north pole), at the pole,
 exactly at nodes; several right-hand sides; batch handles; the full-size
-workload at 1e5 targets.
+workload at 1e5 targets.  The same for the transposed evaluation
+(lbs_eval_T), where the located targets are the sources of the handle's
+own FMM, against the oracle's dense transpose.
 
 The two evaluations are different FMM approximations of the same sums, each
 within the FMM's error at p64 = 30 (ratio 0.47 at worst): each is held to
@@ -19,7 +21,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import evaluate
+from oracle import adjoint, evaluate
 from oracle.geometry import Curves
 
 pytestmark = pytest.mark.gpu
@@ -168,3 +170,58 @@ def test_located_full_size(env):
     v2 = ref_tree.eval(sig, A, tg2)
     assert _rel(_np(u), _np(v)) < 3e-10
     assert _rel(_np(u2), _np(v2)) < 3e-10
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_located_transpose_matches_dense(env, case):
+    torch, lbs = env
+    seed, m, n, rr, lm = case
+    isl = synth.star_islands(seed, m, rr, nodes=n)
+    cv = Curves(isl)
+    tg = np.concatenate([synth.sphere_targets(seed + 6, 400, isl), _near_pole(30, seed + 7),
+                         [[0.0, 0.0, 1.0]]])
+    rng = np.random.default_rng(seed + 9)
+    W = rng.standard_normal((2, len(tg)))
+    loc = lbs.Solver(isl, leaf_max=lm)
+    ref_tree = lbs.Solver(isl, leaf_max=lm, eval_tree=1)
+    gs, ga = loc.eval_T(_t(torch, W), _t(torch, tg))
+    gs2, _ = ref_tree.eval_T(_t(torch, W[:, :400]), _t(torch, tg[:400]))
+    for r in range(2):
+        rs, ra = adjoint.eval_transpose(cv, tg, W[r])
+        print(f"column {r}: located {_rel(_np(gs[r]), rs):.2e}")
+        assert _rel(_np(gs[r]), rs) < 1e-10, r
+        assert _rel(_np(ga[r]), ra) < 1e-12, r
+        rs4, _ = adjoint.eval_transpose(cv, tg[:400], W[r, :400])
+        assert _rel(_np(gs2[r]), rs4) < 1e-10, r
+    # duality with the located forward evaluation: w . u(sigma, A) equals
+    # (eval_T w) . (sigma, A) to the FMM's accuracy
+    sig = synth.random_vector(seed + 10, cv.n)
+    A = synth.random_vector(seed + 11, cv.m)
+    u = _np(loc.eval(_t(torch, sig), _t(torch, A), _t(torch, tg)))
+    lhs = W[0] @ u
+    rhs = _np(gs[0]) @ sig + _np(ga[0]) @ A
+    assert abs(lhs - rhs) < 1e-10 * np.abs(W[0]).sum() * np.abs(u).max()
+
+
+def test_located_transpose_full_size(env):
+    """2000 star islands x 512 nodes, 1e5 targets: the located transposed
+    evaluation against the tree path on every node; timed on a second
+    target set."""
+    torch, lbs = env
+    import time
+    isl = synth.config_islands("stars2000x512")
+    loc = lbs.Solver(isl, leaf_max=64)
+    tg = _t(torch, synth.sphere_targets(94, 100000, isl))
+    w = _t(torch, np.random.default_rng(95).standard_normal(100000))
+    gs, ga = loc.eval_T(w, tg)
+    tg2 = _t(torch, synth.sphere_targets(96, 100000, isl))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gs2, ga2 = loc.eval_T(w, tg2)
+    torch.cuda.synchronize()
+    print(f"eval_T at 1e5 new targets: {1e3 * (time.perf_counter() - t0):.2f} ms", flush=True)
+    del loc
+    ref_tree = lbs.Solver(isl, leaf_max=64, eval_tree=1)
+    hs, ha = ref_tree.eval_T(w, tg)
+    assert _rel(_np(gs), _np(hs)) < 3e-10
+    assert _rel(_np(ga), _np(ha)) < 1e-12
