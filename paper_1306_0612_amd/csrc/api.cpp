@@ -358,7 +358,7 @@ struct GmresState {
 // the nodes the targets.  Targets at the north pole carry no Cauchy part and
 // are left out of the trees.
 struct EvalPlan {
-  std::vector<double> key;      // host copy of the targets (T x 3)
+  DBuf<double> dkey;            // device copy of the targets (T x 3)
   std::vector<int64_t> toff;    // geometry-major target offsets
   std::vector<int32_t> tgeo;    // geometry of each target
   std::vector<double> tx, ty;   // projected non-pole targets (compact)
@@ -433,8 +433,13 @@ struct lbs_ctx {
   DBuf<int32_t> cg_ptr, cg_isl;
   DBuf<double> cg_zone;
   int32_t *count_host = nullptr;
+  // pinned staging for target coordinates read back to the host
+  double *stage_host = nullptr;
+  size_t stage_n = 0;
+  DBuf<int32_t> diff;  // device flag of the target comparison
   ~lbs_ctx() {
     if (count_host) (void)hipHostFree(count_host);
+    if (stage_host) (void)hipHostFree(stage_host);
   }
 };
 
@@ -1572,12 +1577,24 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
   const int G = g.G;
   const int64_t T = toff[G];
   HostPhase ph_all("eval plan (all)");
-  std::vector<double> hx(3 * T);
-  LBS_HIP(hipMemcpyAsync(hx.data(), txyz, 3 * T * sizeof(double), hipMemcpyDeviceToHost, s));
-  LBS_HIP(hipStreamSynchronize(s));
   std::unique_ptr<EvalPlan> &slot = transposed ? c.evt : c.evf;
-  if (slot && slot->toff == toff && slot->key == hx) return *slot;
+  if (slot && slot->toff == toff && slot->dkey.n == (size_t)(3 * T)) {
+    // the same targets as the cached plan's (compared on the device)
+    if (c.diff.n == 0) c.diff.alloc(1);
+    if (!targets_differ(3 * T, txyz, slot->dkey.p, c.diff.p, c.count_host + 1, s)) return *slot;
+  }
   slot.reset();
+  if (c.stage_n < (size_t)(3 * T)) {
+    if (c.stage_host) (void)hipHostFree(c.stage_host);
+    c.stage_host = nullptr;
+    c.stage_n = 0;
+    LBS_HIP(hipHostMalloc((void **)&c.stage_host, 3 * T * sizeof(double), hipHostMallocDefault));
+    c.stage_n = (size_t)(3 * T);
+  }
+  if (T > 0)
+    LBS_HIP(hipMemcpyAsync(c.stage_host, txyz, 3 * T * sizeof(double), hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipStreamSynchronize(s));
+  std::vector<double> hx(c.stage_host, c.stage_host + 3 * T);
   auto ep = std::make_unique<EvalPlan>();
   ep->toff = toff;
   ep->tgeo.resize(T);
@@ -1681,8 +1698,10 @@ EvalPlan &eval_plan(lbs_ctx &c, bool transposed, const std::vector<int64_t> &tof
     HostPhase ph("eval plan close pairs");
     build_close(c, *ep, hx, txyz, s);
   }
+  ep->dkey.alloc((size_t)(3 * T));
+  if (T > 0)
+    LBS_HIP(hipMemcpyAsync(ep->dkey.p, txyz, 3 * T * sizeof(double), hipMemcpyDeviceToDevice, s));
   LBS_HIP(hipStreamSynchronize(s));
-  ep->key = std::move(hx);
   slot = std::move(ep);
   return *slot;
 }

@@ -22,6 +22,7 @@
 // the walk over the whole tree.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -327,6 +328,16 @@ __global__ void __launch_bounds__(256)
 }
 
 __global__ void __launch_bounds__(256)
+    k_differ(int64_t n, const unsigned long long *__restrict__ a,
+             const unsigned long long *__restrict__ b, int32_t *__restrict__ flag) {
+  bool d = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d = d || a[i] != b[i];
+  if (d) *flag = 1;  // every writer writes the same value
+}
+
+__global__ void __launch_bounds__(256)
     k_widen_keys(int64_t n, const int32_t *__restrict__ box, uint64_t *__restrict__ key) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
@@ -387,6 +398,19 @@ void launch_eval_points(int P, int64_t n, const double *tx, const double *ty, co
   LBS_HIP(hipGetLastError());
 }
 
+
+bool targets_differ(int64_t n, const double *a, const double *b, int32_t *dflag,
+                    int32_t *hflag, hipStream_t s) {
+  if (n <= 0) return false;
+  launch_fill_int(1, 0, dflag, s);
+  const unsigned g = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_differ, dim3(g), dim3(256), 0, s, n, (const unsigned long long *)a,
+                     (const unsigned long long *)b, dflag);
+  LBS_HIP(hipGetLastError());
+  LBS_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipStreamSynchronize(s));
+  return *hflag != 0;
+}
 
 void launch_gather_cx(int64_t n, const int32_t *idx, const double *in, double *out,
                       hipStream_t s) {

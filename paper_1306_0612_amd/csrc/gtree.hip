@@ -93,6 +93,77 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
+// Tiled exclusive scan: tiles of 4096 entries, four consecutive entries per
+// thread (coalesced), thread totals scanned across the wave by shuffles and
+// across the 16 waves through LDS; with offs, tile t adds offs[t] (the
+// exclusive scan of the tile sums, k_tile_sums).
+constexpr int kScanTile = 4096;
+__device__ __forceinline__ uint32_t block_exclusive_1024(uint32_t v, uint32_t &total) {
+  __shared__ uint32_t wsum[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += u;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int w = 0; w < 16; ++w) {
+    const uint32_t x = wsum[w];
+    before += w < wave ? x : 0u;
+    all += x;
+  }
+  __syncthreads();  // wsum is rewritten by the next call
+  total = all;
+  return before + inc - v;
+}
+
+__global__ void __launch_bounds__(1024)
+    k_tile_sums(const uint32_t *__restrict__ a, int64_t n, uint32_t *__restrict__ sums) {
+  const int64_t i0 = (int64_t)blockIdx.x * kScanTile + 4 * threadIdx.x;
+  uint32_t v = 0;
+  for (int k = 0; k < 4; ++k)
+    if (i0 + k < n) v += a[i0 + k];
+  uint32_t total;
+  (void)block_exclusive_1024(v, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(1024)
+    k_scan_tiles(uint32_t *__restrict__ a, int64_t n, const uint32_t *__restrict__ offs) {
+  const int64_t i0 = (int64_t)blockIdx.x * kScanTile + 4 * threadIdx.x;
+  uint32_t x[4], v = 0;
+  for (int k = 0; k < 4; ++k) {
+    x[k] = i0 + k < n ? a[i0 + k] : 0u;
+    v += x[k];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_1024(v, total) + (offs ? offs[blockIdx.x] : 0u);
+  for (int k = 0; k < 4; ++k)
+    if (i0 + k < n) {
+      a[i0 + k] = run;
+      run += x[k];
+    }
+}
+
+// In-place exclusive scan of a[0 .. n) with tile sums in sums (at least
+// ceil(n / 4096) entries; not needed for n <= 4096).
+void scan_into(uint32_t *a, int64_t n, uint32_t *sums, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t nt = (n + kScanTile - 1) / kScanTile;
+  if (nt == 1) {
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, a, n, nullptr);
+  } else if (nt <= kScanTile) {
+    hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)nt), dim3(1024), 0, s, a, n, sums);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, sums, nt, nullptr);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(1024), 0, s, a, n, sums);
+  } else {
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, a, n);
+  }
+  LBS_HIP(hipGetLastError());
+}
+
 // Stable scatter of one tile: 16 rounds of 256 consecutive keys; a key's
 // place = the digit's global offset for this tile + the digit's count in
 // earlier rounds + in earlier waves of this round + earlier lanes of its
@@ -149,11 +220,13 @@ __global__ void __launch_bounds__(256)
 struct SortScratch {
   DBuf<uint64_t> k2;
   DBuf<int32_t> v2;
-  DBuf<uint32_t> hist;
+  DBuf<uint32_t> hist, sums;
   void ensure(int64_t n, int ntiles) {
     if ((int64_t)k2.n < n) k2.alloc((size_t)n);
     if ((int64_t)v2.n < n) v2.alloc((size_t)n);
     if ((int64_t)hist.n < (int64_t)256 * ntiles) hist.alloc((size_t)256 * ntiles);
+    const int64_t nt = ((int64_t)256 * ntiles + kScanTile - 1) / kScanTile;
+    if ((int64_t)sums.n < nt) sums.alloc((size_t)nt);
   }
 };
 
@@ -172,7 +245,7 @@ void radix_sort(uint64_t *keys, int32_t *vals, int64_t n, int bits, SortScratch 
   int passes = 0;
   for (int shift = 0; shift < bits; shift += 8, ++passes) {
     hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(256), 0, s, ka, n, shift, ntiles, hist.p);
-    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, hist.p, (int64_t)256 * ntiles);
+    scan_into(hist.p, (int64_t)256 * ntiles, sc.sums.p, s);
     hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(256), 0, s, ka, va, n, shift, ntiles,
                        hist.p, kb, vb);
     std::swap(ka, kb);
@@ -651,7 +724,7 @@ void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t
   int nbox = 1;
   {
     DBuf<int32_t> nc;
-    DBuf<uint32_t> off;
+    DBuf<uint32_t> off, sums;
     DBuf<int64_t> cr;
     int lbeg = 0;
     for (int l = 0;; ++l) {
@@ -663,6 +736,7 @@ void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t
         nc.alloc((size_t)n);
         off.alloc((size_t)n + 1);
         cr.alloc((size_t)n * 16);
+        sums.alloc((size_t)(n + kScanTile) / kScanTile + 1);
       }
       hipLaunchKernelGGL(k_split_count, dim3((n + 255) / 256), dim3(256), 0, s, l, lbeg, lend,
                          leaf_max, self ? 1 : 0, ks.p, self ? ks.p : kt.p, view(), nc.p, cr.p);
@@ -670,7 +744,7 @@ void gpu_build_tree(const double *sx, const double *sy, int64_t sstride, int64_t
       LBS_HIP(hipMemcpyAsync(off.p, nc.p, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
       uint32_t zero = 0;
       LBS_HIP(hipMemcpyAsync(off.p + n, &zero, sizeof(uint32_t), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, off.p, (int64_t)n + 1);
+      scan_into(off.p, (int64_t)n + 1, sums.p, s);
       uint32_t total = 0;
       LBS_HIP(hipMemcpyAsync(&total, off.p + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       LBS_HIP(hipStreamSynchronize(s));
@@ -863,8 +937,10 @@ void launch_flat_fill(int64_t ne, const int32_t *box, const int64_t *eo, const i
 
 void scan_u32(uint32_t *a, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, a, n);
-  LBS_HIP(hipGetLastError());
+  DBuf<uint32_t> sums;
+  if (n > kScanTile) sums.alloc((size_t)((n + kScanTile - 1) / kScanTile));
+  scan_into(a, n, sums.p, s);
+  if (sums.p) LBS_HIP(hipStreamSynchronize(s));  // sums is released on return
 }
 
 void sort_by_key(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {

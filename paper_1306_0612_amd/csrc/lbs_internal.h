@@ -520,6 +520,10 @@ void launch_widen_perm(int64_t n, const int32_t *perm, const int64_t *map, int64
 void launch_fill_int(int64_t n, int32_t v, int32_t *x, hipStream_t s);
 // In-place exclusive scan of a[0 .. n) (gtree.hip)
 void scan_u32(uint32_t *a, int64_t n, hipStream_t s);
+// Whether a[0 .. n) and b[0 .. n) differ bit for bit (dflag: one device
+// int32, hflag: one pinned host int32; waits for the stream).  (evalpts.hip)
+bool targets_differ(int64_t n, const double *a, const double *b, int32_t *dflag,
+                    int32_t *hflag, hipStream_t s);
 // out[k] = in[idx[k]] for complex (double2) entries (evalpts.hip)
 void launch_gather_cx(int64_t n, const int32_t *idx, const double *in, double *out,
                       hipStream_t s);
