@@ -23,8 +23,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 
 #include "cplx.h"
 #include "lbs_internal.h"
@@ -421,25 +424,37 @@ void launch_gather_cx(int64_t n, const int32_t *idx, const double *in, double *o
 }
 
 namespace {
+// Wall time of the phases of a build, printed to stderr when
+// LBS_HOST_TIMING is set (each mark waits for the stream first).
+struct BuildClock {
+  bool on = std::getenv("LBS_HOST_TIMING") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void mark(const char *name, hipStream_t s) {
+    if (!on) return;
+    LBS_HIP(hipStreamSynchronize(s));
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[lbs host] point sources: %-14s %9.3f ms\n", name,
+                 std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
+
 // (box, point) pairs sorted by box (stable, so points keep their order
-// within a box) and their CSR offsets over the plan's boxes.
-void pairs_by_box(int64_t n, DBuf<int32_t> &box, DBuf<int32_t> &pt, int nbox, DBuf<int64_t> &ptr,
-                  hipStream_t s) {
+// within a box) and their CSR offsets over the plan's boxes; key is
+// scratch of at least n + 1 entries.
+void pairs_by_box(int64_t n, const int32_t *box, int32_t *pt, int nbox, uint64_t *key,
+                  SortBufs &sc, DBuf<int64_t> &ptr, hipStream_t s) {
   ptr.alloc((size_t)nbox + 1);
-  DBuf<uint64_t> key;
-  key.alloc((size_t)std::max<int64_t>(n, 1));
-  const unsigned g = (unsigned)((n + 256) / 256);
   if (n > 0) {
-    hipLaunchKernelGGL(k_widen_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, box.p,
-                       key.p);
+    hipLaunchKernelGGL(k_widen_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, box,
+                       key);
     int bits = 1;
     while ((1ll << bits) <= (int64_t)nbox) ++bits;
-    sort_by_key(key.p, pt.p, n, bits, s);
+    sort_by_key(key, pt, n, bits, sc, s);
   }
-  hipLaunchKernelGGL(k_csr_ptr, dim3(g), dim3(256), 0, s, n, key.p, nbox, ptr.p);
+  hipLaunchKernelGGL(k_csr_ptr, dim3((unsigned)((n + 256) / 256)), dim3(256), 0, s, n, key, nbox,
+                     ptr.p);
   LBS_HIP(hipGetLastError());
-  LBS_HIP(hipStreamSynchronize(s));  // key is released on return
-  box.release();
 }
 }  // namespace
 
@@ -449,44 +464,54 @@ void build_point_sources(const DevPlan &pl, int64_t n, const double *x, const do
   ps.n = n;
   ps.x = x;
   ps.y = y;
-  ps.n_m = ps.n_l = 0;
+  ps.n_m = 0;
   ps.nm = 0;
   if (n <= 0) return;
   if (n >= (int64_t)INT32_MAX) throw ApiError{LBS_ERR_UNSUPPORTED, "more than 2^31 points"};
+  BuildClock clk;
   const TreeView t{pl.cx.p, pl.cy.p, pl.rad.p, pl.lev.p, pl.parent.p, pl.child0.p, pl.nchild.p,
                    pl.leaf.p, pl.s0.p, pl.s1.p, pl.sx.p, pl.sy.p};
-  DBuf<uint32_t> cm, cl, cd;
-  for (DBuf<uint32_t> *c : {&cm, &cl, &cd}) {
-    c->alloc((size_t)n + 1);
-    LBS_HIP(hipMemsetAsync(c->p, 0, ((size_t)n + 1) * sizeof(uint32_t), s));
-  }
+  // counts of the three kinds of pairs per point, scanned into offsets
+  const int64_t n1 = n + 1, nts = (n1 + 4095) / 4096;
+  DBuf<uint32_t> cnt;
+  cnt.alloc((size_t)(3 * n1 + 3 * nts));
+  uint32_t *cm = cnt.p, *cl = cm + n1, *cd = cl + n1, *sums = cd + n1;
+  LBS_HIP(hipMemsetAsync(cnt.p, 0, (size_t)(3 * n1) * sizeof(uint32_t), s));
   const unsigned g = (unsigned)((n + 63) / 64);
-  hipLaunchKernelGGL(k_source_pairs<false>, dim3(g), dim3(64), 0, s, n, x, y, box, root, t, cm.p,
-                     cl.p, cd.p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
-  for (DBuf<uint32_t> *c : {&cm, &cl, &cd}) scan_u32(c->p, n + 1, s);
+  hipLaunchKernelGGL(k_source_pairs<false>, dim3(g), dim3(64), 0, s, n, x, y, box, root, t, cm, cl,
+                     cd, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  for (uint32_t *c : {cm, cl, cd}) scan_into(c, n1, sums, s);
   uint32_t tot[3] = {0, 0, 0};
-  LBS_HIP(hipMemcpyAsync(&tot[0], cm.p + n, 4, hipMemcpyDeviceToHost, s));
-  LBS_HIP(hipMemcpyAsync(&tot[1], cl.p + n, 4, hipMemcpyDeviceToHost, s));
-  LBS_HIP(hipMemcpyAsync(&tot[2], cd.p + n, 4, hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipMemcpyAsync(&tot[0], cm + n, 4, hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipMemcpyAsync(&tot[1], cl + n, 4, hipMemcpyDeviceToHost, s));
+  LBS_HIP(hipMemcpyAsync(&tot[2], cd + n, 4, hipMemcpyDeviceToHost, s));
   LBS_HIP(hipStreamSynchronize(s));
+  clk.mark("count", s);
   const int64_t nm = tot[0], nl = tot[1], nd = tot[2];
-  DBuf<int32_t> mb, lb, db;
-  mb.alloc((size_t)std::max<int64_t>(nm, 1));
+  const int64_t nmax = std::max<int64_t>({nm, nl, nd, 1});
+  DBuf<int32_t> boxes;  // the pairs' boxes, each kind in turn
+  boxes.alloc((size_t)(nm + nl + nd + 1));
+  int32_t *mb = boxes.p, *lb = mb + nm, *db = lb + nl;
   ps.m_t.alloc((size_t)std::max<int64_t>(nm, 1));
-  lb.alloc((size_t)std::max<int64_t>(nl, 1));
   ps.l_t.alloc((size_t)std::max<int64_t>(nl, 1));
-  db.alloc((size_t)std::max<int64_t>(nd, 1));
   ps.d_t.alloc((size_t)std::max<int64_t>(nd, 1));
-  hipLaunchKernelGGL(k_source_pairs<true>, dim3(g), dim3(64), 0, s, n, x, y, box, root, t, cm.p,
-                     cl.p, cd.p, mb.p, ps.m_t.p, lb.p, ps.l_t.p, db.p, ps.d_t.p);
+  hipLaunchKernelGGL(k_source_pairs<true>, dim3(g), dim3(64), 0, s, n, x, y, box, root, t, cm, cl,
+                     cd, mb, ps.m_t.p, lb, ps.l_t.p, db, ps.d_t.p);
   LBS_HIP(hipGetLastError());
+  clk.mark("fill", s);
+  DBuf<uint64_t> key;
+  key.alloc((size_t)nmax + 1);
+  SortBufs sc;
   DBuf<int64_t> mptr;
-  pairs_by_box(nm, mb, ps.m_t, pl.nbox, mptr, s);
-  pairs_by_box(nl, lb, ps.l_t, pl.nbox, ps.l_ptr, s);
-  pairs_by_box(nd, db, ps.d_t, pl.nbox, ps.d_ptr, s);
+  pairs_by_box(nm, mb, ps.m_t.p, pl.nbox, key.p, sc, mptr, s);
+  pairs_by_box(nl, lb, ps.l_t.p, pl.nbox, key.p, sc, ps.l_ptr, s);
+  pairs_by_box(nd, db, ps.d_t.p, pl.nbox, key.p, sc, ps.d_ptr, s);
   ps.nm = nm;
-  // multipoles: every box of level >= 2 (boxes without points get zeros)
+  clk.mark("sort", s);
+  // multipoles and local expansions: every box of level >= 2 (the kernels
+  // pass over boxes without pairs)
   std::vector<int32_t> ml;
+  ml.reserve((size_t)pl.nbox);
   for (int b = 0; b < pl.nbox; ++b)
     if (pl.host.level[b] >= 2) ml.push_back(b);
   ps.n_m = (int)ml.size();
@@ -502,15 +527,9 @@ void build_point_sources(const DevPlan &pl, int64_t n, const double *x, const do
   if (nm > 0)
     hipLaunchKernelGGL(k_gather_xy, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, nm,
                        ps.m_t.p, x, y, ps.m_x.p, ps.m_y.p);
-  // local expansions: the boxes with pairs
-  std::vector<int64_t> lp = ps.l_ptr.download(s);
-  std::vector<int32_t> lbx;
-  for (int b = 0; b < pl.nbox; ++b)
-    if (lp[b + 1] > lp[b]) lbx.push_back(b);
-  ps.n_l = (int)lbx.size();
-  ps.l_box.upload(lbx, s);
   LBS_HIP(hipGetLastError());
-  LBS_HIP(hipStreamSynchronize(s));  // host lists and counts are released on return
+  LBS_HIP(hipStreamSynchronize(s));  // scratch and host lists are released on return
+  clk.mark("lists", s);
 }
 
 }  // namespace lbs

@@ -251,6 +251,7 @@ __global__ void __launch_bounds__(64)
   cx<T> *pr = p + (int64_t)r * ns;
   double gsum = 0.0;
   const int64_t e0 = ls_rng[2 * blockIdx.x], e1 = ls_rng[2 * blockIdx.x + 1];
+  if (e1 == e0 && !ss.gpart) return;  // an empty range: the whole wave, M left as it is
   const int vi = lane >> SH;
   const bool writer = (lane & ((1 << SH) - 1)) == 0;
 #pragma unroll
@@ -752,6 +753,7 @@ __global__ void __launch_bounds__(64)
   const int b = boxes[blockIdx.x];
   const int r = blockIdx.y;
   const int64_t xf0 = xf_ptr[b];
+  if (xf_ptr[b + 1] == xf0) return;  // nothing to add (the whole wave)
   p2l_pass<T, P, 0>(xf0, (int)(xf_ptr[b + 1] - xf0), xf_idx, cxv[b], cyv[b],
                     T(rad[b]), sx, sy, p + (int64_t)r * ns,
                     reinterpret_cast<T *>(L + ((int64_t)r * nbox + b) * P),
@@ -1334,7 +1336,12 @@ __global__ void k_strengths_given(int64_t ns, const int64_t *__restrict__ perm,
   p[j] = cx<double>{pin[2 * a], pin[2 * a + 1]};
 }
 
-template <int P>
+// Psi and (DERIV) Psi' at the targets of one leaf (one 64-lane block):
+// lanes are (target, slice) as in the FP32 kernels, tp = pow2 >= #targets
+// (64 above 32 targets) lanes per slice and S = 64 / tp slices, each taking
+// every S-th W-list box and staged source; slices are summed by shuffles.
+// Reciprocals by rcp64 (hardware estimate and two Newton-Raphson steps).
+template <int P, bool DERIV>
 __global__ void __launch_bounds__(64)
     k_leaf64_full(const int32_t *__restrict__ leaves,
                   const int32_t *__restrict__ lev,
@@ -1358,41 +1365,44 @@ __global__ void __launch_bounds__(64)
   const int b = leaves[blockIdx.x];
   const int lane = threadIdx.x;
   const int64_t tb0 = t0[b], ntb = t1[b] - tb0;
+  const int tp = ntb <= 32 ? pow2_at_least((int)ntb) : 64;
+  const int S = 64 / tp, tl = lane % tp, sl = lane / tp;
   const int64_t uf0 = uf_ptr[b];
   const int utot = (int)(uf_ptr[b + 1] - uf0);  // U-list sources of the leaf
   const int wb = w_ptr[b], we = w_ptr[b + 1];
-  for (int64_t tc = 0; tc < ntb; tc += 64) {
-    const int64_t i = tb0 + tc + lane;
-    const bool act = tc + lane < ntb;
+  for (int64_t tc = 0; tc < ntb; tc += tp) {
+    const int64_t i = tb0 + tc + tl;
+    const bool act = tc + tl < ntb;
     const double zx = act ? tx[i] : 0.0, zy = act ? ty[i] : 0.0;
     cx<double> f{0.0, 0.0}, df{0.0, 0.0};
-    if (act && lev[b] >= 2) {
-      const double ir = 1.0 / rad[b];
-      const cx<double> w{(zx - cxv[b]) * ir, (zy - cyv[b]) * ir};
-      const cx<double> *Lb = L + (int64_t)b * P;
-      cx<double> acc = Lb[P - 1], dacc = (double)(P - 1) * Lb[P - 1];
-      for (int l = P - 2; l >= 1; --l) {
-        acc = cfma(acc, w, Lb[l]);
-        dacc = dacc * w + (double)l * Lb[l];
-      }
-      acc = cfma(acc, w, Lb[0]);
-      f = f + acc;
-      df = df + ir * dacc;
-    }
     if (act) {
-      for (int e = wb; e < we; ++e) {
+      if (sl == 0 && lev[b] >= 2) {
+        const double ir = 1.0 / rad[b];
+        const cx<double> w{(zx - cxv[b]) * ir, (zy - cyv[b]) * ir};
+        const cx<double> *Lb = L + (int64_t)b * P;
+        cx<double> acc = Lb[P - 1], dacc = (double)(P - 1) * Lb[P - 1];
+        for (int l = P - 2; l >= 1; --l) {
+          acc = cfma(acc, w, Lb[l]);
+          if constexpr (DERIV) dacc = dacc * w + (double)l * Lb[l];
+        }
+        acc = cfma(acc, w, Lb[0]);
+        f = f + acc;
+        if constexpr (DERIV) df = df + ir * dacc;
+      }
+      for (int e = wb + sl; e < we; e += S) {
         const int c = w_src[e];
-        const cx<double> iz = cinv(cx<double>{zx - cxv[c], zy - cyv[c]});
+        const double dx = zx - cxv[c], dy = zy - cyv[c];
+        const double r2 = rcp64(fma(dx, dx, dy * dy));
+        const cx<double> iz{dx * r2, -dy * r2};
         const cx<double> rho = rad[c] * iz;
         const cx<double> *a = M + (int64_t)c * P;
         cx<double> acc = a[P - 1], dacc = (double)P * a[P - 1];
         for (int k = P - 2; k >= 0; --k) {
           acc = cfma(acc, rho, a[k]);
-          dacc = dacc * rho + (double)(k + 1) * a[k];
+          if constexpr (DERIV) dacc = dacc * rho + (double)(k + 1) * a[k];
         }
         f = f + acc * rho;
-        const cx<double> d = (dacc * rho) * iz;
-        df = df - d;
+        if constexpr (DERIV) df = df - (dacc * rho) * iz;
       }
     }
     {  // the leaf's U-list sources, kStage at a time
@@ -1406,23 +1416,33 @@ __global__ void __launch_bounds__(64)
         }
         __syncthreads();
         if (act) {
-          for (int q = 0; q < take; ++q) {
-            const cx<double> d{zx - sz[q].x, zy - sz[q].y};
-            if (d.x == 0.0 && d.y == 0.0) continue;
-            const cx<double> iv = cinv(d);
+          for (int q = sl; q < take; q += S) {
+            const double dx = zx - sz[q].x, dy = zy - sz[q].y;
+            // 1 / d = conj(d) / |d|^2; the bias makes a source at the
+            // target (d = 0) contribute 0
+            const double r2 = rcp64(fma(dx, dx, fma(dy, dy, 1e-300)));
+            const cx<double> iv{dx * r2, -dy * r2};
             const cx<double> t = cx<double>{sp[q].x, sp[q].y} * iv;
             f = f + t;
-            df = df - t * iv;
+            if constexpr (DERIV) df = df - t * iv;
           }
         }
         __syncthreads();
       }
     }
-    if (act) {
+    for (int o = tp; o < 64; o <<= 1) {
+      f.x += __shfl_xor(f.x, o, 64);
+      f.y += __shfl_xor(f.y, o, 64);
+      if constexpr (DERIV) {
+        df.x += __shfl_xor(df.x, o, 64);
+        df.y += __shfl_xor(df.y, o, 64);
+      }
+    }
+    if (act && sl == 0) {
       const int64_t api = tperm[i];
       psi[2 * api] = f.x;
       psi[2 * api + 1] = f.y;
-      if (dpsi) {
+      if constexpr (DERIV) {
         dpsi[2 * api] = df.x;
         dpsi[2 * api + 1] = df.y;
       }
@@ -1437,14 +1457,16 @@ static void run64_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
   auto *M = (cx<double> *)ws.mult64.p;
   auto *L = (cx<double> *)ws.loc64.p;
   far_field<double, P>(pl, tb, ws, p, M, L, 1, s);
-  if (pl.n_leaf_t > 0)
-    hipLaunchKernelGGL((k_leaf64_full<P>), dim3(pl.n_leaf_t), dim3(64), 0, s,
+  if (pl.n_leaf_t > 0) {
+    auto k = dpsi ? k_leaf64_full<P, true> : k_leaf64_full<P, false>;
+    hipLaunchKernelGGL(k, dim3(pl.n_leaf_t), dim3(64), 0, s,
                        pl.leaf_t.p, pl.lev.p, pl.t0.p, pl.t1.p, pl.s0.p,
                        pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p, pl.tx.p, pl.ty.p,
                        pl.tgt_perm.p, pl.uf_ptr.p, pl.uf_idx.p, pl.w_ptr.p,
                        pl.w_src.p, pl.sx.p, pl.sy.p, (const cx<double> *)p,
                        (const cx<double> *)M, (const cx<double> *)L, psi,
                        dpsi);
+  }
 }
 
 void fmm_apply64_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
@@ -1476,7 +1498,9 @@ static void run64_sources(const DevPlan &pl, const Tables &tb, Workspace &ws,
   auto *L = (cx<double> *)ws.loc64.p;
   const auto *H = (const double *)tb.h64.p;
   const auto *itp = (const cx<double> *)tb.itp64.p;
-  // multipoles of every box of level >= 2 from the points it holds
+  // multipoles of every box of level >= 2 from the points it holds (boxes
+  // without points keep the zeros)
+  launch_fill((int64_t)pl.nbox * P * 2, 0.0, (double *)M, s);
   launch_gather_cx(ps.nm, ps.m_t.p, (const double *)pin, ps.m_p.p, s);
   if (ps.n_m > 0)
     hipLaunchKernelGGL((k_p2m<double, P>), dim3(ps.n_m, 1), dim3(64), 0, s, ps.m_list.p,
@@ -1487,19 +1511,21 @@ static void run64_sources(const DevPlan &pl, const Tables &tb, Workspace &ws,
     hipLaunchKernelGGL((k_m2l<double, P>), dim3(pl.n_m2l, 1), dim3(64), 0, s, pl.m2l_box.p,
                        pl.v_ptr.p, pl.v_src.p, pl.v_code.p, H, itp, (const cx<double> *)M, L,
                        pl.nbox);
-  if (ps.n_l > 0)
-    hipLaunchKernelGGL((k_p2l<double, P>), dim3(ps.n_l, 1), dim3(64), 0, s, ps.l_box.p,
+  if (ps.n_m > 0)
+    hipLaunchKernelGGL((k_p2l<double, P>), dim3(ps.n_m, 1), dim3(64), 0, s, ps.m_list.p,
                        ps.l_ptr.p, ps.l_t.p, pl.cx.p, pl.cy.p, pl.rad.p, ps.x, ps.y, pin, ps.n,
                        L, pl.nbox);
   run_pass<double, P, true>(pl.dn[1], (const double *)tb.bc64.p, (const cx<double> *)tb.pre64.p,
                             (const cx<double> *)tb.post64.p, L, pl.nbox, 1, s);
   // at the plan's targets: local expansions, W lists, direct sums
-  if (pl.n_leaf_t > 0)
-    hipLaunchKernelGGL((k_leaf64_full<P>), dim3(pl.n_leaf_t), dim3(64), 0, s, pl.leaf_t.p,
+  if (pl.n_leaf_t > 0) {
+    auto k = dpsi ? k_leaf64_full<P, true> : k_leaf64_full<P, false>;
+    hipLaunchKernelGGL(k, dim3(pl.n_leaf_t), dim3(64), 0, s, pl.leaf_t.p,
                        pl.lev.p, pl.t0.p, pl.t1.p, pl.s0.p, pl.s1.p, pl.cx.p, pl.cy.p, pl.rad.p,
                        pl.tx.p, pl.ty.p, pl.tgt_perm.p, ps.d_ptr.p, ps.d_t.p, pl.w_ptr.p,
                        pl.w_src.p, ps.x, ps.y, pin, (const cx<double> *)M,
                        (const cx<double> *)L, psi, dpsi);
+  }
 }
 
 void fmm_sources64_full(const DevPlan &pl, const Tables &tb, Workspace &ws, PointSources &ps,

@@ -147,6 +147,8 @@ __global__ void __launch_bounds__(1024)
     }
 }
 
+}  // namespace
+
 // In-place exclusive scan of a[0 .. n) with tile sums in sums (at least
 // ceil(n / 4096) entries; not needed for n <= 4096).
 void scan_into(uint32_t *a, int64_t n, uint32_t *sums, hipStream_t s) {
@@ -163,6 +165,8 @@ void scan_into(uint32_t *a, int64_t n, uint32_t *sums, hipStream_t s) {
   }
   LBS_HIP(hipGetLastError());
 }
+
+namespace {
 
 // Stable scatter of one tile: 16 rounds of 256 consecutive keys; a key's
 // place = the digit's global offset for this tile + the digit's count in
@@ -214,21 +218,17 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Scratch of the radix sorts of one tree build, grown as needed and
-// reused by every sort (fewer allocations, and no device-wide wait in a
+// Scratch of the radix sorts of one tree build (SortBufs), grown as needed
+// and reused by every sort (fewer allocations, and no device-wide wait in a
 // free between the sorts).
-struct SortScratch {
-  DBuf<uint64_t> k2;
-  DBuf<int32_t> v2;
-  DBuf<uint32_t> hist, sums;
-  void ensure(int64_t n, int ntiles) {
-    if ((int64_t)k2.n < n) k2.alloc((size_t)n);
-    if ((int64_t)v2.n < n) v2.alloc((size_t)n);
-    if ((int64_t)hist.n < (int64_t)256 * ntiles) hist.alloc((size_t)256 * ntiles);
-    const int64_t nt = ((int64_t)256 * ntiles + kScanTile - 1) / kScanTile;
-    if ((int64_t)sums.n < nt) sums.alloc((size_t)nt);
-  }
-};
+using SortScratch = SortBufs;
+void ensure_sort(SortScratch &sc, int64_t n, int ntiles) {
+  if ((int64_t)sc.k2.n < n) sc.k2.alloc((size_t)n);
+  if ((int64_t)sc.v2.n < n) sc.v2.alloc((size_t)n);
+  if ((int64_t)sc.hist.n < (int64_t)256 * ntiles) sc.hist.alloc((size_t)256 * ntiles);
+  const int64_t nt = ((int64_t)256 * ntiles + kScanTile - 1) / kScanTile;
+  if ((int64_t)sc.sums.n < nt) sc.sums.alloc((size_t)nt);
+}
 
 // Stable sort of (keys, vals) by the low `bits` bits of the keys; the
 // result is back in keys / vals.
@@ -236,7 +236,7 @@ void radix_sort(uint64_t *keys, int32_t *vals, int64_t n, int bits, SortScratch 
                 hipStream_t s) {
   if (n <= 1) return;
   const int ntiles = (int)((n + kRsTile - 1) / kRsTile);
-  sc.ensure(n, ntiles);
+  ensure_sort(sc, n, ntiles);
   DBuf<uint64_t> &k2 = sc.k2;
   DBuf<int32_t> &v2 = sc.v2;
   DBuf<uint32_t> &hist = sc.hist;
@@ -947,6 +947,11 @@ void sort_by_key(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t
   SortScratch sc;
   radix_sort(keys, vals, n, bits, sc, s);
   LBS_HIP(hipStreamSynchronize(s));  // the scratch is released on return
+}
+
+void sort_by_key(uint64_t *keys, int32_t *vals, int64_t n, int bits, SortBufs &sc,
+                 hipStream_t s) {
+  radix_sort(keys, vals, n, bits, sc, s);
 }
 
 void launch_widen_perm(int64_t n, const int32_t *perm, const int64_t *map, int64_t *out,

@@ -518,8 +518,10 @@ void launch_flat_fill(int64_t ne, const int32_t *box, const int64_t *eo, const i
 void launch_widen_perm(int64_t n, const int32_t *perm, const int64_t *map, int64_t *out,
                        hipStream_t s);
 void launch_fill_int(int64_t n, int32_t v, int32_t *x, hipStream_t s);
-// In-place exclusive scan of a[0 .. n) (gtree.hip)
+// In-place exclusive scan of a[0 .. n) (gtree.hip); scan_into takes the
+// tile sums' scratch (at least ceil(n / 4096) entries) and does not wait.
 void scan_u32(uint32_t *a, int64_t n, hipStream_t s);
+void scan_into(uint32_t *a, int64_t n, uint32_t *sums, hipStream_t s);
 // Whether a[0 .. n) and b[0 .. n) differ bit for bit (dflag: one device
 // int32, hflag: one pinned host int32; waits for the stream).  (evalpts.hip)
 bool targets_differ(int64_t n, const double *a, const double *b, int32_t *dflag,
@@ -532,14 +534,14 @@ void launch_gather_cx(int64_t n, const int32_t *idx, const double *in, double *o
 // root: its tree's root), as (box, point) pairs sorted by box: the
 // multipole of every box of level >= 2 holding the point (list m_list,
 // ranges m_rng into the pair-ordered coordinates m_x, m_y), the local
-// expansions its walk takes by multipole (l_box; offsets l_ptr over the
-// plan's boxes into l_t), the leaves its walk sums directly (d_ptr, d_t).
+// expansions its walk takes by multipole (offsets l_ptr over the plan's
+// boxes into l_t), the leaves its walk sums directly (d_ptr, d_t).
 // The plan needs its tree links on the device.  (evalpts.hip)
 struct PointSources {
   int64_t n = 0, nm = 0;
   const double *x = nullptr, *y = nullptr;  // not owned
-  int n_m = 0, n_l = 0;
-  DBuf<int32_t> m_list, m_t, l_box, l_t, d_t;
+  int n_m = 0;  // entries of m_list (also the boxes passed for local terms)
+  DBuf<int32_t> m_list, m_t, l_t, d_t;
   DBuf<int64_t> m_rng, l_ptr, d_ptr;
   DBuf<double4> m_geo;
   DBuf<double> m_x, m_y, m_p;  // m_p: the pairs' strengths of a call
@@ -553,8 +555,18 @@ void build_point_sources(const DevPlan &pl, int64_t n, const double *x, const do
 // (ws.mult64, ws.loc64, one column).  (fmm.hip)
 void fmm_sources64_full(const DevPlan &pl, const Tables &tb, Workspace &ws, PointSources &ps,
                         const double *pin, double *psi, double *dpsi, hipStream_t s);
-// Stable sort of (keys, vals) by the low `bits` bits of the keys (gtree.hip)
+// Stable sort of (keys, vals) by the low `bits` bits of the keys (gtree.hip);
+// the first form waits for the stream and releases its scratch, the second
+// keeps its scratch in sc for the next sort (release it only after the
+// stream has finished with it).
+struct SortBufs {
+  DBuf<uint64_t> k2;
+  DBuf<int32_t> v2;
+  DBuf<uint32_t> hist, sums;
+};
 void sort_by_key(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
+void sort_by_key(uint64_t *keys, int32_t *vals, int64_t n, int bits, SortBufs &sc,
+                 hipStream_t s);
 // Targets located in a plan's tree (evalpts.hip): the n targets (tx, ty;
 // API index idx; geometry tgeo[idx] or 0) sorted by the deepest box whose
 // square holds them (-1 outside the root square), with their roots and
