@@ -476,66 +476,54 @@ __device__ __noinline__ void pivot_block_inverse(const double *__restrict__ Sg, 
   }
 }
 
-template <int RPT>
-__global__ void __launch_bounds__(kGJT)
-    k_gjp_panel(int j0, const int32_t *__restrict__ gisl, const int64_t *__restrict__ gsinv,
-                const double *__restrict__ S, int *__restrict__ piv,
-                double *__restrict__ Binv, int maxM) {
-  constexpr int NB = kGJ / RPT;
-  __shared__ unsigned long long wk[16];
-  __shared__ double prow[NB], crow[NB];
-  __shared__ int prow_id, crow_id, blk_row[NB];
-  __shared__ double bl[NB][NB + 1];
-  const int g = blockIdx.x;
-  const int Mg = gisl[g + 1] - gisl[g];
-  if (j0 >= Mg) return;
-  const int nb = min(NB, Mg - j0), tid = threadIdx.x;
-  const double *Sg = S + gsinv[g];
-  int orig[RPT];  // the row of S each register row started as
-#pragma unroll
-  for (int i = 0; i < RPT; ++i) orig[i] = j0 + tid + kGJT * i;
-  // v[i][q]: row j0 + tid + kGJT i, column k + q of the panel at step k
-  // (finished columns are shifted out, so that every index into v is a
-  // compile-time constant and v stays in registers)
-  double v[RPT][NB];
-#pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int r = j0 + tid + kGJT * i;
-#pragma unroll
-    for (int q = 0; q < NB; ++q)
-      v[i][q] = (r < Mg && q < nb) ? Sg[(int64_t)r * Mg + j0 + q] : 0.0;
-  }
-#pragma unroll 1
-  for (int k = 0; k < nb; ++k) {
-    const int c = j0 + k;
+// LDS of the panel kernel
+template <int NB>
+struct PanelShared {
+  unsigned long long wk[16];
+  double prow[NB], crow[NB];
+  int prow_id, crow_id, blk_row[NB];
+  double bl[NB][NB + 1];
+};
+
+// Column K of the panel LU (every index into v a compile-time constant;
+// columns below K are finished and no longer read): the pivot row p among
+// the rows >= c = j0 + K, rows c and p exchanged (columns K.. only), the
+// rows below c eliminated in columns K + 1 .. NB - 1.  Steps K >= nb are
+// skipped (uniformly).
+template <int K, int NB, int RPT>
+__device__ __forceinline__ void panel_column(double (&v)[RPT][NB], int (&orig)[RPT], int j0,
+                                             int nb, int Mg, int tid, PanelShared<NB> &sh,
+                                             int *__restrict__ piv_g) {
+  if constexpr (K < NB) {
+    if (K >= nb) return;
+    const int c = j0 + K;
     unsigned long long key = 0;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = j0 + tid + kGJT * i;
       if (r >= c && r < Mg) {
-        const unsigned long long kk = pivot_key(fabs(v[i][0]), r - j0);
+        const unsigned long long kk = pivot_key(fabs(v[i][K]), r - j0);
         key = kk > key ? kk : key;
       }
     }
     key = __ockl_wfred_max_u64(key);
-    if ((tid & 63) == 0) wk[tid >> 6] = key;
+    if ((tid & 63) == 0) sh.wk[tid >> 6] = key;
     __syncthreads();
     // every wave reduces the 16 wave maxima itself
-    key = __ockl_wfred_max_u64(wk[tid & 15]);
+    key = __ockl_wfred_max_u64(sh.wk[tid & 15]);
     const int p = j0 + 8191 - (int)(key & 0x1FFFull);
-    // exchange rows c and p through LDS
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = j0 + tid + kGJT * i;
       if (r == p) {
 #pragma unroll
-        for (int q = 0; q < NB; ++q) prow[q] = v[i][q];
-        prow_id = orig[i];
+        for (int q = K; q < NB; ++q) sh.prow[q] = v[i][q];
+        sh.prow_id = orig[i];
       }
       if (r == c) {
 #pragma unroll
-        for (int q = 0; q < NB; ++q) crow[q] = v[i][q];
-        crow_id = orig[i];
+        for (int q = K; q < NB; ++q) sh.crow[q] = v[i][q];
+        sh.crow_id = orig[i];
       }
     }
     __syncthreads();
@@ -544,38 +532,64 @@ __global__ void __launch_bounds__(kGJT)
       const int r = j0 + tid + kGJT * i;
       if (r == p && r != c) {
 #pragma unroll
-        for (int q = 0; q < NB; ++q) v[i][q] = crow[q];
-        orig[i] = crow_id;
+        for (int q = K; q < NB; ++q) v[i][q] = sh.crow[q];
+        orig[i] = sh.crow_id;
       } else if (r == c) {
-        orig[i] = prow_id;
+        orig[i] = sh.prow_id;
       }
     }
-    // eliminate below the pivot and shift the column out (prow, crow and
-    // wk are rewritten only after the next column's first barrier)
-    const double inv = 1.0 / prow[0];
+    // prow, crow and wk are rewritten only after the next column's first
+    // barrier
+    const double inv = 1.0 / sh.prow[K];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = j0 + tid + kGJT * i;
       if (r > c && r < Mg) {
-        const double l = v[i][0] * inv;
+        const double l = v[i][K] * inv;
 #pragma unroll
-        for (int q = 1; q < NB; ++q) v[i][q] -= l * prow[q];
+        for (int q = K + 1; q < NB; ++q) v[i][q] -= l * sh.prow[q];
       }
-#pragma unroll
-      for (int q = 0; q + 1 < NB; ++q) v[i][q] = v[i][q + 1];
     }
-    if (tid == 0) piv[(int64_t)g * maxM + c] = p;
+    if (tid == 0) piv_g[c] = p;
+    panel_column<K + 1, NB, RPT>(v, orig, j0, nb, Mg, tid, sh, piv_g);
   }
+}
+
+template <int RPT>
+__global__ void __launch_bounds__(kGJT)
+    k_gjp_panel(int j0, const int32_t *__restrict__ gisl, const int64_t *__restrict__ gsinv,
+                const double *__restrict__ S, int *__restrict__ piv,
+                double *__restrict__ Binv, int maxM) {
+  constexpr int NB = kGJ / RPT;
+  __shared__ PanelShared<NB> sh;
+  const int g = blockIdx.x;
+  const int Mg = gisl[g + 1] - gisl[g];
+  if (j0 >= Mg) return;
+  const int nb = min(NB, Mg - j0), tid = threadIdx.x;
+  const double *Sg = S + gsinv[g];
+  int orig[RPT];  // the row of S each register row started as
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) orig[i] = j0 + tid + kGJT * i;
+  // v[i][q]: row j0 + tid + kGJT i, column j0 + q
+  double v[RPT][NB];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = j0 + tid + kGJT * i;
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+      v[i][q] = (r < Mg && q < nb) ? Sg[(int64_t)r * Mg + j0 + q] : 0.0;
+  }
+  panel_column<0, NB, RPT>(v, orig, j0, nb, Mg, tid, sh, piv + (int64_t)g * maxM);
   // Binv = S_JJ^-1 of the pivoted block, read from the rows of S it came
   // from, by Gauss-Jordan elimination without interchanges (one entry per
   // thread; its pivots are those just chosen)
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int r = j0 + tid + kGJT * i;
-    if (r < j0 + nb) blk_row[r - j0] = orig[i];
+    if (r < j0 + nb) sh.blk_row[r - j0] = orig[i];
   }
   __syncthreads();
-  pivot_block_inverse<NB>(Sg, Mg, j0, nb, blk_row, bl, Binv + (int64_t)g * kGJ * kGJ);
+  pivot_block_inverse<NB>(Sg, Mg, j0, nb, sh.blk_row, sh.bl, Binv + (int64_t)g * kGJ * kGJ);
 }
 
 // column c of S_g: the panel's row interchanges in order
