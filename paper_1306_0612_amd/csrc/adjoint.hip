@@ -213,10 +213,10 @@ __global__ void __launch_bounds__(64)
 }
 
 // (E^T y)_m for a tile of TM consecutive centres m per block: threads over
-// the islands k of the geometry, the series ratios q_km and h_km from the
-// dense table Geometry::farT_*, each moment Q_k[l] read once and applied to
-// the TM Horner chains; k near m (m's transposed near list, ascending) is
-// left to the direct sum over its nodes.
+// the islands k of the geometry, the series ratios q_km and h_km formed from
+// the centres and k's frame, each moment Q_k[l] read once and applied to the
+// TM Horner chains; k near m (m's transposed near list, ascending) is left
+// to the direct sum over its nodes.
 template <int TM>
 __global__ void __launch_bounds__(256)
     k_logsrc_T(int M, const int32_t *__restrict__ isl_geo,
@@ -226,9 +226,8 @@ __global__ void __launch_bounds__(256)
                const double *__restrict__ xyz,
                const int32_t *__restrict__ nearT_ptr,
                const int32_t *__restrict__ nearT_idx,
-               const int64_t *__restrict__ farT_ofs,
-               const double *__restrict__ farT_q,
-               const double *__restrict__ farT_h,
+               const double *__restrict__ frame,
+               const double *__restrict__ rhol,
                const double *__restrict__ mom, const double *__restrict__ y,
                double alpha, double *__restrict__ out) {
   constexpr int P = kPlog;
@@ -237,7 +236,7 @@ __global__ void __launch_bounds__(256)
   const int tid = threadIdx.x, ln = tid & 63, wv = tid >> 6;
   // the tile's centres: geometry ranges, table rows, near-list cursors
   int ka[TM], kb[TM], np[TM], ne[TM];
-  int64_t row[TM];
+  double cm[TM][3];
   int klo = M, khi = 0;
 #pragma unroll
   for (int t = 0; t < TM; ++t) {
@@ -246,23 +245,33 @@ __global__ void __launch_bounds__(256)
       const int g = isl_geo[m];
       ka[t] = gisl[g];
       kb[t] = gisl[g + 1];
-      row[t] = farT_ofs[g] + (int64_t)(m - ka[t]) * (kb[t] - ka[t]) - ka[t];
       np[t] = nearT_ptr[m];
       ne[t] = nearT_ptr[m + 1];
       klo = min(klo, ka[t]);
       khi = max(khi, kb[t]);
     } else {
       ka[t] = kb[t] = 0;
-      row[t] = 0;
       np[t] = ne[t] = 0;
     }
   }
   double tot[TM], ysum[TM];
 #pragma unroll
-  for (int t = 0; t < TM; ++t) tot[t] = ysum[t] = 0.0;
+  for (int t = 0; t < TM; ++t) {
+    tot[t] = ysum[t] = 0.0;
+    const int m = mb + t < M ? mb + t : M - 1;
+    cm[t][0] = cxyz[3 * m];
+    cm[t][1] = cxyz[3 * m + 1];
+    cm[t][2] = cxyz[3 * m + 2];
+  }
   for (int k = klo + tid; k < khi; k += 256) {
     const double *mk = mom + k;
     const double Yk = mk[(int64_t)(2 * P) * M], Ek = mk[(int64_t)(2 * P + 1) * M];
+    // k's centre and frame: q_km = 2 rho'_k (a - i b) / |c_k - c_m|^2 and
+    // log|c_k - c_m| are formed here, for the tile's centres c_m
+    const double ck0 = cxyz[3 * k], ck1 = cxyz[3 * k + 1], ck2 = cxyz[3 * k + 2];
+    const double *fk = frame + 6 * k;
+    const double f0 = fk[0], f1 = fk[1], f2 = fk[2], f3 = fk[3], f4 = fk[4], f5 = fk[5];
+    const double rk2 = 2.0 * rhol[k];
     cx<double> q[TM], ser[TM];
     double hk[TM], w[TM];
 #pragma unroll
@@ -271,9 +280,14 @@ __global__ void __launch_bounds__(256)
       if (in) ysum[t] += Yk;
       while (np[t] < ne[t] && nearT_idx[np[t]] < k) ++np[t];
       const bool far = in && !(np[t] < ne[t] && nearT_idx[np[t]] == k);
-      const int64_t e = far ? row[t] + k : 0;
-      q[t] = far ? cx<double>{farT_q[2 * e], farT_q[2 * e + 1]} : cx<double>{0.0, 0.0};
-      hk[t] = far ? farT_h[e] : 0.0;
+      const double x0 = cm[t][0], x1 = cm[t][1], x2 = cm[t][2];
+      const double d0 = x0 - ck0, d1 = x1 - ck1, d2 = x2 - ck2;
+      const double dd = far ? d0 * d0 + d1 * d1 + d2 * d2 : 1.0;  // far pairs: dd > 0
+      const double ff = rk2 / dd;
+      q[t] = far ? cx<double>{(x0 * f0 + x1 * f1 + x2 * f2) * ff,
+                              -(x0 * f3 + x1 * f4 + x2 * f5) * ff}
+                 : cx<double>{0.0, 0.0};
+      hk[t] = far ? 0.5 * log(dd) : 0.0;
       w[t] = far ? 1.0 : 0.0;
       ser[t] = cx<double>{mk[(int64_t)(2 * (P - 1)) * M], mk[(int64_t)(2 * (P - 1) + 1) * M]};
     }
@@ -335,8 +349,8 @@ void launch_logsrc_T(const Geometry &g, const double *y, double *mom,
   constexpr int TM = 4;
   hipLaunchKernelGGL(k_logsrc_T<TM>, dim3((g.M + TM - 1) / TM), dim3(256), 0, s,
                      g.M, g.isl_geo.p, g.dgisl.p, g.doffs.p, g.dcenter.p,
-                     g.xyz.p, g.nearRT_ptr.p, g.nearRT_idx.p, g.farT_ofs.p,
-                     g.farT_q.p, g.farT_h.p, mom, y, alpha, out);
+                     g.xyz.p, g.nearRT_ptr.p, g.nearRT_idx.p, g.frame.p, g.rhol.p, mom, y,
+                     alpha, out);
   LBS_HIP(hipGetLastError());
 }
 

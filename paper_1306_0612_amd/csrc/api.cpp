@@ -861,7 +861,7 @@ void build_far_lists(Geometry &g, const std::vector<int32_t> &isl_geo,
   }
   const int64_t nf = fp[M];
   std::vector<int32_t> fidx(nf);
-  std::vector<double> fq(2 * nf), fh(nf), fa(nf);
+  std::vector<double> fq(2 * nf), fh(nf), fa(nf);  // fa = |q_km|, the sort key
   parallel_for(
       M,
       [&](int64_t k0, int64_t k1) {
@@ -929,44 +929,12 @@ void build_far_lists(Geometry &g, const std::vector<int32_t> &isl_geo,
   std::vector<int64_t> fc;
   std::vector<int32_t> fnt;
   chunks(fp, fa, fc, fnt);
-  // dense per geometry, row m: (q_km, h_km) for every island k of m's
-  // geometry (near pairs included; the transposed kernel skips them)
-  std::vector<int64_t> tofs(g.G + 1, 0);
-  for (int q = 0; q < g.G; ++q) {
-    const int64_t mq = g.gisl[q + 1] - g.gisl[q];
-    tofs[q + 1] = tofs[q] + mq * mq;
-  }
-  const int64_t nt = tofs[g.G];
-  std::vector<double> tq(2 * nt), th(nt);
-  parallel_for(
-      M,
-      [&](int64_t m0, int64_t m1) {
-        for (int64_t m = m0; m < m1; ++m) {
-          const int q = isl_geo[m], a = g.gisl[q];
-          const int64_t mq = g.gisl[q + 1] - a, row = tofs[q] + (m - a) * mq;
-          const double x0 = g.cxyz[3 * m], x1 = g.cxyz[3 * m + 1], x2 = g.cxyz[3 * m + 2];
-          for (int k = a; k < g.gisl[q + 1]; ++k) {
-            const double *ck = &g.cxyz[3 * k], *f = &fr[6 * k];
-            const double d0 = x0 - ck[0], d1 = x1 - ck[1], d2 = x2 - ck[2];
-            const double dd = std::max(d0 * d0 + d1 * d1 + d2 * d2, 1e-300);
-            const double ff = 2.0 * rl[k] / dd;
-            const int64_t e = row + (k - a);
-            tq[2 * e] = (x0 * f[0] + x1 * f[1] + x2 * f[2]) * ff;
-            tq[2 * e + 1] = -(x0 * f[3] + x1 * f[4] + x2 * f[5]) * ff;
-            th[e] = 0.5 * std::log(dd);
-          }
-        }
-      },
-      64);
   g.far_ptr.upload(fp, s);
   g.far_cptr.upload(fc, s);
   g.far_nt.upload(fnt, s);
   g.far_idx.upload(fidx, s);
   g.far_q.upload(fq, s);
   g.far_h.upload(fh, s);
-  g.farT_ofs.upload(tofs, s);
-  g.farT_q.upload(tq, s);
-  g.farT_h.upload(th, s);
   // the host vectors must outlive the asynchronous copies
   LBS_HIP(hipStreamSynchronize(s));
 }

@@ -264,12 +264,12 @@ struct Geometry {
   // and h_km = log|c_k - c_m|^2 / 2.  Grouped by k (far_*), each group
   // sorted by |q| (largest first, ties by m), with per chunk of kLogChunk
   // entries the number of series terms its first |q| needs (far_nt, chunk
-  // offsets far_cptr).  farT_*: dense per geometry (offset farT_ofs[g]),
-  // row m holding (q_km, h_km) for every island k of the geometry, near
-  // pairs included (their values are finite and unused).
-  DBuf<int64_t> far_ptr, far_cptr, farT_ofs;
+  // offsets far_cptr).  The transposed kernel forms q_km and h_km from the
+  // centres and frames instead (its m-major order would need a table of
+  // every pair of a geometry).
+  DBuf<int64_t> far_ptr, far_cptr;
   DBuf<int32_t> far_idx, far_nt;
-  DBuf<double> far_q, far_h, farT_q, farT_h;
+  DBuf<double> far_q, far_h;
   DBuf<lbs_island> disl;             // island parameters
   DBuf<double> dsign;                // orientation sign per island
   DBuf<double> Sinv;                 // block-diagonal inverse Schur complement
