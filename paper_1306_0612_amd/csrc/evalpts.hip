@@ -100,6 +100,14 @@ struct TreeView {
   const double *sx, *sy;
 };
 
+// 1 / d: the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - d r) (each step squares the relative error)
+__device__ __forceinline__ double recip_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
 // Re sum_j p_j / (z - z_j) over the sources [a0, a1) (a source at z adds 0)
 __device__ __forceinline__ double direct_sum(double x, double y, int64_t a0, int64_t a1,
                                              const double *__restrict__ sx,
@@ -110,7 +118,7 @@ __device__ __forceinline__ double direct_sum(double x, double y, int64_t a0, int
     const double dx = x - sx[j], dy = y - sy[j];
     const double d2 = fma(dx, dx, fma(dy, dy, 1e-300));
     const cx<double> pj = p[j];
-    f += fma(pj.x, dx, pj.y * dy) / d2;
+    f = fma(fma(pj.x, dx, pj.y * dy), recip_nr(d2), f);
   }
   return f;
 }
@@ -119,7 +127,9 @@ __device__ __forceinline__ double direct_sum(double x, double y, int64_t a0, int
 template <int P>
 __device__ __forceinline__ double multipole_at(double x, double y, int b, const TreeView &t,
                                                const cx<double> *__restrict__ M) {
-  const cx<double> rho = t.rad[b] * cinv(cx<double>{x - t.cx[b], y - t.cy[b]});
+  const double dx = x - t.cx[b], dy = y - t.cy[b];
+  const double ir = t.rad[b] * recip_nr(fma(dx, dx, dy * dy));
+  const cx<double> rho{dx * ir, -dy * ir};
   const cx<double> *a = M + (int64_t)b * P;
   cx<double> acc = a[P - 1];
   for (int k = P - 2; k >= 0; --k) acc = cfma(acc, rho, a[k]);
