@@ -291,6 +291,89 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// The FP32 leaf multipoles of two leaves per wave (list entries 2 w and
+// 2 w + 1 on lanes 0-31 and 32-63): as k_p2m, with every source loop
+// striding by 32 and the halving sum run inside each half (lane offsets
+// 16 .. 1), so that the sum's fixed cost is shared by two leaves.  One
+// pass: P <= 32 coefficients, NV = 2 P values.
+template <typename T, int NV, int S = 0>
+__device__ __forceinline__ void halving_steps_half(T (&v)[NV], int lane) {
+  if constexpr (S < 5) {
+    constexpr int o = 16 >> S, h = NV >> (S + 1);
+    if constexpr (h >= 1) {
+      const bool up = (lane & o) != 0;
+#pragma unroll
+      for (int k = 0; k < h; ++k) {
+        const T send = up ? v[k] : v[k + h];
+        const T keep = up ? v[k + h] : v[k];
+        v[k] = keep + __shfl_xor(send, o, 64);
+      }
+    } else {
+      v[0] += __shfl_xor(v[0], o, 64);
+    }
+    halving_steps_half<T, NV, S + 1>(v, lane);
+  }
+}
+
+template <int P>
+__global__ void __launch_bounds__(64)
+    k_p2m_pair(const int32_t *__restrict__ leaves, int nleaf,
+               const int64_t *__restrict__ ls_rng,
+               const double4 *__restrict__ ls_geo,
+               const double *__restrict__ sx, const double *__restrict__ sy,
+               cx<float> *__restrict__ p, int64_t ns, cx<float> *__restrict__ M,
+               int nbox, StrengthSrc ss) {
+  constexpr int NV = pow2_ceil(2 * P), SH = 5 - log2_exact(NV);
+  static_assert(P <= 16, "one pass of at most 32 values per lane");
+  const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
+  const int e = 2 * blockIdx.x + half;  // this half's list entry
+  const bool has = e < nleaf;           // uniform within the half
+  const int r = blockIdx.y;
+  cx<float> *pr = p + (int64_t)r * ns;
+  float acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.f;
+  double gsum = 0.0;
+  int b = 0;
+  double ir = 0.0;
+  if (has) {
+    b = leaves[e];
+    const double4 geo = ls_geo[e];
+    const double c_x = geo.x, c_y = geo.y;
+    ir = geo.z;
+    const int64_t e0 = ls_rng[2 * e], e1 = ls_rng[2 * e + 1];
+    for (int64_t j = e0 + hl; j < e1; j += 32) {
+      const cx<float> w{float((sx[j] - c_x) * ir), float((sy[j] - c_y) * ir)};
+      cx<float> pw;
+      if (ss.sigma) {  // form the strength: p_j = -i q_j sigma_j
+        const double sg = ss.sigma[(int64_t)r * ss.ldx + ss.perm[j]];
+        const double qx = ss.qfac_t[2 * j], qy = ss.qfac_t[2 * j + 1];
+        pw = cx<float>{float(qy * sg), float(-qx * sg)};
+        pr[j] = pw;
+        if (ss.gpart) gsum += ss.gw_t[j] * sg;
+      } else {
+        pw = pr[j];
+      }
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        acc[2 * k] += pw.x;
+        acc[2 * k + 1] += pw.y;
+        pw = pw * w;
+      }
+    }
+  }
+  halving_steps_half<float, NV>(acc, lane);
+  const int vi = hl >> SH;
+  if (has && (hl & ((1 << SH) - 1)) == 0 && vi < 2 * P) {
+    float *Mb = reinterpret_cast<float *>(M + ((int64_t)r * nbox + b) * P);
+    Mb[vi] = float(ir) * acc[0];
+  }
+  if (ss.gpart) {  // block-uniform
+    for (int o = 16; o > 0; o >>= 1) gsum += __shfl_xor(gsum, o, 64);
+    if (has && hl == 0) ss.gpart[(int64_t)r * nleaf + e] = gsum;
+  }
+}
+
 // gamma[r G + g] = the sum of the partial sums of geometry g's source
 // leaves, positions gl_ptr[g] .. gl_ptr[g + 1] of the plan's leaf list.
 // Block (c, g, r) sums chunk c of that range into csum; the last block of
@@ -1157,9 +1240,16 @@ static bool far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
   {
     TimerScope ts(tm, ST_UPWARD, s);
     if (pl.n_leaf_s > 0)
-      hipLaunchKernelGGL((k_p2m<T, P>), dim3(pl.n_leaf_s, nrhs), dim3(64), 0,
-                         s, pl.leaf_s.p, pl.ls_rng.p, pl.ls_geo.p, pl.sx.p,
-                         pl.sy.p, p, pl.ns, M, pl.nbox, ss);
+    {
+      if constexpr (sizeof(T) == 4 && P <= 16)  // two leaves per wave
+        hipLaunchKernelGGL((k_p2m_pair<P>), dim3((pl.n_leaf_s + 1) / 2, nrhs), dim3(64), 0, s,
+                           pl.leaf_s.p, pl.n_leaf_s, pl.ls_rng.p, pl.ls_geo.p, pl.sx.p,
+                           pl.sy.p, p, pl.ns, M, pl.nbox, ss);
+      else
+        hipLaunchKernelGGL((k_p2m<T, P>), dim3(pl.n_leaf_s, nrhs), dim3(64), 0,
+                           s, pl.leaf_s.p, pl.ls_rng.p, pl.ls_geo.p, pl.sx.p,
+                           pl.sy.p, p, pl.ns, M, pl.nbox, ss);
+    }
     run_pass<T, P, false>(pl.up[sizeof(T) == 8], bc, pre, post, M, pl.nbox, nrhs, s);
   }
   // the FP32 MFMA M2L also forms the P2L sums of its boxes: every box with
