@@ -273,7 +273,7 @@ def traffic_profile():
 
 
 STAGE_KERNELS32 = {  # stage -> kernels of one mixed application
-    "upward": ["k_p2m<float,16>", "k_pass<float,16,false>"],
+    "upward": ["k_p2m_pair<16>", "k_pass<float,16,false>"],
     "m2l": ["k_m2l_mfma16"],
     "l2l": ["k_pass<float,16,true>"],
     "leaf": ["k_leaf32<16,1>"],

@@ -225,3 +225,27 @@ def test_located_transpose_full_size(env):
     hs, ha = ref_tree.eval_T(w, tg)
     assert _rel(_np(gs), _np(hs)) < 3e-10
     assert _rel(_np(ga), _np(ha)) < 1e-12
+
+
+def test_plan_lookup_sees_changed_targets(env):
+    """The cached placement is found by comparing the targets themselves:
+    targets changed in place in the same tensor get a new placement."""
+    torch, lbs = env
+    isl = synth.star_islands(47, 6, (0.08, 0.2), nodes=64)
+    cv = Curves(isl)
+    sig = synth.random_vector(48, cv.n)
+    A = synth.random_vector(49, cv.m)
+    tg1 = synth.sphere_targets(50, 200, isl)
+    tg2 = synth.sphere_targets(51, 200, isl)
+    sol = lbs.Solver(isl, leaf_max=8)
+    t = _t(torch, tg1)
+    s_, a_ = _t(torch, sig), _t(torch, A)
+    u1 = _np(sol.eval(s_, a_, t))
+    t.copy_(_t(torch, tg2))
+    u2 = _np(sol.eval(s_, a_, t))
+    assert _rel(u1, evaluate.evaluate(cv, sig, A, tg1)) < 1e-10
+    assert _rel(u2, evaluate.evaluate(cv, sig, A, tg2)) < 1e-10
+    w = np.random.default_rng(52).standard_normal(200)
+    gs, _ = sol.eval_T(_t(torch, w), t)
+    rs, _ = adjoint.eval_transpose(cv, tg2, w)
+    assert _rel(_np(gs), rs) < 1e-10
