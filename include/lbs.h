@@ -126,6 +126,9 @@ typedef struct {
                      /* tree per target set); 1: these build a quadtree    */
                      /* over the nodes and the targets per target set.     */
                      /* Both are the FMM of Section 5 at the same order.   */
+  int32_t m2l_groups;/* work-groups of the persistent FP32 M2L launch     */
+                     /* (0 = the default 1024; else 64 .. 8192): the      */
+                     /* launch shape lbs_autotune also tunes               */
 } lbs_options;
 
 typedef struct {
@@ -378,7 +381,7 @@ lbs_status lbs_set_orders(lbs_handle h, int32_t p64, int32_t p32,
  * milliseconds per (I + K) application and its relative error
  * max|y - y_ref| / max|y_ref| against an FP64 order-48 reference. */
 typedef struct {
-  int32_t leaf_max, p32, p64;
+  int32_t leaf_max, p32, p64, m2l_groups;
   double ms, err;
 } lbs_tune_entry;
 
@@ -390,14 +393,34 @@ typedef struct {
  * p64 of the fastest FP64 application on that leaf size with error
  * <= tol_fp64.  Every measured setting is written to entries_host (up to
  * max_entries; n_entries_host receives the count; both may be NULL).
- * LBS_ERR_UNSUPPORTED when no setting meets a tolerance.  Synchronous;
- * builds and destroys one handle per leaf size. */
+ * LBS_ERR_UNSUPPORTED when no setting meets a tolerance.  Then, on the
+ * chosen leaf size and p32, it times the FP32 M2L launch at 512, 1024 and
+ * 2048 work-groups (entries with p32 set and m2l_groups nonzero) and keeps
+ * the fastest in best_host->m2l_groups.  Synchronous; builds and destroys
+ * one handle per leaf size and per launch shape. */
 lbs_status lbs_autotune(const lbs_island *islands_host, int32_t n_islands,
                         const int32_t *nodes_per_curve_host,
                         const lbs_options *base_host, double tol_mixed,
                         double tol_fp64, void *stream, lbs_options *best_host,
                         lbs_tune_entry *entries_host, int32_t max_entries,
                         int32_t *n_entries_host);
+
+/* lbs_autotune with an on-disk cache (for the callers that tune the same
+ * geometry again, e.g. every run of a service): cache_path names a text
+ * file of one line per tuned problem, keyed by a 64-bit FNV-1a hash of the
+ * islands, the node counts, the base options, both tolerances, the device
+ * (architecture name and compute-unit count) and the library build.  A hit
+ * returns the stored best options and entries without touching the GPU; a
+ * miss tunes and appends a line (a line that cannot be written only costs
+ * the next call a new tuning).  *hit_host (may be NULL) tells which.
+ * Concurrent writers append whole lines. */
+lbs_status lbs_autotune_cached(const lbs_island *islands_host, int32_t n_islands,
+                               const int32_t *nodes_per_curve_host,
+                               const lbs_options *base_host, double tol_mixed,
+                               double tol_fp64, void *stream, const char *cache_path,
+                               lbs_options *best_host, lbs_tune_entry *entries_host,
+                               int32_t max_entries, int32_t *n_entries_host,
+                               int32_t *hit_host);
 
 /* Per-stage GPU timing of operator applications.  With enable != 0 every
  * stage of every later lbs_matvec / lbs_solve call is bracketed by a pair

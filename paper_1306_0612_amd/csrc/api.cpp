@@ -152,7 +152,7 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
       w[b] = 4 + 2 * ((nv + 7) / 8) + (nx > 0 ? 4 + 3 * ((nx + 63) / 64) : 0);
     }
     std::stable_sort(mw.begin(), mw.end(), [&](int a, int b) { return w[a] > w[b]; });
-    const int64_t W = 4 * std::min<int64_t>((n + 3) / 4, kM2LGroups);
+    const int64_t W = 4 * std::min<int64_t>((n + 3) / 4, pl.m2l_groups);
     for (int64_t a = W; a < n; a += 2 * W)
       std::reverse(mw.begin() + a, mw.begin() + std::min(n, a + W));
     pl.m2l_wave.upload(mw, s);
@@ -1136,6 +1136,8 @@ void validate_options(const lbs_options &o) {
   if (o.close_eval != 0 && o.close_eval != 1) fail(LBS_ERR_INVALID_ARG, "close_eval must be 0 or 1");
   if (o.gpu_tree != 0 && o.gpu_tree != 1) fail(LBS_ERR_INVALID_ARG, "gpu_tree must be 0 or 1");
   if (o.eval_tree != 0 && o.eval_tree != 1) fail(LBS_ERR_INVALID_ARG, "eval_tree must be 0 or 1");
+  if (o.m2l_groups != 0 && (o.m2l_groups < 64 || o.m2l_groups > 8192))
+    fail(LBS_ERR_INVALID_ARG, "m2l_groups must be 0 or in [64, 8192]");
 }
 
 // Set-up of G geometries (islands and node counts concatenated
@@ -1464,6 +1466,7 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl_in
       }
     }
   }
+  ctx->plan.m2l_groups = o.m2l_groups > 0 ? o.m2l_groups : kM2LGroups;
   upload_plan(ctx->plan.host, ctx->xi_x.data(), ctx->xi_y.data(), nullptr, nullptr, nullptr,
               ctx->plan, s);
   build_passes(ctx->plan, o.p32, o.p64, s);
@@ -1923,6 +1926,7 @@ void lbs_default_options(lbs_options *o) {
   o->close_eval = 1;
   o->gpu_tree = 1;
   o->eval_tree = 0;
+  o->m2l_groups = 0;
 }
 
 lbs_status lbs_refine_tolerances_host(int32_t S, const double *rn2, const double *bn2,

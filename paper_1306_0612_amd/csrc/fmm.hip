@@ -1262,7 +1262,7 @@ static bool far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
       const XListSrc xs{pl.xf_ptr.p, pl.xf_idx.p, pl.cx.p, pl.cy.p, pl.rad.p,
                         pl.sx.p, pl.sy.p, (const cx<float> *)p, pl.ns};
       GammaGroups gg;
-      gg.first = std::min((pl.n_m2l + 3) / 4, kM2LGroups);
+      gg.first = std::min((pl.n_m2l + 3) / 4, pl.m2l_groups);
       int groups = gg.first;
       if (gf && pl.n_leaf_s > 0) {  // the correction sums ride along
         gg = GammaGroups{gf->gl_ptr, ws.gpart.p, ws.gcsum.p, ws.gcnt.p, gf->gamma,

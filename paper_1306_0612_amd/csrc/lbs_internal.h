@@ -111,6 +111,11 @@ struct LeafHdr {
   double cx, cy, ir, pad;
 };
 
+// work-groups (4 waves each) of the FP32 M2L kernel at most by default
+// (option m2l_groups); its waves stride over the M2L boxes.  4096 waves are
+// one resident round on 256 CUs at the kernel's occupancy of 4 per SIMD.
+constexpr int kM2LGroups = 1024;
+
 struct DevPlan {
   int nbox = 0, nlevels = 0;
   int64_t ns = 0, nt = 0;
@@ -119,6 +124,7 @@ struct DevPlan {
   std::vector<int32_t> leaf_t_host;          // leaves with targets
   std::vector<int32_t> leaf_s_host;          // leaves with sources
   int n_leaf_t = 0, n_leaf_s = 0, n_m2l = 0;
+  int m2l_groups = kM2LGroups;               // FP32 M2L launch width
   DBuf<double> cx, cy, rad;
   DBuf<int32_t> parent, child0, nchild, quad, lev;
   DBuf<int32_t> roots;                       // root box of each geometry
@@ -319,10 +325,6 @@ struct Workspace {
 
 constexpr int kPlog = 30;  // terms of the per-island log-source expansions
 constexpr int kLogChunk = 64;  // far-list entries per wave step
-// work-groups (4 waves each) of the FP32 M2L kernel at most; its waves
-// stride over the M2L boxes.  4096 waves are one resident round on 256
-// CUs at the kernel's occupancy of 4 waves per SIMD.
-constexpr int kM2LGroups = 1024;
 
 void set_last_error(const std::string &msg);  // message of lbs_last_error
 // Device arrays of a GPU-built tree that a plan may take instead of host

@@ -8,12 +8,19 @@
 // relative error against a reference application (FP64 far field of
 // order 48 on the smallest leaf size).  It returns the fastest mixed
 // setting within tol_mixed and, for that leaf size, the fastest FP64 order
-// within tol_fp64.  Written on the public C-ABI only.
+// within tol_fp64; then, on that leaf size and FP32 order, the fastest width
+// of the persistent FP32 M2L launch.  lbs_autotune_cached keeps the results
+// in a text file keyed by a hash of the problem, the device and the build.
+// Written on the public C-ABI only.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -184,9 +191,144 @@ extern "C" lbs_status lbs_autotune(const lbs_island *isl, int32_t M, const int32
   best->leaf_max = bm->leaf_max;
   best->p32 = bm->p32;
   best->p64 = bf->p64;
+  // the launch shape of the FP32 M2L on the chosen leaf size and order
+  {
+    const int widths[] = {512, 1024, 2048};
+    double best_ms = 0;
+    int best_w = 0;
+    for (int wdt : widths) {
+      lbs_options c = o;
+      c.leaf_max = bm->leaf_max;
+      c.p32 = bm->p32;
+      c.m2l_groups = wdt;
+      Handle h;
+      lbs_status st = lbs_setup(isl, M, nodes, &c, stream, &h.h);
+      if (st != LBS_OK) return st;
+      lbs_tune_entry e{};
+      e.leaf_max = c.leaf_max;
+      e.p32 = c.p32;
+      e.m2l_groups = wdt;
+      if ((st = timed(h.h, LBS_MIXED, e.ms)) != LBS_OK) return st;
+      e.err = rel_err(out, ref);
+      all.push_back(e);
+      if (e.err <= tol_mixed && (!best_w || e.ms < best_ms)) {
+        best_ms = e.ms;
+        best_w = wdt;
+      }
+    }
+    best->m2l_groups = best_w;  // 0 (the default) if none met tol_mixed
+  }
   if (n_entries) *n_entries = (int32_t)all.size();
   if (entries)
     for (int32_t i = 0; i < std::min<int32_t>(max_entries, (int32_t)all.size()); ++i)
       entries[i] = all[i];
+  return LBS_OK;
+}
+
+namespace {
+
+// 64-bit FNV-1a over a byte range, chained
+uint64_t fnv1a(const void *p, size_t n, uint64_t h = 0xcbf29ce484222325ull) {
+  const unsigned char *b = static_cast<const unsigned char *>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+// The cache key: the problem, the device and this build of the library.
+uint64_t tune_key(const lbs_island *isl, int32_t M, const int32_t *nodes, const lbs_options &o,
+                  double tol_mixed, double tol_fp64) {
+  uint64_t h = fnv1a(isl, sizeof(lbs_island) * (size_t)M);
+  h = fnv1a(nodes, sizeof(int32_t) * (size_t)M, h);
+  lbs_options k = o;
+  k.graphs = 0;  // not part of the schedule
+  h = fnv1a(&k, sizeof(k), h);
+  h = fnv1a(&tol_mixed, sizeof(double), h);
+  h = fnv1a(&tol_fp64, sizeof(double), h);
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    h = fnv1a(prop.gcnArchName, std::strlen(prop.gcnArchName), h);
+    h = fnv1a(&prop.multiProcessorCount, sizeof(int), h);
+  }
+  static const char build[] = __DATE__ " " __TIME__;
+  return fnv1a(build, sizeof(build) - 1, h);
+}
+
+}  // namespace
+
+extern "C" lbs_status lbs_autotune_cached(const lbs_island *isl, int32_t M, const int32_t *nodes,
+                                          const lbs_options *base, double tol_mixed,
+                                          double tol_fp64, void *stream, const char *cache_path,
+                                          lbs_options *best, lbs_tune_entry *entries,
+                                          int32_t max_entries, int32_t *n_entries,
+                                          int32_t *hit) {
+  if (hit) *hit = 0;
+  if (!cache_path || !isl || !nodes || !best || M < 1) {
+    lbs::set_last_error("lbs_autotune_cached: bad argument");
+    return LBS_ERR_INVALID_ARG;
+  }
+  lbs_options o;
+  lbs_default_options(&o);
+  if (base) o = *base;
+  char key[17];
+  std::snprintf(key, sizeof(key), "%016llx",
+                (unsigned long long)tune_key(isl, M, nodes, o, tol_mixed, tol_fp64));
+  // line: "lbs-tune <key> <leaf> <p32> <p64> <groups> <n> then n x (leaf p32
+  // p64 groups ms err)"; the last line with the key wins
+  {
+    std::ifstream in(cache_path);
+    std::string line, found;
+    while (std::getline(in, line))
+      if (line.compare(0, 9, "lbs-tune ") == 0 && line.compare(9, 16, key) == 0) found = line;
+    if (!found.empty()) {
+      std::istringstream ls(found.substr(26));
+      int lm = 0, p32 = 0, p64 = 0, grp = 0, n = 0;
+      std::vector<lbs_tune_entry> all;
+      bool ok = (bool)(ls >> lm >> p32 >> p64 >> grp >> n) && n >= 0;
+      for (int i = 0; ok && i < n; ++i) {
+        lbs_tune_entry e{};
+        ok = (bool)(ls >> e.leaf_max >> e.p32 >> e.p64 >> e.m2l_groups >> e.ms >> e.err);
+        all.push_back(e);
+      }
+      if (ok) {
+        *best = o;
+        best->graphs = base ? base->graphs : 1;
+        best->leaf_max = lm;
+        best->p32 = p32;
+        best->p64 = p64;
+        best->m2l_groups = grp;
+        if (n_entries) *n_entries = n;
+        if (entries)
+          for (int32_t i = 0; i < std::min<int32_t>(max_entries, n); ++i) entries[i] = all[i];
+        if (hit) *hit = 1;
+        return LBS_OK;
+      }
+    }
+  }
+  std::vector<lbs_tune_entry> all(256);
+  int32_t cnt = 0;
+  const lbs_status st = lbs_autotune(isl, M, nodes, base, tol_mixed, tol_fp64, stream, best,
+                                     all.data(), (int32_t)all.size(), &cnt);
+  if (st != LBS_OK) return st;
+  cnt = std::min<int32_t>(cnt, (int32_t)all.size());
+  std::ostringstream os;
+  os.precision(17);
+  os << "lbs-tune " << key << ' ' << best->leaf_max << ' ' << best->p32 << ' ' << best->p64 << ' '
+     << best->m2l_groups << ' ' << cnt;
+  for (int32_t i = 0; i < cnt; ++i)
+    os << ' ' << all[i].leaf_max << ' ' << all[i].p32 << ' ' << all[i].p64 << ' '
+       << all[i].m2l_groups << ' ' << all[i].ms << ' ' << all[i].err;
+  os << '\n';
+  const std::string text = os.str();
+  if (FILE *f = std::fopen(cache_path, "a")) {  // one write of the whole line
+    (void)std::fwrite(text.data(), 1, text.size(), f);
+    (void)std::fclose(f);
+  }
+  if (n_entries) *n_entries = cnt;
+  if (entries)
+    for (int32_t i = 0; i < std::min<int32_t>(max_entries, cnt); ++i) entries[i] = all[i];
   return LBS_OK;
 }

@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("matvec", ctypes.c_int32),
                 ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32),
                 ("close_eval", ctypes.c_int32), ("gpu_tree", ctypes.c_int32),
-                ("eval_tree", ctypes.c_int32)]
+                ("eval_tree", ctypes.c_int32), ("m2l_groups", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -68,8 +68,8 @@ class TreeStats(ctypes.Structure):
 
 class TuneEntry(ctypes.Structure):
     _fields_ = [("leaf_max", ctypes.c_int32), ("p32", ctypes.c_int32),
-                ("p64", ctypes.c_int32), ("ms", ctypes.c_double),
-                ("err", ctypes.c_double)]
+                ("p64", ctypes.c_int32), ("m2l_groups", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("err", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -149,6 +149,12 @@ def load():
                                  ctypes.c_double, vp, ctypes.POINTER(Options),
                                  ctypes.POINTER(TuneEntry), ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_int32)]
+    lib.lbs_autotune_cached.argtypes = [
+        ctypes.POINTER(Island), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+        ctypes.POINTER(Options), ctypes.c_double, ctypes.c_double, vp,
+        ctypes.c_char_p, ctypes.POINTER(Options), ctypes.POINTER(TuneEntry),
+        ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+        ctypes.POINTER(ctypes.c_int32)]
     lib.lbs_setup_sampled.argtypes = [c_double_p, c_double_p, c_double_p,
                                       c_double_p, ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_int32),
@@ -484,8 +490,11 @@ class Solver:
         return st.as_dict()
 
 
-def autotune(islands, tol_mixed=1e-6, tol_fp64=1e-10, nodes=None, **kw):
-    """lbs_autotune: (best Options, [measured settings as dicts])."""
+def autotune(islands, tol_mixed=1e-6, tol_fp64=1e-10, nodes=None, cache=None,
+             **kw):
+    """lbs_autotune (or, with a cache file path, lbs_autotune_cached):
+    (best Options, [measured settings as dicts]); with a cache also whether
+    the result came from the file: (best, entries, hit)."""
     lib = load()
     arr = islands_array(islands)
     m = len(islands.r0)
@@ -496,10 +505,19 @@ def autotune(islands, tol_mixed=1e-6, tol_fp64=1e-10, nodes=None, **kw):
     best = Options()
     ent = (TuneEntry * 64)()
     cnt = ctypes.c_int32()
-    _check(lib.lbs_autotune(arr, m, nn, ctypes.byref(base), float(tol_mixed),
-                            float(tol_fp64), _stream(), ctypes.byref(best),
-                            ent, 64, ctypes.byref(cnt)))
-    return best, [ent[i].as_dict() for i in range(min(cnt.value, 64))]
+    if cache is None:
+        _check(lib.lbs_autotune(arr, m, nn, ctypes.byref(base),
+                                float(tol_mixed), float(tol_fp64), _stream(),
+                                ctypes.byref(best), ent, 64,
+                                ctypes.byref(cnt)))
+        return best, [ent[i].as_dict() for i in range(min(cnt.value, 64))]
+    hit = ctypes.c_int32()
+    _check(lib.lbs_autotune_cached(arr, m, nn, ctypes.byref(base),
+                                   float(tol_mixed), float(tol_fp64), _stream(),
+                                   os.fsencode(cache), ctypes.byref(best), ent,
+                                   64, ctypes.byref(cnt), ctypes.byref(hit)))
+    return (best, [ent[i].as_dict() for i in range(min(cnt.value, 64))],
+            bool(hit.value))
 
 
 def compare_trees(x, y, leaf_max, tx=None, ty=None):

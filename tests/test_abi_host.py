@@ -41,8 +41,8 @@ def test_default_options(lbs):
     o = lbs.default_options()
     assert (o.p64, o.p32, o.restart) == (30, 16, 50)
     assert o.inner_tol == 1e-5
-    assert (o.matvec, o.graphs, o.precond, o.close_eval, o.gpu_tree, o.eval_tree) == \
-        (0, 1, 1, 1, 1, 0)
+    assert (o.matvec, o.graphs, o.precond, o.close_eval, o.gpu_tree, o.eval_tree,
+            o.m2l_groups) == (0, 1, 1, 1, 1, 0, 0)
 
 
 def test_refinement_step_rejects_non_finite_residuals(lbs):

@@ -56,10 +56,14 @@ def test_autotune_meets_tolerances(env, geom):
     torch, lbs = env
     isl, cv, x, ref = geom
     best, entries = lbs.autotune(isl, tol_mixed=1e-6, tol_fp64=1e-10)
-    assert len(entries) == 6 * 8
+    assert len(entries) == 6 * 8 + 3  # leaf sizes x orders, then M2L widths
     assert all(e["ms"] > 0 for e in entries)
     assert best.leaf_max in (24, 32, 48, 64, 96, 128)
     assert best.p32 in (12, 16, 20, 24) and best.p64 in (20, 24, 30, 36)
+    assert best.m2l_groups in (512, 1024, 2048)
+    widths = [e for e in entries if e["m2l_groups"]]
+    assert [e["m2l_groups"] for e in widths] == [512, 1024, 2048]
+    assert all(e["leaf_max"] == best.leaf_max and e["p32"] == best.p32 for e in widths)
     assert best.graphs == 1
     chosen = [e for e in entries if e["leaf_max"] == best.leaf_max and
               e["p32"] == best.p32]
@@ -89,3 +93,32 @@ def test_every_order_against_oracle(env, geom, p64, p32):
     e32 = _rel(sol.matvec(xd, "iplusk", "mixed").cpu().numpy(), ref)
     assert e64 < (1e-10 if p64 >= 30 else 1e-5), e64
     assert e32 < (1e-6 if p32 >= 16 else 1e-4), e32
+
+
+def test_m2l_width_changes_no_result(env, geom):
+    """The FP32 M2L launch width only changes which wave takes which box:
+    the products are bit for bit the same."""
+    torch, lbs = env
+    isl, cv, x, ref = geom
+    xd = _t(torch, x)
+    ys = [lbs.Solver(isl, leaf_max=16, m2l_groups=g).matvec(xd, "iplusk", "mixed")
+          for g in (0, 64, 512, 4096)]
+    for y in ys[1:]:
+        assert torch.equal(y, ys[0])
+
+
+def test_autotune_cache(env, geom, tmp_path):
+    """A second call with the same problem reads the tuned schedule back from
+    the cache file; another tolerance is another key."""
+    torch, lbs = env
+    isl, cv, x, ref = geom
+    path = str(tmp_path / "tune.txt")
+    b1, e1, hit1 = lbs.autotune(isl, tol_mixed=1e-6, tol_fp64=1e-10, cache=path)
+    b2, e2, hit2 = lbs.autotune(isl, tol_mixed=1e-6, tol_fp64=1e-10, cache=path)
+    assert (hit1, hit2) == (False, True)
+    for f in ("leaf_max", "p32", "p64", "m2l_groups", "graphs"):
+        assert getattr(b1, f) == getattr(b2, f), f
+    assert e1 == e2
+    _, _, hit3 = lbs.autotune(isl, tol_mixed=2e-6, tol_fp64=1e-10, cache=path)
+    assert not hit3
+    assert len(open(path).read().splitlines()) == 2
