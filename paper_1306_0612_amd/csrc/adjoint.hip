@@ -380,40 +380,87 @@ void launch_FT(const Geometry &g, const double *z, double a, const double *x,
 }
 
 // ------------------------------------------------------------ T^T
-// (T^T w)_a[m] = sum_t w_t G(x_t, c_m) (direct).
+// (T^T w)_a[m] = sum_t w_t G(x_t, c_m) (direct), in tiles: a work-group
+// takes kTIsl islands (centres in LDS) and kTTgt targets (8 per thread, read
+// once per tile), sums per island over its targets and writes one partial
+// per (island, target chunk); a second kernel adds each island's partials
+// in chunk order.  Chunk c of tile row 0 also writes the chunk's sum of w.
+constexpr int kTIsl = 16;
+constexpr int kTTgt = 2048;
 __global__ void __launch_bounds__(256)
-    k_evalT_logsrc(int64_t T, const double *__restrict__ txyz,
-                   const double *__restrict__ w, int M,
-                   const double *__restrict__ cxyz, double *__restrict__ out) {
-  __shared__ double red[4];
-  const int m = blockIdx.x;
-  const int tid = threadIdx.x, ln = tid & 63;
-  const double c0 = cxyz[3 * m], c1 = cxyz[3 * m + 1], c2 = cxyz[3 * m + 2];
-  double acc = 0.0, ws = 0.0;
-  for (int64_t t = tid; t < T; t += 256) {
-    const double d0 = txyz[3 * t] - c0, d1 = txyz[3 * t + 1] - c1,
-                 d2 = txyz[3 * t + 2] - c2;
-    acc += w[t] * log(d0 * d0 + d1 * d1 + d2 * d2);
-    ws += w[t];
+    k_evalT_logsrc_tile(int64_t T, const double *__restrict__ txyz,
+                        const double *__restrict__ w, int M,
+                        const double *__restrict__ cxyz, int nch,
+                        double *__restrict__ part, double *__restrict__ wpart) {
+  __shared__ double sc[kTIsl][3];
+  __shared__ double red[4][kTIsl + 1];
+  const int tid = threadIdx.x, ln = tid & 63, wv = tid >> 6;
+  const int ch = blockIdx.x, m0 = blockIdx.y * kTIsl;
+  if (tid < kTIsl * 3) {
+    const int i = tid / 3, c = tid % 3;
+    sc[i][c] = m0 + i < M ? cxyz[3 * (m0 + i) + c] : 0.0;
   }
-  acc = wsum(acc);
+  __syncthreads();
+  double acc[kTIsl], ws = 0.0;
+#pragma unroll
+  for (int i = 0; i < kTIsl; ++i) acc[i] = 0.0;
+  const int64_t t0 = (int64_t)ch * kTTgt;
+  for (int j = 0; j < kTTgt / 256; ++j) {
+    const int64_t t = t0 + tid + 256 * j;
+    if (t >= T) break;
+    const double x0 = txyz[3 * t], x1 = txyz[3 * t + 1], x2 = txyz[3 * t + 2], wt = w[t];
+    ws += wt;
+#pragma unroll
+    for (int i = 0; i < kTIsl; ++i) {
+      const double d0 = x0 - sc[i][0], d1 = x1 - sc[i][1], d2 = x2 - sc[i][2];
+      acc[i] += wt * log(d0 * d0 + d1 * d1 + d2 * d2);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kTIsl; ++i) {
+    const double v = wsum(acc[i]);
+    if (ln == 0) red[wv][i] = v;
+  }
+  {
+    const double v = wsum(ws);
+    if (ln == 0) red[wv][kTIsl] = v;
+  }
+  __syncthreads();
+  if (tid < kTIsl && m0 + tid < M)
+    part[(int64_t)(m0 + tid) * nch + ch] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+  if (tid == 0 && blockIdx.y == 0)
+    wpart[ch] = red[0][kTIsl] + red[1][kTIsl] + red[2][kTIsl] + red[3][kTIsl];
+}
+
+__global__ void __launch_bounds__(64)
+    k_evalT_logsrc_sum(int M, int nch, const double *__restrict__ part,
+                       const double *__restrict__ wpart, double *__restrict__ out) {
+  const int m = blockIdx.x, ln = threadIdx.x;
+  double a = 0.0, ws = 0.0;
+  for (int c = ln; c < nch; c += 64) {
+    a += part[(int64_t)m * nch + c];
+    ws += wpart[c];
+  }
+  a = wsum(a);
   ws = wsum(ws);
-  if (ln == 0) red[tid >> 6] = acc;
-  __syncthreads();
-  const double a4 = red[0] + red[1] + red[2] + red[3];
-  __syncthreads();
-  if (ln == 0) red[tid >> 6] = ws;
-  __syncthreads();
-  const double w4 = red[0] + red[1] + red[2] + red[3];
   // G = -(1/4pi) log|d|^2 + log2/4pi
-  if (tid == 0) out[m] = -0.25 * kInvPi_ * a4 + 0.25 * kInvPi_ * kLog2_ * w4;
+  if (ln == 0) out[m] = -0.25 * kInvPi_ * a + 0.25 * kInvPi_ * kLog2_ * ws;
 }
 
 void launch_evalT_logsrc(const Geometry &g, int64_t T, const double *txyz,
-                         const double *w, double *out, hipStream_t s) {
+                         const double *w, double *out, DBuf<double> &scratch, hipStream_t s) {
   if (g.M == 0) return;
-  hipLaunchKernelGGL(k_evalT_logsrc, dim3(g.M), dim3(256), 0, s, T, txyz, w,
-                     g.M, g.dcenter.p, out);
+  const int nch = (int)std::max<int64_t>(1, (T + kTTgt - 1) / kTTgt);
+  const size_t need = (size_t)g.M * nch + nch;
+  if (scratch.n < need) scratch.alloc(need);
+  double *part = scratch.p, *wpart = part + (size_t)g.M * nch;
+  if (T == 0) {
+    launch_fill((int64_t)need, 0.0, scratch.p, s);
+  } else {
+    hipLaunchKernelGGL(k_evalT_logsrc_tile, dim3(nch, (g.M + kTIsl - 1) / kTIsl), dim3(256), 0, s,
+                       T, txyz, w, g.M, g.dcenter.p, nch, part, wpart);
+  }
+  hipLaunchKernelGGL(k_evalT_logsrc_sum, dim3(g.M), dim3(64), 0, s, g.M, nch, part, wpart, out);
   LBS_HIP(hipGetLastError());
 }
 

@@ -392,6 +392,7 @@ struct AdjState {
   DBuf<double> lam;    // N + M
   DBuf<double> pc, Fc; // complex, N x 2
   DBuf<double> ysum;   // per geometry
+  DBuf<double> lpart;  // partial sums of the transposed log-source sums
 };
 
 // HIP graphs of GMRES iterations, keyed by (operator, systems per column
@@ -2174,7 +2175,7 @@ lbs_status lbs_eval_T(lbs_handle h, int32_t nrhs, const double *w, int64_t T, co
       eval_T_field(c, ep, wr, pcw.p, c.adj.Fc.p, nullptr, s);
       launch_sum(T, wr, wsum.p, s);
       launch_evalT_sigma(g, c.adj.Fc.p, wsum.p, gs + (int64_t)r * g.N, s);
-      launch_evalT_logsrc(g, T, txyz, wr, ga + (int64_t)r * g.M, s);
+      launch_evalT_logsrc(g, T, txyz, wr, ga + (int64_t)r * g.M, c.adj.lpart, s);
     }
     LBS_HIP(hipStreamSynchronize(s));
   });

@@ -309,18 +309,33 @@ __global__ void __launch_bounds__(256)
   for (int64_t b = lo + 1; b <= hi; ++b) ptr[b] = k;
 }
 
-// Per entry e of the multipole list (box b = list[e]): its range of the
-// box-sorted multipole pairs and its frame; the pairs' coordinates.
+// chunks of each multipole-list entry's pairs: counts, then their ranges
 __global__ void __launch_bounds__(256)
-    k_mlist(int n, const int32_t *__restrict__ list, const int64_t *__restrict__ ptr,
-            const double *__restrict__ cxv, const double *__restrict__ cyv,
-            const double *__restrict__ rad, int64_t *__restrict__ rng, double4 *__restrict__ geo) {
+    k_chunk_count(int n, const int32_t *__restrict__ list, const int64_t *__restrict__ ptr,
+                  uint32_t *__restrict__ cnt) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const int b = list[e];
-  rng[2 * e] = ptr[b];
-  rng[2 * e + 1] = ptr[b + 1];
-  geo[e] = make_double4(cxv[b], cyv[b], 1.0 / rad[b], 0.0);
+  cnt[e] = (uint32_t)((ptr[b + 1] - ptr[b] + kSrcChunk - 1) / kSrcChunk);
+}
+
+__global__ void __launch_bounds__(256)
+    k_chunk_fill(int n, const int32_t *__restrict__ list, const int64_t *__restrict__ ptr,
+                 const uint32_t *__restrict__ off, const double *__restrict__ cxv,
+                 const double *__restrict__ cyv, const double *__restrict__ rad,
+                 int64_t *__restrict__ rng, double4 *__restrict__ geo, int32_t *__restrict__ iota) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int b = list[e];
+  const int64_t a0 = ptr[b], a1 = ptr[b + 1];
+  const double4 gb = make_double4(cxv[b], cyv[b], 1.0 / rad[b], 0.0);
+  for (uint32_t c = off[e]; c < off[e + 1]; ++c) {
+    const int64_t lo = a0 + (int64_t)(c - off[e]) * kSrcChunk;
+    rng[2 * (int64_t)c] = lo;
+    rng[2 * (int64_t)c + 1] = lo + kSrcChunk < a1 ? lo + kSrcChunk : a1;
+    geo[c] = gb;
+    iota[c] = (int32_t)c;
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -526,11 +541,33 @@ void build_point_sources(const DevPlan &pl, int64_t n, const double *x, const do
     if (pl.host.level[b] >= 2) ml.push_back(b);
   ps.n_m = (int)ml.size();
   ps.m_list.upload(ml, s);
-  ps.m_rng.alloc((size_t)2 * std::max(ps.n_m, 1));
-  ps.m_geo.alloc((size_t)std::max(ps.n_m, 1));
-  if (ps.n_m > 0)
-    hipLaunchKernelGGL(k_mlist, dim3((unsigned)((ps.n_m + 255) / 256)), dim3(256), 0, s, ps.n_m,
-                       ps.m_list.p, mptr.p, pl.cx.p, pl.cy.p, pl.rad.p, ps.m_rng.p, ps.m_geo.p);
+  // chunks of at most kSrcChunk pairs, one wave each
+  {
+    DBuf<uint32_t> coff;
+    coff.alloc((size_t)ps.n_m + 1);
+    LBS_HIP(hipMemsetAsync(coff.p, 0, ((size_t)ps.n_m + 1) * sizeof(uint32_t), s));
+    const unsigned gm = (unsigned)((ps.n_m + 255) / 256);
+    if (ps.n_m > 0)
+      hipLaunchKernelGGL(k_chunk_count, dim3(gm), dim3(256), 0, s, ps.n_m, ps.m_list.p, mptr.p,
+                         coff.p);
+    DBuf<uint32_t> csum;
+    csum.alloc((size_t)((ps.n_m + 1 + 4095) / 4096 + 1));
+    scan_into(coff.p, (int64_t)ps.n_m + 1, csum.p, s);
+    uint32_t nc = 0;
+    LBS_HIP(hipMemcpyAsync(&nc, coff.p + ps.n_m, 4, hipMemcpyDeviceToHost, s));
+    LBS_HIP(hipStreamSynchronize(s));
+    ps.n_c = (int)nc;
+    ps.c_rng.alloc((size_t)2 * std::max(ps.n_c, 1));
+    ps.c_geo.alloc((size_t)std::max(ps.n_c, 1));
+    ps.c_iota.alloc((size_t)std::max(ps.n_c, 1));
+    ps.c_part.alloc((size_t)std::max(ps.n_c, 1) * 2 * 48);  // orders up to 48
+    if (ps.n_m > 0)
+      hipLaunchKernelGGL(k_chunk_fill, dim3(gm), dim3(256), 0, s, ps.n_m, ps.m_list.p, mptr.p,
+                         coff.p, pl.cx.p, pl.cy.p, pl.rad.p, ps.c_rng.p, ps.c_geo.p,
+                         ps.c_iota.p);
+    ps.c_ptr.take(coff);
+    LBS_HIP(hipStreamSynchronize(s));  // csum is released on return
+  }
   ps.m_x.alloc((size_t)std::max<int64_t>(nm, 1));
   ps.m_y.alloc((size_t)std::max<int64_t>(nm, 1));
   ps.m_p.alloc((size_t)2 * std::max<int64_t>(nm, 1));

@@ -1580,6 +1580,20 @@ void fmm_apply64_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
   LBS_HIP(hipGetLastError());
 }
 
+// M[list[e]] = the sum of the partial multipoles of entry e's chunks
+// [ptr[e], ptr[e + 1]), in chunk order; one thread per (entry, coefficient).
+template <int P>
+__global__ void __launch_bounds__(256)
+    k_sum_chunks(int n, const int32_t *__restrict__ list, const uint32_t *__restrict__ ptr,
+                 const cx<double> *__restrict__ part, cx<double> *__restrict__ M) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)n * P) return;
+  const int e = (int)(id / P), k = (int)(id % P);
+  cx<double> a{0.0, 0.0};
+  for (uint32_t c = ptr[e]; c < ptr[e + 1]; ++c) a = a + part[(int64_t)c * P + k];
+  M[(int64_t)list[e] * P + k] = a;
+}
+
 template <int P>
 static void run64_sources(const DevPlan &pl, const Tables &tb, Workspace &ws,
                           PointSources &ps, const cx<double> *pin, double *psi, double *dpsi,
@@ -1588,14 +1602,18 @@ static void run64_sources(const DevPlan &pl, const Tables &tb, Workspace &ws,
   auto *L = (cx<double> *)ws.loc64.p;
   const auto *H = (const double *)tb.h64.p;
   const auto *itp = (const cx<double> *)tb.itp64.p;
-  // multipoles of every box of level >= 2 from the points it holds (boxes
-  // without points keep the zeros)
-  launch_fill((int64_t)pl.nbox * P * 2, 0.0, (double *)M, s);
+  // multipoles of every box of level >= 2 from the points it holds: the
+  // partial multipoles of chunks of at most kSrcChunk pairs, added per box
+  // (boxes without points get zeros)
   launch_gather_cx(ps.nm, ps.m_t.p, (const double *)pin, ps.m_p.p, s);
+  auto *part = (cx<double> *)ps.c_part.p;
+  if (ps.n_c > 0)
+    hipLaunchKernelGGL((k_p2m<double, P>), dim3(ps.n_c, 1), dim3(64), 0, s, ps.c_iota.p,
+                       ps.c_rng.p, ps.c_geo.p, ps.m_x.p, ps.m_y.p, (cx<double> *)ps.m_p.p,
+                       ps.nm, part, ps.n_c, StrengthSrc{});
   if (ps.n_m > 0)
-    hipLaunchKernelGGL((k_p2m<double, P>), dim3(ps.n_m, 1), dim3(64), 0, s, ps.m_list.p,
-                       ps.m_rng.p, ps.m_geo.p, ps.m_x.p, ps.m_y.p, (cx<double> *)ps.m_p.p,
-                       ps.nm, M, pl.nbox, StrengthSrc{});
+    hipLaunchKernelGGL((k_sum_chunks<P>), dim3((unsigned)(((int64_t)ps.n_m * P + 255) / 256)),
+                       dim3(256), 0, s, ps.n_m, ps.m_list.p, ps.c_ptr.p, part, M);
   // the tree's V lists, then the points' own local-expansion terms
   if (pl.n_m2l > 0)
     hipLaunchKernelGGL((k_m2l<double, P>), dim3(pl.n_m2l, 1), dim3(64), 0, s, pl.m2l_box.p,

@@ -534,19 +534,25 @@ void launch_gather_cx(int64_t n, const int32_t *idx, const double *in, double *o
 // Sources at n arbitrary points (x, y) located in a plan's tree (box: the
 // deepest box whose square holds the point, -1 outside the root square;
 // root: its tree's root), as (box, point) pairs sorted by box: the
-// multipole of every box of level >= 2 holding the point (list m_list,
-// ranges m_rng into the pair-ordered coordinates m_x, m_y), the local
+// multipole of every box of level >= 2 holding the point (list m_list; the
+// pairs' coordinates m_x, m_y in pair order), the local
 // expansions its walk takes by multipole (offsets l_ptr over the plan's
 // boxes into l_t), the leaves its walk sums directly (d_ptr, d_t).
 // The plan needs its tree links on the device.  (evalpts.hip)
+// The multipole pairs of a box are cut into chunks of at most kSrcChunk
+// (one wave each, c_rng / c_geo, chunk offsets per m_list entry c_ptr),
+// whose partial multipoles (c_part) are added per box in chunk order.
+constexpr int kSrcChunk = 256;
 struct PointSources {
   int64_t n = 0, nm = 0;
   const double *x = nullptr, *y = nullptr;  // not owned
   int n_m = 0;  // entries of m_list (also the boxes passed for local terms)
-  DBuf<int32_t> m_list, m_t, l_t, d_t;
-  DBuf<int64_t> m_rng, l_ptr, d_ptr;
-  DBuf<double4> m_geo;
-  DBuf<double> m_x, m_y, m_p;  // m_p: the pairs' strengths of a call
+  int n_c = 0;  // chunks of the multipole pairs
+  DBuf<int32_t> m_list, m_t, l_t, d_t, c_iota;
+  DBuf<int64_t> l_ptr, d_ptr, c_rng;
+  DBuf<uint32_t> c_ptr;
+  DBuf<double4> c_geo;
+  DBuf<double> m_x, m_y, m_p, c_part;  // m_p: the pairs' strengths of a call
 };
 void build_point_sources(const DevPlan &pl, int64_t n, const double *x, const double *y,
                          const int32_t *box, const int32_t *root, PointSources &ps,
@@ -606,7 +612,7 @@ void launch_FT(const Geometry &g, const double *z, double a, const double *x,
 void launch_transpose_blocks(const Geometry &g, const double *A, double *AT,
                              hipStream_t s);
 void launch_evalT_logsrc(const Geometry &g, int64_t T, const double *txyz,
-                         const double *w, double *out, hipStream_t s);
+                         const double *w, double *out, DBuf<double> &scratch, hipStream_t s);
 void launch_evalT_sigma(const Geometry &g, const double *FT,
                         const double *wsum_dev, double *out, hipStream_t s);
 void launch_sum(int64_t n, const double *x, double *out, hipStream_t s);
