@@ -381,6 +381,7 @@ struct EvalPlan {
   PointSources src;
   ClosePlan close;              // targets in close zones (close_eval on)
   DBuf<double> closeV;          // boundary values, 2 N per column
+  DBuf<double> lpart;           // log-source partial sums per island chunk
 };
 
 // Buffers of the transposed operators (one column).
@@ -1726,7 +1727,7 @@ void eval_impl(lbs_ctx &c, int nrhs, const double *sigma, const double *A,
   ensure_ws(c, nrhs);
   launch_segdots(c.seg_nodes, nrhs, 1, g.gw.p, 0, 0, sigma, g.N, c.ws.gam.p, c.ws.red.p, s);
   launch_axpby((int64_t)nrhs * G, 0.0, c.ws.gam.p, 0.5, c.ws.gam.p, s);
-  launch_eval_logsrc(g, T, txyz, ep.dtgeo.p, A, g.M, nrhs, c.ws.gam.p, u, T, s);
+  launch_eval_logsrc(g, T, txyz, ep.dtgeo.p, A, g.M, nrhs, c.ws.gam.p, u, T, s, &ep.lpart);
   if (ep.close.n_tgt > 0) {
     if (ep.closeV.n < (size_t)2 * g.N * nrhs) ep.closeV.alloc((size_t)2 * g.N * nrhs);
     launch_close_eval(g, ep.close, nrhs, sigma, g.N, ep.closeV.p, u, T, s);

@@ -484,7 +484,7 @@ void launch_gemv_blocks_with(const Geometry &g, const double *A,
 void launch_eval_logsrc(const Geometry &g, int64_t T, const double *txyz,
                         const int32_t *tgeo, const double *A, int64_t lda,
                         int nrhs, const double *add, double *u, int64_t ldu,
-                        hipStream_t s);
+                        hipStream_t s, DBuf<double> *scratch = nullptr);
 
 // GMRES building blocks (solver.hip)
 void launch_maxpy_seg(int64_t n, int R, int G, int k1, const int32_t *row_geo,

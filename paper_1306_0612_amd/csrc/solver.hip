@@ -908,14 +908,75 @@ __global__ void __launch_bounds__(256)
                              0.25 * kInvPi * kLog2 * asum + add[r * G + g];
 }
 
+// The same for one geometry, split over chunks of 256 islands (grid y) so
+// that a target set of ~1e5 fills the chip: each work-group stages its
+// chunk's centres and strengths in LDS, each thread sums them for one
+// target into part[(r nch + chunk) T + t]; k_eval_logsrc_fin adds the
+// chunks in order.
+__global__ void __launch_bounds__(256)
+    k_eval_logsrc_part(int64_t T, const double *__restrict__ txyz, int M,
+                       const double *__restrict__ cxyz, const double *__restrict__ A,
+                       int64_t lda, double *__restrict__ part) {
+  __shared__ double4 sc[256];  // centre, A
+  const int ch = blockIdx.y, r = blockIdx.z, tid = threadIdx.x, nch = gridDim.y;
+  const int m0 = ch * 256, nm = min(256, M - m0);
+  if (tid < nm) {
+    const int m = m0 + tid;
+    sc[tid] = make_double4(cxyz[3 * m], cxyz[3 * m + 1], cxyz[3 * m + 2],
+                           A[(int64_t)r * lda + m]);
+  }
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * 256 + tid;
+  if (t >= T) return;
+  const double x0 = txyz[3 * t], x1 = txyz[3 * t + 1], x2 = txyz[3 * t + 2];
+  double acc = 0.0;
+  for (int j = 0; j < nm; ++j) {
+    const double4 c = sc[j];
+    const double d0 = x0 - c.x, d1 = x1 - c.y, d2 = x2 - c.z;
+    acc += c.w * log(d0 * d0 + d1 * d1 + d2 * d2);
+  }
+  part[((int64_t)r * nch + ch) * T + t] = acc;
+}
+
+__global__ void __launch_bounds__(256)
+    k_eval_logsrc_fin(int64_t T, int nch, const double *__restrict__ part, int M,
+                      const double *__restrict__ A, int64_t lda, const double *__restrict__ add,
+                      double *__restrict__ u, int64_t ldu) {
+  __shared__ double red[4];
+  const int r = blockIdx.y, tid = threadIdx.x;
+  // sum of A (every work-group forms it; 2000 values)
+  double as = 0.0;
+  for (int m = tid; m < M; m += 256) as += A[(int64_t)r * lda + m];
+  for (int o = 32; o > 0; o >>= 1) as += __shfl_xor(as, o, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = as;
+  __syncthreads();
+  const double asum = red[0] + red[1] + red[2] + red[3];
+  const int64_t t = (int64_t)blockIdx.x * 256 + tid;
+  if (t >= T) return;
+  double acc = 0.0;
+  for (int c = 0; c < nch; ++c) acc += part[((int64_t)r * nch + c) * T + t];
+  // G = -(1/4pi) log|d|^2 + log2/4pi
+  u[(int64_t)r * ldu + t] += -0.25 * kInvPi * acc + 0.25 * kInvPi * kLog2 * asum + add[r];
+}
+
 void launch_eval_logsrc(const Geometry &g, int64_t T, const double *txyz,
                         const int32_t *tgeo, const double *A, int64_t lda,
                         int nrhs, const double *add, double *u, int64_t ldu,
-                        hipStream_t s) {
+                        hipStream_t s, DBuf<double> *scratch) {
   if (T == 0) return;
-  hipLaunchKernelGGL(k_eval_logsrc, dim3((unsigned)((T + 255) / 256), nrhs),
-                     dim3(256), 0, s, T, txyz, tgeo, g.G, g.dgisl.p,
-                     g.dcenter.p, A, lda, add, u, ldu);
+  if (g.G == 1 && scratch) {
+    const int nch = (g.M + 255) / 256;
+    const size_t need = (size_t)nch * T * nrhs;
+    if (scratch->n < need) scratch->alloc(need);
+    const unsigned gt = (unsigned)((T + 255) / 256);
+    hipLaunchKernelGGL(k_eval_logsrc_part, dim3(gt, nch, nrhs), dim3(256), 0, s, T, txyz, g.M,
+                       g.dcenter.p, A, lda, scratch->p);
+    hipLaunchKernelGGL(k_eval_logsrc_fin, dim3(gt, nrhs), dim3(256), 0, s, T, nch, scratch->p,
+                       g.M, A, lda, add, u, ldu);
+  } else
+    hipLaunchKernelGGL(k_eval_logsrc, dim3((unsigned)((T + 255) / 256), nrhs),
+                       dim3(256), 0, s, T, txyz, tgeo, g.G, g.dgisl.p,
+                       g.dcenter.p, A, lda, add, u, ldu);
   LBS_HIP(hipGetLastError());
 }
 
