@@ -129,6 +129,13 @@ typedef struct {
   int32_t m2l_groups;/* work-groups of the persistent FP32 M2L launch     */
                      /* (0 = the default 1024; else 64 .. 8192): the      */
                      /* launch shape lbs_autotune also tunes               */
+  double schur_tol;  /* set-up forms each S_g^-1 (eq. matrix_eqns_c) by   */
+                     /* Gauss-Jordan elimination in the natural order and  */
+                     /* accepts it when the componentwise backward error   */
+                     /* of S_g^-1 x for a fixed probe x is <= schur_tol    */
+                     /* (default 1e-12), else redoes every block with      */
+                     /* partial pivoting; <= 0: partial pivoting only.     */
+                     /* lbs_schur_info reports which was used.             */
 } lbs_options;
 
 typedef struct {
@@ -482,6 +489,14 @@ lbs_status lbs_check_tree_host(const double *x_host, const double *y_host,
                                int64_t n, int32_t leaf_max,
                                int64_t *bad_pairs_host,
                                lbs_tree_stats *stats_host);
+
+/* How set-up formed the Schur-complement inverses (eq. matrix_eqns_c):
+ * *pivoted_host = 0 by Gauss-Jordan elimination in the natural order, 1 by
+ * partial pivoting (options.schur_tol <= 0, or the natural order failed its
+ * check); *omega_host = the probe backward error measured for the natural
+ * order (largest over the geometries), -1 when it was not tried.  Either
+ * pointer may be NULL.  Host only. */
+lbs_status lbs_schur_info(lbs_handle h, int32_t *pivoted_host, double *omega_host);
 
 /* Check of the Schur-complement inverse of the preconditioner (eq.
  * matrix_eqns_c): rebuilds every geometry's block S_g and returns in

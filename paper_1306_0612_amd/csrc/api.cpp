@@ -425,6 +425,7 @@ struct lbs_ctx {
   GmresState gm;
   AdjState adj;
   std::unique_ptr<EvalPlan> evf, evt;  // cached forward / transposed plans
+  SchurInverseInfo sinv_info;          // how set-up formed S^-1
   GraphCache graphs;
   // island centres hashed by (geometry, cell of the unit cube) for the
   // close-zone search of evaluations; built on first use
@@ -1140,6 +1141,7 @@ void validate_options(const lbs_options &o) {
   if (o.eval_tree != 0 && o.eval_tree != 1) fail(LBS_ERR_INVALID_ARG, "eval_tree must be 0 or 1");
   if (o.m2l_groups != 0 && (o.m2l_groups < 64 || o.m2l_groups > 8192))
     fail(LBS_ERR_INVALID_ARG, "m2l_groups must be 0 or in [64, 8192]");
+  if (!(o.schur_tol <= 1e-3)) fail(LBS_ERR_INVALID_ARG, "schur_tol must be <= 1e-3 (not NaN)");
 }
 
 // Set-up of G geometries (islands and node counts concatenated
@@ -1518,7 +1520,7 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl_in
     g.Sinv.alloc((size_t)g.gsinv[G]);
     HostPhase ph("setup Schur + inverse");
     launch_build_schur(g, S.p, s);
-    invert_blocks(g, S.p, g.Sinv.p, s);
+    ctx->sinv_info = invert_schur(g, S.p, g.Sinv.p, o.schur_tol, s);
     if (host_timing()) LBS_HIP(hipStreamSynchronize(s));
   }
   ensure_ws(*ctx, 1);
@@ -1929,6 +1931,7 @@ void lbs_default_options(lbs_options *o) {
   o->gpu_tree = 1;
   o->eval_tree = 0;
   o->m2l_groups = 0;
+  o->schur_tol = 1e-12;
 }
 
 lbs_status lbs_refine_tolerances_host(int32_t S, const double *rn2, const double *bn2,
@@ -2412,6 +2415,14 @@ lbs_status lbs_tree_info(lbs_handle h, lbs_tree_stats *st) {
     check_handle(h);
     if (!st) fail(LBS_ERR_INVALID_ARG, "stats is NULL");
     fill_stats(h->plan.host, st);
+  });
+}
+
+lbs_status lbs_schur_info(lbs_handle h, int32_t *pivoted, double *omega) {
+  return guard([&] {
+    check_handle(h);
+    if (pivoted) *pivoted = h->sinv_info.pivoted;
+    if (omega) *omega = h->sinv_info.omega;
   });
 }
 

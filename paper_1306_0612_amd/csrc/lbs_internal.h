@@ -475,6 +475,15 @@ void launch_constraint_rows(const Geometry &g, const double *sigma,
                             hipStream_t s);
 void launch_build_schur(const Geometry &g, double *S, hipStream_t s);
 void invert_blocks(const Geometry &g, double *S, double *Sinv, hipStream_t s);
+// How a handle's S^-1 was formed: pivoted = 0 by elimination in the natural
+// order (accepted when the probe backward error omega <= the tolerance),
+// 1 by partial pivoting; omega < 0 when the natural order was not tried.
+struct SchurInverseInfo {
+  int pivoted = 0;
+  double omega = -1.0;
+};
+SchurInverseInfo invert_schur(const Geometry &g, double *S, double *Sinv, double tol,
+                              hipStream_t s);
 void launch_gemv_blocks(const Geometry &g, const double *x, int64_t ldx,
                         int nrhs, double *y, int64_t ldy, double alpha,
                         hipStream_t s);

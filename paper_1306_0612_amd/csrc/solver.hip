@@ -810,6 +810,304 @@ void invert_blocks(const Geometry &g, double *S, double *Sinv, hipStream_t s) {
   LBS_HIP(hipStreamSynchronize(s));
 }
 
+// Inversion without row interchanges.  The Schur complements of this
+// problem have the constraint row of ones first and, below it, rows
+// dominated by each island's own log term (the log of its radius against
+// the logs of island distances), so Gauss-Jordan elimination in the natural
+// order is stable for them; invert_schur checks every result and falls back
+// to the pivoted elimination above when the check fails.  Panels of kNP
+// columns J = j0 .. j0 + nb - 1, three launches each:
+//  1. k_gjn_block: Binv = S_JJ^-1 by Gauss-Jordan elimination in the
+//     natural order (one work-group per geometry);
+//  2. k_gjn_rowcol: R = S[J, :], W = Binv R and Cn_i = -S[i, J] Binv for
+//     the rows i outside J (one work-group per 64 columns or 64 rows);
+//  3. k_gjn_update: S_ij += Cn_i R_j (i, j outside J), S_iJ = Cn_i,
+//     S_Jj = W_j, S_JJ = Binv, in 64 x 64 tiles.
+// After the last panel S holds S^-1 with no permutation to undo.
+constexpr int kNP = 64;
+
+// Thread t holds the entries (a0 + u, b), u < 4, of the kNP x kNP block,
+// b = t mod 64, a0 = 4 (t / 64).  Step k needs the step-(k-1) values of
+// row k and column k, which their owners publish in LDS (two copies, so
+// that one barrier per step suffices).  The steps are bound by VALU issue
+// on the one CU (about 0.6 us each; 256 threads with 16 entries each, or
+// one wave with 64, take 1.5 and 4 times as long).
+constexpr int kGJNT = 1024;
+__global__ void __launch_bounds__(kGJNT)
+    k_gjn_block(int j0, const int32_t *__restrict__ gisl, const int64_t *__restrict__ gsinv,
+                const double *__restrict__ S, double *__restrict__ Binv) {
+  constexpr int U = kNP * kNP / kGJNT;
+  __shared__ double rowk[2][kNP], colk[2][kNP];
+  const int g = blockIdx.x;
+  const int Mg = gisl[g + 1] - gisl[g];
+  if (j0 >= Mg) return;
+  const int nb = min(kNP, Mg - j0);
+  const double *Sg = S + gsinv[g];
+  const int b = threadIdx.x & 63, a0 = (threadIdx.x >> 6) * U;
+  double v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int a = a0 + u;
+    v[u] = (a < nb && b < nb) ? Sg[(int64_t)(j0 + a) * Mg + j0 + b] : 0.0;
+  }
+  if (a0 == 0) rowk[0][b] = v[0];
+  if (b == 0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) colk[0][a0 + u] = v[u];
+  }
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    const int cur = k & 1, nxt = cur ^ 1;
+    double ca[U];  // column k of this thread's rows (the same for the wave)
+#pragma unroll
+    for (int u = 0; u < U; ++u) ca[u] = colk[cur][a0 + u];
+    const double pinv = 1.0 / rowk[cur][k];
+    const double rkb = rowk[cur][b] * pinv;  // entry (k, b) over the pivot
+    // the entries off row and column k (the padding past nb stays 0, as
+    // its row and column entries are 0); row k (one wave, uniform) and
+    // column k (one lane per wave) are overwritten after
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = fma(-ca[u], rkb, v[u]);
+    if (b == k) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = -ca[u] * pinv;
+    }
+    if (k >= a0 && k < a0 + U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (a0 + u == k) v[u] = b == k ? pinv : rowk[cur][b] * pinv;
+    }
+    const int kn = k + 1;
+    if (kn < nb) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (a0 + u == kn) rowk[nxt][b] = v[u];
+      if (b == kn) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) colk[nxt][a0 + u] = v[u];
+      }
+    }
+    __syncthreads();
+  }
+  double *Bg = Binv + (int64_t)g * kNP * kNP;
+#pragma unroll
+  for (int u = 0; u < U; ++u) Bg[(a0 + u) * kNP + b] = v[u];
+}
+
+// blockIdx.y = 0: columns c0 .. c0 + 15: R[k][c] = S[j0 + k][c] and
+// W[k][c] = sum_q Binv[k][q] R[q][c]; blockIdx.y = 1: rows i0 .. i0 + 15
+// outside J: Cn[k][i] = -sum_q S[i][j0 + q] Binv[q][k].  R, W and Cn are
+// kNP x maxM per geometry; entries past nb are not written.
+constexpr int kRC = 16;  // columns or rows per work-group
+__global__ void __launch_bounds__(256)
+    k_gjn_rowcol(int j0, const int32_t *__restrict__ gisl, const int64_t *__restrict__ gsinv,
+                 const double *__restrict__ S, const double *__restrict__ Binv,
+                 double *__restrict__ R, double *__restrict__ W, double *__restrict__ Cn,
+                 int maxM) {
+  __shared__ double bl[kNP][kNP + 1];
+  __shared__ double st[kNP][kRC + 1];  // st[q][e]: S[j0 + q][e0 + e] or S[e0 + e][j0 + q]
+  const int g = blockIdx.z;
+  const int Mg = gisl[g + 1] - gisl[g];
+  if (j0 >= Mg) return;
+  const int nb = min(kNP, Mg - j0);
+  const int e0 = blockIdx.x * kRC;
+  if (e0 >= Mg) return;
+  const bool rows = blockIdx.y == 0;
+  const double *X = S + gsinv[g];
+  const double *Bg = Binv + (int64_t)g * kNP * kNP;
+  for (int e = threadIdx.x; e < kNP * kNP; e += 256) bl[e / kNP][e % kNP] = Bg[e];
+  for (int e = threadIdx.x; e < kNP * kRC; e += 256) {
+    if (rows) {
+      const int q = e / kRC, c = e % kRC;
+      st[q][c] = (q < nb && e0 + c < Mg) ? X[(int64_t)(j0 + q) * Mg + e0 + c] : 0.0;
+    } else {
+      const int i = e / kNP, q = e % kNP;
+      st[q][i] = (q < nb && e0 + i < Mg) ? X[(int64_t)(e0 + i) * Mg + j0 + q] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int l = threadIdx.x % kRC, e = e0 + l;
+  if (e >= Mg) return;
+  const int64_t base = (int64_t)g * kNP * maxM;
+  if (rows) {
+    for (int k = threadIdx.x / kRC; k < nb; k += 256 / kRC) {
+      double t = 0.0;
+      for (int q = 0; q < nb; ++q) t += bl[k][q] * st[q][l];
+      R[base + (int64_t)k * maxM + e] = st[k][l];
+      W[base + (int64_t)k * maxM + e] = t;
+    }
+  } else {
+    if (e >= j0 && e < j0 + nb) return;
+    for (int k = threadIdx.x / kRC; k < nb; k += 256 / kRC) {
+      double t = 0.0;
+      for (int q = 0; q < nb; ++q) t += st[q][l] * bl[q][k];
+      Cn[base + (int64_t)k * maxM + e] = -t;
+    }
+  }
+}
+
+// Tiles of 64 x 64 entries, 4 x 4 per thread; the rank-nb product is
+// staged through LDS in two halves of 32 terms, both operands k-major so
+// that each thread reads its four rows and four columns as two 16-byte
+// words each.
+__global__ void __launch_bounds__(256)
+    k_gjn_update(int j0, const int32_t *__restrict__ gisl, const int64_t *__restrict__ gsinv,
+                 double *__restrict__ S, const double *__restrict__ Cn,
+                 const double *__restrict__ R, const double *__restrict__ W,
+                 const double *__restrict__ Binv, int maxM) {
+  constexpr int KH = kNP / 2;
+  __shared__ __align__(16) double cs[KH][64 + 4];
+  __shared__ __align__(16) double rs[KH][64 + 4];
+  const int g = blockIdx.z;
+  const int Mg = gisl[g + 1] - gisl[g];
+  if (j0 >= Mg) return;
+  const int nb = min(kNP, Mg - j0);
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  if (c0 >= Mg || r0 >= Mg) return;
+  const int64_t base = (int64_t)g * kNP * maxM;
+  double *Sg = S + gsinv[g];
+  const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
+  double old[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = r0 + tr + i, c = c0 + tc + j;
+      old[i][j] = (r < Mg && c < Mg) ? Sg[(int64_t)r * Mg + c] : 0.0;
+    }
+  double acc[4][4] = {};
+  for (int h = 0; h < nb; h += KH) {
+    if (h > 0) __syncthreads();
+    for (int e = threadIdx.x; e < 64 * KH; e += 256) {
+      const int kk = e / 64, t = e % 64, k = h + kk;
+      const int r = r0 + t, c = c0 + t;
+      const bool rin = r >= j0 && r < j0 + nb, cin = c >= j0 && c < j0 + nb;
+      cs[kk][t] = (k < nb && r < Mg && !rin) ? Cn[base + (int64_t)k * maxM + r] : 0.0;
+      rs[kk][t] = (k < nb && c < Mg && !cin) ? R[base + (int64_t)k * maxM + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < KH; ++kk) {
+      const double2 a01 = *reinterpret_cast<const double2 *>(&cs[kk][tr]);
+      const double2 a23 = *reinterpret_cast<const double2 *>(&cs[kk][tr + 2]);
+      const double2 b01 = *reinterpret_cast<const double2 *>(&rs[kk][tc]);
+      const double2 b23 = *reinterpret_cast<const double2 *>(&rs[kk][tc + 2]);
+      const double av[4] = {a01.x, a01.y, a23.x, a23.y};
+      const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = r0 + tr + i;
+    if (r >= Mg) continue;
+    const bool rin = r >= j0 && r < j0 + nb;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = c0 + tc + j;
+      if (c >= Mg) continue;
+      const bool cin = c >= j0 && c < j0 + nb;
+      double *X = Sg + (int64_t)r * Mg + c;
+      if (rin && cin) *X = Binv[((int64_t)g * kNP + (r - j0)) * kNP + (c - j0)];
+      else if (rin) *X = W[base + (int64_t)(r - j0) * maxM + c];
+      else if (cin) *X = Cn[base + (int64_t)(c - j0) * maxM + r];
+      else *X = old[i][j] + acc[i][j];
+    }
+  }
+}
+
+// om[i] = |S y - x|_i / (|S| |y| + |x|)_i for row i (the componentwise
+// backward error of y as a solution of S y = x), one wave per row.
+__global__ void __launch_bounds__(256)
+    k_probe_backward(int M, const int32_t *__restrict__ isl_geo,
+                     const int32_t *__restrict__ gisl, const int64_t *__restrict__ gsinv,
+                     const double *__restrict__ S, const double *__restrict__ y,
+                     const double *__restrict__ x, double *__restrict__ om) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int ln = threadIdx.x & 63;
+  if (row >= M) return;
+  const int g = isl_geo[row];
+  const int m0 = gisl[g], Mg = gisl[g + 1] - m0;
+  const double *a = S + gsinv[g] + (int64_t)(row - m0) * Mg;
+  const double *yr = y + m0;
+  double z = 0.0, d = 0.0;
+  for (int j = ln; j < Mg; j += 64) {
+    z += a[j] * yr[j];
+    d += fabs(a[j]) * fabs(yr[j]);
+  }
+  z = wave_sum(z);
+  d = wave_sum(d);
+  if (ln == 0) {
+    const double r = fabs(z - x[row]), den = d + fabs(x[row]);
+    om[row] = den > 0.0 ? r / den : r;
+  }
+}
+
+static void invert_natural_order(const Geometry &g, double *X, hipStream_t s) {
+  const int G = g.G, maxM = g.maxM;
+  DBuf<double> R, W, Cn, Bi;
+  R.alloc((size_t)G * kNP * maxM);
+  W.alloc((size_t)G * kNP * maxM);
+  Cn.alloc((size_t)G * kNP * maxM);
+  Bi.alloc((size_t)G * kNP * kNP);
+  const unsigned n64 = (maxM + 63) / 64, nrc = (maxM + kRC - 1) / kRC;
+  for (int j0 = 0; j0 < maxM; j0 += kNP) {
+    hipLaunchKernelGGL(k_gjn_block, dim3(G), dim3(kGJNT), 0, s, j0, g.dgisl.p, g.dgsinv.p, X,
+                       Bi.p);
+    hipLaunchKernelGGL(k_gjn_rowcol, dim3(nrc, 2, G), dim3(256), 0, s, j0, g.dgisl.p,
+                       g.dgsinv.p, X, Bi.p, R.p, W.p, Cn.p, maxM);
+    hipLaunchKernelGGL(k_gjn_update, dim3(n64, n64, G), dim3(256), 0, s, j0, g.dgisl.p,
+                       g.dgsinv.p, X, Cn.p, R.p, W.p, Bi.p, maxM);
+  }
+  LBS_HIP(hipGetLastError());
+}
+
+// Largest componentwise backward error over the islands of y = Sinv x as a
+// solution of S y = x, x a fixed probe of entries +-[0.5, 1) (NaN if any
+// entry is not finite).
+static double probe_backward_error(const Geometry &g, const double *S, const double *Sinv,
+                                   hipStream_t s) {
+  std::vector<double> hx(g.M);
+  for (int i = 0; i < g.M; ++i) {
+    const double m = 0.5 + (double)(((uint64_t)i * 2654435761ull) % 1000ull) / 2000.0;
+    hx[i] = ((uint64_t)i * 40503ull) % 3ull == 0 ? -m : m;
+  }
+  DBuf<double> x, y, om;
+  x.upload(hx, s);
+  y.alloc(g.M);
+  om.alloc(g.M);
+  launch_gemv_blocks_with(g, Sinv, x.p, g.M, 1, y.p, g.M, 1.0, s);
+  hipLaunchKernelGGL(k_probe_backward, dim3((g.M + 3) / 4), dim3(256), 0, s, g.M, g.isl_geo.p,
+                     g.dgisl.p, g.dgsinv.p, S, y.p, x.p, om.p);
+  LBS_HIP(hipGetLastError());
+  const std::vector<double> ho = om.download(s);
+  double w = 0.0;
+  for (double v : ho)
+    if (!(v <= w)) w = v;  // NaN propagates
+  return w;
+}
+
+SchurInverseInfo invert_schur(const Geometry &g, double *S, double *Sinv, double tol,
+                              hipStream_t s) {
+  SchurInverseInfo info;
+  if (g.M == 0) return info;
+  if (g.maxM > 8 * kGJT)
+    throw ApiError{LBS_ERR_UNSUPPORTED, "more than 8192 islands in one geometry"};
+  if (tol > 0.0) {
+    LBS_HIP(hipMemcpyAsync(Sinv, S, (size_t)g.gsinv[g.G] * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+    invert_natural_order(g, Sinv, s);
+    info.omega = probe_backward_error(g, S, Sinv, s);
+    if (info.omega <= tol) return info;
+  }
+  invert_blocks(g, S, Sinv, s);
+  info.pivoted = 1;
+  return info;
+}
+
 // y[k] = alpha sum_m Sinv_g[kl][ml] x[gisl[g] + ml] (block diagonal),
 // one wave per island row.
 __global__ void __launch_bounds__(256)

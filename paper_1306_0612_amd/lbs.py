@@ -39,7 +39,8 @@ class Options(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("matvec", ctypes.c_int32),
                 ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32),
                 ("close_eval", ctypes.c_int32), ("gpu_tree", ctypes.c_int32),
-                ("eval_tree", ctypes.c_int32), ("m2l_groups", ctypes.c_int32)]
+                ("eval_tree", ctypes.c_int32), ("m2l_groups", ctypes.c_int32),
+                ("schur_tol", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -171,6 +172,8 @@ def load():
                                      vp, ctypes.c_int64, vp, vp, vp]
     lib.lbs_schur_residual.argtypes = [vp, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_double), vp]
+    lib.lbs_schur_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_double)]
     lib.lbs_check_passes_host.argtypes = [c_double_p, c_double_p,
                                           ctypes.c_int64, ctypes.c_int32,
                                           ctypes.c_int32,
@@ -186,7 +189,7 @@ def load():
     for name in ("lbs_refine_tolerances_host", "lbs_setup_sampled",
                  "lbs_vortex_data", "lbs_vortex_field", "lbs_matvec_noalloc",
                  "lbs_compare_trees", "lbs_check_passes_host",
-                 "lbs_schur_residual",
+                 "lbs_schur_residual", "lbs_schur_info",
                  "lbs_resample_curve_host", "lbs_setup", "lbs_sizes",
                  "lbs_nodes", "lbs_matvec", "lbs_solve", "lbs_eval", "lbs_destroy", "lbs_tree_info",
                  "lbs_stage_timing", "lbs_stage_times", "lbs_setup_batch",
@@ -483,6 +486,15 @@ class Solver:
         _check(load().lbs_schur_residual(self._h, int(ncols), ctypes.byref(e),
                                          _stream()))
         return e.value
+
+    def schur_info(self):
+        """(pivoted, omega): 0 when set-up formed S^-1 in the natural order,
+        1 with partial pivoting; omega is the probe backward error of the
+        natural order (-1 when it was not tried)."""
+        piv = ctypes.c_int32()
+        om = ctypes.c_double()
+        _check(load().lbs_schur_info(self._h, ctypes.byref(piv), ctypes.byref(om)))
+        return piv.value, om.value
 
     def tree_info(self):
         st = TreeStats()

@@ -43,6 +43,7 @@ def test_default_options(lbs):
     assert o.inner_tol == 1e-5
     assert (o.matvec, o.graphs, o.precond, o.close_eval, o.gpu_tree, o.eval_tree,
             o.m2l_groups) == (0, 1, 1, 1, 1, 0, 0)
+    assert o.schur_tol == 1e-12
 
 
 def test_refinement_step_rejects_non_finite_residuals(lbs):
