@@ -486,8 +486,8 @@ void apply_K_ws(lbs_ctx &c, Workspace &w, int prec, int nrhs, const double *x, i
     fmm_apply64(c.plan, c.tab64, w, g.qfac_t.p, x, ldx, nrhs, y, ldy, 1.0,
                 as, s, &gf);
   } else {
-    fmm_apply32(c.plan, c.tab32, w, g.qfac_t.p, x, ldx, nrhs, y, ldy, 1.0,
-                as, s, &gf);
+    fmm_apply32(c.plan, c.tab32, w, g.qfac_t.p, g.qm32_t.n ? g.qm32_t.p : nullptr, x, ldx,
+                nrhs, y, ldy, 1.0, as, s, &gf);
   }
 }
 
@@ -1476,6 +1476,9 @@ lbs_ctx *setup_impl(int G, const int32_t *isl_per_geom, const lbs_island *isl_in
   build_passes(ctx->plan, o.p32, o.p64, s);
   g.qfac_t.alloc(2 * N);
   launch_permute_complex(N, ctx->plan.src_perm.p, g.qfac.p, g.qfac_t.p, s);
+  g.qm32_t.alloc(N);
+  launch_qm32(N, g.qfac_t.p, g.qm32_t.p, s);
+  build_p2m_inputs32(ctx->plan, s);
   {
     // gamma weights in tree order, and each geometry's source leaves
     const Tree &F = ctx->plan.host;

@@ -223,6 +223,11 @@ struct StrengthSrc {
   // sources of gw_t[j] sigma_j (FP64), for GammaFused
   const double *gw_t = nullptr;
   double *gpart = nullptr;
+  // optional, for the FP32 leaf multipoles: -i q_j as (Im q_j, -Re q_j)
+  // rounded to FP32 and the permutation as 32-bit indices (half the bytes
+  // of qfac_t and perm)
+  const float2 *qm32 = nullptr;
+  const int32_t *perm32 = nullptr;
 };
 
 // Leaf multipoles, one wave per leaf (every source lies in one leaf): lane
@@ -321,6 +326,7 @@ __global__ void __launch_bounds__(64)
                const int64_t *__restrict__ ls_rng,
                const double4 *__restrict__ ls_geo,
                const double *__restrict__ sx, const double *__restrict__ sy,
+               const float2 *__restrict__ w32,
                cx<float> *__restrict__ p, int64_t ns, cx<float> *__restrict__ M,
                int nbox, StrengthSrc ss) {
   constexpr int NV = pow2_ceil(2 * P), SH = 5 - log2_exact(NV);
@@ -342,15 +348,70 @@ __global__ void __launch_bounds__(64)
     const double c_x = geo.x, c_y = geo.y;
     ir = geo.z;
     const int64_t e0 = ls_rng[2 * e], e1 = ls_rng[2 * e + 1];
+    if (w32 && ss.sigma && ss.qm32) {  // uniform
+      // sources j and j + 32 of this lane per step, every load issued
+      // before the dependent gathers of sigma, the terms added in source
+      // order as below
+      const double *sgr = ss.sigma + (int64_t)r * ss.ldx;
+      for (int64_t j = e0 + hl; j < e1; j += 64) {
+        const bool two = j + 32 < e1;
+        const int64_t jb = two ? j + 32 : j;
+        const int ia = ss.perm32[j], ib = ss.perm32[jb];
+        const float2 wa = w32[j], wb = w32[jb];
+        const float2 qa = ss.qm32[j], qb = ss.qm32[jb];
+        double ga = 0.0, gb = 0.0;
+        if (ss.gpart) {
+          ga = ss.gw_t[j];
+          gb = ss.gw_t[jb];
+        }
+        const double sa = sgr[ia], sb = sgr[ib];
+        cx<float> pa{float((double)qa.x * sa), float((double)qa.y * sa)};
+        cx<float> pb{float((double)qb.x * sb), float((double)qb.y * sb)};
+        pr[j] = pa;
+        if (ss.gpart) gsum += ga * sa;
+        if (two) {
+          pr[jb] = pb;
+          if (ss.gpart) gsum += gb * sb;
+        } else {
+          pb = cx<float>{0.f, 0.f};
+        }
+        const cx<float> wca{wa.x, wa.y}, wcb{wb.x, wb.y};
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+          acc[2 * k] += pa.x;
+          acc[2 * k + 1] += pa.y;
+          pa = pa * wca;
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+          acc[2 * k] += pb.x;
+          acc[2 * k + 1] += pb.y;
+          pb = pb * wcb;
+        }
+      }
+    } else
     for (int64_t j = e0 + hl; j < e1; j += 32) {
-      const cx<float> w{float((sx[j] - c_x) * ir), float((sy[j] - c_y) * ir)};
+      cx<float> w;
+      if (w32) {  // uniform: the leaf-relative positions of set-up
+        const float2 t = w32[j];
+        w = cx<float>{t.x, t.y};
+      } else {
+        w = cx<float>{float((sx[j] - c_x) * ir), float((sy[j] - c_y) * ir)};
+      }
       cx<float> pw;
       if (ss.sigma) {  // form the strength: p_j = -i q_j sigma_j
-        const double sg = ss.sigma[(int64_t)r * ss.ldx + ss.perm[j]];
-        const double qx = ss.qfac_t[2 * j], qy = ss.qfac_t[2 * j + 1];
-        pw = cx<float>{float(qy * sg), float(-qx * sg)};
+        if (ss.qm32) {  // uniform
+          const double sg = ss.sigma[(int64_t)r * ss.ldx + ss.perm32[j]];
+          const float2 q = ss.qm32[j];
+          pw = cx<float>{float((double)q.x * sg), float((double)q.y * sg)};
+          if (ss.gpart) gsum += ss.gw_t[j] * sg;
+        } else {
+          const double sg = ss.sigma[(int64_t)r * ss.ldx + ss.perm[j]];
+          const double qx = ss.qfac_t[2 * j], qy = ss.qfac_t[2 * j + 1];
+          pw = cx<float>{float(qy * sg), float(-qx * sg)};
+          if (ss.gpart) gsum += ss.gw_t[j] * sg;
+        }
         pr[j] = pw;
-        if (ss.gpart) gsum += ss.gw_t[j] * sg;
       } else {
         pw = pr[j];
       }
@@ -1212,6 +1273,50 @@ __global__ void __launch_bounds__(64, RB == 1 ? 8 : 1)
   }
 }
 
+// Set-up of the FP32 leaf multipoles' inputs: w32[j] = (z_j - c) / r of
+// source j's leaf, rounded once to FP32 as the multipole pass forms it, and
+// perm32[j] = src_perm[j]; one wave per source leaf.
+__global__ void __launch_bounds__(64)
+    k_p2m_inputs32(int nleaf, const int64_t *__restrict__ ls_rng,
+                   const double4 *__restrict__ ls_geo, const double *__restrict__ sx,
+                   const double *__restrict__ sy, const int64_t *__restrict__ perm,
+                   float2 *__restrict__ w32, int32_t *__restrict__ perm32) {
+  const int e = blockIdx.x;
+  if (e >= nleaf) return;
+  const double4 geo = ls_geo[e];
+  const int64_t e0 = ls_rng[2 * e], e1 = ls_rng[2 * e + 1];
+  for (int64_t j = e0 + threadIdx.x; j < e1; j += 64) {
+    w32[j] = make_float2(float((sx[j] - geo.x) * geo.z), float((sy[j] - geo.y) * geo.z));
+    perm32[j] = (int32_t)perm[j];
+  }
+}
+
+void build_p2m_inputs32(DevPlan &pl, hipStream_t s) {
+  if (pl.ns > INT32_MAX)
+    throw ApiError{LBS_ERR_UNSUPPORTED, "more than 2^31 - 1 sources in one plan"};
+  pl.w32.alloc((size_t)pl.ns);
+  pl.perm32.alloc((size_t)pl.ns);
+  if (pl.n_leaf_s > 0)
+    hipLaunchKernelGGL(k_p2m_inputs32, dim3(pl.n_leaf_s), dim3(64), 0, s, pl.n_leaf_s,
+                       pl.ls_rng.p, pl.ls_geo.p, pl.sx.p, pl.sy.p, pl.src_perm.p, pl.w32.p,
+                       pl.perm32.p);
+  LBS_HIP(hipGetLastError());
+}
+
+// qm32[j] = (Im q_j, -Re q_j) in FP32 (so that -i q_j sigma = qm32 sigma),
+// q = qfac_t interleaved complex
+__global__ void k_qm32(int64_t n, const double *__restrict__ qfac_t, float2 *__restrict__ qm32) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < n) qm32[j] = make_float2(float(qfac_t[2 * j + 1]), float(-qfac_t[2 * j]));
+}
+
+void launch_qm32(int64_t n, const double *qfac_t, float2 *qm32, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_qm32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, qfac_t,
+                     qm32);
+  LBS_HIP(hipGetLastError());
+}
+
 // ---------------------------------------------------------------- drivers
 // Returns whether the correction sums of gf were formed too (by the FP32
 // MFMA M2L launch).
@@ -1244,7 +1349,7 @@ static bool far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
       if constexpr (sizeof(T) == 4 && P <= 16)  // two leaves per wave
         hipLaunchKernelGGL((k_p2m_pair<P>), dim3((pl.n_leaf_s + 1) / 2, nrhs), dim3(64), 0, s,
                            pl.leaf_s.p, pl.n_leaf_s, pl.ls_rng.p, pl.ls_geo.p, pl.sx.p,
-                           pl.sy.p, p, pl.ns, M, pl.nbox, ss);
+                           pl.sy.p, pl.w32.n ? pl.w32.p : nullptr, p, pl.ns, M, pl.nbox, ss);
       else
         hipLaunchKernelGGL((k_p2m<T, P>), dim3(pl.n_leaf_s, nrhs), dim3(64), 0,
                            s, pl.leaf_s.p, pl.ls_rng.p, pl.ls_geo.p, pl.sx.p,
@@ -1394,13 +1499,15 @@ void fmm_far64(const DevPlan &pl, const Tables &tb, Workspace &ws, const double 
 }
 
 void fmm_apply32(const DevPlan &pl, const Tables &tb, Workspace &ws,
-                 const double *qfac_t, const double *sigma, int64_t ldx,
+                 const double *qfac_t, const float2 *qm32, const double *sigma, int64_t ldx,
                  int nrhs, double *out, int64_t ldy, double scale,
                  const Assembly &as, hipStream_t s, const GammaFused *gf) {
   // the strengths p_j = -i q_j sigma_j (and with gf the partial gamma
   // sums) are formed by the leaf multipole pass
   const StrengthSrc ss{pl.src_perm.p, qfac_t, sigma, ldx, gf ? gf->gw_t : nullptr,
-                       gf ? ws.gpart.p : nullptr};
+                       gf ? ws.gpart.p : nullptr,
+                       qm32 && pl.perm32.n ? qm32 : nullptr,
+                       qm32 && pl.perm32.n ? pl.perm32.p : nullptr};
   switch (tb.P) {
     case 12: run32<12>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss, gf); break;
     case 16: run32<16>(pl, tb, ws, nrhs, out, ldy, scale, as, s, ss, gf); break;

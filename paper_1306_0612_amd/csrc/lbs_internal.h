@@ -154,6 +154,11 @@ struct DevPlan {
   // points in tree order
   DBuf<double> sx, sy, tx, ty;
   DBuf<int64_t> src_perm, tgt_perm;
+  // handle plans: each source's position relative to its leaf (centre,
+  // radius) in FP32 and src_perm as 32-bit indices, for the FP32 leaf
+  // multipoles (build_p2m_inputs32; empty on evaluation plans)
+  DBuf<float2> w32;
+  DBuf<int32_t> perm32;
   Tree host;                                  // host tree (statistics)
 };
 
@@ -252,6 +257,7 @@ struct Geometry {
   DBuf<int32_t> node_geo, isl_geo;   // geometry of each node / island
   DBuf<int32_t> row_geo;             // geometry of each unknown (N + M)
   DBuf<double> qfac_t;               // qfac in tree order
+  DBuf<float2> qm32_t;               // -i qfac in tree order, FP32 (Im, -Re)
   DBuf<double> gw_t;                 // gamma weights in tree order
   DBuf<int32_t> gleaf_ptr;           // per geometry: range in leaf_s
   int gleaf_chunks = 1;              // most 2048-leaf chunks of a geometry
@@ -406,10 +412,14 @@ void fmm_apply64_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
 void fmm_apply32_full(const DevPlan &pl, const Tables &tb, Workspace &ws,
                       const double *pin, double *psi, hipStream_t s);
 void fmm_apply32(const DevPlan &pl, const Tables &tb, Workspace &ws,
-                 const double *qfac_t, const double *sigma, int64_t ldx,
+                 const double *qfac_t, const float2 *qm32, const double *sigma, int64_t ldx,
                  int nrhs, double *out, int64_t ldy, double scale,
                  const Assembly &as, hipStream_t s,
                  const GammaFused *gf = nullptr);
+// set-up of the FP32 leaf multipoles' inputs of a handle plan (w32, perm32)
+void build_p2m_inputs32(DevPlan &pl, hipStream_t s);
+// qm32[j] = (Im q_j, -Re q_j) in FP32 from interleaved complex qfac_t
+void launch_qm32(int64_t n, const double *qfac_t, float2 *qm32, hipStream_t s);
 // direct O(N^2) sums (single-geometry handles)
 void direct_apply64(int64_t N, const double *xi, const double *qfac,
                     const double *sigma, int64_t ldx, int nrhs, double *out,
