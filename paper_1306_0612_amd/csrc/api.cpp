@@ -305,7 +305,23 @@ void build_passes(DevPlan &pl, int p32, int p64, hipStream_t s, bool fp64_only =
       dp.cap = cap;
       dp.round_ptr = pp.round_ptr;
       dp.hdr.upload(pp.hdr, s);
-      dp.ext.upload(pp.ext, s);
+      // inputs at a fixed stride of cap slots per component (box -1 past
+      // its count), so that the kernel's first loads need no header
+      std::vector<int32_t> extc((size_t)2 * cap * pp.ncomp, 0);
+      for (int c = 0; c < pp.ncomp; ++c) {
+        const int e0 = pp.hdr[8 * (size_t)c], ne = pp.hdr[8 * (size_t)c + 1];
+        if (ne > cap) fail(LBS_ERR_UNSUPPORTED, "pass component with more inputs than slots");
+        for (int i = 0; i < cap; ++i) {
+          int32_t *o = extc.data() + 2 * ((size_t)c * cap + i);
+          if (i < ne) {
+            o[0] = pp.ext[2 * (size_t)(e0 + i)];
+            o[1] = pp.ext[2 * (size_t)(e0 + i) + 1];
+          } else {
+            o[0] = -1;
+          }
+        }
+      }
+      dp.ext.upload(extc, s);
       dp.par.upload(pp.par, s);
       dp.stp.upload(pp.stp, s);
       LBS_HIP(hipStreamSynchronize(s));  // pp is released on return

@@ -553,19 +553,21 @@ __global__ void __launch_bounds__(kPassThreads)
   __shared__ cx<T> sPre[4 * P], sPost[4 * P];
   const int tid = threadIdx.x;
   const int32_t *h = hdr + 8 * (int64_t)blockIdx.x;
-  const int e0 = h[0], ne = h[1], p0 = h[2], np = h[3], s0 = h[4], ns = h[5];
+  const int ne = h[1], p0 = h[2], np = h[3], s0 = h[4], ns = h[5];
   cx<T> *Er = E + (int64_t)blockIdx.y * nbox * P;
   int2 d[IT];
   V v[IT];
+  // ext: this component's CAP input slots (box -1 past #ext), read
+  // without waiting for the header
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const int e = tid + i * NT;
-    d[i] = e < ne * CH ? ext[e0 + e / CH] : make_int2(0, 0);
+    d[i] = e < CAP * CH ? ext[(int64_t)blockIdx.x * CAP + e / CH] : make_int2(-1, 0);
   }
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const int e = tid + i * NT;
-    if (e < ne * CH) v[i] = reinterpret_cast<const V *>(Er + (int64_t)d[i].x * P)[e % CH];
+    if (d[i].x >= 0) v[i] = reinterpret_cast<const V *>(Er + (int64_t)d[i].x * P)[e % CH];
   }
   for (int i = tid; i < np; i += NT) spd[i] = par[p0 + i];
   for (int i = tid; i <= ns; i += NT) sst[i] = stp[s0 + i];
@@ -645,7 +647,8 @@ static void run_pass(const DevPass &pg, const T *bc, const cx<T> *pre, const cx<
     const int a = pg.round_ptr[k], n = pg.round_ptr[k + 1] - a;
     if (n <= 0) continue;
     hipLaunchKernelGGL((k_pass<T, P, DOWN>), dim3(n, nrhs), dim3(kPassThreads), 0, s,
-                       pg.hdr.p + 8 * (int64_t)a, reinterpret_cast<const int2 *>(pg.ext.p),
+                       pg.hdr.p + 8 * (int64_t)a,
+                       reinterpret_cast<const int2 *>(pg.ext.p) + (int64_t)a * pg.cap,
                        reinterpret_cast<const int4 *>(pg.par.p), pg.stp.p, bc, pre, post, E,
                        nbox);
   }
