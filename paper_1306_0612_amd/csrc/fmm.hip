@@ -591,33 +591,70 @@ __global__ void __launch_bounds__(kPassThreads)
   __syncthreads();
   for (int st = 0; st < ns; ++st) {
     const int a = sst[st], b = sst[st + 1];
-    for (int it = tid; it < (b - a) * P; it += NT) {
-      const int j = a + it / P, m = it % P;
-      const int4 pd = spd[j];
-      const int box = pd.x & 0x3FFFFFFF, q = (int)((uint32_t)pd.x >> 30);
-      int s4[4] = {pd.z & 0xFFFF, (int)((uint32_t)pd.z >> 16), pd.w & 0xFFFF,
-                   (int)((uint32_t)pd.w >> 16)};
-      if constexpr (!DOWN) {
-        cx<T> sum[4];
-        const cx<T> *ak[4];
+    if constexpr (!DOWN) {
+      if ((b - a) * P * 4 <= NT) {  // uniform
+        // a step of few boxes: four lanes per (box, coefficient), one child
+        // quadrant each, so that the chain per lane is short; the quadrant
+        // sums meet by two cross-lane steps (it & 3 = tid & 3: NT is a
+        // multiple of 4, and the four lanes of a group are active together)
+        for (int it = tid; it < (b - a) * P * 4; it += NT) {
+          const int qq = it & 3, jm = it >> 2;
+          const int j = a + jm / P, m = jm % P;
+          const int4 pd = spd[j];
+          const int box = pd.x & 0x3FFFFFFF, q = (int)((uint32_t)pd.x >> 30);
+          const int w = qq < 2 ? pd.z : pd.w;
+          const int sq = (qq & 1) ? (int)((uint32_t)w >> 16) : (w & 0xFFFF);
+          const cx<T> *ak = sl + (sq == kPassNone ? CAP : sq) * P;
+          cx<T> sum{T(0), T(0)};
 #pragma unroll
-        for (int qq = 0; qq < 4; ++qq) {
-          ak[qq] = sl + (s4[qq] == kPassNone ? CAP : s4[qq]) * P;
-          sum[qq] = cx<T>{T(0), T(0)};
+          for (int k = 0; k < P; ++k) sum = sum + sC[k * P + m] * ak[k];
+          cx<T> acc = sPost[qq * P + m] * sum;
+          acc.x += __shfl_xor(acc.x, 1, 64);
+          acc.y += __shfl_xor(acc.y, 1, 64);
+          acc.x += __shfl_xor(acc.x, 2, 64);
+          acc.y += __shfl_xor(acc.y, 2, 64);
+          if (qq == 0) {
+            const cx<T> A = T(0.5) * acc;
+            Er[(int64_t)box * P + m] = A;
+            sl[(ne + j) * P + m] = A * sPre[q * P + m];
+          }
         }
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-          const T c = sC[k * P + m];
-#pragma unroll
-          for (int qq = 0; qq < 4; ++qq) sum[qq] = sum[qq] + c * ak[qq][k];
-        }
-        cx<T> acc = sPost[m] * sum[0];
-#pragma unroll
-        for (int qq = 1; qq < 4; ++qq) acc = acc + sPost[qq * P + m] * sum[qq];
-        const cx<T> A = T(0.5) * acc;
-        Er[(int64_t)box * P + m] = A;
-        sl[(ne + j) * P + m] = A * sPre[q * P + m];
       } else {
+        // one lane per (box, coefficient), the four quadrant sums side by side
+        for (int it = tid; it < (b - a) * P; it += NT) {
+          const int j = a + it / P, m = it % P;
+          const int4 pd = spd[j];
+          const int box = pd.x & 0x3FFFFFFF, q = (int)((uint32_t)pd.x >> 30);
+          const int s4[4] = {pd.z & 0xFFFF, (int)((uint32_t)pd.z >> 16), pd.w & 0xFFFF,
+                             (int)((uint32_t)pd.w >> 16)};
+          cx<T> sum[4];
+          const cx<T> *ak[4];
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            ak[qq] = sl + (s4[qq] == kPassNone ? CAP : s4[qq]) * P;
+            sum[qq] = cx<T>{T(0), T(0)};
+          }
+#pragma unroll
+          for (int k = 0; k < P; ++k) {
+            const T c = sC[k * P + m];
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) sum[qq] = sum[qq] + c * ak[qq][k];
+          }
+          // the quadrant terms added as the four-lane form adds them
+          const cx<T> t0 = sPost[m] * sum[0], t1 = sPost[P + m] * sum[1];
+          const cx<T> t2 = sPost[2 * P + m] * sum[2], t3 = sPost[3 * P + m] * sum[3];
+          const cx<T> A = T(0.5) * ((t0 + t1) + (t2 + t3));
+          Er[(int64_t)box * P + m] = A;
+          sl[(ne + j) * P + m] = A * sPre[q * P + m];
+        }
+      }
+    } else {
+      for (int it = tid; it < (b - a) * P; it += NT) {
+        const int j = a + it / P, m = it % P;
+        const int4 pd = spd[j];
+        const int box = pd.x & 0x3FFFFFFF, q = (int)((uint32_t)pd.x >> 30);
+        const int s4[4] = {pd.z & 0xFFFF, (int)((uint32_t)pd.z >> 16), pd.w & 0xFFFF,
+                           (int)((uint32_t)pd.w >> 16)};
         const int own = pd.y & 0xFFFF, ver = (int)((uint32_t)pd.y >> 16);
         cx<T> val = sl[own * P + m];
         if (ver != kPassNone) {
