@@ -55,7 +55,7 @@ typedef enum {
   LBS_ERR_NOT_FINITE = 4,     /* NaN or Inf in the data                  */
   LBS_ERR_OUT_OF_MEMORY = 5,
   LBS_ERR_HIP = 6,            /* a HIP runtime call failed               */
-  LBS_ERR_UNSUPPORTED = 7     /* valid request this build does not serve */
+  LBS_ERR_UNSUPPORTED = 7     /* valid request the library does not serve */
 } lbs_status;
 
 /* One island (Section 1.3): a simply connected cap-like region bounded by a

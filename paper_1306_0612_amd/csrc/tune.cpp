@@ -237,7 +237,7 @@ uint64_t fnv1a(const void *p, size_t n, uint64_t h = 0xcbf29ce484222325ull) {
   return h;
 }
 
-// The cache key: the problem, the device and this build of the library.
+// The cache key: the problem, the device and the compile time of the library.
 uint64_t tune_key(const lbs_island *isl, int32_t M, const int32_t *nodes, const lbs_options &o,
                   double tol_mixed, double tol_fp64) {
   uint64_t h = fnv1a(isl, sizeof(lbs_island) * (size_t)M);
