@@ -435,6 +435,80 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// The FP64 leaf multipoles of two leaves per wave (list entries 2 w and
+// 2 w + 1 on lanes 0-31 and 32-63): as k_p2m, KB coefficients per pass
+// over the sources (the first pass forms the strengths, later passes read
+// them back), every source loop striding by 32 and one halving sum per
+// pass inside each half, so that the sums' fixed cost is shared by two
+// leaves.
+template <int P>
+__global__ void __launch_bounds__(64)
+    k_p2m_pair64(const int32_t *__restrict__ leaves, int nleaf,
+                 const int64_t *__restrict__ ls_rng,
+                 const double4 *__restrict__ ls_geo,
+                 const double *__restrict__ sx, const double *__restrict__ sy,
+                 cx<double> *__restrict__ p, int64_t ns, cx<double> *__restrict__ M,
+                 int nbox, StrengthSrc ss) {
+  constexpr int KB = kChunk<double, P>(), NV = pow2_ceil(2 * KB), SH = 5 - log2_exact(NV);
+  static_assert(NV <= 32, "at most one value per lane of a half after the halving sum");
+  const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
+  const int e = 2 * blockIdx.x + half;  // this half's list entry
+  const bool has = e < nleaf;           // uniform within the half
+  const int r = blockIdx.y;
+  cx<double> *pr = p + (int64_t)r * ns;
+  double gsum = 0.0, c_x = 0.0, c_y = 0.0, ir = 0.0;
+  int b = 0;
+  int64_t e0 = 0, e1 = 0;
+  if (has) {
+    b = leaves[e];
+    const double4 geo = ls_geo[e];
+    c_x = geo.x;
+    c_y = geo.y;
+    ir = geo.z;
+    e0 = ls_rng[2 * e];
+    e1 = ls_rng[2 * e + 1];
+  }
+  const int vi = hl >> SH;
+  const bool writer = has && (hl & ((1 << SH) - 1)) == 0;
+#pragma unroll
+  for (int k0 = 0; k0 < P; k0 += KB) {
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int64_t j = e0 + hl; j < e1; j += 32) {
+      const cx<double> w{(sx[j] - c_x) * ir, (sy[j] - c_y) * ir};
+      cx<double> pw;
+      if (k0 == 0 && ss.sigma) {  // form the strength: p_j = -i q_j sigma_j
+        const double sg = ss.sigma[(int64_t)r * ss.ldx + ss.perm[j]];
+        const double qx = ss.qfac_t[2 * j], qy = ss.qfac_t[2 * j + 1];
+        pw = cx<double>{qy * sg, -qx * sg};
+        pr[j] = pw;
+        if (ss.gpart) gsum += ss.gw_t[j] * sg;
+      } else {
+        pw = pr[j];
+      }
+      if (k0 > 0) pw = pw * cpow(w, k0);
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        if (k0 + k < P) {
+          acc[2 * k] += pw.x;
+          acc[2 * k + 1] += pw.y;
+          pw = pw * w;
+        }
+      }
+    }
+    halving_steps_half<double, NV>(acc, lane);
+    if (writer && vi < 2 * KB && 2 * k0 + vi < 2 * P) {
+      double *Mb = reinterpret_cast<double *>(M + ((int64_t)r * nbox + b) * P);
+      Mb[2 * k0 + vi] = ir * acc[0];
+    }
+  }
+  if (ss.gpart) {  // block-uniform
+    for (int o = 16; o > 0; o >>= 1) gsum += __shfl_xor(gsum, o, 64);
+    if (has && hl == 0) ss.gpart[(int64_t)r * nleaf + e] = gsum;
+  }
+}
+
 // gamma[r G + g] = the sum of the partial sums of geometry g's source
 // leaves, positions gl_ptr[g] .. gl_ptr[g + 1] of the plan's leaf list.
 // Block (c, g, r) sums chunk c of that range into csum; the last block of
@@ -1390,6 +1464,10 @@ static bool far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
         hipLaunchKernelGGL((k_p2m_pair<P>), dim3((pl.n_leaf_s + 1) / 2, nrhs), dim3(64), 0, s,
                            pl.leaf_s.p, pl.n_leaf_s, pl.ls_rng.p, pl.ls_geo.p, pl.sx.p,
                            pl.sy.p, pl.w32.n ? pl.w32.p : nullptr, p, pl.ns, M, pl.nbox, ss);
+      else if constexpr (sizeof(T) == 8)  // two leaves per wave
+        hipLaunchKernelGGL((k_p2m_pair64<P>), dim3((pl.n_leaf_s + 1) / 2, nrhs), dim3(64), 0,
+                           s, pl.leaf_s.p, pl.n_leaf_s, pl.ls_rng.p, pl.ls_geo.p, pl.sx.p,
+                           pl.sy.p, (cx<double> *)p, pl.ns, (cx<double> *)M, pl.nbox, ss);
       else
         hipLaunchKernelGGL((k_p2m<T, P>), dim3(pl.n_leaf_s, nrhs), dim3(64), 0,
                            s, pl.leaf_s.p, pl.ls_rng.p, pl.ls_geo.p, pl.sx.p,
