@@ -160,11 +160,11 @@ void upload_plan(Tree &T, const double *sx, const double *sy,
   }
   pl.leaf_t_host = leaf_t;
   pl.leaf_s_host = leaf_s;
-  std::vector<int32_t> xb;
+  // the M2L kernels form the P2L sums of their boxes: every box with an
+  // X list must be one of them
   for (int b = 0; b < nb; ++b)
-    if (T.x_ptr[b + 1] > T.x_ptr[b]) xb.push_back(b);
-  pl.n_x = (int)xb.size();
-  pl.x_box.upload(xb, s);
+    if (T.x_ptr[b + 1] > T.x_ptr[b] && !(T.level[b] >= 2 && has_tgt[b]))
+      fail(LBS_ERR_UNSUPPORTED, "X list on a box outside the M2L boxes");
   pl.cx.upload(T.cx, s);
   pl.cy.upload(T.cy, s);
   pl.rad.upload(T.rad, s);

@@ -770,21 +770,50 @@ struct Groups {
   static constexpr int G = 64 / P;
 };
 
+// P2L parts of one box's local expansion into px (values 2k, 2k + 1 of
+// coefficient k), KB coefficients per pass (p2l_sum).
+template <typename T, int P, int K0>
+__device__ __forceinline__ void p2l_pass_lds(int64_t xf0, int total,
+                                             const int32_t *__restrict__ xf_idx,
+                                             double cxb, double cyb, T rb,
+                                             const double *__restrict__ sx,
+                                             const double *__restrict__ sy,
+                                             const cx<T> *__restrict__ pr, T *px, int lane) {
+  if constexpr (K0 < P) {
+    constexpr int KB = kChunk<T, P>(), NV = pow2_ceil(2 * KB),
+                  SH = 6 - log2_exact(NV);
+    const T tot = p2l_sum<T, P, K0, KB>(xf0, total, xf_idx, cxb, cyb, rb, sx,
+                                        sy, pr, lane);
+    const int vi = lane >> SH;
+    if ((lane & ((1 << SH) - 1)) == 0 && vi < 2 * KB && 2 * K0 + vi < 2 * P)
+      px[2 * K0 + vi] = tot;
+    p2l_pass_lds<T, P, K0 + KB>(xf0, total, xf_idx, cxb, cyb, rb, sx, sy, pr, px, lane);
+  }
+}
+
 // M2L over the V list of every box with targets at level >= 2 (vector
 // ALU).  One 64-lane block per box; lane (g, l) accumulates coefficient l
 // from every G-th list entry with the factorized translation
 // b_l += tau^-l sum_k H[l][k] (tau^-k a_k), H[l][k] = (-1)^k C(k+l-1, l).
+// The box's P2L sum over its X list (every box with an X list whose local
+// expansion is used is one of these boxes) follows in the same block and
+// is added to the M2L result before the one store.
 template <typename T, int P>
 __global__ void __launch_bounds__(64)
     k_m2l(const int32_t *__restrict__ boxes,
           const int32_t *__restrict__ v_ptr, const int32_t *__restrict__ v_src,
           const uint8_t *__restrict__ v_code, const T *__restrict__ H,
           const cx<T> *__restrict__ itp, const cx<T> *__restrict__ M,
-          cx<T> *__restrict__ L, int nbox) {
+          cx<T> *__restrict__ L, int nbox, const int64_t *__restrict__ xf_ptr,
+          const int32_t *__restrict__ xf_idx, const double *__restrict__ cxv,
+          const double *__restrict__ cyv, const double *__restrict__ rad,
+          const double *__restrict__ sx, const double *__restrict__ sy,
+          const cx<T> *__restrict__ p, int64_t ns) {
   constexpr int G = Groups<P>::G;
   constexpr int NP = 2 * P + 1;
   __shared__ cx<T> ybuf[G][P];
   __shared__ cx<T> red[G][P];
+  __shared__ T px[2 * P];
   const int b = boxes[blockIdx.x];
   const int r = blockIdx.y;
   const int lane = threadIdx.x;
@@ -815,11 +844,18 @@ __global__ void __launch_bounds__(64)
     __syncthreads();
   }
   if (act) red[g][l] = acc;
+  // (xf_ptr null: no P2L here)
+  const int64_t xf0 = xf_ptr ? xf_ptr[b] : 0;
+  const int nx = xf_ptr ? (int)(xf_ptr[b + 1] - xf0) : 0;  // block-uniform
+  if (nx > 0)
+    p2l_pass_lds<T, P, 0>(xf0, nx, xf_idx, cxv[b], cyv[b], T(rad[b]), sx, sy,
+                          p + (int64_t)r * ns, px, lane);
   __syncthreads();
   if (act && g == 0) {
     cx<T> s = red[0][l];
 #pragma unroll
     for (int gg = 1; gg < G; ++gg) s = s + red[gg][l];
+    if (nx > 0) s = s + cx<T>{px[2 * l], px[2 * l + 1]};
     L[((int64_t)r * nbox + b) * P + l] = s;
   }
 }
@@ -1500,14 +1536,10 @@ static bool far_field(const DevPlan &pl, const Tables &tb, Workspace &ws,
     } else {
       hipLaunchKernelGGL((k_m2l<T, P>), dim3(pl.n_m2l, nrhs), dim3(64), 0, s,
                          pl.m2l_box.p, pl.v_ptr.p, pl.v_src.p, pl.v_code.p, H,
-                         itp, (const cx<T> *)M, L, pl.nbox);
+                         itp, (const cx<T> *)M, L, pl.nbox, pl.xf_ptr.p, pl.xf_idx.p,
+                         pl.cx.p, pl.cy.p, pl.rad.p, pl.sx.p, pl.sy.p, (const cx<T> *)p,
+                         pl.ns);
     }
-  }
-  if (pl.n_x > 0 && !p2l_in_m2l) {
-    TimerScope ts(tm, ST_P2L, s);
-    hipLaunchKernelGGL((k_p2l<T, P>), dim3(pl.n_x, nrhs), dim3(64), 0, s,
-                       pl.x_box.p, pl.xf_ptr.p, pl.xf_idx.p, pl.cx.p, pl.cy.p,
-                       pl.rad.p, pl.sx.p, pl.sy.p, p, pl.ns, L, pl.nbox);
   }
   TimerScope ts(tm, ST_L2L, s);
   run_pass<T, P, true>(pl.dn[sizeof(T) == 8], bc, pre, post, L, pl.nbox, nrhs, s);
@@ -1843,7 +1875,8 @@ static void run64_sources(const DevPlan &pl, const Tables &tb, Workspace &ws,
   if (pl.n_m2l > 0)
     hipLaunchKernelGGL((k_m2l<double, P>), dim3(pl.n_m2l, 1), dim3(64), 0, s, pl.m2l_box.p,
                        pl.v_ptr.p, pl.v_src.p, pl.v_code.p, H, itp, (const cx<double> *)M, L,
-                       pl.nbox);
+                       pl.nbox, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       nullptr, int64_t(0));
   if (ps.n_m > 0)
     hipLaunchKernelGGL((k_p2l<double, P>), dim3(ps.n_m, 1), dim3(64), 0, s, ps.m_list.p,
                        ps.l_ptr.p, ps.l_t.p, pl.cx.p, pl.cy.p, pl.rad.p, ps.x, ps.y, pin, ps.n,

@@ -146,8 +146,6 @@ struct DevPlan {
   DBuf<int64_t> ls_rng;
   DBuf<double4> ls_geo;
   DBuf<int32_t> m2l_wave;  // M2L boxes in the FP32 kernel's wave order
-  int n_x = 0;
-  DBuf<int32_t> x_box;                       // boxes with an X list
   // Upward (M2M) and downward (L2L) pass programs (PassProgram in tree.h)
   // for the FP32 ([0]) and FP64 ([1]) expansion orders of the handle.
   DevPass up[2], dn[2];
