@@ -146,6 +146,10 @@ def test_setup_rejects_bad_options(lbs):
     assert lbs.setup_status(isl, restart=0) == "LBS_ERR_INVALID_ARG"
     assert lbs.setup_status(isl, nodes=4) == "LBS_ERR_INVALID_ARG"
     assert lbs.setup_status(isl, graphs=2) == "LBS_ERR_INVALID_ARG"
+    assert lbs.setup_status(isl, eval_tree=2) == "LBS_ERR_INVALID_ARG"
+    assert lbs.setup_status(isl, m2l_groups=32) == "LBS_ERR_INVALID_ARG"
+    assert lbs.setup_status(isl, schur_tol=float("nan")) == "LBS_ERR_INVALID_ARG"
+    assert lbs.setup_status(isl, schur_tol=0.5) == "LBS_ERR_INVALID_ARG"
 
 
 def test_deep_tree_geometry_levels_and_coverage(lbs):
