@@ -129,17 +129,16 @@ def stereographic(x, xt, xtt):
     return xi, dxi, ddxi
 
 
-def orientation_sign(xi, dxi, contains_pole=False):
+def orientation_sign(xi, dxi):
     """+1 when the island lies to the left of the planar traversal.
 
-    An island not containing the north pole is the bounded interior of its
-    planar curve, which lies to the left exactly when the curve runs
-    counter-clockwise, i.e. when its signed area (1/2) sum Im(conj(xi) xi')
-    is positive.  An island containing the pole is the unbounded exterior.
+    An island (never containing the north pole: such geometries are
+    rejected) is the bounded interior of its planar curve, which lies to the
+    left exactly when the curve runs counter-clockwise, i.e. when its signed
+    area (1/2) sum Im(conj(xi) xi') is positive.
     """
     area = np.sum(np.imag(np.conj(xi) * dxi))
-    s = 1.0 if area > 0 else -1.0
-    return -s if contains_pole else s
+    return 1.0 if area > 0 else -1.0
 
 
 def island_area(islands, k, n_quad=4096):

@@ -152,14 +152,5 @@ def sphere_kernel_block(cv, rows):
     return val * (cv.h * speed / np.pi)[None, :]
 
 
-def schur_parts(cv):
-    """F, D, the Schur complement S = D - F E and its LU factors
-    (eq. matrix_eqns_c and the text after it)."""
-    F, D = constraint_blocks(cv)
-    E = log_source_block(cv)
-    S = D - F @ E
-    return F, D, E, S, sla.lu_factor(S, check_finite=False)
-
-
 def build(islands):
     return Curves(islands)
