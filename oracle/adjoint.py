@@ -11,9 +11,14 @@ with x = [sigma; A].  The method's quantities are written out densely:
   system matrix of nystrom.system_matrix;
 * dJ/dg = 2 lambda_sigma (the right-hand side is 2 g);
 * dJ/dbeta for the 16 radius coefficients of each island (Section 3's curves
-  r(t) = r0 (1 + sum a_n cos nt + b_n sin nt)) by central differences of the
-  whole dense pipeline: rebuild the curves, solve by LU, evaluate.  The node
-  data g is a vector held fixed when the shape moves.
+  r(t) = r0 (1 + sum a_n cos nt + b_n sin nt)) two ways: by central
+  differences of the whole dense pipeline (rebuild the curves, solve by LU,
+  evaluate), and by the adjoint assembly
+  dJ/dbeta = w . (dT/dbeta) x - lambda . (dA/dbeta) x
+  with the two matrix derivatives by central differences of the assembled
+  matrices (the derivative of A x = b with b fixed gives
+  A dx = -(dA) x, and w . T dx = -lambda . (dA) x).  The node data g is a
+  vector held fixed when the shape moves.
 
 For a quadratic misfit L = 1/2 |u - u*|^2 the same formulas apply with
 w = u - u* at the current shape.
@@ -89,4 +94,29 @@ def grad_shape_fd(islands, g, targets, w, step=1e-4, islands_idx=None):
             f = {s: functional(_with_coef(islands, k, q, b + s * step), g,
                                targets, w) for s in (-2, -1, 1, 2)}
             out[k, q] = (8.0 * (f[1] - f[-1]) - (f[2] - f[-2])) / (12.0 * step)
+    return out
+
+
+def grad_shape_adjoint(islands, g, targets, w, step=1e-5, islands_idx=None):
+    """dJ/dcoef (M x 16) by the adjoint assembly: x = [sigma; A] of the
+    current shape, lambda = A^-T T^T w, and per coefficient
+    w . (dT) x - lambda . (dA) x with dT, dA the central differences
+    (X(+h) - X(-h)) / (2 h) of the dense evaluation and system matrices."""
+    cv = Curves(islands)
+    sigma, A = nystrom.solve_dense(cv, g)
+    x = np.concatenate([sigma, A])
+    gs, ga = eval_transpose(cv, targets, w)
+    lam = np.concatenate(adjoint_solve(cv, gs, ga))
+    w = np.asarray(w, float)
+    m = islands.m
+    out = np.zeros((m, 16))
+    ks = range(m) if islands_idx is None else islands_idx
+    for k in ks:
+        for q in range(16):
+            b = islands.coef[k, q]
+            cp = Curves(_with_coef(islands, k, q, b + step))
+            cm = Curves(_with_coef(islands, k, q, b - step))
+            dT = (eval_matrix(cp, targets) - eval_matrix(cm, targets)) / (2.0 * step)
+            dA = (nystrom.system_matrix(cp) - nystrom.system_matrix(cm)) / (2.0 * step)
+            out[k, q] = w @ (dT @ x) - lam @ (dA @ x)
     return out
